@@ -1,0 +1,450 @@
+"""FP64 CPU oracle for the capacitance -> B_z path and its gradient.
+
+TEST INFRASTRUCTURE ONLY.  This module is the slow, plain reference that the
+HIP library is checked against.  Only the test-suite, the smoke check and the
+CPU-baseline leg of the benchmark may import it; the product path never does.
+It shares no code with the HIP library: the two meet only in the seeded input
+generators of ``workloads``.
+
+What is computed (paper: Sec. I-A names the quasi-static model "circuit model
+combined with the Biot-Savart law"; Sec. II states the forward problem C -> B
+and the MSE inverse problem, Eq. 1; Sec. III gives the RC load, Eq. 2, and the
+S-parameter cosimulation, Eq. 3-7; Sec. IV-A gives the loop impedance, Eq. 11):
+
+1. G[p,k]   z-field at point p per ampere in loop k (Biot-Savart, straight
+            filaments, closed form of Hanson & Hirshman 2002).
+2. M[k,l]   Neumann mutual inductance between loop filaments; the diagonal
+            uses the reduced kernel 1/sqrt(|r-r'|^2 + a^2) with wire radius a.
+3. Phi[k]   flux of the uniform incident field B_ext,z through loop k
+            (z-component of the vector area, shoelace formula).
+4. Z        R + j w M + 1/(j w C) per (configuration, frequency) (Eq. 2, 11).
+5. I        Z I = -j w Phi   (Eq. 6 in impedance form; see ``sform_currents``
+            for the literal S-parameter route, which reaches the same I).
+6. B_z      G I               (Eq. 7, z-component of the superposition).
+7. loss     mean over (f,p) of (|B_z| - T)^2 (Eq. 1 on magnitudes), or
+            mean |B_z - T|^2 (complex mode).
+8. dL/dC    by brute-force forward sensitivity (Eq. 8-10 specialised to
+            dZ/dC_k), by the adjoint, and by central finite differences.
+
+Everything is float64 / complex128 NumPy.  Pins: tests/test_oracle_pins.py.
+"""
+from __future__ import annotations
+
+import math
+from typing import Tuple
+
+import numpy as np
+from scipy import integrate
+
+# Vacuum permeability, CODATA 2018 value (N/A^2).
+MU0 = 1.25663706212e-6
+MU0_4PI = MU0 / (4.0 * math.pi)
+
+LOSS_MAG = 0
+LOSS_COMPLEX = 1
+
+
+# ---------------------------------------------------------------------------
+# geometry helpers
+# ---------------------------------------------------------------------------
+
+def segments(verts: np.ndarray, seg_off: np.ndarray, k: int) -> Tuple[np.ndarray, np.ndarray]:
+    """Start and end points of the closed polygon k."""
+    v = np.asarray(verts[seg_off[k]:seg_off[k + 1]], dtype=np.float64)
+    return v, np.roll(v, -1, axis=0)
+
+
+def vector_area_z(verts: np.ndarray, seg_off: np.ndarray) -> np.ndarray:
+    """z-component of each loop's vector area, 1/2 sum (x_i y_{i+1} - x_{i+1} y_i).
+
+    For a uniform incident field along z the flux is exactly B_ext,z times this."""
+    n = len(seg_off) - 1
+    out = np.zeros(n)
+    for k in range(n):
+        a, b = segments(verts, seg_off, k)
+        out[k] = 0.5 * float(np.sum(a[:, 0] * b[:, 1] - b[:, 0] * a[:, 1]))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# 1. Biot-Savart field matrix
+# ---------------------------------------------------------------------------
+
+def bz_segment(p: np.ndarray, x1: np.ndarray, x2: np.ndarray) -> np.ndarray:
+    """z-field per ampere of the straight filament x1 -> x2 at points p [...,3].
+
+    With a = x1 - p, b = x2 - p the field of a finite straight filament is
+    mu0/(4 pi) * (a x b) (|a| + |b|) / (|a| |b| (|a| |b| + a.b)).
+    Where a.b < 0 (p beside the filament) the factor 1/(|a||b| + a.b) is
+    replaced by the equal (|a||b| - a.b)/|a x b|^2, which does not cancel."""
+    a = x1 - p
+    b = x2 - p
+    la = np.sqrt(np.sum(a * a, axis=-1))
+    lb = np.sqrt(np.sum(b * b, axis=-1))
+    c = np.cross(a, b)
+    cz = c[..., 2]
+    dot = np.sum(a * b, axis=-1)
+    ab = la * lb
+    c2 = np.sum(c * c, axis=-1)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        inv = np.where(dot >= 0, 1.0 / (ab + dot), (ab - dot) / c2)
+    return MU0_4PI * cz * (la + lb) * inv / ab
+
+
+def field_matrix(verts: np.ndarray, seg_off: np.ndarray, pts: np.ndarray) -> np.ndarray:
+    """G[p,k] = sum over the segments of loop k of bz_segment (T/A)."""
+    n = len(seg_off) - 1
+    G = np.zeros((pts.shape[0], n))
+    for k in range(n):
+        a, b = segments(verts, seg_off, k)
+        for s in range(a.shape[0]):
+            G[:, k] += bz_segment(pts, a[s], b[s])
+    return G
+
+
+def bz_segment_quadrature(p: np.ndarray, x1: np.ndarray, x2: np.ndarray,
+                          order: int = 64, panels: int = 8) -> np.ndarray:
+    """Same quantity by composite Gauss-Legendre quadrature of the
+    Biot-Savart integrand (dl x r)/|r|^3 along the filament (a brute-force
+    check of the closed form)."""
+    xg, wg = np.polynomial.legendre.leggauss(order)
+    d = x2 - x1
+    out = np.zeros(p.shape[:-1])
+    for j in range(panels):
+        t = (j + 0.5 * (xg + 1.0)) / panels
+        w = 0.5 * wg / panels
+        for ti, wi in zip(t, w):
+            src = x1 + ti * d
+            r = p - src
+            r3 = np.sum(r * r, axis=-1) ** 1.5
+            out += wi * (d[0] * r[..., 1] - d[1] * r[..., 0]) / r3
+    return MU0_4PI * out
+
+
+# ---------------------------------------------------------------------------
+# 2. Neumann inductance
+# ---------------------------------------------------------------------------
+
+def _parallel_F(u: float, d: float) -> float:
+    """Double antiderivative of 1/sqrt(u^2+d^2); the d -> 0 limit drops the
+    terms that cancel between the four corners (they are linear in |u|)."""
+    if d == 0.0:
+        return 0.0 if u == 0.0 else abs(u) * math.log(abs(u))
+    return u * math.asinh(u / d) - math.sqrt(u * u + d * d)
+
+
+def neumann_segments(x1, x2, y1, y2, a: float = 0.0) -> float:
+    """(mu0/4pi) * integral over both filaments of dl.dl' / sqrt(|r-r'|^2 + a^2).
+
+    Parallel (or anti-parallel) filaments: closed form (Grover).  Perpendicular
+    filaments: exactly zero (dl.dl' = 0).  Otherwise: inner integral in closed
+    form, outer integral by adaptive quadrature (QUADPACK)."""
+    x1 = np.asarray(x1, float); x2 = np.asarray(x2, float)
+    y1 = np.asarray(y1, float); y2 = np.asarray(y2, float)
+    du = x2 - x1
+    dv = y2 - y1
+    L1 = float(np.linalg.norm(du))
+    L2 = float(np.linalg.norm(dv))
+    u = du / L1
+    v = dv / L2
+    cosang = float(np.dot(u, v))
+    cross = np.cross(u, v)
+    sinang = float(np.linalg.norm(cross))
+    if sinang < 1e-12:
+        # both on lines parallel to u; coordinates along u and perpendicular distance
+        sgn = 1.0 if cosang > 0 else -1.0
+        w = y1 - x1
+        s_along = float(np.dot(w, u))
+        perp = w - s_along * u
+        d2 = float(np.dot(perp, perp)) + a * a
+        d = math.sqrt(d2)
+        if d < 1e-12 * max(L1, L2):
+            d = 0.0
+        # filament 2 spans [b1, b2] along u (in the direction of u)
+        b1 = s_along
+        b2 = s_along + sgn * L2
+        lo2, hi2 = min(b1, b2), max(b1, b2)
+        val = (_parallel_F(L1 - lo2, d) - _parallel_F(L1 - hi2, d)
+               - _parallel_F(0.0 - lo2, d) + _parallel_F(0.0 - hi2, d))
+        return MU0_4PI * sgn * val
+    if abs(cosang) < 1e-12:
+        return 0.0
+
+    def inner(s):
+        x = x1 + s * u
+        w = x - y1
+        t0 = float(np.dot(w, v))
+        rho2 = float(np.dot(w, w)) - t0 * t0
+        r = math.sqrt(max(rho2, 0.0) + a * a)
+        if r == 0.0:
+            r = 1e-300
+        return math.asinh((L2 - t0) / r) + math.asinh(t0 / r)
+
+    val, _ = integrate.quad(inner, 0.0, L1, epsabs=0.0, epsrel=1e-13, limit=400)
+    return MU0_4PI * cosang * val
+
+
+def inductance_matrix(verts, seg_off, wire_a) -> np.ndarray:
+    """M[k,l]: exact Neumann integral between the filament axes for k != l;
+    the reduced-kernel self term (offset a = wire radius) on the diagonal.
+    Every entry is computed on its own (no mirroring), so M - M^T is a check."""
+    n = len(seg_off) - 1
+    M = np.zeros((n, n))
+    for k in range(n):
+        ak, bk = segments(verts, seg_off, k)
+        for l in range(n):
+            al, bl = segments(verts, seg_off, l)
+            reg = float(wire_a[k]) if k == l else 0.0
+            acc = 0.0
+            for s in range(ak.shape[0]):
+                for t in range(al.shape[0]):
+                    acc += neumann_segments(ak[s], bk[s], al[t], bl[t], reg)
+            M[k, l] = acc
+    return M
+
+
+def inductance_matrix_fast(verts, seg_off, wire_a) -> np.ndarray:
+    """Same values for arrays of axis-aligned loops (every segment parallel or
+    perpendicular to every other), vectorised over segment pairs with the
+    same closed forms; falls back to ``inductance_matrix`` otherwise."""
+    n = len(seg_off) - 1
+    starts = [segments(verts, seg_off, k) for k in range(n)]
+    allv = np.concatenate([a for a, _ in starts]); allw = np.concatenate([b for _, b in starts])
+    d = allw - allv
+    nz = np.count_nonzero(np.abs(d) > 1e-15 * np.max(np.abs(d)), axis=1)
+    if np.any(nz != 1):
+        return inductance_matrix(verts, seg_off, wire_a)
+    M = np.zeros((n, n))
+    for k in range(n):
+        ak, bk = starts[k]
+        for l in range(n):
+            al, bl = starts[l]
+            reg = float(wire_a[k]) if k == l else 0.0
+            M[k, l] = _axis_aligned_block(ak, bk, al, bl, reg)
+    return M
+
+
+def _axis_aligned_block(ak, bk, al, bl, a):
+    du = bk - ak
+    dv = bl - al
+    axis_u = np.argmax(np.abs(du), axis=1)
+    axis_v = np.argmax(np.abs(dv), axis=1)
+    total = 0.0
+    for ax in range(3):
+        iu = np.nonzero(axis_u == ax)[0]
+        iv = np.nonzero(axis_v == ax)[0]
+        if iu.size == 0 or iv.size == 0:
+            continue
+        x1 = ak[iu][:, None, :]; x2 = bk[iu][:, None, :]
+        y1 = al[iv][None, :, :]; y2 = bl[iv][None, :, :]
+        lo1 = np.minimum(x1[..., ax], x2[..., ax]); hi1 = np.maximum(x1[..., ax], x2[..., ax])
+        lo2 = np.minimum(y1[..., ax], y2[..., ax]); hi2 = np.maximum(y1[..., ax], y2[..., ax])
+        sgn = np.sign(x2[..., ax] - x1[..., ax]) * np.sign(y2[..., ax] - y1[..., ax])
+        others = [c for c in range(3) if c != ax]
+        d2 = sum((x1[..., c] - y1[..., c]) ** 2 for c in others) + a * a
+        dd = np.sqrt(d2)
+        dd = np.where(dd < 1e-12 * (hi1 - lo1), 0.0, dd)
+
+        def F(u):
+            with np.errstate(divide="ignore", invalid="ignore"):
+                par = u * np.arcsinh(u / np.where(dd > 0, dd, 1.0)) - np.sqrt(u * u + dd * dd)
+                au = np.abs(u)
+                lim = np.where(au > 0, au * np.log(np.where(au > 0, au, 1.0)), 0.0)
+            return np.where(dd > 0, par, lim)
+
+        val = F(hi1 - lo2) - F(hi1 - hi2) - F(lo1 - lo2) + F(lo1 - hi2)
+        total += float(np.sum(sgn * val))
+    return MU0_4PI * total
+
+
+# ---------------------------------------------------------------------------
+# 3.-6. excitation, impedance, currents, field
+# ---------------------------------------------------------------------------
+
+def flux(verts, seg_off, bext_z: float) -> np.ndarray:
+    return bext_z * vector_area_z(verts, seg_off)
+
+
+def impedance(M: np.ndarray, R: np.ndarray, C: np.ndarray, omega: float) -> np.ndarray:
+    """Z = diag(R) + j w M + diag(1/(j w C)) for one configuration (Eq. 2, 11)."""
+    Z = 1j * omega * M.astype(np.complex128)
+    Z[np.diag_indices_from(Z)] += R + 1.0 / (1j * omega * C)
+    return Z
+
+
+def currents(M, R, Phi, C, omega) -> np.ndarray:
+    """I[b,f,:] solving Z I = -j w Phi with LAPACK (zgesv) per system."""
+    C = np.atleast_2d(C)
+    omega = np.atleast_1d(omega)
+    out = np.zeros((C.shape[0], omega.shape[0], M.shape[0]), dtype=np.complex128)
+    for b in range(C.shape[0]):
+        for f, w in enumerate(omega):
+            Z = impedance(M, R, C[b], w)
+            out[b, f] = np.linalg.solve(Z, -1j * w * Phi)
+    return out
+
+
+def field(G: np.ndarray, I: np.ndarray) -> np.ndarray:
+    """B_z[b,f,p] = sum_k G[p,k] I[b,f,k] (Eq. 7, z-component)."""
+    return np.einsum("pk,bfk->bfp", G, I)
+
+
+# ---------------------------------------------------------------------------
+# 7. loss
+# ---------------------------------------------------------------------------
+
+def loss(Bz: np.ndarray, T: np.ndarray, mode: int = LOSS_MAG) -> np.ndarray:
+    """Per-configuration loss, mean over (f,p)."""
+    F, P = Bz.shape[1], Bz.shape[2]
+    if mode == LOSS_MAG:
+        e = np.abs(Bz) - T[None, None, :]
+        return np.sum(e * e, axis=(1, 2)) / (F * P)
+    e = Bz - T[None, None, :]
+    return np.sum((e * np.conj(e)).real, axis=(1, 2)) / (F * P)
+
+
+def loss_weights(Bz: np.ndarray, T: np.ndarray, mode: int = LOSS_MAG) -> np.ndarray:
+    """w = dL/d conj(B_z): the loss is real, so dL = 2 Re(sum conj(w) dB).
+    Magnitude mode: w = (|B|-T) B/|B| / (F P), taken as 0 where B = 0."""
+    F, P = Bz.shape[1], Bz.shape[2]
+    if mode == LOSS_MAG:
+        mag = np.abs(Bz)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            unit = np.where(mag > 0, Bz / np.where(mag > 0, mag, 1.0), 0.0)
+        return (mag - T[None, None, :]) * unit / (F * P)
+    return (Bz - T[None, None, :]) / (F * P)
+
+
+def evaluate(G, M, R, Phi, C, omega, T, mode: int = LOSS_MAG):
+    I = currents(M, R, Phi, C, omega)
+    Bz = field(G, I)
+    return I, Bz, loss(Bz, T, mode)
+
+
+# ---------------------------------------------------------------------------
+# 8. gradient
+# ---------------------------------------------------------------------------
+
+def grad_forward_sensitivity(G, M, R, Phi, C, omega, T, mode: int = LOSS_MAG) -> np.ndarray:
+    """dL/dC by differentiating the solve column by column (Eq. 9 with
+    dZ/dC_k = -e_k e_k^T / (j w C_k^2)):  dI/dC_k = Z^-1 e_k I_k / (j w C_k^2),
+    dL/dC_k = 2 Re sum_{f,p} conj(w) (G dI/dC_k)."""
+    C = np.atleast_2d(C)
+    omega = np.atleast_1d(omega)
+    I = currents(M, R, Phi, C, omega)
+    W = loss_weights(field(G, I), T, mode)
+    n = M.shape[0]
+    g = np.zeros(C.shape)
+    for b in range(C.shape[0]):
+        for f, w in enumerate(omega):
+            Z = impedance(M, R, C[b], w)
+            for k in range(n):
+                e = np.zeros(n, dtype=np.complex128)
+                e[k] = 1.0
+                dI = np.linalg.solve(Z, e) * I[b, f, k] / (1j * w * C[b, k] ** 2)
+                dB = G @ dI
+                g[b, k] += 2.0 * float(np.real(np.sum(np.conj(W[b, f]) * dB)))
+    return g
+
+
+def grad_adjoint(G, M, R, Phi, C, omega, T, mode: int = LOSS_MAG) -> np.ndarray:
+    """dL/dC by the adjoint: r = G^T conj(w); Z^T mu = r;
+    dL/dC_k = 2 Re sum_f mu_k I_k / (j w C_k^2)."""
+    C = np.atleast_2d(C)
+    omega = np.atleast_1d(omega)
+    I = currents(M, R, Phi, C, omega)
+    W = loss_weights(field(G, I), T, mode)
+    g = np.zeros(C.shape)
+    for b in range(C.shape[0]):
+        for f, w in enumerate(omega):
+            Z = impedance(M, R, C[b], w)
+            r = G.T @ np.conj(W[b, f])
+            mu = np.linalg.solve(Z.T, r)
+            g[b] += 2.0 * np.real(mu * I[b, f] / (1j * w * C[b] ** 2))
+    return g
+
+
+def grad_fd(G, M, R, Phi, C, omega, T, h: float = 1e-15, mode: int = LOSS_MAG) -> np.ndarray:
+    """Central finite differences of the loss, step h farads."""
+    C = np.atleast_2d(np.asarray(C, float))
+    g = np.zeros(C.shape)
+    for b in range(C.shape[0]):
+        for k in range(C.shape[1]):
+            cp = C[b:b + 1].copy(); cp[0, k] += h
+            cm = C[b:b + 1].copy(); cm[0, k] -= h
+            lp = evaluate(G, M, R, Phi, cp, omega, T, mode)[2][0]
+            lm = evaluate(G, M, R, Phi, cm, omega, T, mode)[2][0]
+            g[b, k] = (lp - lm) / (2 * h)
+    return g
+
+
+def backward_from_field_grad(G, M, R, C, omega, I, gBz) -> np.ndarray:
+    """Real dL/dC given an upstream complex gradient gBz in PyTorch's
+    convention (gBz = 2 dL/d conj(B_z)) for B_z = G I(C)."""
+    C = np.atleast_2d(C)
+    omega = np.atleast_1d(omega)
+    g = np.zeros(C.shape)
+    for b in range(C.shape[0]):
+        for f, w in enumerate(omega):
+            Z = impedance(M, R, C[b], w)
+            r = G.T @ np.conj(0.5 * gBz[b, f])
+            mu = np.linalg.solve(Z.T, r)
+            g[b] += 2.0 * np.real(mu * I[b, f] / (1j * w * C[b] ** 2))
+    return g
+
+
+# ---------------------------------------------------------------------------
+# S-parameter route (Eq. 3-7), used as an independent check of the solve
+# ---------------------------------------------------------------------------
+
+def sform_currents(M, R, Phi, C, omega, Z0: float = 50.0) -> np.ndarray:
+    """Loop currents reached through the paper's wave formulation.
+
+    Each loop is a port loaded by the RC branch of Eq. 2 in series with the
+    induced EMF E = -j w Phi.  The structure is the multiport with impedance
+    matrix j w M, so its scattering matrix is S0 = (Zs - Z0)(Zs + Z0)^-1.
+    The load reflection is Eq. 3 and the source injects Z0 E/(Z_L + Z0) into
+    the incident wave (Eq. 4); Eq. 5-6 give V+ = (1 - Gamma S0)^-1 q and the
+    port current is (V+ - V-)/Z0 = (1 - S0) V+ / Z0."""
+    C = np.atleast_2d(C)
+    omega = np.atleast_1d(omega)
+    n = M.shape[0]
+    out = np.zeros((C.shape[0], omega.shape[0], n), dtype=np.complex128)
+    eye = np.eye(n)
+    for b in range(C.shape[0]):
+        for f, w in enumerate(omega):
+            Zs = 1j * w * M
+            S0 = (Zs - Z0 * eye) @ np.linalg.inv(Zs + Z0 * eye)
+            ZL = R - 1j / (w * C[b])                        # Eq. 2
+            gam = (ZL - Z0) / (ZL + Z0)                      # Eq. 3
+            E = -1j * w * Phi
+            q = Z0 * E / (ZL + Z0)
+            A = eye - np.diag(gam) @ S0                      # A of Eq. 6
+            vp = np.linalg.solve(A, q)
+            vm = S0 @ vp                                     # Eq. 5
+            out[b, f] = (vp - vm) / Z0
+    return out
+
+
+# ---------------------------------------------------------------------------
+# textbook references used by the pins
+# ---------------------------------------------------------------------------
+
+def polygon_axis_bz(N: int, Rc: float, z: float, I: float = 1.0) -> float:
+    """On-axis z-field of a regular N-gon of circumradius Rc carrying I."""
+    s = Rc * math.sin(math.pi / N)
+    h = Rc * math.cos(math.pi / N)
+    return N * MU0 * I * s * h / (2.0 * math.pi * (h * h + z * z) * math.sqrt(Rc * Rc + z * z))
+
+
+def circle_axis_bz(R: float, z: float, I: float = 1.0) -> float:
+    return MU0 * I * R * R / (2.0 * (R * R + z * z) ** 1.5)
+
+
+def coaxial_circles_mutual(R1: float, R2: float, d: float) -> float:
+    """Maxwell's mutual inductance of two coaxial circles at axial distance d,
+    complete elliptic integrals K, E (scipy uses parameter m = k^2)."""
+    from scipy.special import ellipk, ellipe
+    k2 = 4.0 * R1 * R2 / ((R1 + R2) ** 2 + d * d)
+    k = math.sqrt(k2)
+    return MU0 * math.sqrt(R1 * R2) * ((2.0 / k - k) * ellipk(k2) - (2.0 / k) * ellipe(k2))

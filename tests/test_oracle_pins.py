@@ -1,0 +1,325 @@
+"""Pins of the FP64 oracle against closed forms, brute-force quadrature,
+invariants and the paper's own S-parameter equations (Eq. 3-7).
+
+Each test checks the oracle against something other than itself, so that a
+dropped term, a wrong sign or index, or a transposed operand fails here.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _rel(a, b):
+    a = np.asarray(a); b = np.asarray(b)
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+# ---------------------------------------------------------------- geometry
+
+def test_vector_area_square_and_polygon():
+    g = W.square_array(2, 2, 0.03, 0.035, 32)
+    np.testing.assert_allclose(O.vector_area_z(g.verts, g.seg_off), 0.03 ** 2, rtol=1e-14)
+    c = W.single_circle(0.05, 64)
+    exact = 0.5 * 64 * 0.05 ** 2 * math.sin(2 * math.pi / 64)
+    np.testing.assert_allclose(O.vector_area_z(c.verts, c.seg_off), exact, rtol=1e-14)
+    # clockwise loop has negative area
+    v = c.verts[::-1].copy()
+    assert O.vector_area_z(v, c.seg_off)[0] < 0
+
+
+# ---------------------------------------------------------------- G (T1-T3)
+
+def test_T1_segment_closed_form_vs_quadrature():
+    rng = np.random.default_rng(1)
+    for _ in range(20):
+        x1 = rng.uniform(-0.02, 0.02, 3); x2 = rng.uniform(-0.02, 0.02, 3)
+        p = rng.uniform(-0.05, 0.05, (16, 3)); p[:, 2] += 0.03 * np.sign(p[:, 2] + 1e-9)
+        cf = O.bz_segment(p, x1, x2)
+        q = O.bz_segment_quadrature(p, x1, x2, order=48, panels=16)
+        np.testing.assert_allclose(cf, q, rtol=1e-10, atol=1e-12 * np.abs(q).max())
+
+
+def test_T1_sign_right_hand_rule():
+    # current along +x at y=0; a point at y=-1 lies below: B_z < 0 there
+    bz = O.bz_segment(np.array([0.0, -1.0, 0.0]), np.array([-1.0, 0, 0]), np.array([1.0, 0, 0]))
+    assert bz < 0
+    # infinite-wire limit mu0 I / (2 pi d)
+    bz = O.bz_segment(np.array([0.0, 0.1, 0.0]), np.array([-1e4, 0, 0]), np.array([1e4, 0, 0]))
+    np.testing.assert_allclose(bz, O.MU0 / (2 * math.pi * 0.1), rtol=1e-9)
+
+
+@pytest.mark.parametrize("N", [3, 4, 7, 64])
+@pytest.mark.parametrize("z", [0.0, 0.013, -0.04])
+def test_T2_polygon_on_axis(N, z):
+    g = W._pack([W.regular_polygon(0.05, N)], 1e-3, 0.5, 1, 1, 0.0)
+    G = O.field_matrix(g.verts, g.seg_off, np.array([[0.0, 0.0, z]]))
+    np.testing.assert_allclose(G[0, 0], O.polygon_axis_bz(N, 0.05, z), rtol=1e-13)
+
+
+def test_T2_circle_limit():
+    # O(1/N^2) approach to mu0 R^2 / (2 (R^2+z^2)^1.5)
+    errs = []
+    for N in (64, 128, 256):
+        g = W._pack([W.regular_polygon(0.05, N)], 1e-3, 0.5, 1, 1, 0.0)
+        G = O.field_matrix(g.verts, g.seg_off, np.array([[0.0, 0.0, 0.02]]))
+        errs.append(abs(G[0, 0] / O.circle_axis_bz(0.05, 0.02) - 1))
+    assert errs[0] < 6e-4
+    assert 3.5 < errs[0] / errs[1] < 4.5 and 3.5 < errs[1] / errs[2] < 4.5
+
+
+def test_T3_square_on_axis_subdivided():
+    s = 0.03
+    for nseg in (4, 32):
+        g = W.square_array(1, 1, s, 0.0, nseg)
+        for z in (0.0, 0.01, 0.03):
+            G = O.field_matrix(g.verts, g.seg_off, np.array([[0.0, 0.0, z]]))
+            h = s / 2
+            ref = 2 * O.MU0 * h * h / (math.pi * (h * h + z * z) * math.sqrt(2 * h * h + z * z))
+            np.testing.assert_allclose(G[0, 0], ref, rtol=1e-13)
+
+
+def test_G_translation_and_superposition():
+    # a 2x1 array: loop 1's column equals loop 0's column at shifted points
+    g = W.square_array(2, 1, 0.03, 0.035, 32)
+    rng = np.random.default_rng(2)
+    p = W.random_points(rng, 64, 0.2, 0.005, 0.04)
+    G = O.field_matrix(g.verts, g.seg_off, p)
+    shift = np.array([0.035, 0.0, 0.0])
+    G0s = O.field_matrix(g.verts, g.seg_off, p - shift)
+    np.testing.assert_allclose(G[:, 1], G0s[:, 0], rtol=1e-12, atol=1e-18)
+
+
+# ---------------------------------------------------------------- M (T4-T7)
+
+def _brute_neumann(x1, x2, y1, y2, a, order=40, panels=24):
+    """2-D composite Gauss-Legendre of dl.dl'/sqrt(|r-r'|^2+a^2)."""
+    xg, wg = np.polynomial.legendre.leggauss(order)
+    t = ((np.arange(panels)[:, None] + 0.5 * (xg[None, :] + 1)) / panels).ravel()
+    w = np.tile(0.5 * wg / panels, panels)
+    P = x1[None, :] + t[:, None] * (x2 - x1)[None, :]
+    Q = y1[None, :] + t[:, None] * (y2 - y1)[None, :]
+    d = P[:, None, :] - Q[None, :, :]
+    ker = 1.0 / np.sqrt(np.sum(d * d, axis=-1) + a * a)
+    return O.MU0_4PI * float(np.dot(x2 - x1, y2 - y1)) * float(w @ ker @ w)
+
+
+def test_T4_parallel_and_general_pairs_vs_brute_force():
+    rng = np.random.default_rng(4)
+    for _ in range(12):
+        # parallel filaments with an offset, both orientations
+        u = rng.normal(size=3); u /= np.linalg.norm(u)
+        x1 = rng.uniform(-0.01, 0.01, 3); x2 = x1 + 0.02 * u
+        off = rng.normal(size=3); off -= off.dot(u) * u; off *= 0.01 / np.linalg.norm(off)
+        y1 = x1 + off + rng.uniform(-0.01, 0.01) * u
+        y2 = y1 + rng.choice([-1, 1]) * rng.uniform(0.005, 0.03) * u
+        np.testing.assert_allclose(O.neumann_segments(x1, x2, y1, y2),
+                                   _brute_neumann(x1, x2, y1, y2, 0.0), rtol=1e-10)
+        # arbitrary angle, separated
+        y1 = rng.uniform(-0.01, 0.01, 3) + np.array([0, 0, 0.015])
+        y2 = y1 + rng.uniform(-0.02, 0.02, 3)
+        np.testing.assert_allclose(O.neumann_segments(x1, x2, y1, y2),
+                                   _brute_neumann(x1, x2, y1, y2, 0.0), rtol=1e-10)
+        # arbitrary angle with the reduced kernel, sharing a vertex
+        y1 = x2.copy(); y2 = x2 + 0.01 * rng.normal(size=3)
+        np.testing.assert_allclose(O.neumann_segments(x1, x2, y1, y2, 2e-3),
+                                   _brute_neumann(x1, x2, y1, y2, 2e-3, panels=64), rtol=1e-9)
+
+
+def test_T4_perpendicular_is_zero_and_collinear_limit():
+    z = O.neumann_segments([0, 0, 0], [1, 0, 0], [0.5, 0.2, 0], [0.5, 0.9, 0])
+    assert z == 0.0
+    # collinear, separated: the d->0 limit equals the brute-force integral
+    x1, x2 = np.zeros(3), np.array([0.01, 0, 0])
+    y1, y2 = np.array([0.015, 0, 0]), np.array([0.04, 0, 0])
+    np.testing.assert_allclose(O.neumann_segments(x1, x2, y1, y2),
+                               _brute_neumann(x1, x2, y1, y2, 0.0, panels=48), rtol=1e-10)
+    # ... and the nearly-collinear formula approaches it
+    y1b, y2b = y1 + [0, 1e-7, 0], y2 + [0, 1e-7, 0]
+    np.testing.assert_allclose(O.neumann_segments(x1, x2, y1b, y2b),
+                               O.neumann_segments(x1, x2, y1, y2), rtol=1e-8)
+
+
+def test_T5_square_self_inductance_brute_force():
+    s, a = 0.03, 1e-3
+    g = W.square_array(1, 1, s, 0.0, 32)
+    L = O.inductance_matrix_fast(g.verts, g.seg_off, g.wire_a)[0, 0]
+    # brute force: 2-D quadrature of the reduced kernel around the whole loop
+    xg, wg = np.polynomial.legendre.leggauss(16)
+    panels = 96
+    t = ((np.arange(panels)[:, None] + 0.5 * (xg[None, :] + 1)) / panels).ravel()
+    w = np.tile(0.5 * wg / panels, panels) * s
+    h = s / 2
+    sides = [(np.array([-h, -h]), np.array([1.0, 0])), (np.array([h, -h]), np.array([0, 1.0])),
+             (np.array([h, h]), np.array([-1.0, 0])), (np.array([-h, h]), np.array([0, -1.0]))]
+    pts = np.concatenate([o[None, :] + s * t[:, None] * d[None, :] for o, d in sides])
+    dirs = np.concatenate([np.repeat(d[None, :], t.size, 0) for _, d in sides])
+    ww = np.tile(w, 4)
+    diff = pts[:, None, :] - pts[None, :, :]
+    ker = (dirs @ dirs.T) / np.sqrt(np.sum(diff * diff, -1) + a * a)
+    brute = O.MU0_4PI * float(ww @ ker @ ww)
+    np.testing.assert_allclose(L, brute, rtol=2e-9)
+    with open(os.path.join(GOLDEN, "inductance.json")) as f:
+        gold = json.load(f)
+    np.testing.assert_allclose(L, gold["square_3cm_a1mm_self_H"], rtol=1e-12)
+
+
+def test_T6_polygon_self_inductance_tends_to_maxwell_circle():
+    R, a = 0.05, 1e-3
+    ref = O.coaxial_circles_mutual(R, R, a)
+    errs = []
+    for N in (32, 64, 128):
+        v = W.regular_polygon(R, N)
+        b = np.roll(v, -1, 0)
+        # rotational symmetry: every segment sees the same row sum
+        L = N * sum(O.neumann_segments(v[0], b[0], v[t], b[t], a) for t in range(N))
+        errs.append(abs(L / ref - 1))
+    assert errs[1] < 1.2e-3
+    assert 3.5 < errs[0] / errs[1] < 4.5 and 3.5 < errs[1] / errs[2] < 4.5
+    # the full matrix routine agrees with the symmetric row sum
+    g = W.single_circle(R, 64, a)
+    M = O.inductance_matrix(g.verts, g.seg_off, g.wire_a)
+    v = W.regular_polygon(R, 64); b = np.roll(v, -1, 0)
+    Lrow = 64 * sum(O.neumann_segments(v[0], b[0], v[t], b[t], a) for t in range(64))
+    np.testing.assert_allclose(M[0, 0], Lrow, rtol=1e-11)
+    # thin-wire asymptote mu0 R (ln(8R/a) - 2)
+    np.testing.assert_allclose(ref, O.MU0 * R * (math.log(8 * R / a) - 2), rtol=2e-3)
+
+
+def test_T7_reciprocity_and_flux_form():
+    g = W.square_array(3, 2, 0.03, 0.035, 32)
+    M = O.inductance_matrix_fast(g.verts, g.seg_off, g.wire_a)
+    np.testing.assert_allclose(M, M.T, rtol=1e-12, atol=0)
+    Ms = O.inductance_matrix(g.verts, g.seg_off, g.wire_a)
+    np.testing.assert_allclose(M, Ms, rtol=1e-12)
+    # flux of loop l's Biot-Savart field through the square of loop k (k != l)
+    xg, wg = np.polynomial.legendre.leggauss(20)
+    panels = 6
+    t = ((np.arange(panels)[:, None] + 0.5 * (xg[None, :] + 1)) / panels).ravel() - 0.5
+    w = np.tile(0.5 * wg / panels, panels) * 0.03
+    for k, l in [(0, 1), (0, 4), (2, 3), (5, 0)]:
+        c = g.loop(k)[:, :2].mean(axis=0)
+        X, Y = np.meshgrid(c[0] + 0.03 * t, c[1] + 0.03 * t, indexing="ij")
+        pts = np.stack([X.ravel(), Y.ravel(), np.zeros(X.size)], 1)
+        G = O.field_matrix(g.verts, g.seg_off, pts)
+        flux = float(np.outer(w, w).ravel() @ G[:, l])
+        np.testing.assert_allclose(flux, M[k, l], rtol=1e-7)
+    # coplanar neighbours couple negatively
+    assert M[0, 1] < 0
+
+
+# ---------------------------------------------------------------- circuit (T8, T9)
+
+def _small_problem(nx=3, ny=2, B=3, F=2, P=50, seed=0):
+    wl = W.small_array(nx, ny, B, 8, n_freq=F, seed=seed)
+    rng = np.random.default_rng(seed)
+    pts = W.random_points(rng, P, 0.12, 0.005, 0.03)
+    g = wl.geom
+    G = O.field_matrix(g.verts, g.seg_off, pts)
+    M = O.inductance_matrix_fast(g.verts, g.seg_off, g.wire_a)
+    Phi = O.flux(g.verts, g.seg_off, wl.bext_z)
+    T = rng.uniform(0, 2e-7, P)
+    return G, M, g.R, Phi, wl.C, wl.omega, T
+
+
+def test_T8_single_loop_resonance():
+    g = W.single_circle()
+    M = O.inductance_matrix(g.verts, g.seg_off, g.wire_a)
+    L = M[0, 0]
+    w = 2 * math.pi * 128e6
+    Cr = 1.0 / (w * w * L)
+    Z = O.impedance(M, g.R, np.array([Cr]), w)
+    assert abs(Z[0, 0].imag) < 1e-12 * abs(w * L)
+    Phi = O.flux(g.verts, g.seg_off, 1e-6)
+    I = O.currents(M, g.R, Phi, np.array([[Cr]]), np.array([w]))[0, 0, 0]
+    np.testing.assert_allclose(I, -1j * w * Phi[0] / g.R[0], rtol=1e-12)
+    # phase of I sweeps through pi across the resonance
+    Cs = Cr * np.array([0.5, 0.9, 1.1, 2.0])
+    Is = O.currents(M, g.R, Phi, Cs[:, None], np.array([w]))[:, 0, 0]
+    ph = np.unwrap(np.angle(Is))
+    assert abs(abs(ph[-1] - ph[0]) - math.pi) < 0.2
+    # Lenz: with a large capacitance the loop current opposes the applied flux
+    Ib = O.currents(M, g.R, Phi, np.array([[1e-6]]), np.array([w]))[0, 0, 0]
+    assert Ib.real < 0
+
+
+def test_T9_sparameter_route_equals_impedance_solve():
+    G, M, R, Phi, C, om, T = _small_problem()
+    Iz = O.currents(M, R, Phi, C, om)
+    Is = O.sform_currents(M, R, Phi, C, om)
+    assert _rel(Is, Iz) < 1e-12
+    # and through Eq. 7 the fields agree
+    assert _rel(O.field(G, Is), O.field(G, Iz)) < 1e-12
+
+
+# ---------------------------------------------------------------- field, loss, gradient (T10-T12)
+
+def test_T10_linearity_and_dot_product():
+    G, M, R, Phi, C, om, T = _small_problem()
+    I1 = O.currents(M, R, Phi, C, om)
+    I2 = O.currents(M, R, 2.5 * Phi, C, om)
+    np.testing.assert_allclose(I2, 2.5 * I1, rtol=1e-12)
+    rng = np.random.default_rng(5)
+    w = rng.normal(size=G.shape[0]) + 1j * rng.normal(size=G.shape[0])
+    i = I1[0, 0]
+    lhs = np.vdot(G.T @ np.conj(w), np.conj(i))
+    rhs = np.vdot(np.conj(w), np.conj(G @ i))
+    np.testing.assert_allclose(lhs, rhs, rtol=1e-12)
+
+
+def test_loss_weights_are_conjugate_derivative():
+    rng = np.random.default_rng(3)
+    B = rng.normal(size=(1, 2, 7)) + 1j * rng.normal(size=(1, 2, 7))
+    T = rng.uniform(0, 1, 7)
+    for mode in (O.LOSS_MAG, O.LOSS_COMPLEX):
+        w = O.loss_weights(B, T, mode)
+        h = 1e-7
+        for idx in [(0, 0, 0), (0, 1, 4)]:
+            e = np.zeros_like(B); e[idx] = h
+            dre = (O.loss(B + e, T, mode) - O.loss(B - e, T, mode))[0] / (2 * h)
+            dim = (O.loss(B + 1j * e, T, mode) - O.loss(B - 1j * e, T, mode))[0] / (2 * h)
+            # dL/dB_re = 2 Re w, dL/dB_im = 2 Im w
+            np.testing.assert_allclose([dre, dim], [2 * w[idx].real, 2 * w[idx].imag], rtol=1e-6)
+    z = np.zeros((1, 1, 3), complex)
+    assert np.all(O.loss_weights(z, np.ones(3)) == 0)
+
+
+@pytest.mark.parametrize("mode", [O.LOSS_MAG, O.LOSS_COMPLEX])
+def test_T11_adjoint_equals_forward_sensitivity_and_fd(mode):
+    G, M, R, Phi, C, om, T = _small_problem(B=2, F=2)
+    ga = O.grad_adjoint(G, M, R, Phi, C, om, T, mode)
+    gf = O.grad_forward_sensitivity(G, M, R, Phi, C, om, T, mode)
+    assert _rel(ga, gf) < 1e-12
+    gd = O.grad_fd(G, M, R, Phi, C, om, T, h=1e-15, mode=mode)
+    assert _rel(ga, gd) < 1e-6
+
+
+def test_backward_from_field_grad_matches_loss_gradient():
+    G, M, R, Phi, C, om, T = _small_problem(B=2, F=3)
+    I = O.currents(M, R, Phi, C, om)
+    Bz = O.field(G, I)
+    gBz = 2 * O.loss_weights(Bz, T)
+    np.testing.assert_allclose(O.backward_from_field_grad(G, M, R, C, om, I, gBz),
+                               O.grad_adjoint(G, M, R, Phi, C, om, T), rtol=1e-12)
+
+
+def test_T12_gram_identity_complex_mode():
+    G, M, R, Phi, C, om, T = _small_problem(B=2, F=2, P=80)
+    I = O.currents(M, R, Phi, C, om)
+    L = O.loss(O.field(G, I), T, O.LOSS_COMPLEX)
+    H = G.T @ G
+    g = G.T @ T
+    P = G.shape[0]
+    for b in range(C.shape[0]):
+        acc = 0.0
+        for f in range(om.shape[0]):
+            i = I[b, f]
+            acc += (np.real(np.conj(i) @ H @ i) - 2 * np.real(g @ i) + T @ T) / P
+        np.testing.assert_allclose(L[b], acc / om.shape[0], rtol=1e-10)
