@@ -1,0 +1,180 @@
+/*
+ * cosim.h -- C ABI of the MI355X (gfx950) library for the capacitance -> B_z
+ * map of reconfigurable resonant loop arrays and its gradient.
+ *
+ * The computed quantities follow the paper "Differentiable Cosimulator for
+ * Electrically Reconfigurable Structures" (arXiv 2503.18479):
+ *   - forward problem C -> B and the MSE inverse problem: Sec. II, Eq. 1;
+ *   - RC load Z_C = R - j/(wC): Sec. III, Eq. 2; loop impedance
+ *     Z = R + jwL - j/(wC) with L and mutual coupling M: Sec. IV-A, Eq. 11;
+ *   - the quasi-static model "circuit model + Biot-Savart law": Sec. I-A;
+ *   - the wave-ratio solve of Eq. 6 is used in its impedance form
+ *     (R + jwM + 1/(jwC)) I = -jw Phi_ext, which reaches the same currents;
+ *   - field superposition B = G I: Sec. III, Eq. 7 (z-component);
+ *   - gradient through the solve, d(A^-1) = -A^-1 dA A^-1: Sec. III, Eq. 8-10.
+ *
+ * Conventions for every call:
+ *   - Units are SI (m, F, ohm, rad/s, T).  Arrays are row-major.
+ *   - Complex arrays are interleaved (re, im): complex128 = 2 doubles,
+ *     complex64 = 2 floats, as torch.complex128 / torch.complex64 store them.
+ *   - Pointers with the suffix _d are device pointers (HIP device memory of
+ *     the device current when the plan was assembled); all others are host.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  All device work
+ *     of a call is enqueued on it; calls return without synchronising unless
+ *     stated.
+ *   - The caller owns every buffer it passes; the library never frees or
+ *     keeps them past the call, and never writes to inputs.  The library owns
+ *     the geometry and plan objects and the device memory inside a plan.
+ *   - Return value: COSIM_OK (0) or a negative cosim_status.  Argument and
+ *     shape errors are detected on the host before any device work is
+ *     enqueued; cosim_last_error() then describes the problem.  Numerical
+ *     trouble in one (configuration, frequency) system is not a call error:
+ *     it sets bits in that system's status word and NaN outputs for it; the
+ *     rest of the batch is unaffected.
+ *   - Threading: geometry objects are immutable after creation and may be
+ *     shared.  A plan may be used by one host thread and one stream at a time
+ *     (its workspace is reused by every call).
+ */
+#ifndef COSIM_H
+#define COSIM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum cosim_status {
+    COSIM_OK = 0,
+    COSIM_EINVAL = -1,       /* bad argument, shape or pointer */
+    COSIM_ENOMEM = -2,       /* device or host allocation failed */
+    COSIM_EDEVICE = -3,      /* a HIP runtime call failed */
+    COSIM_EUNSUPPORTED = -4  /* valid request outside what this build implements */
+};
+
+/* Arithmetic used for the superposition B = G I and its adjoint G^T w.
+ * Z, the solves, the loss reduction and the gradient are always FP64. */
+enum cosim_precision {
+    COSIM_FP64 = 0,   /* FP64 matrix cores (v_mfma_f64) */
+    COSIM_FP32 = 1,   /* FP32 matrix cores, FP32 accumulation */
+    COSIM_BF16X3 = 2  /* bf16 hi/lo split of both operands, 3 products, FP32 accumulation */
+};
+
+/* Loss of Eq. 1 per configuration b, mean over frequencies f and points p:
+ *   MAG:     L_b = 1/(F P) sum_{f,p} (|B_z| - T_p)^2   (magnitude targets)
+ *   COMPLEX: L_b = 1/(F P) sum_{f,p} |B_z - T_p|^2                          */
+enum cosim_loss { COSIM_LOSS_MAG = 0, COSIM_LOSS_COMPLEX = 1 };
+
+/* Per-system status bits written to status_d[b*F + f]. */
+enum cosim_sys_status {
+    COSIM_SYS_BAD_INPUT = 1,  /* C_k or omega is zero or not finite (outputs NaN) */
+    COSIM_SYS_SINGULAR = 2,   /* zero pivot in the elimination (outputs NaN) */
+    COSIM_SYS_NONFINITE = 4,  /* result not finite */
+    COSIM_SYS_NEGATIVE_C = 8  /* some C_k < 0: accepted (the feasible set is unbounded), flagged */
+};
+
+typedef struct cosim_geom *cosim_geom_t;
+typedef struct cosim_plan *cosim_plan_t;
+
+/* Human-readable description of the last error on the calling thread. */
+const char *cosim_last_error(void);
+
+/* Library ABI version (currently 1). */
+int cosim_version(void);
+
+/* --------------------------------------------------------------------------
+ * Geometry: n_loops closed polygonal wire loops, one tunable capacitor each.
+ *   seg_off [n_loops+1] int32: loop k owns vertices seg_off[k]..seg_off[k+1]-1
+ *                       (seg_off[0] = 0, each loop >= 3 vertices);
+ *   verts   [V][3] double: vertices, V = seg_off[n_loops]; segment s of loop
+ *                       k joins vertex s to s+1 and the last vertex back to
+ *                       the first.  Positive loop current circulates in vertex
+ *                       order (counter-clockwise seen from +z gives +B_z
+ *                       inside the loop);
+ *   wire_a  [n_loops] double > 0: wire radius (regularises the self term);
+ *   R       [n_loops] double >= 0: series resistance of each loop's RC load
+ *                       (Eq. 2).
+ * All inputs are host memory and are copied.  Loops may not touch each other.
+ * -------------------------------------------------------------------------- */
+int cosim_geometry_create(int n_loops, const int32_t *seg_off, const double *verts,
+                          const double *wire_a, const double *R, cosim_geom_t *out);
+int cosim_geometry_destroy(cosim_geom_t g);
+/* Loop count and total vertex count. */
+int cosim_geometry_size(cosim_geom_t g, int *n_loops, int *n_verts);
+
+/* --------------------------------------------------------------------------
+ * Assembly (once per geometry and point set).  Runs on the current device:
+ *   G[p][k]  z-field at point p per ampere in loop k (Biot-Savart law,
+ *            closed form per straight segment), stored FP64 and rounded to
+ *            FP32 and to bf16 hi/lo for the mixed-precision modes;
+ *   M[k][l]  Neumann mutual inductance between loop axes (k != l); the
+ *            diagonal uses the reduced kernel 1/sqrt(|r-r'|^2 + a_k^2)
+ *            (thin-wire surface-current self inductance);
+ *   Phi[k]   flux of the uniform incident field bext_z through loop k.
+ * pts_d [P][3] double, device.  P >= 1.  Synchronises `stream` before return.
+ * The plan keeps its own copies; pts_d may be freed afterwards.
+ * -------------------------------------------------------------------------- */
+int cosim_assemble(cosim_geom_t g, int P, const double *pts_d, double bext_z, void *stream,
+                   cosim_plan_t *out);
+int cosim_plan_destroy(cosim_plan_t p);
+/* Loops n, points P of a plan. */
+int cosim_plan_size(cosim_plan_t p, int *n_loops, int *n_points);
+/* Pre-allocate the workspace for batches up to max_batch configurations of
+ * max_freq frequencies, so that later calls with B*F <= max_batch*max_freq
+ * allocate nothing.  Calls that need more grow the workspace themselves. */
+int cosim_plan_reserve(cosim_plan_t p, int max_batch, int max_freq);
+/* Copies of the assembled operators, for inspection and testing.
+ * G_d: device [P][n] double.  M: host [n][n] double.  phi: host [n] double. */
+int cosim_plan_copy_G(cosim_plan_t p, double *G_d, void *stream);
+int cosim_plan_copy_M(cosim_plan_t p, double *M);
+int cosim_plan_copy_phi(cosim_plan_t p, double *phi);
+
+/* --------------------------------------------------------------------------
+ * Currents (Eq. 6 in impedance form).  For every configuration b < B and
+ * frequency f < F solves
+ *     (diag(R) + j w_f M + diag(1/(j w_f C_b))) I_{b,f} = -j w_f Phi
+ * by Gauss-Jordan elimination with partial pivoting in FP64.
+ *   C_d      [B][n] double, device (farads)
+ *   omega_d  [F] double, device (rad/s)
+ *   I_d      [B][F][n] complex128, device (output, amperes)
+ *   status_d [B][F] int32, device (output, cosim_sys_status bits)
+ * -------------------------------------------------------------------------- */
+int cosim_solve(cosim_plan_t p, int B, int F, const double *C_d, const double *omega_d,
+                double *I_d, int32_t *status_d, void *stream);
+
+/* Field superposition B_z[b][f][p] = sum_k G[p][k] I[b][f][k] (Eq. 7).
+ *   I_d  [B][F][n] complex128, device
+ *   Bz_d [B][F][P] complex128 (precision FP64) or complex64 (FP32, BF16X3),
+ *        device, output.                                                      */
+int cosim_field(cosim_plan_t p, int B, int F, const double *I_d, int precision, void *Bz_d,
+                void *stream);
+
+/* Vector-Jacobian product of C -> B_z (Eq. 8-10 through the adjoint solve).
+ *   gBz_d [B][F][P] complex128, device: upstream gradient in PyTorch's
+ *         convention for a real loss L, gBz = dL/dRe(B) + j dL/dIm(B)
+ *         (= 2 dL/d conj(B));
+ *   gC_d  [B][n] double, device, output: dL/dC.
+ * The contraction G^T conj(gBz) runs in FP64; the impedance is re-factorised
+ * (Z is complex symmetric, so the same elimination serves Z^T). */
+int cosim_field_backward(cosim_plan_t p, int B, int F, const double *C_d, const double *omega_d,
+                         const double *I_d, const double *gBz_d, double *gC_d,
+                         int32_t *status_d, void *stream);
+
+/* Fused forward + loss + gradient (the optimisation step's evaluation).
+ *   T_d      [P] double, device: target field magnitudes (tesla)
+ *   loss_d   [B] double, device, output: L_b of `loss_mode`
+ *   grad_d   [B][n] double, device, output: dL_b/dC_b (may be NULL: loss only)
+ *   status_d [B][F] int32, device, output
+ * B_z is formed in registers tile by tile and never written to memory; the
+ * adjoint contraction G^T conj(w) shares each G tile with the forward
+ * product.  Solves and reductions are FP64; `precision` selects the matrix
+ * core arithmetic of the two contractions.  Deterministic: no atomics. */
+int cosim_loss_and_grad(cosim_plan_t p, int B, int F, const double *C_d, const double *omega_d,
+                        const double *T_d, int loss_mode, int precision, double *loss_d,
+                        double *grad_d, int32_t *status_d, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* COSIM_H */

@@ -1,0 +1,206 @@
+"""Python objects over the C ABI: Geometry, Plan and the autograd Function.
+
+Only argument marshalling happens here; every numerical step runs in the HIP
+kernels of libcosim.so.  Device arrays are torch tensors on the current HIP
+device, work is enqueued on torch's current stream.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Tuple
+
+import numpy as np
+import torch
+
+from ._lib import check, load_library
+
+FP64, FP32, BF16X3 = 0, 1, 2
+LOSS_MAG, LOSS_COMPLEX = 0, 1
+SYS_BAD_INPUT, SYS_SINGULAR, SYS_NONFINITE, SYS_NEGATIVE_C = 1, 2, 4, 8
+
+_PREC_NAMES = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}
+
+
+def precision_code(p) -> int:
+    if isinstance(p, str):
+        return _PREC_NAMES[p.lower()]
+    return int(p)
+
+
+def _stream() -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t: torch.Tensor, dtype: torch.dtype, shape, name: str) -> ctypes.c_void_p:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device.type != "cuda":
+        raise TypeError(f"{name} must live on the GPU (got {t.device})")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype} (got {t.dtype})")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)} (got {tuple(t.shape)})")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _host(a: np.ndarray) -> ctypes.c_void_p:
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+class Geometry:
+    """Closed polygonal loops (see include/cosim.h, cosim_geometry_create)."""
+
+    def __init__(self, verts, seg_off, wire_a, R):
+        self._lib = load_library()
+        self.verts = np.ascontiguousarray(verts, dtype=np.float64).reshape(-1, 3)
+        self.seg_off = np.ascontiguousarray(seg_off, dtype=np.int32)
+        n = int(self.seg_off.shape[0] - 1)
+        self.wire_a = np.ascontiguousarray(np.broadcast_to(wire_a, (n,)), dtype=np.float64)
+        self.R = np.ascontiguousarray(np.broadcast_to(R, (n,)), dtype=np.float64)
+        h = ctypes.c_void_p()
+        check(self._lib.cosim_geometry_create(n, _host(self.seg_off), _host(self.verts),
+                                              _host(self.wire_a), _host(self.R), ctypes.byref(h)))
+        self._h = h
+
+    @classmethod
+    def from_workload(cls, g) -> "Geometry":
+        return cls(g.verts, g.seg_off, g.wire_a, g.R)
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        return self._h
+
+    @property
+    def n(self) -> int:
+        v = ctypes.c_int()
+        check(self._lib.cosim_geometry_size(self._h, ctypes.byref(v), None))
+        return v.value
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._lib.cosim_geometry_destroy(h)
+            self._h = None
+
+
+class Plan:
+    """Assembled operators G, M, Phi for one geometry and point set."""
+
+    def __init__(self, geom: Geometry, pts: torch.Tensor, bext_z: float = 1e-6):
+        self._lib = load_library()
+        P = int(pts.shape[0])
+        ptr = _dev(pts, torch.float64, (P, 3), "pts")
+        h = ctypes.c_void_p()
+        check(self._lib.cosim_assemble(geom.handle, P, ptr, float(bext_z), _stream(),
+                                       ctypes.byref(h)))
+        self._h = h
+        self.n = geom.n
+        self.P = P
+        self.device = pts.device
+        self.bext_z = float(bext_z)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._lib.cosim_plan_destroy(h)
+            self._h = None
+
+    # -- operators ------------------------------------------------------------
+    def reserve(self, max_batch: int, max_freq: int) -> None:
+        check(self._lib.cosim_plan_reserve(self._h, int(max_batch), int(max_freq)))
+
+    def G(self) -> torch.Tensor:
+        out = torch.empty((self.P, self.n), dtype=torch.float64, device=self.device)
+        check(self._lib.cosim_plan_copy_G(self._h, ctypes.c_void_p(out.data_ptr()), _stream()))
+        return out
+
+    def M(self) -> np.ndarray:
+        out = np.empty((self.n, self.n))
+        check(self._lib.cosim_plan_copy_M(self._h, _host(out)))
+        return out
+
+    def phi(self) -> np.ndarray:
+        out = np.empty(self.n)
+        check(self._lib.cosim_plan_copy_phi(self._h, _host(out)))
+        return out
+
+    # -- path -----------------------------------------------------------------
+    def solve(self, C: torch.Tensor, omega: torch.Tensor) -> Tuple[torch.Tensor, torch.Tensor]:
+        B, F = int(C.shape[0]), int(omega.shape[0])
+        I = torch.empty((B, F, self.n), dtype=torch.complex128, device=self.device)
+        st = torch.empty((B, F), dtype=torch.int32, device=self.device)
+        check(self._lib.cosim_solve(self._h, B, F, _dev(C, torch.float64, (B, self.n), "C"),
+                                    _dev(omega, torch.float64, (F,), "omega"),
+                                    ctypes.c_void_p(I.data_ptr()), ctypes.c_void_p(st.data_ptr()),
+                                    _stream()))
+        return I, st
+
+    def field(self, I: torch.Tensor, precision=FP64) -> torch.Tensor:
+        prec = precision_code(precision)
+        B, F = int(I.shape[0]), int(I.shape[1])
+        dt = torch.complex128 if prec == FP64 else torch.complex64
+        Bz = torch.empty((B, F, self.P), dtype=dt, device=self.device)
+        check(self._lib.cosim_field(self._h, B, F, _dev(I, torch.complex128, (B, F, self.n), "I"),
+                                    prec, ctypes.c_void_p(Bz.data_ptr()), _stream()))
+        return Bz
+
+    def field_backward(self, C, omega, I, gBz) -> Tuple[torch.Tensor, torch.Tensor]:
+        B, F = int(C.shape[0]), int(omega.shape[0])
+        gC = torch.empty((B, self.n), dtype=torch.float64, device=self.device)
+        st = torch.empty((B, F), dtype=torch.int32, device=self.device)
+        check(self._lib.cosim_field_backward(
+            self._h, B, F, _dev(C, torch.float64, (B, self.n), "C"),
+            _dev(omega, torch.float64, (F,), "omega"),
+            _dev(I, torch.complex128, (B, F, self.n), "I"),
+            _dev(gBz, torch.complex128, (B, F, self.P), "gBz"),
+            ctypes.c_void_p(gC.data_ptr()), ctypes.c_void_p(st.data_ptr()), _stream()))
+        return gC, st
+
+    def loss_and_grad(self, C: torch.Tensor, omega: torch.Tensor, T: torch.Tensor,
+                      loss_mode: int = LOSS_MAG, precision=FP32, grad: bool = True,
+                      out: Optional[Tuple[torch.Tensor, torch.Tensor, torch.Tensor]] = None):
+        """Per-configuration loss, dL/dC (or None) and per-system status."""
+        prec = precision_code(precision)
+        B, F = int(C.shape[0]), int(omega.shape[0])
+        if out is None:
+            loss = torch.empty((B,), dtype=torch.float64, device=self.device)
+            g = torch.empty((B, self.n), dtype=torch.float64, device=self.device) if grad else None
+            st = torch.empty((B, F), dtype=torch.int32, device=self.device)
+        else:
+            loss, g, st = out
+        gp = ctypes.c_void_p(g.data_ptr()) if g is not None else ctypes.c_void_p()
+        check(self._lib.cosim_loss_and_grad(
+            self._h, B, F, _dev(C, torch.float64, (B, self.n), "C"),
+            _dev(omega, torch.float64, (F,), "omega"), _dev(T, torch.float64, (self.P,), "T"),
+            int(loss_mode), prec, _dev(loss, torch.float64, (B,), "loss"), gp,
+            _dev(st, torch.int32, (B, F), "status"), _stream()))
+        return loss, g, st
+
+
+class CosimField(torch.autograd.Function):
+    """B_z = f(C) with the library's hand-written adjoint as backward.
+
+    forward: cosim_solve + cosim_field; backward: cosim_field_backward, which
+    re-factorises Z (complex symmetric) and returns the real dL/dC."""
+
+    @staticmethod
+    def forward(ctx, C, plan: Plan, omega, precision=FP64):
+        Cd = C.detach().contiguous()
+        I, _ = plan.solve(Cd, omega)
+        Bz = plan.field(I, precision)
+        ctx.plan = plan
+        ctx.save_for_backward(Cd, omega, I)
+        return Bz
+
+    @staticmethod
+    def backward(ctx, gBz):
+        C, omega, I = ctx.saved_tensors
+        g = gBz.to(torch.complex128).contiguous()
+        gC, _ = ctx.plan.field_backward(C, omega, I, g)
+        return gC, None, None, None
+
+
+def cosim_field(C: torch.Tensor, plan: Plan, omega: torch.Tensor, precision=FP64) -> torch.Tensor:
+    return CosimField.apply(C, plan, omega, precision_code(precision))

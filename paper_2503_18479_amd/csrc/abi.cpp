@@ -1,0 +1,444 @@
+// Host side of the C ABI declared in include/cosim.h: argument validation,
+// geometry and plan objects, device memory, and the launch sequence of each
+// call.  Every argument check runs before any HIP call, so the error paths
+// are exercised without a GPU.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "internal.h"
+
+using namespace cosim;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                  \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return fail(COSIM_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+// Gauss-Legendre nodes and weights on [-1, 1] by Newton iteration on the
+// Legendre polynomial P_m (three-term recurrence), starting from the
+// asymptotic root estimate cos(pi (i + 3/4) / (m + 1/2)).
+GLRule make_gl_rule() {
+    GLRule r;
+    const int m = kGLOrder;
+    for (int i = 0; i < (m + 1) / 2; ++i) {
+        double x = std::cos(M_PI * (i + 0.75) / (m + 0.5));
+        double dp = 0.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = x;
+            for (int j = 2; j <= m; ++j) {
+                const double p2 = ((2.0 * j - 1.0) * x * p1 - (j - 1.0) * p0) / j;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = m * (x * p1 - p0) / (x * x - 1.0);
+            const double dx = p1 / dp;
+            x -= dx;
+            if (std::fabs(dx) < 1e-16) break;
+        }
+        double p0 = 1.0, p1 = x;
+        for (int j = 2; j <= m; ++j) {
+            const double p2 = ((2.0 * j - 1.0) * x * p1 - (j - 1.0) * p0) / j;
+            p0 = p1;
+            p1 = p2;
+        }
+        dp = m * (x * p1 - p0) / (x * x - 1.0);
+        const double w = 2.0 / ((1.0 - x * x) * dp * dp);
+        r.x[i] = -x;
+        r.w[i] = w;
+        r.x[m - 1 - i] = x;
+        r.w[m - 1 - i] = w;
+    }
+    return r;
+}
+
+template <typename T>
+void dfree(T *&p) {
+    if (p) (void)hipFree((void *)p);
+    p = nullptr;
+}
+
+void plan_free_workspace(cosim_plan *p) {
+    dfree(p->I_ws);
+    dfree(p->rpart);
+    dfree(p->lpart);
+    dfree(p->gsys);
+    p->cap_systems = 0;
+    p->cap_chunks = 0;
+}
+
+int check_device(const cosim_plan *p) {
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != p->device)
+        return fail(COSIM_EINVAL, "current device %d differs from the plan's device %d", dev,
+                    p->device);
+    return COSIM_OK;
+}
+
+// Make room for `systems` systems and `chunks` P-chunks of partial sums.
+int ensure_workspace(cosim_plan *p, size_t systems, int chunks) {
+    if (systems <= p->cap_systems && chunks <= p->cap_chunks) return COSIM_OK;
+    const size_t ns = std::max(systems, p->cap_systems);
+    const int nc = std::max(chunks, p->cap_chunks);
+    plan_free_workspace(p);
+    const size_t n = (size_t)p->n, NP = (size_t)p->NP;
+    if (hipMalloc((void **)&p->I_ws, ns * n * sizeof(double2)) != hipSuccess ||
+        hipMalloc((void **)&p->rpart, (size_t)nc * ns * NP * sizeof(double2)) != hipSuccess ||
+        hipMalloc((void **)&p->lpart, (size_t)nc * ns * sizeof(double)) != hipSuccess ||
+        hipMalloc((void **)&p->gsys, ns * n * sizeof(double)) != hipSuccess) {
+        plan_free_workspace(p);
+        (void)hipGetLastError();
+        return fail(COSIM_ENOMEM, "workspace allocation for %zu systems x %d chunks failed", ns,
+                    nc);
+    }
+    p->cap_systems = ns;
+    p->cap_chunks = nc;
+    return COSIM_OK;
+}
+
+// P-chunk count of the fused kernels: enough workgroups to fill the chip
+// several times over, bounded by the number of 64-row tiles.
+int choose_chunks(const cosim_plan *p, Prec prec, size_t S) {
+    const size_t per_block = (size_t)fused_systems_per_block(prec, p->NP);
+    const size_t bx = (S + per_block - 1) / per_block;
+    const size_t target = 2048;  // >= 8 workgroups per CU on 256 CUs
+    size_t c = (target + bx - 1) / bx;
+    const size_t tiles = (size_t)p->P_pad / kPTile;
+    c = std::min(c, tiles);
+    c = std::max<size_t>(c, 1);
+    c = std::min<size_t>(c, 64);
+    return (int)c;
+}
+
+int check_batch(const cosim_plan *p, int B, int F) {
+    if (!p) return fail(COSIM_EINVAL, "null plan");
+    if (B < 0 || F < 0) return fail(COSIM_EINVAL, "negative batch (%d) or frequency count (%d)", B, F);
+    if ((size_t)B * (size_t)F > (size_t)INT32_MAX)
+        return fail(COSIM_EINVAL, "B*F = %lld exceeds the system limit", (long long)B * F);
+    return COSIM_OK;
+}
+
+int check_prec(int precision) {
+    if (precision < COSIM_FP64 || precision > COSIM_BF16X3)
+        return fail(COSIM_EINVAL, "unknown precision %d", precision);
+    return COSIM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *cosim_last_error(void) { return g_err; }
+
+int cosim_version(void) { return 1; }
+
+int cosim_geometry_create(int n_loops, const int32_t *seg_off, const double *verts,
+                          const double *wire_a, const double *R, cosim_geom_t *out) {
+    if (!out) return fail(COSIM_EINVAL, "out is null");
+    *out = nullptr;
+    if (n_loops < 1) return fail(COSIM_EINVAL, "n_loops must be >= 1 (got %d)", n_loops);
+    if (!seg_off || !verts || !wire_a || !R) return fail(COSIM_EINVAL, "null input array");
+    if (seg_off[0] != 0) return fail(COSIM_EINVAL, "seg_off[0] must be 0");
+    for (int k = 0; k < n_loops; ++k)
+        if (seg_off[k + 1] - seg_off[k] < 3)
+            return fail(COSIM_EINVAL, "loop %d has fewer than 3 vertices", k);
+    const int V = seg_off[n_loops];
+    for (int i = 0; i < 3 * V; ++i)
+        if (!std::isfinite(verts[i])) return fail(COSIM_EINVAL, "vertex coordinate %d is not finite", i);
+    for (int k = 0; k < n_loops; ++k) {
+        if (!(wire_a[k] > 0.0) || !std::isfinite(wire_a[k]))
+            return fail(COSIM_EINVAL, "wire radius of loop %d must be positive and finite", k);
+        if (!(R[k] >= 0.0) || !std::isfinite(R[k]))
+            return fail(COSIM_EINVAL, "resistance of loop %d must be >= 0 and finite", k);
+    }
+    cosim_geom *g = new (std::nothrow) cosim_geom;
+    if (!g) return fail(COSIM_ENOMEM, "host allocation failed");
+    g->n = n_loops;
+    g->V = V;
+    g->seg_off.assign(seg_off, seg_off + n_loops + 1);
+    g->verts.assign(verts, verts + 3 * (size_t)V);
+    g->wire_a.assign(wire_a, wire_a + n_loops);
+    g->R.assign(R, R + n_loops);
+    g->area_z.resize(n_loops);
+    // z-component of each loop's vector area (shoelace); the flux of a uniform
+    // B_ext,z through the loop is exactly B_ext,z times this
+    for (int k = 0; k < n_loops; ++k) {
+        double acc = 0.0;
+        const int v0 = seg_off[k], v1 = seg_off[k + 1];
+        for (int v = v0; v < v1; ++v) {
+            const int w = (v + 1 == v1) ? v0 : v + 1;
+            acc += g->verts[3 * v] * g->verts[3 * w + 1] - g->verts[3 * w] * g->verts[3 * v + 1];
+        }
+        g->area_z[k] = 0.5 * acc;
+    }
+    *out = g;
+    return COSIM_OK;
+}
+
+int cosim_geometry_destroy(cosim_geom_t g) {
+    delete g;
+    return COSIM_OK;
+}
+
+int cosim_geometry_size(cosim_geom_t g, int *n_loops, int *n_verts) {
+    if (!g) return fail(COSIM_EINVAL, "null geometry");
+    if (n_loops) *n_loops = g->n;
+    if (n_verts) *n_verts = g->V;
+    return COSIM_OK;
+}
+
+int cosim_assemble(cosim_geom_t g, int P, const double *pts_d, double bext_z, void *stream,
+                   cosim_plan_t *out) {
+    if (!out) return fail(COSIM_EINVAL, "out is null");
+    *out = nullptr;
+    if (!g) return fail(COSIM_EINVAL, "null geometry");
+    if (P < 1) return fail(COSIM_EINVAL, "P must be >= 1 (got %d)", P);
+    if (!pts_d) return fail(COSIM_EINVAL, "pts_d is null");
+    if (!std::isfinite(bext_z)) return fail(COSIM_EINVAL, "bext_z is not finite");
+    if (g->n > kMaxLoops)
+        return fail(COSIM_EUNSUPPORTED, "%d loops: this build supports up to %d loops per plan",
+                    g->n, kMaxLoops);
+    hipStream_t st = (hipStream_t)stream;
+    cosim_plan *p = new (std::nothrow) cosim_plan;
+    if (!p) return fail(COSIM_ENOMEM, "host allocation failed");
+    p->n = g->n;
+    p->NP = padded_loops(g->n);
+    p->P = P;
+    p->P_pad = (P + kPTile - 1) / kPTile * kPTile;
+    p->bext_z = bext_z;
+    p->phi_h.resize(g->n);
+    for (int k = 0; k < g->n; ++k) p->phi_h[k] = bext_z * g->area_z[k];
+
+    int32_t *seg_d = nullptr;
+    double *verts_d = nullptr, *wa_d = nullptr;
+    auto cleanup = [&](int code) {
+        dfree(seg_d);
+        dfree(verts_d);
+        dfree(wa_d);
+        if (code != COSIM_OK) {
+            cosim_plan_destroy(p);
+            (void)hipGetLastError();
+        }
+        return code;
+    };
+    if (hipGetDevice(&p->device) != hipSuccess) return cleanup(fail(COSIM_EDEVICE, "hipGetDevice failed"));
+    const size_t gsz = (size_t)p->P_pad * p->NP;
+    const size_t n = (size_t)g->n;
+    if (hipMalloc((void **)&p->G64, gsz * sizeof(double)) != hipSuccess ||
+        hipMalloc((void **)&p->G32, gsz * sizeof(float)) != hipSuccess ||
+        hipMalloc((void **)&p->Ghi, gsz * sizeof(uint16_t)) != hipSuccess ||
+        hipMalloc((void **)&p->Glo, gsz * sizeof(uint16_t)) != hipSuccess ||
+        hipMalloc((void **)&p->M_d, n * n * sizeof(double)) != hipSuccess ||
+        hipMalloc((void **)&p->phi_d, n * sizeof(double)) != hipSuccess ||
+        hipMalloc((void **)&p->R_d, n * sizeof(double)) != hipSuccess ||
+        hipMalloc((void **)&seg_d, (n + 1) * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc((void **)&verts_d, 3 * (size_t)g->V * sizeof(double)) != hipSuccess ||
+        hipMalloc((void **)&wa_d, n * sizeof(double)) != hipSuccess)
+        return cleanup(fail(COSIM_ENOMEM, "device allocation for the operators failed"));
+    hipError_t e = hipSuccess;
+#define ASM_TRY(x)                                                                      \
+    do {                                                                                \
+        e = (x);                                                                        \
+        if (e != hipSuccess)                                                            \
+            return cleanup(fail(COSIM_EDEVICE, "%s failed: %s", #x, hipGetErrorString(e))); \
+    } while (0)
+    ASM_TRY(hipMemcpyAsync(seg_d, g->seg_off.data(), (n + 1) * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    ASM_TRY(hipMemcpyAsync(verts_d, g->verts.data(), 3 * (size_t)g->V * sizeof(double), hipMemcpyHostToDevice, st));
+    ASM_TRY(hipMemcpyAsync(wa_d, g->wire_a.data(), n * sizeof(double), hipMemcpyHostToDevice, st));
+    ASM_TRY(hipMemcpyAsync(p->R_d, g->R.data(), n * sizeof(double), hipMemcpyHostToDevice, st));
+    ASM_TRY(hipMemcpyAsync(p->phi_d, p->phi_h.data(), n * sizeof(double), hipMemcpyHostToDevice, st));
+    ASM_TRY(launch_assemble_G(g->n, p->NP, P, p->P_pad, seg_d, verts_d, pts_d, p->G64, p->G32,
+                              p->Ghi, p->Glo, st));
+    ASM_TRY(launch_assemble_M(g->n, seg_d, verts_d, wa_d, make_gl_rule(), p->M_d, st));
+    p->M_h.resize(n * n);
+    ASM_TRY(hipMemcpyAsync(p->M_h.data(), p->M_d, n * n * sizeof(double), hipMemcpyDeviceToHost, st));
+    ASM_TRY(hipStreamSynchronize(st));
+#undef ASM_TRY
+    cleanup(COSIM_OK);
+    *out = p;
+    return COSIM_OK;
+}
+
+int cosim_plan_destroy(cosim_plan_t p) {
+    if (!p) return COSIM_OK;
+    dfree(p->G64);
+    dfree(p->G32);
+    dfree(p->Ghi);
+    dfree(p->Glo);
+    dfree(p->M_d);
+    dfree(p->phi_d);
+    dfree(p->R_d);
+    plan_free_workspace(p);
+    delete p;
+    return COSIM_OK;
+}
+
+int cosim_plan_size(cosim_plan_t p, int *n_loops, int *n_points) {
+    if (!p) return fail(COSIM_EINVAL, "null plan");
+    if (n_loops) *n_loops = p->n;
+    if (n_points) *n_points = p->P;
+    return COSIM_OK;
+}
+
+int cosim_plan_reserve(cosim_plan_t p, int max_batch, int max_freq) {
+    int rc = check_batch(p, max_batch, max_freq);
+    if (rc) return rc;
+    if ((rc = check_device(p))) return rc;
+    const size_t S = (size_t)max_batch * max_freq;
+    int chunks = 1;
+    for (int pr = COSIM_FP64; pr <= COSIM_BF16X3; ++pr)
+        chunks = std::max(chunks, choose_chunks(p, (Prec)pr, S));
+    return ensure_workspace(p, S, chunks);
+}
+
+int cosim_plan_copy_G(cosim_plan_t p, double *G_d, void *stream) {
+    if (!p) return fail(COSIM_EINVAL, "null plan");
+    if (!G_d) return fail(COSIM_EINVAL, "G_d is null");
+    int rc = check_device(p);
+    if (rc) return rc;
+    // the plan stores rows of NP (>= n) columns; copy the n leading columns
+    HIP_TRY(hipMemcpy2DAsync(G_d, (size_t)p->n * sizeof(double), p->G64, (size_t)p->NP * sizeof(double),
+                             (size_t)p->n * sizeof(double), (size_t)p->P, hipMemcpyDeviceToDevice,
+                             (hipStream_t)stream));
+    return COSIM_OK;
+}
+
+int cosim_plan_copy_M(cosim_plan_t p, double *M) {
+    if (!p) return fail(COSIM_EINVAL, "null plan");
+    if (!M) return fail(COSIM_EINVAL, "M is null");
+    std::memcpy(M, p->M_h.data(), p->M_h.size() * sizeof(double));
+    return COSIM_OK;
+}
+
+int cosim_plan_copy_phi(cosim_plan_t p, double *phi) {
+    if (!p) return fail(COSIM_EINVAL, "null plan");
+    if (!phi) return fail(COSIM_EINVAL, "phi is null");
+    std::memcpy(phi, p->phi_h.data(), p->phi_h.size() * sizeof(double));
+    return COSIM_OK;
+}
+
+int cosim_solve(cosim_plan_t p, int B, int F, const double *C_d, const double *omega_d,
+                double *I_d, int32_t *status_d, void *stream) {
+    int rc = check_batch(p, B, F);
+    if (rc) return rc;
+    if (!C_d || !omega_d || !I_d || !status_d) return fail(COSIM_EINVAL, "null device pointer");
+    if (B == 0 || F == 0) return COSIM_OK;
+    if ((rc = check_device(p))) return rc;
+    const int S = B * F;
+    HIP_TRY(launch_solve_forward(p->NP, p->n, S, F, p->M_d, p->R_d, p->phi_d, C_d, omega_d,
+                                 (double2 *)I_d, status_d, (hipStream_t)stream));
+    return COSIM_OK;
+}
+
+int cosim_field(cosim_plan_t p, int B, int F, const double *I_d, int precision, void *Bz_d,
+                void *stream) {
+    int rc = check_batch(p, B, F);
+    if (rc) return rc;
+    if ((rc = check_prec(precision))) return rc;
+    if (!I_d || !Bz_d) return fail(COSIM_EINVAL, "null device pointer");
+    if (B == 0 || F == 0) return COSIM_OK;
+    if ((rc = check_device(p))) return rc;
+    const int S = B * F;
+    const size_t esz = precision == COSIM_FP64 ? sizeof(double2) : sizeof(float2);
+    // grid.y is limited to 65535 systems per launch
+    for (int s0 = 0; s0 < S; s0 += 65535) {
+        const int ns = std::min(65535, S - s0);
+        HIP_TRY(launch_field((Prec)precision, p->NP, p->P, ns, p->n, p->G64,
+                             (const double2 *)I_d + (size_t)s0 * p->n,
+                             (char *)Bz_d + (size_t)s0 * p->P * esz, (hipStream_t)stream));
+    }
+    return COSIM_OK;
+}
+
+int cosim_field_backward(cosim_plan_t p, int B, int F, const double *C_d, const double *omega_d,
+                         const double *I_d, const double *gBz_d, double *gC_d,
+                         int32_t *status_d, void *stream) {
+    int rc = check_batch(p, B, F);
+    if (rc) return rc;
+    if (!C_d || !omega_d || !I_d || !gBz_d || !gC_d || !status_d)
+        return fail(COSIM_EINVAL, "null device pointer");
+    if (B == 0 || F == 0) return COSIM_OK;
+    if ((rc = check_device(p))) return rc;
+    const size_t S = (size_t)B * F;
+    if ((rc = ensure_workspace(p, S, 1))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(launch_field_backward_contract(p->NP, p->P, (int)S, p->n, p->G64,
+                                           (const double2 *)gBz_d, p->rpart, st));
+    // gBz = 2 dL/d conj(B), so conj(w) = conj(gBz)/2
+    HIP_TRY(launch_solve_adjoint(p->NP, p->n, (int)S, F, p->M_d, p->R_d, C_d, omega_d,
+                                 (const double2 *)I_d, p->rpart, 1, 0.5, p->gsys, status_d, false, st));
+    HIP_TRY(launch_reduce(p->n, B, F, 0, p->gsys, nullptr, 0.0, gC_d, nullptr, st));
+    return COSIM_OK;
+}
+
+int cosim_loss_and_grad(cosim_plan_t p, int B, int F, const double *C_d, const double *omega_d,
+                        const double *T_d, int loss_mode, int precision, double *loss_d,
+                        double *grad_d, int32_t *status_d, void *stream) {
+    int rc = check_batch(p, B, F);
+    if (rc) return rc;
+    if ((rc = check_prec(precision))) return rc;
+    if (loss_mode != COSIM_LOSS_MAG && loss_mode != COSIM_LOSS_COMPLEX)
+        return fail(COSIM_EINVAL, "unknown loss mode %d", loss_mode);
+    if (!C_d || !omega_d || !T_d || !loss_d || !status_d)
+        return fail(COSIM_EINVAL, "null device pointer");
+    if (precision == COSIM_BF16X3 && p->NP % 32 != 0)
+        return fail(COSIM_EUNSUPPORTED, "BF16X3 needs more than 16 loops in this build (n = %d)", p->n);
+    if (B == 0 || F == 0) return COSIM_OK;
+    if ((rc = check_device(p))) return rc;
+    const size_t S = (size_t)B * F;
+    const Prec prec = (Prec)precision;
+    // chunks of whole 64-row tiles; every chunk is non-empty
+    const int tiles = p->P_pad / kPTile;
+    const int tpc = (tiles + choose_chunks(p, prec, S) - 1) / choose_chunks(p, prec, S);
+    const int nchunk = (tiles + tpc - 1) / tpc;
+    if ((rc = ensure_workspace(p, S, nchunk))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(launch_solve_forward(p->NP, p->n, (int)S, F, p->M_d, p->R_d, p->phi_d, C_d, omega_d,
+                                 p->I_ws, status_d, st));
+    FusedArgs a;
+    a.G = precision == COSIM_FP64 ? (const void *)p->G64
+          : precision == COSIM_FP32 ? (const void *)p->G32
+                                    : (const void *)p->Ghi;
+    a.Glo = p->Glo;
+    a.T = T_d;
+    a.P = p->P;
+    a.P_pad = p->P_pad;
+    a.nchunk = nchunk;
+    a.rows_per_chunk = tpc * kPTile;
+    a.I = p->I_ws;
+    a.S = (int)S;
+    a.n = p->n;
+    a.rpart = p->rpart;
+    a.lpart = p->lpart;
+    const bool grad = grad_d != nullptr;
+    HIP_TRY(launch_fused(prec, p->NP, loss_mode, grad, a, st));
+    const double scale = 1.0 / ((double)F * (double)p->P);
+    if (grad)
+        HIP_TRY(launch_solve_adjoint(p->NP, p->n, (int)S, F, p->M_d, p->R_d, C_d, omega_d, p->I_ws,
+                                     p->rpart, nchunk, scale, p->gsys, status_d, true, st));
+    HIP_TRY(launch_reduce(p->n, B, F, nchunk, grad ? p->gsys : nullptr, p->lpart, scale, grad_d,
+                          loss_d, st));
+    return COSIM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,462 @@
+// Fused superposition + loss + adjoint contraction on gfx950 matrix cores.
+//
+// For every system s = (b, f) the forward product is B_z = G I (Eq. 7,
+// z-component) and the loss of Eq. 1 needs, per field point, the residual
+// weight w = dL/d conj(B); the gradient then needs r = G^T conj(w) (the
+// adjoint right-hand side of Eq. 8-10).  Both are real-split contractions
+// with the same G:
+//     forward  [P x NP] . [NP x 2S]   (columns: Re I and Im I per system)
+//     adjoint  [NP x P] . [P x 2S]
+// One workgroup (4 waves) streams a P-chunk of G through LDS in 64-row tiles;
+// each wave keeps I of its 16*NB systems as matrix-core B operands in
+// registers for the whole chunk, computes B for a 16-row sub-tile with
+// 16x16x4 MFMA (f32 or f64), turns it into w in registers, and feeds w
+// straight back as the B operand of the adjoint MFMA: the accumulator layout
+// of the forward product (lane holds rows 4q..4q+3 of column lane%16) equals
+// the operand layout of the adjoint product once the contraction index p is
+// permuted to pi(4kk + q) = 4q + kk, so no data moves between the two.  B_z
+// itself is never written.  The forward K index (loop k) is likewise permuted
+// to sigma(4kk + q) = (NP/4) q + kk so that each lane reads NP/4 contiguous
+// elements of a G row.  Partial r and loss per (chunk, system) go to memory
+// and are summed in a fixed order by the solve/reduce kernels (no atomics).
+//
+// BF16X3: G = Gh + Gl and I = Ih + Il with bf16 hi/lo parts; the product is
+// Gh Ih + Gh Il + Gl Ih accumulated in FP32 with 16x16x32 bf16 MFMA; w is split
+// the same way for the adjoint.
+#include "internal.h"
+
+namespace cosim {
+
+namespace {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+
+template <typename T>
+struct Mma;
+template <>
+struct Mma<float> {
+    typedef f32x4 V;
+    static __device__ inline V op(float a, float b, V c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+};
+template <>
+struct Mma<double> {
+    typedef f64x4 V;
+    static __device__ inline V op(double a, double b, V c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+};
+
+template <typename T>
+__device__ inline T tcast(double x) {
+    return (T)x;
+}
+
+// Per-element loss epilogue.  MAG: e = |B| - T, w = e B/|B| (0 where B = 0).
+// COMPLEX: e = B - T, w = e.  Returns e^2 (|e|^2) and overwrites (x, y) by w.
+template <int LOSS, typename T>
+__device__ inline double epilogue(T &x, T &y, T t) {
+    if (LOSS == COSIM_LOSS_MAG) {
+        const T mag = sqrt(x * x + y * y);
+        const T e = mag - t;
+        const T c = mag > T(0) ? e / mag : T(0);
+        x *= c;
+        y *= c;
+        return (double)e * (double)e;
+    } else {
+        const T ex = x - t;
+        const double v = (double)ex * ex + (double)y * y;
+        x = ex;
+        return v;
+    }
+}
+
+template <typename T, int NP, int NB, int LOSS, bool GRAD>
+__global__ __launch_bounds__(256) void k_fused(FusedArgs a) {
+    typedef typename Mma<T>::V V;
+    constexpr int KS = NP / 4;   // forward k-steps of 4
+    constexpr int IB = NP / 16;  // 16-row blocks of the adjoint output
+    constexpr int PT = kPTile;
+    constexpr int LDR = NP + (sizeof(T) == 4 ? 4 : 2);  // padded LDS row
+    __shared__ __attribute__((aligned(16))) T sG[PT * LDR];
+    __shared__ T sT[PT];
+
+    const T *__restrict__ G = (const T *)a.G;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r16 = lane & 15, q = lane >> 4;
+    const int sys0 = (blockIdx.x * 4 + wave) * (16 * NB);
+    const int chunk = blockIdx.y;
+    const int pb = chunk * a.rows_per_chunk;
+    const int pe = min(a.P_pad, pb + a.rows_per_chunk);
+
+    // I as forward B operands: lane (r16, q), k-step kk holds I[sys][KS q + kk]
+    T Ire[NB][KS], Iim[NB][KS];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const int s = sys0 + 16 * b + r16;
+#pragma unroll
+        for (int kk = 0; kk < KS; ++kk) {
+            const int k = KS * q + kk;
+            double2 v = make_double2(0.0, 0.0);
+            if (s < a.S && k < a.n) v = a.I[(size_t)s * a.n + k];
+            Ire[b][kk] = tcast<T>(v.x);
+            Iim[b][kk] = tcast<T>(v.y);
+        }
+    }
+    V racc[IB][NB][2];
+#pragma unroll
+    for (int ib = 0; ib < IB; ++ib)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            racc[ib][b][0] = V{};
+            racc[ib][b][1] = V{};
+        }
+    double lacc[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) lacc[b] = 0.0;
+
+    constexpr int E = 16 / sizeof(T);  // elements per 16-byte vector
+    constexpr int NV = PT * NP / E;
+    for (int p0 = pb; p0 < pe; p0 += PT) {
+        __syncthreads();
+        for (int v = threadIdx.x; v < NV; v += 256) {
+            const int e0 = v * E;
+            const int row = e0 / NP, col = e0 - row * NP;
+            const uint4 val = *(const uint4 *)(G + (size_t)(p0 + row) * NP + col);
+            *(uint4 *)(sG + row * LDR + col) = val;
+        }
+        if (threadIdx.x < PT) {
+            const int p = p0 + threadIdx.x;
+            sT[threadIdx.x] = p < a.P ? tcast<T>(a.T[p]) : T(0);
+        }
+        __syncthreads();
+#pragma unroll 1
+        for (int sp = 0; sp < PT / 16; ++sp) {
+            T af[KS];
+#pragma unroll
+            for (int kk = 0; kk < KS; ++kk) af[kk] = sG[(16 * sp + r16) * LDR + KS * q + kk];
+            V br[NB], bi[NB];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                br[b] = V{};
+                bi[b] = V{};
+#pragma unroll
+                for (int kk = 0; kk < KS; ++kk) {
+                    br[b] = Mma<T>::op(af[kk], Ire[b][kk], br[b]);
+                    bi[b] = Mma<T>::op(af[kk], Iim[b][kk], bi[b]);
+                }
+            }
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const T t = sT[16 * sp + 4 * q + m];
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    T x = br[b][m], y = bi[b][m];
+                    lacc[b] += epilogue<LOSS>(x, y, t);
+                    br[b][m] = x;
+                    bi[b][m] = y;
+                }
+            }
+            if (GRAD) {
+#pragma unroll
+                for (int ib = 0; ib < IB; ++ib) {
+                    T at[4];
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk)
+                        at[kk] = sG[(16 * sp + 4 * q + kk) * LDR + 16 * ib + r16];
+#pragma unroll
+                    for (int b = 0; b < NB; ++b)
+#pragma unroll
+                        for (int kk = 0; kk < 4; ++kk) {
+                            racc[ib][b][0] = Mma<T>::op(at[kk], br[b][kk], racc[ib][b][0]);
+                            racc[ib][b][1] = Mma<T>::op(at[kk], bi[b][kk], racc[ib][b][1]);
+                        }
+                }
+            }
+        }
+    }
+
+    // ---- partial results of this chunk -------------------------------------
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const int s = sys0 + 16 * b + r16;
+        double v = lacc[b];
+        v += __shfl_xor(v, 16);
+        v += __shfl_xor(v, 32);
+        if (s < a.S) {
+            if (q == 0) a.lpart[(size_t)chunk * a.S + s] = v;
+            if (GRAD) {
+                double2 *dst = a.rpart + ((size_t)chunk * a.S + s) * NP;
+#pragma unroll
+                for (int ib = 0; ib < IB; ++ib)
+#pragma unroll
+                    for (int m = 0; m < 4; ++m)
+                        dst[16 * ib + 4 * q + m] = make_double2((double)racc[ib][b][0][m],
+                                                                (double)racc[ib][b][1][m]);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// BF16X3
+// ---------------------------------------------------------------------------
+__device__ inline uint16_t bf16_bits(float x) {
+    uint32_t u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ inline float bf16_val(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+
+__device__ inline f32x4 mma_bf16(s16x8 a, s16x8 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                  __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+}
+
+// Split a float into hi/lo bf16 bit patterns.
+__device__ inline void split_bf16(float x, short &hi, short &lo) {
+    const uint16_t h = bf16_bits(x);
+    hi = (short)h;
+    lo = (short)bf16_bits(x - bf16_val(h));
+}
+
+// Sub-tiles of 32 rows: the forward product of a 16-row block uses K = 32
+// (loop index, 8 per lane), the adjoint uses K = 32 rows of P taken from two
+// forward accumulators: lane (r16, q) supplies rows {4q..4q+3} of the first
+// 16-row block and {16+4q..16+4q+3} of the second, i.e. the contraction order
+// pi(8q + j) = (j < 4 ? 4q + j : 16 + 4q + j - 4).
+template <int NP, int NB, int LOSS, bool GRAD>
+__global__ __launch_bounds__(256) void k_fused_bf16x3(FusedArgs a) {
+    constexpr int KS = NP / 32;  // forward k-steps of 32
+    constexpr int IB = NP / 16;
+    constexpr int PT = kPTile;
+    constexpr int LDR = NP + 8;  // padded LDS row in bf16 elements (16-byte aligned)
+    __shared__ __attribute__((aligned(16))) uint16_t sH[PT * LDR];
+    __shared__ __attribute__((aligned(16))) uint16_t sL[PT * LDR];
+    __shared__ float sT[PT];
+    static_assert(NP % 32 == 0, "bf16x3 path needs NP multiple of 32");
+
+    const uint16_t *__restrict__ Gh = (const uint16_t *)a.G;
+    const uint16_t *__restrict__ Gl = (const uint16_t *)a.Glo;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r16 = lane & 15, q = lane >> 4;
+    const int sys0 = (blockIdx.x * 4 + wave) * (16 * NB);
+    const int chunk = blockIdx.y;
+    const int pb = chunk * a.rows_per_chunk;
+    const int pe = min(a.P_pad, pb + a.rows_per_chunk);
+
+    // forward B operand for k-step kk: I[sys][32 kk + 8 q + j], j = 0..7
+    s16x8 Ih[NB][2][KS], Il[NB][2][KS];  // [b][re/im][kk]
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const int s = sys0 + 16 * b + r16;
+#pragma unroll
+        for (int kk = 0; kk < KS; ++kk)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int k = 32 * kk + 8 * q + j;
+                double2 v = make_double2(0.0, 0.0);
+                if (s < a.S && k < a.n) v = a.I[(size_t)s * a.n + k];
+                short h, l;
+                split_bf16((float)v.x, h, l);
+                Ih[b][0][kk][j] = h;
+                Il[b][0][kk][j] = l;
+                split_bf16((float)v.y, h, l);
+                Ih[b][1][kk][j] = h;
+                Il[b][1][kk][j] = l;
+            }
+    }
+    f32x4 racc[IB][NB][2];
+#pragma unroll
+    for (int ib = 0; ib < IB; ++ib)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            racc[ib][b][0] = f32x4{};
+            racc[ib][b][1] = f32x4{};
+        }
+    double lacc[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) lacc[b] = 0.0;
+
+    constexpr int NV = PT * NP / 8;  // 16-byte vectors per tile and part
+    for (int p0 = pb; p0 < pe; p0 += PT) {
+        __syncthreads();
+        for (int v = threadIdx.x; v < NV; v += 256) {
+            const int e0 = v * 8;
+            const int row = e0 / NP, col = e0 - row * NP;
+            const size_t go = (size_t)(p0 + row) * NP + col;
+            *(uint4 *)(sH + row * LDR + col) = *(const uint4 *)(Gh + go);
+            *(uint4 *)(sL + row * LDR + col) = *(const uint4 *)(Gl + go);
+        }
+        if (threadIdx.x < PT) {
+            const int p = p0 + threadIdx.x;
+            sT[threadIdx.x] = p < a.P ? (float)a.T[p] : 0.0f;
+        }
+        __syncthreads();
+#pragma unroll 1
+        for (int sp = 0; sp < PT / 32; ++sp) {
+            f32x4 br[2][NB], bi[2][NB];  // [16-row half][b]
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int row = 32 * sp + 16 * h + r16;
+                s16x8 ah[KS], al[KS];
+#pragma unroll
+                for (int kk = 0; kk < KS; ++kk) {
+                    ah[kk] = *(const s16x8 *)(sH + row * LDR + 32 * kk + 8 * q);
+                    al[kk] = *(const s16x8 *)(sL + row * LDR + 32 * kk + 8 * q);
+                }
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    f32x4 xr = f32x4{}, xi = f32x4{};
+#pragma unroll
+                    for (int kk = 0; kk < KS; ++kk) {
+                        xr = mma_bf16(al[kk], Ih[b][0][kk], xr);
+                        xr = mma_bf16(ah[kk], Il[b][0][kk], xr);
+                        xr = mma_bf16(ah[kk], Ih[b][0][kk], xr);
+                        xi = mma_bf16(al[kk], Ih[b][1][kk], xi);
+                        xi = mma_bf16(ah[kk], Il[b][1][kk], xi);
+                        xi = mma_bf16(ah[kk], Ih[b][1][kk], xi);
+                    }
+                    br[h][b] = xr;
+                    bi[h][b] = xi;
+                }
+            }
+            // epilogue on both halves, then pack w into bf16 hi/lo operands
+            s16x8 wrh[NB], wrl[NB], wih[NB], wil[NB];
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    const float t = sT[32 * sp + 16 * h + 4 * q + m];
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) {
+                        float x = br[h][b][m], y = bi[h][b][m];
+                        lacc[b] += epilogue<LOSS>(x, y, t);
+                        short hh, ll;
+                        split_bf16(x, hh, ll);
+                        wrh[b][4 * h + m] = hh;
+                        wrl[b][4 * h + m] = ll;
+                        split_bf16(y, hh, ll);
+                        wih[b][4 * h + m] = hh;
+                        wil[b][4 * h + m] = ll;
+                    }
+                }
+            if (GRAD) {
+#pragma unroll
+                for (int ib = 0; ib < IB; ++ib) {
+                    // A operand: Gt[i = 16 ib + r16][p = pi(8q + j)]
+                    s16x8 th, tl;
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) {
+                        const int pr = 32 * sp + (j < 4 ? 4 * q + j : 16 + 4 * q + (j - 4));
+                        th[j] = (short)sH[pr * LDR + 16 * ib + r16];
+                        tl[j] = (short)sL[pr * LDR + 16 * ib + r16];
+                    }
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) {
+                        racc[ib][b][0] = mma_bf16(tl, wrh[b], racc[ib][b][0]);
+                        racc[ib][b][0] = mma_bf16(th, wrl[b], racc[ib][b][0]);
+                        racc[ib][b][0] = mma_bf16(th, wrh[b], racc[ib][b][0]);
+                        racc[ib][b][1] = mma_bf16(tl, wih[b], racc[ib][b][1]);
+                        racc[ib][b][1] = mma_bf16(th, wil[b], racc[ib][b][1]);
+                        racc[ib][b][1] = mma_bf16(th, wih[b], racc[ib][b][1]);
+                    }
+                }
+            }
+        }
+    }
+
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const int s = sys0 + 16 * b + r16;
+        double v = lacc[b];
+        v += __shfl_xor(v, 16);
+        v += __shfl_xor(v, 32);
+        if (s < a.S) {
+            if (q == 0) a.lpart[(size_t)chunk * a.S + s] = v;
+            if (GRAD) {
+                double2 *dst = a.rpart + ((size_t)chunk * a.S + s) * NP;
+#pragma unroll
+                for (int ib = 0; ib < IB; ++ib)
+#pragma unroll
+                    for (int m = 0; m < 4; ++m)
+                        dst[16 * ib + 4 * q + m] = make_double2((double)racc[ib][b][0][m],
+                                                                (double)racc[ib][b][1][m]);
+            }
+        }
+    }
+}
+
+// Systems per wave (16 * NB) for each precision.
+template <typename T>
+struct NBFor {
+    static constexpr int value = sizeof(T) == 8 ? 1 : 2;
+};
+constexpr int kNBbf16 = 2;
+
+template <typename T, int NP, int LOSS, bool GRAD>
+hipError_t go_typed(const FusedArgs &a, hipStream_t st) {
+    constexpr int NB = NBFor<T>::value;
+    const int per_block = 4 * 16 * NB;
+    dim3 grid((a.S + per_block - 1) / per_block, a.nchunk);
+    hipLaunchKernelGGL((k_fused<T, NP, NB, LOSS, GRAD>), grid, dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+template <int NP, int LOSS, bool GRAD>
+hipError_t go_bf16(const FusedArgs &a, hipStream_t st) {
+    const int per_block = 4 * 16 * kNBbf16;
+    dim3 grid((a.S + per_block - 1) / per_block, a.nchunk);
+    hipLaunchKernelGGL((k_fused_bf16x3<NP, kNBbf16, LOSS, GRAD>), grid, dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+template <int NP, int LOSS, bool GRAD>
+hipError_t go_np(Prec prec, const FusedArgs &a, hipStream_t st) {
+    switch (prec) {
+        case Prec::F64: return go_typed<double, NP, LOSS, GRAD>(a, st);
+        case Prec::F32: return go_typed<float, NP, LOSS, GRAD>(a, st);
+        case Prec::BF16X3:
+            if constexpr (NP % 32 == 0) return go_bf16<NP, LOSS, GRAD>(a, st);
+            else return hipErrorInvalidValue;
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int LOSS, bool GRAD>
+hipError_t go_loss(Prec prec, int NP, const FusedArgs &a, hipStream_t st) {
+    switch (NP) {
+        case 16: return go_np<16, LOSS, GRAD>(prec, a, st);
+        case 32: return go_np<32, LOSS, GRAD>(prec, a, st);
+        case 64: return go_np<64, LOSS, GRAD>(prec, a, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+int fused_systems_per_block(Prec prec, int NP) {
+    (void)NP;
+    switch (prec) {
+        case Prec::F64: return 64 * NBFor<double>::value;
+        case Prec::F32: return 64 * NBFor<float>::value;
+        case Prec::BF16X3: return 64 * kNBbf16;
+    }
+    return 64;
+}
+
+hipError_t launch_fused(Prec prec, int NP, int loss_mode, bool grad, const FusedArgs &a,
+                        hipStream_t st) {
+    if (loss_mode == COSIM_LOSS_MAG) {
+        return grad ? go_loss<COSIM_LOSS_MAG, true>(prec, NP, a, st)
+                    : go_loss<COSIM_LOSS_MAG, false>(prec, NP, a, st);
+    }
+    return grad ? go_loss<COSIM_LOSS_COMPLEX, true>(prec, NP, a, st)
+                : go_loss<COSIM_LOSS_COMPLEX, false>(prec, NP, a, st);
+}
+
+}  // namespace cosim

@@ -1,0 +1,118 @@
+// Internal declarations shared by the host entry points and the HIP kernels
+// of libcosim.  Not part of the public ABI (see include/cosim.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "cosim.h"
+
+namespace cosim {
+
+// Vacuum permeability, CODATA 2018 (N/A^2), and mu0/(4 pi).
+constexpr double kMu0 = 1.25663706212e-6;
+constexpr double kMu0Over4Pi = kMu0 / (4.0 * 3.14159265358979323846);
+
+// Gauss-Legendre rule used for the outer integral of non-parallel segment
+// pairs in the Neumann assembly (inner integral is closed form).
+constexpr int kGLOrder = 16;
+
+struct GLRule {
+    double x[kGLOrder];  // nodes on [-1, 1]
+    double w[kGLOrder];  // weights
+};
+
+// Matrix-core precision of the superposition (mirrors cosim_precision).
+enum class Prec { F64 = 0, F32 = 1, BF16X3 = 2 };
+
+// Padded loop dimension used by the solver and the contraction kernels.
+inline int padded_loops(int n) { return n <= 16 ? 16 : (n <= 32 ? 32 : 64); }
+constexpr int kMaxLoops = 64;      // fused path and solver limit of this build
+constexpr int kPTile = 64;         // rows of G per LDS tile in the fused kernels
+
+// ---------------------------------------------------------------------------
+// kernel launchers (implemented in the .hip files); all return hipError_t
+// ---------------------------------------------------------------------------
+hipError_t launch_assemble_G(int n, int NP, int P, int P_pad, const int32_t *seg_off_d,
+                             const double *verts_d, const double *pts_d, double *G64,
+                             float *G32, uint16_t *Ghi, uint16_t *Glo, hipStream_t st);
+
+hipError_t launch_assemble_M(int n, const int32_t *seg_off_d, const double *verts_d,
+                             const double *wire_a_d, const GLRule &gl, double *M_d,
+                             hipStream_t st);
+
+// Forward solve: Z I = -j w Phi for S = B*F systems (s = b*F + f).
+hipError_t launch_solve_forward(int NP, int n, int S, int F, const double *M_d,
+                                const double *R_d, const double *phi_d, const double *C_d,
+                                const double *omega_d, double2 *I_d, int32_t *status_d,
+                                hipStream_t st);
+
+// Adjoint solve: Z mu = rscale * sum_c (rr_c - j ri_c); writes the per-system
+// gradient term gsys[s][k] = 2 Re(mu_k I_k / (j w C_k^2)).  The system status
+// is OR-ed into status_d when or_status, else assigned.
+hipError_t launch_solve_adjoint(int NP, int n, int S, int F, const double *M_d,
+                                const double *R_d, const double *C_d, const double *omega_d,
+                                const double2 *I_d, const double2 *rpart_d, int nchunk,
+                                double rscale, double *gsys_d, int32_t *status_d,
+                                bool or_status, hipStream_t st);
+
+// Sum over frequencies (and chunks for the loss) per configuration.
+hipError_t launch_reduce(int n, int B, int F, int nchunk, const double *gsys_d,
+                         const double *lpart_d, double lscale, double *grad_d, double *loss_d,
+                         hipStream_t st);
+
+// Fused B = G I, loss epilogue, r = G^T conj(w) over a P-chunk grid.
+struct FusedArgs {
+    const void *G;        // [P_pad][NP] in the precision's storage type
+    const void *Glo;      // bf16 lo part (BF16X3 only)
+    const double *T;      // [P] target
+    int P, P_pad, rows_per_chunk, nchunk;
+    const double2 *I;     // [S][n]
+    int S, n;
+    double2 *rpart;       // [nchunk][S][NP] (rr, ri); may be null when !grad
+    double *lpart;        // [nchunk][S]
+};
+hipError_t launch_fused(Prec prec, int NP, int loss_mode, bool grad, const FusedArgs &a,
+                        hipStream_t st);
+// Number of systems one workgroup of the fused kernel covers.
+int fused_systems_per_block(Prec prec, int NP);
+
+// Materialised field B[s][p] (complex128 for F64, complex64 otherwise).
+hipError_t launch_field(Prec prec, int NP, int P, int S, int n, const double *G64,
+                        const double2 *I_d, void *Bz_d, hipStream_t st);
+
+// r[s][i] = sum_p G[p][i] * gBz[s][p]  (rr, ri parts; FP64), stored in rpart[0].
+hipError_t launch_field_backward_contract(int NP, int P, int S, int n, const double *G64,
+                                          const double2 *gBz_d, double2 *rpart_d,
+                                          hipStream_t st);
+
+}  // namespace cosim
+
+// Library-owned objects behind the opaque handles.
+struct cosim_geom {
+    int n = 0, V = 0;
+    std::vector<int32_t> seg_off;
+    std::vector<double> verts, wire_a, R, area_z;
+};
+
+struct cosim_plan {
+    int device = 0;
+    int n = 0, NP = 0, P = 0, P_pad = 0;
+    double bext_z = 0.0;
+    std::vector<double> M_h, phi_h;
+    // operators (device)
+    double *G64 = nullptr;
+    float *G32 = nullptr;
+    uint16_t *Ghi = nullptr, *Glo = nullptr;
+    double *M_d = nullptr, *phi_d = nullptr, *R_d = nullptr;
+    // workspace (device)
+    size_t cap_systems = 0;
+    int cap_chunks = 0;
+    double2 *I_ws = nullptr;
+    double2 *rpart = nullptr;
+    double *lpart = nullptr;
+    double *gsys = nullptr;
+};

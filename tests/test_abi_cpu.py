@@ -1,0 +1,110 @@
+"""CPU-only checks of the C ABI: the library loads, exports every function
+the header declares, and rejects bad arguments on the host (no GPU needed:
+these error paths return before any HIP call)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2503_18479_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cosim.h")
+
+EINVAL, EUNSUPPORTED = -1, -4
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(cosim_[a-z_0-9A-Z]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return _lib.load_library()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = _declared()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(_lib.SIGNATURES), "binding and header disagree"
+    assert lib.cosim_version() == 1
+
+
+def _geom_args(n=2, nv=4):
+    seg = np.arange(0, n * nv + 1, nv, dtype=np.int32)
+    ang = np.linspace(0, 2 * np.pi, nv, endpoint=False)
+    v = np.zeros((n * nv, 3))
+    for k in range(n):
+        v[k * nv:(k + 1) * nv, 0] = 0.01 * np.cos(ang) + 0.05 * k
+        v[k * nv:(k + 1) * nv, 1] = 0.01 * np.sin(ang)
+    return seg, v, np.full(n, 1e-3), np.full(n, 0.3)
+
+
+def _create(lib, n, seg, v, a, R):
+    h = ctypes.c_void_p()
+    rc = lib.cosim_geometry_create(n, seg.ctypes.data if seg is not None else None,
+                                   v.ctypes.data if v is not None else None,
+                                   a.ctypes.data if a is not None else None,
+                                   R.ctypes.data if R is not None else None, ctypes.byref(h))
+    return rc, h
+
+
+def test_geometry_create_and_errors(lib):
+    seg, v, a, R = _geom_args()
+    rc, h = _create(lib, 2, seg, v, a, R)
+    assert rc == 0 and h.value
+    n = ctypes.c_int(); V = ctypes.c_int()
+    assert lib.cosim_geometry_size(h, ctypes.byref(n), ctypes.byref(V)) == 0
+    assert (n.value, V.value) == (2, 8)
+    assert lib.cosim_geometry_destroy(h) == 0
+    assert _create(lib, 0, seg, v, a, R)[0] == EINVAL
+    assert _create(lib, 2, None, v, a, R)[0] == EINVAL
+    bad = seg.copy(); bad[1] = 2  # a loop with 2 vertices
+    assert _create(lib, 2, bad, v, a, R)[0] == EINVAL
+    assert b"fewer than 3" in lib.cosim_last_error()
+    vv = v.copy(); vv[3, 1] = np.nan
+    assert _create(lib, 2, seg, vv, a, R)[0] == EINVAL
+    aa = a.copy(); aa[1] = 0.0
+    assert _create(lib, 2, seg, v, aa, R)[0] == EINVAL
+    RR = R.copy(); RR[0] = -1.0
+    assert _create(lib, 2, seg, v, a, RR)[0] == EINVAL
+    s0 = seg.copy(); s0[0] = 1
+    assert _create(lib, 2, s0, v, a, R)[0] == EINVAL
+
+
+def test_assemble_argument_errors(lib):
+    seg, v, a, R = _geom_args()
+    rc, g = _create(lib, 2, seg, v, a, R)
+    out = ctypes.c_void_p()
+    assert lib.cosim_assemble(g, 10, None, 1e-6, None, ctypes.byref(out)) == EINVAL
+    assert lib.cosim_assemble(g, 0, ctypes.c_void_p(16), 1e-6, None, ctypes.byref(out)) == EINVAL
+    assert lib.cosim_assemble(None, 10, ctypes.c_void_p(16), 1e-6, None, ctypes.byref(out)) == EINVAL
+    assert lib.cosim_assemble(g, 10, ctypes.c_void_p(16), float("inf"), None, ctypes.byref(out)) == EINVAL
+    assert lib.cosim_assemble(g, 10, ctypes.c_void_p(16), 1e-6, None, None) == EINVAL
+    lib.cosim_geometry_destroy(g)
+    # more loops than this build's solver supports
+    seg, v, a, R = _geom_args(n=65)
+    rc, g = _create(lib, 65, seg, v, a, R)
+    assert rc == 0
+    assert lib.cosim_assemble(g, 10, ctypes.c_void_p(16), 1e-6, None, ctypes.byref(out)) == EUNSUPPORTED
+    lib.cosim_geometry_destroy(g)
+
+
+def test_hot_call_argument_errors(lib):
+    dummy = ctypes.c_void_p(64)
+    # null plan
+    assert lib.cosim_solve(None, 1, 1, dummy, dummy, dummy, dummy, None) == EINVAL
+    assert lib.cosim_loss_and_grad(None, 1, 1, dummy, dummy, dummy, 0, 1, dummy, dummy, dummy, None) == EINVAL
+    assert lib.cosim_field(None, 1, 1, dummy, 0, dummy, None) == EINVAL
+    assert lib.cosim_field_backward(None, 1, 1, dummy, dummy, dummy, dummy, dummy, dummy, None) == EINVAL
+    assert lib.cosim_plan_reserve(None, 1, 1) == EINVAL
+    assert lib.cosim_plan_copy_M(None, dummy) == EINVAL
+    assert lib.cosim_plan_destroy(None) == 0
+    assert lib.cosim_geometry_destroy(None) == 0
+    assert lib.cosim_last_error() != b""
