@@ -341,8 +341,8 @@ int cosim_solve(cosim_plan_t p, int B, int F, const double *C_d, const double *o
                 double *I_d, int32_t *status_d, void *stream) {
     int rc = check_batch(p, B, F);
     if (rc) return rc;
+    if (B == 0 || F == 0) return COSIM_OK;  // empty batch: nothing to do
     if (!C_d || !omega_d || !I_d || !status_d) return fail(COSIM_EINVAL, "null device pointer");
-    if (B == 0 || F == 0) return COSIM_OK;
     if ((rc = check_device(p))) return rc;
     const int S = B * F;
     HIP_TRY(launch_solve_forward(p->NP, p->n, S, F, p->M_d, p->R_d, p->phi_d, C_d, omega_d,
@@ -354,9 +354,9 @@ int cosim_field(cosim_plan_t p, int B, int F, const double *I_d, int precision, 
                 void *stream) {
     int rc = check_batch(p, B, F);
     if (rc) return rc;
+    if (B == 0 || F == 0) return COSIM_OK;  // empty batch: nothing to do
     if ((rc = check_prec(precision))) return rc;
     if (!I_d || !Bz_d) return fail(COSIM_EINVAL, "null device pointer");
-    if (B == 0 || F == 0) return COSIM_OK;
     if ((rc = check_device(p))) return rc;
     const int S = B * F;
     const size_t esz = precision == COSIM_FP64 ? sizeof(double2) : sizeof(float2);
@@ -375,9 +375,9 @@ int cosim_field_backward(cosim_plan_t p, int B, int F, const double *C_d, const 
                          int32_t *status_d, void *stream) {
     int rc = check_batch(p, B, F);
     if (rc) return rc;
+    if (B == 0 || F == 0) return COSIM_OK;  // empty batch: nothing to do
     if (!C_d || !omega_d || !I_d || !gBz_d || !gC_d || !status_d)
         return fail(COSIM_EINVAL, "null device pointer");
-    if (B == 0 || F == 0) return COSIM_OK;
     if ((rc = check_device(p))) return rc;
     const size_t S = (size_t)B * F;
     if ((rc = ensure_workspace(p, S, 1))) return rc;
@@ -396,6 +396,7 @@ int cosim_loss_and_grad(cosim_plan_t p, int B, int F, const double *C_d, const d
                         double *grad_d, int32_t *status_d, void *stream) {
     int rc = check_batch(p, B, F);
     if (rc) return rc;
+    if (B == 0 || F == 0) return COSIM_OK;  // empty batch: nothing to do
     if ((rc = check_prec(precision))) return rc;
     if (loss_mode != COSIM_LOSS_MAG && loss_mode != COSIM_LOSS_COMPLEX)
         return fail(COSIM_EINVAL, "unknown loss mode %d", loss_mode);
@@ -403,7 +404,6 @@ int cosim_loss_and_grad(cosim_plan_t p, int B, int F, const double *C_d, const d
         return fail(COSIM_EINVAL, "null device pointer");
     if (precision == COSIM_BF16X3 && p->NP % 32 != 0)
         return fail(COSIM_EUNSUPPORTED, "BF16X3 needs more than 16 loops in this build (n = %d)", p->n);
-    if (B == 0 || F == 0) return COSIM_OK;
     if ((rc = check_device(p))) return rc;
     const size_t S = (size_t)B * F;
     const Prec prec = (Prec)precision;

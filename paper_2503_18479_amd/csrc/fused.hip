@@ -12,9 +12,10 @@
 // registers for the whole chunk, computes B for a 16-row sub-tile with
 // 16x16x4 MFMA (f32 or f64), turns it into w in registers, and feeds w
 // straight back as the B operand of the adjoint MFMA: the accumulator layout
-// of the forward product (lane holds rows 4q..4q+3 of column lane%16) equals
-// the operand layout of the adjoint product once the contraction index p is
-// permuted to pi(4kk + q) = 4q + kk, so no data moves between the two.  B_z
+// of the forward product (register m of lane group q holds row row(q, m) of
+// column lane%16) equals the operand layout of the adjoint product once the
+// contraction index p is permuted to pi(4kk + q) = row(q, kk), so no data
+// moves between the two.  B_z
 // itself is never written.  The forward K index (loop k) is likewise permuted
 // to sigma(4kk + q) = (NP/4) q + kk so that each lane reads NP/4 contiguous
 // elements of a G row.  Partial r and loss per (chunk, system) go to memory
@@ -36,12 +37,17 @@ typedef short s16x8 __attribute__((ext_vector_type(8)));
 
 template <typename T>
 struct Mma;
+// row(g, m): row of the 16x16 accumulator held in register m by the lanes of
+// group g = lane / 16 (the column is lane % 16).  Measured on gfx950:
+// f32 16x16x4 keeps rows 4g..4g+3 per lane, f64 16x16x4 interleaves them
+// (rows g, g+4, g+8, g+12).
 template <>
 struct Mma<float> {
     typedef f32x4 V;
     static __device__ inline V op(float a, float b, V c) {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }
+    static __device__ constexpr int row(int g, int m) { return 4 * g + m; }
 };
 template <>
 struct Mma<double> {
@@ -49,6 +55,7 @@ struct Mma<double> {
     static __device__ inline V op(double a, double b, V c) {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
+    static __device__ constexpr int row(int g, int m) { return g + 4 * m; }
 };
 
 template <typename T>
@@ -152,7 +159,7 @@ __global__ __launch_bounds__(256) void k_fused(FusedArgs a) {
             }
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
-                const T t = sT[16 * sp + 4 * q + m];
+                const T t = sT[16 * sp + Mma<T>::row(q, m)];
 #pragma unroll
                 for (int b = 0; b < NB; ++b) {
                     T x = br[b][m], y = bi[b][m];
@@ -167,7 +174,7 @@ __global__ __launch_bounds__(256) void k_fused(FusedArgs a) {
                     T at[4];
 #pragma unroll
                     for (int kk = 0; kk < 4; ++kk)
-                        at[kk] = sG[(16 * sp + 4 * q + kk) * LDR + 16 * ib + r16];
+                        at[kk] = sG[(16 * sp + Mma<T>::row(q, kk)) * LDR + 16 * ib + r16];
 #pragma unroll
                     for (int b = 0; b < NB; ++b)
 #pragma unroll
@@ -195,8 +202,8 @@ __global__ __launch_bounds__(256) void k_fused(FusedArgs a) {
                 for (int ib = 0; ib < IB; ++ib)
 #pragma unroll
                     for (int m = 0; m < 4; ++m)
-                        dst[16 * ib + 4 * q + m] = make_double2((double)racc[ib][b][0][m],
-                                                                (double)racc[ib][b][1][m]);
+                        dst[16 * ib + Mma<T>::row(q, m)] = make_double2(
+                            (double)racc[ib][b][0][m], (double)racc[ib][b][1][m]);
             }
         }
     }

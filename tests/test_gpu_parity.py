@@ -148,8 +148,8 @@ def test_solve_resonance_single_loop(dev):
     L = c.plan.M()[0, 0]
     w = 2 * np.pi * 128e6
     Cr = 1.0 / (w * w * L)
-    C = torch.tensor([[Cr]], device=dev)
-    I, st = c.plan.solve(C, torch.tensor([w], device=dev))
+    C = torch.tensor([[Cr]], dtype=torch.float64, device=dev)
+    I, st = c.plan.solve(C, torch.tensor([w], dtype=torch.float64, device=dev))
     ref = -1j * w * c.plan.phi()[0] / c.wl.geom.R[0]
     np.testing.assert_allclose(I.cpu().numpy()[0, 0, 0], ref, rtol=1e-10)
 
