@@ -1,0 +1,219 @@
+"""Benchmark: forward + adjoint evaluations of C -> B_z per second on one MI355X.
+
+Workload: the 8x8 metasurface (64 square loops of 3 cm at 3.5 cm pitch, 32
+segments each), B_z on 256x256 points at z = 1 cm (65,536 points), 21
+frequencies 118..138 MHz, a batch of 4,096 capacitance configurations.  One
+step is one cosim_loss_and_grad call over the whole batch: the forward solve of
+every (configuration, frequency) system, B_z = G I with the loss epilogue, the
+adjoint contraction G^T conj(w), the adjoint solve and the gradient reduction.
+Inputs are resident in HBM before the timed region.
+
+The value is the mixed-precision throughput (matrix-core contraction in the
+chosen mixed mode, FP64 solves); the FP64 mode is timed on the same GPU and
+reported beside it.  One JSON line is printed.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}
+PREC_CODE = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+FUSED_KERNEL_SRC = os.path.join(ROOT, "paper_2503_18479_amd", "csrc", "fused.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fused_traffic.json")
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--mixed", default="bf16x3", choices=["fp32", "bf16x3"],
+                    help="mixed mode reported as the value")
+    ap.add_argument("--batch", type=int, default=4096)
+    ap.add_argument("--grid", type=int, default=256)
+    ap.add_argument("--freqs", type=int, default=21)
+    ap.add_argument("--two-planes", action="store_true",
+                    help="131,072 points (z = 1 cm and 3 cm) instead of 65,536")
+    ap.add_argument("--fp64-steps", type=int, default=None,
+                    help="timed steps of the FP64 comparison (default: steps/2, >= 3)")
+    ap.add_argument("--cpu-configs", type=int, default=2,
+                    help="configurations the oracle evaluates for the CPU baseline (0: skip)")
+    ap.add_argument("--profile-steps", type=int, default=None,
+                    help="run only this many steps of the headline mode (for rocprofv3)")
+    return ap.parse_args()
+
+
+def _src_hash(path: str) -> str:
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def time_mode(plan, C, om, T, prec: str, steps: int, warmup: int, torch):
+    loss = torch.empty((C.shape[0],), dtype=torch.float64, device=C.device)
+    grad = torch.empty_like(C)
+    st = torch.empty((C.shape[0], om.shape[0]), dtype=torch.int32, device=C.device)
+    out = (loss, grad, st)
+    for _ in range(warmup):
+        plan.loss_and_grad(C, om, T, precision=PREC_CODE[prec], out=out)
+    torch.cuda.synchronize()
+    plan.timing(steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.loss_and_grad(C, om, T, precision=PREC_CODE[prec], out=out)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    phases = plan.timing_read()
+    plan.timing(0)
+    bad = int((st != 0).sum())
+    return dt, phases, bad
+
+
+def cpu_baseline(wl, n_configs: int):
+    """The FP64 oracle on the host cores, on a bounded sample of the workload."""
+    import oracle as O
+    try:
+        import threadpoolctl
+        threads = max(i.get("num_threads", 1) for i in threadpoolctl.threadpool_info()) or 1
+    except Exception:  # pragma: no cover
+        threads = 1
+    g = wl.geom
+    t0 = time.perf_counter()
+    G = O.field_matrix(g.verts, g.seg_off, wl.pts)
+    M = O.inductance_matrix_fast(g.verts, g.seg_off, g.wire_a)
+    Phi = O.flux(g.verts, g.seg_off, wl.bext_z)
+    t_asm = time.perf_counter() - t0
+    C = wl.C[:n_configs]
+    t0 = time.perf_counter()
+    O.evaluate(G, M, g.R, Phi, C, wl.omega, wl.target)
+    O.grad_adjoint(G, M, g.R, Phi, C, wl.omega, wl.target)
+    t_eval = time.perf_counter() - t0
+    return {
+        "value": n_configs / t_eval,
+        "unit": "evals/s",
+        "cores": int(threads),
+        "kind": "oracle",
+        "sample": (f"{n_configs} configurations x {wl.F} frequencies at all {wl.P} points "
+                   f"(loss + adjoint gradient, {t_eval:.1f} s); G/M assembly by the oracle "
+                   f"took {t_asm:.1f} s and is excluded, as on the GPU"),
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(the batch shards over configurations; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads as W
+    from paper_2503_18479_amd import Geometry, Plan
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    wl = W.config3_array8x8(batch=args.batch, grid=args.grid, two_planes=args.two_planes,
+                            n_freq=args.freqs)
+    g = wl.geom
+    t0 = time.perf_counter()
+    plan = Plan(Geometry.from_workload(g), torch.tensor(wl.pts, device=dev), wl.bext_z)
+    t_asm = time.perf_counter() - t0
+    C = torch.tensor(wl.C, device=dev)
+    om = torch.tensor(wl.omega, device=dev)
+    T = torch.tensor(wl.target, device=dev)
+    plan.reserve(wl.B, wl.F)
+    print(f"[bench] assembled {wl.summary()} in {t_asm:.2f} s", file=sys.stderr, flush=True)
+
+    if args.profile_steps is not None:
+        time_mode(plan, C, om, T, args.mixed, args.profile_steps, 1, torch)
+        print(f"[bench] profiled {args.profile_steps} steps of {args.mixed}", file=sys.stderr)
+        return
+
+    S = wl.B * wl.F
+    flops = 8.0 * wl.P * g.n * S  # forward 4 P n S + adjoint 4 P n S (real-split)
+    res = {}
+    modes = [args.mixed, "fp64"]
+    other = "fp32" if args.mixed == "bf16x3" else "bf16x3"
+    modes.append(other)
+    for m in modes:
+        steps = args.steps if m != "fp64" else (args.fp64_steps or max(3, args.steps // 2))
+        dt, ph, bad = time_mode(plan, C, om, T, m, steps, args.warmup, torch)
+        fused = float(np.mean(ph[:, 1]))
+        res[m] = {
+            "evals_per_s": wl.B * steps / dt,
+            "ms_per_step": 1e3 * dt / steps,
+            "steps": steps,
+            "phase_ms": {name: float(np.mean(ph[:, i])) for i, name in enumerate(Plan.PHASES)},
+            "fused_tflops": flops / (fused * 1e-3) / 1e12,
+            "flagged_systems": bad,
+        }
+        print(f"[bench] {m}: {res[m]['evals_per_s']:.0f} evals/s, {res[m]['ms_per_step']:.2f} ms/step, "
+              f"phases {res[m]['phase_ms']}", file=sys.stderr, flush=True)
+
+    head = res[args.mixed]
+    fused_ms = head["phase_ms"]["fused_contraction"]
+    achieved = head["fused_tflops"]
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as f:
+            tr = json.load(f)
+        if (tr.get("kernel_src_sha256_16") == _src_hash(FUSED_KERNEL_SRC)
+                and tr.get("precision") == args.mixed and tr.get("workload") == wl.name
+                and tr.get("batch") == wl.B and tr.get("points") == wl.P):
+            traffic = tr.get("bytes_per_launch")
+
+    line = {
+        "metric": "fwd+adjoint C->B_z evals/sec, 8x8 array, 65k pts: mixed vs FP64, same GPU",
+        "value": head["evals_per_s"],
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": head["steps"],
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": f"{args.mixed}+f64",
+        "data": "synthetic",
+        "config": {
+            "workload": wl.name, "loops": g.n, "segments_per_loop": 32, "points": wl.P,
+            "freqs": wl.F, "batch": wl.B, "systems": S, "precision": args.mixed,
+            "solve": "fp64 Gauss-Jordan, partial pivoting", "loss": "magnitude MSE",
+        },
+        "fp64": {"value": res["fp64"]["evals_per_s"], "ms_per_step": res["fp64"]["ms_per_step"],
+                 "steps": res["fp64"]["steps"]},
+        "mixed_vs_fp64": head["evals_per_s"] / res["fp64"]["evals_per_s"],
+        "modes": res,
+        "roofline": {
+            "bound": "mfma",
+            "kernel": "fused contraction (B = G I, loss epilogue, G^T conj(w))",
+            "achieved": achieved,
+            "peak": PEAK_TFLOPS[args.mixed],
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_TFLOPS[args.mixed],
+            "traffic": traffic,
+            "flops_per_launch": flops,
+            "avg_launch_ms": fused_ms,
+        },
+    }
+    if args.cpu_configs > 0:
+        print("[bench] timing the oracle on the host", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(wl, args.cpu_configs)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

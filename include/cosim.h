@@ -173,6 +173,22 @@ int cosim_loss_and_grad(cosim_plan_t p, int B, int F, const double *C_d, const d
                         const double *T_d, int loss_mode, int precision, double *loss_d,
                         double *grad_d, int32_t *status_d, void *stream);
 
+/* --------------------------------------------------------------------------
+ * Phase timing of cosim_loss_and_grad with HIP events on the call's stream
+ * (for benchmarks and metrics; not a paper quantity).
+ * cosim_plan_timing(p, max_records) creates event sets for the next
+ * max_records calls of cosim_loss_and_grad (0 switches timing off and frees
+ * them); each of those calls records its phase boundaries.
+ * cosim_plan_timing_read waits for the recorded calls and writes, per call,
+ * COSIM_PHASES durations in milliseconds to ms[record][phase]:
+ *   0 forward solve, 1 fused contraction (B = G I, loss, G^T w),
+ *   2 adjoint solve, 3 reductions.
+ * *n_records receives the number of calls recorded; recording restarts at 0.
+ * -------------------------------------------------------------------------- */
+enum { COSIM_PHASES = 4 };
+int cosim_plan_timing(cosim_plan_t p, int max_records);
+int cosim_plan_timing_read(cosim_plan_t p, double *ms, int max_records, int *n_records);
+
 #ifdef __cplusplus
 }
 #endif

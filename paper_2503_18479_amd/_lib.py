@@ -35,6 +35,8 @@ SIGNATURES = {
                                      c_void_p, c_void_p, c_void_p]),
     "cosim_loss_and_grad": (c_int, [c_void_p, c_int, c_int, c_void_p, c_void_p, c_void_p, c_int,
                                     c_int, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "cosim_plan_timing": (c_int, [c_void_p, c_int]),
+    "cosim_plan_timing_read": (c_int, [c_void_p, c_void_p, c_int, P(c_int)]),
 }
 
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EUNSUPPORTED"}

@@ -126,6 +126,20 @@ class Plan:
         check(self._lib.cosim_plan_copy_phi(self._h, _host(out)))
         return out
 
+    # -- phase timing (HIP events on the call's stream) ------------------------
+    PHASES = ("solve_forward", "fused_contraction", "solve_adjoint", "reduce")
+
+    def timing(self, max_records: int) -> None:
+        check(self._lib.cosim_plan_timing(self._h, int(max_records)))
+        self._timing_cap = int(max_records)
+
+    def timing_read(self) -> np.ndarray:
+        cap = getattr(self, "_timing_cap", 0)
+        out = np.zeros((max(cap, 1), len(self.PHASES)))
+        nr = ctypes.c_int()
+        check(self._lib.cosim_plan_timing_read(self._h, _host(out), cap, ctypes.byref(nr)))
+        return out[:nr.value]
+
     # -- path -----------------------------------------------------------------
     def solve(self, C: torch.Tensor, omega: torch.Tensor) -> Tuple[torch.Tensor, torch.Tensor]:
         B, F = int(C.shape[0]), int(omega.shape[0])

@@ -281,6 +281,8 @@ int cosim_assemble(cosim_geom_t g, int P, const double *pts_d, double bext_z, vo
 
 int cosim_plan_destroy(cosim_plan_t p) {
     if (!p) return COSIM_OK;
+    for (hipEvent_t e : p->events) (void)hipEventDestroy(e);
+    p->events.clear();
     dfree(p->G64);
     dfree(p->G32);
     dfree(p->Ghi);
@@ -413,8 +415,12 @@ int cosim_loss_and_grad(cosim_plan_t p, int B, int F, const double *C_d, const d
     const int nchunk = (tiles + tpc - 1) / tpc;
     if ((rc = ensure_workspace(p, S, nchunk))) return rc;
     hipStream_t st = (hipStream_t)stream;
+    hipEvent_t *ev = nullptr;
+    if (p->timing_used < p->timing_cap) ev = &p->events[(size_t)p->timing_used++ * (COSIM_PHASES + 1)];
+    if (ev) HIP_TRY(hipEventRecord(ev[0], st));
     HIP_TRY(launch_solve_forward(p->NP, p->n, (int)S, F, p->M_d, p->R_d, p->phi_d, C_d, omega_d,
                                  p->I_ws, status_d, st));
+    if (ev) HIP_TRY(hipEventRecord(ev[1], st));
     FusedArgs a;
     a.G = precision == COSIM_FP64 ? (const void *)p->G64
           : precision == COSIM_FP32 ? (const void *)p->G32
@@ -432,12 +438,54 @@ int cosim_loss_and_grad(cosim_plan_t p, int B, int F, const double *C_d, const d
     a.lpart = p->lpart;
     const bool grad = grad_d != nullptr;
     HIP_TRY(launch_fused(prec, p->NP, loss_mode, grad, a, st));
+    if (ev) HIP_TRY(hipEventRecord(ev[2], st));
     const double scale = 1.0 / ((double)F * (double)p->P);
     if (grad)
         HIP_TRY(launch_solve_adjoint(p->NP, p->n, (int)S, F, p->M_d, p->R_d, C_d, omega_d, p->I_ws,
                                      p->rpart, nchunk, scale, p->gsys, status_d, true, st));
+    if (ev) HIP_TRY(hipEventRecord(ev[3], st));
     HIP_TRY(launch_reduce(p->n, B, F, nchunk, grad ? p->gsys : nullptr, p->lpart, scale, grad_d,
                           loss_d, st));
+    if (ev) HIP_TRY(hipEventRecord(ev[4], st));
+    return COSIM_OK;
+}
+
+int cosim_plan_timing(cosim_plan_t p, int max_records) {
+    if (!p) return fail(COSIM_EINVAL, "null plan");
+    if (max_records < 0) return fail(COSIM_EINVAL, "max_records must be >= 0");
+    int rc = check_device(p);
+    if (rc) return rc;
+    for (hipEvent_t e : p->events) (void)hipEventDestroy(e);
+    p->events.clear();
+    p->timing_cap = p->timing_used = 0;
+    const size_t ne = (size_t)max_records * (COSIM_PHASES + 1);
+    p->events.resize(ne, nullptr);
+    for (size_t i = 0; i < ne; ++i) {
+        if (hipEventCreate(&p->events[i]) != hipSuccess) {
+            for (size_t j = 0; j < i; ++j) (void)hipEventDestroy(p->events[j]);
+            p->events.clear();
+            return fail(COSIM_EDEVICE, "hipEventCreate failed");
+        }
+    }
+    p->timing_cap = max_records;
+    return COSIM_OK;
+}
+
+int cosim_plan_timing_read(cosim_plan_t p, double *ms, int max_records, int *n_records) {
+    if (!p) return fail(COSIM_EINVAL, "null plan");
+    if (!n_records || (max_records > 0 && !ms)) return fail(COSIM_EINVAL, "null output");
+    const int nr = std::min(p->timing_used, max_records);
+    for (int r = 0; r < nr; ++r) {
+        hipEvent_t *ev = &p->events[(size_t)r * (COSIM_PHASES + 1)];
+        HIP_TRY(hipEventSynchronize(ev[COSIM_PHASES]));
+        for (int ph = 0; ph < COSIM_PHASES; ++ph) {
+            float t = 0.f;
+            HIP_TRY(hipEventElapsedTime(&t, ev[ph], ev[ph + 1]));
+            ms[(size_t)r * COSIM_PHASES + ph] = (double)t;
+        }
+    }
+    *n_records = nr;
+    p->timing_used = 0;
     return COSIM_OK;
 }
 

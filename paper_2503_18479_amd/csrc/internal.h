@@ -115,4 +115,7 @@ struct cosim_plan {
     double2 *rpart = nullptr;
     double *lpart = nullptr;
     double *gsys = nullptr;
+    // optional phase timing: (COSIM_PHASES + 1) events per recorded call
+    std::vector<hipEvent_t> events;
+    int timing_cap = 0, timing_used = 0;
 };
