@@ -3,20 +3,15 @@
 //
 // One workgroup per (configuration, frequency) system.  Z (NP x NP complex,
 // NP = n padded to 16/32/64 with an identity block) lives in registers: thread
-// (ti, tj) owns the 4x4 tile Z[4ti..4ti+3][4tj..4tj+3].  Gauss-Jordan
-// elimination with partial pivoting (pivot = largest |re|+|im| among rows not
-// yet used, rows are never swapped) eliminates column k from every other row,
-// so the solution is read off at the end as x_k = b'_{p_k} / pivot_k with no
-// back substitution.  Per step:
-//   * the NT lanes owning column k (one column of tiles, always inside one
-//     wave) find the pivot with a shuffle reduction and publish the
-//     multipliers l_i = a_ik / a_pk through LDS (one block barrier);
-//   * inside each wave the owner of the pivot row's tile publishes that tile
-//     through LDS (wave-local, no barrier) and every thread applies the rank-1
-//     update to its tile; tiles left of column k are skipped.
-// The right-hand side is carried by the column of tiles holding column n-1.
-// Z is complex symmetric (M symmetric, R and C diagonal), so the same routine
-// serves the adjoint system Z^T mu = r.
+// (ti, tj) owns the 4x4 tile Z[4ti..4ti+3][4tj..4tj+3]; the NT threads of a
+// column of tiles (a "column group") are consecutive lanes of one wave.
+// Gauss-Jordan elimination with partial pivoting (pivot = largest |re|+|im|
+// among rows not yet used; rows are never swapped) eliminates each column from
+// every other row, so the solution is read off at the end as
+// x_k = b'_{p_k} / pivot_k with no back substitution.  Columns are processed
+// in panels of 4 (see k_gj); the right-hand side is carried by the column
+// group holding column n-1.  Z is complex symmetric (M symmetric, R and C
+// diagonal), so the same routine serves the adjoint system Z^T mu = r.
 #include <type_traits>
 
 #include "internal.h"
@@ -27,10 +22,6 @@ namespace {
 
 __device__ inline double2 cmul(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-__device__ inline double2 csub_mul(double2 acc, double2 a, double2 b) {
-    // acc - a*b
-    return make_double2(acc.x - (a.x * b.x - a.y * b.y), acc.y - (a.x * b.y + a.y * b.x));
 }
 __device__ inline double2 cinv(double2 a) {
     const double d = a.x * a.x + a.y * a.y;
@@ -44,9 +35,62 @@ struct GJShape {
     static constexpr int BLOCK = NTHR < 64 ? 64 : NTHR;
 };
 
+// acc - l*u with explicit fused multiply-adds (4 per complex product)
+__device__ inline double2 cfms(double2 acc, double2 l, double2 u) {
+    double2 r;
+    r.x = fma(-l.x, u.x, fma(l.y, u.y, acc.x));
+    r.y = fma(-l.x, u.y, fma(-l.y, u.x, acc.y));
+    return r;
+}
+
+// DPP move of a double inside rows of 16 lanes
+template <int CTRL>
+__device__ inline double dpp_d(double x) {
+    const int lo = __builtin_amdgcn_update_dpp(__double2loint(x), __double2loint(x), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(__double2hiint(x), __double2hiint(x), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ inline int dpp_i(int x) {
+    return __builtin_amdgcn_update_dpp(x, x, CTRL, 0xF, 0xF, false);
+}
+
+// (magnitude, row, value) arg-max step with a DPP partner; ties -> lower row
+template <int CTRL>
+__device__ inline void amax_step(double &m, int &idx, double &vx, double &vy) {
+    const double m2 = dpp_d<CTRL>(m);
+    const int i2 = dpp_i<CTRL>(idx);
+    const double x2 = dpp_d<CTRL>(vx), y2 = dpp_d<CTRL>(vy);
+    const bool take = (m2 > m) || (m2 == m && i2 < idx);
+    m = take ? m2 : m;
+    idx = take ? i2 : idx;
+    vx = take ? x2 : vx;
+    vy = take ? y2 : vy;
+}
+
+// arg-max over the NT lanes of a column group (NT = 4, 8 or 16 consecutive
+// lanes inside one DPP row); every lane of the group ends with the result
+template <int NT>
+__device__ inline void group_amax(double &m, int &idx, double &vx, double &vy) {
+    amax_step<0xB1>(m, idx, vx, vy);                    // quad_perm [1,0,3,2]
+    amax_step<0x4E>(m, idx, vx, vy);                    // quad_perm [2,3,0,1]
+    if (NT >= 8) amax_step<0x141>(m, idx, vx, vy);      // row_half_mirror
+    if (NT >= 16) amax_step<0x140>(m, idx, vx, vy);     // row_mirror
+}
+
 // ADJ = false: rhs = -j w Phi, writes I[s][k].
 // ADJ = true : rhs = rscale * sum_c (rr - j ri) of rpart[c][s][:], writes
 //              gsys[s][k] = 2 Re(mu_k I_k / (j w C_k^2)).
+//
+// Blocked Gauss-Jordan, panels of 4 columns.  Panel kt is owned by the lane
+// group tj == kt, which runs the four pivot steps on its own 4 columns
+// (arg-max by DPP, pivot-row entries by lane shuffles, no barrier) and
+// publishes the multiplier columns l_c (c = 0..3) and pivot rows p_c through
+// LDS.  After one block barrier every other column group applies the
+// composite rank-4 update  a_ij -= sum_c l_c[i] u_cj  with
+//   u_cj = a_{p_c j} - sum_{c' < c} l_{c'}[p_c] u_{c' j}
+// (the pivot row of step c as it stands after steps c' < c).  Column groups
+// left of the panel hold only eliminated columns and skip the update.
 template <int NP, bool ADJ>
 __global__ __launch_bounds__(GJShape<NP>::BLOCK) void k_gj(
     int n, int S, int F, const double *__restrict__ M, const double *__restrict__ Rv,
@@ -62,12 +106,12 @@ __global__ __launch_bounds__(GJShape<NP>::BLOCK) void k_gj(
     const int ti = t % NT, tj = t / NT;
     const int b = s / F, f = s - b * F;
 
-    __shared__ double2 sL[2][NP];
-    __shared__ int sP[2];
+    __shared__ double2 sL[2][4][NP];      // multiplier columns of a panel
+    __shared__ int sP[2][4];              // pivot rows of a panel
     __shared__ double2 sPiv[NP];
     __shared__ int sKof[NP];
-    __shared__ double2 sU[NT][4][4];
-    __shared__ double2 sRhs[4];
+    __shared__ double2 sU[NT][4][4][4];   // [group][step c][row in tile][col in tile]
+    __shared__ double2 sRb[4][4];         // rhs tiles of the pivot-row owners
     __shared__ int sFlag;
 
     if (t == 0) sFlag = 0;
@@ -75,7 +119,7 @@ __global__ __launch_bounds__(GJShape<NP>::BLOCK) void k_gj(
 
     const double w = omega[f];
     const double *Cb = C + (size_t)b * n;
-    const int tb = (n - 1) >> 2;  // column of tiles that carries the rhs
+    const int tb = (n - 1) >> 2;  // column group that carries the rhs
 
     // ---- build the tile of Z and the rhs ---------------------------------
     double2 a[4][4];
@@ -128,106 +172,155 @@ __global__ __launch_bounds__(GJShape<NP>::BLOCK) void k_gj(
         if (flag) atomicOr(&sFlag, flag);
     }
 
-    // ---- elimination ------------------------------------------------------
+    // ---- elimination, one panel of 4 columns per iteration ------------------
     uint64_t used = 0;
-    // one elimination step for column k = 4 kt + C; C is a compile-time
-    // constant so that every access to the tile a[][] has a constant index
-    auto step = [&](int kt, auto cconst) {
-        constexpr int c = decltype(cconst)::value;
-        const int k = 4 * kt + c;
-        if (k >= n) return;  // uniform
-        const int buf = k & 1;
+    for (int kt = 0; 4 * kt < n; ++kt) {
+        const int buf = kt & 1;
+        const int nc = min(4, n - 4 * kt);  // real columns in this panel
+        // -- panel factorisation by the owning column group
         if (act && tj == kt) {
-            double best = -1.0;
-            int bi = 1 << 30;
+            int pc[4];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int i = 4 * ti + r;
-                if (i < n && !((used >> i) & 1ull)) {
-                    double m = fabs(a[r][c].x) + fabs(a[r][c].y);
-                    if (!(m == m)) m = __builtin_inf();  // NaN rows still yield a valid pivot index
-                    if (m > best) {
-                        best = m;
-                        bi = i;
+            for (int c = 0; c < 4; ++c) {
+                pc[c] = 0;
+                if (c >= nc) continue;  // uniform
+                double best = -1.0, vx = 0.0, vy = 0.0;
+                int bi = 1 << 30;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i = 4 * ti + r;
+                    if (i < n && !((used >> i) & 1ull)) {
+                        double m = fabs(a[r][c].x) + fabs(a[r][c].y);
+                        if (!(m == m)) m = __builtin_inf();  // NaN rows still yield a pivot
+                        if (m > best) {
+                            best = m;
+                            bi = i;
+                            vx = a[r][c].x;
+                            vy = a[r][c].y;
+                        }
                     }
                 }
-            }
+                group_amax<NT>(best, bi, vx, vy);
+                // an unused valid row always exists; the clamp keeps the index in range
+                const int p = bi < n ? bi : n - 1;
+                const double2 piv = make_double2(vx, vy);
+                const bool sing = !(piv.x != 0.0 || piv.y != 0.0);
+                const double2 inv = sing ? make_double2(0.0, 0.0) : cinv(piv);
+                const int pr = p & 3, src = p >> 2;
+                double2 l[4];
 #pragma unroll
-            for (int off = 1; off < NT; off <<= 1) {
-                const double ob = __shfl_xor(best, off, NT);
-                const int oi = __shfl_xor(bi, off, NT);
-                if (ob > best || (ob == best && oi < bi)) {
-                    best = ob;
-                    bi = oi;
+                for (int r = 0; r < 4; ++r) {
+                    const int i = 4 * ti + r;
+                    l[r] = (i == p) ? make_double2(0.0, 0.0) : cmul(a[r][c], inv);
+                    sL[buf][c][i] = l[r];
+                }
+                // remaining panel columns: a_ic' -= l_i a_pc'
+#pragma unroll
+                for (int c2 = c + 1; c2 < 4; ++c2) {
+                    const double sx = pr == 0 ? a[0][c2].x : (pr == 1 ? a[1][c2].x : (pr == 2 ? a[2][c2].x : a[3][c2].x));
+                    const double sy = pr == 0 ? a[0][c2].y : (pr == 1 ? a[1][c2].y : (pr == 2 ? a[2][c2].y : a[3][c2].y));
+                    const double2 up = make_double2(__shfl(sx, src, NT), __shfl(sy, src, NT));
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) a[r][c2] = cfms(a[r][c2], l[r], up);
+                }
+                used |= 1ull << p;
+                pc[c] = p;
+                if (ti == 0) {
+                    sPiv[4 * kt + c] = piv;
+                    sKof[p] = 4 * kt + c;
+                    if (sing) atomicOr(&sFlag, COSIM_SYS_SINGULAR);
                 }
             }
-            // every column has an unused valid row, so bi < n; the clamp keeps
-            // the index in range whatever the data
-            const int p = bi < n ? bi : n - 1;
-            const int pr = p & 3;
-            // value select (no address select) of the pivot row's entry
-            const double m0x = a[0][c].x, m0y = a[0][c].y, m1x = a[1][c].x, m1y = a[1][c].y;
-            const double m2x = a[2][c].x, m2y = a[2][c].y, m3x = a[3][c].x, m3y = a[3][c].y;
-            const double mx = pr == 0 ? m0x : (pr == 1 ? m1x : (pr == 2 ? m2x : m3x));
-            const double my = pr == 0 ? m0y : (pr == 1 ? m1y : (pr == 2 ? m2y : m3y));
-            double2 piv;
-            piv.x = __shfl(mx, p >> 2, NT);
-            piv.y = __shfl(my, p >> 2, NT);
-            const bool sing = !(piv.x != 0.0 || piv.y != 0.0);
-            const double2 inv = sing ? make_double2(0.0, 0.0) : cinv(piv);
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int i = 4 * ti + r;
-                sL[buf][i] = (i == p) ? make_double2(0.0, 0.0) : cmul(a[r][c], inv);
-            }
             if (ti == 0) {
-                sP[buf] = p;
-                sPiv[k] = piv;
-                sKof[p] = k;
-                if (sing) atomicOr(&sFlag, COSIM_SYS_SINGULAR);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) sP[buf][c] = pc[c];
+            }
+            if (nc < 4) {  // unused steps of a ragged last panel contribute nothing
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    if (c >= nc)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) sL[buf][c][4 * ti + r] = make_double2(0.0, 0.0);
             }
         }
         __syncthreads();
-        const int p = sP[buf];
-        used |= 1ull << p;
-        if (act && 4 * tj + 3 >= k) {
-            const int pr = p & 3;
-            if (ti == (p >> 2)) {
+        int pc[4];
 #pragma unroll
-                for (int r = 0; r < 4; ++r)
+        for (int c = 0; c < 4; ++c) pc[c] = sP[buf][c];
+        if (!(act && tj == kt)) {
 #pragma unroll
-                    for (int cc = 0; cc < 4; ++cc) sU[tj][r][cc] = a[r][cc];
-                if (tj == tb) {
+            for (int c = 0; c < 4; ++c)
+                if (c < nc) used |= 1ull << pc[c];
+        }
+        const bool upd_tile = act && tj > kt;
+        const bool upd_rhs = act && tj == tb;
+        if (upd_tile || upd_rhs) {
+            // pivot-row owners of this column group publish their tiles / rhs
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) sRhs[r] = rhs[r];
+            for (int c = 0; c < 4; ++c) {
+                if (c < nc && ti == (pc[c] >> 2)) {
+                    if (upd_tile) {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+#pragma unroll
+                            for (int cc = 0; cc < 4; ++cc) sU[tj][c][r][cc] = a[r][cc];
+                    }
+                    if (upd_rhs) {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) sRb[c][r] = rhs[r];
+                    }
                 }
             }
-            // writer and readers of sU[tj] / sRhs are lanes of one wave
+            // writers and readers are lanes of one wave
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
-            double2 u[4], l[4];
+            // l_{c'}[p_c] for c' < c
+            double2 lp[4][4];
 #pragma unroll
-            for (int cc = 0; cc < 4; ++cc) u[cc] = sU[tj][pr][cc];
+            for (int c = 1; c < 4; ++c)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) l[r] = sL[buf][4 * ti + r];
+                for (int c2 = 0; c2 < c; ++c2)
+                    lp[c][c2] = c < nc ? sL[buf][c2][pc[c]] : make_double2(0.0, 0.0);
+            if (upd_tile) {
+                double2 u[4][4];
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
+                for (int c = 0; c < 4; ++c) {
 #pragma unroll
-                for (int cc = 0; cc < 4; ++cc) a[r][cc] = csub_mul(a[r][cc], l[r], u[cc]);
-            if (tj == tb) {
-                const double2 ub = sRhs[pr];
+                    for (int cc = 0; cc < 4; ++cc) {
+                        double2 v = c < nc ? sU[tj][c][pc[c] & 3][cc] : make_double2(0.0, 0.0);
 #pragma unroll
-                for (int r = 0; r < 4; ++r) rhs[r] = csub_mul(rhs[r], l[r], ub);
+                        for (int c2 = 0; c2 < c; ++c2) v = cfms(v, lp[c][c2], u[c2][cc]);
+                        u[c][cc] = v;
+                    }
+                }
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    double2 lr[4];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) lr[r] = sL[buf][c][4 * ti + r];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+#pragma unroll
+                        for (int cc = 0; cc < 4; ++cc) a[r][cc] = cfms(a[r][cc], lr[r], u[c][cc]);
+                }
+            }
+            if (upd_rhs) {
+                double2 ub[4];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    double2 v = c < nc ? sRb[c][pc[c] & 3] : make_double2(0.0, 0.0);
+#pragma unroll
+                    for (int c2 = 0; c2 < c; ++c2) v = cfms(v, lp[c][c2], ub[c2]);
+                    ub[c] = v;
+                }
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) rhs[r] = cfms(rhs[r], sL[buf][c][4 * ti + r], ub[c]);
             }
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
         }
-    };
-    for (int kt = 0; 4 * kt < n; ++kt) {
-        step(kt, std::integral_constant<int, 0>{});
-        step(kt, std::integral_constant<int, 1>{});
-        step(kt, std::integral_constant<int, 2>{});
-        step(kt, std::integral_constant<int, 3>{});
     }
     __syncthreads();
 
