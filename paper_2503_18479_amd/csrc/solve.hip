@@ -24,8 +24,8 @@ __device__ inline double2 cmul(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 __device__ inline double2 cinv(double2 a) {
-    const double d = a.x * a.x + a.y * a.y;
-    return make_double2(a.x / d, -a.y / d);
+    const double d = 1.0 / (a.x * a.x + a.y * a.y);
+    return make_double2(a.x * d, -a.y * d);
 }
 
 template <int NP>
@@ -43,39 +43,36 @@ __device__ inline double2 cfms(double2 acc, double2 l, double2 u) {
     return r;
 }
 
-// DPP move of a double inside rows of 16 lanes
-template <int CTRL>
-__device__ inline double dpp_d(double x) {
-    const int lo = __builtin_amdgcn_update_dpp(__double2loint(x), __double2loint(x), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(__double2hiint(x), __double2hiint(x), CTRL, 0xF, 0xF, false);
-    return __hiloint2double(hi, lo);
-}
 template <int CTRL>
 __device__ inline int dpp_i(int x) {
     return __builtin_amdgcn_update_dpp(x, x, CTRL, 0xF, 0xF, false);
 }
 
-// (magnitude, row, value) arg-max step with a DPP partner; ties -> lower row
+// (magnitude, row) arg-max step with a DPP partner; ties -> lower row
 template <int CTRL>
-__device__ inline void amax_step(double &m, int &idx, double &vx, double &vy) {
-    const double m2 = dpp_d<CTRL>(m);
+__device__ inline void amax_step(float &m, int &idx) {
+    const float m2 = __int_as_float(dpp_i<CTRL>(__float_as_int(m)));
     const int i2 = dpp_i<CTRL>(idx);
-    const double x2 = dpp_d<CTRL>(vx), y2 = dpp_d<CTRL>(vy);
     const bool take = (m2 > m) || (m2 == m && i2 < idx);
     m = take ? m2 : m;
     idx = take ? i2 : idx;
-    vx = take ? x2 : vx;
-    vy = take ? y2 : vy;
 }
 
 // arg-max over the NT lanes of a column group (NT = 4, 8 or 16 consecutive
 // lanes inside one DPP row); every lane of the group ends with the result
 template <int NT>
-__device__ inline void group_amax(double &m, int &idx, double &vx, double &vy) {
-    amax_step<0xB1>(m, idx, vx, vy);                    // quad_perm [1,0,3,2]
-    amax_step<0x4E>(m, idx, vx, vy);                    // quad_perm [2,3,0,1]
-    if (NT >= 8) amax_step<0x141>(m, idx, vx, vy);      // row_half_mirror
-    if (NT >= 16) amax_step<0x140>(m, idx, vx, vy);     // row_mirror
+__device__ inline void group_amax(float &m, int &idx) {
+    amax_step<0xB1>(m, idx);                    // quad_perm [1,0,3,2]
+    amax_step<0x4E>(m, idx);                    // quad_perm [2,3,0,1]
+    if (NT >= 8) amax_step<0x141>(m, idx);      // row_half_mirror
+    if (NT >= 16) amax_step<0x140>(m, idx);     // row_mirror
+}
+
+// value of a double held by lane `src` (wave-uniform index) for every lane
+__device__ inline double readlane_d(double x, int src) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(x), src);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), src);
+    return __hiloint2double(hi, lo);
 }
 
 // ADJ = false: rhs = -j w Phi, writes I[s][k].
@@ -84,13 +81,15 @@ __device__ inline void group_amax(double &m, int &idx, double &vx, double &vy) {
 //
 // Blocked Gauss-Jordan, panels of 4 columns.  Panel kt is owned by the lane
 // group tj == kt, which runs the four pivot steps on its own 4 columns
-// (arg-max by DPP, pivot-row entries by lane shuffles, no barrier) and
+// (arg-max by DPP, pivot-row entries by readlane, no barrier) and
 // publishes the multiplier columns l_c (c = 0..3) and pivot rows p_c through
 // LDS.  After one block barrier every other column group applies the
 // composite rank-4 update  a_ij -= sum_c l_c[i] u_cj  with
 //   u_cj = a_{p_c j} - sum_{c' < c} l_{c'}[p_c] u_{c' j}
-// (the pivot row of step c as it stands after steps c' < c).  Column groups
-// left of the panel hold only eliminated columns and skip the update.
+// (the pivot row of step c as it stands after steps c' < c), i.e. u = W a_p
+// with W = (I + N)^-1, N[c][c'] = l_{c'}[p_c]; the panel group publishes W.
+// Column groups left of the panel hold only eliminated columns and skip the
+// update.
 template <int NP, bool ADJ>
 __global__ __launch_bounds__(GJShape<NP>::BLOCK) void k_gj(
     int n, int S, int F, const double *__restrict__ M, const double *__restrict__ Rv,
@@ -111,6 +110,8 @@ __global__ __launch_bounds__(GJShape<NP>::BLOCK) void k_gj(
     __shared__ double2 sPiv[NP];
     __shared__ int sKof[NP];
     __shared__ double2 sU[NT][4][4][4];   // [group][step c][row in tile][col in tile]
+    __shared__ double2 sUu[NT][4][4];     // [group][step c][col in tile]: u_c of the group's columns
+    __shared__ double2 sW[2][4][4];       // W = (I + N)^-1, N[c][c'] = l_c'[p_c] (c' < c)
     __shared__ double2 sRb[4][4];         // rhs tiles of the pivot-row owners
     __shared__ int sFlag;
 
@@ -179,34 +180,45 @@ __global__ __launch_bounds__(GJShape<NP>::BLOCK) void k_gj(
         const int nc = min(4, n - 4 * kt);  // real columns in this panel
         // -- panel factorisation by the owning column group
         if (act && tj == kt) {
+            // first lane of this column group (the group is the only active one here)
+            const int gbase = __builtin_amdgcn_readfirstlane((int)(threadIdx.x & 63));
             int pc[4];
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 pc[c] = 0;
                 if (c >= nc) continue;  // uniform
-                double best = -1.0, vx = 0.0, vy = 0.0;
+                // pivot search on |re| + |im| rounded to float: any near-maximal
+                // pivot is as good, and the float arg-max needs 2 DPP moves per round
+                float best = -1.0f;
                 int bi = 1 << 30;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int i = 4 * ti + r;
                     if (i < n && !((used >> i) & 1ull)) {
-                        double m = fabs(a[r][c].x) + fabs(a[r][c].y);
-                        if (!(m == m)) m = __builtin_inf();  // NaN rows still yield a pivot
+                        float m = (float)(fabs(a[r][c].x) + fabs(a[r][c].y));
+                        if (!(m == m)) m = __builtin_inff();  // NaN rows still yield a pivot
                         if (m > best) {
                             best = m;
                             bi = i;
-                            vx = a[r][c].x;
-                            vy = a[r][c].y;
                         }
                     }
                 }
-                group_amax<NT>(best, bi, vx, vy);
-                // an unused valid row always exists; the clamp keeps the index in range
-                const int p = bi < n ? bi : n - 1;
-                const double2 piv = make_double2(vx, vy);
+                group_amax<NT>(best, bi);
+                // the group's lanes agree on the pivot: make it wave-uniform; an unused
+                // valid row always exists and the clamp keeps the index in range
+                int p = __builtin_amdgcn_readfirstlane(bi);
+                p = p < n ? p : n - 1;
+                const int pr = p & 3;
+                const int src = gbase + (p >> 2);  // lane holding row p
+                auto rowsel = [&](int cc, bool im) {
+                    const double v0 = im ? a[0][cc].y : a[0][cc].x, v1 = im ? a[1][cc].y : a[1][cc].x;
+                    const double v2 = im ? a[2][cc].y : a[2][cc].x, v3 = im ? a[3][cc].y : a[3][cc].x;
+                    return pr == 0 ? v0 : (pr == 1 ? v1 : (pr == 2 ? v2 : v3));
+                };
+                const double2 piv = make_double2(readlane_d(rowsel(c, false), src),
+                                                 readlane_d(rowsel(c, true), src));
                 const bool sing = !(piv.x != 0.0 || piv.y != 0.0);
                 const double2 inv = sing ? make_double2(0.0, 0.0) : cinv(piv);
-                const int pr = p & 3, src = p >> 2;
                 double2 l[4];
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
@@ -217,9 +229,8 @@ __global__ __launch_bounds__(GJShape<NP>::BLOCK) void k_gj(
                 // remaining panel columns: a_ic' -= l_i a_pc'
 #pragma unroll
                 for (int c2 = c + 1; c2 < 4; ++c2) {
-                    const double sx = pr == 0 ? a[0][c2].x : (pr == 1 ? a[1][c2].x : (pr == 2 ? a[2][c2].x : a[3][c2].x));
-                    const double sy = pr == 0 ? a[0][c2].y : (pr == 1 ? a[1][c2].y : (pr == 2 ? a[2][c2].y : a[3][c2].y));
-                    const double2 up = make_double2(__shfl(sx, src, NT), __shfl(sy, src, NT));
+                    const double2 up = make_double2(readlane_d(rowsel(c2, false), src),
+                                                    readlane_d(rowsel(c2, true), src));
 #pragma unroll
                     for (int r = 0; r < 4; ++r) a[r][c2] = cfms(a[r][c2], l[r], up);
                 }
@@ -234,6 +245,33 @@ __global__ __launch_bounds__(GJShape<NP>::BLOCK) void k_gj(
             if (ti == 0) {
 #pragma unroll
                 for (int c = 0; c < 4; ++c) sP[buf][c] = pc[c];
+            }
+            // W = (I + N)^-1 (unit lower triangular) so that the pivot rows as
+            // they stand at their own step are u = W a_p (a_p: rows before the panel)
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            if (ti == 0) {
+                double2 N[4][4], Wm[4][4];
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+#pragma unroll
+                    for (int c2 = 0; c2 < 4; ++c2) {
+                        N[c][c2] = (c2 < c && c < nc) ? sL[buf][c2][pc[c]] : make_double2(0.0, 0.0);
+                        Wm[c][c2] = make_double2(c == c2 ? 1.0 : 0.0, 0.0);
+                    }
+#pragma unroll
+                for (int c = 1; c < 4; ++c)
+#pragma unroll
+                    for (int c2 = 0; c2 < c; ++c2) {
+                        double2 v = make_double2(0.0, 0.0);
+#pragma unroll
+                        for (int c3 = c2; c3 < c; ++c3) v = cfms(v, N[c][c3], Wm[c3][c2]);
+                        Wm[c][c2] = v;
+                    }
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+#pragma unroll
+                    for (int c2 = 0; c2 < 4; ++c2) sW[buf][c][c2] = Wm[c][c2];
             }
             if (nc < 4) {  // unused steps of a ragged last panel contribute nothing
 #pragma unroll
@@ -274,49 +312,55 @@ __global__ __launch_bounds__(GJShape<NP>::BLOCK) void k_gj(
             // writers and readers are lanes of one wave
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
-            // l_{c'}[p_c] for c' < c
-            double2 lp[4][4];
-#pragma unroll
-            for (int c = 1; c < 4; ++c)
-#pragma unroll
-                for (int c2 = 0; c2 < c; ++c2)
-                    lp[c][c2] = c < nc ? sL[buf][c2][pc[c]] : make_double2(0.0, 0.0);
             if (upd_tile) {
-                double2 u[4][4];
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-#pragma unroll
-                    for (int cc = 0; cc < 4; ++cc) {
-                        double2 v = c < nc ? sU[tj][c][pc[c] & 3][cc] : make_double2(0.0, 0.0);
-#pragma unroll
-                        for (int c2 = 0; c2 < c; ++c2) v = cfms(v, lp[c][c2], u[c2][cc]);
-                        u[c][cc] = v;
+                // lane ti forms u[c][cc] for c = ti / 4, cc = ti % 4 (NT >= 16), or a
+                // strided share of the 16 entries (NT < 16)
+                for (int e = ti; e < 16; e += NT) {
+                    const int c = e >> 2, cc = e & 3;
+                    double2 v = make_double2(0.0, 0.0);
+                    if (c < nc) {
+                        for (int c2 = 0; c2 <= c; ++c2) {
+                            const double2 wv = sW[buf][c][c2];
+                            const double2 ap = sU[tj][c2][pc[c2] & 3][cc];
+                            v.x = fma(wv.x, ap.x, fma(-wv.y, ap.y, v.x));
+                            v.y = fma(wv.x, ap.y, fma(wv.y, ap.x, v.y));
+                        }
                     }
+                    sUu[tj][c][cc] = v;
                 }
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                __builtin_amdgcn_wave_barrier();
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
-                    double2 lr[4];
+                    if (c >= nc) continue;  // uniform
+                    double2 lr[4], uc[4];
 #pragma unroll
                     for (int r = 0; r < 4; ++r) lr[r] = sL[buf][c][4 * ti + r];
 #pragma unroll
+                    for (int cc = 0; cc < 4; ++cc) uc[cc] = sUu[tj][c][cc];
+#pragma unroll
                     for (int r = 0; r < 4; ++r)
 #pragma unroll
-                        for (int cc = 0; cc < 4; ++cc) a[r][cc] = cfms(a[r][cc], lr[r], u[c][cc]);
+                        for (int cc = 0; cc < 4; ++cc) a[r][cc] = cfms(a[r][cc], lr[r], uc[cc]);
                 }
             }
             if (upd_rhs) {
-                double2 ub[4];
+                double2 bp[4];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) bp[c] = c < nc ? sRb[c][pc[c] & 3] : make_double2(0.0, 0.0);
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
-                    double2 v = c < nc ? sRb[c][pc[c] & 3] : make_double2(0.0, 0.0);
+                    if (c >= nc) continue;  // uniform
+                    double2 ub = make_double2(0.0, 0.0);
 #pragma unroll
-                    for (int c2 = 0; c2 < c; ++c2) v = cfms(v, lp[c][c2], ub[c2]);
-                    ub[c] = v;
+                    for (int c2 = 0; c2 <= c; ++c2) {
+                        const double2 wv = sW[buf][c][c2];
+                        ub.x = fma(wv.x, bp[c2].x, fma(-wv.y, bp[c2].y, ub.x));
+                        ub.y = fma(wv.x, bp[c2].y, fma(wv.y, bp[c2].x, ub.y));
+                    }
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) rhs[r] = cfms(rhs[r], sL[buf][c][4 * ti + r], ub);
                 }
-#pragma unroll
-                for (int c = 0; c < 4; ++c)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) rhs[r] = cfms(rhs[r], sL[buf][c][4 * ti + r], ub[c]);
             }
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
