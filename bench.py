@@ -139,7 +139,15 @@ def main():
 
     if args.profile_steps is not None:
         time_mode(plan, C, om, T, args.mixed, args.profile_steps, 1, torch)
-        print(f"[bench] profiled {args.profile_steps} steps of {args.mixed}", file=sys.stderr)
+        # reference copy of known size (256 MiB read + 256 MiB written) that
+        # calibrates the HBM byte counters of a profiler run
+        x = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=dev)
+        x.fill_(1.0)
+        y = x.clone()
+        torch.cuda.synchronize()
+        del x, y
+        print(f"[bench] profiled {args.profile_steps} steps of {args.mixed} and a 256 MiB copy",
+              file=sys.stderr)
         return
 
     S = wl.B * wl.F
