@@ -82,6 +82,9 @@ void plan_free_workspace(cosim_plan *p) {
     dfree(p->rpart);
     dfree(p->lpart);
     dfree(p->gsys);
+    dfree(p->fac.L);
+    dfree(p->fac.piv_row);
+    dfree(p->fac.piv_val);
     p->cap_systems = 0;
     p->cap_chunks = 0;
 }
@@ -105,7 +108,10 @@ int ensure_workspace(cosim_plan *p, size_t systems, int chunks) {
     if (hipMalloc((void **)&p->I_ws, ns * n * sizeof(double2)) != hipSuccess ||
         hipMalloc((void **)&p->rpart, (size_t)nc * ns * NP * sizeof(double2)) != hipSuccess ||
         hipMalloc((void **)&p->lpart, (size_t)nc * ns * sizeof(double)) != hipSuccess ||
-        hipMalloc((void **)&p->gsys, ns * n * sizeof(double)) != hipSuccess) {
+        hipMalloc((void **)&p->gsys, ns * n * sizeof(double)) != hipSuccess ||
+        hipMalloc((void **)&p->fac.L, ns * NP * NP * sizeof(double2)) != hipSuccess ||
+        hipMalloc((void **)&p->fac.piv_row, ns * NP * sizeof(int)) != hipSuccess ||
+        hipMalloc((void **)&p->fac.piv_val, ns * NP * sizeof(double2)) != hipSuccess) {
         plan_free_workspace(p);
         (void)hipGetLastError();
         return fail(COSIM_ENOMEM, "workspace allocation for %zu systems x %d chunks failed", ns,
@@ -348,7 +354,7 @@ int cosim_solve(cosim_plan_t p, int B, int F, const double *C_d, const double *o
     if ((rc = check_device(p))) return rc;
     const int S = B * F;
     HIP_TRY(launch_solve_forward(p->NP, p->n, S, F, p->M_d, p->R_d, p->phi_d, C_d, omega_d,
-                                 (double2 *)I_d, status_d, (hipStream_t)stream));
+                                 (double2 *)I_d, status_d, GJFactor{}, (hipStream_t)stream));
     return COSIM_OK;
 }
 
@@ -418,8 +424,11 @@ int cosim_loss_and_grad(cosim_plan_t p, int B, int F, const double *C_d, const d
     hipEvent_t *ev = nullptr;
     if (p->timing_used < p->timing_cap) ev = &p->events[(size_t)p->timing_used++ * (COSIM_PHASES + 1)];
     if (ev) HIP_TRY(hipEventRecord(ev[0], st));
+    // the forward elimination is recorded when the gradient is wanted, and the
+    // adjoint solve replays it instead of eliminating Z a second time
+    const bool grad = grad_d != nullptr;
     HIP_TRY(launch_solve_forward(p->NP, p->n, (int)S, F, p->M_d, p->R_d, p->phi_d, C_d, omega_d,
-                                 p->I_ws, status_d, st));
+                                 p->I_ws, status_d, grad ? p->fac : GJFactor{}, st));
     if (ev) HIP_TRY(hipEventRecord(ev[1], st));
     FusedArgs a;
     a.G = precision == COSIM_FP64 ? (const void *)p->G64
@@ -436,13 +445,12 @@ int cosim_loss_and_grad(cosim_plan_t p, int B, int F, const double *C_d, const d
     a.n = p->n;
     a.rpart = p->rpart;
     a.lpart = p->lpart;
-    const bool grad = grad_d != nullptr;
     HIP_TRY(launch_fused(prec, p->NP, loss_mode, grad, a, st));
     if (ev) HIP_TRY(hipEventRecord(ev[2], st));
     const double scale = 1.0 / ((double)F * (double)p->P);
     if (grad)
-        HIP_TRY(launch_solve_adjoint(p->NP, p->n, (int)S, F, p->M_d, p->R_d, C_d, omega_d, p->I_ws,
-                                     p->rpart, nchunk, scale, p->gsys, status_d, true, st));
+        HIP_TRY(launch_solve_adjoint_replay(p->NP, p->n, (int)S, F, p->fac, C_d, omega_d, p->I_ws,
+                                            p->rpart, nchunk, scale, p->gsys, status_d, st));
     if (ev) HIP_TRY(hipEventRecord(ev[3], st));
     HIP_TRY(launch_reduce(p->n, B, F, nchunk, grad ? p->gsys : nullptr, p->lpart, scale, grad_d,
                           loss_d, st));

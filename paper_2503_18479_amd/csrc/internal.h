@@ -44,11 +44,28 @@ hipError_t launch_assemble_M(int n, const int32_t *seg_off_d, const double *vert
                              const double *wire_a_d, const GLRule &gl, double *M_d,
                              hipStream_t st);
 
-// Forward solve: Z I = -j w Phi for S = B*F systems (s = b*F + f).
+// Record of a forward elimination (optional): multiplier column of every step
+// L[s][k][i] (NP x NP per system), pivot row piv_row[s][k] and value piv_val[s][k].
+struct GJFactor {
+    double2 *L = nullptr;
+    int *piv_row = nullptr;
+    double2 *piv_val = nullptr;
+};
+
+// Forward solve: Z I = -j w Phi for S = B*F systems (s = b*F + f); records
+// the elimination in `fac` when fac.L is set.
 hipError_t launch_solve_forward(int NP, int n, int S, int F, const double *M_d,
                                 const double *R_d, const double *phi_d, const double *C_d,
                                 const double *omega_d, double2 *I_d, int32_t *status_d,
-                                hipStream_t st);
+                                GJFactor fac, hipStream_t st);
+
+// Adjoint solve by replaying a recorded forward elimination (same result as
+// launch_solve_adjoint with or_status = true, without a second elimination).
+hipError_t launch_solve_adjoint_replay(int NP, int n, int S, int F, GJFactor fac,
+                                       const double *C_d, const double *omega_d,
+                                       const double2 *I_d, const double2 *rpart_d, int nchunk,
+                                       double rscale, double *gsys_d, int32_t *status_d,
+                                       hipStream_t st);
 
 // Adjoint solve: Z mu = rscale * sum_c (rr_c - j ri_c); writes the per-system
 // gradient term gsys[s][k] = 2 Re(mu_k I_k / (j w C_k^2)).  The system status
@@ -115,6 +132,7 @@ struct cosim_plan {
     double2 *rpart = nullptr;
     double *lpart = nullptr;
     double *gsys = nullptr;
+    cosim::GJFactor fac;  // recorded forward eliminations (loss_and_grad)
     // optional phase timing: (COSIM_PHASES + 1) events per recorded call
     std::vector<hipEvent_t> events;
     int timing_cap = 0, timing_used = 0;

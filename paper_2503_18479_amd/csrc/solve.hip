@@ -96,7 +96,8 @@ __global__ __launch_bounds__(GJShape<NP>::BLOCK) void k_gj(
     const double *__restrict__ phi, const double *__restrict__ C,
     const double *__restrict__ omega, const double2 *__restrict__ Iin,
     const double2 *__restrict__ rpart, int nchunk, double rscale, double2 *__restrict__ Iout,
-    double *__restrict__ gsys, int32_t *__restrict__ status, bool or_status) {
+    double *__restrict__ gsys, int32_t *__restrict__ status, bool or_status,
+    GJFactor fac) {
     constexpr int NT = GJShape<NP>::NT;
     constexpr int NTHR = GJShape<NP>::NTHR;
     const int s = blockIdx.x;
@@ -220,11 +221,13 @@ __global__ __launch_bounds__(GJShape<NP>::BLOCK) void k_gj(
                 const bool sing = !(piv.x != 0.0 || piv.y != 0.0);
                 const double2 inv = sing ? make_double2(0.0, 0.0) : cinv(piv);
                 double2 l[4];
+                double2 *lcol = fac.L ? fac.L + ((size_t)s * NP + 4 * kt + c) * NP : nullptr;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int i = 4 * ti + r;
                     l[r] = (i == p) ? make_double2(0.0, 0.0) : cmul(a[r][c], inv);
                     sL[buf][c][i] = l[r];
+                    if (lcol) lcol[i] = l[r];
                 }
                 // remaining panel columns: a_ic' -= l_i a_pc'
 #pragma unroll
@@ -240,6 +243,10 @@ __global__ __launch_bounds__(GJShape<NP>::BLOCK) void k_gj(
                     sPiv[4 * kt + c] = piv;
                     sKof[p] = 4 * kt + c;
                     if (sing) atomicOr(&sFlag, COSIM_SYS_SINGULAR);
+                    if (fac.L) {
+                        fac.piv_row[(size_t)s * NP + 4 * kt + c] = p;
+                        fac.piv_val[(size_t)s * NP + 4 * kt + c] = piv;
+                    }
                 }
             }
             if (ti == 0) {
@@ -401,6 +408,76 @@ __global__ __launch_bounds__(GJShape<NP>::BLOCK) void k_gj(
     }
 }
 
+// Replays the row operations recorded by a forward elimination on a new
+// right-hand side (the adjoint rhs), so the adjoint needs no second
+// elimination: b <- b - l_k b_{p_k} for k = 0..n-1, then mu_k = b_{p_k} / piv_k
+// (Z is complex symmetric, so the same transform solves Z^T mu = r).  One
+// wave per system, lane i holds b_i; step k reads the recorded multiplier
+// column l_k (one coalesced 16-byte load per lane) and broadcasts b_{p_k}
+// with readlane.  Writes gsys[s][k] = 2 Re(mu_k I_k / (j w C_k^2)).
+template <int NP>
+__global__ __launch_bounds__(256) void k_gj_apply(int n, int S, int F, GJFactor fac,
+                                                  const double *__restrict__ C,
+                                                  const double *__restrict__ omega,
+                                                  const double2 *__restrict__ Iin,
+                                                  const double2 *__restrict__ rpart, int nchunk,
+                                                  double rscale, double *__restrict__ gsys,
+                                                  int32_t *__restrict__ status) {
+    const int lane = threadIdx.x & 63;
+    const int s = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
+    if (s >= S) return;  // whole wave; no block-level synchronisation below
+    const int b = s / F, f = s - b * F;
+    const double w = omega[f];
+    double2 x = make_double2(0.0, 0.0);
+    if (lane < n) {
+        double rr = 0.0, ri = 0.0;
+        for (int c = 0; c < nchunk; ++c) {
+            const double2 v = rpart[((size_t)c * S + s) * NP + lane];
+            rr += v.x;
+            ri += v.y;
+        }
+        x = make_double2(rscale * rr, -rscale * ri);
+    }
+    const double2 *__restrict__ Ls = fac.L + (size_t)s * NP * NP;
+    const int *__restrict__ Ps = fac.piv_row + (size_t)s * NP;
+    constexpr int U = 8;
+    int k0 = 0;
+    for (; k0 + U <= n; k0 += U) {
+        double2 l[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            l[u] = lane < NP ? Ls[(size_t)(k0 + u) * NP + lane] : make_double2(0.0, 0.0);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int p = Ps[k0 + u];
+            const double2 bp = make_double2(readlane_d(x.x, p), readlane_d(x.y, p));
+            x = cfms(x, l[u], bp);
+        }
+    }
+    for (; k0 < n; ++k0) {
+        const double2 l = lane < NP ? Ls[(size_t)k0 * NP + lane] : make_double2(0.0, 0.0);
+        const int p = Ps[k0];
+        const double2 bp = make_double2(readlane_d(x.x, p), readlane_d(x.y, p));
+        x = cfms(x, l, bp);
+    }
+    const int pk = lane < n ? Ps[lane] : 0;
+    const double2 bpk = make_double2(__shfl(x.x, pk), __shfl(x.y, pk));
+    const int flag = status[s];
+    const bool bad = (flag & (COSIM_SYS_BAD_INPUT | COSIM_SYS_SINGULAR)) != 0;
+    bool nonfinite = false;
+    if (lane < n) {
+        double2 mu = cmul(bpk, cinv(fac.piv_val[(size_t)s * NP + lane]));
+        if (bad) mu = make_double2(__builtin_nan(""), __builtin_nan(""));
+        const double2 Ik = Iin[(size_t)s * n + lane];
+        const double ck = C[(size_t)b * n + lane];
+        // 2 Re(mu I / (j w C^2)) = 2 Im(mu I) / (w C^2)
+        const double g = 2.0 * (mu.x * Ik.y + mu.y * Ik.x) / (w * ck * ck);
+        gsys[(size_t)s * n + lane] = g;
+        nonfinite = !bad && !isfinite(g);
+    }
+    if (__ballot(nonfinite) != 0 && lane == 0) status[s] = flag | COSIM_SYS_NONFINITE;
+}
+
 __global__ __launch_bounds__(256) void k_reduce(int n, int B, int F, int nchunk,
                                                 const double *__restrict__ gsys,
                                                 const double *__restrict__ lpart, double lscale,
@@ -427,22 +504,23 @@ template <bool ADJ>
 hipError_t launch_gj(int NP, int n, int S, int F, const double *M, const double *R,
                      const double *phi, const double *C, const double *omega, const double2 *Iin,
                      const double2 *rpart, int nchunk, double rscale, double2 *Iout,
-                     double *gsys, int32_t *status, bool or_status, hipStream_t st) {
+                     double *gsys, int32_t *status, bool or_status, GJFactor fac,
+                     hipStream_t st) {
     switch (NP) {
         case 16:
             hipLaunchKernelGGL((k_gj<16, ADJ>), dim3(S), dim3(GJShape<16>::BLOCK), 0, st, n, S,
                                F, M, R, phi, C, omega, Iin, rpart, nchunk, rscale, Iout, gsys,
-                               status, or_status);
+                               status, or_status, fac);
             break;
         case 32:
             hipLaunchKernelGGL((k_gj<32, ADJ>), dim3(S), dim3(GJShape<32>::BLOCK), 0, st, n, S,
                                F, M, R, phi, C, omega, Iin, rpart, nchunk, rscale, Iout, gsys,
-                               status, or_status);
+                               status, or_status, fac);
             break;
         case 64:
             hipLaunchKernelGGL((k_gj<64, ADJ>), dim3(S), dim3(GJShape<64>::BLOCK), 0, st, n, S,
                                F, M, R, phi, C, omega, Iin, rpart, nchunk, rscale, Iout, gsys,
-                               status, or_status);
+                               status, or_status, fac);
             break;
         default:
             return hipErrorInvalidValue;
@@ -455,9 +533,34 @@ hipError_t launch_gj(int NP, int n, int S, int F, const double *M, const double 
 hipError_t launch_solve_forward(int NP, int n, int S, int F, const double *M_d,
                                 const double *R_d, const double *phi_d, const double *C_d,
                                 const double *omega_d, double2 *I_d, int32_t *status_d,
-                                hipStream_t st) {
+                                GJFactor fac, hipStream_t st) {
     return launch_gj<false>(NP, n, S, F, M_d, R_d, phi_d, C_d, omega_d, nullptr, nullptr, 0, 0.0,
-                            I_d, nullptr, status_d, false, st);
+                            I_d, nullptr, status_d, false, fac, st);
+}
+
+hipError_t launch_solve_adjoint_replay(int NP, int n, int S, int F, GJFactor fac,
+                                       const double *C_d, const double *omega_d,
+                                       const double2 *I_d, const double2 *rpart_d, int nchunk,
+                                       double rscale, double *gsys_d, int32_t *status_d,
+                                       hipStream_t st) {
+    const dim3 grid((S + 3) / 4);
+    switch (NP) {
+        case 16:
+            hipLaunchKernelGGL(k_gj_apply<16>, grid, dim3(256), 0, st, n, S, F, fac, C_d, omega_d,
+                               I_d, rpart_d, nchunk, rscale, gsys_d, status_d);
+            break;
+        case 32:
+            hipLaunchKernelGGL(k_gj_apply<32>, grid, dim3(256), 0, st, n, S, F, fac, C_d, omega_d,
+                               I_d, rpart_d, nchunk, rscale, gsys_d, status_d);
+            break;
+        case 64:
+            hipLaunchKernelGGL(k_gj_apply<64>, grid, dim3(256), 0, st, n, S, F, fac, C_d, omega_d,
+                               I_d, rpart_d, nchunk, rscale, gsys_d, status_d);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_solve_adjoint(int NP, int n, int S, int F, const double *M_d,
@@ -466,7 +569,7 @@ hipError_t launch_solve_adjoint(int NP, int n, int S, int F, const double *M_d,
                                 double rscale, double *gsys_d, int32_t *status_d,
                                 bool or_status, hipStream_t st) {
     return launch_gj<true>(NP, n, S, F, M_d, R_d, nullptr, C_d, omega_d, I_d, rpart_d, nchunk,
-                           rscale, nullptr, gsys_d, status_d, or_status, st);
+                           rscale, nullptr, gsys_d, status_d, or_status, GJFactor{}, st);
 }
 
 hipError_t launch_reduce(int n, int B, int F, int nchunk, const double *gsys_d,
