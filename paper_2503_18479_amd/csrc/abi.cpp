@@ -85,6 +85,7 @@ void plan_free_workspace(cosim_plan *p) {
     dfree(p->fac.L);
     dfree(p->fac.piv_row);
     dfree(p->fac.piv_val);
+    dfree(p->fac.fmt);
     p->cap_systems = 0;
     p->cap_chunks = 0;
 }
@@ -111,7 +112,8 @@ int ensure_workspace(cosim_plan *p, size_t systems, int chunks) {
         hipMalloc((void **)&p->gsys, ns * n * sizeof(double)) != hipSuccess ||
         hipMalloc((void **)&p->fac.L, ns * NP * NP * sizeof(double2)) != hipSuccess ||
         hipMalloc((void **)&p->fac.piv_row, ns * NP * sizeof(int)) != hipSuccess ||
-        hipMalloc((void **)&p->fac.piv_val, ns * NP * sizeof(double2)) != hipSuccess) {
+        hipMalloc((void **)&p->fac.piv_val, ns * NP * sizeof(double2)) != hipSuccess ||
+        hipMalloc((void **)&p->fac.fmt, ns * sizeof(int)) != hipSuccess) {
         plan_free_workspace(p);
         (void)hipGetLastError();
         return fail(COSIM_ENOMEM, "workspace allocation for %zu systems x %d chunks failed", ns,
@@ -234,6 +236,8 @@ int cosim_assemble(cosim_geom_t g, int P, const double *pts_d, double bext_z, vo
     p->bext_z = bext_z;
     p->phi_h.resize(g->n);
     for (int k = 0; k < g->n; ++k) p->phi_h[k] = bext_z * g->area_z[k];
+    p->ldl_ok = true;
+    for (int k = 0; k < g->n; ++k) p->ldl_ok = p->ldl_ok && g->R[k] > 0.0;
 
     int32_t *seg_d = nullptr;
     double *verts_d = nullptr, *wa_d = nullptr;
@@ -424,11 +428,21 @@ int cosim_loss_and_grad(cosim_plan_t p, int B, int F, const double *C_d, const d
     hipEvent_t *ev = nullptr;
     if (p->timing_used < p->timing_cap) ev = &p->events[(size_t)p->timing_used++ * (COSIM_PHASES + 1)];
     if (ev) HIP_TRY(hipEventRecord(ev[0], st));
-    // the forward elimination is recorded when the gradient is wanted, and the
-    // adjoint solve replays it instead of eliminating Z a second time
+    // Z is factorised once and the factorisation recorded; the forward solve and
+    // the adjoint solve both replay the record.  With every R_k > 0 the
+    // unpivoted LDL^T path runs and hands systems with a small pivot to the
+    // pivoted Gauss-Jordan fallback; otherwise Gauss-Jordan runs for all.
     const bool grad = grad_d != nullptr;
-    HIP_TRY(launch_solve_forward(p->NP, p->n, (int)S, F, p->M_d, p->R_d, p->phi_d, C_d, omega_d,
-                                 p->I_ws, status_d, grad ? p->fac : GJFactor{}, st));
+    if (p->ldl_ok) {
+        HIP_TRY(launch_ldl(p->NP, p->n, (int)S, F, p->M_d, p->R_d, C_d, omega_d, p->fac, status_d, st));
+        HIP_TRY(launch_solve_fallback(p->NP, p->n, (int)S, F, p->M_d, p->R_d, p->phi_d, C_d,
+                                      omega_d, p->I_ws, status_d, p->fac, st));
+        HIP_TRY(launch_replay_forward(p->NP, p->n, (int)S, F, p->fac, p->phi_d, omega_d, p->I_ws,
+                                      status_d, st));
+    } else {
+        HIP_TRY(launch_solve_forward(p->NP, p->n, (int)S, F, p->M_d, p->R_d, p->phi_d, C_d,
+                                     omega_d, p->I_ws, status_d, p->fac, st));
+    }
     if (ev) HIP_TRY(hipEventRecord(ev[1], st));
     FusedArgs a;
     a.G = precision == COSIM_FP64 ? (const void *)p->G64
@@ -449,8 +463,8 @@ int cosim_loss_and_grad(cosim_plan_t p, int B, int F, const double *C_d, const d
     if (ev) HIP_TRY(hipEventRecord(ev[2], st));
     const double scale = 1.0 / ((double)F * (double)p->P);
     if (grad)
-        HIP_TRY(launch_solve_adjoint_replay(p->NP, p->n, (int)S, F, p->fac, C_d, omega_d, p->I_ws,
-                                            p->rpart, nchunk, scale, p->gsys, status_d, st));
+        HIP_TRY(launch_replay_adjoint(p->NP, p->n, (int)S, F, p->fac, C_d, omega_d, p->I_ws,
+                                      p->rpart, nchunk, scale, p->gsys, status_d, st));
     if (ev) HIP_TRY(hipEventRecord(ev[3], st));
     HIP_TRY(launch_reduce(p->n, B, F, nchunk, grad ? p->gsys : nullptr, p->lpart, scale, grad_d,
                           loss_d, st));

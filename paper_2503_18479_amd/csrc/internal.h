@@ -44,32 +44,51 @@ hipError_t launch_assemble_M(int n, const int32_t *seg_off_d, const double *vert
                              const double *wire_a_d, const GLRule &gl, double *M_d,
                              hipStream_t st);
 
-// Record of a forward elimination (optional): multiplier column of every step
-// L[s][k][i] (NP x NP per system), pivot row piv_row[s][k] and value piv_val[s][k].
+// Record of a factorisation, per system s, in one of two formats (fmt[s]):
+//   kFmtLDL: L[s][k][i] = L_ik (i > k) of Z = L D L^T, piv_val[s][k] = 1/d_k;
+//   kFmtGJ : L[s][k][i] = multiplier of Gauss-Jordan step k for row i,
+//            piv_row[s][k] = pivot row, piv_val[s][k] = pivot value.
 struct GJFactor {
     double2 *L = nullptr;
     int *piv_row = nullptr;
     double2 *piv_val = nullptr;
+    int *fmt = nullptr;
 };
+constexpr int kFmtLDL = 0, kFmtGJ = 1, kFmtNeedsPivot = 2;
+constexpr int kFlagPivot = 1 << 16;  // kernel-internal status bit, never returned
 
-// Forward solve: Z I = -j w Phi for S = B*F systems (s = b*F + f); records
-// the elimination in `fac` when fac.L is set.
+// LDL^T fast path (all R_k > 0): factorises and records; marks systems that
+// need pivoting (fmt = kFmtNeedsPivot) for launch_solve_fallback.
+hipError_t launch_ldl(int NP, int n, int S, int F, const double *M_d, const double *R_d,
+                      const double *C_d, const double *omega_d, GJFactor fac, int32_t *status_d,
+                      hipStream_t st);
+// Pivoted Gauss-Jordan for the marked systems only (writes I and a kFmtGJ record).
+hipError_t launch_solve_fallback(int NP, int n, int S, int F, const double *M_d,
+                                 const double *R_d, const double *phi_d, const double *C_d,
+                                 const double *omega_d, double2 *I_d, int32_t *status_d,
+                                 GJFactor fac, hipStream_t st);
+// Forward solve I = Z^-1 (-j w Phi) from the record (kFmtLDL systems).
+hipError_t launch_replay_forward(int NP, int n, int S, int F, GJFactor fac, const double *phi_d,
+                                 const double *omega_d, double2 *I_d, int32_t *status_d,
+                                 hipStream_t st);
+// Adjoint solve from the record and the per-system gradient terms.
+hipError_t launch_replay_adjoint(int NP, int n, int S, int F, GJFactor fac, const double *C_d,
+                                 const double *omega_d, double2 *I_d, const double2 *rpart_d,
+                                 int nchunk, double rscale, double *gsys_d, int32_t *status_d,
+                                 hipStream_t st);
+
+// Forward solve by pivoted Gauss-Jordan: Z I = -j w Phi for S = B*F systems
+// (s = b*F + f); records the elimination (kFmtGJ) in `fac` when fac.L is set.
 hipError_t launch_solve_forward(int NP, int n, int S, int F, const double *M_d,
                                 const double *R_d, const double *phi_d, const double *C_d,
                                 const double *omega_d, double2 *I_d, int32_t *status_d,
                                 GJFactor fac, hipStream_t st);
 
-// Adjoint solve by replaying a recorded forward elimination (same result as
-// launch_solve_adjoint with or_status = true, without a second elimination).
-hipError_t launch_solve_adjoint_replay(int NP, int n, int S, int F, GJFactor fac,
-                                       const double *C_d, const double *omega_d,
-                                       const double2 *I_d, const double2 *rpart_d, int nchunk,
-                                       double rscale, double *gsys_d, int32_t *status_d,
-                                       hipStream_t st);
-
-// Adjoint solve: Z mu = rscale * sum_c (rr_c - j ri_c); writes the per-system
-// gradient term gsys[s][k] = 2 Re(mu_k I_k / (j w C_k^2)).  The system status
-// is OR-ed into status_d when or_status, else assigned.
+// Adjoint solve by a second pivoted Gauss-Jordan elimination of Z (used by the
+// vector-Jacobian product, which has no recorded factorisation):
+// Z mu = rscale * sum_c (rr_c - j ri_c); writes the per-system gradient term
+// gsys[s][k] = 2 Re(mu_k I_k / (j w C_k^2)).  The system status is OR-ed into
+// status_d when or_status, else assigned.
 hipError_t launch_solve_adjoint(int NP, int n, int S, int F, const double *M_d,
                                 const double *R_d, const double *C_d, const double *omega_d,
                                 const double2 *I_d, const double2 *rpart_d, int nchunk,
@@ -136,4 +155,5 @@ struct cosim_plan {
     // optional phase timing: (COSIM_PHASES + 1) events per recorded call
     std::vector<hipEvent_t> events;
     int timing_cap = 0, timing_used = 0;
+    bool ldl_ok = false;  // every R_k > 0: the LDL^T fast path applies
 };

@@ -97,10 +97,12 @@ __global__ __launch_bounds__(GJShape<NP>::BLOCK) void k_gj(
     const double *__restrict__ omega, const double2 *__restrict__ Iin,
     const double2 *__restrict__ rpart, int nchunk, double rscale, double2 *__restrict__ Iout,
     double *__restrict__ gsys, int32_t *__restrict__ status, bool or_status,
-    GJFactor fac) {
+    GJFactor fac, bool fallback_only) {
     constexpr int NT = GJShape<NP>::NT;
     constexpr int NTHR = GJShape<NP>::NTHR;
     const int s = blockIdx.x;
+    // fallback launch: only systems the LDL^T fast path handed over
+    if (fallback_only && fac.fmt[s] != kFmtNeedsPivot) return;  // uniform per block
     const int t = threadIdx.x;
     const bool act = t < NTHR;
     const int ti = t % NT, tj = t / NT;
@@ -405,75 +407,314 @@ __global__ __launch_bounds__(GJShape<NP>::BLOCK) void k_gj(
     if (t == 0) {
         if (or_status) status[s] |= sFlag;
         else status[s] = sFlag;
+        if (fac.L) fac.fmt[s] = kFmtGJ;
     }
 }
 
-// Replays the row operations recorded by a forward elimination on a new
-// right-hand side (the adjoint rhs), so the adjoint needs no second
-// elimination: b <- b - l_k b_{p_k} for k = 0..n-1, then mu_k = b_{p_k} / piv_k
-// (Z is complex symmetric, so the same transform solves Z^T mu = r).  One
-// wave per system, lane i holds b_i; step k reads the recorded multiplier
-// column l_k (one coalesced 16-byte load per lane) and broadcasts b_{p_k}
-// with readlane.  Writes gsys[s][k] = 2 Re(mu_k I_k / (j w C_k^2)).
+// Sum of a complex value over the 64 lanes of a wave (all lanes active):
+// DPP butterflies inside each row of 16, then the four row sums.
+template <int CTRL>
+__device__ inline double dpp_sum_step(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(__double2loint(v), __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(__double2hiint(v), __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return v + __hiloint2double(hi, lo);
+}
+__device__ inline double wave_sum(double v) {
+    v = dpp_sum_step<0xB1>(v);   // quad_perm [1,0,3,2]
+    v = dpp_sum_step<0x4E>(v);   // quad_perm [2,3,0,1]
+    v = dpp_sum_step<0x141>(v);  // row_half_mirror
+    v = dpp_sum_step<0x140>(v);  // row_mirror
+    return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
+}
+
+// Complex-symmetric LDL^T factorisation without pivoting, Z = L D L^T.
+// The Hermitian part of Z is diag(R) (j w M and 1/(j w C) are skew-Hermitian),
+// so with every R_k > 0 each Schur complement keeps a positive-definite real
+// part and no pivot can vanish; the elimination needs no row exchanges and
+// touches only the lower triangle.  Layout as k_gj (4x4 complex tile per
+// thread), lower tiles only.  Panels of 4 columns: the diagonal-tile thread
+// factors its 4x4 block in registers and publishes L11 and D11^-1 to its
+// column group (wave-local); the group forms V21 = A21 L11^-T and
+// L21 = V21 D11^-1; after one barrier every tile right of the panel applies
+// A22 -= L21 V21^T.  The factor is recorded (L by columns, D^-1) for the
+// replay kernel, which does the forward and the adjoint solves.  A system whose
+// smallest pivot is below 1e-5 of its largest impedance diagonal (or is not
+// finite) is marked for the pivoted Gauss-Jordan fallback.
 template <int NP>
-__global__ __launch_bounds__(256) void k_gj_apply(int n, int S, int F, GJFactor fac,
-                                                  const double *__restrict__ C,
-                                                  const double *__restrict__ omega,
-                                                  const double2 *__restrict__ Iin,
-                                                  const double2 *__restrict__ rpart, int nchunk,
-                                                  double rscale, double *__restrict__ gsys,
-                                                  int32_t *__restrict__ status) {
+__global__ __launch_bounds__(GJShape<NP>::BLOCK) void k_ldl(
+    int n, int S, int F, const double *__restrict__ M, const double *__restrict__ Rv,
+    const double *__restrict__ C, const double *__restrict__ omega, GJFactor fac,
+    int32_t *__restrict__ status) {
+    constexpr int NT = GJShape<NP>::NT;
+    constexpr int NTHR = GJShape<NP>::NTHR;
+    const int s = blockIdx.x;
+    const int t = threadIdx.x;
+    const int ti = t % NT, tj = t / NT;
+    const bool act = t < NTHR && ti >= tj;
+    const int b = s / F, f = s - b * F;
+
+    __shared__ double2 sLp[2][NP][4];  // L21 rows of the current panel
+    __shared__ double2 sVp[2][NP][4];  // V21 = L21 D11 rows
+    __shared__ double2 sDg[NT][10];    // per column group: L11 (6 entries) and D11^-1 (4)
+    __shared__ int sFlag;
+    __shared__ int sZmax;              // max |re|+|im| of diag(Z), float bits
+
+    if (t == 0) {
+        sFlag = 0;
+        sZmax = 0;
+    }
+    __syncthreads();
+
+    const double w = omega[f];
+    const double *Cb = C + (size_t)b * n;
+    double2 a[4][4];
+    if (act) {
+        int flag = 0;
+        float zmax = 0.0f;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = 4 * ti + r;
+            double dre = 0.0, dim = 0.0;
+            if (i < n) {
+                const double c = Cb[i];
+                if (tj == 0) {
+                    if (!isfinite(c) || c == 0.0 || !isfinite(w) || w == 0.0) flag |= COSIM_SYS_BAD_INPUT;
+                    else if (c < 0.0) flag |= COSIM_SYS_NEGATIVE_C;
+                }
+                dre = Rv[i];
+                dim = -1.0 / (w * c);
+            }
+#pragma unroll
+            for (int cc = 0; cc < 4; ++cc) {
+                const int j = 4 * tj + cc;
+                double2 z = make_double2(0.0, 0.0);
+                if (i < n && j < n) {
+                    z.y = w * M[(size_t)i * n + j];
+                    if (i == j) {
+                        z.x += dre;
+                        z.y += dim;
+                    }
+                } else if (i == j) {
+                    z.x = 1.0;
+                }
+                a[r][cc] = z;
+                if (i == j && i < n) zmax = fmaxf(zmax, (float)(fabs(z.x) + fabs(z.y)));
+            }
+        }
+        if (flag) atomicOr(&sFlag, flag);
+        if (ti == tj) atomicMax(&sZmax, __float_as_int(zmax));  // non-negative floats order as ints
+    }
+    double dmin = __builtin_inf();  // smallest |re|+|im| pivot (diagonal threads)
+
+    for (int kt = 0; 4 * kt < n; ++kt) {
+        const int buf = kt & 1;
+        const int nc = min(4, n - 4 * kt);
+        if (act && tj == kt) {
+            if (ti == kt) {
+                // LDL^T of the 4x4 diagonal block in place (lower triangle)
+                double2 dinv[4];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const double2 d = a[c][c];
+                    if (c < nc) dmin = fmin(dmin, fabs(d.x) + fabs(d.y));
+                    dinv[c] = cinv(d);
+                    double2 l[4];
+#pragma unroll
+                    for (int r = c + 1; r < 4; ++r) l[r] = cmul(a[r][c], dinv[c]);
+#pragma unroll
+                    for (int r = c + 1; r < 4; ++r)
+#pragma unroll
+                        for (int r2 = c + 1; r2 <= r; ++r2) a[r][r2] = cfms(a[r][r2], l[r], a[r2][c]);
+#pragma unroll
+                    for (int r = c + 1; r < 4; ++r) a[r][c] = l[r];
+                }
+                sDg[kt][0] = a[1][0];
+                sDg[kt][1] = a[2][0];
+                sDg[kt][2] = a[2][1];
+                sDg[kt][3] = a[3][0];
+                sDg[kt][4] = a[3][1];
+                sDg[kt][5] = a[3][2];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) sDg[kt][6 + c] = dinv[c];
+                // record: L11 below the diagonal, D^-1
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    double2 *col = fac.L + ((size_t)s * NP + 4 * kt + c) * NP + 4 * kt;
+#pragma unroll
+                    for (int r = c + 1; r < 4; ++r) col[r] = a[r][c];
+                    fac.piv_val[(size_t)s * NP + 4 * kt + c] = dinv[c];
+                }
+            }
+            // the diagonal thread and the rest of the column group share a wave
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            if (ti > kt) {
+                const double2 l10 = sDg[kt][0], l20 = sDg[kt][1], l21 = sDg[kt][2];
+                const double2 l30 = sDg[kt][3], l31 = sDg[kt][4], l32 = sDg[kt][5];
+                double2 dinv[4];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) dinv[c] = sDg[kt][6 + c];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    // V row = A21 row . L11^-T (forward substitution over the columns)
+                    double2 v0 = a[r][0];
+                    double2 v1 = cfms(a[r][1], v0, l10);
+                    double2 v2 = cfms(cfms(a[r][2], v0, l20), v1, l21);
+                    double2 v3 = cfms(cfms(cfms(a[r][3], v0, l30), v1, l31), v2, l32);
+                    const int i = 4 * ti + r;
+                    sVp[buf][i][0] = v0;
+                    sVp[buf][i][1] = v1;
+                    sVp[buf][i][2] = v2;
+                    sVp[buf][i][3] = v3;
+                    a[r][0] = cmul(v0, dinv[0]);
+                    a[r][1] = cmul(v1, dinv[1]);
+                    a[r][2] = cmul(v2, dinv[2]);
+                    a[r][3] = cmul(v3, dinv[3]);
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        sLp[buf][i][c] = a[r][c];
+                        fac.L[((size_t)s * NP + 4 * kt + c) * NP + i] = a[r][c];
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        if (act && tj > kt) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                double2 lr[4], vc[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) lr[r] = sLp[buf][4 * ti + r][c];
+#pragma unroll
+                for (int cc = 0; cc < 4; ++cc) vc[cc] = sVp[buf][4 * tj + cc][c];
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int cc = 0; cc < 4; ++cc) a[r][cc] = cfms(a[r][cc], lr[r], vc[cc]);
+            }
+        }
+    }
+    const float zmax = __int_as_float(sZmax);
+    if (act && ti == tj && !(dmin >= 1e-5 * (double)zmax)) atomicOr(&sFlag, kFlagPivot);
+    __syncthreads();
+    if (t == 0) {
+        const int fl = sFlag;
+        const bool pivot = (fl & (kFlagPivot | COSIM_SYS_BAD_INPUT)) != 0;
+        status[s] = fl & ~kFlagPivot;
+        fac.fmt[s] = pivot ? kFmtNeedsPivot : kFmtLDL;
+    }
+}
+
+// Solves with a recorded factorisation, one wave per system, lane i holds
+// component i.  Format kFmtLDL: y = L^-1 b by columns (readlane broadcast of
+// y_k, one coalesced column load), z = D^-1 y, then L^T x = z by
+// dot products (wave sums).  Format kFmtGJ: replays the recorded Gauss-Jordan
+// row operations b <- b - l_k b_{p_k}, then x_k = b_{p_k} / piv_k.
+// ADJ = false: b = -j w Phi, writes I (systems in the Gauss-Jordan format
+// already have I from the elimination and are skipped).
+// ADJ = true : b = rscale * sum_c (rr - j ri); writes
+//              gsys[s][k] = 2 Re(mu_k I_k / (j w C_k^2)).
+template <int NP, bool ADJ>
+__global__ __launch_bounds__(256) void k_replay(int n, int S, int F, GJFactor fac,
+                                                const double *__restrict__ phi,
+                                                const double *__restrict__ C,
+                                                const double *__restrict__ omega,
+                                                double2 *__restrict__ I,
+                                                const double2 *__restrict__ rpart, int nchunk,
+                                                double rscale, double *__restrict__ gsys,
+                                                int32_t *__restrict__ status) {
     const int lane = threadIdx.x & 63;
     const int s = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
     if (s >= S) return;  // whole wave; no block-level synchronisation below
+    const int fmt = __builtin_amdgcn_readfirstlane(fac.fmt[s]);
+    if (!ADJ && fmt == kFmtGJ) return;
     const int b = s / F, f = s - b * F;
     const double w = omega[f];
     double2 x = make_double2(0.0, 0.0);
     if (lane < n) {
-        double rr = 0.0, ri = 0.0;
-        for (int c = 0; c < nchunk; ++c) {
-            const double2 v = rpart[((size_t)c * S + s) * NP + lane];
-            rr += v.x;
-            ri += v.y;
+        if (!ADJ) {
+            x = make_double2(0.0, -w * phi[lane]);
+        } else {
+            double rr = 0.0, ri = 0.0;
+            for (int c = 0; c < nchunk; ++c) {
+                const double2 v = rpart[((size_t)c * S + s) * NP + lane];
+                rr += v.x;
+                ri += v.y;
+            }
+            x = make_double2(rscale * rr, -rscale * ri);
         }
-        x = make_double2(rscale * rr, -rscale * ri);
     }
     const double2 *__restrict__ Ls = fac.L + (size_t)s * NP * NP;
-    const int *__restrict__ Ps = fac.piv_row + (size_t)s * NP;
     constexpr int U = 8;
-    int k0 = 0;
-    for (; k0 + U <= n; k0 += U) {
-        double2 l[U];
+    if (fmt == kFmtLDL) {
+        // forward: y_i -= L_ik y_k for i > k
+        int k0 = 0;
+        for (; k0 + U <= n; k0 += U) {
+            double2 l[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-            l[u] = lane < NP ? Ls[(size_t)(k0 + u) * NP + lane] : make_double2(0.0, 0.0);
+            for (int u = 0; u < U; ++u)
+                l[u] = (lane > k0 + u && lane < n) ? Ls[(size_t)(k0 + u) * NP + lane] : make_double2(0.0, 0.0);
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int p = Ps[k0 + u];
-            const double2 bp = make_double2(readlane_d(x.x, p), readlane_d(x.y, p));
-            x = cfms(x, l[u], bp);
+            for (int u = 0; u < U; ++u) {
+                const double2 yk = make_double2(readlane_d(x.x, k0 + u), readlane_d(x.y, k0 + u));
+                x = cfms(x, l[u], yk);
+            }
         }
+        for (; k0 < n; ++k0) {
+            const double2 l = (lane > k0 && lane < n) ? Ls[(size_t)k0 * NP + lane] : make_double2(0.0, 0.0);
+            const double2 yk = make_double2(readlane_d(x.x, k0), readlane_d(x.y, k0));
+            x = cfms(x, l, yk);
+        }
+        if (lane < n) x = cmul(x, fac.piv_val[(size_t)s * NP + lane]);  // D^-1
+        // backward: x_k = z_k - sum_{i > k} L_ik x_i
+        for (int k = n - 1; k >= 0; --k) {
+            const double2 l = (lane > k && lane < n) ? Ls[(size_t)k * NP + lane] : make_double2(0.0, 0.0);
+            const double pr = l.x * x.x - l.y * x.y;
+            const double pi = l.x * x.y + l.y * x.x;
+            const double sr = wave_sum(pr), si = wave_sum(pi);
+            if (lane == k) x = make_double2(x.x - sr, x.y - si);
+        }
+    } else {
+        const int *__restrict__ Ps = fac.piv_row + (size_t)s * NP;
+        int k0 = 0;
+        for (; k0 + U <= n; k0 += U) {
+            double2 l[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                l[u] = lane < NP ? Ls[(size_t)(k0 + u) * NP + lane] : make_double2(0.0, 0.0);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int p = Ps[k0 + u];
+                const double2 bp = make_double2(readlane_d(x.x, p), readlane_d(x.y, p));
+                x = cfms(x, l[u], bp);
+            }
+        }
+        for (; k0 < n; ++k0) {
+            const double2 l = lane < NP ? Ls[(size_t)k0 * NP + lane] : make_double2(0.0, 0.0);
+            const int p = Ps[k0];
+            const double2 bp = make_double2(readlane_d(x.x, p), readlane_d(x.y, p));
+            x = cfms(x, l, bp);
+        }
+        const int pk = lane < n ? Ps[lane] : 0;
+        const double2 bpk = make_double2(__shfl(x.x, pk), __shfl(x.y, pk));
+        x = lane < n ? cmul(bpk, cinv(fac.piv_val[(size_t)s * NP + lane])) : make_double2(0.0, 0.0);
     }
-    for (; k0 < n; ++k0) {
-        const double2 l = lane < NP ? Ls[(size_t)k0 * NP + lane] : make_double2(0.0, 0.0);
-        const int p = Ps[k0];
-        const double2 bp = make_double2(readlane_d(x.x, p), readlane_d(x.y, p));
-        x = cfms(x, l, bp);
-    }
-    const int pk = lane < n ? Ps[lane] : 0;
-    const double2 bpk = make_double2(__shfl(x.x, pk), __shfl(x.y, pk));
     const int flag = status[s];
     const bool bad = (flag & (COSIM_SYS_BAD_INPUT | COSIM_SYS_SINGULAR)) != 0;
     bool nonfinite = false;
     if (lane < n) {
-        double2 mu = cmul(bpk, cinv(fac.piv_val[(size_t)s * NP + lane]));
-        if (bad) mu = make_double2(__builtin_nan(""), __builtin_nan(""));
-        const double2 Ik = Iin[(size_t)s * n + lane];
-        const double ck = C[(size_t)b * n + lane];
-        // 2 Re(mu I / (j w C^2)) = 2 Im(mu I) / (w C^2)
-        const double g = 2.0 * (mu.x * Ik.y + mu.y * Ik.x) / (w * ck * ck);
-        gsys[(size_t)s * n + lane] = g;
-        nonfinite = !bad && !isfinite(g);
+        if (bad) x = make_double2(__builtin_nan(""), __builtin_nan(""));
+        if (!ADJ) {
+            I[(size_t)s * n + lane] = x;
+            nonfinite = !bad && !(isfinite(x.x) && isfinite(x.y));
+        } else {
+            const double2 Ik = I[(size_t)s * n + lane];
+            const double ck = C[(size_t)b * n + lane];
+            // 2 Re(mu I / (j w C^2)) = 2 Im(mu I) / (w C^2)
+            const double g = 2.0 * (x.x * Ik.y + x.y * Ik.x) / (w * ck * ck);
+            gsys[(size_t)s * n + lane] = g;
+            nonfinite = !bad && !isfinite(g);
+        }
     }
     if (__ballot(nonfinite) != 0 && lane == 0) status[s] = flag | COSIM_SYS_NONFINITE;
 }
@@ -505,22 +746,22 @@ hipError_t launch_gj(int NP, int n, int S, int F, const double *M, const double 
                      const double *phi, const double *C, const double *omega, const double2 *Iin,
                      const double2 *rpart, int nchunk, double rscale, double2 *Iout,
                      double *gsys, int32_t *status, bool or_status, GJFactor fac,
-                     hipStream_t st) {
+                     bool fallback_only, hipStream_t st) {
     switch (NP) {
         case 16:
             hipLaunchKernelGGL((k_gj<16, ADJ>), dim3(S), dim3(GJShape<16>::BLOCK), 0, st, n, S,
                                F, M, R, phi, C, omega, Iin, rpart, nchunk, rscale, Iout, gsys,
-                               status, or_status, fac);
+                               status, or_status, fac, fallback_only);
             break;
         case 32:
             hipLaunchKernelGGL((k_gj<32, ADJ>), dim3(S), dim3(GJShape<32>::BLOCK), 0, st, n, S,
                                F, M, R, phi, C, omega, Iin, rpart, nchunk, rscale, Iout, gsys,
-                               status, or_status, fac);
+                               status, or_status, fac, fallback_only);
             break;
         case 64:
             hipLaunchKernelGGL((k_gj<64, ADJ>), dim3(S), dim3(GJShape<64>::BLOCK), 0, st, n, S,
                                F, M, R, phi, C, omega, Iin, rpart, nchunk, rscale, Iout, gsys,
-                               status, or_status, fac);
+                               status, or_status, fac, fallback_only);
             break;
         default:
             return hipErrorInvalidValue;
@@ -535,32 +776,77 @@ hipError_t launch_solve_forward(int NP, int n, int S, int F, const double *M_d,
                                 const double *omega_d, double2 *I_d, int32_t *status_d,
                                 GJFactor fac, hipStream_t st) {
     return launch_gj<false>(NP, n, S, F, M_d, R_d, phi_d, C_d, omega_d, nullptr, nullptr, 0, 0.0,
-                            I_d, nullptr, status_d, false, fac, st);
+                            I_d, nullptr, status_d, false, fac, false, st);
 }
 
-hipError_t launch_solve_adjoint_replay(int NP, int n, int S, int F, GJFactor fac,
-                                       const double *C_d, const double *omega_d,
-                                       const double2 *I_d, const double2 *rpart_d, int nchunk,
-                                       double rscale, double *gsys_d, int32_t *status_d,
-                                       hipStream_t st) {
-    const dim3 grid((S + 3) / 4);
+hipError_t launch_ldl(int NP, int n, int S, int F, const double *M_d, const double *R_d,
+                      const double *C_d, const double *omega_d, GJFactor fac, int32_t *status_d,
+                      hipStream_t st) {
     switch (NP) {
         case 16:
-            hipLaunchKernelGGL(k_gj_apply<16>, grid, dim3(256), 0, st, n, S, F, fac, C_d, omega_d,
-                               I_d, rpart_d, nchunk, rscale, gsys_d, status_d);
+            hipLaunchKernelGGL(k_ldl<16>, dim3(S), dim3(GJShape<16>::BLOCK), 0, st, n, S, F, M_d,
+                               R_d, C_d, omega_d, fac, status_d);
             break;
         case 32:
-            hipLaunchKernelGGL(k_gj_apply<32>, grid, dim3(256), 0, st, n, S, F, fac, C_d, omega_d,
-                               I_d, rpart_d, nchunk, rscale, gsys_d, status_d);
+            hipLaunchKernelGGL(k_ldl<32>, dim3(S), dim3(GJShape<32>::BLOCK), 0, st, n, S, F, M_d,
+                               R_d, C_d, omega_d, fac, status_d);
             break;
         case 64:
-            hipLaunchKernelGGL(k_gj_apply<64>, grid, dim3(256), 0, st, n, S, F, fac, C_d, omega_d,
-                               I_d, rpart_d, nchunk, rscale, gsys_d, status_d);
+            hipLaunchKernelGGL(k_ldl<64>, dim3(S), dim3(GJShape<64>::BLOCK), 0, st, n, S, F, M_d,
+                               R_d, C_d, omega_d, fac, status_d);
             break;
         default:
             return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+hipError_t launch_solve_fallback(int NP, int n, int S, int F, const double *M_d,
+                                 const double *R_d, const double *phi_d, const double *C_d,
+                                 const double *omega_d, double2 *I_d, int32_t *status_d,
+                                 GJFactor fac, hipStream_t st) {
+    return launch_gj<false>(NP, n, S, F, M_d, R_d, phi_d, C_d, omega_d, nullptr, nullptr, 0, 0.0,
+                            I_d, nullptr, status_d, false, fac, true, st);
+}
+
+template <bool ADJ>
+hipError_t launch_replay_t(int NP, int n, int S, int F, GJFactor fac, const double *phi_d,
+                           const double *C_d, const double *omega_d, double2 *I_d,
+                           const double2 *rpart_d, int nchunk, double rscale, double *gsys_d,
+                           int32_t *status_d, hipStream_t st) {
+    const dim3 grid((S + 3) / 4);
+    switch (NP) {
+        case 16:
+            hipLaunchKernelGGL((k_replay<16, ADJ>), grid, dim3(256), 0, st, n, S, F, fac, phi_d,
+                               C_d, omega_d, I_d, rpart_d, nchunk, rscale, gsys_d, status_d);
+            break;
+        case 32:
+            hipLaunchKernelGGL((k_replay<32, ADJ>), grid, dim3(256), 0, st, n, S, F, fac, phi_d,
+                               C_d, omega_d, I_d, rpart_d, nchunk, rscale, gsys_d, status_d);
+            break;
+        case 64:
+            hipLaunchKernelGGL((k_replay<64, ADJ>), grid, dim3(256), 0, st, n, S, F, fac, phi_d,
+                               C_d, omega_d, I_d, rpart_d, nchunk, rscale, gsys_d, status_d);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_replay_forward(int NP, int n, int S, int F, GJFactor fac, const double *phi_d,
+                                 const double *omega_d, double2 *I_d, int32_t *status_d,
+                                 hipStream_t st) {
+    return launch_replay_t<false>(NP, n, S, F, fac, phi_d, nullptr, omega_d, I_d, nullptr, 0, 0.0,
+                                  nullptr, status_d, st);
+}
+
+hipError_t launch_replay_adjoint(int NP, int n, int S, int F, GJFactor fac, const double *C_d,
+                                 const double *omega_d, double2 *I_d, const double2 *rpart_d,
+                                 int nchunk, double rscale, double *gsys_d, int32_t *status_d,
+                                 hipStream_t st) {
+    return launch_replay_t<true>(NP, n, S, F, fac, nullptr, C_d, omega_d, I_d, rpart_d, nchunk,
+                                 rscale, gsys_d, status_d, st);
 }
 
 hipError_t launch_solve_adjoint(int NP, int n, int S, int F, const double *M_d,
@@ -569,7 +855,7 @@ hipError_t launch_solve_adjoint(int NP, int n, int S, int F, const double *M_d,
                                 double rscale, double *gsys_d, int32_t *status_d,
                                 bool or_status, hipStream_t st) {
     return launch_gj<true>(NP, n, S, F, M_d, R_d, nullptr, C_d, omega_d, I_d, rpart_d, nchunk,
-                           rscale, nullptr, gsys_d, status_d, or_status, GJFactor{}, st);
+                           rscale, nullptr, gsys_d, status_d, or_status, GJFactor{}, false, st);
 }
 
 hipError_t launch_reduce(int n, int B, int F, int nchunk, const double *gsys_d,

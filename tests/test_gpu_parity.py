@@ -309,3 +309,52 @@ def test_full_size_array8x8_sampled(dev):
         eg = _nrel(grad.cpu().numpy()[sample], gr, axis=1)
         _say(f"[full] precision {prec}: loss err {el.max():.2e} grad err {eg.max():.2e}")
         assert el.max() < TOL[prec] and eg.max() < TOL[prec]
+
+
+# ----------------------------------------------------------------- solver paths
+
+def _custom_case(dev, R, C_override=None, seed=21):
+    from paper_2503_18479_amd import Geometry, Plan
+    wl = W.small_array(3, 2, batch=3, grid=11, n_freq=2, seed=seed)
+    g = wl.geom
+    g.R[:] = R
+    if C_override is not None:
+        C_override(wl)
+    G = O.field_matrix(g.verts, g.seg_off, wl.pts)
+    M = O.inductance_matrix_fast(g.verts, g.seg_off, g.wire_a)
+    Phi = O.flux(g.verts, g.seg_off, wl.bext_z)
+    plan = Plan(Geometry.from_workload(g), torch.tensor(wl.pts, device=dev), wl.bext_z)
+    return wl, G, M, Phi, plan
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_loss_and_grad_without_resistance_uses_pivoting(dev, prec):
+    """R = 0: the unpivoted LDL^T path does not apply; results still match."""
+    wl, G, M, Phi, plan = _custom_case(dev, 0.0)
+    C = torch.tensor(wl.C, device=dev); om = torch.tensor(wl.omega, device=dev)
+    T = torch.tensor(wl.target, device=dev)
+    loss, grad, st = plan.loss_and_grad(C, om, T, precision=prec)
+    Lr = O.evaluate(G, M, wl.geom.R, Phi, wl.C, wl.omega, wl.target)[2]
+    gr = O.grad_adjoint(G, M, wl.geom.R, Phi, wl.C, wl.omega, wl.target)
+    assert int(st.abs().sum()) == 0
+    assert np.max(np.abs(loss.cpu().numpy() - Lr) / Lr) < TOL[prec]
+    assert _nrel(grad.cpu().numpy(), gr, axis=1).max() < TOL[prec]
+
+
+def test_loss_and_grad_small_pivot_falls_back(dev):
+    """Tiny R with one loop tuned to its own resonance gives a tiny LDL^T pivot;
+    that configuration is re-solved with pivoting, the others are not."""
+    def tune(wl):
+        g = wl.geom
+        Mloc = O.inductance_matrix_fast(g.verts, g.seg_off, g.wire_a)
+        w = wl.omega[0]
+        wl.C[0, 0] = 1.0 / (w * w * Mloc[0, 0])
+    wl, G, M, Phi, plan = _custom_case(dev, 1e-6, tune)
+    C = torch.tensor(wl.C, device=dev); om = torch.tensor(wl.omega, device=dev)
+    T = torch.tensor(wl.target, device=dev)
+    loss, grad, st = plan.loss_and_grad(C, om, T, precision=0)
+    Lr = O.evaluate(G, M, wl.geom.R, Phi, wl.C, wl.omega, wl.target)[2]
+    gr = O.grad_adjoint(G, M, wl.geom.R, Phi, wl.C, wl.omega, wl.target)
+    assert int(st.abs().sum()) == 0
+    assert np.max(np.abs(loss.cpu().numpy() - Lr) / Lr) < 1e-9
+    assert _nrel(grad.cpu().numpy(), gr, axis=1).max() < 1e-9
