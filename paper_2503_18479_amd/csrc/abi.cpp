@@ -258,6 +258,8 @@ int cosim_assemble(cosim_geom_t g, int P, const double *pts_d, double bext_z, vo
         hipMalloc((void **)&p->G32, gsz * sizeof(float)) != hipSuccess ||
         hipMalloc((void **)&p->Ghi, gsz * sizeof(uint16_t)) != hipSuccess ||
         hipMalloc((void **)&p->Glo, gsz * sizeof(uint16_t)) != hipSuccess ||
+        hipMalloc((void **)&p->GThi, gsz * sizeof(uint16_t)) != hipSuccess ||
+        hipMalloc((void **)&p->GTlo, gsz * sizeof(uint16_t)) != hipSuccess ||
         hipMalloc((void **)&p->M_d, n * n * sizeof(double)) != hipSuccess ||
         hipMalloc((void **)&p->phi_d, n * sizeof(double)) != hipSuccess ||
         hipMalloc((void **)&p->R_d, n * sizeof(double)) != hipSuccess ||
@@ -278,7 +280,7 @@ int cosim_assemble(cosim_geom_t g, int P, const double *pts_d, double bext_z, vo
     ASM_TRY(hipMemcpyAsync(p->R_d, g->R.data(), n * sizeof(double), hipMemcpyHostToDevice, st));
     ASM_TRY(hipMemcpyAsync(p->phi_d, p->phi_h.data(), n * sizeof(double), hipMemcpyHostToDevice, st));
     ASM_TRY(launch_assemble_G(g->n, p->NP, P, p->P_pad, seg_d, verts_d, pts_d, p->G64, p->G32,
-                              p->Ghi, p->Glo, st));
+                              p->Ghi, p->Glo, p->GThi, p->GTlo, st));
     ASM_TRY(launch_assemble_M(g->n, seg_d, verts_d, wa_d, make_gl_rule(), p->M_d, st));
     p->M_h.resize(n * n);
     ASM_TRY(hipMemcpyAsync(p->M_h.data(), p->M_d, n * n * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -297,6 +299,8 @@ int cosim_plan_destroy(cosim_plan_t p) {
     dfree(p->G32);
     dfree(p->Ghi);
     dfree(p->Glo);
+    dfree(p->GThi);
+    dfree(p->GTlo);
     dfree(p->M_d);
     dfree(p->phi_d);
     dfree(p->R_d);
@@ -449,6 +453,8 @@ int cosim_loss_and_grad(cosim_plan_t p, int B, int F, const double *C_d, const d
           : precision == COSIM_FP32 ? (const void *)p->G32
                                     : (const void *)p->Ghi;
     a.Glo = p->Glo;
+    a.GThi = p->GThi;
+    a.GTlo = p->GTlo;
     a.T = T_d;
     a.P = p->P;
     a.P_pad = p->P_pad;

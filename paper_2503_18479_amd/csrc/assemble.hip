@@ -49,7 +49,9 @@ __global__ __launch_bounds__(256) void k_assemble_G(int n, int NP, int P, int P_
                                                     double *__restrict__ G64,
                                                     float *__restrict__ G32,
                                                     uint16_t *__restrict__ Ghi,
-                                                    uint16_t *__restrict__ Glo) {
+                                                    uint16_t *__restrict__ Glo,
+                                                    uint16_t *__restrict__ GThi,
+                                                    uint16_t *__restrict__ GTlo) {
     __shared__ double tile[kGPts][kMaxLoops + 1];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -100,6 +102,17 @@ __global__ __launch_bounds__(256) void k_assemble_G(int n, int NP, int P, int P_
         const uint16_t hi = bf16_rne(g32);
         Ghi[o] = hi;
         Glo[o] = bf16_rne(g32 - bf16_to_f(hi));
+    }
+    // transposed bf16 copies [NP][P_pad]: each loop's column is contiguous in p
+    for (int e = threadIdx.x; e < kGPts * NP; e += 256) {
+        const int k = e / kGPts, r = e - k * kGPts;
+        const int pr = prow0 + r;
+        if (pr >= P_pad) continue;
+        const float g32 = (float)tile[r][k];
+        const uint16_t hi = bf16_rne(g32);
+        const size_t o = (size_t)k * P_pad + pr;
+        GThi[o] = hi;
+        GTlo[o] = bf16_rne(g32 - bf16_to_f(hi));
     }
 }
 
@@ -235,10 +248,11 @@ __global__ __launch_bounds__(256) void k_assemble_M(int n, const int32_t *__rest
 
 hipError_t launch_assemble_G(int n, int NP, int P, int P_pad, const int32_t *seg_off_d,
                              const double *verts_d, const double *pts_d, double *G64,
-                             float *G32, uint16_t *Ghi, uint16_t *Glo, hipStream_t st) {
+                             float *G32, uint16_t *Ghi, uint16_t *Glo, uint16_t *GThi,
+                             uint16_t *GTlo, hipStream_t st) {
     const int blocks = (P_pad + kGPts - 1) / kGPts;
     hipLaunchKernelGGL(k_assemble_G, dim3(blocks), dim3(256), 0, st, n, NP, P, P_pad, seg_off_d,
-                       verts_d, pts_d, G64, G32, Ghi, Glo);
+                       verts_d, pts_d, G64, G32, Ghi, Glo, GThi, GTlo);
     return hipGetLastError();
 }
 

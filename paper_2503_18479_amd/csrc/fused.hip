@@ -33,7 +33,6 @@ namespace {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef short s16x8 __attribute__((ext_vector_type(8)));
 
 template <typename T>
 struct Mma;
@@ -65,9 +64,30 @@ __device__ inline T tcast(double x) {
 
 // Per-element loss epilogue.  MAG: e = |B| - T, w = e B/|B| (0 where B = 0).
 // COMPLEX: e = B - T, w = e.  Returns e^2 (|e|^2) and overwrites (x, y) by w.
+// FP32 form: with s = 1/sqrt(|B|^2) (hardware rsq, ~1 ulp), |B| = |B|^2 s and
+// e/|B| = 1 - T s, which needs neither a square root nor a division.
+template <int LOSS>
+__device__ inline float epilogue_f(float &x, float &y, float t) {
+    if (LOSS == COSIM_LOSS_MAG) {
+        const float m2 = fmaf(x, x, y * y);
+        const float rs = __builtin_amdgcn_rsqf(m2);
+        const float e = fmaf(m2, rs, -t);
+        const float c = m2 > 0.0f ? fmaf(-t, rs, 1.0f) : 0.0f;
+        x *= c;
+        y *= c;
+        return m2 > 0.0f ? e * e : t * t;
+    } else {
+        const float ex = x - t;
+        x = ex;
+        return fmaf(ex, ex, y * y);
+    }
+}
+
 template <int LOSS, typename T>
 __device__ inline double epilogue(T &x, T &y, T t) {
-    if (LOSS == COSIM_LOSS_MAG) {
+    if constexpr (sizeof(T) == 4) {
+        return (double)epilogue_f<LOSS>(x, y, t);
+    } else if (LOSS == COSIM_LOSS_MAG) {
         const T mag = sqrt(x * x + y * y);
         const T e = mag - t;
         const T c = mag > T(0) ? e / mag : T(0);
@@ -239,38 +259,36 @@ __global__ __launch_bounds__(256) void k_fused(FusedArgs a) {
 // ---------------------------------------------------------------------------
 // BF16X3
 // ---------------------------------------------------------------------------
-__device__ inline uint16_t bf16_bits(float x) {
-    uint32_t u = __float_as_uint(x);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
-__device__ inline float bf16_val(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
-
-__device__ inline f32x4 mma_bf16(s16x8 a, s16x8 b, f32x4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
-                                                  __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+__device__ inline f32x4 mma_bf16(bf16x8 a, bf16x8 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
-// Split a float into hi/lo bf16 bit patterns.
-__device__ inline void split_bf16(float x, short &hi, short &lo) {
-    const uint16_t h = bf16_bits(x);
-    hi = (short)h;
-    lo = (short)bf16_bits(x - bf16_val(h));
+// hi = RNE_bf16(x), lo = RNE_bf16(x - hi) (v_cvt_pk_bf16_f32 on gfx950)
+__device__ inline void split2(float x, __bf16 &hi, __bf16 &lo) {
+    hi = (__bf16)x;
+    lo = (__bf16)(x - (float)hi);
 }
 
-// Sub-tiles of 32 rows: the forward product of a 16-row block uses K = 32
-// (loop index, 8 per lane), the adjoint uses K = 32 rows of P taken from two
-// forward accumulators: lane (r16, q) supplies rows {4q..4q+3} of the first
-// 16-row block and {16+4q..16+4q+3} of the second, i.e. the contraction order
-// pi(8q + j) = (j < 4 ? 4q + j : 16 + 4q + j - 4).
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+
+// Sub-tiles of 32 rows.  Forward: the 16-row halves of a sub-tile use K = 32
+// (loop index; lane (r16, q) holds k = 8q..8q+7 of each 32-wide k-step).
+// Adjoint: K = the sub-tile's 32 rows, taken from the two forward
+// accumulators: lane (r16, q) supplies rows {4q..4q+3} of the first half and
+// {16+4q..16+4q+3} of the second, i.e. pi(8q + j) = (j < 4 ? 4q + j :
+// 16 + 4q + j - 4).  The adjoint A operand G^T[i][pi(8q + j)] is two 8-byte
+// reads of the transposed tile held in LDS next to the row-major one.
 template <int NP, int NB, int LOSS, bool GRAD>
-__global__ __launch_bounds__(256) void k_fused_bf16x3(FusedArgs a) {
+__global__ __launch_bounds__(256, 2) void k_fused_bf16x3(FusedArgs a) {
     constexpr int KS = NP / 32;  // forward k-steps of 32
     constexpr int IB = NP / 16;
     constexpr int PT = kPTile;
-    constexpr int LDR = NP + 8;  // padded LDS row in bf16 elements (16-byte aligned)
+    constexpr int LDR = NP + 8;  // row-major tile: padded row (bf16 elements)
+    constexpr int LDT = PT + 8;  // transposed tile: padded row
     __shared__ __attribute__((aligned(16))) uint16_t sH[PT * LDR];
     __shared__ __attribute__((aligned(16))) uint16_t sL[PT * LDR];
+    __shared__ __attribute__((aligned(16))) uint16_t tH[GRAD ? NP * LDT : 8];
+    __shared__ __attribute__((aligned(16))) uint16_t tL[GRAD ? NP * LDT : 8];
     __shared__ float sT[PT];
     static_assert(NP % 32 == 0, "bf16x3 path needs NP multiple of 32");
 
@@ -284,7 +302,7 @@ __global__ __launch_bounds__(256) void k_fused_bf16x3(FusedArgs a) {
     const int pe = min(a.P_pad, pb + a.rows_per_chunk);
 
     // forward B operand for k-step kk: I[sys][32 kk + 8 q + j], j = 0..7
-    s16x8 Ih[NB][2][KS], Il[NB][2][KS];  // [b][re/im][kk]
+    bf16x8 Ih[NB][2][KS], Il[NB][2][KS];  // [b][re/im][kk]
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         const int s = sys0 + 16 * b + r16;
@@ -295,11 +313,11 @@ __global__ __launch_bounds__(256) void k_fused_bf16x3(FusedArgs a) {
                 const int k = 32 * kk + 8 * q + j;
                 double2 v = make_double2(0.0, 0.0);
                 if (s < a.S && k < a.n) v = a.I[(size_t)s * a.n + k];
-                short h, l;
-                split_bf16((float)v.x, h, l);
+                __bf16 h, l;
+                split2((float)v.x, h, l);
                 Ih[b][0][kk][j] = h;
                 Il[b][0][kk][j] = l;
-                split_bf16((float)v.y, h, l);
+                split2((float)v.y, h, l);
                 Ih[b][1][kk][j] = h;
                 Il[b][1][kk][j] = l;
             }
@@ -326,6 +344,15 @@ __global__ __launch_bounds__(256) void k_fused_bf16x3(FusedArgs a) {
             *(uint4 *)(sH + row * LDR + col) = *(const uint4 *)(Gh + go);
             *(uint4 *)(sL + row * LDR + col) = *(const uint4 *)(Gl + go);
         }
+        if (GRAD) {
+            for (int v = threadIdx.x; v < NV; v += 256) {
+                const int e0 = v * 8;
+                const int row = e0 / PT, col = e0 - row * PT;  // row = loop index i
+                const size_t go = (size_t)row * a.P_pad + p0 + col;
+                *(uint4 *)(tH + row * LDT + col) = *(const uint4 *)(a.GThi + go);
+                *(uint4 *)(tL + row * LDT + col) = *(const uint4 *)(a.GTlo + go);
+            }
+        }
         if (threadIdx.x < PT) {
             const int p = p0 + threadIdx.x;
             sT[threadIdx.x] = p < a.P ? (float)a.T[p] : 0.0f;
@@ -337,11 +364,11 @@ __global__ __launch_bounds__(256) void k_fused_bf16x3(FusedArgs a) {
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 const int row = 32 * sp + 16 * h + r16;
-                s16x8 ah[KS], al[KS];
+                bf16x8 ah[KS], al[KS];
 #pragma unroll
                 for (int kk = 0; kk < KS; ++kk) {
-                    ah[kk] = *(const s16x8 *)(sH + row * LDR + 32 * kk + 8 * q);
-                    al[kk] = *(const s16x8 *)(sL + row * LDR + 32 * kk + 8 * q);
+                    ah[kk] = *(const bf16x8 *)(sH + row * LDR + 32 * kk + 8 * q);
+                    al[kk] = *(const bf16x8 *)(sL + row * LDR + 32 * kk + 8 * q);
                 }
 #pragma unroll
                 for (int b = 0; b < NB; ++b) {
@@ -359,8 +386,11 @@ __global__ __launch_bounds__(256) void k_fused_bf16x3(FusedArgs a) {
                     bi[h][b] = xi;
                 }
             }
-            // epilogue on both halves, then pack w into bf16 hi/lo operands
-            s16x8 wrh[NB], wrl[NB], wih[NB], wil[NB];
+            // epilogue on both halves, then w as bf16 hi/lo operands
+            bf16x8 wrh[NB], wrl[NB], wih[NB], wil[NB];
+            float lsub[NB];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) lsub[b] = 0.0f;
 #pragma unroll
             for (int h = 0; h < 2; ++h)
 #pragma unroll
@@ -369,27 +399,27 @@ __global__ __launch_bounds__(256) void k_fused_bf16x3(FusedArgs a) {
 #pragma unroll
                     for (int b = 0; b < NB; ++b) {
                         float x = br[h][b][m], y = bi[h][b][m];
-                        lacc[b] += epilogue<LOSS>(x, y, t);
-                        short hh, ll;
-                        split_bf16(x, hh, ll);
+                        lsub[b] += epilogue_f<LOSS>(x, y, t);
+                        __bf16 hh, ll;
+                        split2(x, hh, ll);
                         wrh[b][4 * h + m] = hh;
                         wrl[b][4 * h + m] = ll;
-                        split_bf16(y, hh, ll);
+                        split2(y, hh, ll);
                         wih[b][4 * h + m] = hh;
                         wil[b][4 * h + m] = ll;
                     }
                 }
+#pragma unroll
+            for (int b = 0; b < NB; ++b) lacc[b] += (double)lsub[b];
             if (GRAD) {
 #pragma unroll
                 for (int ib = 0; ib < IB; ++ib) {
                     // A operand: Gt[i = 16 ib + r16][p = pi(8q + j)]
-                    s16x8 th, tl;
-#pragma unroll
-                    for (int j = 0; j < 8; ++j) {
-                        const int pr = 32 * sp + (j < 4 ? 4 * q + j : 16 + 4 * q + (j - 4));
-                        th[j] = (short)sH[pr * LDR + 16 * ib + r16];
-                        tl[j] = (short)sL[pr * LDR + 16 * ib + r16];
-                    }
+                    const int base = (16 * ib + r16) * LDT + 32 * sp + 4 * q;
+                    const s16x4 h0 = *(const s16x4 *)(tH + base), h1 = *(const s16x4 *)(tH + base + 16);
+                    const s16x4 l0 = *(const s16x4 *)(tL + base), l1 = *(const s16x4 *)(tL + base + 16);
+                    const bf16x8 th = __builtin_bit_cast(bf16x8, __builtin_shufflevector(h0, h1, 0, 1, 2, 3, 4, 5, 6, 7));
+                    const bf16x8 tl = __builtin_bit_cast(bf16x8, __builtin_shufflevector(l0, l1, 0, 1, 2, 3, 4, 5, 6, 7));
 #pragma unroll
                     for (int b = 0; b < NB; ++b) {
                         racc[ib][b][0] = mma_bf16(tl, wrh[b], racc[ib][b][0]);

@@ -38,7 +38,8 @@ constexpr int kPTile = 64;         // rows of G per LDS tile in the fused kernel
 // ---------------------------------------------------------------------------
 hipError_t launch_assemble_G(int n, int NP, int P, int P_pad, const int32_t *seg_off_d,
                              const double *verts_d, const double *pts_d, double *G64,
-                             float *G32, uint16_t *Ghi, uint16_t *Glo, hipStream_t st);
+                             float *G32, uint16_t *Ghi, uint16_t *Glo, uint16_t *GThi,
+                             uint16_t *GTlo, hipStream_t st);
 
 hipError_t launch_assemble_M(int n, const int32_t *seg_off_d, const double *verts_d,
                              const double *wire_a_d, const GLRule &gl, double *M_d,
@@ -104,6 +105,7 @@ hipError_t launch_reduce(int n, int B, int F, int nchunk, const double *gsys_d,
 struct FusedArgs {
     const void *G;        // [P_pad][NP] in the precision's storage type
     const void *Glo;      // bf16 lo part (BF16X3 only)
+    const uint16_t *GThi, *GTlo;  // [NP][P_pad] transposed bf16 hi/lo (BF16X3 only)
     const double *T;      // [P] target
     int P, P_pad, rows_per_chunk, nchunk;
     const double2 *I;     // [S][n]
@@ -143,6 +145,7 @@ struct cosim_plan {
     double *G64 = nullptr;
     float *G32 = nullptr;
     uint16_t *Ghi = nullptr, *Glo = nullptr;
+    uint16_t *GThi = nullptr, *GTlo = nullptr;  // transposed copies [NP][P_pad]
     double *M_d = nullptr, *phi_d = nullptr, *R_d = nullptr;
     // workspace (device)
     size_t cap_systems = 0;
