@@ -431,176 +431,182 @@ __device__ inline double wave_sum(double v) {
 // The Hermitian part of Z is diag(R) (j w M and 1/(j w C) are skew-Hermitian),
 // so with every R_k > 0 each Schur complement keeps a positive-definite real
 // part and no pivot can vanish; the elimination needs no row exchanges and
-// touches only the lower triangle.  Layout as k_gj (4x4 complex tile per
-// thread), lower tiles only.  Panels of 4 columns: the diagonal-tile thread
-// factors its 4x4 block in registers and publishes L11 and D11^-1 to its
-// column group (wave-local); the group forms V21 = A21 L11^-T and
-// L21 = V21 D11^-1; after one barrier every tile right of the panel applies
-// A22 -= L21 V21^T.  The factor is recorded (L by columns, D^-1) for the
-// replay kernel, which does the forward and the adjoint solves.  A system whose
-// smallest pivot is below 1e-5 of its largest impedance diagonal (or is not
-// finite) is marked for the pivoted Gauss-Jordan fallback.
+// touches only the lower triangle.
+//
+// One wave per system.  The lower triangle is held as NB(NB+1)/2 blocks of
+// 16x16 (NB = NP/16), each as two FP64 matrix-core accumulators (real and
+// imaginary part; lane l holds column l%16, rows g+4m, g = l/16, m = 0..3).
+// Panels of 4 columns:
+//   1. the lanes holding the panel's columns copy them to LDS;
+//   2. every lane factors the 4x4 diagonal block (L11, D11) redundantly;
+//   3. lane r forms row r of V21 = A21 L11^-T and L21 = V21 D11^-1;
+//   4. every lower block right of the panel takes the rank-4 update
+//      A -= L21 V21^T as four 16x16x4 FP64 MFMAs (complex = 4 real products).
+// Columns left of the trailing part also receive updates; they are finished
+// and never read again.  The factor is recorded (L by columns, D^-1) for the
+// replay kernel.  A system whose smallest pivot is below 1e-5 of its largest
+// impedance diagonal (or is not finite) is marked for the pivoted fallback.
 template <int NP>
-__global__ __launch_bounds__(GJShape<NP>::BLOCK) void k_ldl(
-    int n, int S, int F, const double *__restrict__ M, const double *__restrict__ Rv,
-    const double *__restrict__ C, const double *__restrict__ omega, GJFactor fac,
-    int32_t *__restrict__ status) {
-    constexpr int NT = GJShape<NP>::NT;
-    constexpr int NTHR = GJShape<NP>::NTHR;
-    const int s = blockIdx.x;
-    const int t = threadIdx.x;
-    const int ti = t % NT, tj = t / NT;
-    const bool act = t < NTHR && ti >= tj;
+__global__ __launch_bounds__(256) void k_ldl(int n, int S, int F, const double *__restrict__ M,
+                                             const double *__restrict__ Rv,
+                                             const double *__restrict__ C,
+                                             const double *__restrict__ omega, GJFactor fac,
+                                             int32_t *__restrict__ status) {
+    constexpr int NB = NP / 16;
+    constexpr int NBLK = NB * (NB + 1) / 2;
+    typedef double f64x4 __attribute__((ext_vector_type(4)));
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __shared__ double2 sPan[4][NP][4];  // per wave: panel rows (A, then L21)
+    __shared__ double2 sV[4][NP][4];    // per wave: V21 rows
+    const int s = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + wv));
+    if (s >= S) return;  // whole wave; the block never synchronises
     const int b = s / F, f = s - b * F;
-
-    __shared__ double2 sLp[2][NP][4];  // L21 rows of the current panel
-    __shared__ double2 sVp[2][NP][4];  // V21 = L21 D11 rows
-    __shared__ double2 sDg[NT][10];    // per column group: L11 (6 entries) and D11^-1 (4)
-    __shared__ int sFlag;
-    __shared__ int sZmax;              // max |re|+|im| of diag(Z), float bits
-
-    if (t == 0) {
-        sFlag = 0;
-        sZmax = 0;
-    }
-    __syncthreads();
-
     const double w = omega[f];
     const double *Cb = C + (size_t)b * n;
-    double2 a[4][4];
-    if (act) {
-        int flag = 0;
-        float zmax = 0.0f;
+    const int g = lane >> 4, c16 = lane & 15;
+
+    // ---- Z in accumulator layout: block (bi, bj) at index bi (bi + 1) / 2 + bj
+    f64x4 Xr[NBLK], Xi[NBLK];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int i = 4 * ti + r;
-            double dre = 0.0, dim = 0.0;
-            if (i < n) {
-                const double c = Cb[i];
-                if (tj == 0) {
-                    if (!isfinite(c) || c == 0.0 || !isfinite(w) || w == 0.0) flag |= COSIM_SYS_BAD_INPUT;
-                    else if (c < 0.0) flag |= COSIM_SYS_NEGATIVE_C;
-                }
-                dre = Rv[i];
-                dim = -1.0 / (w * c);
-            }
+    for (int bi = 0; bi < NB; ++bi)
 #pragma unroll
-            for (int cc = 0; cc < 4; ++cc) {
-                const int j = 4 * tj + cc;
-                double2 z = make_double2(0.0, 0.0);
+        for (int bj = 0; bj <= bi; ++bj) {
+            const int bx = bi * (bi + 1) / 2 + bj;
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const int i = 16 * bi + g + 4 * m, j = 16 * bj + c16;
+                double zr = 0.0, zi = 0.0;
                 if (i < n && j < n) {
-                    z.y = w * M[(size_t)i * n + j];
+                    zi = w * M[(size_t)i * n + j];
                     if (i == j) {
-                        z.x += dre;
-                        z.y += dim;
+                        zr = Rv[i];
+                        zi -= 1.0 / (w * Cb[i]);
                     }
                 } else if (i == j) {
-                    z.x = 1.0;
+                    zr = 1.0;
                 }
-                a[r][cc] = z;
-                if (i == j && i < n) zmax = fmaxf(zmax, (float)(fabs(z.x) + fabs(z.y)));
+                Xr[bx][m] = zr;
+                Xi[bx][m] = zi;
             }
         }
-        if (flag) atomicOr(&sFlag, flag);
-        if (ti == tj) atomicMax(&sZmax, __float_as_int(zmax));  // non-negative floats order as ints
+    // input flags and the largest |re|+|im| diagonal entry (lane k handles k)
+    int flag = 0;
+    float zdiag = 0.0f;
+    if (lane < n) {
+        const double c = Cb[lane];
+        if (!isfinite(c) || c == 0.0 || !isfinite(w) || w == 0.0) flag = COSIM_SYS_BAD_INPUT;
+        else if (c < 0.0) flag = COSIM_SYS_NEGATIVE_C;
+        zdiag = (float)(fabs(Rv[lane]) + fabs(w * M[(size_t)lane * n + lane] - 1.0 / (w * c)));
     }
-    double dmin = __builtin_inf();  // smallest |re|+|im| pivot (diagonal threads)
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        flag |= __shfl_xor(flag, off);
+        zdiag = fmaxf(zdiag, __shfl_xor(zdiag, off));
+    }
+    double dmin = __builtin_inf();
 
-    for (int kt = 0; 4 * kt < n; ++kt) {
-        const int buf = kt & 1;
-        const int nc = min(4, n - 4 * kt);
-        if (act && tj == kt) {
-            if (ti == kt) {
-                // LDL^T of the 4x4 diagonal block in place (lower triangle)
-                double2 dinv[4];
+    double2 (*pan)[4] = sPan[wv];
+    double2 (*vv)[4] = sV[wv];
 #pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    const double2 d = a[c][c];
-                    if (c < nc) dmin = fmin(dmin, fabs(d.x) + fabs(d.y));
-                    dinv[c] = cinv(d);
-                    double2 l[4];
+    for (int bc = 0; bc < NB; ++bc) {
+        for (int pp = 0; pp < 4; ++pp) {
+            const int k0 = 16 * bc + 4 * pp;  // first column of the panel
+            if (k0 >= n) break;               // uniform
+            const int nc = min(4, n - k0);
+            // 1. panel columns -> LDS (rows >= k0 matter)
+            if (c16 >= 4 * pp && c16 < 4 * pp + 4) {
+                const int c = c16 - 4 * pp;
 #pragma unroll
-                    for (int r = c + 1; r < 4; ++r) l[r] = cmul(a[r][c], dinv[c]);
+                for (int bi = bc; bi < NB; ++bi) {
+                    const int bx = bi * (bi + 1) / 2 + bc;
 #pragma unroll
-                    for (int r = c + 1; r < 4; ++r)
-#pragma unroll
-                        for (int r2 = c + 1; r2 <= r; ++r2) a[r][r2] = cfms(a[r][r2], l[r], a[r2][c]);
-#pragma unroll
-                    for (int r = c + 1; r < 4; ++r) a[r][c] = l[r];
-                }
-                sDg[kt][0] = a[1][0];
-                sDg[kt][1] = a[2][0];
-                sDg[kt][2] = a[2][1];
-                sDg[kt][3] = a[3][0];
-                sDg[kt][4] = a[3][1];
-                sDg[kt][5] = a[3][2];
-#pragma unroll
-                for (int c = 0; c < 4; ++c) sDg[kt][6 + c] = dinv[c];
-                // record: L11 below the diagonal, D^-1
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    double2 *col = fac.L + ((size_t)s * NP + 4 * kt + c) * NP + 4 * kt;
-#pragma unroll
-                    for (int r = c + 1; r < 4; ++r) col[r] = a[r][c];
-                    fac.piv_val[(size_t)s * NP + 4 * kt + c] = dinv[c];
+                    for (int m = 0; m < 4; ++m) pan[16 * bi + g + 4 * m][c] = make_double2(Xr[bx][m], Xi[bx][m]);
                 }
             }
-            // the diagonal thread and the rest of the column group share a wave
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
-            if (ti > kt) {
-                const double2 l10 = sDg[kt][0], l20 = sDg[kt][1], l21 = sDg[kt][2];
-                const double2 l30 = sDg[kt][3], l31 = sDg[kt][4], l32 = sDg[kt][5];
-                double2 dinv[4];
+            // 2. LDL^T of the 4x4 diagonal block, redundantly in every lane
+            double2 d4[4][4];
 #pragma unroll
-                for (int c = 0; c < 4; ++c) dinv[c] = sDg[kt][6 + c];
+            for (int r = 0; r < 4; ++r)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    // V row = A21 row . L11^-T (forward substitution over the columns)
-                    double2 v0 = a[r][0];
-                    double2 v1 = cfms(a[r][1], v0, l10);
-                    double2 v2 = cfms(cfms(a[r][2], v0, l20), v1, l21);
-                    double2 v3 = cfms(cfms(cfms(a[r][3], v0, l30), v1, l31), v2, l32);
-                    const int i = 4 * ti + r;
-                    sVp[buf][i][0] = v0;
-                    sVp[buf][i][1] = v1;
-                    sVp[buf][i][2] = v2;
-                    sVp[buf][i][3] = v3;
-                    a[r][0] = cmul(v0, dinv[0]);
-                    a[r][1] = cmul(v1, dinv[1]);
-                    a[r][2] = cmul(v2, dinv[2]);
-                    a[r][3] = cmul(v3, dinv[3]);
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) {
-                        sLp[buf][i][c] = a[r][c];
-                        fac.L[((size_t)s * NP + 4 * kt + c) * NP + i] = a[r][c];
-                    }
-                }
-            }
-        }
-        __syncthreads();
-        if (act && tj > kt) {
+                for (int c = 0; c <= r; ++c) d4[r][c] = pan[k0 + r][c];
+            double2 dinv[4];
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-                double2 lr[4], vc[4];
+                const double2 d = d4[c][c];
+                if (c < nc) dmin = fmin(dmin, fabs(d.x) + fabs(d.y));
+                dinv[c] = cinv(d);
+                double2 l[4];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) lr[r] = sLp[buf][4 * ti + r][c];
+                for (int r = c + 1; r < 4; ++r) l[r] = cmul(d4[r][c], dinv[c]);
 #pragma unroll
-                for (int cc = 0; cc < 4; ++cc) vc[cc] = sVp[buf][4 * tj + cc][c];
+                for (int r = c + 1; r < 4; ++r)
 #pragma unroll
-                for (int r = 0; r < 4; ++r)
+                    for (int r2 = c + 1; r2 <= r; ++r2) d4[r][r2] = cfms(d4[r][r2], l[r], d4[r2][c]);
 #pragma unroll
-                    for (int cc = 0; cc < 4; ++cc) a[r][cc] = cfms(a[r][cc], lr[r], vc[cc]);
+                for (int r = c + 1; r < 4; ++r) d4[r][c] = l[r];
             }
+            if (lane == 0) {
+                // record D^-1 of the panel and the L11 entries below the diagonal
+                double2 *col = fac.L + ((size_t)s * NP + k0) * NP + k0;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    fac.piv_val[(size_t)s * NP + k0 + c] = dinv[c];
+#pragma unroll
+                    for (int r = c + 1; r < 4; ++r) col[(size_t)c * NP + r] = d4[r][c];
+                }
+            }
+            // 3. row lane of V21 and L21 (rows below the diagonal block)
+            const int r = lane;
+            double2 lrow[4] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0),
+                               make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
+            double2 vrow[4] = {lrow[0], lrow[1], lrow[2], lrow[3]};
+            if (r >= k0 + 4 && r < NP) {
+                const double2 a0 = pan[r][0], a1 = pan[r][1], a2 = pan[r][2], a3 = pan[r][3];
+                vrow[0] = a0;
+                vrow[1] = cfms(a1, vrow[0], d4[1][0]);
+                vrow[2] = cfms(cfms(a2, vrow[0], d4[2][0]), vrow[1], d4[2][1]);
+                vrow[3] = cfms(cfms(cfms(a3, vrow[0], d4[3][0]), vrow[1], d4[3][1]), vrow[2], d4[3][2]);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    lrow[c] = cmul(vrow[c], dinv[c]);
+                    fac.L[((size_t)s * NP + k0 + c) * NP + r] = lrow[c];
+                }
+            }
+            if (r < NP) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    pan[r][c] = lrow[c];
+                    vv[r][c] = vrow[c];
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            // 4. rank-4 update of every lower block right of the panel
+            double2 La[NB], Vb[NB];
+#pragma unroll
+            for (int bi = bc; bi < NB; ++bi) {
+                La[bi] = pan[16 * bi + c16][g];  // A operand: row c16 of block bi, k = g
+                Vb[bi] = vv[16 * bi + c16][g];   // B operand: column c16 of block bi, k = g
+            }
+#pragma unroll
+            for (int bi = bc; bi < NB; ++bi)
+#pragma unroll
+                for (int bj = bc; bj <= bi; ++bj) {
+                    const int bx = bi * (bi + 1) / 2 + bj;
+                    Xr[bx] = __builtin_amdgcn_mfma_f64_16x16x4f64(-La[bi].x, Vb[bj].x, Xr[bx], 0, 0, 0);
+                    Xr[bx] = __builtin_amdgcn_mfma_f64_16x16x4f64(La[bi].y, Vb[bj].y, Xr[bx], 0, 0, 0);
+                    Xi[bx] = __builtin_amdgcn_mfma_f64_16x16x4f64(-La[bi].x, Vb[bj].y, Xi[bx], 0, 0, 0);
+                    Xi[bx] = __builtin_amdgcn_mfma_f64_16x16x4f64(-La[bi].y, Vb[bj].x, Xi[bx], 0, 0, 0);
+                }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
         }
     }
-    const float zmax = __int_as_float(sZmax);
-    if (act && ti == tj && !(dmin >= 1e-5 * (double)zmax)) atomicOr(&sFlag, kFlagPivot);
-    __syncthreads();
-    if (t == 0) {
-        const int fl = sFlag;
-        const bool pivot = (fl & (kFlagPivot | COSIM_SYS_BAD_INPUT)) != 0;
-        status[s] = fl & ~kFlagPivot;
+    if (lane == 0) {
+        const bool pivot = (flag & COSIM_SYS_BAD_INPUT) || !(dmin >= 1e-5 * (double)zdiag);
+        status[s] = flag;
         fac.fmt[s] = pivot ? kFmtNeedsPivot : kFmtLDL;
     }
 }
@@ -782,18 +788,19 @@ hipError_t launch_solve_forward(int NP, int n, int S, int F, const double *M_d,
 hipError_t launch_ldl(int NP, int n, int S, int F, const double *M_d, const double *R_d,
                       const double *C_d, const double *omega_d, GJFactor fac, int32_t *status_d,
                       hipStream_t st) {
+    const dim3 grid((S + 3) / 4);
     switch (NP) {
         case 16:
-            hipLaunchKernelGGL(k_ldl<16>, dim3(S), dim3(GJShape<16>::BLOCK), 0, st, n, S, F, M_d,
-                               R_d, C_d, omega_d, fac, status_d);
+            hipLaunchKernelGGL(k_ldl<16>, grid, dim3(256), 0, st, n, S, F, M_d, R_d, C_d, omega_d,
+                               fac, status_d);
             break;
         case 32:
-            hipLaunchKernelGGL(k_ldl<32>, dim3(S), dim3(GJShape<32>::BLOCK), 0, st, n, S, F, M_d,
-                               R_d, C_d, omega_d, fac, status_d);
+            hipLaunchKernelGGL(k_ldl<32>, grid, dim3(256), 0, st, n, S, F, M_d, R_d, C_d, omega_d,
+                               fac, status_d);
             break;
         case 64:
-            hipLaunchKernelGGL(k_ldl<64>, dim3(S), dim3(GJShape<64>::BLOCK), 0, st, n, S, F, M_d,
-                               R_d, C_d, omega_d, fac, status_d);
+            hipLaunchKernelGGL(k_ldl<64>, grid, dim3(256), 0, st, n, S, F, M_d, R_d, C_d, omega_d,
+                               fac, status_d);
             break;
         default:
             return hipErrorInvalidValue;
