@@ -6,7 +6,9 @@ frequencies 118..138 MHz, a batch of 4,096 capacitance configurations.  One
 step is one cosim_loss_and_grad call over the whole batch: the forward solve of
 every (configuration, frequency) system, B_z = G I with the loss epilogue, the
 adjoint contraction G^T conj(w), the adjoint solve and the gradient reduction.
-Inputs are resident in HBM before the timed region.
+Inputs are resident in HBM before the timed region.  Before each mode is
+timed, cosim_plan_autotune picks the fastest fused-kernel variant for it
+(outside the timed region, like the one-time assembly).
 
 The value is the mixed-precision throughput (matrix-core contraction in the
 chosen mixed mode, FP64 solves); the FP64 mode is timed on the same GPU and
@@ -49,6 +51,8 @@ def parse():
                     help="timed steps of the FP64 comparison (default: steps/2, >= 3)")
     ap.add_argument("--cpu-configs", type=int, default=2,
                     help="configurations the oracle evaluates for the CPU baseline (0: skip)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip cosim_plan_autotune (use the default kernel variants)")
     ap.add_argument("--profile-steps", type=int, default=None,
                     help="run only this many steps of the headline mode (for rocprofv3)")
     return ap.parse_args()
@@ -59,7 +63,11 @@ def _src_hash(path: str) -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def time_mode(plan, C, om, T, prec: str, steps: int, warmup: int, torch):
+def time_mode(plan, C, om, T, prec: str, steps: int, warmup: int, torch, tune: bool = True):
+    tuned = None
+    if tune:
+        chosen, ms = plan.autotune(C, om, T, precision=PREC_CODE[prec], reps=2)
+        tuned = {"variant": int(chosen), "variant_ms": [float(x) for x in ms]}
     loss = torch.empty((C.shape[0],), dtype=torch.float64, device=C.device)
     grad = torch.empty_like(C)
     st = torch.empty((C.shape[0], om.shape[0]), dtype=torch.int32, device=C.device)
@@ -77,7 +85,7 @@ def time_mode(plan, C, om, T, prec: str, steps: int, warmup: int, torch):
     phases = plan.timing_read()
     plan.timing(0)
     bad = int((st != 0).sum())
-    return dt, phases, bad
+    return dt, phases, bad, tuned
 
 
 def cpu_baseline(wl, n_configs: int):
@@ -138,7 +146,7 @@ def main():
     print(f"[bench] assembled {wl.summary()} in {t_asm:.2f} s", file=sys.stderr, flush=True)
 
     if args.profile_steps is not None:
-        time_mode(plan, C, om, T, args.mixed, args.profile_steps, 1, torch)
+        time_mode(plan, C, om, T, args.mixed, args.profile_steps, 1, torch, tune=not args.no_autotune)
         # reference copy of known size (256 MiB read + 256 MiB written) that
         # calibrates the HBM byte counters of a profiler run
         x = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=dev)
@@ -158,7 +166,8 @@ def main():
     modes.append(other)
     for m in modes:
         steps = args.steps if m != "fp64" else (args.fp64_steps or max(3, args.steps // 2))
-        dt, ph, bad = time_mode(plan, C, om, T, m, steps, args.warmup, torch)
+        dt, ph, bad, tuned = time_mode(plan, C, om, T, m, steps, args.warmup, torch,
+                                       tune=not args.no_autotune)
         fused = float(np.mean(ph[:, 1]))
         res[m] = {
             "evals_per_s": wl.B * steps / dt,
@@ -167,6 +176,7 @@ def main():
             "phase_ms": {name: float(np.mean(ph[:, i])) for i, name in enumerate(Plan.PHASES)},
             "fused_tflops": flops / (fused * 1e-3) / 1e12,
             "flagged_systems": bad,
+            "autotune": tuned,
         }
         print(f"[bench] {m}: {res[m]['evals_per_s']:.0f} evals/s, {res[m]['ms_per_step']:.2f} ms/step, "
               f"phases {res[m]['phase_ms']}", file=sys.stderr, flush=True)

@@ -174,6 +174,24 @@ int cosim_loss_and_grad(cosim_plan_t p, int B, int F, const double *C_d, const d
                         double *grad_d, int32_t *status_d, void *stream);
 
 /* --------------------------------------------------------------------------
+ * Tuning of the fused contraction (performance only; every variant computes
+ * the same quantities to the precision's tolerance).  A variant fixes the
+ * systems per wavefront and the field points per LDS tile.
+ * cosim_plan_set_variant / cosim_plan_get_variant select or read the variant
+ * used for `precision` (0 is the default; n_variants receives the count).
+ * cosim_plan_autotune runs cosim_loss_and_grad reps times (after one warm-up)
+ * with every variant on the given inputs, keeps the fastest for `precision`,
+ * and writes the mean milliseconds per call of each variant to ms_out (host,
+ * n_variants entries; may be NULL).  It allocates and frees its own scratch
+ * and synchronises `stream`; it is a set-up call, not a hot one.
+ * -------------------------------------------------------------------------- */
+int cosim_plan_set_variant(cosim_plan_t p, int precision, int variant);
+int cosim_plan_get_variant(cosim_plan_t p, int precision, int *variant, int *n_variants);
+int cosim_plan_autotune(cosim_plan_t p, int B, int F, const double *C_d, const double *omega_d,
+                        const double *T_d, int loss_mode, int precision, int reps, void *stream,
+                        double *ms_out);
+
+/* --------------------------------------------------------------------------
  * Phase timing of cosim_loss_and_grad with HIP events on the call's stream
  * (for benchmarks and metrics; not a paper quantity).
  * cosim_plan_timing(p, max_records) creates event sets for the next

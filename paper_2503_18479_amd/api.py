@@ -126,6 +126,29 @@ class Plan:
         check(self._lib.cosim_plan_copy_phi(self._h, _host(out)))
         return out
 
+    # -- tuning of the fused contraction ------------------------------------------
+    def variants(self, precision) -> Tuple[int, int]:
+        v = ctypes.c_int(); nv = ctypes.c_int()
+        check(self._lib.cosim_plan_get_variant(self._h, precision_code(precision), ctypes.byref(v),
+                                               ctypes.byref(nv)))
+        return v.value, nv.value
+
+    def set_variant(self, precision, variant: int) -> None:
+        check(self._lib.cosim_plan_set_variant(self._h, precision_code(precision), int(variant)))
+
+    def autotune(self, C, omega, T, precision=FP32, loss_mode: int = LOSS_MAG, reps: int = 3):
+        """Times every fused-kernel variant on these inputs and keeps the fastest.
+        Returns (chosen variant, ms per call of each variant)."""
+        prec = precision_code(precision)
+        B, F = int(C.shape[0]), int(omega.shape[0])
+        _, nv = self.variants(prec)
+        ms = np.zeros(nv)
+        check(self._lib.cosim_plan_autotune(
+            self._h, B, F, _dev(C, torch.float64, (B, self.n), "C"),
+            _dev(omega, torch.float64, (F,), "omega"), _dev(T, torch.float64, (self.P,), "T"),
+            int(loss_mode), prec, int(reps), _stream(), _host(ms)))
+        return self.variants(prec)[0], ms
+
     # -- phase timing (HIP events on the call's stream) ------------------------
     PHASES = ("solve_forward", "fused_contraction", "solve_adjoint", "reduce")
 

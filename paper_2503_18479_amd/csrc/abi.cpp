@@ -126,8 +126,8 @@ int ensure_workspace(cosim_plan *p, size_t systems, int chunks) {
 
 // P-chunk count of the fused kernels: enough workgroups to fill the chip
 // several times over, bounded by the number of 64-row tiles.
-int choose_chunks(const cosim_plan *p, Prec prec, size_t S) {
-    const size_t per_block = (size_t)fused_systems_per_block(prec, p->NP);
+int choose_chunks(const cosim_plan *p, Prec prec, size_t S, int variant) {
+    const size_t per_block = (size_t)fused_systems_per_block(prec, p->NP, variant);
     const size_t bx = (S + per_block - 1) / per_block;
     const size_t target = 2048;  // >= 8 workgroups per CU on 256 CUs
     size_t c = (target + bx - 1) / bx;
@@ -136,6 +136,15 @@ int choose_chunks(const cosim_plan *p, Prec prec, size_t S) {
     c = std::max<size_t>(c, 1);
     c = std::min<size_t>(c, 64);
     return (int)c;
+}
+
+// chunks of whole 64-row tiles, every chunk non-empty; *tiles_per_chunk out
+int chunks_for(const cosim_plan *p, Prec prec, size_t S, int variant, int *tiles_per_chunk = nullptr) {
+    const int tiles = p->P_pad / kPTile;
+    const int want = choose_chunks(p, prec, S, variant);
+    const int tpc = (tiles + want - 1) / want;
+    if (tiles_per_chunk) *tiles_per_chunk = tpc;
+    return (tiles + tpc - 1) / tpc;
 }
 
 int check_batch(const cosim_plan *p, int B, int F) {
@@ -323,7 +332,8 @@ int cosim_plan_reserve(cosim_plan_t p, int max_batch, int max_freq) {
     const size_t S = (size_t)max_batch * max_freq;
     int chunks = 1;
     for (int pr = COSIM_FP64; pr <= COSIM_BF16X3; ++pr)
-        chunks = std::max(chunks, choose_chunks(p, (Prec)pr, S));
+        for (int v = 0; v < fused_variant_count((Prec)pr); ++v)
+            chunks = std::max(chunks, chunks_for(p, (Prec)pr, S, v));
     return ensure_workspace(p, S, chunks);
 }
 
@@ -423,10 +433,9 @@ int cosim_loss_and_grad(cosim_plan_t p, int B, int F, const double *C_d, const d
     if ((rc = check_device(p))) return rc;
     const size_t S = (size_t)B * F;
     const Prec prec = (Prec)precision;
-    // chunks of whole 64-row tiles; every chunk is non-empty
-    const int tiles = p->P_pad / kPTile;
-    const int tpc = (tiles + choose_chunks(p, prec, S) - 1) / choose_chunks(p, prec, S);
-    const int nchunk = (tiles + tpc - 1) / tpc;
+    const int variant = p->variant[precision];
+    int tpc = 1;
+    const int nchunk = chunks_for(p, prec, S, variant, &tpc);
     if ((rc = ensure_workspace(p, S, nchunk))) return rc;
     hipStream_t st = (hipStream_t)stream;
     hipEvent_t *ev = nullptr;
@@ -465,7 +474,7 @@ int cosim_loss_and_grad(cosim_plan_t p, int B, int F, const double *C_d, const d
     a.n = p->n;
     a.rpart = p->rpart;
     a.lpart = p->lpart;
-    HIP_TRY(launch_fused(prec, p->NP, loss_mode, grad, a, st));
+    HIP_TRY(launch_fused(prec, p->NP, variant, loss_mode, grad, a, st));
     if (ev) HIP_TRY(hipEventRecord(ev[2], st));
     const double scale = 1.0 / ((double)F * (double)p->P);
     if (grad)
@@ -476,6 +485,88 @@ int cosim_loss_and_grad(cosim_plan_t p, int B, int F, const double *C_d, const d
                           loss_d, st));
     if (ev) HIP_TRY(hipEventRecord(ev[4], st));
     return COSIM_OK;
+}
+
+int cosim_plan_set_variant(cosim_plan_t p, int precision, int variant) {
+    if (!p) return fail(COSIM_EINVAL, "null plan");
+    int rc = check_prec(precision);
+    if (rc) return rc;
+    if (variant < 0 || variant >= fused_variant_count((Prec)precision))
+        return fail(COSIM_EINVAL, "variant %d out of range [0, %d)", variant,
+                    fused_variant_count((Prec)precision));
+    p->variant[precision] = variant;
+    return COSIM_OK;
+}
+
+int cosim_plan_get_variant(cosim_plan_t p, int precision, int *variant, int *n_variants) {
+    if (!p) return fail(COSIM_EINVAL, "null plan");
+    int rc = check_prec(precision);
+    if (rc) return rc;
+    if (variant) *variant = p->variant[precision];
+    if (n_variants) *n_variants = fused_variant_count((Prec)precision);
+    return COSIM_OK;
+}
+
+int cosim_plan_autotune(cosim_plan_t p, int B, int F, const double *C_d, const double *omega_d,
+                        const double *T_d, int loss_mode, int precision, int reps, void *stream,
+                        double *ms_out) {
+    int rc = check_batch(p, B, F);
+    if (rc) return rc;
+    if ((rc = check_prec(precision))) return rc;
+    if (B == 0 || F == 0) return COSIM_OK;
+    if (!C_d || !omega_d || !T_d) return fail(COSIM_EINVAL, "null device pointer");
+    if (reps < 1) return fail(COSIM_EINVAL, "reps must be >= 1");
+    if ((rc = check_device(p))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const size_t S = (size_t)B * F;
+    double *loss = nullptr, *grad = nullptr;
+    int32_t *status = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto done = [&](int code) {
+        dfree(loss);
+        dfree(grad);
+        dfree(status);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        return code;
+    };
+    if (hipMalloc((void **)&loss, (size_t)B * sizeof(double)) != hipSuccess ||
+        hipMalloc((void **)&grad, (size_t)B * p->n * sizeof(double)) != hipSuccess ||
+        hipMalloc((void **)&status, S * sizeof(int32_t)) != hipSuccess ||
+        hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return done(fail(COSIM_ENOMEM, "autotune scratch allocation failed"));
+    const int nv = fused_variant_count((Prec)precision);
+    int best = 0;
+    float best_ms = 0.f;
+    const int saved_timing = p->timing_cap;
+    p->timing_cap = 0;  // tuning calls are not recorded
+    for (int v = 0; v < nv; ++v) {
+        p->variant[precision] = v;
+        rc = cosim_loss_and_grad(p, B, F, C_d, omega_d, T_d, loss_mode, precision, loss, grad,
+                                 status, stream);  // warm-up (and workspace growth)
+        if (rc) { p->timing_cap = saved_timing; return done(rc); }
+        if (hipEventRecord(e0, st) != hipSuccess) { p->timing_cap = saved_timing; return done(fail(COSIM_EDEVICE, "hipEventRecord failed")); }
+        for (int r = 0; r < reps; ++r) {
+            rc = cosim_loss_and_grad(p, B, F, C_d, omega_d, T_d, loss_mode, precision, loss, grad,
+                                     status, stream);
+            if (rc) { p->timing_cap = saved_timing; return done(rc); }
+        }
+        float ms = 0.f;
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            p->timing_cap = saved_timing;
+            return done(fail(COSIM_EDEVICE, "timing the variants failed"));
+        }
+        ms /= (float)reps;
+        if (ms_out) ms_out[v] = ms;
+        if (v == 0 || ms < best_ms) {
+            best = v;
+            best_ms = ms;
+        }
+    }
+    p->timing_cap = saved_timing;
+    p->variant[precision] = best;
+    return done(COSIM_OK);
 }
 
 int cosim_plan_timing(cosim_plan_t p, int max_records) {

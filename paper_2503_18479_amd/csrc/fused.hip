@@ -278,11 +278,11 @@ typedef short s16x4 __attribute__((ext_vector_type(4)));
 // {16+4q..16+4q+3} of the second, i.e. pi(8q + j) = (j < 4 ? 4q + j :
 // 16 + 4q + j - 4).  The adjoint A operand G^T[i][pi(8q + j)] is two 8-byte
 // reads of the transposed tile held in LDS next to the row-major one.
-template <int NP, int NB, int LOSS, bool GRAD>
+template <int NP, int NB, int PT, int LOSS, bool GRAD>
 __global__ __launch_bounds__(256, 2) void k_fused_bf16x3(FusedArgs a) {
     constexpr int KS = NP / 32;  // forward k-steps of 32
     constexpr int IB = NP / 16;
-    constexpr int PT = kPTile;
+    static_assert(kPTile % PT == 0, "tile rows must divide the 64-row padding of G");
     constexpr int LDR = NP + 8;  // row-major tile: padded row (bf16 elements)
     constexpr int LDT = PT + 8;  // transposed tile: padded row
     __shared__ __attribute__((aligned(16))) uint16_t sH[PT * LDR];
@@ -455,72 +455,101 @@ __global__ __launch_bounds__(256, 2) void k_fused_bf16x3(FusedArgs a) {
     }
 }
 
-// Systems per wave (16 * NB) for each precision.
-template <typename T>
-struct NBFor {
-    static constexpr int value = sizeof(T) == 8 ? 1 : 2;
+// Tuning variants of the fused kernels: systems per wave (16 * NB) and rows
+// per LDS tile (PT).  Variant 0 is the default; cosim_plan_autotune picks per
+// plan and precision.
+struct Variant {
+    int nb, pt;
 };
-constexpr int kNBbf16 = 2;
+constexpr Variant kVarF64[] = {{1, 64}, {2, 64}};
+constexpr Variant kVarF32[] = {{2, 64}, {1, 64}};
+constexpr Variant kVarBF16[] = {{2, 64}, {1, 64}, {2, 32}, {1, 32}};
 
-template <typename T, int NP, int LOSS, bool GRAD>
+template <typename T, int NP, int NB, int LOSS, bool GRAD>
 hipError_t go_typed(const FusedArgs &a, hipStream_t st) {
-    constexpr int NB = NBFor<T>::value;
     const int per_block = 4 * 16 * NB;
     dim3 grid((a.S + per_block - 1) / per_block, a.nchunk);
     hipLaunchKernelGGL((k_fused<T, NP, NB, LOSS, GRAD>), grid, dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
-template <int NP, int LOSS, bool GRAD>
+template <int NP, int NB, int PT, int LOSS, bool GRAD>
 hipError_t go_bf16(const FusedArgs &a, hipStream_t st) {
-    const int per_block = 4 * 16 * kNBbf16;
+    const int per_block = 4 * 16 * NB;
     dim3 grid((a.S + per_block - 1) / per_block, a.nchunk);
-    hipLaunchKernelGGL((k_fused_bf16x3<NP, kNBbf16, LOSS, GRAD>), grid, dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_fused_bf16x3<NP, NB, PT, LOSS, GRAD>), grid, dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
 template <int NP, int LOSS, bool GRAD>
-hipError_t go_np(Prec prec, const FusedArgs &a, hipStream_t st) {
+hipError_t go_np(Prec prec, int variant, const FusedArgs &a, hipStream_t st) {
     switch (prec) {
-        case Prec::F64: return go_typed<double, NP, LOSS, GRAD>(a, st);
-        case Prec::F32: return go_typed<float, NP, LOSS, GRAD>(a, st);
+        case Prec::F64:
+            switch (variant) {
+                case 0: return go_typed<double, NP, 1, LOSS, GRAD>(a, st);
+                case 1: return go_typed<double, NP, 2, LOSS, GRAD>(a, st);
+            }
+            break;
+        case Prec::F32:
+            switch (variant) {
+                case 0: return go_typed<float, NP, 2, LOSS, GRAD>(a, st);
+                case 1: return go_typed<float, NP, 1, LOSS, GRAD>(a, st);
+            }
+            break;
         case Prec::BF16X3:
-            if constexpr (NP % 32 == 0) return go_bf16<NP, LOSS, GRAD>(a, st);
-            else return hipErrorInvalidValue;
+            if constexpr (NP % 32 == 0) {
+                switch (variant) {
+                    case 0: return go_bf16<NP, 2, 64, LOSS, GRAD>(a, st);
+                    case 1: return go_bf16<NP, 1, 64, LOSS, GRAD>(a, st);
+                    case 2: return go_bf16<NP, 2, 32, LOSS, GRAD>(a, st);
+                    case 3: return go_bf16<NP, 1, 32, LOSS, GRAD>(a, st);
+                }
+            }
+            break;
     }
     return hipErrorInvalidValue;
 }
 
 template <int LOSS, bool GRAD>
-hipError_t go_loss(Prec prec, int NP, const FusedArgs &a, hipStream_t st) {
+hipError_t go_loss(Prec prec, int NP, int variant, const FusedArgs &a, hipStream_t st) {
     switch (NP) {
-        case 16: return go_np<16, LOSS, GRAD>(prec, a, st);
-        case 32: return go_np<32, LOSS, GRAD>(prec, a, st);
-        case 64: return go_np<64, LOSS, GRAD>(prec, a, st);
+        case 16: return go_np<16, LOSS, GRAD>(prec, variant, a, st);
+        case 32: return go_np<32, LOSS, GRAD>(prec, variant, a, st);
+        case 64: return go_np<64, LOSS, GRAD>(prec, variant, a, st);
     }
     return hipErrorInvalidValue;
 }
 
 }  // namespace
 
-int fused_systems_per_block(Prec prec, int NP) {
+int fused_variant_count(Prec prec) {
+    switch (prec) {
+        case Prec::F64: return (int)(sizeof(kVarF64) / sizeof(Variant));
+        case Prec::F32: return (int)(sizeof(kVarF32) / sizeof(Variant));
+        case Prec::BF16X3: return (int)(sizeof(kVarBF16) / sizeof(Variant));
+    }
+    return 1;
+}
+
+int fused_systems_per_block(Prec prec, int NP, int variant) {
     (void)NP;
     switch (prec) {
-        case Prec::F64: return 64 * NBFor<double>::value;
-        case Prec::F32: return 64 * NBFor<float>::value;
-        case Prec::BF16X3: return 64 * kNBbf16;
+        case Prec::F64: return 64 * kVarF64[variant].nb;
+        case Prec::F32: return 64 * kVarF32[variant].nb;
+        case Prec::BF16X3: return 64 * kVarBF16[variant].nb;
     }
     return 64;
 }
 
-hipError_t launch_fused(Prec prec, int NP, int loss_mode, bool grad, const FusedArgs &a,
-                        hipStream_t st) {
+hipError_t launch_fused(Prec prec, int NP, int variant, int loss_mode, bool grad,
+                        const FusedArgs &a, hipStream_t st) {
+    if (variant < 0 || variant >= fused_variant_count(prec)) return hipErrorInvalidValue;
     if (loss_mode == COSIM_LOSS_MAG) {
-        return grad ? go_loss<COSIM_LOSS_MAG, true>(prec, NP, a, st)
-                    : go_loss<COSIM_LOSS_MAG, false>(prec, NP, a, st);
+        return grad ? go_loss<COSIM_LOSS_MAG, true>(prec, NP, variant, a, st)
+                    : go_loss<COSIM_LOSS_MAG, false>(prec, NP, variant, a, st);
     }
-    return grad ? go_loss<COSIM_LOSS_COMPLEX, true>(prec, NP, a, st)
-                : go_loss<COSIM_LOSS_COMPLEX, false>(prec, NP, a, st);
+    return grad ? go_loss<COSIM_LOSS_COMPLEX, true>(prec, NP, variant, a, st)
+                : go_loss<COSIM_LOSS_COMPLEX, false>(prec, NP, variant, a, st);
 }
 
 }  // namespace cosim

@@ -113,10 +113,12 @@ struct FusedArgs {
     double2 *rpart;       // [nchunk][S][NP] (rr, ri); may be null when !grad
     double *lpart;        // [nchunk][S]
 };
-hipError_t launch_fused(Prec prec, int NP, int loss_mode, bool grad, const FusedArgs &a,
-                        hipStream_t st);
-// Number of systems one workgroup of the fused kernel covers.
-int fused_systems_per_block(Prec prec, int NP);
+hipError_t launch_fused(Prec prec, int NP, int variant, int loss_mode, bool grad,
+                        const FusedArgs &a, hipStream_t st);
+// Tuning variants of the fused kernel per precision, and the number of
+// systems one workgroup of a variant covers.
+int fused_variant_count(Prec prec);
+int fused_systems_per_block(Prec prec, int NP, int variant);
 
 // Materialised field B[s][p] (complex128 for F64, complex64 otherwise).
 hipError_t launch_field(Prec prec, int NP, int P, int S, int n, const double *G64,
@@ -159,4 +161,5 @@ struct cosim_plan {
     std::vector<hipEvent_t> events;
     int timing_cap = 0, timing_used = 0;
     bool ldl_ok = false;  // every R_k > 0: the LDL^T fast path applies
+    int variant[3] = {0, 0, 0};  // fused-kernel variant per precision
 };

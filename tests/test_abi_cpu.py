@@ -108,3 +108,11 @@ def test_hot_call_argument_errors(lib):
     assert lib.cosim_plan_destroy(None) == 0
     assert lib.cosim_geometry_destroy(None) == 0
     assert lib.cosim_last_error() != b""
+
+
+def test_tuning_argument_errors(lib):
+    v = ctypes.c_int()
+    assert lib.cosim_plan_set_variant(None, 0, 0) == EINVAL
+    assert lib.cosim_plan_get_variant(None, 0, ctypes.byref(v), None) == EINVAL
+    assert lib.cosim_plan_autotune(None, 1, 1, None, None, None, 0, 0, 1, None, None) == EINVAL
+    assert lib.cosim_plan_timing(None, 4) == EINVAL

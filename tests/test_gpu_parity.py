@@ -358,3 +358,33 @@ def test_loss_and_grad_small_pivot_falls_back(dev):
     assert int(st.abs().sum()) == 0
     assert np.max(np.abs(loss.cpu().numpy() - Lr) / Lr) < 1e-9
     assert _nrel(grad.cpu().numpy(), gr, axis=1).max() < 1e-9
+
+
+# ----------------------------------------------------------------- tuning variants
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_every_fused_variant_matches_oracle(dev, prec):
+    c = _case("n64")
+    _, nv = c.plan.variants(prec)
+    assert nv >= 2
+    Lr = c.oracle_eval()[2]
+    gr = c.oracle_grad()
+    try:
+        for v in range(nv):
+            _say(f"[variant] prec={prec} variant={v}")
+            c.plan.set_variant(prec, v)
+            loss, grad, st = c.plan.loss_and_grad(c.C, c.om, c.T, precision=prec)
+            assert np.max(np.abs(loss.cpu().numpy() - Lr) / Lr) < TOL[prec], v
+            assert _nrel(grad.cpu().numpy(), gr, axis=1).max() < TOL[prec], v
+    finally:
+        c.plan.set_variant(prec, 0)
+
+
+def test_autotune_picks_a_variant(dev):
+    c = _case("n64")
+    chosen, ms = c.plan.autotune(c.C, c.om, c.T, precision=2, reps=1)
+    assert 0 <= chosen < len(ms) and np.all(ms > 0)
+    assert ms[chosen] == ms.min()
+    loss, grad, st = c.plan.loss_and_grad(c.C, c.om, c.T, precision=2)
+    assert np.max(np.abs(loss.cpu().numpy() - c.oracle_eval()[2]) / c.oracle_eval()[2]) < TOL[2]
+    c.plan.set_variant(2, 0)
