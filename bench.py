@@ -49,7 +49,7 @@ def parse():
                     help="131,072 points (z = 1 cm and 3 cm) instead of 65,536")
     ap.add_argument("--fp64-steps", type=int, default=None,
                     help="timed steps of the FP64 comparison (default: steps/2, >= 3)")
-    ap.add_argument("--cpu-configs", type=int, default=2,
+    ap.add_argument("--cpu-configs", type=int, default=16,
                     help="configurations the oracle evaluates for the CPU baseline (0: skip)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip cosim_plan_autotune (use the default kernel variants)")

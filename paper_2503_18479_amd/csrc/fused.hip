@@ -69,13 +69,16 @@ __device__ inline T tcast(double x) {
 template <int LOSS>
 __device__ inline float epilogue_f(float &x, float &y, float t) {
     if (LOSS == COSIM_LOSS_MAG) {
+        // |B|^2 is clamped to a normal floor before rsq: at B = 0 this gives
+        // e = -t (loss t^2) and w = c B = 0 without a branch; below |B| ~ 1e-18
+        // the magnitude's derivative is singular anyway.
         const float m2 = fmaf(x, x, y * y);
-        const float rs = __builtin_amdgcn_rsqf(m2);
+        const float rs = __builtin_amdgcn_rsqf(fmaxf(m2, 1e-36f));
         const float e = fmaf(m2, rs, -t);
-        const float c = m2 > 0.0f ? fmaf(-t, rs, 1.0f) : 0.0f;
+        const float c = fmaf(-t, rs, 1.0f);
         x *= c;
         y *= c;
-        return m2 > 0.0f ? e * e : t * t;
+        return e * e;
     } else {
         const float ex = x - t;
         x = ex;
@@ -269,7 +272,21 @@ __device__ inline void split2(float x, __bf16 &hi, __bf16 &lo) {
     lo = (__bf16)(x - (float)hi);
 }
 
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// split2 of two values at once, packed as they sit in an MFMA operand dword:
+// one packed convert for the high parts, which are widened back from the
+// packed dword itself (shift / mask), and one for the low parts.
+__device__ inline void split2_pair(float a, float b, unsigned &hi, unsigned &lo) {
+    hi = __builtin_bit_cast(unsigned, __builtin_convertvector(f32x2{a, b}, bf16x2));
+    const float ha = __builtin_bit_cast(float, hi << 16);
+    const float hb = __builtin_bit_cast(float, hi & 0xffff0000u);
+    lo = __builtin_bit_cast(unsigned, __builtin_convertvector(f32x2{a - ha, b - hb}, bf16x2));
+}
+
 typedef short s16x4 __attribute__((ext_vector_type(4)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
 // Sub-tiles of 32 rows.  Forward: the 16-row halves of a sub-tile use K = 32
 // (loop index; lane (r16, q) holds k = 8q..8q+7 of each 32-wide k-step).
@@ -278,18 +295,23 @@ typedef short s16x4 __attribute__((ext_vector_type(4)));
 // {16+4q..16+4q+3} of the second, i.e. pi(8q + j) = (j < 4 ? 4q + j :
 // 16 + 4q + j - 4).  The adjoint A operand G^T[i][pi(8q + j)] is two 8-byte
 // reads of the transposed tile held in LDS next to the row-major one.
-template <int NP, int NB, int PT, int LOSS, bool GRAD>
+// DB: two LDS buffers, the next tile's global loads in flight in registers
+// while the current tile is computed (one barrier per tile); otherwise one
+// buffer, loaded between two barriers (half the LDS, so more blocks per CU).
+template <int NP, int NB, int PT, bool DB, int LOSS, bool GRAD>
 __global__ __launch_bounds__(256, 2) void k_fused_bf16x3(FusedArgs a) {
     constexpr int KS = NP / 32;  // forward k-steps of 32
     constexpr int IB = NP / 16;
     static_assert(kPTile % PT == 0, "tile rows must divide the 64-row padding of G");
     constexpr int LDR = NP + 8;  // row-major tile: padded row (bf16 elements)
     constexpr int LDT = PT + 8;  // transposed tile: padded row
-    __shared__ __attribute__((aligned(16))) uint16_t sH[PT * LDR];
-    __shared__ __attribute__((aligned(16))) uint16_t sL[PT * LDR];
-    __shared__ __attribute__((aligned(16))) uint16_t tH[GRAD ? NP * LDT : 8];
-    __shared__ __attribute__((aligned(16))) uint16_t tL[GRAD ? NP * LDT : 8];
-    __shared__ float sT[PT];
+    constexpr int TSZ = PT * LDR, TTSZ = GRAD ? NP * LDT : 8;
+    constexpr int NBUF = DB ? 2 : 1;
+    __shared__ __attribute__((aligned(16))) uint16_t sH[NBUF][TSZ];
+    __shared__ __attribute__((aligned(16))) uint16_t sL[NBUF][TSZ];
+    __shared__ __attribute__((aligned(16))) uint16_t tH[NBUF][TTSZ];
+    __shared__ __attribute__((aligned(16))) uint16_t tL[NBUF][TTSZ];
+    __shared__ __attribute__((aligned(16))) float sTg[NBUF][PT];
     static_assert(NP % 32 == 0, "bf16x3 path needs NP multiple of 32");
 
     const uint16_t *__restrict__ Gh = (const uint16_t *)a.G;
@@ -334,30 +356,73 @@ __global__ __launch_bounds__(256, 2) void k_fused_bf16x3(FusedArgs a) {
 #pragma unroll
     for (int b = 0; b < NB; ++b) lacc[b] = 0.0;
 
-    constexpr int NV = PT * NP / 8;  // 16-byte vectors per tile and part
-    for (int p0 = pb; p0 < pe; p0 += PT) {
-        __syncthreads();
-        for (int v = threadIdx.x; v < NV; v += 256) {
-            const int e0 = v * 8;
+    // tile staging: each thread moves VPT 16-byte vectors per part
+    constexpr int NV = PT * NP / 8;
+    static_assert(NV % 64 == 0, "tile must split evenly over whole waves");
+    constexpr int VPT = (NV + 255) / 256;
+    u32x4 rgh[VPT], rgl[VPT], rth[VPT], rtl[VPT];
+    float rT = 0.0f;
+    auto fetch = [&](int p0) __attribute__((always_inline)) {
+#pragma unroll
+        for (int u = 0; u < VPT; ++u) {
+            const int e0 = (threadIdx.x + 256 * u) * 8;
+            if (NV % 256 != 0 && e0 >= 8 * NV) continue;
             const int row = e0 / NP, col = e0 - row * NP;
             const size_t go = (size_t)(p0 + row) * NP + col;
-            *(uint4 *)(sH + row * LDR + col) = *(const uint4 *)(Gh + go);
-            *(uint4 *)(sL + row * LDR + col) = *(const uint4 *)(Gl + go);
-        }
-        if (GRAD) {
-            for (int v = threadIdx.x; v < NV; v += 256) {
-                const int e0 = v * 8;
-                const int row = e0 / PT, col = e0 - row * PT;  // row = loop index i
-                const size_t go = (size_t)row * a.P_pad + p0 + col;
-                *(uint4 *)(tH + row * LDT + col) = *(const uint4 *)(a.GThi + go);
-                *(uint4 *)(tL + row * LDT + col) = *(const uint4 *)(a.GTlo + go);
+            rgh[u] = *(const u32x4 *)(Gh + go);
+            rgl[u] = *(const u32x4 *)(Gl + go);
+            if (GRAD) {
+                const int trow = e0 / PT, tcol = e0 - trow * PT;  // trow = loop index i
+                const size_t to = (size_t)trow * a.P_pad + p0 + tcol;
+                rth[u] = *(const u32x4 *)(a.GThi + to);
+                rtl[u] = *(const u32x4 *)(a.GTlo + to);
             }
         }
         if (threadIdx.x < PT) {
             const int p = p0 + threadIdx.x;
-            sT[threadIdx.x] = p < a.P ? (float)a.T[p] : 0.0f;
+            rT = p < a.P ? (float)a.T[p] : 0.0f;
+        }
+    };
+    auto stash = [&](int buf) __attribute__((always_inline)) {
+#pragma unroll
+        for (int u = 0; u < VPT; ++u) {
+            const int e0 = (threadIdx.x + 256 * u) * 8;
+            if (NV % 256 != 0 && e0 >= 8 * NV) continue;
+            const int row = e0 / NP, col = e0 - row * NP;
+            *(u32x4 *)(&sH[buf][row * LDR + col]) = rgh[u];
+            *(u32x4 *)(&sL[buf][row * LDR + col]) = rgl[u];
+            if (GRAD) {
+                const int trow = e0 / PT, tcol = e0 - trow * PT;
+                *(u32x4 *)(&tH[buf][trow * LDT + tcol]) = rth[u];
+                *(u32x4 *)(&tL[buf][trow * LDT + tcol]) = rtl[u];
+            }
+        }
+        if (threadIdx.x < PT) sTg[buf][threadIdx.x] = rT;
+    };
+
+    if (DB) {
+        if (pb < pe) {
+            fetch(pb);
+            stash(0);
         }
         __syncthreads();
+    }
+    int cur = 0;
+    for (int p0 = pb; p0 < pe; p0 += PT, cur ^= (DB ? 1 : 0)) {
+        const bool more = p0 + PT < pe;
+        if (DB) {
+            if (more) fetch(p0 + PT);  // loads in flight during the compute below
+        } else {
+            if (p0 != pb) __syncthreads();  // every wave is done with the previous tile
+            fetch(p0);
+            stash(0);
+            __syncthreads();
+        }
+        const uint16_t *__restrict__ cH = sH[cur];
+        const uint16_t *__restrict__ cL = sL[cur];
+        const uint16_t *__restrict__ ctH = tH[cur];
+        const uint16_t *__restrict__ ctL = tL[cur];
+        const float *__restrict__ sT = sTg[cur];
 #pragma unroll 1
         for (int sp = 0; sp < PT / 32; ++sp) {
             f32x4 br[2][NB], bi[2][NB];  // [16-row half][b]
@@ -367,8 +432,8 @@ __global__ __launch_bounds__(256, 2) void k_fused_bf16x3(FusedArgs a) {
                 bf16x8 ah[KS], al[KS];
 #pragma unroll
                 for (int kk = 0; kk < KS; ++kk) {
-                    ah[kk] = *(const bf16x8 *)(sH + row * LDR + 32 * kk + 8 * q);
-                    al[kk] = *(const bf16x8 *)(sL + row * LDR + 32 * kk + 8 * q);
+                    ah[kk] = *(const bf16x8 *)(cH + row * LDR + 32 * kk + 8 * q);
+                    al[kk] = *(const bf16x8 *)(cL + row * LDR + 32 * kk + 8 * q);
                 }
 #pragma unroll
                 for (int b = 0; b < NB; ++b) {
@@ -387,37 +452,51 @@ __global__ __launch_bounds__(256, 2) void k_fused_bf16x3(FusedArgs a) {
                 }
             }
             // epilogue on both halves, then w as bf16 hi/lo operands
-            bf16x8 wrh[NB], wrl[NB], wih[NB], wil[NB];
+            u32x4 rh[NB], rl[NB], ih[NB], il[NB];  // packed pairs of rows
             float lsub[NB];
 #pragma unroll
             for (int b = 0; b < NB; ++b) lsub[b] = 0.0f;
 #pragma unroll
-            for (int h = 0; h < 2; ++h)
+            for (int h = 0; h < 2; ++h) {
+                const f32x4 t4 = *(const f32x4 *)(sT + 32 * sp + 16 * h + 4 * q);
 #pragma unroll
-                for (int m = 0; m < 4; ++m) {
-                    const float t = sT[32 * sp + 16 * h + 4 * q + m];
+                for (int b = 0; b < NB; ++b) {
+                    f32x4 x = br[h][b], y = bi[h][b];
 #pragma unroll
-                    for (int b = 0; b < NB; ++b) {
-                        float x = br[h][b][m], y = bi[h][b][m];
-                        lsub[b] += epilogue_f<LOSS>(x, y, t);
-                        __bf16 hh, ll;
-                        split2(x, hh, ll);
-                        wrh[b][4 * h + m] = hh;
-                        wrl[b][4 * h + m] = ll;
-                        split2(y, hh, ll);
-                        wih[b][4 * h + m] = hh;
-                        wil[b][4 * h + m] = ll;
+                    for (int m = 0; m < 4; ++m) {
+                        float xm = x[m], ym = y[m];
+                        lsub[b] += epilogue_f<LOSS>(xm, ym, t4[m]);
+                        x[m] = xm;
+                        y[m] = ym;
+                    }
+#pragma unroll
+                    for (int mp = 0; mp < 2; ++mp) {
+                        unsigned hh, ll;
+                        split2_pair(x[2 * mp], x[2 * mp + 1], hh, ll);
+                        rh[b][2 * h + mp] = hh;
+                        rl[b][2 * h + mp] = ll;
+                        split2_pair(y[2 * mp], y[2 * mp + 1], hh, ll);
+                        ih[b][2 * h + mp] = hh;
+                        il[b][2 * h + mp] = ll;
                     }
                 }
+            }
+            bf16x8 wrh[NB], wrl[NB], wih[NB], wil[NB];
 #pragma unroll
-            for (int b = 0; b < NB; ++b) lacc[b] += (double)lsub[b];
+            for (int b = 0; b < NB; ++b) {
+                lacc[b] += (double)lsub[b];
+                wrh[b] = __builtin_bit_cast(bf16x8, rh[b]);
+                wrl[b] = __builtin_bit_cast(bf16x8, rl[b]);
+                wih[b] = __builtin_bit_cast(bf16x8, ih[b]);
+                wil[b] = __builtin_bit_cast(bf16x8, il[b]);
+            }
             if (GRAD) {
 #pragma unroll
                 for (int ib = 0; ib < IB; ++ib) {
                     // A operand: Gt[i = 16 ib + r16][p = pi(8q + j)]
                     const int base = (16 * ib + r16) * LDT + 32 * sp + 4 * q;
-                    const s16x4 h0 = *(const s16x4 *)(tH + base), h1 = *(const s16x4 *)(tH + base + 16);
-                    const s16x4 l0 = *(const s16x4 *)(tL + base), l1 = *(const s16x4 *)(tL + base + 16);
+                    const s16x4 h0 = *(const s16x4 *)(ctH + base), h1 = *(const s16x4 *)(ctH + base + 16);
+                    const s16x4 l0 = *(const s16x4 *)(ctL + base), l1 = *(const s16x4 *)(ctL + base + 16);
                     const bf16x8 th = __builtin_bit_cast(bf16x8, __builtin_shufflevector(h0, h1, 0, 1, 2, 3, 4, 5, 6, 7));
                     const bf16x8 tl = __builtin_bit_cast(bf16x8, __builtin_shufflevector(l0, l1, 0, 1, 2, 3, 4, 5, 6, 7));
 #pragma unroll
@@ -431,6 +510,10 @@ __global__ __launch_bounds__(256, 2) void k_fused_bf16x3(FusedArgs a) {
                     }
                 }
             }
+        }
+        if (DB) {
+            if (more) stash(cur ^ 1);
+            __syncthreads();
         }
     }
 
@@ -455,15 +538,17 @@ __global__ __launch_bounds__(256, 2) void k_fused_bf16x3(FusedArgs a) {
     }
 }
 
-// Tuning variants of the fused kernels: systems per wave (16 * NB) and rows
-// per LDS tile (PT).  Variant 0 is the default; cosim_plan_autotune picks per
-// plan and precision.
+// Tuning variants of the fused kernels: systems per wave (16 * NB), rows per
+// LDS tile (PT) and, for BF16X3, single or double LDS buffering.  Variant 0 is
+// the default; cosim_plan_autotune picks per plan and precision.
 struct Variant {
     int nb, pt;
+    bool db;
 };
-constexpr Variant kVarF64[] = {{1, 64}, {2, 64}};
-constexpr Variant kVarF32[] = {{2, 64}, {1, 64}};
-constexpr Variant kVarBF16[] = {{2, 64}, {1, 64}, {2, 32}, {1, 32}};
+constexpr Variant kVarF64[] = {{1, 64, false}, {2, 64, false}};
+constexpr Variant kVarF32[] = {{2, 64, false}, {1, 64, false}};
+constexpr Variant kVarBF16[] = {{2, 64, false}, {1, 64, false}, {2, 32, false}, {1, 32, false},
+                                {2, 64, true},  {1, 64, true},  {2, 32, true},  {1, 32, true}};
 
 template <typename T, int NP, int NB, int LOSS, bool GRAD>
 hipError_t go_typed(const FusedArgs &a, hipStream_t st) {
@@ -473,11 +558,11 @@ hipError_t go_typed(const FusedArgs &a, hipStream_t st) {
     return hipGetLastError();
 }
 
-template <int NP, int NB, int PT, int LOSS, bool GRAD>
+template <int NP, int NB, int PT, bool DB, int LOSS, bool GRAD>
 hipError_t go_bf16(const FusedArgs &a, hipStream_t st) {
     const int per_block = 4 * 16 * NB;
     dim3 grid((a.S + per_block - 1) / per_block, a.nchunk);
-    hipLaunchKernelGGL((k_fused_bf16x3<NP, NB, PT, LOSS, GRAD>), grid, dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_fused_bf16x3<NP, NB, PT, DB, LOSS, GRAD>), grid, dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
@@ -499,10 +584,18 @@ hipError_t go_np(Prec prec, int variant, const FusedArgs &a, hipStream_t st) {
         case Prec::BF16X3:
             if constexpr (NP % 32 == 0) {
                 switch (variant) {
-                    case 0: return go_bf16<NP, 2, 64, LOSS, GRAD>(a, st);
-                    case 1: return go_bf16<NP, 1, 64, LOSS, GRAD>(a, st);
-                    case 2: return go_bf16<NP, 2, 32, LOSS, GRAD>(a, st);
-                    case 3: return go_bf16<NP, 1, 32, LOSS, GRAD>(a, st);
+#define COSIM_BF16_CASE(i)                                                               \
+    case i:                                                                              \
+        return go_bf16<NP, kVarBF16[i].nb, kVarBF16[i].pt, kVarBF16[i].db, LOSS, GRAD>(a, st);
+                    COSIM_BF16_CASE(0)
+                    COSIM_BF16_CASE(1)
+                    COSIM_BF16_CASE(2)
+                    COSIM_BF16_CASE(3)
+                    COSIM_BF16_CASE(4)
+                    COSIM_BF16_CASE(5)
+                    COSIM_BF16_CASE(6)
+                    COSIM_BF16_CASE(7)
+#undef COSIM_BF16_CASE
                 }
             }
             break;
