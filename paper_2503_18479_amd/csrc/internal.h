@@ -46,7 +46,9 @@ hipError_t launch_assemble_M(int n, const int32_t *seg_off_d, const double *vert
                              hipStream_t st);
 
 // Record of a factorisation, per system s, in one of two formats (fmt[s]):
-//   kFmtLDL: L[s][k][i] = L_ik (i > k) of Z = L D L^T, piv_val[s][k] = 1/d_k;
+//   kFmtLDL: strictly lower part of Z = L D L^T packed by columns inside the
+//            system's NP*NP slot: L_ik (i > k) at L[s*NP*NP + ldl_col(NP, k) +
+//            i - k - 1]; piv_val[s][k] = 1/d_k;
 //   kFmtGJ : L[s][k][i] = multiplier of Gauss-Jordan step k for row i,
 //            piv_row[s][k] = pivot row, piv_val[s][k] = pivot value.
 struct GJFactor {
@@ -56,6 +58,8 @@ struct GJFactor {
     int *fmt = nullptr;
 };
 constexpr int kFmtLDL = 0, kFmtGJ = 1, kFmtNeedsPivot = 2;
+// first element of column k in the packed LDL^T record (columns of NP - 1 - k)
+__host__ __device__ constexpr int ldl_col(int NP, int k) { return k * (2 * NP - k - 1) / 2; }
 constexpr int kFlagPivot = 1 << 16;  // kernel-internal status bit, never returned
 
 // LDL^T fast path (all R_k > 0): factorises and records; marks systems that

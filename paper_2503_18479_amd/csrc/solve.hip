@@ -27,6 +27,19 @@ __device__ inline double2 cinv(double2 a) {
     const double d = 1.0 / (a.x * a.x + a.y * a.y);
     return make_double2(a.x * d, -a.y * d);
 }
+// 1/a for a pivot known to be a normal, finite number away from zero or
+// flagged afterwards: hardware reciprocal and two Newton steps (relative error
+// at the level of the rounding of the result), no IEEE division sequence.
+__device__ inline double rcp_nr(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return r;
+}
+__device__ inline double2 cinv_nr(double2 a) {
+    const double d = rcp_nr(fma(a.x, a.x, a.y * a.y));
+    return make_double2(a.x * d, -a.y * d);
+}
 
 template <int NP>
 struct GJShape {
@@ -465,7 +478,16 @@ __global__ __launch_bounds__(256) void k_ldl(int n, int S, int F, const double *
     const double *Cb = C + (size_t)b * n;
     const int g = lane >> 4, c16 = lane & 15;
 
-    // ---- Z in accumulator layout: block (bi, bj) at index bi (bi + 1) / 2 + bj
+    // ---- Z in accumulator layout: block (bi, bj) at index bi (bi + 1) / 2 + bj.
+    // Loads use clamped indices and no branches, so they are all in flight at
+    // once; out-of-range entries are replaced by the identity padding.
+    double rdg[NB], cdg[NB];  // R_j, 1/(w C_j) of column j = 16 bj + c16
+#pragma unroll
+    for (int bj = 0; bj < NB; ++bj) {
+        const int j = min(16 * bj + c16, n - 1);
+        rdg[bj] = Rv[j];
+        cdg[bj] = Cb[j];
+    }
     f64x4 Xr[NBLK], Xi[NBLK];
 #pragma unroll
     for (int bi = 0; bi < NB; ++bi)
@@ -475,20 +497,24 @@ __global__ __launch_bounds__(256) void k_ldl(int n, int S, int F, const double *
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
                 const int i = 16 * bi + g + 4 * m, j = 16 * bj + c16;
-                double zr = 0.0, zi = 0.0;
-                if (i < n && j < n) {
-                    zi = w * M[(size_t)i * n + j];
-                    if (i == j) {
-                        zr = Rv[i];
-                        zi -= 1.0 / (w * Cb[i]);
-                    }
-                } else if (i == j) {
-                    zr = 1.0;
-                }
-                Xr[bx][m] = zr;
-                Xi[bx][m] = zi;
+                const double mij = M[(size_t)min(i, n - 1) * n + min(j, n - 1)];
+                Xr[bx][m] = 0.0;
+                Xi[bx][m] = (i < n && j < n) ? w * mij : 0.0;
             }
         }
+#pragma unroll
+    for (int bj = 0; bj < NB; ++bj) {
+        const double xc = 1.0 / (w * cdg[bj]);
+        const int bx = bj * (bj + 1) / 2 + bj;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            if (g + 4 * m == c16) {  // diagonal entry i = j = 16 bj + c16
+                const bool real = 16 * bj + c16 < n;
+                Xr[bx][m] = real ? rdg[bj] : 1.0;
+                Xi[bx][m] = real ? Xi[bx][m] - xc : 0.0;
+            }
+        }
+    }
     // input flags and the largest |re|+|im| diagonal entry (lane k handles k)
     int flag = 0;
     float zdiag = 0.0f;
@@ -536,7 +562,7 @@ __global__ __launch_bounds__(256) void k_ldl(int n, int S, int F, const double *
             for (int c = 0; c < 4; ++c) {
                 const double2 d = d4[c][c];
                 if (c < nc) dmin = fmin(dmin, fabs(d.x) + fabs(d.y));
-                dinv[c] = cinv(d);
+                dinv[c] = cinv_nr(d);
                 double2 l[4];
 #pragma unroll
                 for (int r = c + 1; r < 4; ++r) l[r] = cmul(d4[r][c], dinv[c]);
@@ -547,14 +573,14 @@ __global__ __launch_bounds__(256) void k_ldl(int n, int S, int F, const double *
 #pragma unroll
                 for (int r = c + 1; r < 4; ++r) d4[r][c] = l[r];
             }
+            double2 *Ls = fac.L + (size_t)s * NP * NP;  // packed columns, see ldl_col
             if (lane == 0) {
                 // record D^-1 of the panel and the L11 entries below the diagonal
-                double2 *col = fac.L + ((size_t)s * NP + k0) * NP + k0;
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
                     fac.piv_val[(size_t)s * NP + k0 + c] = dinv[c];
 #pragma unroll
-                    for (int r = c + 1; r < 4; ++r) col[(size_t)c * NP + r] = d4[r][c];
+                    for (int r = c + 1; r < 4; ++r) Ls[ldl_col(NP, k0 + c) + r - c - 1] = d4[r][c];
                 }
             }
             // 3. row lane of V21 and L21 (rows below the diagonal block)
@@ -571,7 +597,7 @@ __global__ __launch_bounds__(256) void k_ldl(int n, int S, int F, const double *
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
                     lrow[c] = cmul(vrow[c], dinv[c]);
-                    fac.L[((size_t)s * NP + k0 + c) * NP + r] = lrow[c];
+                    Ls[ldl_col(NP, k0 + c) + r - (k0 + c) - 1] = lrow[c];
                 }
             }
             if (r < NP) {
@@ -653,13 +679,16 @@ __global__ __launch_bounds__(256) void k_replay(int n, int S, int F, GJFactor fa
     const double2 *__restrict__ Ls = fac.L + (size_t)s * NP * NP;
     constexpr int U = 8;
     if (fmt == kFmtLDL) {
+        // column k of L as lane i sees it: L_ik for k < i < n, else 0
+        auto lcol = [&](int k) {
+            return (lane > k && lane < n) ? Ls[ldl_col(NP, k) + lane - k - 1] : make_double2(0.0, 0.0);
+        };
         // forward: y_i -= L_ik y_k for i > k
         int k0 = 0;
         for (; k0 + U <= n; k0 += U) {
             double2 l[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u)
-                l[u] = (lane > k0 + u && lane < n) ? Ls[(size_t)(k0 + u) * NP + lane] : make_double2(0.0, 0.0);
+            for (int u = 0; u < U; ++u) l[u] = lcol(k0 + u);
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const double2 yk = make_double2(readlane_d(x.x, k0 + u), readlane_d(x.y, k0 + u));
@@ -667,14 +696,27 @@ __global__ __launch_bounds__(256) void k_replay(int n, int S, int F, GJFactor fa
             }
         }
         for (; k0 < n; ++k0) {
-            const double2 l = (lane > k0 && lane < n) ? Ls[(size_t)k0 * NP + lane] : make_double2(0.0, 0.0);
+            const double2 l = lcol(k0);
             const double2 yk = make_double2(readlane_d(x.x, k0), readlane_d(x.y, k0));
             x = cfms(x, l, yk);
         }
         if (lane < n) x = cmul(x, fac.piv_val[(size_t)s * NP + lane]);  // D^-1
-        // backward: x_k = z_k - sum_{i > k} L_ik x_i
-        for (int k = n - 1; k >= 0; --k) {
-            const double2 l = (lane > k && lane < n) ? Ls[(size_t)k * NP + lane] : make_double2(0.0, 0.0);
+        // backward: x_k = z_k - sum_{i > k} L_ik x_i, U columns loaded at a time
+        int k1 = n;  // columns >= k1 are done
+        for (; k1 >= U; k1 -= U) {
+            double2 l[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) l[u] = lcol(k1 - 1 - u);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const double pr = l[u].x * x.x - l[u].y * x.y;
+                const double pi = l[u].x * x.y + l[u].y * x.x;
+                const double sr = wave_sum(pr), si = wave_sum(pi);
+                if (lane == k1 - 1 - u) x = make_double2(x.x - sr, x.y - si);
+            }
+        }
+        for (int k = k1 - 1; k >= 0; --k) {
+            const double2 l = lcol(k);
             const double pr = l.x * x.x - l.y * x.y;
             const double pi = l.x * x.y + l.y * x.x;
             const double sr = wave_sum(pr), si = wave_sum(pi);
