@@ -295,41 +295,18 @@ typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 // {16+4q..16+4q+3} of the second, i.e. pi(8q + j) = (j < 4 ? 4q + j :
 // 16 + 4q + j - 4).  The adjoint A operand G^T[i][pi(8q + j)] is two 8-byte
 // reads of the transposed tile held in LDS next to the row-major one.
-// DB: two LDS buffers, the next tile's global loads in flight in registers
-// while the current tile is computed (one barrier per tile); otherwise one
-// buffer, loaded between two barriers (half the LDS, so more blocks per CU).
-template <int NP, int NB, int PT, bool DB, int LOSS, bool GRAD>
-__global__ __launch_bounds__(256, 2) void k_fused_bf16x3(FusedArgs a) {
-    constexpr int KS = NP / 32;  // forward k-steps of 32
-    constexpr int IB = NP / 16;
-    static_assert(kPTile % PT == 0, "tile rows must divide the 64-row padding of G");
-    constexpr int LDR = NP + 8;  // row-major tile: padded row (bf16 elements)
-    constexpr int LDT = PT + 8;  // transposed tile: padded row
-    constexpr int TSZ = PT * LDR, TTSZ = GRAD ? NP * LDT : 8;
-    constexpr int NBUF = DB ? 2 : 1;
-    __shared__ __attribute__((aligned(16))) uint16_t sH[NBUF][TSZ];
-    __shared__ __attribute__((aligned(16))) uint16_t sL[NBUF][TSZ];
-    __shared__ __attribute__((aligned(16))) uint16_t tH[NBUF][TTSZ];
-    __shared__ __attribute__((aligned(16))) uint16_t tL[NBUF][TTSZ];
-    __shared__ __attribute__((aligned(16))) float sTg[NBUF][PT];
-    static_assert(NP % 32 == 0, "bf16x3 path needs NP multiple of 32");
 
-    const uint16_t *__restrict__ Gh = (const uint16_t *)a.G;
-    const uint16_t *__restrict__ Gl = (const uint16_t *)a.Glo;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int r16 = lane & 15, q = lane >> 4;
-    const int sys0 = (blockIdx.x * 4 + wave) * (16 * NB);
-    const int chunk = blockIdx.y;
-    const int pb = chunk * a.rows_per_chunk;
-    const int pe = min(a.P_pad, pb + a.rows_per_chunk);
-
-    // forward B operand for k-step kk: I[sys][32 kk + 8 q + j], j = 0..7
-    bf16x8 Ih[NB][2][KS], Il[NB][2][KS];  // [b][re/im][kk]
+// I of the wave's 16 NB systems as forward B operands (hi/lo), k-step kk:
+// I[sys][32 kk + 8 q + j], j = 0..7.
+template <int NP, int NB>
+__device__ __forceinline__ void bf3_load_I(const FusedArgs &a, int sys0, int r16, int q,
+                                           bf16x8 (&Ih)[NB][2][NP / 32],
+                                           bf16x8 (&Il)[NB][2][NP / 32]) {
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         const int s = sys0 + 16 * b + r16;
 #pragma unroll
-        for (int kk = 0; kk < KS; ++kk)
+        for (int kk = 0; kk < NP / 32; ++kk)
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 const int k = 32 * kk + 8 * q + j;
@@ -344,179 +321,179 @@ __global__ __launch_bounds__(256, 2) void k_fused_bf16x3(FusedArgs a) {
                 Il[b][1][kk][j] = l;
             }
     }
-    f32x4 racc[IB][NB][2];
-#pragma unroll
-    for (int ib = 0; ib < IB; ++ib)
-#pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            racc[ib][b][0] = f32x4{};
-            racc[ib][b][1] = f32x4{};
-        }
-    double lacc[NB];
-#pragma unroll
-    for (int b = 0; b < NB; ++b) lacc[b] = 0.0;
+}
 
-    // tile staging: each thread moves VPT 16-byte vectors per part
-    constexpr int NV = PT * NP / 8;
+// One PT-row tile of G (hi/lo, row-major with padded rows), of G^T (hi/lo,
+// PT columns) and of T, moved global -> registers (fetch) -> LDS (stash) in
+// 16-byte vectors by the 256 threads of the block.
+template <int NP, int PT, bool GRAD>
+struct Bf3Stage {
+    static constexpr int NV = PT * NP / 8;
     static_assert(NV % 64 == 0, "tile must split evenly over whole waves");
-    constexpr int VPT = (NV + 255) / 256;
-    u32x4 rgh[VPT], rgl[VPT], rth[VPT], rtl[VPT];
-    float rT = 0.0f;
-    auto fetch = [&](int p0) __attribute__((always_inline)) {
+    static constexpr int VPT = (NV + 255) / 256;
+    static constexpr int LDR = NP + 8, LDT = PT + 8;
+    u32x4 gh[VPT], gl[VPT], th[VPT], tl[VPT];
+    float t = 0.0f;
+
+    __device__ __forceinline__ void fetch(const FusedArgs &a, int p0) {
+        const uint16_t *__restrict__ Gh = (const uint16_t *)a.G;
+        const uint16_t *__restrict__ Gl = (const uint16_t *)a.Glo;
 #pragma unroll
         for (int u = 0; u < VPT; ++u) {
             const int e0 = (threadIdx.x + 256 * u) * 8;
             if (NV % 256 != 0 && e0 >= 8 * NV) continue;
             const int row = e0 / NP, col = e0 - row * NP;
             const size_t go = (size_t)(p0 + row) * NP + col;
-            rgh[u] = *(const u32x4 *)(Gh + go);
-            rgl[u] = *(const u32x4 *)(Gl + go);
+            gh[u] = *(const u32x4 *)(Gh + go);
+            gl[u] = *(const u32x4 *)(Gl + go);
             if (GRAD) {
                 const int trow = e0 / PT, tcol = e0 - trow * PT;  // trow = loop index i
                 const size_t to = (size_t)trow * a.P_pad + p0 + tcol;
-                rth[u] = *(const u32x4 *)(a.GThi + to);
-                rtl[u] = *(const u32x4 *)(a.GTlo + to);
+                th[u] = *(const u32x4 *)(a.GThi + to);
+                tl[u] = *(const u32x4 *)(a.GTlo + to);
             }
         }
         if (threadIdx.x < PT) {
             const int p = p0 + threadIdx.x;
-            rT = p < a.P ? (float)a.T[p] : 0.0f;
+            t = p < a.P ? (float)a.T[p] : 0.0f;
         }
-    };
-    auto stash = [&](int buf) __attribute__((always_inline)) {
+    }
+    __device__ __forceinline__ void stash(uint16_t *sH, uint16_t *sL, uint16_t *tH, uint16_t *tL,
+                                          float *sT) const {
 #pragma unroll
         for (int u = 0; u < VPT; ++u) {
             const int e0 = (threadIdx.x + 256 * u) * 8;
             if (NV % 256 != 0 && e0 >= 8 * NV) continue;
             const int row = e0 / NP, col = e0 - row * NP;
-            *(u32x4 *)(&sH[buf][row * LDR + col]) = rgh[u];
-            *(u32x4 *)(&sL[buf][row * LDR + col]) = rgl[u];
+            *(u32x4 *)(sH + row * LDR + col) = gh[u];
+            *(u32x4 *)(sL + row * LDR + col) = gl[u];
             if (GRAD) {
                 const int trow = e0 / PT, tcol = e0 - trow * PT;
-                *(u32x4 *)(&tH[buf][trow * LDT + tcol]) = rth[u];
-                *(u32x4 *)(&tL[buf][trow * LDT + tcol]) = rtl[u];
+                *(u32x4 *)(tH + trow * LDT + tcol) = th[u];
+                *(u32x4 *)(tL + trow * LDT + tcol) = tl[u];
             }
         }
-        if (threadIdx.x < PT) sTg[buf][threadIdx.x] = rT;
-    };
-
-    if (DB) {
-        if (pb < pe) {
-            fetch(pb);
-            stash(0);
-        }
-        __syncthreads();
+        if (threadIdx.x < PT) sT[threadIdx.x] = t;
     }
-    int cur = 0;
-    for (int p0 = pb; p0 < pe; p0 += PT, cur ^= (DB ? 1 : 0)) {
-        const bool more = p0 + PT < pe;
-        if (DB) {
-            if (more) fetch(p0 + PT);  // loads in flight during the compute below
-        } else {
-            if (p0 != pb) __syncthreads();  // every wave is done with the previous tile
-            fetch(p0);
-            stash(0);
-            __syncthreads();
+};
+
+// Forward: B = G I for the 32 rows starting at row0 of the LDS tile, 16x16
+// accumulators per 16-row half h and system group b.
+template <int NP, int NB>
+__device__ __forceinline__ void bf3_forward(const uint16_t *__restrict__ cH,
+                                            const uint16_t *__restrict__ cL, int row0, int r16,
+                                            int q, const bf16x8 (&Ih)[NB][2][NP / 32],
+                                            const bf16x8 (&Il)[NB][2][NP / 32],
+                                            f32x4 (&br)[2][NB], f32x4 (&bi)[2][NB]) {
+    constexpr int KS = NP / 32, LDR = NP + 8;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int row = row0 + 16 * h + r16;
+        bf16x8 ah[KS], al[KS];
+#pragma unroll
+        for (int kk = 0; kk < KS; ++kk) {
+            ah[kk] = *(const bf16x8 *)(cH + row * LDR + 32 * kk + 8 * q);
+            al[kk] = *(const bf16x8 *)(cL + row * LDR + 32 * kk + 8 * q);
         }
-        const uint16_t *__restrict__ cH = sH[cur];
-        const uint16_t *__restrict__ cL = sL[cur];
-        const uint16_t *__restrict__ ctH = tH[cur];
-        const uint16_t *__restrict__ ctL = tL[cur];
-        const float *__restrict__ sT = sTg[cur];
-#pragma unroll 1
-        for (int sp = 0; sp < PT / 32; ++sp) {
-            f32x4 br[2][NB], bi[2][NB];  // [16-row half][b]
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int row = 32 * sp + 16 * h + r16;
-                bf16x8 ah[KS], al[KS];
+        for (int b = 0; b < NB; ++b) {
+            f32x4 xr = f32x4{}, xi = f32x4{};
 #pragma unroll
-                for (int kk = 0; kk < KS; ++kk) {
-                    ah[kk] = *(const bf16x8 *)(cH + row * LDR + 32 * kk + 8 * q);
-                    al[kk] = *(const bf16x8 *)(cL + row * LDR + 32 * kk + 8 * q);
-                }
-#pragma unroll
-                for (int b = 0; b < NB; ++b) {
-                    f32x4 xr = f32x4{}, xi = f32x4{};
-#pragma unroll
-                    for (int kk = 0; kk < KS; ++kk) {
-                        xr = mma_bf16(al[kk], Ih[b][0][kk], xr);
-                        xr = mma_bf16(ah[kk], Il[b][0][kk], xr);
-                        xr = mma_bf16(ah[kk], Ih[b][0][kk], xr);
-                        xi = mma_bf16(al[kk], Ih[b][1][kk], xi);
-                        xi = mma_bf16(ah[kk], Il[b][1][kk], xi);
-                        xi = mma_bf16(ah[kk], Ih[b][1][kk], xi);
-                    }
-                    br[h][b] = xr;
-                    bi[h][b] = xi;
-                }
+            for (int kk = 0; kk < KS; ++kk) {
+                xr = mma_bf16(al[kk], Ih[b][0][kk], xr);
+                xr = mma_bf16(ah[kk], Il[b][0][kk], xr);
+                xr = mma_bf16(ah[kk], Ih[b][0][kk], xr);
+                xi = mma_bf16(al[kk], Ih[b][1][kk], xi);
+                xi = mma_bf16(ah[kk], Il[b][1][kk], xi);
+                xi = mma_bf16(ah[kk], Ih[b][1][kk], xi);
             }
-            // epilogue on both halves, then w as bf16 hi/lo operands
-            u32x4 rh[NB], rl[NB], ih[NB], il[NB];  // packed pairs of rows
-            float lsub[NB];
-#pragma unroll
-            for (int b = 0; b < NB; ++b) lsub[b] = 0.0f;
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const f32x4 t4 = *(const f32x4 *)(sT + 32 * sp + 16 * h + 4 * q);
-#pragma unroll
-                for (int b = 0; b < NB; ++b) {
-                    f32x4 x = br[h][b], y = bi[h][b];
-#pragma unroll
-                    for (int m = 0; m < 4; ++m) {
-                        float xm = x[m], ym = y[m];
-                        lsub[b] += epilogue_f<LOSS>(xm, ym, t4[m]);
-                        x[m] = xm;
-                        y[m] = ym;
-                    }
-#pragma unroll
-                    for (int mp = 0; mp < 2; ++mp) {
-                        unsigned hh, ll;
-                        split2_pair(x[2 * mp], x[2 * mp + 1], hh, ll);
-                        rh[b][2 * h + mp] = hh;
-                        rl[b][2 * h + mp] = ll;
-                        split2_pair(y[2 * mp], y[2 * mp + 1], hh, ll);
-                        ih[b][2 * h + mp] = hh;
-                        il[b][2 * h + mp] = ll;
-                    }
-                }
-            }
-            bf16x8 wrh[NB], wrl[NB], wih[NB], wil[NB];
-#pragma unroll
-            for (int b = 0; b < NB; ++b) {
-                lacc[b] += (double)lsub[b];
-                wrh[b] = __builtin_bit_cast(bf16x8, rh[b]);
-                wrl[b] = __builtin_bit_cast(bf16x8, rl[b]);
-                wih[b] = __builtin_bit_cast(bf16x8, ih[b]);
-                wil[b] = __builtin_bit_cast(bf16x8, il[b]);
-            }
-            if (GRAD) {
-#pragma unroll
-                for (int ib = 0; ib < IB; ++ib) {
-                    // A operand: Gt[i = 16 ib + r16][p = pi(8q + j)]
-                    const int base = (16 * ib + r16) * LDT + 32 * sp + 4 * q;
-                    const s16x4 h0 = *(const s16x4 *)(ctH + base), h1 = *(const s16x4 *)(ctH + base + 16);
-                    const s16x4 l0 = *(const s16x4 *)(ctL + base), l1 = *(const s16x4 *)(ctL + base + 16);
-                    const bf16x8 th = __builtin_bit_cast(bf16x8, __builtin_shufflevector(h0, h1, 0, 1, 2, 3, 4, 5, 6, 7));
-                    const bf16x8 tl = __builtin_bit_cast(bf16x8, __builtin_shufflevector(l0, l1, 0, 1, 2, 3, 4, 5, 6, 7));
-#pragma unroll
-                    for (int b = 0; b < NB; ++b) {
-                        racc[ib][b][0] = mma_bf16(tl, wrh[b], racc[ib][b][0]);
-                        racc[ib][b][0] = mma_bf16(th, wrl[b], racc[ib][b][0]);
-                        racc[ib][b][0] = mma_bf16(th, wrh[b], racc[ib][b][0]);
-                        racc[ib][b][1] = mma_bf16(tl, wih[b], racc[ib][b][1]);
-                        racc[ib][b][1] = mma_bf16(th, wil[b], racc[ib][b][1]);
-                        racc[ib][b][1] = mma_bf16(th, wih[b], racc[ib][b][1]);
-                    }
-                }
-            }
-        }
-        if (DB) {
-            if (more) stash(cur ^ 1);
-            __syncthreads();
+            br[h][b] = xr;
+            bi[h][b] = xi;
         }
     }
+}
 
+// Loss of the 32 rows starting at row0 (accumulated into lacc) and
+// w = dL/d conj(B) as packed bf16 hi/lo adjoint B operands.
+template <int NB, int LOSS>
+__device__ __forceinline__ void bf3_epilogue(const float *__restrict__ sT, int row0, int q,
+                                             const f32x4 (&br)[2][NB], const f32x4 (&bi)[2][NB],
+                                             bf16x8 (&wrh)[NB], bf16x8 (&wrl)[NB],
+                                             bf16x8 (&wih)[NB], bf16x8 (&wil)[NB],
+                                             double (&lacc)[NB]) {
+    u32x4 rh[NB], rl[NB], ih[NB], il[NB];  // packed pairs of rows
+    float lsub[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) lsub[b] = 0.0f;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const f32x4 t4 = *(const f32x4 *)(sT + row0 + 16 * h + 4 * q);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            f32x4 x = br[h][b], y = bi[h][b];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                float xm = x[m], ym = y[m];
+                lsub[b] += epilogue_f<LOSS>(xm, ym, t4[m]);
+                x[m] = xm;
+                y[m] = ym;
+            }
+#pragma unroll
+            for (int mp = 0; mp < 2; ++mp) {
+                unsigned hh, ll;
+                split2_pair(x[2 * mp], x[2 * mp + 1], hh, ll);
+                rh[b][2 * h + mp] = hh;
+                rl[b][2 * h + mp] = ll;
+                split2_pair(y[2 * mp], y[2 * mp + 1], hh, ll);
+                ih[b][2 * h + mp] = hh;
+                il[b][2 * h + mp] = ll;
+            }
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        lacc[b] += (double)lsub[b];
+        wrh[b] = __builtin_bit_cast(bf16x8, rh[b]);
+        wrl[b] = __builtin_bit_cast(bf16x8, rl[b]);
+        wih[b] = __builtin_bit_cast(bf16x8, ih[b]);
+        wil[b] = __builtin_bit_cast(bf16x8, il[b]);
+    }
+}
+
+// Adjoint: racc += G^T w over the 32 rows starting at column col0 of the
+// transposed LDS tile (row stride LDT).
+template <int NP, int NB, int LDT>
+__device__ __forceinline__ void bf3_adjoint(const uint16_t *__restrict__ ctH,
+                                            const uint16_t *__restrict__ ctL, int col0, int r16,
+                                            int q, const bf16x8 (&wrh)[NB],
+                                            const bf16x8 (&wrl)[NB], const bf16x8 (&wih)[NB],
+                                            const bf16x8 (&wil)[NB],
+                                            f32x4 (&racc)[NP / 16][NB][2]) {
+#pragma unroll
+    for (int ib = 0; ib < NP / 16; ++ib) {
+        // A operand: Gt[i = 16 ib + r16][p = pi(8q + j)]
+        const int base = (16 * ib + r16) * LDT + col0 + 4 * q;
+        const s16x4 h0 = *(const s16x4 *)(ctH + base), h1 = *(const s16x4 *)(ctH + base + 16);
+        const s16x4 l0 = *(const s16x4 *)(ctL + base), l1 = *(const s16x4 *)(ctL + base + 16);
+        const bf16x8 th = __builtin_bit_cast(bf16x8, __builtin_shufflevector(h0, h1, 0, 1, 2, 3, 4, 5, 6, 7));
+        const bf16x8 tl = __builtin_bit_cast(bf16x8, __builtin_shufflevector(l0, l1, 0, 1, 2, 3, 4, 5, 6, 7));
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            racc[ib][b][0] = mma_bf16(tl, wrh[b], racc[ib][b][0]);
+            racc[ib][b][0] = mma_bf16(th, wrl[b], racc[ib][b][0]);
+            racc[ib][b][0] = mma_bf16(th, wrh[b], racc[ib][b][0]);
+            racc[ib][b][1] = mma_bf16(tl, wih[b], racc[ib][b][1]);
+            racc[ib][b][1] = mma_bf16(th, wil[b], racc[ib][b][1]);
+            racc[ib][b][1] = mma_bf16(th, wih[b], racc[ib][b][1]);
+        }
+    }
+}
+
+// Per-chunk partial loss and adjoint right-hand side of the wave's systems.
+template <int NP, int NB, bool GRAD>
+__device__ __forceinline__ void bf3_store(const FusedArgs &a, int chunk, int sys0, int r16, int q,
+                                          const double (&lacc)[NB],
+                                          const f32x4 (&racc)[NP / 16][NB][2]) {
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         const int s = sys0 + 16 * b + r16;
@@ -528,7 +505,7 @@ __global__ __launch_bounds__(256, 2) void k_fused_bf16x3(FusedArgs a) {
             if (GRAD) {
                 double2 *dst = a.rpart + ((size_t)chunk * a.S + s) * NP;
 #pragma unroll
-                for (int ib = 0; ib < IB; ++ib)
+                for (int ib = 0; ib < NP / 16; ++ib)
 #pragma unroll
                     for (int m = 0; m < 4; ++m)
                         dst[16 * ib + 4 * q + m] = make_double2((double)racc[ib][b][0][m],
@@ -538,17 +515,166 @@ __global__ __launch_bounds__(256, 2) void k_fused_bf16x3(FusedArgs a) {
     }
 }
 
+// Sub-tile by sub-tile: forward, epilogue, adjoint.
+// DB: two LDS buffers, the next tile's global loads in flight in registers
+// while the current tile is computed (one barrier per tile); otherwise one
+// buffer, loaded between two barriers (half the LDS, so more blocks per CU).
+template <int NP, int NB, int PT, bool DB, int LOSS, bool GRAD>
+__global__ __launch_bounds__(256, 2) void k_fused_bf16x3(FusedArgs a) {
+    static_assert(NP % 32 == 0, "bf16x3 path needs NP multiple of 32");
+    static_assert(kPTile % PT == 0, "tile rows must divide the 64-row padding of G");
+    constexpr int IB = NP / 16;
+    constexpr int LDR = NP + 8, LDT = PT + 8;
+    constexpr int TSZ = PT * LDR, TTSZ = GRAD ? NP * LDT : 8;
+    constexpr int NBUF = DB ? 2 : 1;
+    __shared__ __attribute__((aligned(16))) uint16_t sH[NBUF][TSZ];
+    __shared__ __attribute__((aligned(16))) uint16_t sL[NBUF][TSZ];
+    __shared__ __attribute__((aligned(16))) uint16_t tH[NBUF][TTSZ];
+    __shared__ __attribute__((aligned(16))) uint16_t tL[NBUF][TTSZ];
+    __shared__ __attribute__((aligned(16))) float sTg[NBUF][PT];
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r16 = lane & 15, q = lane >> 4;
+    const int sys0 = (blockIdx.x * 4 + wave) * (16 * NB);
+    const int chunk = blockIdx.y;
+    const int pb = chunk * a.rows_per_chunk;
+    const int pe = min(a.P_pad, pb + a.rows_per_chunk);
+
+    bf16x8 Ih[NB][2][NP / 32], Il[NB][2][NP / 32];
+    bf3_load_I<NP, NB>(a, sys0, r16, q, Ih, Il);
+    f32x4 racc[IB][NB][2];
+#pragma unroll
+    for (int ib = 0; ib < IB; ++ib)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) racc[ib][b][0] = racc[ib][b][1] = f32x4{};
+    double lacc[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) lacc[b] = 0.0;
+
+    Bf3Stage<NP, PT, GRAD> stg;
+    if (DB) {
+        if (pb < pe) {
+            stg.fetch(a, pb);
+            stg.stash(sH[0], sL[0], tH[0], tL[0], sTg[0]);
+        }
+        __syncthreads();
+    }
+    int cur = 0;
+    for (int p0 = pb; p0 < pe; p0 += PT, cur ^= (DB ? 1 : 0)) {
+        const bool more = p0 + PT < pe;
+        if (DB) {
+            if (more) stg.fetch(a, p0 + PT);  // loads in flight during the compute below
+        } else {
+            if (p0 != pb) __syncthreads();  // every wave is done with the previous tile
+            stg.fetch(a, p0);
+            stg.stash(sH[0], sL[0], tH[0], tL[0], sTg[0]);
+            __syncthreads();
+        }
+#pragma unroll 1
+        for (int sp = 0; sp < PT / 32; ++sp) {
+            f32x4 br[2][NB], bi[2][NB];
+            bf3_forward<NP, NB>(sH[cur], sL[cur], 32 * sp, r16, q, Ih, Il, br, bi);
+            bf16x8 wrh[NB], wrl[NB], wih[NB], wil[NB];
+            bf3_epilogue<NB, LOSS>(sTg[cur], 32 * sp, q, br, bi, wrh, wrl, wih, wil, lacc);
+            if (GRAD) bf3_adjoint<NP, NB, LDT>(tH[cur], tL[cur], 32 * sp, r16, q, wrh, wrl, wih, wil, racc);
+        }
+        if (DB) {
+            if (more) stg.stash(sH[cur ^ 1], sL[cur ^ 1], tH[cur ^ 1], tL[cur ^ 1], sTg[cur ^ 1]);
+            __syncthreads();
+        }
+    }
+    bf3_store<NP, NB, GRAD>(a, chunk, sys0, r16, q, lacc, racc);
+}
+
+// Software-pipelined form: the forward MFMAs of sub-tile j+1 are issued in the
+// same basic block as the epilogue (VALU) of sub-tile j, so the matrix cores
+// and the vector ALUs of a wave work side by side; the adjoint of sub-tile j
+// follows.  Tiles are double-buffered; crossing into tile t+1 costs two
+// barriers (every wave done with the buffer tile t-1 used, then tile t+1
+// visible), and tile t+2 is fetched into registers right after.  The last
+// iteration's look-ahead forward reads a stale buffer and is discarded.
+template <int NP, int NB, int PT, int LOSS, bool GRAD>
+__global__ __launch_bounds__(256, 2) void k_fused_bf16x3_pipe(FusedArgs a) {
+    static_assert(NP % 32 == 0, "bf16x3 path needs NP multiple of 32");
+    static_assert(kPTile % PT == 0, "tile rows must divide the 64-row padding of G");
+    constexpr int IB = NP / 16;
+    constexpr int LDR = NP + 8, LDT = PT + 8;
+    constexpr int TSZ = PT * LDR, TTSZ = GRAD ? NP * LDT : 8;
+    constexpr int SPT = PT / 32;  // sub-tiles per tile
+    __shared__ __attribute__((aligned(16))) uint16_t sH[2][TSZ];
+    __shared__ __attribute__((aligned(16))) uint16_t sL[2][TSZ];
+    __shared__ __attribute__((aligned(16))) uint16_t tH[2][TTSZ];
+    __shared__ __attribute__((aligned(16))) uint16_t tL[2][TTSZ];
+    __shared__ __attribute__((aligned(16))) float sTg[2][PT];
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r16 = lane & 15, q = lane >> 4;
+    const int sys0 = (blockIdx.x * 4 + wave) * (16 * NB);
+    const int chunk = blockIdx.y;
+    const int pb = chunk * a.rows_per_chunk;
+    const int pe = min(a.P_pad, pb + a.rows_per_chunk);
+    const int ntile = pe > pb ? (pe - pb) / PT : 0;
+
+    bf16x8 Ih[NB][2][NP / 32], Il[NB][2][NP / 32];
+    bf3_load_I<NP, NB>(a, sys0, r16, q, Ih, Il);
+    f32x4 racc[IB][NB][2];
+#pragma unroll
+    for (int ib = 0; ib < IB; ++ib)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) racc[ib][b][0] = racc[ib][b][1] = f32x4{};
+    double lacc[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) lacc[b] = 0.0;
+
+    if (ntile > 0) {
+        Bf3Stage<NP, PT, GRAD> stg;
+        stg.fetch(a, pb);
+        stg.stash(sH[0], sL[0], tH[0], tL[0], sTg[0]);
+        __syncthreads();
+        if (ntile > 1) stg.fetch(a, pb + PT);
+        f32x4 br[2][NB], bi[2][NB];
+        bf3_forward<NP, NB>(sH[0], sL[0], 0, r16, q, Ih, Il, br, bi);
+        const int nsub = ntile * SPT;
+#pragma unroll 1
+        for (int j = 0; j < nsub; ++j) {
+            const int t = j / SPT, s = j - t * SPT;
+            const int t1 = (j + 1) / SPT, s1 = (j + 1) - t1 * SPT;
+            if (s1 == 0 && t1 < ntile) {  // uniform over the block
+                __syncthreads();
+                stg.stash(sH[t1 & 1], sL[t1 & 1], tH[t1 & 1], tL[t1 & 1], sTg[t1 & 1]);
+                __syncthreads();
+                if (t1 + 1 < ntile) stg.fetch(a, pb + (t1 + 1) * PT);
+            }
+            f32x4 brn[2][NB], bin[2][NB];
+            bf3_forward<NP, NB>(sH[t1 & 1], sL[t1 & 1], 32 * s1, r16, q, Ih, Il, brn, bin);
+            bf16x8 wrh[NB], wrl[NB], wih[NB], wil[NB];
+            bf3_epilogue<NB, LOSS>(sTg[t & 1], 32 * s, q, br, bi, wrh, wrl, wih, wil, lacc);
+            if (GRAD) bf3_adjoint<NP, NB, LDT>(tH[t & 1], tL[t & 1], 32 * s, r16, q, wrh, wrl, wih, wil, racc);
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    br[h][b] = brn[h][b];
+                    bi[h][b] = bin[h][b];
+                }
+        }
+    }
+    bf3_store<NP, NB, GRAD>(a, chunk, sys0, r16, q, lacc, racc);
+}
+
 // Tuning variants of the fused kernels: systems per wave (16 * NB), rows per
 // LDS tile (PT) and, for BF16X3, single or double LDS buffering.  Variant 0 is
 // the default; cosim_plan_autotune picks per plan and precision.
 struct Variant {
     int nb, pt;
-    bool db;
+    bool db, pipe;
 };
-constexpr Variant kVarF64[] = {{1, 64, false}, {2, 64, false}};
-constexpr Variant kVarF32[] = {{2, 64, false}, {1, 64, false}};
-constexpr Variant kVarBF16[] = {{2, 64, false}, {1, 64, false}, {2, 32, false}, {1, 32, false},
-                                {2, 64, true},  {1, 64, true},  {2, 32, true},  {1, 32, true}};
+constexpr Variant kVarF64[] = {{1, 64, false, false}, {2, 64, false, false}};
+constexpr Variant kVarF32[] = {{2, 64, false, false}, {1, 64, false, false}};
+constexpr Variant kVarBF16[] = {{2, 64, false, false}, {2, 32, false, false}, {1, 64, false, false},
+                                {1, 32, false, false}, {2, 64, true, false},  {2, 32, true, false},
+                                {1, 64, true, true},   {1, 32, true, true},   {2, 32, true, true},
+                                {2, 64, true, true}};
 
 template <typename T, int NP, int NB, int LOSS, bool GRAD>
 hipError_t go_typed(const FusedArgs &a, hipStream_t st) {
@@ -558,11 +684,14 @@ hipError_t go_typed(const FusedArgs &a, hipStream_t st) {
     return hipGetLastError();
 }
 
-template <int NP, int NB, int PT, bool DB, int LOSS, bool GRAD>
+template <int NP, int NB, int PT, bool DB, bool PIPE, int LOSS, bool GRAD>
 hipError_t go_bf16(const FusedArgs &a, hipStream_t st) {
     const int per_block = 4 * 16 * NB;
     dim3 grid((a.S + per_block - 1) / per_block, a.nchunk);
-    hipLaunchKernelGGL((k_fused_bf16x3<NP, NB, PT, DB, LOSS, GRAD>), grid, dim3(256), 0, st, a);
+    if constexpr (PIPE)
+        hipLaunchKernelGGL((k_fused_bf16x3_pipe<NP, NB, PT, LOSS, GRAD>), grid, dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_fused_bf16x3<NP, NB, PT, DB, LOSS, GRAD>), grid, dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
@@ -586,7 +715,8 @@ hipError_t go_np(Prec prec, int variant, const FusedArgs &a, hipStream_t st) {
                 switch (variant) {
 #define COSIM_BF16_CASE(i)                                                               \
     case i:                                                                              \
-        return go_bf16<NP, kVarBF16[i].nb, kVarBF16[i].pt, kVarBF16[i].db, LOSS, GRAD>(a, st);
+        return go_bf16<NP, kVarBF16[i].nb, kVarBF16[i].pt, kVarBF16[i].db, kVarBF16[i].pipe, \
+                       LOSS, GRAD>(a, st);
                     COSIM_BF16_CASE(0)
                     COSIM_BF16_CASE(1)
                     COSIM_BF16_CASE(2)
@@ -595,6 +725,8 @@ hipError_t go_np(Prec prec, int variant, const FusedArgs &a, hipStream_t st) {
                     COSIM_BF16_CASE(5)
                     COSIM_BF16_CASE(6)
                     COSIM_BF16_CASE(7)
+                    COSIM_BF16_CASE(8)
+                    COSIM_BF16_CASE(9)
 #undef COSIM_BF16_CASE
                 }
             }

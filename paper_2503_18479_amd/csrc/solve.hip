@@ -440,6 +440,41 @@ __device__ inline double wave_sum(double v) {
     return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
 }
 
+template <int CTRL>
+__device__ inline double dpp_d(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(__double2loint(v), __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(__double2hiint(v), __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+// One butterfly stage of a transposed reduction: lanes with `upper` keep the
+// upper half of their values and send the lower half to the DPP partner,
+// which does the opposite; each keeps the pair sum of its half.
+template <int CTRL, int N>
+__device__ inline void halve(const double (&v)[2 * N], double (&w)[N], bool upper) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        const double send = upper ? v[j] : v[j + N];
+        const double keep = upper ? v[j + N] : v[j];
+        w[j] = keep + dpp_d<CTRL>(send);
+    }
+}
+// Sixteen wave sums at once: returns, in lane l, the sum over all 64 lanes
+// of v[l & 15].  Within each row of 16 lanes the partners are 15 - i
+// (row_mirror), the mirror inside each half row, then i ^ 2 and i ^ 1, so
+// lane i keeps value index i; the four row results are then added across
+// rows (lane ^ 16, lane ^ 32).
+__device__ inline double wave_sum16(const double (&v)[16], int lane) {
+    double w8[8], w4[4], w2[2], w1[1];
+    halve<0x140, 8>(v, w8, (lane & 8) != 0);
+    halve<0x141, 4>(w8, w4, (lane & 4) != 0);
+    halve<0x4E, 2>(w4, w2, (lane & 2) != 0);
+    halve<0xB1, 1>(w2, w1, (lane & 1) != 0);
+    double t = w1[0];
+    t += __shfl_xor(t, 16);
+    t += __shfl_xor(t, 32);
+    return t;
+}
+
 // Complex-symmetric LDL^T factorisation without pivoting, Z = L D L^T.
 // The Hermitian part of Z is diag(R) (j w M and 1/(j w C) are skew-Hermitian),
 // so with every R_k > 0 each Schur complement keeps a positive-definite real
@@ -655,6 +690,7 @@ __global__ __launch_bounds__(256) void k_replay(int n, int S, int F, GJFactor fa
                                                 const double2 *__restrict__ rpart, int nchunk,
                                                 double rscale, double *__restrict__ gsys,
                                                 int32_t *__restrict__ status) {
+    __shared__ double2 sTr[4][64];  // per wave: an 8x8 block of L, transposed
     const int lane = threadIdx.x & 63;
     const int s = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
     if (s >= S) return;  // whole wave; no block-level synchronisation below
@@ -683,17 +719,26 @@ __global__ __launch_bounds__(256) void k_replay(int n, int S, int F, GJFactor fa
         auto lcol = [&](int k) {
             return (lane > k && lane < n) ? Ls[ldl_col(NP, k) + lane - k - 1] : make_double2(0.0, 0.0);
         };
-        // forward: y_i -= L_ik y_k for i > k
-        int k0 = 0;
-        for (; k0 + U <= n; k0 += U) {
-            double2 l[U];
+        // Columns are loaded in groups of U; the next group's loads are in
+        // flight while the current group is applied (cur / nxt registers).
+        double2 cur[U], nxt[U];
+        auto load_group = [&](double2(&l)[U], int k0) {
 #pragma unroll
             for (int u = 0; u < U; ++u) l[u] = lcol(k0 + u);
+        };
+        // forward: y_i -= L_ik y_k for i > k
+        const int nfg = n / U;  // full groups
+        if (nfg > 0) load_group(cur, 0);
+        int k0 = 0;
+        for (; k0 + U <= n; k0 += U) {
+            if (k0 + 2 * U <= n) load_group(nxt, k0 + U);
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const double2 yk = make_double2(readlane_d(x.x, k0 + u), readlane_d(x.y, k0 + u));
-                x = cfms(x, l[u], yk);
+                x = cfms(x, cur[u], yk);
             }
+#pragma unroll
+            for (int u = 0; u < U; ++u) cur[u] = nxt[u];
         }
         for (; k0 < n; ++k0) {
             const double2 l = lcol(k0);
@@ -701,18 +746,52 @@ __global__ __launch_bounds__(256) void k_replay(int n, int S, int F, GJFactor fa
             x = cfms(x, l, yk);
         }
         if (lane < n) x = cmul(x, fac.piv_val[(size_t)s * NP + lane]);  // D^-1
-        // backward: x_k = z_k - sum_{i > k} L_ik x_i, U columns loaded at a time
+        // backward: x_k = z_k - sum_{i > k} L_ik x_i, in blocks of U = 8
+        // columns [k0, k1) from the bottom.  The terms with i >= k1 (x_i final)
+        // of all 8 columns are summed by one 16-value reduction; the terms
+        // inside the block use L's 8x8 diagonal block, transposed through LDS
+        // so that lane k0 + u holds row entries L_{k0+ii, k0+u}, and x_{k0+ii}
+        // broadcast from its lane as soon as it is final.
+        static_assert(U == 8, "the block reduction handles 8 complex columns");
+        double2 *tr = sTr[threadIdx.x >> 6];
         int k1 = n;  // columns >= k1 are done
+        if (n >= U) load_group(cur, n - U);
         for (; k1 >= U; k1 -= U) {
+            const int k0 = k1 - U;
+            const int ub = (lane - k0) & (U - 1);  // column of the block lane k0 + ub owns
+            if (k0 >= U) load_group(nxt, k0 - U);
             double2 l[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) l[u] = lcol(k1 - 1 - u);
+            for (int u = 0; u < U; ++u) {
+                l[u] = cur[u];
+                cur[u] = nxt[u];
+            }
+            const bool ext = lane >= k1;
+            double v[2 * U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const double pr = l[u].x * x.x - l[u].y * x.y;
-                const double pi = l[u].x * x.y + l[u].y * x.x;
-                const double sr = wave_sum(pr), si = wave_sum(pi);
-                if (lane == k1 - 1 - u) x = make_double2(x.x - sr, x.y - si);
+                v[2 * u] = ext ? l[u].x * x.x - l[u].y * x.y : 0.0;
+                v[2 * u + 1] = ext ? l[u].x * x.y + l[u].y * x.x : 0.0;
+            }
+            const double tot = wave_sum16(v, lane);
+            const bool blk = lane >= k0 && lane < k1;
+            const double er = __shfl(tot, 2 * ub), ei = __shfl(tot, 2 * ub + 1);
+            if (blk) {
+                x = make_double2(x.x - er, x.y - ei);
+#pragma unroll
+                for (int u = 0; u < U; ++u) tr[ub * U + u] = l[u];
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            double2 t[U];
+#pragma unroll
+            for (int ii = 1; ii < U; ++ii) t[ii] = blk ? tr[ii * U + ub] : make_double2(0.0, 0.0);
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int ii = U - 1; ii >= 1; --ii) {
+                const double2 xk = make_double2(readlane_d(x.x, k0 + ii), readlane_d(x.y, k0 + ii));
+                x = cfms(x, t[ii], xk);  // t[ii] = 0 unless lane < k0 + ii in the block
             }
         }
         for (int k = k1 - 1; k >= 0; --k) {
