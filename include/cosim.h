@@ -168,10 +168,34 @@ int cosim_field_backward(cosim_plan_t p, int B, int F, const double *C_d, const 
  * B_z is formed in registers tile by tile and never written to memory; the
  * adjoint contraction G^T conj(w) shares each G tile with the forward
  * product.  Solves and reductions are FP64; `precision` selects the matrix
- * core arithmetic of the two contractions.  Deterministic: no atomics. */
+ * core arithmetic of the two contractions.  Deterministic: no atomics.
+ * Once the workspace covers B*F systems (cosim_plan_reserve, or an earlier
+ * call of that size) the call only enqueues kernels on `stream`: no
+ * allocation, memset, copy or synchronisation, so it can be captured in a HIP
+ * graph (phase timing, when switched on, adds event records). */
 int cosim_loss_and_grad(cosim_plan_t p, int B, int F, const double *C_d, const double *omega_d,
                         const double *T_d, int loss_mode, int precision, double *loss_d,
                         double *grad_d, int32_t *status_d, void *stream);
+
+/* One Adam step on the capacitances, the optimiser the paper runs on C
+ * (Sec. IV; learning rate 1e-13 F there), with the bias-corrected moments of
+ * Kingma & Ba: with t the 1-based step and g = dL/dC,
+ *   m <- b1 m + (1 - b1) g,   v <- b2 v + (1 - b2) g^2,
+ *   C <- C - (lr / (1 - b1^t)) m / (sqrt(v) / sqrt(1 - b2^t) + eps).
+ *   count    number of elements (B*n for a batch of configurations); 0 is a no-op
+ *   C_d      [count] double, device, updated in place
+ *   grad_d   [count] double, device (e.g. grad_d of cosim_loss_and_grad)
+ *   m_d, v_d [count] double, device: moments, zero before the first step,
+ *            updated in place (caller-owned)
+ *   step_d   [1] int32, device: steps taken so far (0 before the first step);
+ *            read as t - 1 and advanced by one
+ * Requires 0 <= beta1, beta2 < 1, finite lr and eps >= 0 (else COSIM_EINVAL).
+ * Enqueues two kernels on `stream` and nothing else; together with a reserved
+ * cosim_loss_and_grad it can be captured in one HIP graph and replayed for
+ * any number of steps, since t is read from device memory. */
+int cosim_adam_step(int count, double *C_d, const double *grad_d, double *m_d, double *v_d,
+                    int32_t *step_d, double lr, double beta1, double beta2, double eps,
+                    void *stream);
 
 /* --------------------------------------------------------------------------
  * Tuning of the fused contraction (performance only; every variant computes

@@ -25,6 +25,8 @@ S-parameter cosimulation, Eq. 3-7; Sec. IV-A gives the loop impedance, Eq. 11):
             mean |B_z - T|^2 (complex mode).
 8. dL/dC    by brute-force forward sensitivity (Eq. 8-10 specialised to
             dZ/dC_k), by the adjoint, and by central finite differences.
+9. Adam     the optimiser the paper runs on C (Sec. IV), one step as defined
+            by Kingma & Ba (bias-corrected first and second moments).
 
 Everything is float64 / complex128 NumPy.  Pins: tests/test_oracle_pins.py.
 """
@@ -391,6 +393,22 @@ def backward_from_field_grad(G, M, R, C, omega, I, gBz) -> np.ndarray:
             mu = np.linalg.solve(Z.T, r)
             g[b] += 2.0 * np.real(mu * I[b, f] / (1j * w * C[b] ** 2))
     return g
+
+
+# ---------------------------------------------------------------------------
+# Optimiser on C (Sec. IV: Adam on the capacitances)
+# ---------------------------------------------------------------------------
+
+def adam_step(C, g, m, v, t: int, lr: float = 1e-13, beta1: float = 0.9,
+              beta2: float = 0.999, eps: float = 1e-8):
+    """Step t (1-based) of Adam (Kingma & Ba 2015, Algorithm 1): moments
+    m, v of g, their bias corrections m / (1 - beta1^t), v / (1 - beta2^t),
+    and C - lr * mhat / (sqrt(vhat) + eps).  Returns new (C, m, v)."""
+    m = beta1 * np.asarray(m, dtype=np.float64) + (1.0 - beta1) * g
+    v = beta2 * np.asarray(v, dtype=np.float64) + (1.0 - beta2) * g * g
+    mhat = m / (1.0 - beta1 ** t)
+    vhat = v / (1.0 - beta2 ** t)
+    return C - lr * mhat / (np.sqrt(vhat) + eps), m, v
 
 
 # ---------------------------------------------------------------------------

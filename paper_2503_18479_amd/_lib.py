@@ -35,6 +35,8 @@ SIGNATURES = {
                                      c_void_p, c_void_p, c_void_p]),
     "cosim_loss_and_grad": (c_int, [c_void_p, c_int, c_int, c_void_p, c_void_p, c_void_p, c_int,
                                     c_int, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "cosim_adam_step": (c_int, [c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_double,
+                                c_double, c_double, c_double, c_void_p]),
     "cosim_plan_set_variant": (c_int, [c_void_p, c_int, c_int]),
     "cosim_plan_get_variant": (c_int, [c_void_p, c_int, P(c_int), P(c_int)]),
     "cosim_plan_autotune": (c_int, [c_void_p, c_int, c_int, c_void_p, c_void_p, c_void_p, c_int,

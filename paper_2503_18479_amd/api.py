@@ -216,6 +216,62 @@ class Plan:
         return loss, g, st
 
 
+    # -- optimisation driver ----------------------------------------------------
+    def optimize(self, C: torch.Tensor, omega: torch.Tensor, T: torch.Tensor, steps: int,
+                 lr: float = 1e-13, betas=(0.9, 0.999), eps: float = 1e-8, precision=FP32,
+                 loss_mode: int = LOSS_MAG, graph: bool = False):
+        """Adam on C (updated in place) for `steps` steps of cosim_loss_and_grad +
+        cosim_adam_step.  With graph=True one step is captured in a HIP graph and
+        replayed.  Returns (loss per step [steps][B], status of the last step)."""
+        B, F = int(C.shape[0]), int(omega.shape[0])
+        self.reserve(B, F)
+        loss = torch.empty((B,), dtype=torch.float64, device=self.device)
+        g = torch.empty_like(C)
+        st = torch.empty((B, F), dtype=torch.int32, device=self.device)
+        m = torch.zeros_like(C)
+        v = torch.zeros_like(C)
+        t = torch.zeros((1,), dtype=torch.int32, device=self.device)
+        hist = torch.empty((steps, B), dtype=torch.float64, device=self.device)
+
+        def one_step():
+            self.loss_and_grad(C, omega, T, loss_mode=loss_mode, precision=precision,
+                               out=(loss, g, st))
+            adam_step(C, g, m, v, t, lr=lr, betas=betas, eps=eps)
+
+        if not graph:
+            for k in range(steps):
+                one_step()
+                hist[k].copy_(loss)
+            return hist, st
+        # warm the variant choice and the workspace on a copy, then capture
+        C0, side = C.clone(), torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            self.loss_and_grad(C0, omega, T, loss_mode=loss_mode, precision=precision,
+                               out=(loss, g, st))
+        torch.cuda.current_stream().wait_stream(side)
+        gr = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(gr):
+            one_step()
+        for k in range(steps):
+            gr.replay()
+            hist[k].copy_(loss)
+        return hist, st
+
+
+def adam_step(C: torch.Tensor, grad: torch.Tensor, m: torch.Tensor, v: torch.Tensor,
+              step: torch.Tensor, lr: float = 1e-13, betas=(0.9, 0.999), eps: float = 1e-8) -> None:
+    """One cosim_adam_step on C (in place); m, v, step are the caller's state."""
+    lib = load_library()
+    shape = tuple(C.shape)
+    count = int(C.numel())
+    check(lib.cosim_adam_step(count, _dev(C, torch.float64, shape, "C"),
+                              _dev(grad, torch.float64, shape, "grad"),
+                              _dev(m, torch.float64, shape, "m"), _dev(v, torch.float64, shape, "v"),
+                              _dev(step, torch.int32, (1,), "step"), float(lr), float(betas[0]),
+                              float(betas[1]), float(eps), _stream()))
+
+
 class CosimField(torch.autograd.Function):
     """B_z = f(C) with the library's hand-written adjoint as backward.
 

@@ -19,7 +19,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libcosim.so")
 ARCH = os.environ.get("COSIM_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["abi.cpp", "assemble.hip", "solve.hip", "fused.hip", "field.hip"]
+SOURCES = ["abi.cpp", "assemble.hip", "solve.hip", "fused.hip", "field.hip", "optim.hip"]
 
 COMMON = [
     "-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",

@@ -487,6 +487,21 @@ int cosim_loss_and_grad(cosim_plan_t p, int B, int F, const double *C_d, const d
     return COSIM_OK;
 }
 
+int cosim_adam_step(int count, double *C_d, const double *grad_d, double *m_d, double *v_d,
+                    int32_t *step_d, double lr, double beta1, double beta2, double eps,
+                    void *stream) {
+    if (count < 0) return fail(COSIM_EINVAL, "count = %d", count);
+    if (!(beta1 >= 0.0 && beta1 < 1.0) || !(beta2 >= 0.0 && beta2 < 1.0))
+        return fail(COSIM_EINVAL, "betas must lie in [0, 1) (got %g, %g)", beta1, beta2);
+    if (!std::isfinite(lr) || !(eps >= 0.0) || !std::isfinite(eps))
+        return fail(COSIM_EINVAL, "lr must be finite and eps finite and >= 0");
+    if (count == 0) return COSIM_OK;
+    if (!C_d || !grad_d || !m_d || !v_d || !step_d) return fail(COSIM_EINVAL, "null device pointer");
+    HIP_TRY(launch_adam(count, C_d, grad_d, m_d, v_d, step_d, lr, beta1, beta2, eps,
+                        (hipStream_t)stream));
+    return COSIM_OK;
+}
+
 int cosim_plan_set_variant(cosim_plan_t p, int precision, int variant) {
     if (!p) return fail(COSIM_EINVAL, "null plan");
     int rc = check_prec(precision);

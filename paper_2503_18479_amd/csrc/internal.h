@@ -121,6 +121,9 @@ hipError_t launch_fused(Prec prec, int NP, int variant, int loss_mode, bool grad
                         const FusedArgs &a, hipStream_t st);
 // Tuning variants of the fused kernel per precision, and the number of
 // systems one workgroup of a variant covers.
+hipError_t launch_adam(int count, double *C_d, const double *grad_d, double *m_d, double *v_d,
+                       int32_t *step_d, double lr, double beta1, double beta2, double eps,
+                       hipStream_t st);
 int fused_variant_count(Prec prec);
 int fused_systems_per_block(Prec prec, int NP, int variant);
 

@@ -116,3 +116,17 @@ def test_tuning_argument_errors(lib):
     assert lib.cosim_plan_get_variant(None, 0, ctypes.byref(v), None) == EINVAL
     assert lib.cosim_plan_autotune(None, 1, 1, None, None, None, 0, 0, 1, None, None) == EINVAL
     assert lib.cosim_plan_timing(None, 4) == EINVAL
+
+
+def test_adam_step_argument_errors(lib):
+    d = ctypes.c_void_p(64)
+    # count 0 is a no-op even with null pointers; the checks below return
+    # before any HIP call
+    assert lib.cosim_adam_step(0, None, None, None, None, None, 1e-13, 0.9, 0.999, 1e-8, None) == 0
+    assert lib.cosim_adam_step(-1, d, d, d, d, d, 1e-13, 0.9, 0.999, 1e-8, None) == EINVAL
+    assert lib.cosim_adam_step(4, None, d, d, d, d, 1e-13, 0.9, 0.999, 1e-8, None) == EINVAL
+    assert lib.cosim_adam_step(4, d, d, d, d, None, 1e-13, 0.9, 0.999, 1e-8, None) == EINVAL
+    assert lib.cosim_adam_step(4, d, d, d, d, d, 1e-13, 1.0, 0.999, 1e-8, None) == EINVAL
+    assert lib.cosim_adam_step(4, d, d, d, d, d, 1e-13, 0.9, -0.1, 1e-8, None) == EINVAL
+    assert lib.cosim_adam_step(4, d, d, d, d, d, float("nan"), 0.9, 0.999, 1e-8, None) == EINVAL
+    assert lib.cosim_adam_step(4, d, d, d, d, d, 1e-13, 0.9, 0.999, -1.0, None) == EINVAL

@@ -388,3 +388,81 @@ def test_autotune_picks_a_variant(dev):
     loss, grad, st = c.plan.loss_and_grad(c.C, c.om, c.T, precision=2)
     assert np.max(np.abs(loss.cpu().numpy() - c.oracle_eval()[2]) / c.oracle_eval()[2]) < TOL[2]
     c.plan.set_variant(2, 0)
+
+
+# ----------------------------------------------------------- driver: Adam and graphs
+def test_adam_step_matches_oracle(dev):
+    from paper_2503_18479_amd import adam_step
+    rng = np.random.default_rng(31)
+    C0 = rng.uniform(20e-12, 150e-12, size=(7, 9))
+    grads = [rng.standard_normal(C0.shape) * 10.0 ** rng.uniform(-4, 1) for _ in range(5)]
+    C = torch.tensor(C0, device=dev)
+    m = torch.zeros_like(C); v = torch.zeros_like(C)
+    t = torch.zeros((1,), dtype=torch.int32, device=dev)
+    Co, mo, vo = C0.copy(), np.zeros_like(C0), np.zeros_like(C0)
+    for k, g in enumerate(grads, start=1):
+        _say(f"[adam] step {k}")
+        adam_step(C, torch.tensor(g, device=dev), m, v, t, lr=1e-13)
+        Co, mo, vo = O.adam_step(Co, g, mo, vo, k, lr=1e-13)
+    torch.cuda.synchronize()
+    assert int(t.item()) == len(grads)
+    np.testing.assert_allclose(C.cpu().numpy(), Co, rtol=1e-14, atol=0)
+    np.testing.assert_allclose(m.cpu().numpy(), mo, rtol=1e-14, atol=0)
+    np.testing.assert_allclose(v.cpu().numpy(), vo, rtol=1e-13, atol=0)
+
+
+def test_optimize_follows_oracle_adam(dev):
+    """Four Adam steps driven by cosim_loss_and_grad (FP64) against the oracle's
+    loss, adjoint gradient and Adam step."""
+    c = _case("n6")
+    _say("[optimize] n6 fp64, 4 steps")
+    C = c.C.clone()
+    hist, st = c.plan.optimize(C, c.om, c.T, steps=4, lr=1e-13, precision=0)
+    torch.cuda.synchronize()
+    assert int((st != 0).sum()) == 0
+    Co = c.wl.C.copy(); m = np.zeros_like(Co); v = np.zeros_like(Co)
+    for k in range(1, 5):
+        L = c.oracle_eval(Co)[2]
+        assert _nrel(hist[k - 1].cpu().numpy(), L) < 1e-9, k
+        g = c.oracle_grad(Co)
+        Co, m, v = O.adam_step(Co, g, m, v, k, lr=1e-13)
+    np.testing.assert_allclose(C.cpu().numpy(), Co, rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("prec", [0, 2])
+def test_loss_and_grad_graph_replays_match_eager(dev, prec):
+    """cosim_loss_and_grad captured once in a HIP graph; each replay (with new C
+    written in place and eager work in between) equals the eager call bit for bit."""
+    c = _case("n64") if prec == 2 else _case("n6")
+    B, F = c.C.shape[0], c.om.shape[0]
+    c.plan.reserve(B, F)
+    C = c.C.clone()
+    outs = (torch.empty((B,), dtype=torch.float64, device=dev), torch.empty_like(C),
+            torch.empty((B, F), dtype=torch.int32, device=dev))
+    c.plan.loss_and_grad(C, c.om, c.T, precision=prec, out=outs)  # warm-up
+    torch.cuda.synchronize()
+    gr = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(gr):
+        c.plan.loss_and_grad(C, c.om, c.T, precision=prec, out=outs)
+    for rep in range(3):
+        _say(f"[graph] prec={prec} replay {rep}")
+        C.copy_(c.C * (1.0 + 0.05 * rep))
+        gr.replay()
+        torch.cuda.synchronize()
+        got = [o.clone() for o in outs]
+        loss, g, st = c.plan.loss_and_grad(C, c.om, c.T, precision=prec)
+        torch.cuda.synchronize()
+        assert torch.equal(got[0], loss) and torch.equal(got[1], g) and torch.equal(got[2], st)
+        L = c.oracle_eval(C.cpu().numpy())[2]
+        assert _nrel(got[0].cpu().numpy(), L) < TOL[prec]
+
+
+def test_optimize_in_one_graph_equals_eager(dev):
+    c = _case("n25")
+    _say("[optimize] n25 bf16x3, graph vs eager")
+    Ca, Cb = c.C.clone(), c.C.clone()
+    ha, _ = c.plan.optimize(Ca, c.om, c.T, steps=5, precision=2, graph=False)
+    hb, _ = c.plan.optimize(Cb, c.om, c.T, steps=5, precision=2, graph=True)
+    torch.cuda.synchronize()
+    assert torch.equal(Ca, Cb) and torch.equal(ha, hb)
+    assert not torch.equal(Ca, c.C)

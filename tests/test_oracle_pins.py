@@ -323,3 +323,36 @@ def test_T12_gram_identity_complex_mode():
             i = I[b, f]
             acc += (np.real(np.conj(i) @ H @ i) - 2 * np.real(g @ i) + T @ T) / P
         np.testing.assert_allclose(L[b], acc / om.shape[0], rtol=1e-10)
+
+
+# ---------------------------------------------------------------- the optimiser on C
+def test_adam_first_step_and_constant_gradient_closed_forms():
+    """Step 1 of Adam moves every coordinate by lr * g / (|g| + eps) (both bias
+    corrections are exact at t = 1), and under a constant gradient every later
+    step does the same, so after t steps C = C0 - t * lr * g / (|g| + eps)."""
+    rng = np.random.default_rng(7)
+    C0 = rng.uniform(20e-12, 150e-12, size=(3, 5))
+    g = rng.standard_normal((3, 5)) * 1e-2
+    lr, eps = 1e-13, 1e-8
+    C, m, v = O.adam_step(C0, g, np.zeros_like(C0), np.zeros_like(C0), 1, lr=lr, eps=eps)
+    np.testing.assert_allclose(C, C0 - lr * g / (np.abs(g) + eps), rtol=0, atol=1e-26)
+    for t in range(2, 8):
+        C, m, v = O.adam_step(C, g, m, v, t, lr=lr, eps=eps)
+    np.testing.assert_allclose(C, C0 - 7 * lr * g / (np.abs(g) + eps), rtol=0, atol=1e-25)
+
+
+def test_adam_matches_torch_optimizer():
+    """Independent implementation: torch.optim.Adam (CPU, float64) on the same
+    gradient sequence follows the same trajectory."""
+    import torch
+    rng = np.random.default_rng(8)
+    C0 = rng.uniform(20e-12, 150e-12, size=(4, 6))
+    grads = [rng.standard_normal(C0.shape) * 10.0 ** rng.uniform(-3, 1) for _ in range(6)]
+    p = torch.nn.Parameter(torch.tensor(C0))
+    opt = torch.optim.Adam([p], lr=1e-13, betas=(0.9, 0.999), eps=1e-8)
+    C, m, v = C0.copy(), np.zeros_like(C0), np.zeros_like(C0)
+    for t, g in enumerate(grads, start=1):
+        p.grad = torch.tensor(g)
+        opt.step()
+        C, m, v = O.adam_step(C, g, m, v, t)
+    np.testing.assert_allclose(C, p.detach().numpy(), rtol=1e-14, atol=0)
