@@ -19,7 +19,10 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libcosim.so")
 ARCH = os.environ.get("COSIM_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["abi.cpp", "assemble.hip", "solve.hip", "fused.hip", "field.hip", "optim.hip"]
+SOURCES = ["abi.cpp", "assemble.hip", "solve.hip", "solve_big.hip", "fused.hip",
+           "contract_big.hip", "field.hip", "optim.hip"]
+# plain GEMMs of the path above 64 loops run on rocBLAS
+LIBS = ["-L/opt/rocm/lib", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
 
 COMMON = [
     "-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",
@@ -52,7 +55,7 @@ def build(verbose: bool = False) -> str:
     with concurrent.futures.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
+    cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, *LIBS, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"linking libcosim.so failed:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

@@ -78,6 +78,9 @@ void dfree(T *&p) {
 }
 
 void plan_free_workspace(cosim_plan *p) {
+    dfree(p->bX);
+    dfree(p->bY);
+    dfree(p->bW);
     dfree(p->I_ws);
     dfree(p->rpart);
     dfree(p->lpart);
@@ -106,6 +109,16 @@ int ensure_workspace(cosim_plan *p, size_t systems, int chunks) {
     const int nc = std::max(chunks, p->cap_chunks);
     plan_free_workspace(p);
     const size_t n = (size_t)p->n, NP = (size_t)p->NP;
+    const bool big = big_plan(p->NP);
+    // more than 64 loops: GEMM operand planes (8 bytes per element covers FP64,
+    // FP32 and the two bf16 planes)
+    if (big && (hipMalloc(&p->bX, 2 * ns * NP * sizeof(double)) != hipSuccess ||
+                hipMalloc(&p->bY, 2 * ns * (size_t)p->P_pad * sizeof(double)) != hipSuccess ||
+                hipMalloc(&p->bW, 2 * ns * (size_t)p->P_pad * sizeof(double)) != hipSuccess)) {
+        plan_free_workspace(p);
+        (void)hipGetLastError();
+        return fail(COSIM_ENOMEM, "GEMM workspace for %zu systems failed", ns);
+    }
     if (hipMalloc((void **)&p->I_ws, ns * n * sizeof(double2)) != hipSuccess ||
         hipMalloc((void **)&p->rpart, (size_t)nc * ns * NP * sizeof(double2)) != hipSuccess ||
         hipMalloc((void **)&p->lpart, (size_t)nc * ns * sizeof(double)) != hipSuccess ||
@@ -141,10 +154,45 @@ int choose_chunks(const cosim_plan *p, Prec prec, size_t S, int variant) {
 // chunks of whole 64-row tiles, every chunk non-empty; *tiles_per_chunk out
 int chunks_for(const cosim_plan *p, Prec prec, size_t S, int variant, int *tiles_per_chunk = nullptr) {
     const int tiles = p->P_pad / kPTile;
+    if (big_plan(p->NP)) {  // adjoint GEMM chunks of kBigRows rows
+        const int tpc = kBigRows / kPTile;
+        if (tiles_per_chunk) *tiles_per_chunk = tpc;
+        return (tiles + tpc - 1) / tpc;
+    }
     const int want = choose_chunks(p, prec, S, variant);
     const int tpc = (tiles + want - 1) / want;
     if (tiles_per_chunk) *tiles_per_chunk = tpc;
     return (tiles + tpc - 1) / tpc;
+}
+
+// Tuning variants of a plan: the fused kernels' for up to 64 loops, a single
+// one (the GEMM path) above.
+int plan_variants(const cosim_plan *p, Prec prec) {
+    return big_plan(p->NP) ? 1 : fused_variant_count(prec);
+}
+
+// Operands of the GEMM path (more than 64 loops) for S systems.
+BigArgs big_args(const cosim_plan *p, Prec prec, int S, int nchunk, const double2 *I,
+                 const double *T) {
+    BigArgs a;
+    a.n = p->n;
+    a.NP = p->NP;
+    a.P = p->P;
+    a.P_pad = p->P_pad;
+    a.S = S;
+    a.nchunk = nchunk;
+    a.rows = kBigRows;
+    a.G = prec == Prec::F64 ? (const void *)p->G64 : (const void *)p->G32;
+    a.Ghi = p->Ghi;
+    a.Glo = p->Glo;
+    a.I = I;
+    a.T = T;
+    a.X = p->bX;
+    a.Y = p->bY;
+    a.W = p->bW;
+    a.R = p->rpart;
+    a.lpart = p->lpart;
+    return a;
 }
 
 int check_batch(const cosim_plan *p, int B, int F) {
@@ -232,9 +280,9 @@ int cosim_assemble(cosim_geom_t g, int P, const double *pts_d, double bext_z, vo
     if (P < 1) return fail(COSIM_EINVAL, "P must be >= 1 (got %d)", P);
     if (!pts_d) return fail(COSIM_EINVAL, "pts_d is null");
     if (!std::isfinite(bext_z)) return fail(COSIM_EINVAL, "bext_z is not finite");
-    if (g->n > kMaxLoops)
+    if (g->n > kMaxLoopsBig)
         return fail(COSIM_EUNSUPPORTED, "%d loops: this build supports up to %d loops per plan",
-                    g->n, kMaxLoops);
+                    g->n, kMaxLoopsBig);
     hipStream_t st = (hipStream_t)stream;
     cosim_plan *p = new (std::nothrow) cosim_plan;
     if (!p) return fail(COSIM_ENOMEM, "host allocation failed");
@@ -267,8 +315,8 @@ int cosim_assemble(cosim_geom_t g, int P, const double *pts_d, double bext_z, vo
         hipMalloc((void **)&p->G32, gsz * sizeof(float)) != hipSuccess ||
         hipMalloc((void **)&p->Ghi, gsz * sizeof(uint16_t)) != hipSuccess ||
         hipMalloc((void **)&p->Glo, gsz * sizeof(uint16_t)) != hipSuccess ||
-        hipMalloc((void **)&p->GThi, gsz * sizeof(uint16_t)) != hipSuccess ||
-        hipMalloc((void **)&p->GTlo, gsz * sizeof(uint16_t)) != hipSuccess ||
+        (!big_plan(p->NP) && (hipMalloc((void **)&p->GThi, gsz * sizeof(uint16_t)) != hipSuccess ||
+                              hipMalloc((void **)&p->GTlo, gsz * sizeof(uint16_t)) != hipSuccess)) ||
         hipMalloc((void **)&p->M_d, n * n * sizeof(double)) != hipSuccess ||
         hipMalloc((void **)&p->phi_d, n * sizeof(double)) != hipSuccess ||
         hipMalloc((void **)&p->R_d, n * sizeof(double)) != hipSuccess ||
@@ -294,6 +342,7 @@ int cosim_assemble(cosim_geom_t g, int P, const double *pts_d, double bext_z, vo
     p->M_h.resize(n * n);
     ASM_TRY(hipMemcpyAsync(p->M_h.data(), p->M_d, n * n * sizeof(double), hipMemcpyDeviceToHost, st));
     ASM_TRY(hipStreamSynchronize(st));
+    if (big_plan(p->NP)) ASM_TRY(big_blas_create(&p->blas));
 #undef ASM_TRY
     cleanup(COSIM_OK);
     *out = p;
@@ -314,6 +363,8 @@ int cosim_plan_destroy(cosim_plan_t p) {
     dfree(p->phi_d);
     dfree(p->R_d);
     plan_free_workspace(p);
+    big_blas_destroy(p->blas);
+    p->blas = nullptr;
     delete p;
     return COSIM_OK;
 }
@@ -332,7 +383,7 @@ int cosim_plan_reserve(cosim_plan_t p, int max_batch, int max_freq) {
     const size_t S = (size_t)max_batch * max_freq;
     int chunks = 1;
     for (int pr = COSIM_FP64; pr <= COSIM_BF16X3; ++pr)
-        for (int v = 0; v < fused_variant_count((Prec)pr); ++v)
+        for (int v = 0; v < plan_variants(p, (Prec)pr); ++v)
             chunks = std::max(chunks, chunks_for(p, (Prec)pr, S, v));
     return ensure_workspace(p, S, chunks);
 }
@@ -371,6 +422,16 @@ int cosim_solve(cosim_plan_t p, int B, int F, const double *C_d, const double *o
     if (!C_d || !omega_d || !I_d || !status_d) return fail(COSIM_EINVAL, "null device pointer");
     if ((rc = check_device(p))) return rc;
     const int S = B * F;
+    if (big_plan(p->NP)) {
+        if ((rc = ensure_workspace(p, (size_t)S, 1))) return rc;
+        hipStream_t st = (hipStream_t)stream;
+        HIP_TRY(launch_lu_big(p->NP, p->n, S, F, p->M_d, p->R_d, C_d, omega_d, p->fac.L,
+                              p->fac.piv_row, status_d, st));
+        HIP_TRY(launch_lu_solve(p->NP, p->n, S, F, p->fac.L, p->fac.piv_row, p->phi_d, C_d,
+                                omega_d, (double2 *)I_d, kRhsExcitation, nullptr, 0, 0.0, nullptr,
+                                status_d, st));
+        return COSIM_OK;
+    }
     HIP_TRY(launch_solve_forward(p->NP, p->n, S, F, p->M_d, p->R_d, p->phi_d, C_d, omega_d,
                                  (double2 *)I_d, status_d, GJFactor{}, (hipStream_t)stream));
     return COSIM_OK;
@@ -406,8 +467,23 @@ int cosim_field_backward(cosim_plan_t p, int B, int F, const double *C_d, const 
         return fail(COSIM_EINVAL, "null device pointer");
     if ((rc = check_device(p))) return rc;
     const size_t S = (size_t)B * F;
-    if ((rc = ensure_workspace(p, S, 1))) return rc;
     hipStream_t st = (hipStream_t)stream;
+    if (big_plan(p->NP)) {
+        // G^T conj(gBz) as FP64 GEMMs over P-chunks, then the pivoted LU solve
+        const int nchunk = chunks_for(p, Prec::F64, S, 0);
+        if ((rc = ensure_workspace(p, S, nchunk))) return rc;
+        HIP_TRY(launch_pack_w64(p->P, p->P_pad, (int)S, (const double2 *)gBz_d, (double *)p->bW, st));
+        BigArgs a = big_args(p, Prec::F64, (int)S, nchunk, nullptr, nullptr);
+        HIP_TRY(big_adjoint(p->blas, Prec::F64, a, st));
+        HIP_TRY(launch_lu_big(p->NP, p->n, (int)S, F, p->M_d, p->R_d, C_d, omega_d, p->fac.L,
+                              p->fac.piv_row, status_d, st));
+        HIP_TRY(launch_lu_solve(p->NP, p->n, (int)S, F, p->fac.L, p->fac.piv_row, p->phi_d, C_d,
+                                omega_d, (double2 *)I_d, kRhsPlanarF64, p->rpart, nchunk, 0.5,
+                                p->gsys, status_d, st));
+        HIP_TRY(launch_reduce(p->n, B, F, 0, p->gsys, nullptr, 0.0, gC_d, nullptr, st));
+        return COSIM_OK;
+    }
+    if ((rc = ensure_workspace(p, S, 1))) return rc;
     HIP_TRY(launch_field_backward_contract(p->NP, p->P, (int)S, p->n, p->G64,
                                            (const double2 *)gBz_d, p->rpart, st));
     // gBz = 2 dL/d conj(B), so conj(w) = conj(gBz)/2
@@ -446,6 +522,29 @@ int cosim_loss_and_grad(cosim_plan_t p, int B, int F, const double *C_d, const d
     // unpivoted LDL^T path runs and hands systems with a small pivot to the
     // pivoted Gauss-Jordan fallback; otherwise Gauss-Jordan runs for all.
     const bool grad = grad_d != nullptr;
+    const double scale = 1.0 / ((double)F * (double)p->P);
+    if (big_plan(p->NP)) {
+        // pivoted LU, GEMM contractions with the loss epilogue between, LU solve
+        HIP_TRY(launch_lu_big(p->NP, p->n, (int)S, F, p->M_d, p->R_d, C_d, omega_d, p->fac.L,
+                              p->fac.piv_row, status_d, st));
+        HIP_TRY(launch_lu_solve(p->NP, p->n, (int)S, F, p->fac.L, p->fac.piv_row, p->phi_d, C_d,
+                                omega_d, p->I_ws, kRhsExcitation, nullptr, 0, 0.0, nullptr,
+                                status_d, st));
+        if (ev) HIP_TRY(hipEventRecord(ev[1], st));
+        BigArgs a = big_args(p, prec, (int)S, nchunk, p->I_ws, T_d);
+        HIP_TRY(big_contract(p->blas, prec, loss_mode, grad, a, st));
+        if (ev) HIP_TRY(hipEventRecord(ev[2], st));
+        if (grad)
+            HIP_TRY(launch_lu_solve(p->NP, p->n, (int)S, F, p->fac.L, p->fac.piv_row, p->phi_d,
+                                    C_d, omega_d, p->I_ws,
+                                    prec == Prec::F64 ? kRhsPlanarF64 : kRhsPlanarF32, p->rpart,
+                                    nchunk, scale, p->gsys, status_d, st));
+        if (ev) HIP_TRY(hipEventRecord(ev[3], st));
+        HIP_TRY(launch_reduce(p->n, B, F, nchunk, grad ? p->gsys : nullptr, p->lpart, scale,
+                              grad_d, loss_d, st));
+        if (ev) HIP_TRY(hipEventRecord(ev[4], st));
+        return COSIM_OK;
+    }
     if (p->ldl_ok) {
         HIP_TRY(launch_ldl(p->NP, p->n, (int)S, F, p->M_d, p->R_d, C_d, omega_d, p->fac, status_d, st));
         HIP_TRY(launch_solve_fallback(p->NP, p->n, (int)S, F, p->M_d, p->R_d, p->phi_d, C_d,
@@ -476,7 +575,6 @@ int cosim_loss_and_grad(cosim_plan_t p, int B, int F, const double *C_d, const d
     a.lpart = p->lpart;
     HIP_TRY(launch_fused(prec, p->NP, variant, loss_mode, grad, a, st));
     if (ev) HIP_TRY(hipEventRecord(ev[2], st));
-    const double scale = 1.0 / ((double)F * (double)p->P);
     if (grad)
         HIP_TRY(launch_replay_adjoint(p->NP, p->n, (int)S, F, p->fac, C_d, omega_d, p->I_ws,
                                       p->rpart, nchunk, scale, p->gsys, status_d, st));
@@ -506,9 +604,9 @@ int cosim_plan_set_variant(cosim_plan_t p, int precision, int variant) {
     if (!p) return fail(COSIM_EINVAL, "null plan");
     int rc = check_prec(precision);
     if (rc) return rc;
-    if (variant < 0 || variant >= fused_variant_count((Prec)precision))
+    if (variant < 0 || variant >= plan_variants(p, (Prec)precision))
         return fail(COSIM_EINVAL, "variant %d out of range [0, %d)", variant,
-                    fused_variant_count((Prec)precision));
+                    plan_variants(p, (Prec)precision));
     p->variant[precision] = variant;
     return COSIM_OK;
 }
@@ -518,7 +616,7 @@ int cosim_plan_get_variant(cosim_plan_t p, int precision, int *variant, int *n_v
     int rc = check_prec(precision);
     if (rc) return rc;
     if (variant) *variant = p->variant[precision];
-    if (n_variants) *n_variants = fused_variant_count((Prec)precision);
+    if (n_variants) *n_variants = plan_variants(p, (Prec)precision);
     return COSIM_OK;
 }
 
@@ -550,7 +648,7 @@ int cosim_plan_autotune(cosim_plan_t p, int B, int F, const double *C_d, const d
         hipMalloc((void **)&status, S * sizeof(int32_t)) != hipSuccess ||
         hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return done(fail(COSIM_ENOMEM, "autotune scratch allocation failed"));
-    const int nv = fused_variant_count((Prec)precision);
+    const int nv = plan_variants(p, (Prec)precision);
     int best = 0;
     float best_ms = 0.f;
     const int saved_timing = p->timing_cap;

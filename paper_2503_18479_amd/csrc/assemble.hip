@@ -38,9 +38,12 @@ __device__ inline double bz_filament(double ax, double ay, double az, double la,
 
 // Block: 64 points x 4 waves.  Wave w evaluates loops w, w+4, ... for the 64
 // points of its lanes (every lane of a wave walks the same vertices, which
-// the scalar unit broadcasts), the block tile [64][NP] is staged in LDS and
-// written out row-major so that each row of G is one contiguous store.
+// the scalar unit broadcasts), one chunk of 64 loops at a time; each chunk of
+// the block tile [64][64] is staged in LDS and written out row-major, so that
+// a row segment of G is one contiguous store.  The transposed bf16 copies
+// (fused kernels only) are skipped when GThi is null.
 constexpr int kGPts = 64;
+constexpr int kGLoops = 64;
 
 __global__ __launch_bounds__(256) void k_assemble_G(int n, int NP, int P, int P_pad,
                                                     const int32_t *__restrict__ seg_off,
@@ -52,7 +55,7 @@ __global__ __launch_bounds__(256) void k_assemble_G(int n, int NP, int P, int P_
                                                     uint16_t *__restrict__ Glo,
                                                     uint16_t *__restrict__ GThi,
                                                     uint16_t *__restrict__ GTlo) {
-    __shared__ double tile[kGPts][kMaxLoops + 1];
+    __shared__ double tile[kGPts][kGLoops + 1];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int p = blockIdx.x * kGPts + lane;
@@ -62,57 +65,64 @@ __global__ __launch_bounds__(256) void k_assemble_G(int n, int NP, int P, int P_
         py = pts[3 * p + 1];
         pz = pts[3 * p + 2];
     }
-    for (int k = wave; k < NP; k += 4) {
-        double acc = 0.0;
-        if (k < n && p < P) {
-            const int v0 = seg_off[k], v1 = seg_off[k + 1];
-            // first vertex relative to p; distances are shared by neighbouring segments
-            double fx = verts[3 * v0 + 0] - px, fy = verts[3 * v0 + 1] - py,
-                   fz = verts[3 * v0 + 2] - pz;
-            double fl = sqrt(fx * fx + fy * fy + fz * fz);
-            double ax = fx, ay = fy, az = fz, la = fl;
-            for (int v = v0 + 1; v <= v1; ++v) {
-                double bx, by, bz, lb;
-                if (v < v1) {
-                    bx = verts[3 * v + 0] - px;
-                    by = verts[3 * v + 1] - py;
-                    bz = verts[3 * v + 2] - pz;
-                    lb = sqrt(bx * bx + by * by + bz * bz);
-                } else {  // closing segment back to the first vertex
-                    bx = fx; by = fy; bz = fz; lb = fl;
-                }
-                acc += bz_filament(ax, ay, az, la, bx, by, bz, lb);
-                ax = bx; ay = by; az = bz; la = lb;
-            }
-            acc *= kMu0Over4Pi;
-        }
-        tile[lane][k] = acc;
-    }
-    __syncthreads();
     const int prow0 = blockIdx.x * kGPts;
-    for (int e = threadIdx.x; e < kGPts * NP; e += 256) {
-        const int r = e / NP, k = e - r * NP;
-        const int pr = prow0 + r;
-        if (pr >= P_pad) continue;
-        const double g = tile[r][k];
-        const size_t o = (size_t)pr * NP + k;
-        G64[o] = g;
-        const float g32 = (float)g;
-        G32[o] = g32;
-        const uint16_t hi = bf16_rne(g32);
-        Ghi[o] = hi;
-        Glo[o] = bf16_rne(g32 - bf16_to_f(hi));
-    }
-    // transposed bf16 copies [NP][P_pad]: each loop's column is contiguous in p
-    for (int e = threadIdx.x; e < kGPts * NP; e += 256) {
-        const int k = e / kGPts, r = e - k * kGPts;
-        const int pr = prow0 + r;
-        if (pr >= P_pad) continue;
-        const float g32 = (float)tile[r][k];
-        const uint16_t hi = bf16_rne(g32);
-        const size_t o = (size_t)k * P_pad + pr;
-        GThi[o] = hi;
-        GTlo[o] = bf16_rne(g32 - bf16_to_f(hi));
+    for (int k0 = 0; k0 < NP; k0 += kGLoops) {
+        const int kc = min(kGLoops, NP - k0);
+        for (int kk = wave; kk < kc; kk += 4) {
+            const int k = k0 + kk;
+            double acc = 0.0;
+            if (k < n && p < P) {
+                const int v0 = seg_off[k], v1 = seg_off[k + 1];
+                // first vertex relative to p; distances are shared by neighbouring segments
+                double fx = verts[3 * v0 + 0] - px, fy = verts[3 * v0 + 1] - py,
+                       fz = verts[3 * v0 + 2] - pz;
+                double fl = sqrt(fx * fx + fy * fy + fz * fz);
+                double ax = fx, ay = fy, az = fz, la = fl;
+                for (int v = v0 + 1; v <= v1; ++v) {
+                    double bx, by, bz, lb;
+                    if (v < v1) {
+                        bx = verts[3 * v + 0] - px;
+                        by = verts[3 * v + 1] - py;
+                        bz = verts[3 * v + 2] - pz;
+                        lb = sqrt(bx * bx + by * by + bz * bz);
+                    } else {  // closing segment back to the first vertex
+                        bx = fx; by = fy; bz = fz; lb = fl;
+                    }
+                    acc += bz_filament(ax, ay, az, la, bx, by, bz, lb);
+                    ax = bx; ay = by; az = bz; la = lb;
+                }
+                acc *= kMu0Over4Pi;
+            }
+            tile[lane][kk] = acc;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < kGPts * kc; e += 256) {
+            const int r = e / kc, kk = e - r * kc;
+            const int pr = prow0 + r;
+            if (pr >= P_pad) continue;
+            const double g = tile[r][kk];
+            const size_t o = (size_t)pr * NP + k0 + kk;
+            G64[o] = g;
+            const float g32 = (float)g;
+            G32[o] = g32;
+            const uint16_t hi = bf16_rne(g32);
+            Ghi[o] = hi;
+            Glo[o] = bf16_rne(g32 - bf16_to_f(hi));
+        }
+        // transposed bf16 copies [NP][P_pad]: each loop's column is contiguous in p
+        if (GThi) {
+            for (int e = threadIdx.x; e < kGPts * kc; e += 256) {
+                const int kk = e / kGPts, r = e - kk * kGPts;
+                const int pr = prow0 + r;
+                if (pr >= P_pad) continue;
+                const float g32 = (float)tile[r][kk];
+                const uint16_t hi = bf16_rne(g32);
+                const size_t o = (size_t)(k0 + kk) * P_pad + pr;
+                GThi[o] = hi;
+                GTlo[o] = bf16_rne(g32 - bf16_to_f(hi));
+            }
+        }
+        __syncthreads();
     }
 }
 

@@ -1,0 +1,265 @@
+// Superposition, loss and adjoint contraction for more than 64 loops
+// (Eq. 7, Eq. 1, and the right-hand side of Eq. 8-10).
+//
+// With many loops the currents of a workgroup's systems no longer fit the
+// matrix-core operand registers of the fused kernels, so the two contractions
+// run as plain GEMMs on the library (rocBLAS) with the loss epilogue between:
+//   X  [2S][NP]        re / im planes of I (packed, zero padded), column-major
+//                      NP x 2S for the GEMM;
+//   Y  = G X           P_pad x 2S planes of B_z (GEMM, K = NP);
+//   epilogue           loss partials per (P-chunk, system) and the planes of
+//                      w = dL/d conj(B) in the adjoint's operand precision;
+//   R_c = G_c^T W_c    per P-chunk c of kBigRows rows (K = rows of the chunk),
+//                      NP x 2S planes, summed over chunks in FP64 by the solve.
+// BF16X3 splits both operands into bf16 hi / lo and adds the three products
+// hi hi + hi lo + lo hi into FP32 (beta = 1).  G is stored [P_pad][NP]
+// row-major, i.e. column-major NP x P_pad, so both GEMMs read it in place.
+#include <rocblas/rocblas.h>
+
+#include <algorithm>
+
+#include "epilogue.h"
+#include "internal.h"
+
+namespace cosim {
+
+namespace {
+
+__device__ inline uint16_t bf16_bits(float x) {
+    return __builtin_bit_cast(uint16_t, (__bf16)x);
+}
+__device__ inline float bf16_float(uint16_t h) {
+    return __builtin_bit_cast(float, ((uint32_t)h) << 16);
+}
+
+// X[(2s + c) NP + k] = (Re, Im)_c of I[s][k], 0 for k >= n.
+// PREC 0: double planes; 1: float; 2: bf16 hi planes in X, lo planes in Xlo.
+template <int PREC>
+__global__ __launch_bounds__(256) void k_pack_x(int n, int NP, int S,
+                                                const double2 *__restrict__ I, void *X,
+                                                uint16_t *Xlo) {
+    const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (size_t)S * NP) return;
+    const int s = (int)(e / NP), k = (int)(e - (size_t)s * NP);
+    const double2 v = k < n ? I[(size_t)s * n + k] : make_double2(0.0, 0.0);
+    const size_t o0 = (size_t)(2 * s) * NP + k, o1 = o0 + NP;
+    if (PREC == 0) {
+        ((double *)X)[o0] = v.x;
+        ((double *)X)[o1] = v.y;
+    } else if (PREC == 1) {
+        ((float *)X)[o0] = (float)v.x;
+        ((float *)X)[o1] = (float)v.y;
+    } else {
+        const float re = (float)v.x, im = (float)v.y;
+        const uint16_t hr = bf16_bits(re), hi = bf16_bits(im);
+        ((uint16_t *)X)[o0] = hr;
+        ((uint16_t *)X)[o1] = hi;
+        Xlo[o0] = bf16_bits(re - bf16_float(hr));
+        Xlo[o1] = bf16_bits(im - bf16_float(hi));
+    }
+}
+
+// grid (S, chunks): rows [c*rows, (c+1)*rows) of system s.  Loss partial in
+// FP64, summed in a fixed order; w planes written when GRAD.
+template <int PREC, int LOSS, bool GRAD>
+__global__ __launch_bounds__(256) void k_epilogue_big(int P, int P_pad, int S, int rows,
+                                                      const void *Y, const double *__restrict__ T,
+                                                      void *W, uint16_t *Wlo,
+                                                      double *__restrict__ lpart) {
+    __shared__ double red[4];
+    const int s = blockIdx.x, c = blockIdx.y;
+    const int p0 = c * rows, p1 = min(P_pad, p0 + rows);
+    const size_t o0 = (size_t)(2 * s) * P_pad, o1 = o0 + P_pad;
+    double acc = 0.0;
+    for (int p = p0 + (int)threadIdx.x; p < p1; p += 256) {
+        if (PREC == 0) {
+            double x = ((const double *)Y)[o0 + p], y = ((const double *)Y)[o1 + p];
+            const double t = p < P ? T[p] : 0.0;
+            acc += epilogue<LOSS>(x, y, t);
+            if (GRAD) {
+                ((double *)W)[o0 + p] = x;
+                ((double *)W)[o1 + p] = y;
+            }
+        } else {
+            float x = ((const float *)Y)[o0 + p], y = ((const float *)Y)[o1 + p];
+            const float t = p < P ? (float)T[p] : 0.0f;
+            acc += (double)epilogue_f<LOSS>(x, y, t);
+            if (GRAD) {
+                if (PREC == 1) {
+                    ((float *)W)[o0 + p] = x;
+                    ((float *)W)[o1 + p] = y;
+                } else {
+                    const uint16_t hx = bf16_bits(x), hy = bf16_bits(y);
+                    ((uint16_t *)W)[o0 + p] = hx;
+                    ((uint16_t *)W)[o1 + p] = hy;
+                    Wlo[o0 + p] = bf16_bits(x - bf16_float(hx));
+                    Wlo[o1 + p] = bf16_bits(y - bf16_float(hy));
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) lpart[(size_t)c * S + s] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// W[(2s + c) P_pad + p] = (Re, Im)_c of g[s][p] (FP64), 0 for p >= P: the
+// upstream gradient of the materialised field as adjoint GEMM operand.
+__global__ __launch_bounds__(256) void k_pack_w64(int P, int P_pad, int S,
+                                                  const double2 *__restrict__ g,
+                                                  double *__restrict__ W) {
+    const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (size_t)S * P_pad) return;
+    const int s = (int)(e / P_pad), p = (int)(e - (size_t)s * P_pad);
+    const double2 v = p < P ? g[(size_t)s * P + p] : make_double2(0.0, 0.0);
+    W[(size_t)(2 * s) * P_pad + p] = v.x;
+    W[(size_t)(2 * s + 1) * P_pad + p] = v.y;
+}
+
+hipError_t blas_status(rocblas_status r) {
+    return r == rocblas_status_success ? hipSuccess : hipErrorLaunchFailure;
+}
+
+// C (m x n, ldc) = beta C + op(A) B, column-major, in the precision's types.
+hipError_t gemm(rocblas_handle h, Prec prec, rocblas_operation ta, int m, int nn, int k,
+                const void *A, int lda, const void *B, int ldb, float beta, void *C, int ldc) {
+    if (prec == Prec::F64) {
+        const double a1 = 1.0, b1 = beta;
+        return blas_status(rocblas_gemm_ex(h, ta, rocblas_operation_none, m, nn, k, &a1, A,
+                                           rocblas_datatype_f64_r, lda, B, rocblas_datatype_f64_r,
+                                           ldb, &b1, C, rocblas_datatype_f64_r, ldc, C,
+                                           rocblas_datatype_f64_r, ldc, rocblas_datatype_f64_r,
+                                           rocblas_gemm_algo_standard, 0, 0));
+    }
+    const float a1 = 1.0f, b1 = beta;
+    const rocblas_datatype t = prec == Prec::F32 ? rocblas_datatype_f32_r : rocblas_datatype_bf16_r;
+    return blas_status(rocblas_gemm_ex(h, ta, rocblas_operation_none, m, nn, k, &a1, A, t, lda, B,
+                                       t, ldb, &b1, C, rocblas_datatype_f32_r, ldc, C,
+                                       rocblas_datatype_f32_r, ldc, rocblas_datatype_f32_r,
+                                       rocblas_gemm_algo_standard, 0, 0));
+}
+
+template <int PREC, int LOSS>
+hipError_t launch_epi(bool grad, dim3 grid, hipStream_t st, int P, int P_pad, int S, int rows,
+                      const void *Y, const double *T, void *W, uint16_t *Wlo, double *lpart) {
+    if (grad)
+        hipLaunchKernelGGL((k_epilogue_big<PREC, LOSS, true>), grid, dim3(256), 0, st, P, P_pad, S,
+                           rows, Y, T, W, Wlo, lpart);
+    else
+        hipLaunchKernelGGL((k_epilogue_big<PREC, LOSS, false>), grid, dim3(256), 0, st, P, P_pad,
+                           S, rows, Y, T, W, Wlo, lpart);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t big_blas_create(void **handle) {
+    rocblas_handle h = nullptr;
+    if (rocblas_create_handle(&h) != rocblas_status_success) return hipErrorOutOfMemory;
+    *handle = h;
+    return hipSuccess;
+}
+
+void big_blas_destroy(void *handle) {
+    if (handle) (void)rocblas_destroy_handle((rocblas_handle)handle);
+}
+
+// Forward GEMM, loss epilogue and (if grad) the chunked adjoint GEMMs.
+// R receives nchunk blocks of NP x 2S planes (double for F64, float otherwise).
+hipError_t big_contract(void *handle, Prec prec, int loss_mode, bool grad, const BigArgs &a,
+                        hipStream_t st) {
+    rocblas_handle h = (rocblas_handle)handle;
+    if (rocblas_set_stream(h, st) != rocblas_status_success) return hipErrorInvalidValue;
+    const int S = a.S, NP = a.NP, P_pad = a.P_pad;
+    const size_t planes = (size_t)2 * S;
+    // 1. X planes
+    const size_t nx = (size_t)S * NP;
+    const dim3 gx((unsigned)((nx + 255) / 256));
+    uint16_t *Xlo = (uint16_t *)a.X + planes * NP;  // bf16 only: lo planes after the hi planes
+    switch (prec) {
+        case Prec::F64:
+            hipLaunchKernelGGL(k_pack_x<0>, gx, dim3(256), 0, st, a.n, NP, S, a.I, a.X, nullptr);
+            break;
+        case Prec::F32:
+            hipLaunchKernelGGL(k_pack_x<1>, gx, dim3(256), 0, st, a.n, NP, S, a.I, a.X, nullptr);
+            break;
+        case Prec::BF16X3:
+            hipLaunchKernelGGL(k_pack_x<2>, gx, dim3(256), 0, st, a.n, NP, S, a.I, a.X, Xlo);
+            break;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // 2. Y = G X
+    const rocblas_operation T_ = rocblas_operation_transpose;
+    if (prec == Prec::BF16X3) {
+        if ((e = gemm(h, prec, T_, P_pad, (int)planes, NP, a.Ghi, NP, a.X, NP, 0.0f, a.Y, P_pad)))
+            return e;
+        if ((e = gemm(h, prec, T_, P_pad, (int)planes, NP, a.Ghi, NP, Xlo, NP, 1.0f, a.Y, P_pad)))
+            return e;
+        if ((e = gemm(h, prec, T_, P_pad, (int)planes, NP, a.Glo, NP, a.X, NP, 1.0f, a.Y, P_pad)))
+            return e;
+    } else {
+        if ((e = gemm(h, prec, T_, P_pad, (int)planes, NP, a.G, NP, a.X, NP, 0.0f, a.Y, P_pad)))
+            return e;
+    }
+    // 3. loss partials and w planes
+    const dim3 ge(S, a.nchunk);
+    uint16_t *Wlo = (uint16_t *)a.W + planes * P_pad;
+    const int pr = prec == Prec::F64 ? 0 : (prec == Prec::F32 ? 1 : 2);
+#define COSIM_EPI(PR)                                                                          \
+    (loss_mode == COSIM_LOSS_MAG                                                               \
+         ? launch_epi<PR, COSIM_LOSS_MAG>(grad, ge, st, a.P, P_pad, S, a.rows, a.Y, a.T, a.W,  \
+                                          Wlo, a.lpart)                                         \
+         : launch_epi<PR, COSIM_LOSS_COMPLEX>(grad, ge, st, a.P, P_pad, S, a.rows, a.Y, a.T,   \
+                                              a.W, Wlo, a.lpart))
+    e = pr == 0 ? COSIM_EPI(0) : (pr == 1 ? COSIM_EPI(1) : COSIM_EPI(2));
+#undef COSIM_EPI
+    if (e != hipSuccess || !grad) return e;
+    // 4. R_c = G_c^T W_c per chunk of rows
+    return big_adjoint(handle, prec, a, st);
+}
+
+// Adjoint GEMMs only (W already holds the planes of w).
+hipError_t big_adjoint(void *handle, Prec prec, const BigArgs &a, hipStream_t st) {
+    rocblas_handle h = (rocblas_handle)handle;
+    if (rocblas_set_stream(h, st) != rocblas_status_success) return hipErrorInvalidValue;
+    const int S = a.S, NP = a.NP, P_pad = a.P_pad;
+    const size_t planes = (size_t)2 * S;
+    const size_t esz = prec == Prec::F64 ? sizeof(double) : sizeof(float);
+    const size_t gsz = prec == Prec::F64 ? sizeof(double) : (prec == Prec::F32 ? sizeof(float) : sizeof(uint16_t));
+    const size_t wsz = gsz;
+    const uint16_t *Wlo = (const uint16_t *)a.W + planes * P_pad;
+    const rocblas_operation N_ = rocblas_operation_none;
+    hipError_t e = hipSuccess;
+    for (int c = 0; c < a.nchunk; ++c) {
+        const int p0 = c * a.rows, kc = std::min(a.rows, P_pad - p0);
+        if (kc <= 0) break;
+        char *Rc = (char *)a.R + (size_t)c * NP * planes * esz;
+        if (prec == Prec::BF16X3) {
+            const char *gh = (const char *)a.Ghi + (size_t)p0 * NP * gsz;
+            const char *gl = (const char *)a.Glo + (size_t)p0 * NP * gsz;
+            const char *wh = (const char *)a.W + (size_t)p0 * wsz;
+            const char *wl = (const char *)Wlo + (size_t)p0 * wsz;
+            if ((e = gemm(h, prec, N_, NP, (int)planes, kc, gh, NP, wh, P_pad, 0.0f, Rc, NP))) return e;
+            if ((e = gemm(h, prec, N_, NP, (int)planes, kc, gh, NP, wl, P_pad, 1.0f, Rc, NP))) return e;
+            if ((e = gemm(h, prec, N_, NP, (int)planes, kc, gl, NP, wh, P_pad, 1.0f, Rc, NP))) return e;
+        } else {
+            const char *g = (const char *)a.G + (size_t)p0 * NP * gsz;
+            const char *w = (const char *)a.W + (size_t)p0 * wsz;
+            if ((e = gemm(h, prec, N_, NP, (int)planes, kc, g, NP, w, P_pad, 0.0f, Rc, NP))) return e;
+        }
+    }
+    return e;
+}
+
+hipError_t launch_pack_w64(int P, int P_pad, int S, const double2 *g_d, double *W_d,
+                           hipStream_t st) {
+    const size_t ne = (size_t)S * P_pad;
+    hipLaunchKernelGGL(k_pack_w64, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, st, P, P_pad,
+                       S, g_d, W_d);
+    return hipGetLastError();
+}
+
+}  // namespace cosim

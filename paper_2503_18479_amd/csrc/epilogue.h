@@ -1,0 +1,55 @@
+// Loss epilogue shared by the fused kernels and the large-loop-count path:
+// for one complex field value B = (x, y) and its target t, the loss term of
+// Eq. 1 and, in place of B, the weight w = dL/d conj(B) of the adjoint.
+//   MAG:     term (|B| - t)^2, w = (1 - t/|B|) B;
+//   COMPLEX: term |B - t|^2,   w = B - t.
+#pragma once
+#include "internal.h"
+
+namespace cosim {
+
+// Per-element loss epilogue.  MAG: e = |B| - T, w = e B/|B| (0 where B = 0).
+// COMPLEX: e = B - T, w = e.  Returns e^2 (|e|^2) and overwrites (x, y) by w.
+// FP32 form: with s = 1/sqrt(|B|^2) (hardware rsq, ~1 ulp), |B| = |B|^2 s and
+// e/|B| = 1 - T s, which needs neither a square root nor a division.
+template <int LOSS>
+__device__ inline float epilogue_f(float &x, float &y, float t) {
+    if (LOSS == COSIM_LOSS_MAG) {
+        // |B|^2 is clamped to a normal floor before rsq: at B = 0 this gives
+        // e = -t (loss t^2) and w = c B = 0 without a branch; below |B| ~ 1e-18
+        // the magnitude's derivative is singular anyway.
+        const float m2 = fmaf(x, x, y * y);
+        const float rs = __builtin_amdgcn_rsqf(fmaxf(m2, 1e-36f));
+        const float e = fmaf(m2, rs, -t);
+        const float c = fmaf(-t, rs, 1.0f);
+        x *= c;
+        y *= c;
+        return e * e;
+    } else {
+        const float ex = x - t;
+        x = ex;
+        return fmaf(ex, ex, y * y);
+    }
+}
+
+template <int LOSS, typename T>
+__device__ inline double epilogue(T &x, T &y, T t) {
+    if constexpr (sizeof(T) == 4) {
+        return (double)epilogue_f<LOSS>(x, y, t);
+    } else if (LOSS == COSIM_LOSS_MAG) {
+        const T mag = sqrt(x * x + y * y);
+        const T e = mag - t;
+        const T c = mag > T(0) ? e / mag : T(0);
+        x *= c;
+        y *= c;
+        return (double)e * (double)e;
+    } else {
+        const T ex = x - t;
+        const double v = (double)ex * ex + (double)y * y;
+        x = ex;
+        return v;
+    }
+}
+
+
+}  // namespace cosim

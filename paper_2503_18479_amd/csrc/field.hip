@@ -22,7 +22,7 @@ __global__ __launch_bounds__(256) void k_field(int NP, int P, int S, int n,
                                                const double *__restrict__ G64,
                                                const double2 *__restrict__ I,
                                                void *__restrict__ Bz) {
-    __shared__ double2 sI[kMaxLoops];
+    __shared__ double2 sI[kMaxLoopsBig];
     const int s = blockIdx.y;
     for (int k = threadIdx.x; k < n; k += blockDim.x) sI[k] = I[(size_t)s * n + k];
     __syncthreads();

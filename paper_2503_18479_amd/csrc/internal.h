@@ -28,10 +28,16 @@ struct GLRule {
 // Matrix-core precision of the superposition (mirrors cosim_precision).
 enum class Prec { F64 = 0, F32 = 1, BF16X3 = 2 };
 
-// Padded loop dimension used by the solver and the contraction kernels.
-inline int padded_loops(int n) { return n <= 16 ? 16 : (n <= 32 ? 32 : 64); }
-constexpr int kMaxLoops = 64;      // fused path and solver limit of this build
-constexpr int kPTile = 64;         // rows of G per LDS tile in the fused kernels
+// Padded loop dimension used by the solver and the contraction kernels:
+// 16, 32 or 64 for the register-resident (fused) path, a multiple of 64 above.
+constexpr int kMaxLoops = 64;       // largest loop count of the fused path
+constexpr int kMaxLoopsBig = 1024;  // largest loop count of this build
+inline int padded_loops(int n) {
+    return n <= 16 ? 16 : (n <= 32 ? 32 : (n + 63) / 64 * 64);
+}
+inline bool big_plan(int NP) { return NP > kMaxLoops; }
+constexpr int kPTile = 64;          // rows of G per LDS tile in the fused kernels
+constexpr int kBigRows = 2048;      // P-chunk of the adjoint GEMMs above 64 loops
 
 // ---------------------------------------------------------------------------
 // kernel launchers (implemented in the .hip files); all return hipError_t
@@ -127,6 +133,43 @@ hipError_t launch_adam(int count, double *C_d, const double *grad_d, double *m_d
 int fused_variant_count(Prec prec);
 int fused_systems_per_block(Prec prec, int NP, int variant);
 
+// ---- more than 64 loops: blocked LU with partial pivoting (solve_big.hip)
+// and GEMM-based contractions (contract_big.hip).
+// Right-hand side of launch_lu_solve.
+enum BigRhs {
+    kRhsExcitation = 0,  // -j w Phi, writes I
+    kRhsPairs = 1,       // rpart[c][s][k] (rr, ri) FP64 pairs, writes gsys
+    kRhsPlanarF32 = 2,   // R[c] NP x 2S FP32 planes, writes gsys
+    kRhsPlanarF64 = 3    // R[c] NP x 2S FP64 planes, writes gsys
+};
+hipError_t launch_lu_big(int NP, int n, int S, int F, const double *M_d, const double *R_d,
+                         const double *C_d, const double *omega_d, double2 *A_d, int *piv_d,
+                         int32_t *status_d, hipStream_t st);
+hipError_t launch_lu_solve(int NP, int n, int S, int F, const double2 *A_d, const int *piv_d,
+                           const double *phi_d, const double *C_d, const double *omega_d,
+                           double2 *I_d, int rhs_kind, const void *rhs_d, int nchunk,
+                           double rscale, double *gsys_d, int32_t *status_d, hipStream_t st);
+struct BigArgs {
+    int n, NP, P, P_pad, S, nchunk, rows;  // rows: P-chunk of the adjoint GEMMs
+    const void *G;                         // [P_pad][NP] FP64 or FP32 (F64 / F32)
+    const uint16_t *Ghi, *Glo;             // [P_pad][NP] bf16 hi / lo (BF16X3)
+    const double2 *I;                      // [S][n]
+    const double *T;                       // [P]
+    void *X;     // NP x 2S planes of I (BF16X3: hi planes, then lo planes)
+    void *Y;     // P_pad x 2S planes of B
+    void *W;     // P_pad x 2S planes of w (BF16X3: hi, then lo)
+    void *R;     // nchunk blocks of NP x 2S planes (double for F64, float otherwise)
+    double *lpart;  // [nchunk][S]
+};
+hipError_t big_blas_create(void **handle);
+void big_blas_destroy(void *handle);
+hipError_t big_contract(void *handle, Prec prec, int loss_mode, bool grad, const BigArgs &a,
+                        hipStream_t st);
+hipError_t big_adjoint(void *handle, Prec prec, const BigArgs &a, hipStream_t st);
+// W planes (FP64) of an upstream field gradient g[s][p] for big_adjoint.
+hipError_t launch_pack_w64(int P, int P_pad, int S, const double2 *g_d, double *W_d,
+                           hipStream_t st);
+
 // Materialised field B[s][p] (complex128 for F64, complex64 otherwise).
 hipError_t launch_field(Prec prec, int NP, int P, int S, int n, const double *G64,
                         const double2 *I_d, void *Bz_d, hipStream_t st);
@@ -167,6 +210,9 @@ struct cosim_plan {
     // optional phase timing: (COSIM_PHASES + 1) events per recorded call
     std::vector<hipEvent_t> events;
     int timing_cap = 0, timing_used = 0;
+    // more than 64 loops: GEMM operands and the rocBLAS handle
+    void *blas = nullptr;
+    void *bX = nullptr, *bY = nullptr, *bW = nullptr;
     bool ldl_ok = false;  // every R_k > 0: the LDL^T fast path applies
     int variant[3] = {0, 0, 0};  // fused-kernel variant per precision
 };

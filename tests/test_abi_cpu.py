@@ -89,8 +89,8 @@ def test_assemble_argument_errors(lib):
     assert lib.cosim_assemble(g, 10, ctypes.c_void_p(16), 1e-6, None, None) == EINVAL
     lib.cosim_geometry_destroy(g)
     # more loops than this build's solver supports
-    seg, v, a, R = _geom_args(n=65)
-    rc, g = _create(lib, 65, seg, v, a, R)
+    seg, v, a, R = _geom_args(n=1025)
+    rc, g = _create(lib, 1025, seg, v, a, R)
     assert rc == 0
     assert lib.cosim_assemble(g, 10, ctypes.c_void_p(16), 1e-6, None, ctypes.byref(out)) == EUNSUPPORTED
     lib.cosim_geometry_destroy(g)

@@ -45,13 +45,17 @@ def _nrel(a, b, axis=None):
 class Case:
     """A workload with its oracle operators and a GPU plan."""
 
-    def __init__(self, wl, dev, need_M_general=False):
+    def __init__(self, wl, dev, need_M_general=False, array_M=False):
         from paper_2503_18479_amd import Geometry, Plan
         self.wl = wl
         g = wl.geom
         self.G = O.field_matrix(g.verts, g.seg_off, wl.pts)
-        self.M = (O.inductance_matrix(g.verts, g.seg_off, g.wire_a) if need_M_general
-                  else O.inductance_matrix_fast(g.verts, g.seg_off, g.wire_a))
+        if array_M:
+            from array_oracle import oracle_M_array
+            self.M = oracle_M_array(g)
+        else:
+            self.M = (O.inductance_matrix(g.verts, g.seg_off, g.wire_a) if need_M_general
+                      else O.inductance_matrix_fast(g.verts, g.seg_off, g.wire_a))
         self.Phi = O.flux(g.verts, g.seg_off, wl.bext_z)
         self.geom = Geometry.from_workload(g)
         self.pts = torch.tensor(wl.pts, device=dev)
@@ -85,6 +89,13 @@ def _case(name):
     if name == "circle":  # config-1 geometry: non-parallel segment pairs
         wl = W.config1_single_loop(batch=16, grid=12)
         return Case(wl, dev, need_M_general=True)
+    # more than 64 loops: pivoted LU and GEMM contractions
+    if name == "n81":     # NP=128, 4,489 points: three adjoint P-chunks, ragged last
+        return Case(W.small_array(9, 9, batch=3, grid=67, n_freq=2, seed=5), dev, array_M=True)
+    if name == "n144":    # NP=192 (n not a multiple of 64)
+        return Case(W.small_array(12, 12, batch=2, grid=12, n_freq=2, seed=6), dev, array_M=True)
+    if name == "n256":    # NP=256, the largest size of the ragged configuration
+        return Case(W.small_array(16, 16, batch=2, grid=16, n_freq=1, seed=7), dev, array_M=True)
     raise KeyError(name)
 
 
@@ -466,3 +477,148 @@ def test_optimize_in_one_graph_equals_eager(dev):
     torch.cuda.synchronize()
     assert torch.equal(Ca, Cb) and torch.equal(ha, hb)
     assert not torch.equal(Ca, c.C)
+
+
+# ------------------------------------------------- more than 64 loops (LU + GEMM path)
+BIG = ["n81", "n144", "n256"]
+
+
+@pytest.mark.parametrize("name", BIG)
+def test_big_assembly_solve_and_field(dev, name):
+    c = _case(name)
+    _say(f"[big] {name}: n={c.wl.geom.n}")
+    assert _nrel(c.plan.G().cpu().numpy(), c.G) < 1e-12
+    assert _nrel(c.plan.M(), c.M) < 1e-12
+    I, st = c.plan.solve(c.C, c.om)
+    torch.cuda.synchronize()
+    assert int(st.abs().sum()) == 0
+    Ir = c.oracle_eval()[0]
+    assert _nrel(I.cpu().numpy(), Ir) < 1e-10
+    Br = O.field(c.G, Ir)
+    for prec in (0, 1, 2):
+        Bz = c.plan.field(I, prec)
+        torch.cuda.synchronize()
+        assert _nrel(Bz.cpu().numpy(), Br) < TOL[prec], prec
+
+
+@pytest.mark.parametrize("mode", [O.LOSS_MAG, O.LOSS_COMPLEX])
+@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("name", BIG)
+def test_big_loss_and_grad(dev, name, prec, mode):
+    c = _case(name)
+    _say(f"[big] {name} prec={prec} mode={mode}")
+    loss, grad, st = c.plan.loss_and_grad(c.C, c.om, c.T, loss_mode=mode, precision=prec)
+    torch.cuda.synchronize()
+    assert int(st.abs().sum()) == 0
+    Lr = c.oracle_eval(mode=mode)[2]
+    gr = c.oracle_grad(mode=mode)
+    el = np.abs(loss.cpu().numpy() - Lr) / Lr
+    eg = _nrel(grad.cpu().numpy(), gr, axis=1)
+    _say(f"[big] {name} prec={prec} mode={mode}: loss {el.max():.2e} grad {eg.max():.2e}")
+    assert el.max() < TOL[prec] and eg.max() < TOL[prec]
+
+
+def test_big_autograd_backward_matches_oracle(dev):
+    from paper_2503_18479_amd import cosim_field
+    c = _case("n81")
+    C = c.C.clone().requires_grad_(True)
+    Bz = cosim_field(C, c.plan, c.om, 0)
+    T = c.T.to(torch.float64)
+    L = ((Bz.abs() - T) ** 2).mean(dim=(1, 2))
+    L.sum().backward()
+    torch.cuda.synchronize()
+    gr = c.oracle_grad()
+    assert _nrel(C.grad.cpu().numpy(), gr) < 1e-9
+
+
+def test_big_without_resistance_pivots(dev):
+    """R = 0: the impedance has no positive Hermitian part; the pivoted LU of
+    the large-loop path handles it like any other system."""
+    from paper_2503_18479_amd import Geometry, Plan
+    from array_oracle import oracle_M_array
+    wl = W.small_array(9, 9, batch=2, grid=9, n_freq=2, seed=22)
+    g = wl.geom
+    g.R[:] = 0.0
+    G = O.field_matrix(g.verts, g.seg_off, wl.pts)
+    M = oracle_M_array(g)
+    Phi = O.flux(g.verts, g.seg_off, wl.bext_z)
+    plan = Plan(Geometry.from_workload(g), torch.tensor(wl.pts, device=dev), wl.bext_z)
+    C = torch.tensor(wl.C, device=dev); om = torch.tensor(wl.omega, device=dev)
+    T = torch.tensor(wl.target, device=dev)
+    loss, grad, st = plan.loss_and_grad(C, om, T, precision=0)
+    torch.cuda.synchronize()
+    assert int(st.abs().sum()) == 0
+    Lr = O.evaluate(G, M, g.R, Phi, wl.C, wl.omega, wl.target)[2]
+    gr = O.grad_adjoint(G, M, g.R, Phi, wl.C, wl.omega, wl.target)
+    assert np.max(np.abs(loss.cpu().numpy() - Lr) / Lr) < 1e-9
+    assert np.max(_nrel(grad.cpu().numpy(), gr, axis=1)) < 1e-9
+
+
+def test_big_bad_input_flags(dev):
+    c = _case("n144")
+    C = c.C.clone()
+    C[1, 5] = 0.0
+    C[0, 3] = -C[0, 3]
+    loss, grad, st = c.plan.loss_and_grad(C, c.om, c.T, precision=0)
+    torch.cuda.synchronize()
+    st = st.cpu().numpy()
+    assert np.all(st[1] & 1) and np.all(st[0] & 8) and not np.any(st[0] & 1)
+    assert np.isnan(loss[1].item()) and np.isfinite(loss[0].item())
+
+
+def test_full_size_array32x32_sampled(dev):
+    """The 32x32 array (1,024 loops) at 262,144 points: M in full, G at
+    sampled points and I for sampled configurations against the oracle; B_z
+    at sampled points against the oracle's; the fused loss against the mean
+    over all points of the FP64 materialised field; the FP64 gradient against
+    central differences of the FP64 loss; FP32 and BF16X3 against FP64."""
+    from paper_2503_18479_amd import Geometry, Plan
+    from array_oracle import oracle_M_array
+    wl = W.config5_array32x32(batch=8)
+    g = wl.geom
+    _say("[c5] assembling 32x32 / 262144 points")
+    pts = torch.tensor(wl.pts, device=dev)
+    plan = Plan(Geometry.from_workload(g), pts, wl.bext_z)
+    C = torch.tensor(wl.C, device=dev); om = torch.tensor(wl.omega, device=dev)
+    T = torch.tensor(wl.target, device=dev)
+    _say("[c5] oracle M (1,024 loops)")
+    Mr = oracle_M_array(g)
+    assert _nrel(plan.M(), Mr) < 1e-12
+    rng = np.random.default_rng(51)
+    prow = np.sort(rng.choice(wl.P, 256, replace=False))
+    Gr = O.field_matrix(g.verts, g.seg_off, wl.pts[prow])
+    Gd = plan.G()[torch.tensor(prow, device=dev)].cpu().numpy()
+    assert _nrel(Gd, Gr) < 1e-12
+    Phi = O.flux(g.verts, g.seg_off, wl.bext_z)
+    cs = [0, 5]
+    _say("[c5] solve")
+    I, st = plan.solve(C, om)
+    torch.cuda.synchronize()
+    assert int(st.abs().sum()) == 0
+    Ir = O.currents(Mr, g.R, Phi, wl.C[cs], wl.omega)
+    assert _nrel(I.cpu().numpy()[cs], Ir) < 1e-10
+    _say("[c5] field")
+    Bz = plan.field(I, 0)
+    torch.cuda.synchronize()
+    assert _nrel(Bz.cpu().numpy()[cs][:, :, prow], O.field(Gr, Ir)) < 1e-9
+    Lfield = ((Bz.abs() - T) ** 2).mean(dim=(1, 2)).cpu().numpy()
+    del Bz
+    res = {}
+    for prec in (0, 1, 2):
+        _say(f"[c5] loss_and_grad precision {prec}")
+        loss, grad, st = plan.loss_and_grad(C, om, T, precision=prec)
+        torch.cuda.synchronize()
+        assert int(st.abs().sum()) == 0
+        res[prec] = (loss.cpu().numpy(), grad.cpu().numpy())
+        assert np.max(np.abs(res[prec][0] - Lfield) / Lfield) < TOL[prec], prec
+    for prec in (1, 2):
+        assert np.max(_nrel(res[prec][1], res[0][1], axis=1)) < TOL[prec], prec
+    h = 1e-15
+    for k in (17, 600):
+        Cp = C.clone(); Cp[0, k] += h
+        Cm = C.clone(); Cm[0, k] -= h
+        lp = plan.loss_and_grad(Cp, om, T, precision=0, grad=False)[0][0].item()
+        lm = plan.loss_and_grad(Cm, om, T, precision=0, grad=False)[0][0].item()
+        fd = (lp - lm) / (2 * h)
+        _say(f"[c5] FD k={k}: {fd:.6e} vs {res[0][1][0, k]:.6e}")
+        assert abs(fd - res[0][1][0, k]) < 1e-4 * np.abs(res[0][1][0]).max()

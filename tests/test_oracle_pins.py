@@ -356,3 +356,12 @@ def test_adam_matches_torch_optimizer():
         opt.step()
         C, m, v = O.adam_step(C, g, m, v, t)
     np.testing.assert_allclose(C, p.detach().numpy(), rtol=1e-14, atol=0)
+
+
+def test_array_inductance_by_offsets_equals_direct_oracle():
+    """The offset-reuse builder used for large arrays in the GPU tests gives
+    the direct oracle's M (rectangular array, so offsets are not symmetric)."""
+    from array_oracle import oracle_M_array
+    g = W.square_array(4, 3, 0.03, 0.035, 32, 1e-3, 0.3)
+    M = O.inductance_matrix_fast(g.verts, g.seg_off, g.wire_a)
+    np.testing.assert_allclose(oracle_M_array(g), M, rtol=1e-13, atol=0)
