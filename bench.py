@@ -55,6 +55,8 @@ def parse():
                     help="skip cosim_plan_autotune (use the default kernel variants)")
     ap.add_argument("--profile-steps", type=int, default=None,
                     help="run only this many steps of the headline mode (for rocprofv3)")
+    ap.add_argument("--variant", type=int, default=None,
+                    help="with --profile-steps: use this fused-kernel variant instead of tuning")
     return ap.parse_args()
 
 
@@ -107,11 +109,22 @@ def cpu_baseline(wl, n_configs: int):
     O.evaluate(G, M, g.R, Phi, C, wl.omega, wl.target)
     O.grad_adjoint(G, M, g.R, Phi, C, wl.omega, wl.target)
     t_eval = time.perf_counter() - t0
+    one = None
+    try:  # the same work on one core, for two configurations
+        import threadpoolctl
+        with threadpoolctl.threadpool_limits(1):
+            t0 = time.perf_counter()
+            O.evaluate(G, M, g.R, Phi, C[:2], wl.omega, wl.target)
+            O.grad_adjoint(G, M, g.R, Phi, C[:2], wl.omega, wl.target)
+            one = 2 / (time.perf_counter() - t0)
+    except Exception:  # pragma: no cover
+        pass
     return {
         "value": n_configs / t_eval,
         "unit": "evals/s",
         "cores": int(threads),
         "kind": "oracle",
+        "value_one_core": one,
         "sample": (f"{n_configs} configurations x {wl.F} frequencies at all {wl.P} points "
                    f"(loss + adjoint gradient, {t_eval:.1f} s); G/M assembly by the oracle "
                    f"took {t_asm:.1f} s and is excluded, as on the GPU"),
@@ -146,7 +159,10 @@ def main():
     print(f"[bench] assembled {wl.summary()} in {t_asm:.2f} s", file=sys.stderr, flush=True)
 
     if args.profile_steps is not None:
-        time_mode(plan, C, om, T, args.mixed, args.profile_steps, 1, torch, tune=not args.no_autotune)
+        if args.variant is not None:
+            plan.set_variant(PREC_CODE[args.mixed], args.variant)
+        time_mode(plan, C, om, T, args.mixed, args.profile_steps, 1, torch,
+                  tune=not args.no_autotune and args.variant is None)
         # reference copy of known size (256 MiB read + 256 MiB written) that
         # calibrates the HBM byte counters of a profiler run
         x = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=dev)
@@ -185,13 +201,27 @@ def main():
     fused_ms = head["phase_ms"]["fused_contraction"]
     achieved = head["fused_tflops"]
     traffic = None
+    tuned_variant = (head["autotune"] or {}).get("variant", 0)
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as f:
             tr = json.load(f)
         if (tr.get("kernel_src_sha256_16") == _src_hash(FUSED_KERNEL_SRC)
                 and tr.get("precision") == args.mixed and tr.get("workload") == wl.name
                 and tr.get("batch") == wl.B and tr.get("points") == wl.P):
-            traffic = tr.get("bytes_per_launch")
+            traffic = (tr.get("variants") or {}).get(str(tuned_variant), {}).get("bytes_per_launch")
+    # FP64 solve phases: LDL^T (4/3 n^3 real flops) + one substitution pair
+    # (8 n^2) per system in the forward phase, one substitution pair in the
+    # adjoint phase; the factor record is n(n-1)/2 complex per system.
+    n = g.n
+    rec_bytes = S * n * (n - 1) / 2 * 16.0
+    phases = {}
+    for name, flops_ps, byts in (("solve_forward", 4.0 / 3.0 * n ** 3 + 8.0 * n * n, 2 * rec_bytes),
+                                 ("solve_adjoint", 8.0 * n * n, rec_bytes)):
+        ms = head["phase_ms"][name]
+        tf = S * flops_ps / (ms * 1e-3) / 1e12
+        gbs = byts / (ms * 1e-3) / 1e9
+        phases[name] = {"ms": ms, "fp64_tflops": tf, "fp64_frac": tf / PEAK_TFLOPS["fp64"],
+                        "record_gbs": gbs, "hbm_frac": gbs / 8000.0}
 
     line = {
         "metric": "fwd+adjoint C->B_z evals/sec, 8x8 array, 65k pts: mixed vs FP64, same GPU",
@@ -209,7 +239,7 @@ def main():
         "config": {
             "workload": wl.name, "loops": g.n, "segments_per_loop": 32, "points": wl.P,
             "freqs": wl.F, "batch": wl.B, "systems": S, "precision": args.mixed,
-            "solve": "fp64 Gauss-Jordan, partial pivoting", "loss": "magnitude MSE",
+            "solve": "fp64 LDL^T (pivoted fallback)", "loss": "magnitude MSE",
         },
         "fp64": {"value": res["fp64"]["evals_per_s"], "ms_per_step": res["fp64"]["ms_per_step"],
                  "steps": res["fp64"]["steps"]},
@@ -225,6 +255,8 @@ def main():
             "traffic": traffic,
             "flops_per_launch": flops,
             "avg_launch_ms": fused_ms,
+            "variant": tuned_variant,
+            "phases": phases,
         },
     }
     if args.cpu_configs > 0:

@@ -504,8 +504,11 @@ __global__ __launch_bounds__(256) void k_ldl(int n, int S, int F, const double *
     constexpr int NBLK = NB * (NB + 1) / 2;
     typedef double f64x4 __attribute__((ext_vector_type(4)));
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    __shared__ double2 sPan[4][NP][4];  // per wave: panel rows (A, then L21)
-    __shared__ double2 sV[4][NP][4];    // per wave: V21 rows
+    // per wave: panel rows (A, then L21) and V21 rows; a row holds 4 entries
+    // padded to 5 (80 bytes), so that the row-per-lane accesses of 16
+    // consecutive lanes fall on disjoint LDS banks
+    __shared__ double2 sPan[4][NP][5];
+    __shared__ double2 sV[4][NP][5];
     const int s = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + wv));
     if (s >= S) return;  // whole wave; the block never synchronises
     const int b = s / F, f = s - b * F;
@@ -566,8 +569,8 @@ __global__ __launch_bounds__(256) void k_ldl(int n, int S, int F, const double *
     }
     double dmin = __builtin_inf();
 
-    double2 (*pan)[4] = sPan[wv];
-    double2 (*vv)[4] = sV[wv];
+    double2 (*pan)[5] = sPan[wv];
+    double2 (*vv)[5] = sV[wv];
 #pragma unroll
     for (int bc = 0; bc < NB; ++bc) {
         for (int pp = 0; pp < 4; ++pp) {
