@@ -311,10 +311,10 @@ struct Bf3Stage {
                 tl[u] = *(const u32x4 *)(a.GTlo + to);
             }
         }
-        if (threadIdx.x < PT) {
-            const int p = p0 + threadIdx.x;
-            t = p < a.P ? (float)a.T[p] : 0.0f;
-        }
+        // every thread holds the target of row threadIdx.x % PT, so that the
+        // store below needs no branch (equal values to equal addresses)
+        const int p = p0 + (int)(threadIdx.x & (PT - 1));
+        t = p < a.P ? (float)a.T[p] : 0.0f;
     }
     __device__ __forceinline__ void stash(uint16_t *sH, uint16_t *sL, uint16_t *tH, uint16_t *tL,
                                           float *sT) const {
@@ -331,7 +331,7 @@ struct Bf3Stage {
                 *(u32x4 *)(tL + trow * LDT + tcol) = tl[u];
             }
         }
-        if (threadIdx.x < PT) sT[threadIdx.x] = t;
+        sT[threadIdx.x & (PT - 1)] = t;
     }
 };
 
@@ -625,14 +625,15 @@ __global__ __launch_bounds__(256, 2) void k_fused_bf16x3_pipe(FusedArgs a) {
 // the default; cosim_plan_autotune picks per plan and precision.
 struct Variant {
     int nb, pt;
-    bool db, pipe;
+    bool db;
+    int pipe;  // 0: sub-tile by sub-tile, 1: look-ahead forward of the next sub-tile
 };
-constexpr Variant kVarF64[] = {{1, 64, false, false}, {2, 64, false, false}};
-constexpr Variant kVarF32[] = {{2, 64, false, false}, {1, 64, false, false}};
-constexpr Variant kVarBF16[] = {{2, 64, false, false}, {2, 32, false, false}, {1, 64, false, false},
-                                {1, 32, false, false}, {2, 64, true, false},  {2, 32, true, false},
-                                {1, 64, true, true},   {1, 32, true, true},   {2, 32, true, true},
-                                {2, 64, true, true}};
+constexpr Variant kVarF64[] = {{1, 64, false, 0}, {2, 64, false, 0}};
+constexpr Variant kVarF32[] = {{2, 64, false, 0}, {1, 64, false, 0}};
+constexpr Variant kVarBF16[] = {{2, 64, false, 0}, {2, 32, false, 0}, {1, 64, false, 0},
+                                {1, 32, false, 0}, {2, 64, true, 0},  {2, 32, true, 0},
+                                {1, 64, true, 1},  {1, 32, true, 1},  {2, 32, true, 1},
+                                {2, 64, true, 1}};
 
 template <typename T, int NP, int NB, int LOSS, bool GRAD>
 hipError_t go_typed(const FusedArgs &a, hipStream_t st) {
@@ -642,11 +643,11 @@ hipError_t go_typed(const FusedArgs &a, hipStream_t st) {
     return hipGetLastError();
 }
 
-template <int NP, int NB, int PT, bool DB, bool PIPE, int LOSS, bool GRAD>
+template <int NP, int NB, int PT, bool DB, int PIPE, int LOSS, bool GRAD>
 hipError_t go_bf16(const FusedArgs &a, hipStream_t st) {
     const int per_block = 4 * 16 * NB;
     dim3 grid((a.S + per_block - 1) / per_block, a.nchunk);
-    if constexpr (PIPE)
+    if constexpr (PIPE == 1)
         hipLaunchKernelGGL((k_fused_bf16x3_pipe<NP, NB, PT, LOSS, GRAD>), grid, dim3(256), 0, st, a);
     else
         hipLaunchKernelGGL((k_fused_bf16x3<NP, NB, PT, DB, LOSS, GRAD>), grid, dim3(256), 0, st, a);
