@@ -55,6 +55,9 @@ def parse():
                     help="skip cosim_plan_autotune (use the default kernel variants)")
     ap.add_argument("--profile-steps", type=int, default=None,
                     help="run only this many steps of the headline mode (for rocprofv3)")
+    ap.add_argument("--ragged", type=int, default=256,
+                    help="also time this many independent instances of the ragged configuration "
+                         "(16-256 loops, 16k-65k points, 1-8 frequencies; 2048 is the full set; 0: skip)")
     ap.add_argument("--variant", type=int, default=None,
                     help="with --profile-steps: use this fused-kernel variant instead of tuning")
     return ap.parse_args()
@@ -129,6 +132,42 @@ def cpu_baseline(wl, n_configs: int):
                    f"(loss + adjoint gradient, {t_eval:.1f} s); G/M assembly by the oracle "
                    f"took {t_asm:.1f} s and is excluded, as on the GPU"),
     }
+
+
+def ragged_line(n_inst: int, mixed: str, steps: int, torch) -> dict:
+    """Independent instances of the ragged configuration, one
+    cosim_loss_and_grad_many call per step (plans keep only the mixed
+    precision's copies of G)."""
+    import workloads as W
+    from paper_2503_18479_amd import Geometry, Plan, loss_and_grad_many
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    wls = W.config4_instances(n_inst)
+    plans, Cs, Os, Ts = [], [], [], []
+    for wl in wls:
+        pl = Plan(Geometry.from_workload(wl.geom), torch.tensor(wl.pts, device=dev), wl.bext_z,
+                  precisions=[mixed])
+        pl.reserve(wl.B, wl.F)
+        plans.append(pl)
+        Cs.append(torch.tensor(wl.C, device=dev))
+        Os.append(torch.tensor(wl.omega, device=dev))
+        Ts.append(torch.tensor(wl.target, device=dev))
+    t_setup = time.perf_counter() - t0
+    outs = loss_and_grad_many(plans, Cs, Os, Ts, precision=PREC_CODE[mixed])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        loss_and_grad_many(plans, Cs, Os, Ts, precision=PREC_CODE[mixed], outs=outs)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    bad = sum(int((o[2] != 0).sum()) for o in outs)
+    systems = sum(wl.B * wl.F for wl in wls)
+    flops = sum(8.0 * wl.P * wl.geom.n * wl.B * wl.F for wl in wls)
+    return {"instances": n_inst, "instance_evals_per_s": n_inst / dt, "ms_per_step": 1e3 * dt,
+            "steps": steps, "systems": systems, "contraction_tflops": flops / dt / 1e12,
+            "loops": sorted(set(wl.geom.n for wl in wls)), "points_min": min(wl.P for wl in wls),
+            "points_max": max(wl.P for wl in wls), "flagged_systems": bad,
+            "setup_s": t_setup, "precision": mixed}
 
 
 def main():
@@ -259,6 +298,13 @@ def main():
             "phases": phases,
         },
     }
+    if args.ragged > 0:
+        print(f"[bench] ragged configuration: {args.ragged} instances", file=sys.stderr, flush=True)
+        del plan
+        torch.cuda.empty_cache()
+        line["ragged"] = ragged_line(args.ragged, args.mixed, 3, torch)
+        print(f"[bench] ragged: {line['ragged']['ms_per_step']:.1f} ms per step", file=sys.stderr,
+              flush=True)
     if args.cpu_configs > 0:
         print("[bench] timing the oracle on the host", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(wl, args.cpu_configs)

@@ -60,6 +60,9 @@ enum cosim_precision {
     COSIM_BF16X3 = 2  /* bf16 hi/lo split of both operands, 3 products, FP32 accumulation */
 };
 
+/* Masks of precisions for cosim_assemble_ex: bit (1 << precision). */
+enum { COSIM_PREC_ALL = (1 << COSIM_FP64) | (1 << COSIM_FP32) | (1 << COSIM_BF16X3) };
+
 /* Loss of Eq. 1 per configuration b, mean over frequencies f and points p:
  *   MAG:     L_b = 1/(F P) sum_{f,p} (|B_z| - T_p)^2   (magnitude targets)
  *   COMPLEX: L_b = 1/(F P) sum_{f,p} |B_z - T_p|^2                          */
@@ -116,6 +119,15 @@ int cosim_geometry_size(cosim_geom_t g, int *n_loops, int *n_verts);
  * -------------------------------------------------------------------------- */
 int cosim_assemble(cosim_geom_t g, int P, const double *pts_d, double bext_z, void *stream,
                    cosim_plan_t *out);
+/* The same, keeping only the copies of G that the precisions in the mask
+ * `precisions` (bits 1 << COSIM_FP64 / FP32 / BF16X3, non-empty subset of
+ * COSIM_PREC_ALL) need: 8, 4 and 8 bytes per entry of G.  Calls that read a
+ * missing copy return COSIM_EINVAL: cosim_loss_and_grad and
+ * cosim_plan_autotune in a precision outside the mask, and cosim_field,
+ * cosim_field_backward and cosim_plan_copy_G without the FP64 bit.  For many
+ * plans at once (independent instances). */
+int cosim_assemble_ex(cosim_geom_t g, int P, const double *pts_d, double bext_z, int precisions,
+                      void *stream, cosim_plan_t *out);
 int cosim_plan_destroy(cosim_plan_t p);
 /* Loops n, points P of a plan. */
 int cosim_plan_size(cosim_plan_t p, int *n_loops, int *n_points);
@@ -196,6 +208,23 @@ int cosim_loss_and_grad(cosim_plan_t p, int B, int F, const double *C_d, const d
 int cosim_adam_step(int count, double *C_d, const double *grad_d, double *m_d, double *v_d,
                     int32_t *step_d, double lr, double beta1, double beta2, double eps,
                     void *stream);
+
+/* cosim_loss_and_grad over `count` independent instances (own geometry,
+ * points, targets, batch and frequencies; e.g. unevenly sized arrays).  Host
+ * arrays of `count` entries: plans[i] (each plan at most once), B[i], F[i],
+ * and the device pointers of instance i with the meaning and shapes of
+ * cosim_loss_and_grad (grad_d may be NULL for loss only, or hold NULL
+ * entries).  Every instance is validated before anything is enqueued; an
+ * error names the instance.  The instances run on 8 library-owned side
+ * streams (default priority) that wait for `stream` and that `stream` waits
+ * for when the call returns, so the work is ordered on `stream` as one
+ * operation and can be captured with it.  Each plan's own workspace is used:
+ * reserve every plan beforehand to keep the call allocation-free. */
+int cosim_loss_and_grad_many(int count, const cosim_plan_t *plans, const int *B, const int *F,
+                             const double *const *C_d, const double *const *omega_d,
+                             const double *const *T_d, int loss_mode, int precision,
+                             double *const *loss_d, double *const *grad_d,
+                             int32_t *const *status_d, void *stream);
 
 /* --------------------------------------------------------------------------
  * Tuning of the fused contraction (performance only; every variant computes

@@ -35,6 +35,10 @@ SIGNATURES = {
                                      c_void_p, c_void_p, c_void_p]),
     "cosim_loss_and_grad": (c_int, [c_void_p, c_int, c_int, c_void_p, c_void_p, c_void_p, c_int,
                                     c_int, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "cosim_assemble_ex": (c_int, [c_void_p, c_int, c_void_p, c_double, c_int, c_void_p, P(c_void_p)]),
+    "cosim_loss_and_grad_many": (c_int, [c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                         c_void_p, c_int, c_int, c_void_p, c_void_p, c_void_p,
+                                         c_void_p]),
     "cosim_adam_step": (c_int, [c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_double,
                                 c_double, c_double, c_double, c_void_p]),
     "cosim_plan_set_variant": (c_int, [c_void_p, c_int, c_int]),

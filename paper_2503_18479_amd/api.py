@@ -86,15 +86,26 @@ class Geometry:
 
 
 class Plan:
-    """Assembled operators G, M, Phi for one geometry and point set."""
+    """Assembled operators G, M, Phi for one geometry and point set.
 
-    def __init__(self, geom: Geometry, pts: torch.Tensor, bext_z: float = 1e-6):
+    precisions: None for every precision, or an iterable of precisions whose
+    copies of G the plan keeps (cosim_assemble_ex)."""
+
+    def __init__(self, geom: Geometry, pts: torch.Tensor, bext_z: float = 1e-6,
+                 precisions=None):
         self._lib = load_library()
         P = int(pts.shape[0])
         ptr = _dev(pts, torch.float64, (P, 3), "pts")
         h = ctypes.c_void_p()
-        check(self._lib.cosim_assemble(geom.handle, P, ptr, float(bext_z), _stream(),
-                                       ctypes.byref(h)))
+        if precisions is None:
+            check(self._lib.cosim_assemble(geom.handle, P, ptr, float(bext_z), _stream(),
+                                           ctypes.byref(h)))
+        else:
+            mask = 0
+            for pr in precisions:
+                mask |= 1 << precision_code(pr)
+            check(self._lib.cosim_assemble_ex(geom.handle, P, ptr, float(bext_z), mask, _stream(),
+                                              ctypes.byref(h)))
         self._h = h
         self.n = geom.n
         self.P = P
@@ -257,6 +268,36 @@ class Plan:
             gr.replay()
             hist[k].copy_(loss)
         return hist, st
+
+
+def loss_and_grad_many(plans, Cs, omegas, Ts, loss_mode: int = LOSS_MAG, precision=FP32,
+                       grad: bool = True, outs=None):
+    """cosim_loss_and_grad_many over independent instances (lists of equal
+    length).  Returns lists of per-instance (loss, grad or None, status)."""
+    lib = load_library()
+    k = len(plans)
+    prec = precision_code(precision)
+    Bs = [int(C.shape[0]) for C in Cs]
+    Fs = [int(o.shape[0]) for o in omegas]
+    if outs is None:
+        outs = []
+        for pl, B, F in zip(plans, Bs, Fs):
+            outs.append((torch.empty((B,), dtype=torch.float64, device=pl.device),
+                         torch.empty((B, pl.n), dtype=torch.float64, device=pl.device) if grad else None,
+                         torch.empty((B, F), dtype=torch.int32, device=pl.device)))
+    ptrs = lambda xs: (ctypes.c_void_p * k)(*[ctypes.c_void_p(x) for x in xs])
+    arr_p = (ctypes.c_void_p * k)(*[pl._h for pl in plans])
+    arr_B = (ctypes.c_int * k)(*Bs)
+    arr_F = (ctypes.c_int * k)(*Fs)
+    c_p = ptrs([_dev(C, torch.float64, (B, pl.n), "C").value for C, B, pl in zip(Cs, Bs, plans)])
+    o_p = ptrs([_dev(o, torch.float64, (F,), "omega").value for o, F in zip(omegas, Fs)])
+    t_p = ptrs([_dev(T, torch.float64, (pl.P,), "T").value for T, pl in zip(Ts, plans)])
+    l_p = ptrs([o[0].data_ptr() for o in outs])
+    g_p = ptrs([o[1].data_ptr() for o in outs]) if grad else None
+    s_p = ptrs([o[2].data_ptr() for o in outs])
+    check(lib.cosim_loss_and_grad_many(k, arr_p, arr_B, arr_F, c_p, o_p, t_p, int(loss_mode), prec,
+                                       l_p, g_p, s_p, _stream()))
+    return outs
 
 
 def adam_step(C: torch.Tensor, grad: torch.Tensor, m: torch.Tensor, v: torch.Tensor,

@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "internal.h"
@@ -203,6 +204,65 @@ int check_batch(const cosim_plan *p, int B, int F) {
     return COSIM_OK;
 }
 
+// Side streams of the multi-instance call, per device, created on first use
+// and kept for the life of the process (default priority), with one event per
+// stream to join back and one to fork from.
+struct StreamPool {
+    int device = -1;
+    std::vector<hipStream_t> streams;
+    std::vector<hipEvent_t> done;
+    hipEvent_t start = nullptr;
+};
+constexpr int kPoolStreams = 8;
+
+int stream_pool(int device, StreamPool **out) {
+    static std::mutex mu;
+    static std::vector<StreamPool *> pools;
+    std::lock_guard<std::mutex> lock(mu);
+    for (StreamPool *p : pools)
+        if (p->device == device) {
+            *out = p;
+            return COSIM_OK;
+        }
+    StreamPool *p = new (std::nothrow) StreamPool;
+    if (!p) return fail(COSIM_ENOMEM, "host allocation failed");
+    p->device = device;
+    bool ok = hipEventCreateWithFlags(&p->start, hipEventDisableTiming) == hipSuccess;
+    for (int i = 0; ok && i < kPoolStreams; ++i) {
+        hipStream_t st = nullptr;
+        hipEvent_t ev = nullptr;
+        ok = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess &&
+             hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess;
+        if (st) p->streams.push_back(st);
+        if (ev) p->done.push_back(ev);
+    }
+    if (!ok) {
+        for (hipStream_t st : p->streams) (void)hipStreamDestroy(st);
+        for (hipEvent_t ev : p->done) (void)hipEventDestroy(ev);
+        if (p->start) (void)hipEventDestroy(p->start);
+        delete p;
+        (void)hipGetLastError();
+        return fail(COSIM_EDEVICE, "creating the side streams failed");
+    }
+    pools.push_back(p);
+    *out = p;
+    return COSIM_OK;
+}
+
+// Prefixes the current error message with the index of a multi-instance call.
+int fail_instance(int code, int i) {
+    char msg[sizeof(g_err)];
+    std::snprintf(msg, sizeof(msg), "%s", g_err);
+    return fail(code, "instance %d: %s", i, msg);
+}
+
+int check_assembled(const cosim_plan *p, int precision) {
+    if (!(p->prec_mask & (1 << precision)))
+        return fail(COSIM_EINVAL, "the plan was assembled without precision %d (mask %d)", precision,
+                    p->prec_mask);
+    return COSIM_OK;
+}
+
 int check_prec(int precision) {
     if (precision < COSIM_FP64 || precision > COSIM_BF16X3)
         return fail(COSIM_EINVAL, "unknown precision %d", precision);
@@ -274,12 +334,20 @@ int cosim_geometry_size(cosim_geom_t g, int *n_loops, int *n_verts) {
 
 int cosim_assemble(cosim_geom_t g, int P, const double *pts_d, double bext_z, void *stream,
                    cosim_plan_t *out) {
+    return cosim_assemble_ex(g, P, pts_d, bext_z, COSIM_PREC_ALL, stream, out);
+}
+
+int cosim_assemble_ex(cosim_geom_t g, int P, const double *pts_d, double bext_z, int precisions,
+                      void *stream, cosim_plan_t *out) {
     if (!out) return fail(COSIM_EINVAL, "out is null");
     *out = nullptr;
     if (!g) return fail(COSIM_EINVAL, "null geometry");
     if (P < 1) return fail(COSIM_EINVAL, "P must be >= 1 (got %d)", P);
     if (!pts_d) return fail(COSIM_EINVAL, "pts_d is null");
     if (!std::isfinite(bext_z)) return fail(COSIM_EINVAL, "bext_z is not finite");
+    if (precisions <= 0 || (precisions & ~COSIM_PREC_ALL))
+        return fail(COSIM_EINVAL, "precision mask %d is not a non-empty subset of %d", precisions,
+                    COSIM_PREC_ALL);
     if (g->n > kMaxLoopsBig)
         return fail(COSIM_EUNSUPPORTED, "%d loops: this build supports up to %d loops per plan",
                     g->n, kMaxLoopsBig);
@@ -295,6 +363,9 @@ int cosim_assemble(cosim_geom_t g, int P, const double *pts_d, double bext_z, vo
     for (int k = 0; k < g->n; ++k) p->phi_h[k] = bext_z * g->area_z[k];
     p->ldl_ok = true;
     for (int k = 0; k < g->n; ++k) p->ldl_ok = p->ldl_ok && g->R[k] > 0.0;
+    p->prec_mask = precisions;
+    const bool want64 = precisions & (1 << COSIM_FP64), want32 = precisions & (1 << COSIM_FP32);
+    const bool want16 = precisions & (1 << COSIM_BF16X3);
 
     int32_t *seg_d = nullptr;
     double *verts_d = nullptr, *wa_d = nullptr;
@@ -311,12 +382,13 @@ int cosim_assemble(cosim_geom_t g, int P, const double *pts_d, double bext_z, vo
     if (hipGetDevice(&p->device) != hipSuccess) return cleanup(fail(COSIM_EDEVICE, "hipGetDevice failed"));
     const size_t gsz = (size_t)p->P_pad * p->NP;
     const size_t n = (size_t)g->n;
-    if (hipMalloc((void **)&p->G64, gsz * sizeof(double)) != hipSuccess ||
-        hipMalloc((void **)&p->G32, gsz * sizeof(float)) != hipSuccess ||
-        hipMalloc((void **)&p->Ghi, gsz * sizeof(uint16_t)) != hipSuccess ||
-        hipMalloc((void **)&p->Glo, gsz * sizeof(uint16_t)) != hipSuccess ||
-        (!big_plan(p->NP) && (hipMalloc((void **)&p->GThi, gsz * sizeof(uint16_t)) != hipSuccess ||
-                              hipMalloc((void **)&p->GTlo, gsz * sizeof(uint16_t)) != hipSuccess)) ||
+    if ((want64 && hipMalloc((void **)&p->G64, gsz * sizeof(double)) != hipSuccess) ||
+        (want32 && hipMalloc((void **)&p->G32, gsz * sizeof(float)) != hipSuccess) ||
+        (want16 && hipMalloc((void **)&p->Ghi, gsz * sizeof(uint16_t)) != hipSuccess) ||
+        (want16 && hipMalloc((void **)&p->Glo, gsz * sizeof(uint16_t)) != hipSuccess) ||
+        (want16 && !big_plan(p->NP) &&
+         (hipMalloc((void **)&p->GThi, gsz * sizeof(uint16_t)) != hipSuccess ||
+          hipMalloc((void **)&p->GTlo, gsz * sizeof(uint16_t)) != hipSuccess)) ||
         hipMalloc((void **)&p->M_d, n * n * sizeof(double)) != hipSuccess ||
         hipMalloc((void **)&p->phi_d, n * sizeof(double)) != hipSuccess ||
         hipMalloc((void **)&p->R_d, n * sizeof(double)) != hipSuccess ||
@@ -391,8 +463,9 @@ int cosim_plan_reserve(cosim_plan_t p, int max_batch, int max_freq) {
 int cosim_plan_copy_G(cosim_plan_t p, double *G_d, void *stream) {
     if (!p) return fail(COSIM_EINVAL, "null plan");
     if (!G_d) return fail(COSIM_EINVAL, "G_d is null");
-    int rc = check_device(p);
+    int rc = check_assembled(p, COSIM_FP64);
     if (rc) return rc;
+    if ((rc = check_device(p))) return rc;
     // the plan stores rows of NP (>= n) columns; copy the n leading columns
     HIP_TRY(hipMemcpy2DAsync(G_d, (size_t)p->n * sizeof(double), p->G64, (size_t)p->NP * sizeof(double),
                              (size_t)p->n * sizeof(double), (size_t)p->P, hipMemcpyDeviceToDevice,
@@ -443,6 +516,7 @@ int cosim_field(cosim_plan_t p, int B, int F, const double *I_d, int precision, 
     if (rc) return rc;
     if (B == 0 || F == 0) return COSIM_OK;  // empty batch: nothing to do
     if ((rc = check_prec(precision))) return rc;
+    if ((rc = check_assembled(p, COSIM_FP64))) return rc;  // every precision reads the FP64 copy
     if (!I_d || !Bz_d) return fail(COSIM_EINVAL, "null device pointer");
     if ((rc = check_device(p))) return rc;
     const int S = B * F;
@@ -463,6 +537,7 @@ int cosim_field_backward(cosim_plan_t p, int B, int F, const double *C_d, const 
     int rc = check_batch(p, B, F);
     if (rc) return rc;
     if (B == 0 || F == 0) return COSIM_OK;  // empty batch: nothing to do
+    if ((rc = check_assembled(p, COSIM_FP64))) return rc;
     if (!C_d || !omega_d || !I_d || !gBz_d || !gC_d || !status_d)
         return fail(COSIM_EINVAL, "null device pointer");
     if ((rc = check_device(p))) return rc;
@@ -500,12 +575,11 @@ int cosim_loss_and_grad(cosim_plan_t p, int B, int F, const double *C_d, const d
     if (rc) return rc;
     if (B == 0 || F == 0) return COSIM_OK;  // empty batch: nothing to do
     if ((rc = check_prec(precision))) return rc;
+    if ((rc = check_assembled(p, precision))) return rc;
     if (loss_mode != COSIM_LOSS_MAG && loss_mode != COSIM_LOSS_COMPLEX)
         return fail(COSIM_EINVAL, "unknown loss mode %d", loss_mode);
     if (!C_d || !omega_d || !T_d || !loss_d || !status_d)
         return fail(COSIM_EINVAL, "null device pointer");
-    if (precision == COSIM_BF16X3 && p->NP % 32 != 0)
-        return fail(COSIM_EUNSUPPORTED, "BF16X3 needs more than 16 loops in this build (n = %d)", p->n);
     if ((rc = check_device(p))) return rc;
     const size_t S = (size_t)B * F;
     const Prec prec = (Prec)precision;
@@ -600,6 +674,57 @@ int cosim_adam_step(int count, double *C_d, const double *grad_d, double *m_d, d
     return COSIM_OK;
 }
 
+int cosim_loss_and_grad_many(int count, const cosim_plan_t *plans, const int *B, const int *F,
+                             const double *const *C_d, const double *const *omega_d,
+                             const double *const *T_d, int loss_mode, int precision,
+                             double *const *loss_d, double *const *grad_d,
+                             int32_t *const *status_d, void *stream) {
+    if (count < 0) return fail(COSIM_EINVAL, "count = %d", count);
+    if (count == 0) return COSIM_OK;
+    if (!plans || !B || !F || !C_d || !omega_d || !T_d || !loss_d || !status_d)
+        return fail(COSIM_EINVAL, "null host array");
+    int rc = check_prec(precision);
+    if (rc) return rc;
+    if (loss_mode != COSIM_LOSS_MAG && loss_mode != COSIM_LOSS_COMPLEX)
+        return fail(COSIM_EINVAL, "unknown loss mode %d", loss_mode);
+    // every instance is checked before anything is enqueued
+    for (int i = 0; i < count; ++i) {
+        if ((rc = check_batch(plans[i], B[i], F[i])))
+            return fail_instance(rc, i);
+        if ((size_t)B[i] * F[i] == 0) continue;
+        if ((rc = check_assembled(plans[i], precision)) || (rc = check_device(plans[i])))
+            return fail_instance(rc, i);
+        if (!C_d[i] || !omega_d[i] || !T_d[i] || !loss_d[i] || !status_d[i])
+            return fail(COSIM_EINVAL, "instance %d: null device pointer", i);
+    }
+    {  // a plan's workspace serves one instance at a time
+        std::vector<cosim_plan_t> sorted(plans, plans + count);
+        std::sort(sorted.begin(), sorted.end());
+        if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
+            return fail(COSIM_EINVAL, "a plan appears more than once");
+    }
+    // instances run on side streams (round robin) that wait for `stream` and
+    // that `stream` waits for afterwards
+    StreamPool *pool = nullptr;
+    if ((rc = stream_pool(plans[0]->device, &pool))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(hipEventRecord(pool->start, st));
+    const int ns = std::min(kPoolStreams, count);
+    for (int k = 0; k < ns; ++k) HIP_TRY(hipStreamWaitEvent(pool->streams[k], pool->start, 0));
+    int first_rc = COSIM_OK;
+    for (int i = 0; i < count && first_rc == COSIM_OK; ++i) {
+        if ((rc = cosim_loss_and_grad(plans[i], B[i], F[i], C_d[i], omega_d[i], T_d[i], loss_mode,
+                                      precision, loss_d[i], grad_d ? grad_d[i] : nullptr,
+                                      status_d[i], pool->streams[i % ns])))
+            first_rc = fail_instance(rc, i);
+    }
+    for (int k = 0; k < ns; ++k) {  // join even after an error
+        HIP_TRY(hipEventRecord(pool->done[k], pool->streams[k]));
+        HIP_TRY(hipStreamWaitEvent(st, pool->done[k], 0));
+    }
+    return first_rc;
+}
+
 int cosim_plan_set_variant(cosim_plan_t p, int precision, int variant) {
     if (!p) return fail(COSIM_EINVAL, "null plan");
     int rc = check_prec(precision);
@@ -626,6 +751,7 @@ int cosim_plan_autotune(cosim_plan_t p, int B, int F, const double *C_d, const d
     int rc = check_batch(p, B, F);
     if (rc) return rc;
     if ((rc = check_prec(precision))) return rc;
+    if ((rc = check_assembled(p, precision))) return rc;
     if (B == 0 || F == 0) return COSIM_OK;
     if (!C_d || !omega_d || !T_d) return fail(COSIM_EINVAL, "null device pointer");
     if (reps < 1) return fail(COSIM_EINVAL, "reps must be >= 1");

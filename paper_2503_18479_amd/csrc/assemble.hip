@@ -102,12 +102,14 @@ __global__ __launch_bounds__(256) void k_assemble_G(int n, int NP, int P, int P_
             if (pr >= P_pad) continue;
             const double g = tile[r][kk];
             const size_t o = (size_t)pr * NP + k0 + kk;
-            G64[o] = g;
             const float g32 = (float)g;
-            G32[o] = g32;
-            const uint16_t hi = bf16_rne(g32);
-            Ghi[o] = hi;
-            Glo[o] = bf16_rne(g32 - bf16_to_f(hi));
+            if (G64) G64[o] = g;  // copies the plan did not ask for are null
+            if (G32) G32[o] = g32;
+            if (Ghi) {
+                const uint16_t hi = bf16_rne(g32);
+                Ghi[o] = hi;
+                Glo[o] = bf16_rne(g32 - bf16_to_f(hi));
+            }
         }
         // transposed bf16 copies [NP][P_pad]: each loop's column is contiguous in p
         if (GThi) {

@@ -221,34 +221,65 @@ hipError_t big_contract(void *handle, Prec prec, int loss_mode, bool grad, const
     return big_adjoint(handle, prec, a, st);
 }
 
-// Adjoint GEMMs only (W already holds the planes of w).
+// One adjoint product over `nb` consecutive chunks of `rows` rows starting at
+// row p0: C_c = A_c B_c for c < nb, with A_c = G rows [p0 + c rows, ...) (NP x
+// rows, column-major), B_c the same rows of W (rows x 2S, ld P_pad), C_c the
+// chunk's NP x 2S block of R; one strided-batched call.
+hipError_t gemm_chunks(rocblas_handle h, Prec prec, int NP, int planes, int rows, int nb, int P_pad,
+                       const char *A, size_t a_esz, const char *B, size_t b_esz, float beta, char *C,
+                       size_t c_esz) {
+    const rocblas_operation N_ = rocblas_operation_none;
+    const rocblas_stride sa = (rocblas_stride)rows * NP, sb = rows, sc = (rocblas_stride)NP * planes;
+    (void)a_esz;
+    (void)b_esz;
+    (void)c_esz;
+    if (prec == Prec::F64) {
+        const double a1 = 1.0, b1 = beta;
+        return blas_status(rocblas_gemm_strided_batched_ex(
+            h, N_, N_, NP, planes, rows, &a1, A, rocblas_datatype_f64_r, NP, sa, B,
+            rocblas_datatype_f64_r, P_pad, sb, &b1, C, rocblas_datatype_f64_r, NP, sc, C,
+            rocblas_datatype_f64_r, NP, sc, nb, rocblas_datatype_f64_r, rocblas_gemm_algo_standard,
+            0, 0));
+    }
+    const float a1 = 1.0f, b1 = beta;
+    const rocblas_datatype t = prec == Prec::F32 ? rocblas_datatype_f32_r : rocblas_datatype_bf16_r;
+    return blas_status(rocblas_gemm_strided_batched_ex(
+        h, N_, N_, NP, planes, rows, &a1, A, t, NP, sa, B, t, P_pad, sb, &b1, C,
+        rocblas_datatype_f32_r, NP, sc, C, rocblas_datatype_f32_r, NP, sc, nb,
+        rocblas_datatype_f32_r, rocblas_gemm_algo_standard, 0, 0));
+}
+
+// Adjoint GEMMs only (W already holds the planes of w): the full chunks in one
+// strided-batched call per product, a shorter last chunk in another.
 hipError_t big_adjoint(void *handle, Prec prec, const BigArgs &a, hipStream_t st) {
     rocblas_handle h = (rocblas_handle)handle;
     if (rocblas_set_stream(h, st) != rocblas_status_success) return hipErrorInvalidValue;
     const int S = a.S, NP = a.NP, P_pad = a.P_pad;
-    const size_t planes = (size_t)2 * S;
+    const int planes = 2 * S;
     const size_t esz = prec == Prec::F64 ? sizeof(double) : sizeof(float);
     const size_t gsz = prec == Prec::F64 ? sizeof(double) : (prec == Prec::F32 ? sizeof(float) : sizeof(uint16_t));
-    const size_t wsz = gsz;
-    const uint16_t *Wlo = (const uint16_t *)a.W + planes * P_pad;
-    const rocblas_operation N_ = rocblas_operation_none;
+    const uint16_t *Wlo = (const uint16_t *)a.W + (size_t)planes * P_pad;
+    const int full = P_pad / a.rows;                   // whole chunks
+    const int tail = P_pad - full * a.rows;            // rows of a last, shorter chunk
     hipError_t e = hipSuccess;
-    for (int c = 0; c < a.nchunk; ++c) {
-        const int p0 = c * a.rows, kc = std::min(a.rows, P_pad - p0);
-        if (kc <= 0) break;
-        char *Rc = (char *)a.R + (size_t)c * NP * planes * esz;
+    for (int part = 0; part < 2; ++part) {
+        const int nb = part == 0 ? full : (tail > 0 ? 1 : 0);
+        const int rows = part == 0 ? a.rows : tail;
+        if (nb == 0) continue;
+        const size_t p0 = part == 0 ? 0 : (size_t)full * a.rows;
+        char *R = (char *)a.R + (part == 0 ? 0 : (size_t)full * NP * planes * esz);
         if (prec == Prec::BF16X3) {
-            const char *gh = (const char *)a.Ghi + (size_t)p0 * NP * gsz;
-            const char *gl = (const char *)a.Glo + (size_t)p0 * NP * gsz;
-            const char *wh = (const char *)a.W + (size_t)p0 * wsz;
-            const char *wl = (const char *)Wlo + (size_t)p0 * wsz;
-            if ((e = gemm(h, prec, N_, NP, (int)planes, kc, gh, NP, wh, P_pad, 0.0f, Rc, NP))) return e;
-            if ((e = gemm(h, prec, N_, NP, (int)planes, kc, gh, NP, wl, P_pad, 1.0f, Rc, NP))) return e;
-            if ((e = gemm(h, prec, N_, NP, (int)planes, kc, gl, NP, wh, P_pad, 1.0f, Rc, NP))) return e;
+            const char *gh = (const char *)a.Ghi + p0 * NP * gsz;
+            const char *gl = (const char *)a.Glo + p0 * NP * gsz;
+            const char *wh = (const char *)a.W + p0 * gsz;
+            const char *wl = (const char *)Wlo + p0 * gsz;
+            if ((e = gemm_chunks(h, prec, NP, planes, rows, nb, P_pad, gh, gsz, wh, gsz, 0.0f, R, esz))) return e;
+            if ((e = gemm_chunks(h, prec, NP, planes, rows, nb, P_pad, gh, gsz, wl, gsz, 1.0f, R, esz))) return e;
+            if ((e = gemm_chunks(h, prec, NP, planes, rows, nb, P_pad, gl, gsz, wh, gsz, 1.0f, R, esz))) return e;
         } else {
-            const char *g = (const char *)a.G + (size_t)p0 * NP * gsz;
-            const char *w = (const char *)a.W + (size_t)p0 * wsz;
-            if ((e = gemm(h, prec, N_, NP, (int)planes, kc, g, NP, w, P_pad, 0.0f, Rc, NP))) return e;
+            const char *g = (const char *)a.G + p0 * NP * gsz;
+            const char *w = (const char *)a.W + p0 * gsz;
+            if ((e = gemm_chunks(h, prec, NP, planes, rows, nb, P_pad, g, gsz, w, gsz, 0.0f, R, esz))) return e;
         }
     }
     return e;

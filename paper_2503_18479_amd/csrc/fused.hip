@@ -697,7 +697,6 @@ hipError_t go_np(Prec prec, int variant, const FusedArgs &a, hipStream_t st) {
 template <int LOSS, bool GRAD>
 hipError_t go_loss(Prec prec, int NP, int variant, const FusedArgs &a, hipStream_t st) {
     switch (NP) {
-        case 16: return go_np<16, LOSS, GRAD>(prec, variant, a, st);
         case 32: return go_np<32, LOSS, GRAD>(prec, variant, a, st);
         case 64: return go_np<64, LOSS, GRAD>(prec, variant, a, st);
     }

@@ -29,11 +29,12 @@ struct GLRule {
 enum class Prec { F64 = 0, F32 = 1, BF16X3 = 2 };
 
 // Padded loop dimension used by the solver and the contraction kernels:
-// 16, 32 or 64 for the register-resident (fused) path, a multiple of 64 above.
+// 32 or 64 for the register-resident (fused) path (the bf16 matrix-core
+// product needs K = 32), a multiple of 64 above.
 constexpr int kMaxLoops = 64;       // largest loop count of the fused path
 constexpr int kMaxLoopsBig = 1024;  // largest loop count of this build
 inline int padded_loops(int n) {
-    return n <= 16 ? 16 : (n <= 32 ? 32 : (n + 63) / 64 * 64);
+    return n <= 32 ? 32 : (n + 63) / 64 * 64;
 }
 inline bool big_plan(int NP) { return NP > kMaxLoops; }
 constexpr int kPTile = 64;          // rows of G per LDS tile in the fused kernels
@@ -213,6 +214,7 @@ struct cosim_plan {
     // more than 64 loops: GEMM operands and the rocBLAS handle
     void *blas = nullptr;
     void *bX = nullptr, *bY = nullptr, *bW = nullptr;
+    int prec_mask = 7;    // precisions whose copies of G were assembled (bit 1 << precision)
     bool ldl_ok = false;  // every R_k > 0: the LDL^T fast path applies
     int variant[3] = {0, 0, 0};  // fused-kernel variant per precision
 };

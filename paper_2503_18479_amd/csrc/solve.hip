@@ -878,11 +878,6 @@ hipError_t launch_gj(int NP, int n, int S, int F, const double *M, const double 
                      double *gsys, int32_t *status, bool or_status, GJFactor fac,
                      bool fallback_only, hipStream_t st) {
     switch (NP) {
-        case 16:
-            hipLaunchKernelGGL((k_gj<16, ADJ>), dim3(S), dim3(GJShape<16>::BLOCK), 0, st, n, S,
-                               F, M, R, phi, C, omega, Iin, rpart, nchunk, rscale, Iout, gsys,
-                               status, or_status, fac, fallback_only);
-            break;
         case 32:
             hipLaunchKernelGGL((k_gj<32, ADJ>), dim3(S), dim3(GJShape<32>::BLOCK), 0, st, n, S,
                                F, M, R, phi, C, omega, Iin, rpart, nchunk, rscale, Iout, gsys,
@@ -914,10 +909,6 @@ hipError_t launch_ldl(int NP, int n, int S, int F, const double *M_d, const doub
                       hipStream_t st) {
     const dim3 grid((S + 3) / 4);
     switch (NP) {
-        case 16:
-            hipLaunchKernelGGL(k_ldl<16>, grid, dim3(256), 0, st, n, S, F, M_d, R_d, C_d, omega_d,
-                               fac, status_d);
-            break;
         case 32:
             hipLaunchKernelGGL(k_ldl<32>, grid, dim3(256), 0, st, n, S, F, M_d, R_d, C_d, omega_d,
                                fac, status_d);
@@ -947,10 +938,6 @@ hipError_t launch_replay_t(int NP, int n, int S, int F, GJFactor fac, const doub
                            int32_t *status_d, hipStream_t st) {
     const dim3 grid((S + 3) / 4);
     switch (NP) {
-        case 16:
-            hipLaunchKernelGGL((k_replay<16, ADJ>), grid, dim3(256), 0, st, n, S, F, fac, phi_d,
-                               C_d, omega_d, I_d, rpart_d, nchunk, rscale, gsys_d, status_d);
-            break;
         case 32:
             hipLaunchKernelGGL((k_replay<32, ADJ>), grid, dim3(256), 0, st, n, S, F, fac, phi_d,
                                C_d, omega_d, I_d, rpart_d, nchunk, rscale, gsys_d, status_d);

@@ -130,3 +130,27 @@ def test_adam_step_argument_errors(lib):
     assert lib.cosim_adam_step(4, d, d, d, d, d, 1e-13, 0.9, -0.1, 1e-8, None) == EINVAL
     assert lib.cosim_adam_step(4, d, d, d, d, d, float("nan"), 0.9, 0.999, 1e-8, None) == EINVAL
     assert lib.cosim_adam_step(4, d, d, d, d, d, 1e-13, 0.9, 0.999, -1.0, None) == EINVAL
+
+
+def test_assemble_mask_and_many_argument_errors(lib):
+    seg, v, a, R = _geom_args()
+    rc, g = _create(lib, 2, seg, v, a, R)
+    out = ctypes.c_void_p()
+    d = ctypes.c_void_p(16)
+    for mask in (0, 8, -1):
+        assert lib.cosim_assemble_ex(g, 10, d, 1e-6, mask, None, ctypes.byref(out)) == EINVAL
+    lib.cosim_geometry_destroy(g)
+    arr = (ctypes.c_void_p * 1)(None)
+    ints = (ctypes.c_int * 1)(1)
+    assert lib.cosim_loss_and_grad_many(0, None, None, None, None, None, None, 0, 0, None, None,
+                                        None, None) == 0
+    assert lib.cosim_loss_and_grad_many(-1, arr, ints, ints, arr, arr, arr, 0, 0, arr, None,
+                                        arr, None) == EINVAL
+    assert lib.cosim_loss_and_grad_many(1, None, ints, ints, arr, arr, arr, 0, 0, arr, None,
+                                        arr, None) == EINVAL
+    assert lib.cosim_loss_and_grad_many(1, arr, ints, ints, arr, arr, arr, 0, 7, arr, None,
+                                        arr, None) == EINVAL
+    # a null plan is reported with its instance index
+    assert lib.cosim_loss_and_grad_many(1, arr, ints, ints, arr, arr, arr, 0, 0, arr, None,
+                                        arr, None) == EINVAL
+    assert b"instance 0" in lib.cosim_last_error()

@@ -232,6 +232,31 @@ def config3_array8x8(batch: int = 4096, grid: int = 256, two_planes: bool = Fals
     return Workload("array_8x8", g, pts, C, freqs, T)
 
 
+def config4_instances(count: int = 2048, grid_range=(128, 256), stream: int = 0) -> list:
+    """Ragged configuration: `count` independent instances, each its own
+    square array (n_side uniform in {4, 6, 8, 12, 16}: 16 to 256 loops, 3 cm
+    squares at 3.5 cm pitch, 32 segments), its own g x g grid at z = 1 cm over
+    the array footprint (g uniform integer in grid_range), its own F uniform in
+    1..8 frequencies drawn uniformly in [118, 138] MHz (sorted), one
+    configuration with C log-uniform in [10, 300] pF, and a Gaussian hotspot
+    target (sigma 3 cm, 1 uT, seeded centre)."""
+    rng = rng_for(4, stream)
+    out = []
+    for i in range(count):
+        ns = int(rng.choice([4, 6, 8, 12, 16]))
+        gsz = int(rng.integers(grid_range[0], grid_range[1] + 1))
+        nf = int(rng.integers(1, 9))
+        g = square_array(ns, ns, 0.03, 0.035, 32, 1e-3, 0.3)
+        ext = ns * 0.035
+        pts = grid_points(gsz, ext, [0.01])
+        freqs = np.sort(rng.uniform(118e6, 138e6, size=nf))
+        C = np.exp(rng.uniform(np.log(10e-12), np.log(300e-12), size=(1, ns * ns)))
+        c = rng.uniform(-ext / 2, ext / 2, size=2)
+        T = gaussian_hotspot(pts, c, 0.03, 1e-6)
+        out.append(Workload(f"ragged_{i}", g, pts, C, freqs, T))
+    return out
+
+
 def config5_array32x32(batch: int = 256, grid: int = 512) -> Workload:
     """32x32 array (1024 loops), 512x512 points at z=2 cm, batch 256, F=1,
     smooth random target (Gaussian-filtered noise, sigma=4 cm, peak 2 uT)."""
