@@ -486,20 +486,23 @@ __device__ inline double wave_sum16(const double (&v)[16], int lane) {
 // imaginary part; lane l holds column l%16, rows g+4m, g = l/16, m = 0..3).
 // Panels of 4 columns:
 //   1. the lanes holding the panel's columns copy them to LDS;
-//   2. every lane factors the 4x4 diagonal block (L11, D11) redundantly;
-//   3. lane r forms row r of V21 = A21 L11^-T and L21 = V21 D11^-1;
+//   2. lane r eliminates row r of the panel (diagonal block and below) column
+//      by column, with the diagonal-block rows broadcast by readlane, giving
+//      L and V = L D in registers;
+//   3. L21 and V21 go to LDS;
 //   4. every lower block right of the panel takes the rank-4 update
 //      A -= L21 V21^T as four 16x16x4 FP64 MFMAs (complex = 4 real products).
 // Columns left of the trailing part also receive updates; they are finished
 // and never read again.  The factor is recorded (L by columns, D^-1) for the
 // replay kernel.  A system whose smallest pivot is below 1e-5 of its largest
 // impedance diagonal (or is not finite) is marked for the pivoted fallback.
+// The accumulators and the row state fit 256 registers, so two systems share
+// a SIMD: one wave's panel elimination runs while the other's MFMAs do.
 template <int NP>
-__global__ __launch_bounds__(256) void k_ldl(int n, int S, int F, const double *__restrict__ M,
-                                             const double *__restrict__ Rv,
-                                             const double *__restrict__ C,
-                                             const double *__restrict__ omega, GJFactor fac,
-                                             int32_t *__restrict__ status) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_ldl(
+    int n, int S, int F, const double *__restrict__ M, const double *__restrict__ Rv,
+    const double *__restrict__ C, const double *__restrict__ omega, GJFactor fac,
+    int32_t *__restrict__ status) {
     constexpr int NB = NP / 16;
     constexpr int NBLK = NB * (NB + 1) / 2;
     typedef double f64x4 __attribute__((ext_vector_type(4)));
@@ -589,81 +592,60 @@ __global__ __launch_bounds__(256) void k_ldl(int n, int S, int F, const double *
             }
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
-            // 2. LDL^T of the 4x4 diagonal block, redundantly in every lane
-            double2 d4[4][4];
+            // 2. lane r takes row r of the panel, column by column:
+            //      V_rc = A_rc - sum_{j<c} L_rj V_cj,  D_c = V_cc,  L_rc = V_rc / D_c;
+            //    row c of the diagonal block is held by lane k0 + c, and the
+            //    entries V_cj, D_c reach every lane by readlane broadcast
+            const int r = lane;
+            double2 v[4], l[4];
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-#pragma unroll
-                for (int c = 0; c <= r; ++c) d4[r][c] = pan[k0 + r][c];
-            double2 dinv[4];
+            for (int c = 0; c < 4; ++c) v[c] = pan[min(r, NP - 1)][c];
+            double2 *Ls = fac.L + (size_t)s * NP * NP;  // packed columns, see ldl_col
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-                const double2 d = d4[c][c];
+#pragma unroll
+                for (int j = 0; j < c; ++j) {
+                    const double2 vcj = make_double2(readlane_d(v[j].x, k0 + c), readlane_d(v[j].y, k0 + c));
+                    v[c] = cfms(v[c], l[j], vcj);
+                }
+                const double2 d = make_double2(readlane_d(v[c].x, k0 + c), readlane_d(v[c].y, k0 + c));
                 if (c < nc) dmin = fmin(dmin, fabs(d.x) + fabs(d.y));
-                dinv[c] = cinv_nr(d);
-                double2 l[4];
-#pragma unroll
-                for (int r = c + 1; r < 4; ++r) l[r] = cmul(d4[r][c], dinv[c]);
-#pragma unroll
-                for (int r = c + 1; r < 4; ++r)
-#pragma unroll
-                    for (int r2 = c + 1; r2 <= r; ++r2) d4[r][r2] = cfms(d4[r][r2], l[r], d4[r2][c]);
-#pragma unroll
-                for (int r = c + 1; r < 4; ++r) d4[r][c] = l[r];
+                const double2 dinv = cinv_nr(d);
+                l[c] = cmul(v[c], dinv);
+                // L below the diagonal (rows of the diagonal block and below it), D^-1
+                if (r > k0 + c && r < NP) Ls[ldl_col(NP, k0 + c) + r - (k0 + c) - 1] = l[c];
+                if (lane == 0) fac.piv_val[(size_t)s * NP + k0 + c] = dinv;
             }
-            double2 *Ls = fac.L + (size_t)s * NP * NP;  // packed columns, see ldl_col
-            if (lane == 0) {
-                // record D^-1 of the panel and the L11 entries below the diagonal
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    fac.piv_val[(size_t)s * NP + k0 + c] = dinv[c];
-#pragma unroll
-                    for (int r = c + 1; r < 4; ++r) Ls[ldl_col(NP, k0 + c) + r - c - 1] = d4[r][c];
-                }
-            }
-            // 3. row lane of V21 and L21 (rows below the diagonal block)
-            const int r = lane;
-            double2 lrow[4] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0),
-                               make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
-            double2 vrow[4] = {lrow[0], lrow[1], lrow[2], lrow[3]};
-            if (r >= k0 + 4 && r < NP) {
-                const double2 a0 = pan[r][0], a1 = pan[r][1], a2 = pan[r][2], a3 = pan[r][3];
-                vrow[0] = a0;
-                vrow[1] = cfms(a1, vrow[0], d4[1][0]);
-                vrow[2] = cfms(cfms(a2, vrow[0], d4[2][0]), vrow[1], d4[2][1]);
-                vrow[3] = cfms(cfms(cfms(a3, vrow[0], d4[3][0]), vrow[1], d4[3][1]), vrow[2], d4[3][2]);
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    lrow[c] = cmul(vrow[c], dinv[c]);
-                    Ls[ldl_col(NP, k0 + c) + r - (k0 + c) - 1] = lrow[c];
-                }
-            }
+            // 3. L and V rows to LDS.  Only rows below the diagonal block (L21,
+            // V21) matter: an L row i < k0 + 4 changes only entries of row i
+            // right of column k0 + 3 (upper triangle), a V row j < k0 + 4 only
+            // column j (already eliminated); neither is read again, so rows
+            // above are stored as they come, without masking
             if (r < NP) {
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
-                    pan[r][c] = lrow[c];
-                    vv[r][c] = vrow[c];
+                    pan[r][c] = l[c];
+                    vv[r][c] = v[c];
                 }
             }
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
-            // 4. rank-4 update of every lower block right of the panel
-            double2 La[NB], Vb[NB];
+            // 4. rank-4 update of every lower block right of the panel; the
+            // operands of a block row are read from LDS just before its MFMAs
+            // (fewer live registers: two waves fit a SIMD)
 #pragma unroll
             for (int bi = bc; bi < NB; ++bi) {
-                La[bi] = pan[16 * bi + c16][g];  // A operand: row c16 of block bi, k = g
-                Vb[bi] = vv[16 * bi + c16][g];   // B operand: column c16 of block bi, k = g
-            }
-#pragma unroll
-            for (int bi = bc; bi < NB; ++bi)
+                const double2 La = pan[16 * bi + c16][g];  // A operand: row c16 of block bi, k = g
 #pragma unroll
                 for (int bj = bc; bj <= bi; ++bj) {
+                    const double2 Vb = vv[16 * bj + c16][g];  // B operand: column c16 of block bj, k = g
                     const int bx = bi * (bi + 1) / 2 + bj;
-                    Xr[bx] = __builtin_amdgcn_mfma_f64_16x16x4f64(-La[bi].x, Vb[bj].x, Xr[bx], 0, 0, 0);
-                    Xr[bx] = __builtin_amdgcn_mfma_f64_16x16x4f64(La[bi].y, Vb[bj].y, Xr[bx], 0, 0, 0);
-                    Xi[bx] = __builtin_amdgcn_mfma_f64_16x16x4f64(-La[bi].x, Vb[bj].y, Xi[bx], 0, 0, 0);
-                    Xi[bx] = __builtin_amdgcn_mfma_f64_16x16x4f64(-La[bi].y, Vb[bj].x, Xi[bx], 0, 0, 0);
+                    Xr[bx] = __builtin_amdgcn_mfma_f64_16x16x4f64(-La.x, Vb.x, Xr[bx], 0, 0, 0);
+                    Xr[bx] = __builtin_amdgcn_mfma_f64_16x16x4f64(La.y, Vb.y, Xr[bx], 0, 0, 0);
+                    Xi[bx] = __builtin_amdgcn_mfma_f64_16x16x4f64(-La.x, Vb.y, Xi[bx], 0, 0, 0);
+                    Xi[bx] = __builtin_amdgcn_mfma_f64_16x16x4f64(-La.y, Vb.x, Xi[bx], 0, 0, 0);
                 }
+            }
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
         }
