@@ -620,11 +620,12 @@ int cosim_loss_and_grad(cosim_plan_t p, int B, int F, const double *C_d, const d
         return COSIM_OK;
     }
     if (p->ldl_ok) {
-        HIP_TRY(launch_ldl(p->NP, p->n, (int)S, F, p->M_d, p->R_d, C_d, omega_d, p->fac, status_d, st));
+        HIP_TRY(launch_ldl(p->NP, p->n, (int)S, F, p->M_d, p->R_d, C_d, omega_d, p->phi_d,
+                           p->fac, p->I_ws, status_d, st));
         HIP_TRY(launch_solve_fallback(p->NP, p->n, (int)S, F, p->M_d, p->R_d, p->phi_d, C_d,
                                       omega_d, p->I_ws, status_d, p->fac, st));
-        HIP_TRY(launch_replay_forward(p->NP, p->n, (int)S, F, p->fac, p->phi_d, omega_d, p->I_ws,
-                                      status_d, st));
+        HIP_TRY(launch_replay_forward(p->NP, p->n, (int)S, F, p->fac, omega_d, p->I_ws, status_d,
+                                      st));
     } else {
         HIP_TRY(launch_solve_forward(p->NP, p->n, (int)S, F, p->M_d, p->R_d, p->phi_d, C_d,
                                      omega_d, p->I_ws, status_d, p->fac, st));

@@ -69,18 +69,20 @@ constexpr int kFmtLDL = 0, kFmtGJ = 1, kFmtNeedsPivot = 2;
 __host__ __device__ constexpr int ldl_col(int NP, int k) { return k * (2 * NP - k - 1) / 2; }
 constexpr int kFlagPivot = 1 << 16;  // kernel-internal status bit, never returned
 
-// LDL^T fast path (all R_k > 0): factorises and records; marks systems that
-// need pivoting (fmt = kFmtNeedsPivot) for launch_solve_fallback.
+// LDL^T fast path (all R_k > 0): factorises and records, leaves
+// z = D^-1 L^-1 (-j w Phi) in I_d for launch_replay_forward; marks systems
+// that need pivoting (fmt = kFmtNeedsPivot) for launch_solve_fallback.
 hipError_t launch_ldl(int NP, int n, int S, int F, const double *M_d, const double *R_d,
-                      const double *C_d, const double *omega_d, GJFactor fac, int32_t *status_d,
-                      hipStream_t st);
+                      const double *C_d, const double *omega_d, const double *phi_d, GJFactor fac,
+                      double2 *I_d, int32_t *status_d, hipStream_t st);
 // Pivoted Gauss-Jordan for the marked systems only (writes I and a kFmtGJ record).
 hipError_t launch_solve_fallback(int NP, int n, int S, int F, const double *M_d,
                                  const double *R_d, const double *phi_d, const double *C_d,
                                  const double *omega_d, double2 *I_d, int32_t *status_d,
                                  GJFactor fac, hipStream_t st);
-// Forward solve I = Z^-1 (-j w Phi) from the record (kFmtLDL systems).
-hipError_t launch_replay_forward(int NP, int n, int S, int F, GJFactor fac, const double *phi_d,
+// Forward solve I = Z^-1 (-j w Phi) of the kFmtLDL systems: the backward
+// substitution from the z that launch_ldl left in I_d.
+hipError_t launch_replay_forward(int NP, int n, int S, int F, GJFactor fac,
                                  const double *omega_d, double2 *I_d, int32_t *status_d,
                                  hipStream_t st);
 // Adjoint solve from the record and the per-system gradient terms.

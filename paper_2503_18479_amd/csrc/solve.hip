@@ -494,14 +494,17 @@ __device__ inline double wave_sum16(const double (&v)[16], int lane) {
 //      A -= L21 V21^T as four 16x16x4 FP64 MFMAs (complex = 4 real products).
 // Columns left of the trailing part also receive updates; they are finished
 // and never read again.  The factor is recorded (L by columns, D^-1) for the
-// replay kernel.  A system whose smallest pivot is below 1e-5 of its largest
+// replay kernels, and the forward right-hand side b = -j w Phi rides along:
+// y = L^-1 b is formed panel by panel and z = D^-1 y is written to Z, so that
+// the forward replay only runs the backward substitution.  A system whose smallest pivot is below 1e-5 of its largest
 // impedance diagonal (or is not finite) is marked for the pivoted fallback.
 // The accumulators and the row state fit 256 registers, so two systems share
 // a SIMD: one wave's panel elimination runs while the other's MFMAs do.
 template <int NP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_ldl(
     int n, int S, int F, const double *__restrict__ M, const double *__restrict__ Rv,
-    const double *__restrict__ C, const double *__restrict__ omega, GJFactor fac,
+    const double *__restrict__ C, const double *__restrict__ omega,
+    const double *__restrict__ phi, GJFactor fac, double2 *__restrict__ Z,
     int32_t *__restrict__ status) {
     constexpr int NB = NP / 16;
     constexpr int NBLK = NB * (NB + 1) / 2;
@@ -571,6 +574,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         zdiag = fmaxf(zdiag, __shfl_xor(zdiag, off));
     }
     double dmin = __builtin_inf();
+    // right-hand side b = -j w Phi (lane i holds b_i), turned into y = L^-1 b
+    // column by column as L is formed; dl = D_i^-1 of the lane's own column
+    double2 y = make_double2(0.0, lane < n ? -w * phi[lane] : 0.0);
+    double2 dl = make_double2(1.0, 0.0);
 
     double2 (*pan)[5] = sPan[wv];
     double2 (*vv)[5] = sV[wv];
@@ -615,6 +622,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                 // L below the diagonal (rows of the diagonal block and below it), D^-1
                 if (r > k0 + c && r < NP) Ls[ldl_col(NP, k0 + c) + r - (k0 + c) - 1] = l[c];
                 if (lane == 0) fac.piv_val[(size_t)s * NP + k0 + c] = dinv;
+                if (lane == k0 + c) dl = dinv;
+            }
+            // forward substitution for the panel's columns: y_r -= L_rc y_c (r > k0 + c)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const double2 yc = make_double2(readlane_d(y.x, k0 + c), readlane_d(y.y, k0 + c));
+                const double2 yn = cfms(y, l[c], yc);
+                const bool below = r > k0 + c;
+                y.x = below ? yn.x : y.x;  // componentwise: a select of the
+                y.y = below ? yn.y : y.y;  // vector struct goes through memory
             }
             // 3. L and V rows to LDS.  Only rows below the diagonal block (L21,
             // V21) matter: an L row i < k0 + 4 changes only entries of row i
@@ -650,6 +667,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
             __builtin_amdgcn_wave_barrier();
         }
     }
+    if (lane < n) Z[(size_t)s * n + lane] = cmul(y, dl);  // z = D^-1 L^-1 b
     if (lane == 0) {
         const bool pivot = (flag & COSIM_SYS_BAD_INPUT) || !(dmin >= 1e-5 * (double)zdiag);
         status[s] = flag;
@@ -660,9 +678,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 // Solves with a recorded factorisation, one wave per system, lane i holds
 // component i.  Format kFmtLDL: y = L^-1 b by columns (readlane broadcast of
 // y_k, one coalesced column load), z = D^-1 y, then L^T x = z by
-// dot products (wave sums).  Format kFmtGJ: replays the recorded Gauss-Jordan
+// dot products (wave sums); the forward solve starts from z, which the
+// factorisation left in I.  Format kFmtGJ: replays the recorded Gauss-Jordan
 // row operations b <- b - l_k b_{p_k}, then x_k = b_{p_k} / piv_k.
-// ADJ = false: b = -j w Phi, writes I (systems in the Gauss-Jordan format
+// ADJ = false: z in I, writes I (systems in the Gauss-Jordan format
 // already have I from the elimination and are skipped).
 // ADJ = true : b = rscale * sum_c (rr - j ri); writes
 //              gsys[s][k] = 2 Re(mu_k I_k / (j w C_k^2)).
@@ -686,7 +705,7 @@ __global__ __launch_bounds__(256) void k_replay(int n, int S, int F, GJFactor fa
     double2 x = make_double2(0.0, 0.0);
     if (lane < n) {
         if (!ADJ) {
-            x = make_double2(0.0, -w * phi[lane]);
+            x = I[(size_t)s * n + lane];  // z = D^-1 L^-1 b from the factorisation
         } else {
             double rr = 0.0, ri = 0.0;
             for (int c = 0; c < nchunk; ++c) {
@@ -711,26 +730,29 @@ __global__ __launch_bounds__(256) void k_replay(int n, int S, int F, GJFactor fa
 #pragma unroll
             for (int u = 0; u < U; ++u) l[u] = lcol(k0 + u);
         };
-        // forward: y_i -= L_ik y_k for i > k
-        const int nfg = n / U;  // full groups
-        if (nfg > 0) load_group(cur, 0);
-        int k0 = 0;
-        for (; k0 + U <= n; k0 += U) {
-            if (k0 + 2 * U <= n) load_group(nxt, k0 + U);
+        if (ADJ) {
+            // forward: y_i -= L_ik y_k for i > k (the forward solve had it
+            // done by the factorisation)
+            const int nfg = n / U;  // full groups
+            if (nfg > 0) load_group(cur, 0);
+            int k0 = 0;
+            for (; k0 + U <= n; k0 += U) {
+                if (k0 + 2 * U <= n) load_group(nxt, k0 + U);
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const double2 yk = make_double2(readlane_d(x.x, k0 + u), readlane_d(x.y, k0 + u));
-                x = cfms(x, cur[u], yk);
+                for (int u = 0; u < U; ++u) {
+                    const double2 yk = make_double2(readlane_d(x.x, k0 + u), readlane_d(x.y, k0 + u));
+                    x = cfms(x, cur[u], yk);
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) cur[u] = nxt[u];
             }
-#pragma unroll
-            for (int u = 0; u < U; ++u) cur[u] = nxt[u];
+            for (; k0 < n; ++k0) {
+                const double2 l = lcol(k0);
+                const double2 yk = make_double2(readlane_d(x.x, k0), readlane_d(x.y, k0));
+                x = cfms(x, l, yk);
+            }
+            if (lane < n) x = cmul(x, fac.piv_val[(size_t)s * NP + lane]);  // D^-1
         }
-        for (; k0 < n; ++k0) {
-            const double2 l = lcol(k0);
-            const double2 yk = make_double2(readlane_d(x.x, k0), readlane_d(x.y, k0));
-            x = cfms(x, l, yk);
-        }
-        if (lane < n) x = cmul(x, fac.piv_val[(size_t)s * NP + lane]);  // D^-1
         // backward: x_k = z_k - sum_{i > k} L_ik x_i, in blocks of U = 8
         // columns [k0, k1) from the bottom.  The terms with i >= k1 (x_i final)
         // of all 8 columns are summed by one 16-value reduction; the terms
@@ -887,17 +909,17 @@ hipError_t launch_solve_forward(int NP, int n, int S, int F, const double *M_d,
 }
 
 hipError_t launch_ldl(int NP, int n, int S, int F, const double *M_d, const double *R_d,
-                      const double *C_d, const double *omega_d, GJFactor fac, int32_t *status_d,
-                      hipStream_t st) {
+                      const double *C_d, const double *omega_d, const double *phi_d, GJFactor fac,
+                      double2 *I_d, int32_t *status_d, hipStream_t st) {
     const dim3 grid((S + 3) / 4);
     switch (NP) {
         case 32:
             hipLaunchKernelGGL(k_ldl<32>, grid, dim3(256), 0, st, n, S, F, M_d, R_d, C_d, omega_d,
-                               fac, status_d);
+                               phi_d, fac, I_d, status_d);
             break;
         case 64:
             hipLaunchKernelGGL(k_ldl<64>, grid, dim3(256), 0, st, n, S, F, M_d, R_d, C_d, omega_d,
-                               fac, status_d);
+                               phi_d, fac, I_d, status_d);
             break;
         default:
             return hipErrorInvalidValue;
@@ -934,11 +956,11 @@ hipError_t launch_replay_t(int NP, int n, int S, int F, GJFactor fac, const doub
     return hipGetLastError();
 }
 
-hipError_t launch_replay_forward(int NP, int n, int S, int F, GJFactor fac, const double *phi_d,
+hipError_t launch_replay_forward(int NP, int n, int S, int F, GJFactor fac,
                                  const double *omega_d, double2 *I_d, int32_t *status_d,
                                  hipStream_t st) {
-    return launch_replay_t<false>(NP, n, S, F, fac, phi_d, nullptr, omega_d, I_d, nullptr, 0, 0.0,
-                                  nullptr, status_d, st);
+    return launch_replay_t<false>(NP, n, S, F, fac, nullptr, nullptr, omega_d, I_d, nullptr, 0,
+                                  0.0, nullptr, status_d, st);
 }
 
 hipError_t launch_replay_adjoint(int NP, int n, int S, int F, GJFactor fac, const double *C_d,
