@@ -58,6 +58,9 @@ def parse():
     ap.add_argument("--ragged", type=int, default=256,
                     help="also time this many independent instances of the ragged configuration "
                          "(16-256 loops, 16k-65k points, 1-8 frequencies; 2048 is the full set; 0: skip)")
+    ap.add_argument("--large-adam", type=int, default=200,
+                    help="the 32x32 array (1,024 loops, 262,144 points, batch 256): this many "
+                         "Adam steps after the per-step timing (0: skip the line)")
     ap.add_argument("--variant", type=int, default=None,
                     help="with --profile-steps: use this fused-kernel variant instead of tuning")
     return ap.parse_args()
@@ -168,6 +171,67 @@ def ragged_line(n_inst: int, mixed: str, steps: int, torch) -> dict:
             "loops": sorted(set(wl.geom.n for wl in wls)), "points_min": min(wl.P for wl in wls),
             "points_max": max(wl.P for wl in wls), "flagged_systems": bad,
             "setup_s": t_setup, "precision": mixed}
+
+
+def large_line(adam_steps: int, mixed: str, steps: int, torch) -> dict:
+    """The 32x32 array (1,024 loops, 512x512 points at z = 2 cm, batch 256,
+    one frequency): per-step time and phases of cosim_loss_and_grad in the
+    mixed precision and in FP64, the mixed-precision loss and gradient against
+    FP64 at the same C, and `adam_steps` Adam steps (eager launches) from the
+    seeded C in the mixed precision."""
+    import workloads as W
+    from paper_2503_18479_amd import Geometry, Plan
+    dev = torch.device("cuda:0")
+    wl = W.config5_array32x32()
+    t0 = time.perf_counter()
+    plan = Plan(Geometry.from_workload(wl.geom), torch.tensor(wl.pts, device=dev), wl.bext_z,
+                precisions=["fp64", mixed])
+    C = torch.tensor(wl.C, device=dev)
+    om = torch.tensor(wl.omega, device=dev)
+    T = torch.tensor(wl.target, device=dev)
+    plan.reserve(wl.B, wl.F)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    n, S = wl.geom.n, wl.B * wl.F
+    modes, vals = {}, {}
+    for m in (mixed, "fp64"):
+        dt, ph, bad, _ = time_mode(plan, C, om, T, m, steps, 1, torch, tune=False)
+        loss, grad, _ = plan.loss_and_grad(C, om, T, precision=PREC_CODE[m])
+        vals[m] = (loss.cpu().numpy(), grad.cpu().numpy())
+        pm = {name: float(np.mean(ph[:, i])) for i, name in enumerate(Plan.PHASES)}
+        # pivoted LU: (8/3) n^3 real flops per complex system; the contraction
+        # phase: 8 P n flops per system (forward and adjoint, real-split)
+        lu_tf = S * 8.0 / 3.0 * n ** 3 / (pm["solve_forward"] * 1e-3) / 1e12
+        modes[m] = {"ms_per_step": 1e3 * dt / steps, "evals_per_s": wl.B * steps / dt,
+                    "steps": steps, "phase_ms": pm, "flagged_systems": bad,
+                    "solve_forward_fp64_tflops": lu_tf,
+                    "contraction_tflops": 8.0 * wl.P * n * S / (pm["fused_contraction"] * 1e-3) / 1e12}
+        print(f"[bench] 32x32 {m}: {modes[m]['ms_per_step']:.1f} ms/step, phases {pm}",
+              file=sys.stderr, flush=True)
+    lm, gm = vals[mixed]
+    l64, g64 = vals["fp64"]
+    err = {"loss_rel_max": float(np.max(np.abs(lm - l64) / np.abs(l64))),
+           "grad_normwise_rel_max": float(np.max(np.linalg.norm(gm - g64, axis=1)
+                                                 / np.linalg.norm(g64, axis=1)))}
+    adam = None
+    if adam_steps > 0:
+        C1 = C.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        hist, st = plan.optimize(C1, om, T, adam_steps, precision=PREC_CODE[mixed])
+        torch.cuda.synchronize()
+        t_adam = time.perf_counter() - t0
+        h = hist.cpu().numpy()
+        adam = {"steps": adam_steps, "s": t_adam, "ms_per_step": 1e3 * t_adam / adam_steps,
+                "loss_first_mean": float(h[0].mean()), "loss_last_mean": float(h[-1].mean()),
+                "flagged_systems": int((st != 0).sum()), "precision": mixed, "lr": 1e-13}
+        print(f"[bench] 32x32 Adam: {adam_steps} steps in {t_adam:.1f} s, mean loss "
+              f"{adam['loss_first_mean']:.4e} -> {adam['loss_last_mean']:.4e}", file=sys.stderr,
+              flush=True)
+    return {"workload": wl.name, "loops": n, "points": wl.P, "batch": wl.B, "freqs": wl.F,
+            "setup_s": t_setup, "modes": modes, "mixed_vs_fp64_error": err,
+            "mixed_vs_fp64_speed": modes["fp64"]["ms_per_step"] / modes[mixed]["ms_per_step"],
+            "adam": adam, "solve": "fp64 pivoted LU (blocked, one workgroup per system)"}
 
 
 def main():
@@ -298,13 +362,17 @@ def main():
             "phases": phases,
         },
     }
+    del plan
+    torch.cuda.empty_cache()
     if args.ragged > 0:
         print(f"[bench] ragged configuration: {args.ragged} instances", file=sys.stderr, flush=True)
-        del plan
-        torch.cuda.empty_cache()
         line["ragged"] = ragged_line(args.ragged, args.mixed, 3, torch)
         print(f"[bench] ragged: {line['ragged']['ms_per_step']:.1f} ms per step", file=sys.stderr,
               flush=True)
+    if args.large_adam > 0:
+        print("[bench] 32x32 array", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+        line["large"] = large_line(args.large_adam, args.mixed, 3, torch)
     if args.cpu_configs > 0:
         print("[bench] timing the oracle on the host", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(wl, args.cpu_configs)

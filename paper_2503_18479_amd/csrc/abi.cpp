@@ -82,6 +82,9 @@ void plan_free_workspace(cosim_plan *p) {
     dfree(p->bX);
     dfree(p->bY);
     dfree(p->bW);
+    dfree(p->bWt);
+    dfree(p->bZmax);
+    dfree(p->bTinv);
     dfree(p->I_ws);
     dfree(p->rpart);
     dfree(p->lpart);
@@ -92,6 +95,17 @@ void plan_free_workspace(cosim_plan *p) {
     dfree(p->fac.fmt);
     p->cap_systems = 0;
     p->cap_chunks = 0;
+}
+
+// The blocked LDL^T above 64 loops when every R_k > 0, else pivoted LU.
+BigFactor big_factor_args(const cosim_plan *p) {
+    BigFactor bf;
+    bf.ldl = p->ldl_ok;
+    bf.fmt = p->fac.fmt;
+    bf.zmax = p->bZmax;
+    bf.wt = p->bWt;
+    bf.tinv = p->bTinv;
+    return bf;
 }
 
 int check_device(const cosim_plan *p) {
@@ -119,6 +133,14 @@ int ensure_workspace(cosim_plan *p, size_t systems, int chunks) {
         plan_free_workspace(p);
         (void)hipGetLastError();
         return fail(COSIM_ENOMEM, "GEMM workspace for %zu systems failed", ns);
+    }
+    if (big && p->ldl_ok &&
+        (hipMalloc((void **)&p->bWt, ns * 64 * NP * sizeof(double2)) != hipSuccess ||
+         hipMalloc((void **)&p->bZmax, ns * sizeof(double)) != hipSuccess ||
+         hipMalloc((void **)&p->bTinv, ns * 64 * 64 * sizeof(double2)) != hipSuccess)) {
+        plan_free_workspace(p);
+        (void)hipGetLastError();
+        return fail(COSIM_ENOMEM, "LDL^T panel workspace for %zu systems failed", ns);
     }
     if (hipMalloc((void **)&p->I_ws, ns * n * sizeof(double2)) != hipSuccess ||
         hipMalloc((void **)&p->rpart, (size_t)nc * ns * NP * sizeof(double2)) != hipSuccess ||
@@ -498,8 +520,8 @@ int cosim_solve(cosim_plan_t p, int B, int F, const double *C_d, const double *o
     if (big_plan(p->NP)) {
         if ((rc = ensure_workspace(p, (size_t)S, 1))) return rc;
         hipStream_t st = (hipStream_t)stream;
-        HIP_TRY(launch_lu_big(p->NP, p->n, S, F, p->M_d, p->R_d, C_d, omega_d, p->fac.L,
-                              p->fac.piv_row, status_d, st));
+        HIP_TRY(big_factor(big_factor_args(p), p->NP, p->n, S, F, p->M_d, p->R_d,
+                           C_d, omega_d, p->fac.L, p->fac.piv_row, status_d, st));
         HIP_TRY(launch_lu_solve(p->NP, p->n, S, F, p->fac.L, p->fac.piv_row, p->phi_d, C_d,
                                 omega_d, (double2 *)I_d, kRhsExcitation, nullptr, 0, 0.0, nullptr,
                                 status_d, st));
@@ -550,8 +572,8 @@ int cosim_field_backward(cosim_plan_t p, int B, int F, const double *C_d, const 
         HIP_TRY(launch_pack_w64(p->P, p->P_pad, (int)S, (const double2 *)gBz_d, (double *)p->bW, st));
         BigArgs a = big_args(p, Prec::F64, (int)S, nchunk, nullptr, nullptr);
         HIP_TRY(big_adjoint(p->blas, Prec::F64, a, st));
-        HIP_TRY(launch_lu_big(p->NP, p->n, (int)S, F, p->M_d, p->R_d, C_d, omega_d, p->fac.L,
-                              p->fac.piv_row, status_d, st));
+        HIP_TRY(big_factor(big_factor_args(p), p->NP, p->n, (int)S, F, p->M_d, p->R_d,
+                           C_d, omega_d, p->fac.L, p->fac.piv_row, status_d, st));
         HIP_TRY(launch_lu_solve(p->NP, p->n, (int)S, F, p->fac.L, p->fac.piv_row, p->phi_d, C_d,
                                 omega_d, (double2 *)I_d, kRhsPlanarF64, p->rpart, nchunk, 0.5,
                                 p->gsys, status_d, st));
@@ -599,8 +621,8 @@ int cosim_loss_and_grad(cosim_plan_t p, int B, int F, const double *C_d, const d
     const double scale = 1.0 / ((double)F * (double)p->P);
     if (big_plan(p->NP)) {
         // pivoted LU, GEMM contractions with the loss epilogue between, LU solve
-        HIP_TRY(launch_lu_big(p->NP, p->n, (int)S, F, p->M_d, p->R_d, C_d, omega_d, p->fac.L,
-                              p->fac.piv_row, status_d, st));
+        HIP_TRY(big_factor(big_factor_args(p), p->NP, p->n, (int)S, F, p->M_d, p->R_d,
+                           C_d, omega_d, p->fac.L, p->fac.piv_row, status_d, st));
         HIP_TRY(launch_lu_solve(p->NP, p->n, (int)S, F, p->fac.L, p->fac.piv_row, p->phi_d, C_d,
                                 omega_d, p->I_ws, kRhsExcitation, nullptr, 0, 0.0, nullptr,
                                 status_d, st));

@@ -148,6 +148,20 @@ enum BigRhs {
 hipError_t launch_lu_big(int NP, int n, int S, int F, const double *M_d, const double *R_d,
                          const double *C_d, const double *omega_d, double2 *A_d, int *piv_d,
                          int32_t *status_d, hipStream_t st);
+// Workspace of the blocked LDL^T above 64 loops (ldl: every R_k > 0).
+struct BigFactor {
+    bool ldl = false;
+    int *fmt = nullptr;       // [S] kFmtLDL / kFmtNeedsPivot
+    double *zmax = nullptr;   // [S] largest |re| + |im| of a diagonal entry of Z
+    double2 *wt = nullptr;    // [S][64][NP] L21 of the current panel, column-major
+    double2 *tinv = nullptr;  // [S][64][64] L11^-T of the current panel
+};
+// Factor of the S systems in the launch_lu_solve format: blocked LDL^T with
+// pivoted LU for the marked systems when bf.ldl, else pivoted LU throughout.
+hipError_t big_factor(const BigFactor &bf, int NP, int n, int S, int F,
+                      const double *M_d, const double *R_d, const double *C_d,
+                      const double *omega_d, double2 *A_d, int *piv_d, int32_t *status_d,
+                      hipStream_t st);
 hipError_t launch_lu_solve(int NP, int n, int S, int F, const double2 *A_d, const int *piv_d,
                            const double *phi_d, const double *C_d, const double *omega_d,
                            double2 *I_d, int rhs_kind, const void *rhs_d, int nchunk,
@@ -216,6 +230,9 @@ struct cosim_plan {
     // more than 64 loops: GEMM operands and the rocBLAS handle
     void *blas = nullptr;
     void *bX = nullptr, *bY = nullptr, *bW = nullptr;
+    double2 *bWt = nullptr;   // blocked LDL^T panel copy ([S][64][NP], see BigFactor)
+    double2 *bTinv = nullptr; // blocked LDL^T L11^-T ([S][64][64])
+    double *bZmax = nullptr;  // [S] largest diagonal |Z_kk| (blocked LDL^T)
     int prec_mask = 7;    // precisions whose copies of G were assembled (bit 1 << precision)
     bool ldl_ok = false;  // every R_k > 0: the LDL^T fast path applies
     int variant[3] = {0, 0, 0};  // fused-kernel variant per precision

@@ -14,6 +14,23 @@
 // replays the swaps on the right-hand side and runs the two triangular solves
 // in blocks of 16 rows (dot products against solved rows, then the 16x16
 // diagonal block inside one wave).
+//
+// When every R_k > 0 the impedance is complex symmetric with a positive
+// definite real part, and Z = L D L^T needs no row exchanges (as for the
+// smaller systems).  big_factor then runs a blocked LDL^T in panels of 64
+// columns, the matrix in HBM and only its lower triangle maintained:
+//   1. k_ldl_big_diag: the 64x64 diagonal block factored in LDS (one
+//      workgroup per system), written back as L11, D and U11 = D L11^T, with
+//      T = L11^-T for step 2;
+//   2.-3. k_ldl_big_panel: V21 = A21 T on FP64 matrix cores, then
+//      L21 = V21 D^-1 to the lower part, U12 = V21^T to the upper part, a
+//      copy of L21 for step 4;
+//   4. k_ldl_big_update: A22 -= L21 V21^T (= L21 D L21^T) on the tiles on and
+//      below the diagonal, FP64 matrix cores.
+// The upper triangle then holds U = D L^T, so with identity swaps the record
+// is an LU factor and k_lu_solve serves both.  Systems whose smallest pivot is
+// below 1e-5 of the largest |Z_kk| (or not finite), or whose input is invalid,
+// are marked and re-factored by k_lu_big with pivoting.
 #include "internal.h"
 
 namespace cosim {
@@ -74,6 +91,7 @@ __global__ __launch_bounds__(kTB) void k_lu_big(int n, int NP, int S, int F,
                                                 const double *__restrict__ C,
                                                 const double *__restrict__ omega,
                                                 double2 *__restrict__ Aall, int *__restrict__ pivall,
+                                                const int *__restrict__ only,
                                                 int32_t *__restrict__ status) {
     __shared__ double sm[kTB / 64];
     __shared__ int si[kTB / 64];
@@ -84,6 +102,7 @@ __global__ __launch_bounds__(kTB) void k_lu_big(int n, int NP, int S, int F,
     __shared__ double2 sUt[kPW][16 + 1];
     const int s = blockIdx.x;
     if (s >= S) return;  // whole workgroup
+    if (only && only[s] != kFmtNeedsPivot) return;  // re-factor marked systems only
     const int tid = threadIdx.x;
     double2 *A = Aall + (size_t)s * NP * NP;
     int *piv = pivall + (size_t)s * NP;
@@ -189,6 +208,269 @@ __global__ __launch_bounds__(kTB) void k_lu_big(int n, int NP, int S, int F,
         }
     }
     if (tid == 0) status[s] = sFlag;
+}
+
+// Lower triangle of Z = diag(R) + j w M + diag(1/(j w C)) (identity padding),
+// grid (S, NP/16): workgroup y writes rows 16y .. 16y + 15; the one with
+// y = 0 also sets the input flags, fmt = kFmtLDL (kFmtNeedsPivot for invalid
+// input) and the largest |re| + |im| of a diagonal entry.
+__global__ __launch_bounds__(kTB) void k_big_assemble(int n, int NP, int S, int F,
+                                                      const double *__restrict__ M,
+                                                      const double *__restrict__ Rv,
+                                                      const double *__restrict__ C,
+                                                      const double *__restrict__ omega,
+                                                      double2 *__restrict__ Aall,
+                                                      int *__restrict__ fmt,
+                                                      double *__restrict__ zmax,
+                                                      int32_t *__restrict__ status) {
+    __shared__ double sm[kTB / 64];
+    __shared__ int si[kTB / 64];
+    __shared__ int sFlag;
+    const int s = blockIdx.x;
+    if (s >= S) return;  // whole workgroup
+    const int tid = threadIdx.x;
+    double2 *A = Aall + (size_t)s * NP * NP;
+    const int b = s / F, f = s - b * F;
+    const double w = omega[f];
+    const double *Cb = C + (size_t)b * n;
+    if (tid == 0) sFlag = 0;
+    __syncthreads();
+    double zm = 0.0;
+    const bool first = blockIdx.y == 0;
+    for (int k = tid; first && k < n; k += kTB) {
+        const double c = Cb[k];
+        if (!isfinite(c) || c == 0.0 || !isfinite(w) || w == 0.0) atomicOr(&sFlag, COSIM_SYS_BAD_INPUT);
+        else if (c < 0.0) atomicOr(&sFlag, COSIM_SYS_NEGATIVE_C);
+        zm = fmax(zm, fabs(Rv[k]) + fabs(w * M[(size_t)k * n + k] - 1.0 / (w * c)));
+    }
+    // row i, columns j <= i: lanes along j (coalesced), waves over rows
+    for (int i = 16 * blockIdx.y + (tid >> 6); i < 16 * blockIdx.y + 16; i += kTB / 64) {
+        for (int j = tid & 63; j <= i; j += 64) {
+            double zr = 0.0, zi = 0.0;
+            if (i < n && j < n) {
+                zi = w * M[(size_t)i * n + j];
+                if (i == j) {
+                    zr = Rv[i];
+                    zi -= 1.0 / (w * Cb[i]);
+                }
+            } else if (i == j) {
+                zr = 1.0;
+            }
+            A[(size_t)i * NP + j] = make_double2(zr, zi);
+        }
+    }
+    if (!first) return;  // whole workgroup
+    int dummy = 0;
+    block_amax(zm, dummy, sm, si);  // max over the workgroup (index unused)
+    if (tid == 0) {
+        status[s] = sFlag;
+        fmt[s] = (sFlag & COSIM_SYS_BAD_INPUT) ? kFmtNeedsPivot : kFmtLDL;
+        zmax[s] = zm;
+    }
+}
+
+// Step 1 of the blocked LDL^T: the diagonal block at k0 (lower triangle in
+// HBM) factored in LDS by columns, V (= L D, unscaled) kept in place:
+//   a_rc2 -= v_r v_c2 / d_c  for c < c2 <= r,
+// while the same eliminations turn an identity into X = L11^-1:
+//   x_rc2 -= l_rc x_cc2  for c2 <= c < r.
+// Written back: L_rc = v_rc / d_c below the diagonal, d_c on it, U_cr = v_rc
+// above it, identity swaps, and T = X^T = L11^-T ([64][64] per system) for
+// step 2; a pivot below 1e-5 zmax marks the system.
+__global__ __launch_bounds__(kTB) void k_ldl_big_diag(int NP, int k0, int S,
+                                                      double2 *__restrict__ Aall,
+                                                      int *__restrict__ pivall,
+                                                      int *__restrict__ fmt,
+                                                      const double *__restrict__ zmax,
+                                                      double2 *__restrict__ tinv) {
+    __shared__ double2 sa[64][65];
+    __shared__ double2 sx[64][65];
+    const int s = blockIdx.x;
+    if (s >= S) return;  // whole workgroup
+    const int tid = threadIdx.x;
+    double2 *A = Aall + (size_t)s * NP * NP + (size_t)k0 * NP + k0;
+    for (int e = tid; e < 64 * 64; e += kTB) {
+        const int r = e >> 6, c = e & 63;
+        sa[r][c] = c <= r ? A[(size_t)r * NP + c] : make_double2(0.0, 0.0);
+        sx[r][c] = make_double2(r == c ? 1.0 : 0.0, 0.0);
+    }
+    __syncthreads();
+    const int rr = tid >> 2, q = tid & 3;  // four threads per row
+    for (int c = 0; c < 63; ++c) {
+        if (rr > c) {
+            const double2 dinv = zinv(sa[c][c]);
+            const double2 l = zmul(sa[rr][c], dinv);
+            for (int c2 = c + 1 + q; c2 <= rr; c2 += 4) sa[rr][c2] = zfms(sa[rr][c2], l, sa[c2][c]);
+            for (int c2 = q; c2 <= c; c2 += 4) sx[rr][c2] = zfms(sx[rr][c2], l, sx[c][c2]);
+        }
+        __syncthreads();
+    }
+    double2 *T = tinv + (size_t)s * 64 * 64;
+    for (int e = tid; e < 64 * 64; e += kTB) T[e] = sx[e & 63][e >> 6];  // T[k][c] = X[c][k]
+    double dmin = __builtin_inf();
+    for (int e = tid; e < 64 * 64; e += kTB) {
+        const int r = e >> 6, c = e & 63;  // lower part and diagonal by rows
+        if (c < r) A[(size_t)r * NP + c] = zmul(sa[r][c], zinv(sa[c][c]));
+        else if (c == r) {
+            const double2 d = sa[r][r];
+            A[(size_t)r * NP + r] = d;
+            const double ad = fabs(d.x) + fabs(d.y);
+            dmin = ad == ad ? fmin(dmin, ad) : 0.0;  // a NaN pivot counts as zero
+        }
+        const int c2 = e >> 6, r2 = e & 63;  // upper part by rows: U_c2,r2 = v_r2,c2
+        if (r2 > c2) A[(size_t)c2 * NP + r2] = sa[r2][c2];
+    }
+    if (tid < 64) pivall[(size_t)s * NP + k0 + tid] = k0 + tid;
+    int dummy = 0;
+    double neg = -dmin;  // min via the arg-max helper
+    __shared__ double sm[kTB / 64];
+    __shared__ int si[kTB / 64];
+    block_amax(neg, dummy, sm, si);
+    if (tid == 0 && !(-neg >= 1e-5 * zmax[s])) fmt[s] = kFmtNeedsPivot;
+}
+
+// Steps 2-3 for 64 rows i of the panel below the diagonal block, grid
+// (S, m/64): V21 = A21 T (T = L11^-T from step 1) on FP64 matrix cores, then
+// L21 = V21 D^-1 to the lower part, U12 = V21^T to the upper part and L21
+// again as column-major [64][NP] rows of wt (the A operand of step 4).  The
+// rows of A21 are staged in LDS (rows padded to 65 entries); each wave forms
+// a 32x32 quarter as 2x2 blocks of 16x16 (the layout of k_ldl_big_update,
+// with the contraction index k = 16 g + ks); V goes back through the same
+// LDS tile so that every HBM write is a run of consecutive entries.
+__global__ __launch_bounds__(kTB) void k_ldl_big_panel(int NP, int k0, int S,
+                                                       double2 *__restrict__ Aall,
+                                                       const double2 *__restrict__ tinv,
+                                                       double2 *__restrict__ wt) {
+    typedef double f64x4 __attribute__((ext_vector_type(4)));
+    __shared__ double2 sv[64][65];
+    __shared__ double2 dinv[64];
+    const int s = blockIdx.x;
+    if (s >= S) return;  // whole workgroup
+    const int tid = threadIdx.x;
+    double2 *A = Aall + (size_t)s * NP * NP;
+    const int i0 = k0 + 64 + 64 * blockIdx.y;  // first row of this block
+    if (tid < 64) dinv[tid] = zinv(A[(size_t)(k0 + tid) * NP + k0 + tid]);
+    for (int e = tid; e < 64 * 64; e += kTB) {
+        const int r = e >> 6, c = e & 63;
+        sv[r][c] = A[(size_t)(i0 + r) * NP + k0 + c];
+    }
+    __syncthreads();
+    const int lane = tid & 63, wv = tid >> 6;
+    const int g = lane >> 4, r16 = lane & 15;
+    const int wr = 32 * (wv >> 1), wc = 32 * (wv & 1);
+    const double2 *T = tinv + (size_t)s * 64 * 64 + (size_t)(16 * g) * 64 + wc + r16;
+    f64x4 Vr[2][2], Vi[2][2];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) {
+            Vr[bi][bj] = f64x4{0.0, 0.0, 0.0, 0.0};
+            Vi[bi][bj] = f64x4{0.0, 0.0, 0.0, 0.0};
+        }
+#pragma unroll 4
+    for (int ks = 0; ks < 16; ++ks) {
+        double2 a[2], t[2];
+#pragma unroll
+        for (int b2 = 0; b2 < 2; ++b2) {
+            a[b2] = sv[wr + 16 * b2 + r16][16 * g + ks];
+            t[b2] = T[ks * 64 + 16 * b2];
+        }
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj) {
+                Vr[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi].x, t[bj].x, Vr[bi][bj], 0, 0, 0);
+                Vr[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[bi].y, t[bj].y, Vr[bi][bj], 0, 0, 0);
+                Vi[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi].x, t[bj].y, Vi[bi][bj], 0, 0, 0);
+                Vi[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi].y, t[bj].x, Vi[bi][bj], 0, 0, 0);
+            }
+    }
+    __syncthreads();  // every wave is done reading A21
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+                sv[wr + 16 * bi + g + 4 * m][wc + 16 * bj + r16] =
+                    make_double2(Vr[bi][bj][m], Vi[bi][bj][m]);
+    __syncthreads();
+    double2 *W = wt + (size_t)s * 64 * NP;
+    for (int e = tid; e < 64 * 64; e += kTB) {
+        const int r = e >> 6, c = e & 63;
+        A[(size_t)(i0 + r) * NP + k0 + c] = zmul(sv[r][c], dinv[c]);
+        const int c2 = e >> 6, r2 = e & 63;  // transposed: consecutive threads along rows
+        A[(size_t)(k0 + c2) * NP + i0 + r2] = sv[r2][c2];
+        W[(size_t)c2 * NP + (i0 - k0 - 64) + r2] = zmul(sv[r2][c2], dinv[c2]);
+    }
+}
+
+// Step 4: A22 -= L21 V21^T on the 64x64 tiles of the trailing matrix on or
+// below the diagonal (a diagonal tile is updated in full; its part above the
+// diagonal is never read).  grid (S, nt(nt+1)/2), tile t = ti(ti+1)/2 + tj.
+// Each wave takes a 32x32 quarter as 2x2 FP64 MFMA blocks of 16x16 (real and
+// imaginary accumulators; lane l holds column l%16, rows g + 4m, g = l/16).
+// Panel column c enters as MFMA step ks = c % 16 of lane group g = c / 16 for
+// both operands, so each lane's operand is one 16-byte load and the 16 lanes
+// of a group read 256 consecutive bytes: the A operand from wt (rows of
+// L21^T), the B operand from U12 (rows of V21^T).
+__global__ __launch_bounds__(kTB) void k_ldl_big_update(int NP, int k0, int S,
+                                                        double2 *__restrict__ Aall,
+                                                        const double2 *__restrict__ wt) {
+    typedef double f64x4 __attribute__((ext_vector_type(4)));
+    const int s = blockIdx.x;
+    if (s >= S) return;  // whole workgroup
+    const int t = blockIdx.y;
+    int ti = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+    while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+    while (ti * (ti + 1) / 2 > t) --ti;
+    const int tj = t - ti * (ti + 1) / 2;
+    const int base = k0 + 64;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int g = lane >> 4, r16 = lane & 15;
+    const int wi = base + 64 * ti + 32 * (wv >> 1);  // first row of this wave's quarter
+    const int wj = base + 64 * tj + 32 * (wv & 1);   // first column
+    double2 *A = Aall + (size_t)s * NP * NP;
+    // lane's operand streams: L21[wi + 16 bi + r16][16 g + ks] and V21[wj + 16 bj + r16][16 g + ks]
+    const double2 *La = wt + (size_t)s * 64 * NP + (size_t)(16 * g) * NP + (wi - base) + r16;
+    const double2 *Vb = A + (size_t)(k0 + 16 * g) * NP + wj + r16;
+    f64x4 Cr[2][2], Ci[2][2];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) {
+            Cr[bi][bj] = f64x4{0.0, 0.0, 0.0, 0.0};
+            Ci[bi][bj] = f64x4{0.0, 0.0, 0.0, 0.0};
+        }
+#pragma unroll 4
+    for (int ks = 0; ks < 16; ++ks) {
+        double2 l[2], v[2];
+#pragma unroll
+        for (int b2 = 0; b2 < 2; ++b2) {
+            l[b2] = La[(size_t)ks * NP + 16 * b2];
+            v[b2] = Vb[(size_t)ks * NP + 16 * b2];
+        }
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj) {
+                // (lr + j li)(vr + j vi): re = lr vr - li vi, im = lr vi + li vr
+                Cr[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(l[bi].x, v[bj].x, Cr[bi][bj], 0, 0, 0);
+                Cr[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(-l[bi].y, v[bj].y, Cr[bi][bj], 0, 0, 0);
+                Ci[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(l[bi].x, v[bj].y, Ci[bi][bj], 0, 0, 0);
+                Ci[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(l[bi].y, v[bj].x, Ci[bi][bj], 0, 0, 0);
+            }
+    }
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                double2 *c = A + (size_t)(wi + 16 * bi + g + 4 * m) * NP + wj + 16 * bj + r16;
+                const double2 a = *c;
+                *c = make_double2(a.x - Cr[bi][bj][m], a.y - Ci[bi][bj][m]);
+            }
 }
 
 // Adjoint right-hand side: rscale * conj(sum over chunks of (rr + j ri)).
@@ -334,7 +616,38 @@ hipError_t launch_lu_big(int NP, int n, int S, int F, const double *M_d, const d
                          int32_t *status_d, hipStream_t st) {
     if (NP % 64 != 0 || NP > kMaxLoopsBig) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_lu_big, dim3(S), dim3(kTB), 0, st, n, NP, S, F, M_d, R_d, C_d, omega_d,
-                       A_d, piv_d, status_d);
+                       A_d, piv_d, nullptr, status_d);
+    return hipGetLastError();
+}
+
+hipError_t big_factor(const BigFactor &bf, int NP, int n, int S, int F,
+                      const double *M_d, const double *R_d, const double *C_d,
+                      const double *omega_d, double2 *A_d, int *piv_d, int32_t *status_d,
+                      hipStream_t st) {
+    if (!bf.ldl) return launch_lu_big(NP, n, S, F, M_d, R_d, C_d, omega_d, A_d, piv_d, status_d, st);
+    if (NP % 64 != 0 || NP > kMaxLoopsBig || !bf.fmt || !bf.zmax || !bf.wt || !bf.tinv)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_big_assemble, dim3(S, NP / 16), dim3(kTB), 0, st, n, NP, S, F, M_d,
+                       R_d, C_d, omega_d, A_d, bf.fmt, bf.zmax, status_d);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    for (int k0 = 0; k0 < NP; k0 += 64) {
+        hipLaunchKernelGGL(k_ldl_big_diag, dim3(S), dim3(kTB), 0, st, NP, k0, S, A_d, piv_d,
+                           bf.fmt, bf.zmax, bf.tinv);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        const int m = NP - k0 - 64;
+        if (m == 0) break;
+        hipLaunchKernelGGL(k_ldl_big_panel, dim3(S, m / 64), dim3(kTB), 0, st, NP, k0, S, A_d,
+                           bf.tinv, bf.wt);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        const int nt = m / 64;
+        hipLaunchKernelGGL(k_ldl_big_update, dim3(S, nt * (nt + 1) / 2), dim3(kTB), 0, st, NP,
+                           k0, S, A_d, bf.wt);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    // pivoted LU (from a fresh Z) for the systems marked on the way
+    hipLaunchKernelGGL(k_lu_big, dim3(S), dim3(kTB), 0, st, n, NP, S, F, M_d, R_d, C_d, omega_d,
+                       A_d, piv_d, bf.fmt, status_d);
     return hipGetLastError();
 }
 
