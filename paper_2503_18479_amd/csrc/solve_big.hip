@@ -473,6 +473,23 @@ __global__ __launch_bounds__(kTB) void k_ldl_big_update(int NP, int k0, int S,
             }
 }
 
+// sum of row[j] x[j] over j = j0, j0 + 16, ... < j1, as four independent
+// partial sums (stride 64) so that four row loads are in flight at once
+__device__ inline double2 dot_run(const double2 *__restrict__ row, const double2 *x, int j0,
+                                  int j1) {
+    double2 a0 = make_double2(0.0, 0.0), a1 = a0, a2 = a0, a3 = a0;
+    int j = j0;
+    for (; j + 48 < j1; j += 64) {
+        const double2 r0 = row[j], r1 = row[j + 16], r2 = row[j + 32], r3 = row[j + 48];
+        a0 = zfma(a0, r0, x[j]);
+        a1 = zfma(a1, r1, x[j + 16]);
+        a2 = zfma(a2, r2, x[j + 32]);
+        a3 = zfma(a3, r3, x[j + 48]);
+    }
+    for (; j < j1; j += 16) a0 = zfma(a0, row[j], x[j]);
+    return make_double2((a0.x + a1.x) + (a2.x + a3.x), (a0.y + a1.y) + (a2.y + a3.y));
+}
+
 // Adjoint right-hand side: rscale * conj(sum over chunks of (rr + j ri)).
 // Forward: I[s][k]; adjoint: gsys[s][k] = 2 Re(mu_k I_k / (j w C_k^2)).
 template <int RHS>
@@ -539,9 +556,8 @@ __global__ __launch_bounds__(kTB) void k_lu_solve(int n, int NP, int S, int F,
     const int r = tid >> 4, q = tid & 15;
     // forward: L y = P b, L unit lower
     for (int r0 = 0; r0 < NP; r0 += 16) {
-        double2 acc = make_double2(0.0, 0.0);
         const double2 *row = A + (size_t)(r0 + r) * NP;
-        for (int j = q; j < r0; j += 16) acc = zfma(acc, row[j], sx[j]);
+        double2 acc = dot_run(row, sx, q, r0);
 #pragma unroll
         for (int off = 8; off >= 1; off >>= 1) {
             acc.x += __shfl_xor(acc.x, off);
@@ -563,9 +579,8 @@ __global__ __launch_bounds__(kTB) void k_lu_solve(int n, int NP, int S, int F,
     }
     // backward: U x = y
     for (int r0 = NP - 16; r0 >= 0; r0 -= 16) {
-        double2 acc = make_double2(0.0, 0.0);
         const double2 *row = A + (size_t)(r0 + r) * NP;
-        for (int j = r0 + 16 + q; j < NP; j += 16) acc = zfma(acc, row[j], sx[j]);
+        double2 acc = dot_run(row, sx, r0 + 16 + q, NP);
 #pragma unroll
         for (int off = 8; off >= 1; off >>= 1) {
             acc.x += __shfl_xor(acc.x, off);

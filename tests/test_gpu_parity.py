@@ -550,6 +550,36 @@ def test_big_without_resistance_pivots(dev):
     assert np.max(_nrel(grad.cpu().numpy(), gr, axis=1)) < 1e-9
 
 
+def test_big_small_pivot_falls_back(dev):
+    """Above 64 loops: tiny R with one loop tuned to its own resonance gives a
+    tiny pivot in the blocked LDL^T; that system is re-factored with pivoting
+    and every result still matches the oracle."""
+    from paper_2503_18479_amd import Geometry, Plan
+    from array_oracle import oracle_M_array
+    wl = W.small_array(9, 9, batch=3, grid=9, n_freq=2, seed=23)
+    g = wl.geom
+    g.R[:] = 1e-6
+    M = oracle_M_array(g)
+    w = wl.omega[0]
+    wl.C[1, 0] = 1.0 / (w * w * M[0, 0])
+    G = O.field_matrix(g.verts, g.seg_off, wl.pts)
+    Phi = O.flux(g.verts, g.seg_off, wl.bext_z)
+    plan = Plan(Geometry.from_workload(g), torch.tensor(wl.pts, device=dev), wl.bext_z)
+    C = torch.tensor(wl.C, device=dev); om = torch.tensor(wl.omega, device=dev)
+    T = torch.tensor(wl.target, device=dev)
+    loss, grad, st = plan.loss_and_grad(C, om, T, precision=0)
+    torch.cuda.synchronize()
+    assert int(st.abs().sum()) == 0
+    Lr = O.evaluate(G, M, g.R, Phi, wl.C, wl.omega, wl.target)[2]
+    gr = O.grad_adjoint(G, M, g.R, Phi, wl.C, wl.omega, wl.target)
+    assert np.max(np.abs(loss.cpu().numpy() - Lr) / Lr) < 1e-9
+    assert np.max(_nrel(grad.cpu().numpy(), gr, axis=1)) < 1e-9
+    I, st = plan.solve(C, om)
+    torch.cuda.synchronize()
+    Ir = O.evaluate(G, M, g.R, Phi, wl.C, wl.omega, wl.target)[0]
+    assert _nrel(I.cpu().numpy(), Ir) < 1e-9
+
+
 def test_big_bad_input_flags(dev):
     c = _case("n144")
     C = c.C.clone()
