@@ -61,6 +61,9 @@ def parse():
     ap.add_argument("--large-adam", type=int, default=200,
                     help="the 32x32 array (1,024 loops, 262,144 points, batch 256): this many "
                          "Adam steps after the per-step timing (0: skip the line)")
+    ap.add_argument("--profile-large", type=int, default=None,
+                    help="only the 32x32 array: time this many steps per mode (no Adam, no "
+                         "8x8 line), for a profiler run")
     ap.add_argument("--variant", type=int, default=None,
                     help="with --profile-steps: use this fused-kernel variant instead of tuning")
     return ap.parse_args()
@@ -173,6 +176,16 @@ def ragged_line(n_inst: int, mixed: str, steps: int, torch) -> dict:
             "setup_s": t_setup, "precision": mixed}
 
 
+def reference_copy(torch, dev):
+    """A device copy of known size (256 MiB read + 256 MiB written) that
+    calibrates the HBM byte counters of a profiler run."""
+    x = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=dev)
+    x.fill_(1.0)
+    y = x.clone()
+    torch.cuda.synchronize()
+    del x, y
+
+
 def large_line(adam_steps: int, mixed: str, steps: int, torch) -> dict:
     """The 32x32 array (1,024 loops, 512x512 points at z = 2 cm, batch 256,
     one frequency): per-step time and phases of cosim_loss_and_grad in the
@@ -249,6 +262,11 @@ def main():
         print("bench.py needs a HIP device", file=sys.stderr)
         sys.exit(1)
     dev = torch.device("cuda:0")
+    if args.profile_large is not None:
+        out = large_line(0, args.mixed, args.profile_large, torch)
+        reference_copy(torch, dev)
+        print(f"[bench] profiled the 32x32 array: {out['modes']}", file=sys.stderr, flush=True)
+        return
     wl = W.config3_array8x8(batch=args.batch, grid=args.grid, two_planes=args.two_planes,
                             n_freq=args.freqs)
     g = wl.geom
@@ -266,13 +284,7 @@ def main():
             plan.set_variant(PREC_CODE[args.mixed], args.variant)
         time_mode(plan, C, om, T, args.mixed, args.profile_steps, 1, torch,
                   tune=not args.no_autotune and args.variant is None)
-        # reference copy of known size (256 MiB read + 256 MiB written) that
-        # calibrates the HBM byte counters of a profiler run
-        x = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=dev)
-        x.fill_(1.0)
-        y = x.clone()
-        torch.cuda.synchronize()
-        del x, y
+        reference_copy(torch, dev)
         print(f"[bench] profiled {args.profile_steps} steps of {args.mixed} and a 256 MiB copy",
               file=sys.stderr)
         return

@@ -407,7 +407,13 @@ __global__ __launch_bounds__(kTB) void k_ldl_big_panel(int NP, int k0, int S,
 
 // Step 4: A22 -= L21 V21^T on the 64x64 tiles of the trailing matrix on or
 // below the diagonal (a diagonal tile is updated in full; its part above the
-// diagonal is never read).  grid (S, nt(nt+1)/2), tile t = ti(ti+1)/2 + tj.
+// diagonal is never read), nt(nt+1)/2 = T tiles per system, tile
+// t = ti(ti+1)/2 + tj.  One-dimensional grid of 8 ceil(S/8) T workgroups,
+// mapped so that every tile of a system runs on one XCD and the tiles of a
+// system are consecutive there (workgroups are dealt to the 8 XCDs round
+// robin): workgroup id -> XCD x = id % 8, its k = id / 8-th workgroup on that
+// XCD takes tile k % T of system 8 (k / T) + x.  The L21 and V21 panels of
+// the few systems in flight on an XCD then stay in its L2 across their tiles.
 // Each wave takes a 32x32 quarter as 2x2 FP64 MFMA blocks of 16x16 (real and
 // imaginary accumulators; lane l holds column l%16, rows g + 4m, g = l/16).
 // Panel column c enters as MFMA step ks = c % 16 of lane group g = c / 16 for
@@ -416,11 +422,12 @@ __global__ __launch_bounds__(kTB) void k_ldl_big_panel(int NP, int k0, int S,
 // L21^T), the B operand from U12 (rows of V21^T).
 __global__ __launch_bounds__(kTB) void k_ldl_big_update(int NP, int k0, int S,
                                                         double2 *__restrict__ Aall,
-                                                        const double2 *__restrict__ wt) {
+                                                        const double2 *__restrict__ wt, int T) {
     typedef double f64x4 __attribute__((ext_vector_type(4)));
-    const int s = blockIdx.x;
+    const int kx = blockIdx.x >> 3;
+    const int s = 8 * (kx / T) + (blockIdx.x & 7);
     if (s >= S) return;  // whole workgroup
-    const int t = blockIdx.y;
+    const int t = kx % T;
     int ti = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
     while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
     while (ti * (ti + 1) / 2 > t) --ti;
@@ -655,9 +662,9 @@ hipError_t big_factor(const BigFactor &bf, int NP, int n, int S, int F,
         hipLaunchKernelGGL(k_ldl_big_panel, dim3(S, m / 64), dim3(kTB), 0, st, NP, k0, S, A_d,
                            bf.tinv, bf.wt);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        const int nt = m / 64;
-        hipLaunchKernelGGL(k_ldl_big_update, dim3(S, nt * (nt + 1) / 2), dim3(kTB), 0, st, NP,
-                           k0, S, A_d, bf.wt);
+        const int nt = m / 64, T = nt * (nt + 1) / 2;
+        hipLaunchKernelGGL(k_ldl_big_update, dim3(8 * ((S + 7) / 8) * T), dim3(kTB), 0, st, NP,
+                           k0, S, A_d, bf.wt, T);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     // pivoted LU (from a fresh Z) for the systems marked on the way
