@@ -15,7 +15,7 @@ c_void_p = ctypes.c_void_p
 c_char_p = ctypes.c_char_p
 P = ctypes.POINTER
 
-# name -> (restype, argtypes); mirrors include/cosim.h
+# name -> (restype, argtypes); mirrors include/cosim.h and include/cosim_sparam.h
 SIGNATURES = {
     "cosim_last_error": (c_char_p, []),
     "cosim_version": (c_int, []),
@@ -47,6 +47,17 @@ SIGNATURES = {
                                     c_int, c_int, c_void_p, c_void_p]),
     "cosim_plan_timing": (c_int, [c_void_p, c_int]),
     "cosim_plan_timing_read": (c_int, [c_void_p, c_void_p, c_int, P(c_int)]),
+    "cosim_sp_create": (c_int, [c_int, c_int, c_int, c_int, c_int, c_void_p, c_void_p, c_void_p,
+                                c_int, c_void_p, c_void_p, c_void_p, c_int, c_void_p, P(c_void_p)]),
+    "cosim_sp_destroy": (c_int, [c_void_p]),
+    "cosim_sp_reserve": (c_int, [c_void_p, c_int]),
+    "cosim_sp_field": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "cosim_sp_loss_and_grad": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_int, c_int, c_int,
+                                       c_void_p, c_void_p, c_void_p, c_void_p]),
+    "cosim_sp_rc": (c_int, [c_int, c_int, c_int, c_void_p, c_void_p, c_void_p, c_double, c_void_p,
+                            c_int, c_void_p]),
+    "cosim_sp_rc_backward": (c_int, [c_int, c_int, c_int, c_void_p, c_void_p, c_void_p, c_double,
+                                     c_void_p, c_int, c_void_p, c_void_p]),
 }
 
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EUNSUPPORTED"}

@@ -338,3 +338,120 @@ class CosimField(torch.autograd.Function):
 
 def cosim_field(C: torch.Tensor, plan: Plan, omega: torch.Tensor, precision=FP64) -> torch.Tensor:
     return CosimField.apply(C, plan, omega, precision_code(precision))
+
+
+# ---------------------------------------------------------------------------
+# S-parameter pipeline (include/cosim_sparam.h)
+# ---------------------------------------------------------------------------
+
+class SParamPlan:
+    """Exports of an n0-port structure (S0 [F][n0][n0] and per-port fields
+    [F][P][ncomp][n0], complex128 on the GPU) connected through
+    S_C = S_C,const + S_C,var (variable entries at rows idx_x, columns idx_y) to
+    n1 external ports driven by the waves `exc` (cosim_sp_create)."""
+
+    def __init__(self, S0: torch.Tensor, fields: torch.Tensor, idx_x, idx_y, exc,
+                 sc_const: Optional[torch.Tensor] = None, precisions=("fp64", "fp32")):
+        self._lib = load_library()
+        F, n0 = int(S0.shape[0]), int(S0.shape[1])
+        P, ncomp = int(fields.shape[1]), int(fields.shape[2])
+        self.idx_x = np.ascontiguousarray(idx_x, dtype=np.int32)
+        self.idx_y = np.ascontiguousarray(idx_y, dtype=np.int32)
+        self.exc = np.ascontiguousarray(np.atleast_1d(exc), dtype=np.complex128)
+        n1 = int(self.exc.shape[0])
+        nvar = int(self.idx_x.shape[0])
+        if self.idx_y.shape[0] != nvar:
+            raise ValueError("idx_x and idx_y differ in length")
+        N = n0 + n1
+        s0 = _dev(S0, torch.complex128, (F, n0, n0), "S0")
+        fp = _dev(fields, torch.complex128, (F, P, ncomp, n0), "fields")
+        scp = None if sc_const is None else _dev(sc_const, torch.complex128, (F, N, N), "sc_const")
+        mask = 0
+        for pr in precisions:
+            mask |= 1 << precision_code(pr)
+        h = ctypes.c_void_p()
+        check(self._lib.cosim_sp_create(n0, n1, F, P, ncomp, s0, fp, scp, nvar,
+                                        _host(self.idx_x) if nvar else None,
+                                        _host(self.idx_y) if nvar else None, _host(self.exc),
+                                        mask, _stream(), ctypes.byref(h)))
+        self._h = h
+        self.n0, self.n1, self.F, self.P, self.ncomp, self.nvar = n0, n1, F, P, ncomp, nvar
+        self.device = S0.device
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._lib.cosim_sp_destroy(h)
+            self._h = None
+
+    def reserve(self, max_batch: int) -> None:
+        check(self._lib.cosim_sp_reserve(self._h, int(max_batch)))
+
+    def _values(self, values: torch.Tensor, B: int):
+        if self.nvar == 0:
+            return None
+        return _dev(values, torch.complex128, (B, self.F, self.nvar), "values")
+
+    def field(self, values: torch.Tensor, want_field: bool = True):
+        """Returns (x [B][F][n0], B_comb [B][F][P][ncomp] or None, status [B][F])."""
+        B = int(values.shape[0])
+        x = torch.empty((B, self.F, self.n0), dtype=torch.complex128, device=self.device)
+        Bc = (torch.empty((B, self.F, self.P, self.ncomp), dtype=torch.complex128, device=self.device)
+              if want_field else None)
+        st = torch.empty((B, self.F), dtype=torch.int32, device=self.device)
+        check(self._lib.cosim_sp_field(self._h, B, self._values(values, B),
+                                       ctypes.c_void_p(x.data_ptr()),
+                                       ctypes.c_void_p(Bc.data_ptr()) if Bc is not None else None,
+                                       ctypes.c_void_p(st.data_ptr()), _stream()))
+        return x, Bc, st
+
+    def loss_and_grad(self, values: torch.Tensor, T: torch.Tensor, comp: int = 0,
+                      loss_mode: int = LOSS_MAG, precision=FP64, grad: bool = True, out=None):
+        """Returns (loss [B], 2 dL/dconj(values) [B][F][nvar] or None, status [B][F])."""
+        B = int(values.shape[0])
+        if out is None:
+            loss = torch.empty((B,), dtype=torch.float64, device=self.device)
+            g = (torch.empty((B, self.F, self.nvar), dtype=torch.complex128, device=self.device)
+                 if grad else None)
+            st = torch.empty((B, self.F), dtype=torch.int32, device=self.device)
+        else:
+            loss, g, st = out
+        check(self._lib.cosim_sp_loss_and_grad(
+            self._h, B, self._values(values, B), _dev(T, torch.float64, (self.P,), "T"), int(comp),
+            int(loss_mode), precision_code(precision), ctypes.c_void_p(loss.data_ptr()),
+            ctypes.c_void_p(g.data_ptr()) if g is not None else None,
+            ctypes.c_void_p(st.data_ptr()), _stream()))
+        return loss, g, st
+
+
+def sp_rc(R: torch.Tensor, C: torch.Tensor, omega: torch.Tensor, z0: float = 50.0,
+          out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Reflection of the RC loads (Eq. 2-3) [B][F][n], or into the first n
+    columns of out [B][F][ld] (cosim_sp_rc)."""
+    lib = load_library()
+    B, n = int(C.shape[0]), int(C.shape[1])
+    F = int(omega.shape[0])
+    if out is None:
+        out = torch.empty((B, F, n), dtype=torch.complex128, device=C.device)
+    ld = int(out.shape[2])
+    check(lib.cosim_sp_rc(B, F, n, _dev(R, torch.float64, (n,), "R"), _dev(C, torch.float64, (B, n), "C"),
+                          _dev(omega, torch.float64, (F,), "omega"), float(z0),
+                          _dev(out, torch.complex128, (B, F, ld), "out"), ld, _stream()))
+    return out
+
+
+def sp_rc_backward(R: torch.Tensor, C: torch.Tensor, omega: torch.Tensor, g: torch.Tensor,
+                   z0: float = 50.0) -> torch.Tensor:
+    """dL/dC [B][n] from g = 2 dL/dconj(Gamma) in the first n columns of g
+    [B][F][ld] (cosim_sp_rc_backward)."""
+    lib = load_library()
+    B, n = int(C.shape[0]), int(C.shape[1])
+    F = int(omega.shape[0])
+    ld = int(g.shape[2])
+    gC = torch.empty((B, n), dtype=torch.float64, device=C.device)
+    check(lib.cosim_sp_rc_backward(B, F, n, _dev(R, torch.float64, (n,), "R"),
+                                   _dev(C, torch.float64, (B, n), "C"),
+                                   _dev(omega, torch.float64, (F,), "omega"), float(z0),
+                                   _dev(g, torch.complex128, (B, F, ld), "g"), ld,
+                                   ctypes.c_void_p(gC.data_ptr()), _stream()))
+    return gC

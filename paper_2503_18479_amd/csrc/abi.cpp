@@ -11,7 +11,9 @@
 #include <cstring>
 #include <mutex>
 #include <new>
+#include <vector>
 
+#include "cosim_sparam.h"
 #include "internal.h"
 
 using namespace cosim;
@@ -867,6 +869,256 @@ int cosim_plan_timing_read(cosim_plan_t p, double *ms, int max_records, int *n_r
     }
     *n_records = nr;
     p->timing_used = 0;
+    return COSIM_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// S-parameter pipeline (include/cosim_sparam.h)
+// ---------------------------------------------------------------------------
+
+struct cosim_sp {
+    int device = -1;
+    int N = 0, prec_mask = 0;
+    SpDev d;
+    SpWork w;
+    size_t cap = 0;  // configurations the workspace holds
+    void *blas = nullptr;
+    std::vector<int> ix, iy;  // host copies of the index pairs
+    ~cosim_sp() {
+        dfree(d.S0);
+        dfree(d.K);
+        dfree(d.r0);
+        dfree(d.exc);
+        dfree(d.ix);
+        dfree(d.iy);
+        dfree(d.fields64);
+        dfree(d.fields32);
+        dfree(w.X);
+        dfree(w.Xg);
+        dfree(w.Y);
+        dfree(w.Rp);
+        dfree(w.lpart);
+        big_blas_destroy(blas);
+    }
+};
+
+namespace {
+
+std::once_flag g_sp_lds_once;
+hipError_t g_sp_lds_err = hipSuccess;
+
+int sp_check_device(const cosim_sp *p) {
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != p->device)
+        return fail(COSIM_EINVAL, "current device %d differs from the S-parameter plan's device %d",
+                    dev, p->device);
+    return COSIM_OK;
+}
+
+// P-chunk of the contractions: about sqrt(P n0) rows (a multiple of 256), which
+// balances the chunk of B_comb (S rows entries) against the per-chunk partial
+// sums (S n0 P / rows entries), and at most 2^28 / S rows
+int sp_rows(int P, int n0, size_t systems) {
+    size_t rows = (size_t)std::ceil(std::sqrt((double)P * n0) / 256.0) * 256;
+    const size_t cap = std::max<size_t>(256, (((size_t)1 << 28) / std::max<size_t>(systems, 1)) / 256 * 256);
+    rows = std::min(std::max<size_t>(rows, 256), cap);
+    return (int)std::min<size_t>(rows, (size_t)P);
+}
+
+int sp_ensure(cosim_sp *p, int B) {
+    if ((size_t)B <= p->cap) return COSIM_OK;
+    dfree(p->w.X);
+    dfree(p->w.Xg);
+    dfree(p->w.Y);
+    dfree(p->w.Rp);
+    dfree(p->w.lpart);
+    p->cap = 0;
+    const size_t S = (size_t)B * p->d.F, n0 = (size_t)p->d.n0;
+    const int rows = sp_rows(p->d.P, p->d.n0, S);
+    const int nchunk = (p->d.P + rows - 1) / rows;
+    if (hipMalloc((void **)&p->w.X, S * n0 * sizeof(double2)) != hipSuccess ||
+        hipMalloc(&p->w.Xg, S * n0 * sizeof(double2)) != hipSuccess ||
+        hipMalloc(&p->w.Y, S * (size_t)rows * sizeof(double2)) != hipSuccess ||
+        hipMalloc(&p->w.Rp, (size_t)nchunk * S * n0 * sizeof(double2)) != hipSuccess ||
+        hipMalloc((void **)&p->w.lpart, (size_t)nchunk * S * sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(COSIM_ENOMEM, "S-parameter workspace for %d configurations failed", B);
+    }
+    p->w.B = B;
+    p->w.rows = rows;
+    p->w.nchunk = nchunk;
+    p->cap = (size_t)B;
+    return COSIM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cosim_sp_create(int n0, int n1, int F, int P, int ncomp, const double *S0_d,
+                    const double *fields_d, const double *sc_const_d, int nvar,
+                    const int32_t *idx_x, const int32_t *idx_y, const double *exc,
+                    int precisions, void *stream, cosim_sp_t *out) {
+    if (!out) return fail(COSIM_EINVAL, "null output pointer");
+    *out = nullptr;
+    if (n0 < 1 || n0 > COSIM_SP_MAX_PORTS)
+        return fail(COSIM_EINVAL, "n0 = %d outside 1..%d", n0, (int)COSIM_SP_MAX_PORTS);
+    if (n1 < 1 || n1 > COSIM_SP_MAX_EXTERNAL)
+        return fail(COSIM_EINVAL, "n1 = %d outside 1..%d", n1, (int)COSIM_SP_MAX_EXTERNAL);
+    if (F < 1 || P < 1) return fail(COSIM_EINVAL, "F = %d, P = %d (both must be >= 1)", F, P);
+    if (ncomp < 1 || ncomp > 3) return fail(COSIM_EINVAL, "ncomp = %d outside 1..3", ncomp);
+    if (!S0_d || !fields_d) return fail(COSIM_EINVAL, "null S0 or field pointer");
+    if (nvar < 0 || (nvar > 0 && (!idx_x || !idx_y)))
+        return fail(COSIM_EINVAL, "nvar = %d with null index arrays", nvar);
+    if (!exc) return fail(COSIM_EINVAL, "null drive waves");
+    if (precisions & (1 << COSIM_BF16X3))
+        return fail(COSIM_EUNSUPPORTED, "BF16X3 contractions are not offered for S-parameter plans");
+    if (precisions & ~((1 << COSIM_FP64) | (1 << COSIM_FP32)) || precisions == 0)
+        return fail(COSIM_EINVAL, "precision mask %d", precisions);
+    const int N = n0 + n1;
+    for (int e = 0; e < nvar; ++e)
+        if (idx_x[e] < 0 || idx_x[e] >= N || idx_y[e] < 0 || idx_y[e] >= N)
+            return fail(COSIM_EINVAL, "index pair %d = (%d, %d) outside the %d x %d network", e,
+                        idx_x[e], idx_y[e], N, N);
+    if ((size_t)F * P * ncomp * n0 > ((size_t)1 << 31))
+        return fail(COSIM_EUNSUPPORTED, "field tensor of %zu entries per plan exceeds 2^31",
+                    (size_t)F * P * ncomp * n0);
+    cosim_sp *p = new (std::nothrow) cosim_sp;
+    if (!p) return fail(COSIM_ENOMEM, "host allocation failed");
+    auto cleanup = [&](int code) {
+        if (code != COSIM_OK) delete p;
+        return code;
+    };
+#define SP_TRY(x)                                                                          \
+    do {                                                                                    \
+        hipError_t e_ = (x);                                                                \
+        if (e_ != hipSuccess) {                                                             \
+            (void)hipGetLastError();                                                        \
+            return cleanup(fail(e_ == hipErrorOutOfMemory ? COSIM_ENOMEM : COSIM_EDEVICE,   \
+                                "%s failed: %s", #x, hipGetErrorString(e_)));               \
+        }                                                                                   \
+    } while (0)
+    hipStream_t st = (hipStream_t)stream;
+    SP_TRY(hipGetDevice(&p->device));
+    std::call_once(g_sp_lds_once, [] { g_sp_lds_err = sp_set_lds_limit(); });
+    SP_TRY(g_sp_lds_err);
+    p->N = N;
+    p->prec_mask = precisions;
+    SpDev &d = p->d;
+    d.n0 = n0;
+    d.n1 = n1;
+    d.F = F;
+    d.P = P;
+    d.ncomp = ncomp;
+    d.nvar = nvar;
+    p->ix.assign(idx_x, idx_x + nvar);
+    p->iy.assign(idx_y, idx_y + nvar);
+    const size_t nf = (size_t)F * P * ncomp * n0;
+    SP_TRY(hipMalloc((void **)&d.S0, (size_t)F * n0 * n0 * sizeof(double2)));
+    SP_TRY(hipMalloc((void **)&d.K, (size_t)F * n0 * n0 * sizeof(double2)));
+    SP_TRY(hipMalloc((void **)&d.r0, (size_t)F * n0 * sizeof(double2)));
+    SP_TRY(hipMalloc((void **)&d.exc, (size_t)n1 * sizeof(double2)));
+    SP_TRY(hipMalloc((void **)&d.ix, std::max(nvar, 1) * sizeof(int)));
+    SP_TRY(hipMalloc((void **)&d.iy, std::max(nvar, 1) * sizeof(int)));
+    SP_TRY(hipMalloc((void **)&d.fields64, nf * sizeof(double2)));
+    if (precisions & (1 << COSIM_FP32)) SP_TRY(hipMalloc((void **)&d.fields32, nf * sizeof(float2)));
+    SP_TRY(hipMemcpyAsync(d.S0, S0_d, (size_t)F * n0 * n0 * sizeof(double2), hipMemcpyDeviceToDevice, st));
+    SP_TRY(hipMemcpyAsync(d.fields64, fields_d, nf * sizeof(double2), hipMemcpyDeviceToDevice, st));
+    SP_TRY(hipMemcpyAsync(d.exc, exc, (size_t)n1 * sizeof(double2), hipMemcpyHostToDevice, st));
+    if (nvar > 0) {
+        SP_TRY(hipMemcpyAsync(d.ix, p->ix.data(), nvar * sizeof(int), hipMemcpyHostToDevice, st));
+        SP_TRY(hipMemcpyAsync(d.iy, p->iy.data(), nvar * sizeof(int), hipMemcpyHostToDevice, st));
+    }
+    if (d.fields32) SP_TRY(sp_to_c64(nf, d.fields64, d.fields32, st));
+    SP_TRY(sp_prep(d, (const double2 *)sc_const_d, st));
+    SP_TRY(big_blas_create(&p->blas));
+    SP_TRY(hipStreamSynchronize(st));  // host index copies and the caller's inputs are done with
+#undef SP_TRY
+    *out = p;
+    return COSIM_OK;
+}
+
+int cosim_sp_destroy(cosim_sp_t p) {
+    delete p;
+    return COSIM_OK;
+}
+
+int cosim_sp_reserve(cosim_sp_t p, int max_batch) {
+    if (!p) return fail(COSIM_EINVAL, "null plan");
+    if (max_batch < 0) return fail(COSIM_EINVAL, "max_batch = %d", max_batch);
+    int rc = sp_check_device(p);
+    if (rc != COSIM_OK) return rc;
+    return sp_ensure(p, max_batch);
+}
+
+int cosim_sp_field(cosim_sp_t p, int B, const double *values_d, double *x_d, double *field_d,
+                   int32_t *status_d, void *stream) {
+    if (!p) return fail(COSIM_EINVAL, "null plan");
+    if (B < 0) return fail(COSIM_EINVAL, "B = %d", B);
+    if (B == 0) return COSIM_OK;
+    if ((p->d.nvar > 0 && !values_d) || !status_d)
+        return fail(COSIM_EINVAL, "null values or status pointer");
+    int rc = sp_check_device(p);
+    if (rc != COSIM_OK) return rc;
+    if ((rc = sp_ensure(p, B)) != COSIM_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(sp_forward(p->d, B, (const double2 *)values_d, p->w.X, p->w.Xg, 0, status_d, st));
+    const size_t S = (size_t)B * p->d.F;
+    if (x_d)
+        HIP_TRY(hipMemcpyAsync(x_d, p->w.X, S * p->d.n0 * sizeof(double2), hipMemcpyDeviceToDevice, st));
+    if (field_d) HIP_TRY(sp_field(p->blas, p->d, B, (const double2 *)p->w.Xg, (double2 *)field_d, st));
+    return COSIM_OK;
+}
+
+int cosim_sp_loss_and_grad(cosim_sp_t p, int B, const double *values_d, const double *T_d,
+                           int comp, int loss_mode, int precision, double *loss_d, double *grad_d,
+                           int32_t *status_d, void *stream) {
+    if (!p) return fail(COSIM_EINVAL, "null plan");
+    if (B < 0) return fail(COSIM_EINVAL, "B = %d", B);
+    if (comp < 0 || comp >= p->d.ncomp)
+        return fail(COSIM_EINVAL, "component %d outside 0..%d", comp, p->d.ncomp - 1);
+    if (loss_mode != COSIM_LOSS_MAG && loss_mode != COSIM_LOSS_COMPLEX)
+        return fail(COSIM_EINVAL, "loss mode %d", loss_mode);
+    if (precision == COSIM_BF16X3)
+        return fail(COSIM_EUNSUPPORTED, "BF16X3 contractions are not offered for S-parameter plans");
+    if (precision != COSIM_FP64 && precision != COSIM_FP32)
+        return fail(COSIM_EINVAL, "precision %d", precision);
+    if (!(p->prec_mask & (1 << precision)))
+        return fail(COSIM_EINVAL, "the plan was created without precision %d", precision);
+    if (B == 0) return COSIM_OK;
+    if ((p->d.nvar > 0 && !values_d) || !T_d || !loss_d || !status_d)
+        return fail(COSIM_EINVAL, "null values, target, loss or status pointer");
+    int rc = sp_check_device(p);
+    if (rc != COSIM_OK) return rc;
+    if ((rc = sp_ensure(p, B)) != COSIM_OK) return rc;
+    HIP_TRY(sp_loss_and_grad(p->blas, p->d, p->w, B, (const double2 *)values_d, T_d, comp, loss_mode,
+                             precision == COSIM_FP64 ? 0 : 1, loss_d, (double2 *)grad_d, status_d,
+                             (hipStream_t)stream));
+    return COSIM_OK;
+}
+
+int cosim_sp_rc(int B, int F, int n, const double *R_d, const double *C_d, const double *omega_d,
+                double z0, double *gamma_d, int ld, void *stream) {
+    if (B < 0 || F < 1 || n < 1) return fail(COSIM_EINVAL, "B = %d, F = %d, n = %d", B, F, n);
+    if (ld < n) return fail(COSIM_EINVAL, "row stride %d below n = %d", ld, n);
+    if (!(z0 > 0.0)) return fail(COSIM_EINVAL, "reference impedance %g", z0);
+    if (B > 0 && (!R_d || !C_d || !omega_d || !gamma_d)) return fail(COSIM_EINVAL, "null pointer");
+    HIP_TRY(sp_rc(B, F, n, R_d, C_d, omega_d, z0, (double2 *)gamma_d, ld, (hipStream_t)stream));
+    return COSIM_OK;
+}
+
+int cosim_sp_rc_backward(int B, int F, int n, const double *R_d, const double *C_d,
+                         const double *omega_d, double z0, const double *g_d, int ld, double *gC_d,
+                         void *stream) {
+    if (B < 0 || F < 1 || n < 1) return fail(COSIM_EINVAL, "B = %d, F = %d, n = %d", B, F, n);
+    if (ld < n) return fail(COSIM_EINVAL, "row stride %d below n = %d", ld, n);
+    if (!(z0 > 0.0)) return fail(COSIM_EINVAL, "reference impedance %g", z0);
+    if (B > 0 && (!R_d || !C_d || !omega_d || !g_d || !gC_d)) return fail(COSIM_EINVAL, "null pointer");
+    HIP_TRY(sp_rc_backward(B, F, n, R_d, C_d, omega_d, z0, (const double2 *)g_d, ld, gC_d,
+                           (hipStream_t)stream));
     return COSIM_OK;
 }
 

@@ -196,6 +196,46 @@ hipError_t launch_field_backward_contract(int NP, int P, int S, int n, const dou
                                           const double2 *gBz_d, double2 *rpart_d,
                                           hipStream_t st);
 
+// ---- S-parameter pipeline (sparam.hip)
+constexpr int kSpMaxPorts = 64;
+// Device-side view of an S-parameter plan (all complex arrays complex128
+// unless noted).
+struct SpDev {
+    int n0 = 0, n1 = 0, F = 0, P = 0, ncomp = 0, nvar = 0;
+    double2 *S0 = nullptr;        // [F][n0][n0]
+    double2 *K = nullptr;         // [F][n0][n0]  I - S_C11,const S0
+    double2 *r0 = nullptr;        // [F][n0]      S_C12,const exc
+    double2 *exc = nullptr;       // [n1]
+    int *ix = nullptr, *iy = nullptr;  // [nvar] rows / columns of the variable entries
+    double2 *fields64 = nullptr;  // [F][P][ncomp][n0]
+    float2 *fields32 = nullptr;   // the same in complex64 (FP32 contractions)
+};
+// Workspace for B configurations (s = b F + f).
+struct SpWork {
+    int B = 0, rows = 0, nchunk = 0;  // P-chunk of the contractions
+    double2 *X = nullptr;             // [S][n0] forward solution, FP64
+    void *Xg = nullptr;               // [F][B][n0] GEMM operand (complex128 or complex64)
+    void *Y = nullptr;                // [F][B][rows] B_comb, then conj(w), of one chunk
+    void *Rp = nullptr;               // [nchunk][F][B][n0] conj(fields^H w) per chunk
+    double *lpart = nullptr;          // [nchunk][F][B] loss partial sums
+};
+hipError_t sp_prep(const SpDev &d, const double2 *sc_const, hipStream_t st);
+hipError_t sp_set_lds_limit();
+hipError_t sp_to_c64(size_t count, const double2 *a, float2 *b, hipStream_t st);
+// Forward solves: X and Xg (prec 0: complex128, 1: complex64), status.
+hipError_t sp_forward(const SpDev &d, int B, const double2 *values, double2 *X, void *Xg, int prec,
+                      int32_t *status, hipStream_t st);
+// B_comb of every component: out[b][f][p][c] from the complex128 Xg of sp_forward.
+hipError_t sp_field(void *blas, const SpDev &d, int B, const double2 *Xg64, double2 *out,
+                    hipStream_t st);
+hipError_t sp_loss_and_grad(void *blas, const SpDev &d, const SpWork &w, int B,
+                            const double2 *values, const double *T, int comp, int loss_mode, int prec,
+                            double *loss, double2 *grad, int32_t *status, hipStream_t st);
+hipError_t sp_rc(int B, int F, int n, const double *R, const double *C, const double *omega,
+                 double z0, double2 *gam, int ld, hipStream_t st);
+hipError_t sp_rc_backward(int B, int F, int n, const double *R, const double *C, const double *omega,
+                          double z0, const double2 *g, int ld, double *gC, hipStream_t st);
+
 }  // namespace cosim
 
 // Library-owned objects behind the opaque handles.

@@ -11,15 +11,17 @@ import pytest
 from paper_2503_18479_amd import _lib
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "cosim.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("cosim.h", "cosim_sparam.h")]
 
 EINVAL, EUNSUPPORTED = -1, -4
 
 
 def _declared():
-    src = open(HEADER).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(cosim_[a-z_0-9A-Z]+)\s*\(", src)))
+    names = set()
+    for h in HEADERS:
+        src = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(cosim_[a-z_0-9A-Z]+)\s*\(", src))
+    return sorted(names)
 
 
 @pytest.fixture(scope="module")
@@ -154,3 +156,55 @@ def test_assemble_mask_and_many_argument_errors(lib):
     assert lib.cosim_loss_and_grad_many(1, arr, ints, ints, arr, arr, arr, 0, 0, arr, None,
                                         arr, None) == EINVAL
     assert b"instance 0" in lib.cosim_last_error()
+
+
+def test_sparam_argument_errors(lib):
+    """cosim_sp_* reject bad shapes, indices, masks and pointers on the host."""
+    ix = np.array([0, 1], dtype=np.int32)
+    iy = np.array([0, 2], dtype=np.int32)
+    exc = np.array([1.0, 0.0])
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: every call below fails first
+    h = ctypes.c_void_p()
+
+    def create(n0=2, n1=1, F=1, P=4, nc=1, s0=fake, fl=fake, nvar=2, x=ix, y=iy, e=exc, mask=1,
+               out=True):
+        return lib.cosim_sp_create(n0, n1, F, P, nc, s0, fl, None, nvar,
+                                   x.ctypes.data if x is not None else None,
+                                   y.ctypes.data if y is not None else None,
+                                   e.ctypes.data if e is not None else None, mask, None,
+                                   ctypes.byref(h) if out else None)
+
+    assert create(out=False) == EINVAL
+    assert create(n0=0) == EINVAL
+    assert create(n0=65) == EINVAL
+    assert create(n1=0) == EINVAL
+    assert create(n1=9) == EINVAL
+    assert create(F=0) == EINVAL
+    assert create(P=0) == EINVAL
+    assert create(nc=4) == EINVAL
+    assert create(s0=None) == EINVAL
+    assert create(fl=None) == EINVAL
+    assert create(x=None) == EINVAL
+    assert create(e=None) == EINVAL
+    assert create(mask=1 << 2) == EUNSUPPORTED
+    assert create(mask=0) == EINVAL
+    assert create(mask=1 << 5) == EINVAL
+    bad = np.array([0, 3], dtype=np.int32)  # column 3 outside the 3 x 3 network
+    assert create(y=bad) == EINVAL
+    assert b"outside" in lib.cosim_last_error()
+    neg = np.array([-1, 0], dtype=np.int32)
+    assert create(x=neg) == EINVAL
+    # calls on a null plan
+    assert lib.cosim_sp_reserve(None, 4) == EINVAL
+    assert lib.cosim_sp_field(None, 1, fake, None, None, fake, None) == EINVAL
+    assert lib.cosim_sp_loss_and_grad(None, 1, fake, fake, 0, 0, 0, fake, None, fake, None) == EINVAL
+    assert lib.cosim_sp_destroy(None) == 0
+    # RC preprocessing
+    assert lib.cosim_sp_rc(-1, 1, 2, fake, fake, fake, 50.0, fake, 2, None) == EINVAL
+    assert lib.cosim_sp_rc(1, 0, 2, fake, fake, fake, 50.0, fake, 2, None) == EINVAL
+    assert lib.cosim_sp_rc(1, 1, 2, fake, fake, fake, 50.0, fake, 1, None) == EINVAL
+    assert lib.cosim_sp_rc(1, 1, 2, fake, fake, fake, 0.0, fake, 2, None) == EINVAL
+    assert lib.cosim_sp_rc(1, 1, 2, None, fake, fake, 50.0, fake, 2, None) == EINVAL
+    assert lib.cosim_sp_rc(0, 1, 2, None, None, None, 50.0, None, 2, None) == 0  # empty batch
+    assert lib.cosim_sp_rc_backward(1, 1, 2, fake, fake, fake, 50.0, fake, 2, None, None) == EINVAL
+    assert lib.cosim_sp_rc_backward(0, 1, 2, None, None, None, 50.0, None, 2, None, None) == 0
