@@ -27,6 +27,10 @@ S-parameter cosimulation, Eq. 3-7; Sec. IV-A gives the loop impedance, Eq. 11):
             dZ/dC_k), by the adjoint, and by central finite differences.
 9. Adam     the optimiser the paper runs on C (Sec. IV), one step as defined
             by Kingma & Ba (bias-corrected first and second moments).
+10. the other circuit variables of Fig. 2: dL/dR, dL/dL (a series
+            inductance per loop) and dL/dw, by forward sensitivity, by the
+            adjoint and by central differences; the resonance capacitance of
+            Eq. 13; the bounded tanh projection of C and its derivative.
 
 Everything is float64 / complex128 NumPy.  Pins: tests/test_oracle_pins.py.
 """
@@ -378,6 +382,115 @@ def grad_fd(G, M, R, Phi, C, omega, T, h: float = 1e-15, mode: int = LOSS_MAG) -
             lm = evaluate(G, M, R, Phi, cm, omega, T, mode)[2][0]
             g[b, k] = (lp - lm) / (2 * h)
     return g
+
+
+def grad_params_forward_sensitivity(G, M, R, Phi, C, omega, T, mode: int = LOSS_MAG):
+    """Gradients of each configuration's loss with respect to the other circuit
+    parameters of Eq. 11 (the variables of Fig. 2 besides C), by perturbing one
+    parameter at a time through the solve (Eq. 9): dI = Z^-1 (dV - dZ I) with
+    V = -j w Phi, and dL = 2 Re sum_p conj(w_p) (G dI)_p.
+      R_k:  dZ = e_k e_k^T;
+      L_k (a series inductance added to loop k): dZ = j w e_k e_k^T;
+      w_f:  dZ = j M - diag(1 / (j w^2 C)) and dV = -j Phi (G does not depend on w).
+    Returns (dL/dR [B][n], dL/dL [B][n], dL/dw [B][F])."""
+    C = np.atleast_2d(C)
+    omega = np.atleast_1d(omega)
+    I = currents(M, R, Phi, C, omega)
+    W = loss_weights(field(G, I), T, mode)
+    B, n, F = C.shape[0], M.shape[0], omega.shape[0]
+    gR = np.zeros((B, n))
+    gL = np.zeros((B, n))
+    gw = np.zeros((B, F))
+    for b in range(B):
+        for f, w in enumerate(omega):
+            Z = impedance(M, R, C[b], w)
+            i = I[b, f]
+
+            def dL(dZ, dV):
+                dI = np.linalg.solve(Z, dV - dZ @ i)
+                return 2.0 * float(np.real(np.sum(np.conj(W[b, f]) * (G @ dI))))
+
+            zero = np.zeros(n, dtype=np.complex128)
+            for k in range(n):
+                E = np.zeros((n, n), dtype=np.complex128)
+                E[k, k] = 1.0
+                gR[b, k] += dL(E, zero)
+                gL[b, k] += dL(1j * w * E, zero)
+            dZw = 1j * M - np.diag(1.0 / (1j * w * w * C[b]))
+            gw[b, f] = dL(dZw, -1j * Phi)
+    return gR, gL, gw
+
+
+def grad_params_adjoint(G, M, R, Phi, C, omega, T, mode: int = LOSS_MAG):
+    """The same gradients through the adjoint of each system: with
+    Z mu = G^T conj(w) (Z is complex symmetric), dL = 2 Re(mu^T (dV - dZ I)):
+      dL/dR_k = -2 Re(mu_k I_k),  dL/dL_k = 2 w Im(mu_k I_k),
+      dL/dw = 2 Re(-j mu^T Phi - j mu^T M I + sum_k mu_k I_k / (j w^2 C_k))."""
+    C = np.atleast_2d(C)
+    omega = np.atleast_1d(omega)
+    I = currents(M, R, Phi, C, omega)
+    W = loss_weights(field(G, I), T, mode)
+    B, n, F = C.shape[0], M.shape[0], omega.shape[0]
+    gR = np.zeros((B, n))
+    gL = np.zeros((B, n))
+    gw = np.zeros((B, F))
+    for b in range(B):
+        for f, w in enumerate(omega):
+            Z = impedance(M, R, C[b], w)
+            mu = np.linalg.solve(Z, G.T @ np.conj(W[b, f]))
+            i = I[b, f]
+            gR[b] += -2.0 * np.real(mu * i)
+            gL[b] += 2.0 * w * np.imag(mu * i)
+            t = -1j * (mu @ Phi) - 1j * (mu @ (M @ i)) + np.sum(mu * i / (1j * w * w * C[b]))
+            gw[b, f] = 2.0 * np.real(t)
+    return gR, gL, gw
+
+
+def grad_params_fd(G, M, R, Phi, C, omega, T, mode: int = LOSS_MAG, hR: float = 1e-7,
+                   hL: float = 1e-15, hw: float = 1.0):
+    """Central differences of the loss for the same parameters (steps in ohm,
+    henry and rad/s); a series inductance L_k enters as M_kk + L_k."""
+    C = np.atleast_2d(C)
+    omega = np.atleast_1d(np.asarray(omega, float))
+    B, n, F = C.shape[0], M.shape[0], omega.shape[0]
+    gR = np.zeros((B, n))
+    gL = np.zeros((B, n))
+    gw = np.zeros((B, F))
+    L0 = evaluate  # local alias
+
+    def loss_of(Mv, Rv, om):
+        return L0(G, Mv, Rv, Phi, C, om, T, mode)[2]
+
+    for k in range(n):
+        Rp, Rm = R.copy(), R.copy()
+        Rp[k] += hR
+        Rm[k] -= hR
+        gR[:, k] = (loss_of(M, Rp, omega) - loss_of(M, Rm, omega)) / (2 * hR)
+        Mp, Mm = M.copy(), M.copy()
+        Mp[k, k] += hL
+        Mm[k, k] -= hL
+        gL[:, k] = (loss_of(Mp, R, omega) - loss_of(Mm, R, omega)) / (2 * hL)
+    for f in range(F):
+        op, om_ = omega.copy(), omega.copy()
+        op[f] += hw
+        om_[f] -= hw
+        gw[:, f] = (loss_of(M, R, op) - loss_of(M, R, om_)) / (2 * hw)
+    return gR, gL, gw
+
+
+def resonant_capacitance(M, omega: float, coupled: bool = True) -> np.ndarray:
+    """Eq. 13: C_r = 1 / (w^2 (L + M)).  L_k = M_kk; with `coupled`, M is the
+    sum of the loop's mutual inductances to all others (every loop carrying the
+    same current), otherwise 0 (the single-cell case of Sec. IV-A)."""
+    Lk = np.diag(M) if not coupled else M.sum(axis=1)
+    return 1.0 / (omega * omega * Lk)
+
+
+def tanh_projection(theta, cmin: float, cmax: float):
+    """The bounded projection discussed in Sec. V: C = cmin + (cmax - cmin)
+    (1 + tanh(theta)) / 2, and dC/dtheta = (cmax - cmin) (1 - tanh^2) / 2."""
+    t = np.tanh(theta)
+    return cmin + 0.5 * (cmax - cmin) * (1.0 + t), 0.5 * (cmax - cmin) * (1.0 - t * t)
 
 
 def backward_from_field_grad(G, M, R, C, omega, I, gBz) -> np.ndarray:

@@ -365,3 +365,46 @@ def test_array_inductance_by_offsets_equals_direct_oracle():
     g = W.square_array(4, 3, 0.03, 0.035, 32, 1e-3, 0.3)
     M = O.inductance_matrix_fast(g.verts, g.seg_off, g.wire_a)
     np.testing.assert_allclose(oracle_M_array(g), M, rtol=1e-13, atol=0)
+
+
+# ------------------------------------------- the other circuit variables (R, L, w)
+
+@pytest.mark.parametrize("mode", [O.LOSS_MAG, O.LOSS_COMPLEX])
+def test_parameter_gradients_adjoint_sensitivity_fd(mode):
+    """dL/dR, dL/dL (series inductance per loop) and dL/dw: the adjoint equals
+    forward sensitivity through the solve, and both equal central differences."""
+    G, M, R, Phi, C, om, T = _small_problem(B=2, F=2)
+    a = O.grad_params_adjoint(G, M, R, Phi, C, om, T, mode)
+    s = O.grad_params_forward_sensitivity(G, M, R, Phi, C, om, T, mode)
+    d = O.grad_params_fd(G, M, R, Phi, C, om, T, mode)
+    for x, y, z in zip(a, s, d):
+        assert _rel(x, y) < 1e-12
+        assert _rel(y, z) < 1e-6
+
+
+def test_resonant_capacitance_eq13():
+    """Eq. 13 makes the reactance vanish: for one loop Im Z(C_r) = 0; for the
+    coupled array with equal currents in every loop Im (Z 1)_k = 0."""
+    g = W.single_circle()
+    M1 = O.inductance_matrix(g.verts, g.seg_off, g.wire_a)
+    w = 2 * math.pi * 128e6
+    Cr = O.resonant_capacitance(M1, w, coupled=False)
+    assert abs(O.impedance(M1, g.R, Cr, w)[0, 0].imag) < 1e-12 * w * M1[0, 0]
+    wl = W.small_array(3, 2, 1, 4, n_freq=1)
+    M = O.inductance_matrix_fast(wl.geom.verts, wl.geom.seg_off, wl.geom.wire_a)
+    Cr = O.resonant_capacitance(M, w, coupled=True)
+    Z = O.impedance(M, wl.geom.R, Cr, w)
+    assert np.max(np.abs((Z @ np.ones(len(Cr))).imag)) < 1e-10 * w * np.abs(M).max()
+    Cs = O.resonant_capacitance(M, w, coupled=False)
+    np.testing.assert_allclose(Cs, 1.0 / (w * w * np.diag(M)), rtol=1e-15)
+
+
+def test_tanh_projection_range_and_derivative():
+    th = np.linspace(-6, 6, 13)
+    C, dC = O.tanh_projection(th, 10e-12, 300e-12)
+    assert np.all(C > 10e-12) and np.all(C < 300e-12)
+    np.testing.assert_allclose(O.tanh_projection(np.array([0.0]), 10e-12, 300e-12)[0], 155e-12, rtol=1e-15)
+    h = 1e-6
+    fd = (O.tanh_projection(th + h, 10e-12, 300e-12)[0] - O.tanh_projection(th - h, 10e-12, 300e-12)[0]) / (2 * h)
+    # differences of values of order 1e-10 with step 1e-6 round at about 1e-20
+    np.testing.assert_allclose(dC, fd, rtol=1e-7, atol=1e-9 * np.abs(dC).max())
