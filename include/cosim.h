@@ -189,6 +189,41 @@ int cosim_loss_and_grad(cosim_plan_t p, int B, int F, const double *C_d, const d
                         const double *T_d, int loss_mode, int precision, double *loss_d,
                         double *grad_d, int32_t *status_d, void *stream);
 
+/* Loss, dL/dC and the gradients with respect to the other circuit variables of
+ * Fig. 2 / Eq. 11, for the same call as cosim_loss_and_grad (which it runs):
+ *   gR_d     [B][n] or NULL: dL_b/dR_k = -2 sum_f Re(mu_k I_k);
+ *   gL_d     [B][n] or NULL: dL_b/dL_k of a series inductance added to loop k
+ *            (Z_kk += j w L_k), 2 sum_f w Im(mu_k I_k);
+ *   gomega_d [B][F] or NULL: dL_b/dw_f = 2 [Im(mu^T Phi) + Im(mu^T M I)
+ *            + sum_k Im(mu_k I_k) / (w^2 C_k)] (V = -j w Phi and Z both depend
+ *            on w; G does not);
+ * with mu the adjoint solution of each system (Z mu = G^T conj(w), Eq. 8-10;
+ * Z is complex symmetric).  gC_d is required (the adjoint always runs).
+ * Allocates a [S][n] workspace for mu on first use at a new size.  Systems with
+ * status bits get NaN terms, as in cosim_loss_and_grad. */
+int cosim_loss_and_grad_params(cosim_plan_t plan, int B, int F, const double *C_d,
+                               const double *omega_d, const double *T_d, int loss_mode,
+                               int precision, double *loss_d, double *gC_d, double *gR_d,
+                               double *gL_d, double *gomega_d, int32_t *status_d, void *stream);
+
+/* Resonance capacitance of Eq. 13, C_r = 1 / (w^2 (L + M)), per frequency and
+ * loop: Cr_d [F][n] from omega_d [F].  L_k = M_kk; coupled != 0 adds the loop's
+ * mutual inductances to all others (the array resonance with equal currents),
+ * coupled = 0 neglects them (the single-cell case of Sec. IV-A). */
+int cosim_resonant_capacitance(cosim_plan_t plan, int F, const double *omega_d, int coupled,
+                               double *Cr_d, void *stream);
+
+/* Bounded projection of the capacitances (Sec. V): for count elements,
+ * C = cmin + (cmax - cmin) (1 + tanh(theta)) / 2 and, if dC_d is not NULL,
+ * dC/dtheta = (cmax - cmin) (1 - tanh^2(theta)) / 2 (the chain rule factor).
+ * Requires cmin < cmax, both finite. */
+int cosim_tanh_projection(int64_t count, const double *theta_d, double cmin, double cmax,
+                          double *C_d, double *dC_d, void *stream);
+
+/* Clipping in place to [lo, hi] (Sec. V: a wide range and clipping in place of a
+ * bounded projection).  Requires lo <= hi. */
+int cosim_clip(int64_t count, double *x_d, double lo, double hi, void *stream);
+
 /* One Adam step on the capacitances, the optimiser the paper runs on C
  * (Sec. IV; learning rate 1e-13 F there), with the bias-corrected moments of
  * Kingma & Ba: with t the 1-based step and g = dL/dC,

@@ -47,6 +47,13 @@ SIGNATURES = {
                                     c_int, c_int, c_void_p, c_void_p]),
     "cosim_plan_timing": (c_int, [c_void_p, c_int]),
     "cosim_plan_timing_read": (c_int, [c_void_p, c_void_p, c_int, P(c_int)]),
+    "cosim_loss_and_grad_params": (c_int, [c_void_p, c_int, c_int, c_void_p, c_void_p, c_void_p,
+                                           c_int, c_int, c_void_p, c_void_p, c_void_p, c_void_p,
+                                           c_void_p, c_void_p, c_void_p]),
+    "cosim_resonant_capacitance": (c_int, [c_void_p, c_int, c_void_p, c_int, c_void_p, c_void_p]),
+    "cosim_tanh_projection": (c_int, [ctypes.c_int64, c_void_p, c_double, c_double, c_void_p,
+                                      c_void_p, c_void_p]),
+    "cosim_clip": (c_int, [ctypes.c_int64, c_void_p, c_double, c_double, c_void_p]),
     "cosim_sp_create": (c_int, [c_int, c_int, c_int, c_int, c_int, c_void_p, c_void_p, c_void_p,
                                 c_int, c_void_p, c_void_p, c_void_p, c_int, c_void_p, P(c_void_p)]),
     "cosim_sp_destroy": (c_int, [c_void_p]),

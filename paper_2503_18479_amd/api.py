@@ -228,6 +228,35 @@ class Plan:
 
 
     # -- optimisation driver ----------------------------------------------------
+    def loss_and_grad_params(self, C: torch.Tensor, omega: torch.Tensor, T: torch.Tensor,
+                             loss_mode: int = LOSS_MAG, precision=FP32):
+        """cosim_loss_and_grad_params: (loss [B], dL/dC [B][n], dL/dR [B][n],
+        dL/dL [B][n] of a series inductance per loop, dL/dw [B][F], status [B][F])."""
+        B, F = int(C.shape[0]), int(omega.shape[0])
+        dev = self.device
+        loss = torch.empty((B,), dtype=torch.float64, device=dev)
+        gC = torch.empty((B, self.n), dtype=torch.float64, device=dev)
+        gR = torch.empty((B, self.n), dtype=torch.float64, device=dev)
+        gL = torch.empty((B, self.n), dtype=torch.float64, device=dev)
+        gw = torch.empty((B, F), dtype=torch.float64, device=dev)
+        st = torch.empty((B, F), dtype=torch.int32, device=dev)
+        ptr = lambda t: ctypes.c_void_p(t.data_ptr())
+        check(self._lib.cosim_loss_and_grad_params(
+            self._h, B, F, _dev(C, torch.float64, (B, self.n), "C"),
+            _dev(omega, torch.float64, (F,), "omega"), _dev(T, torch.float64, (self.P,), "T"),
+            int(loss_mode), precision_code(precision), ptr(loss), ptr(gC), ptr(gR), ptr(gL), ptr(gw),
+            ptr(st), _stream()))
+        return loss, gC, gR, gL, gw, st
+
+    def resonant_capacitance(self, omega: torch.Tensor, coupled: bool = True) -> torch.Tensor:
+        """Eq. 13 per frequency and loop [F][n] (cosim_resonant_capacitance)."""
+        F = int(omega.shape[0])
+        out = torch.empty((F, self.n), dtype=torch.float64, device=self.device)
+        check(self._lib.cosim_resonant_capacitance(self._h, F, _dev(omega, torch.float64, (F,), "omega"),
+                                                   int(bool(coupled)), ctypes.c_void_p(out.data_ptr()),
+                                                   _stream()))
+        return out
+
     def optimize(self, C: torch.Tensor, omega: torch.Tensor, T: torch.Tensor, steps: int,
                  lr: float = 1e-13, betas=(0.9, 0.999), eps: float = 1e-8, precision=FP32,
                  loss_mode: int = LOSS_MAG, graph: bool = False):
@@ -311,6 +340,30 @@ def adam_step(C: torch.Tensor, grad: torch.Tensor, m: torch.Tensor, v: torch.Ten
                               _dev(m, torch.float64, shape, "m"), _dev(v, torch.float64, shape, "v"),
                               _dev(step, torch.int32, (1,), "step"), float(lr), float(betas[0]),
                               float(betas[1]), float(eps), _stream()))
+
+
+def tanh_projection(theta: torch.Tensor, cmin: float, cmax: float, derivative: bool = False):
+    """C = cmin + (cmax - cmin)(1 + tanh theta)/2 (and dC/dtheta) (cosim_tanh_projection)."""
+    lib = load_library()
+    th = theta.contiguous()
+    if th.dtype != torch.float64 or th.device.type != "cuda":
+        raise TypeError("theta must be a float64 GPU tensor")
+    C = torch.empty_like(th)
+    dC = torch.empty_like(th) if derivative else None
+    check(lib.cosim_tanh_projection(th.numel(), ctypes.c_void_p(th.data_ptr()), float(cmin),
+                                    float(cmax), ctypes.c_void_p(C.data_ptr()),
+                                    ctypes.c_void_p(dC.data_ptr()) if dC is not None else None,
+                                    _stream()))
+    return (C, dC) if derivative else C
+
+
+def clip_(x: torch.Tensor, lo: float, hi: float) -> torch.Tensor:
+    """Clamp x to [lo, hi] in place (cosim_clip)."""
+    lib = load_library()
+    if x.dtype != torch.float64 or x.device.type != "cuda" or not x.is_contiguous():
+        raise TypeError("x must be a contiguous float64 GPU tensor")
+    check(lib.cosim_clip(x.numel(), ctypes.c_void_p(x.data_ptr()), float(lo), float(hi), _stream()))
+    return x
 
 
 class CosimField(torch.autograd.Function):

@@ -459,6 +459,11 @@ int cosim_plan_destroy(cosim_plan_t p) {
     dfree(p->phi_d);
     dfree(p->R_d);
     plan_free_workspace(p);
+    // the parameter-gradient workspace has its own lifetime: a growing regular
+    // workspace must not free it while a call still holds its address
+    dfree(p->mu_ws);
+    dfree(p->gpar_ws);
+    p->par_cap = 0;
     big_blas_destroy(p->blas);
     p->blas = nullptr;
     delete p;
@@ -587,14 +592,17 @@ int cosim_field_backward(cosim_plan_t p, int B, int F, const double *C_d, const 
                                            (const double2 *)gBz_d, p->rpart, st));
     // gBz = 2 dL/d conj(B), so conj(w) = conj(gBz)/2
     HIP_TRY(launch_solve_adjoint(p->NP, p->n, (int)S, F, p->M_d, p->R_d, C_d, omega_d,
-                                 (const double2 *)I_d, p->rpart, 1, 0.5, p->gsys, status_d, false, st));
+                                 (const double2 *)I_d, p->rpart, 1, 0.5, p->gsys, nullptr, status_d,
+                                 false, st));
     HIP_TRY(launch_reduce(p->n, B, F, 0, p->gsys, nullptr, 0.0, gC_d, nullptr, st));
     return COSIM_OK;
 }
 
-int cosim_loss_and_grad(cosim_plan_t p, int B, int F, const double *C_d, const double *omega_d,
-                        const double *T_d, int loss_mode, int precision, double *loss_d,
-                        double *grad_d, int32_t *status_d, void *stream) {
+// The body of cosim_loss_and_grad; mu (optional, [S][n]) receives the adjoint
+// solutions for the gradients of the other circuit variables.
+static int loss_and_grad_impl(cosim_plan_t p, int B, int F, const double *C_d, const double *omega_d,
+                       const double *T_d, int loss_mode, int precision, double *loss_d,
+                       double *grad_d, int32_t *status_d, void *stream, double2 *mu) {
     int rc = check_batch(p, B, F);
     if (rc) return rc;
     if (B == 0 || F == 0) return COSIM_OK;  // empty batch: nothing to do
@@ -636,7 +644,7 @@ int cosim_loss_and_grad(cosim_plan_t p, int B, int F, const double *C_d, const d
             HIP_TRY(launch_lu_solve(p->NP, p->n, (int)S, F, p->fac.L, p->fac.piv_row, p->phi_d,
                                     C_d, omega_d, p->I_ws,
                                     prec == Prec::F64 ? kRhsPlanarF64 : kRhsPlanarF32, p->rpart,
-                                    nchunk, scale, p->gsys, status_d, st));
+                                    nchunk, scale, p->gsys, status_d, st, mu));
         if (ev) HIP_TRY(hipEventRecord(ev[3], st));
         HIP_TRY(launch_reduce(p->n, B, F, nchunk, grad ? p->gsys : nullptr, p->lpart, scale,
                               grad_d, loss_d, st));
@@ -676,11 +684,87 @@ int cosim_loss_and_grad(cosim_plan_t p, int B, int F, const double *C_d, const d
     if (ev) HIP_TRY(hipEventRecord(ev[2], st));
     if (grad)
         HIP_TRY(launch_replay_adjoint(p->NP, p->n, (int)S, F, p->fac, C_d, omega_d, p->I_ws,
-                                      p->rpart, nchunk, scale, p->gsys, status_d, st));
+                                      p->rpart, nchunk, scale, p->gsys, mu, status_d, st));
     if (ev) HIP_TRY(hipEventRecord(ev[3], st));
     HIP_TRY(launch_reduce(p->n, B, F, nchunk, grad ? p->gsys : nullptr, p->lpart, scale, grad_d,
                           loss_d, st));
     if (ev) HIP_TRY(hipEventRecord(ev[4], st));
+    return COSIM_OK;
+}
+
+int cosim_loss_and_grad(cosim_plan_t p, int B, int F, const double *C_d, const double *omega_d,
+                        const double *T_d, int loss_mode, int precision, double *loss_d,
+                        double *grad_d, int32_t *status_d, void *stream) {
+    return loss_and_grad_impl(p, B, F, C_d, omega_d, T_d, loss_mode, precision, loss_d, grad_d,
+                              status_d, stream, nullptr);
+}
+
+int cosim_loss_and_grad_params(cosim_plan_t p, int B, int F, const double *C_d,
+                               const double *omega_d, const double *T_d, int loss_mode,
+                               int precision, double *loss_d, double *gC_d, double *gR_d,
+                               double *gL_d, double *gomega_d, int32_t *status_d, void *stream) {
+    if (!p) return fail(COSIM_EINVAL, "null plan");
+    if (!gC_d) return fail(COSIM_EINVAL, "null capacitance gradient (the adjoint always runs)");
+    int rc = check_batch(p, B, F);
+    if (rc) return rc;
+    if (B == 0 || F == 0) return COSIM_OK;
+    if (!gR_d && !gL_d && !gomega_d)
+        return loss_and_grad_impl(p, B, F, C_d, omega_d, T_d, loss_mode, precision, loss_d, gC_d,
+                                  status_d, stream, nullptr);
+    if ((rc = check_device(p))) return rc;
+    const size_t S = (size_t)B * F, n = (size_t)p->n;
+    if (S > p->par_cap) {
+        dfree(p->mu_ws);
+        dfree(p->gpar_ws);
+        p->par_cap = 0;
+        if (hipMalloc((void **)&p->mu_ws, S * n * sizeof(double2)) != hipSuccess ||
+            hipMalloc((void **)&p->gpar_ws, (2 * S * n + S) * sizeof(double)) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(COSIM_ENOMEM, "parameter-gradient workspace for %zu systems failed", S);
+        }
+        p->par_cap = S;
+    }
+    if ((rc = loss_and_grad_impl(p, B, F, C_d, omega_d, T_d, loss_mode, precision, loss_d, gC_d,
+                                 status_d, stream, p->mu_ws)))
+        return rc;
+    // workspace: R terms [S][n], L terms [S][n], then S values of dL/dw when the
+    // caller does not want them
+    double *gw = gomega_d ? gomega_d : p->gpar_ws + 2 * S * n;
+    HIP_TRY(launch_param_grads(p->n, B, F, p->I_ws, p->mu_ws, C_d, omega_d, p->phi_d, p->M_d,
+                               p->gpar_ws, p->gpar_ws + S * n, gR_d, gL_d, gw,
+                               (hipStream_t)stream));
+    return COSIM_OK;
+}
+
+int cosim_resonant_capacitance(cosim_plan_t p, int F, const double *omega_d, int coupled,
+                               double *Cr_d, void *stream) {
+    if (!p) return fail(COSIM_EINVAL, "null plan");
+    if (F < 0) return fail(COSIM_EINVAL, "F = %d", F);
+    if (F == 0) return COSIM_OK;
+    if (!omega_d || !Cr_d) return fail(COSIM_EINVAL, "null device pointer");
+    int rc = check_device(p);
+    if (rc) return rc;
+    HIP_TRY(launch_resonant_c(p->n, F, p->M_d, omega_d, coupled ? 1 : 0, Cr_d, (hipStream_t)stream));
+    return COSIM_OK;
+}
+
+int cosim_tanh_projection(int64_t count, const double *theta_d, double cmin, double cmax,
+                          double *C_d, double *dC_d, void *stream) {
+    if (count < 0) return fail(COSIM_EINVAL, "count = %lld", (long long)count);
+    if (!(cmin < cmax) || !std::isfinite(cmin) || !std::isfinite(cmax))
+        return fail(COSIM_EINVAL, "range [%g, %g]", cmin, cmax);
+    if (count == 0) return COSIM_OK;
+    if (!theta_d || !C_d) return fail(COSIM_EINVAL, "null device pointer");
+    HIP_TRY(launch_tanh_project((size_t)count, theta_d, cmin, cmax, C_d, dC_d, (hipStream_t)stream));
+    return COSIM_OK;
+}
+
+int cosim_clip(int64_t count, double *x_d, double lo, double hi, void *stream) {
+    if (count < 0) return fail(COSIM_EINVAL, "count = %lld", (long long)count);
+    if (!(lo <= hi)) return fail(COSIM_EINVAL, "range [%g, %g]", lo, hi);
+    if (count == 0) return COSIM_OK;
+    if (!x_d) return fail(COSIM_EINVAL, "null device pointer");
+    HIP_TRY(launch_clip((size_t)count, x_d, lo, hi, (hipStream_t)stream));
     return COSIM_OK;
 }
 

@@ -86,10 +86,11 @@ hipError_t launch_replay_forward(int NP, int n, int S, int F, GJFactor fac,
                                  const double *omega_d, double2 *I_d, int32_t *status_d,
                                  hipStream_t st);
 // Adjoint solve from the record and the per-system gradient terms.
+// mu_d (optional, [S][n]): the adjoint solution itself.
 hipError_t launch_replay_adjoint(int NP, int n, int S, int F, GJFactor fac, const double *C_d,
                                  const double *omega_d, double2 *I_d, const double2 *rpart_d,
-                                 int nchunk, double rscale, double *gsys_d, int32_t *status_d,
-                                 hipStream_t st);
+                                 int nchunk, double rscale, double *gsys_d, double2 *mu_d,
+                                 int32_t *status_d, hipStream_t st);
 
 // Forward solve by pivoted Gauss-Jordan: Z I = -j w Phi for S = B*F systems
 // (s = b*F + f); records the elimination (kFmtGJ) in `fac` when fac.L is set.
@@ -106,7 +107,7 @@ hipError_t launch_solve_forward(int NP, int n, int S, int F, const double *M_d,
 hipError_t launch_solve_adjoint(int NP, int n, int S, int F, const double *M_d,
                                 const double *R_d, const double *C_d, const double *omega_d,
                                 const double2 *I_d, const double2 *rpart_d, int nchunk,
-                                double rscale, double *gsys_d, int32_t *status_d,
+                                double rscale, double *gsys_d, double2 *mu_d, int32_t *status_d,
                                 bool or_status, hipStream_t st);
 
 // Sum over frequencies (and chunks for the loss) per configuration.
@@ -165,7 +166,8 @@ hipError_t big_factor(const BigFactor &bf, int NP, int n, int S, int F,
 hipError_t launch_lu_solve(int NP, int n, int S, int F, const double2 *A_d, const int *piv_d,
                            const double *phi_d, const double *C_d, const double *omega_d,
                            double2 *I_d, int rhs_kind, const void *rhs_d, int nchunk,
-                           double rscale, double *gsys_d, int32_t *status_d, hipStream_t st);
+                           double rscale, double *gsys_d, int32_t *status_d, hipStream_t st,
+                           double2 *mu_d = nullptr);
 struct BigArgs {
     int n, NP, P, P_pad, S, nchunk, rows;  // rows: P-chunk of the adjoint GEMMs
     const void *G;                         // [P_pad][NP] FP64 or FP32 (F64 / F32)
@@ -195,6 +197,20 @@ hipError_t launch_field(Prec prec, int NP, int P, int S, int n, const double *G6
 hipError_t launch_field_backward_contract(int NP, int P, int S, int n, const double *G64,
                                           const double2 *gBz_d, double2 *rpart_d,
                                           hipStream_t st);
+
+// ---- the other circuit variables and the helpers around C (params.hip)
+// Per system from I and mu ([S][n]): the R and L terms to gRs, gLs ([S][n])
+// and dL/dw to gw ([B][F]); then, if gR / gL is set, their sums over
+// frequencies ([B][n]).
+hipError_t launch_param_grads(int n, int B, int F, const double2 *I, const double2 *mu,
+                              const double *C, const double *omega, const double *phi,
+                              const double *M, double *gRs, double *gLs, double *gR, double *gL,
+                              double *gw, hipStream_t st);
+hipError_t launch_resonant_c(int n, int F, const double *M, const double *omega, int coupled,
+                             double *Cr, hipStream_t st);
+hipError_t launch_tanh_project(size_t count, const double *theta, double cmin, double cmax,
+                               double *C, double *dC, hipStream_t st);
+hipError_t launch_clip(size_t count, double *x, double lo, double hi, hipStream_t st);
 
 // ---- S-parameter pipeline (sparam.hip)
 constexpr int kSpMaxPorts = 64;
@@ -273,6 +289,9 @@ struct cosim_plan {
     double2 *bWt = nullptr;   // blocked LDL^T panel copy ([S][64][NP], see BigFactor)
     double2 *bTinv = nullptr; // blocked LDL^T L11^-T ([S][64][64])
     double *bZmax = nullptr;  // [S] largest diagonal |Z_kk| (blocked LDL^T)
+    double2 *mu_ws = nullptr; // [S][n] adjoint solutions (gradients of R, L, w)
+    double *gpar_ws = nullptr; // [2][S][n] per-system R and L terms
+    size_t par_cap = 0;       // systems mu_ws / gpar_ws hold
     int prec_mask = 7;    // precisions whose copies of G were assembled (bit 1 << precision)
     bool ldl_ok = false;  // every R_k > 0: the LDL^T fast path applies
     int variant[3] = {0, 0, 0};  // fused-kernel variant per precision

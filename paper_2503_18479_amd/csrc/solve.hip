@@ -411,6 +411,7 @@ __global__ __launch_bounds__(GJShape<NP>::BLOCK) void k_gj(
                 // 2 Re(mu I / (j w C^2)) = 2 Im(mu I) / (w C^2)
                 const double g = 2.0 * (x.x * Ik.y + x.y * Ik.x) / (w * ck * ck);
                 gsys[(size_t)s * n + k] = g;
+                if (Iout) Iout[(size_t)s * n + k] = x;  // the adjoint solution mu, on request
                 if (!bad && !isfinite(g)) oflag |= COSIM_SYS_NONFINITE;
             }
         }
@@ -693,6 +694,7 @@ __global__ __launch_bounds__(256) void k_replay(int n, int S, int F, GJFactor fa
                                                 double2 *__restrict__ I,
                                                 const double2 *__restrict__ rpart, int nchunk,
                                                 double rscale, double *__restrict__ gsys,
+                                                double2 *__restrict__ mu,
                                                 int32_t *__restrict__ status) {
     __shared__ double2 sTr[4][64];  // per wave: an 8x8 block of L, transposed
     const int lane = threadIdx.x & 63;
@@ -847,6 +849,7 @@ __global__ __launch_bounds__(256) void k_replay(int n, int S, int F, GJFactor fa
             // 2 Re(mu I / (j w C^2)) = 2 Im(mu I) / (w C^2)
             const double g = 2.0 * (x.x * Ik.y + x.y * Ik.x) / (w * ck * ck);
             gsys[(size_t)s * n + lane] = g;
+            if (mu) mu[(size_t)s * n + lane] = x;
             nonfinite = !bad && !isfinite(g);
         }
     }
@@ -939,16 +942,16 @@ template <bool ADJ>
 hipError_t launch_replay_t(int NP, int n, int S, int F, GJFactor fac, const double *phi_d,
                            const double *C_d, const double *omega_d, double2 *I_d,
                            const double2 *rpart_d, int nchunk, double rscale, double *gsys_d,
-                           int32_t *status_d, hipStream_t st) {
+                           double2 *mu_d, int32_t *status_d, hipStream_t st) {
     const dim3 grid((S + 3) / 4);
     switch (NP) {
         case 32:
             hipLaunchKernelGGL((k_replay<32, ADJ>), grid, dim3(256), 0, st, n, S, F, fac, phi_d,
-                               C_d, omega_d, I_d, rpart_d, nchunk, rscale, gsys_d, status_d);
+                               C_d, omega_d, I_d, rpart_d, nchunk, rscale, gsys_d, mu_d, status_d);
             break;
         case 64:
             hipLaunchKernelGGL((k_replay<64, ADJ>), grid, dim3(256), 0, st, n, S, F, fac, phi_d,
-                               C_d, omega_d, I_d, rpart_d, nchunk, rscale, gsys_d, status_d);
+                               C_d, omega_d, I_d, rpart_d, nchunk, rscale, gsys_d, mu_d, status_d);
             break;
         default:
             return hipErrorInvalidValue;
@@ -960,24 +963,24 @@ hipError_t launch_replay_forward(int NP, int n, int S, int F, GJFactor fac,
                                  const double *omega_d, double2 *I_d, int32_t *status_d,
                                  hipStream_t st) {
     return launch_replay_t<false>(NP, n, S, F, fac, nullptr, nullptr, omega_d, I_d, nullptr, 0,
-                                  0.0, nullptr, status_d, st);
+                                  0.0, nullptr, nullptr, status_d, st);
 }
 
 hipError_t launch_replay_adjoint(int NP, int n, int S, int F, GJFactor fac, const double *C_d,
                                  const double *omega_d, double2 *I_d, const double2 *rpart_d,
-                                 int nchunk, double rscale, double *gsys_d, int32_t *status_d,
-                                 hipStream_t st) {
+                                 int nchunk, double rscale, double *gsys_d, double2 *mu_d,
+                                 int32_t *status_d, hipStream_t st) {
     return launch_replay_t<true>(NP, n, S, F, fac, nullptr, C_d, omega_d, I_d, rpart_d, nchunk,
-                                 rscale, gsys_d, status_d, st);
+                                 rscale, gsys_d, mu_d, status_d, st);
 }
 
 hipError_t launch_solve_adjoint(int NP, int n, int S, int F, const double *M_d,
                                 const double *R_d, const double *C_d, const double *omega_d,
                                 const double2 *I_d, const double2 *rpart_d, int nchunk,
-                                double rscale, double *gsys_d, int32_t *status_d,
+                                double rscale, double *gsys_d, double2 *mu_d, int32_t *status_d,
                                 bool or_status, hipStream_t st) {
     return launch_gj<true>(NP, n, S, F, M_d, R_d, nullptr, C_d, omega_d, I_d, rpart_d, nchunk,
-                           rscale, nullptr, gsys_d, status_d, or_status, GJFactor{}, false, st);
+                           rscale, mu_d, gsys_d, status_d, or_status, GJFactor{}, false, st);
 }
 
 hipError_t launch_reduce(int n, int B, int F, int nchunk, const double *gsys_d,

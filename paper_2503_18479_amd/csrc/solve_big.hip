@@ -509,6 +509,7 @@ __global__ __launch_bounds__(kTB) void k_lu_solve(int n, int NP, int S, int F,
                                                   double2 *__restrict__ I, const void *rhs,
                                                   int nchunk, double rscale,
                                                   double *__restrict__ gsys,
+                                                  double2 *__restrict__ mu,
                                                   int32_t *__restrict__ status) {
     __shared__ double2 sx[kMaxLoopsBig];
     __shared__ double2 st[16];
@@ -623,6 +624,7 @@ __global__ __launch_bounds__(kTB) void k_lu_solve(int n, int NP, int S, int F,
             const double ck = C[(size_t)b * n + k];
             const double g = 2.0 * (x.x * Ik.y + x.y * Ik.x) / (w * ck * ck);
             gsys[(size_t)s * n + k] = g;
+            if (mu) mu[(size_t)s * n + k] = x;
             if (!bad && !isfinite(g)) oflag = COSIM_SYS_NONFINITE;
         }
     }
@@ -676,27 +678,28 @@ hipError_t big_factor(const BigFactor &bf, int NP, int n, int S, int F,
 hipError_t launch_lu_solve(int NP, int n, int S, int F, const double2 *A_d, const int *piv_d,
                            const double *phi_d, const double *C_d, const double *omega_d,
                            double2 *I_d, int rhs_kind, const void *rhs_d, int nchunk,
-                           double rscale, double *gsys_d, int32_t *status_d, hipStream_t st) {
+                           double rscale, double *gsys_d, int32_t *status_d, hipStream_t st,
+                           double2 *mu_d) {
     if (NP % 64 != 0 || NP > kMaxLoopsBig) return hipErrorInvalidValue;
     const dim3 grid(S), blk(kTB);
     switch (rhs_kind) {
         case kRhsExcitation:
             hipLaunchKernelGGL(k_lu_solve<kRhsExcitation>, grid, blk, 0, st, n, NP, S, F, A_d, piv_d,
-                               phi_d, C_d, omega_d, I_d, rhs_d, nchunk, rscale, gsys_d, status_d);
+                               phi_d, C_d, omega_d, I_d, rhs_d, nchunk, rscale, gsys_d, mu_d, status_d);
             break;
         case kRhsPairs:
             hipLaunchKernelGGL(k_lu_solve<kRhsPairs>, grid, blk, 0, st, n, NP, S, F, A_d, piv_d,
-                               phi_d, C_d, omega_d, I_d, rhs_d, nchunk, rscale, gsys_d, status_d);
+                               phi_d, C_d, omega_d, I_d, rhs_d, nchunk, rscale, gsys_d, mu_d, status_d);
             break;
         case kRhsPlanarF32:
             hipLaunchKernelGGL(k_lu_solve<kRhsPlanarF32>, grid, blk, 0, st, n, NP, S, F, A_d,
                                piv_d, phi_d, C_d, omega_d, I_d, rhs_d, nchunk, rscale, gsys_d,
-                               status_d);
+                               mu_d, status_d);
             break;
         case kRhsPlanarF64:
             hipLaunchKernelGGL(k_lu_solve<kRhsPlanarF64>, grid, blk, 0, st, n, NP, S, F, A_d,
                                piv_d, phi_d, C_d, omega_d, I_d, rhs_d, nchunk, rscale, gsys_d,
-                               status_d);
+                               mu_d, status_d);
             break;
         default:
             return hipErrorInvalidValue;

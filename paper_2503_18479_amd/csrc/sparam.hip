@@ -9,8 +9,8 @@
 // Kernels:
 //   k_sp_prep   per frequency: K = I - S_C11,const S0 and r0 = S_C12,const exc
 //               (the constant parts; the variable entries are applied per system);
-//   k_sp_solve  one wave per system, the n0 x n0 matrix in LDS (rows padded to
-//               n0 + 1 entries): A = K minus the variable rows of S_C11 S0, the
+//   k_sp_solve  one workgroup of four waves per system, the n0 x n0 matrix in
+//               LDS (rows padded to a multiple of 16 plus 4 entries): A = K minus the variable rows of S_C11 S0, the
 //               right-hand side r0 plus the variable entries of S_C12 exc, LU with
 //               partial pivoting (largest |re| + |im|, ties to the lower row)
 //               applied to the right-hand side as it goes, back substitution.
@@ -48,21 +48,48 @@ __device__ inline double2 zinv(double2 a) {
     return make_double2(a.x * d, -a.y * d);
 }
 __device__ inline double2 zconj(double2 a) { return make_double2(a.x, -a.y); }
+
+// LDS row stride (complex entries) of the per-system matrix: a multiple of 16
+// plus 4, so that the 16 lanes of one 16-byte access pass (4 rows x 4
+// consecutive columns in the trailing update) fall on distinct banks
+__host__ __device__ inline int sp_ld(int n0) { return (n0 + 15) / 16 * 16 + 4; }
+
+template <int CTRL>
+__device__ inline int dpp_i(int x) {
+    return __builtin_amdgcn_update_dpp(x, x, CTRL, 0xF, 0xF, false);
+}
+// (magnitude, row) arg-max step with a DPP partner; ties to the lower row
+template <int CTRL>
+__device__ inline void amax_step(float &m, int &idx) {
+    const float m2 = __int_as_float(dpp_i<CTRL>(__float_as_int(m)));
+    const int i2 = dpp_i<CTRL>(idx);
+    const bool take = (m2 > m) || (m2 == m && i2 < idx);
+    m = take ? m2 : m;
+    idx = take ? i2 : idx;
+}
+// arg-max over the wave: DPP inside each row of 16 lanes, shuffles across rows
+__device__ inline int wave_amax(float m, int idx) {
+    amax_step<0xB1>(m, idx);   // quad_perm [1,0,3,2]
+    amax_step<0x4E>(m, idx);   // quad_perm [2,3,0,1]
+    amax_step<0x141>(m, idx);  // row_half_mirror
+    amax_step<0x140>(m, idx);  // row_mirror
+#pragma unroll
+    for (int off = 16; off <= 32; off <<= 1) {
+        const float om = __shfl_xor(m, off);
+        const int oi = __shfl_xor(idx, off);
+        if (om > m || (om == m && oi < idx)) {
+            m = om;
+            idx = oi;
+        }
+    }
+    return __builtin_amdgcn_readfirstlane(idx);
+}
 __device__ inline double rl(double v, int src) {
     const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
     const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
     return __hiloint2double(hi, lo);
 }
 __device__ inline double2 rl2(double2 v, int src) { return make_double2(rl(v.x, src), rl(v.y, src)); }
-__device__ inline double wsum(double v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
-    return v;
-}
-__device__ inline void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-}
 
 // K[f] = I - S11c[f] S0[f], r0[f] = S12c[f] exc; grid (n0, F), 64 threads.
 __global__ __launch_bounds__(64) void k_sp_prep(int n0, int n1, int F, const double2 *__restrict__ S0,
@@ -95,53 +122,74 @@ __global__ __launch_bounds__(64) void k_sp_prep(int n0, int n1, int F, const dou
     }
 }
 
-// One wave per system s = b F + f.  ADJ = false: solves A x = S_C12 exc, writes
-// X[s][n0] (FP64) and the GEMM operand Xg[f][b][n0] (PREC 0: complex128,
-// 1: complex64).  ADJ = true: right-hand side r = rscale conj(sum over chunks of
-// Rp[c][f][b][:]) (the chunks hold conj(fields^H w)), solves A^H lam = r and
-// writes the gradient of every variable entry to grad[s][nvar].
+// One workgroup of four waves per system s = b F + f; the matrix in LDS (rows
+// padded to sp_ld(n0) entries) and the right-hand side after it.  Elimination
+// step k: every wave finds the pivot row itself (shuffles over column k), the
+// row exchange runs over columns, the trailing update over (row, column
+// quarter) with four threads per row, two workgroup barriers per step; wave 0
+// then runs the back substitution and writes the outputs.
+// ADJ = false: solves A x = S_C12 exc, writes X[s][n0] (FP64) and the GEMM
+// operand Xg[f][b][n0] (PREC 0: complex128, 1: complex64).  ADJ = true:
+// right-hand side r = rscale conj(sum over chunks of Rp[c][f][b][:]) (the chunks
+// hold conj(fields^H w)), solves A^H lam = r and writes the gradient of every
+// variable entry to grad[s][nvar].
 template <bool ADJ, int PREC>
-__global__ __launch_bounds__(64) void k_sp_solve(SpDev d, int B, const double2 *__restrict__ values,
-                                                 double2 *__restrict__ X, void *Xg,
-                                                 const void *Rp, int nchunk, double rscale,
-                                                 double2 *__restrict__ grad,
-                                                 int32_t *__restrict__ status) {
+__global__ __launch_bounds__(256) void k_sp_solve(SpDev d, int B, const double2 *__restrict__ values,
+                                                  double2 *__restrict__ X, void *Xg,
+                                                  const void *Rp, int nchunk, double rscale,
+                                                  double2 *__restrict__ grad,
+                                                  int32_t *__restrict__ status) {
     extern __shared__ double2 sa[];
-    const int n0 = d.n0, ld = n0 + 1, F = d.F, nvar = d.nvar;
+    const int n0 = d.n0, ld = sp_ld(n0), F = d.F, nvar = d.nvar;
+    double2 *sx = sa + (size_t)n0 * ld;  // right-hand side, then solution
     const int s = blockIdx.x;
     const int b = s / F, f = s - b * F;
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63;
     const double2 *K = d.K + (size_t)f * n0 * n0;
     const double2 *S0f = d.S0 + (size_t)f * n0 * n0;
     const double2 *v = values + (size_t)s * nvar;
+    __shared__ int s_ix[256], s_iy[256];
+    __shared__ double2 s_v[256];
     // A = K - sum over variable S_C11 entries (r, c) of v e_r S0[c][:]
-    for (int i = 0; i < n0; ++i)
-        for (int j = lane; j < n0; j += 64) sa[i * ld + j] = K[(size_t)i * n0 + j];
-    for (int e = 0; e < nvar; ++e) {
-        const int r = d.ix[e], c = d.iy[e];
-        if (r < n0 && c < n0) {
-            const double2 ve = v[e];
-            for (int j = lane; j < n0; j += 64) sa[r * ld + j] = zfms(sa[r * ld + j], ve, S0f[(size_t)c * n0 + j]);
-        }
+#pragma unroll 4
+    for (int e = tid; e < n0 * n0; e += 256) {
+        const int i = e / n0, j = e - i * n0;
+        sa[i * ld + j] = K[e];
     }
-    double2 x = make_double2(0.0, 0.0);  // lane i: right-hand side, then solution
-    if (!ADJ) {
-        if (lane < n0) {
-            x = d.r0[(size_t)f * n0 + lane];
-            for (int e = 0; e < nvar; ++e) {
-                const int r = d.ix[e], c = d.iy[e];
-                if (r == lane && c >= n0) {
-                    const double2 t = zmul(v[e], d.exc[c - n0]);
+    double2 x = make_double2(0.0, 0.0);  // thread i < n0: right-hand side entry i
+    if (!ADJ && tid < n0) x = d.r0[(size_t)f * n0 + tid];
+    // the variable entries, 256 at a time through LDS; thread j owns column j,
+    // so repeated rows keep their order
+    for (int e0 = 0; e0 < nvar; e0 += 256) {
+        const int ne = min(256, nvar - e0);
+        __syncthreads();
+        if (tid < ne) {
+            s_ix[tid] = d.ix[e0 + tid];
+            s_iy[tid] = d.iy[e0 + tid];
+            s_v[tid] = v[e0 + tid];
+        }
+        __syncthreads();
+        if (tid < n0) {
+            const int j = tid;
+#pragma unroll 4
+            for (int e = 0; e < ne; ++e) {
+                const int r = s_ix[e], c = s_iy[e];
+                if (r < n0 && c < n0) sa[r * ld + j] = zfms(sa[r * ld + j], s_v[e], S0f[(size_t)c * n0 + j]);
+                if (!ADJ && r == j && c >= n0) {
+                    const double2 t = zmul(s_v[e], d.exc[c - n0]);
                     x.x += t.x;
                     x.y += t.y;
                 }
             }
         }
-    } else {
-        if (lane < n0) {
+    }
+    if (tid < n0) {
+        const int i = tid;
+        if (ADJ) {
             double sr = 0.0, si = 0.0;
+#pragma unroll 8
             for (int c = 0; c < nchunk; ++c) {
-                const size_t o = (((size_t)c * F + f) * B + b) * n0 + lane;
+                const size_t o = (((size_t)c * F + f) * B + b) * n0 + i;
                 if (PREC == 0) {
                     const double2 t = ((const double2 *)Rp)[o];
                     sr += t.x;
@@ -154,11 +202,14 @@ __global__ __launch_bounds__(64) void k_sp_solve(SpDev d, int B, const double2 *
             }
             x = make_double2(rscale * sr, -rscale * si);
         }
-        wave_sync();
-        // A -> A^H in place: lane i takes row i right of the diagonal and column
-        // i below it (disjoint from every other lane's entries)
-        if (lane < n0) {
-            const int i = lane;
+        sx[i] = x;
+    }
+    __syncthreads();
+    if (ADJ) {
+        // A -> A^H in place: thread i takes row i right of the diagonal and
+        // column i below it (disjoint from every other thread's entries)
+        if (tid < n0) {
+            const int i = tid;
             sa[i * ld + i] = zconj(sa[i * ld + i]);
             for (int j = i + 1; j < n0; ++j) {
                 const double2 t = sa[i * ld + j];
@@ -166,51 +217,59 @@ __global__ __launch_bounds__(64) void k_sp_solve(SpDev d, int B, const double2 *
                 sa[j * ld + i] = zconj(t);
             }
         }
+        __syncthreads();
     }
-    wave_sync();
     // LU with partial pivoting, right-hand side eliminated alongside
     int flag = 0;
+    const int ur = tid >> 2, uq = tid & 3;  // update: row k + 1 + ur, columns = uq mod 4
     for (int k = 0; k < n0; ++k) {
-        double mg = -1.0;
+        // pivot: largest |re| + |im| in column k (compared in FP32; a NaN wins)
+        float mg = -1.0f;
         if (lane >= k && lane < n0) {
             const double2 a = sa[lane * ld + k];
-            mg = fabs(a.x) + fabs(a.y);
-            if (!(mg == mg)) mg = __builtin_inf();
+            mg = (float)(fabs(a.x) + fabs(a.y));
+            if (!(mg == mg)) mg = __builtin_inff();
         }
-        int idx = lane;
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) {
-            const double om = __shfl_xor(mg, off);
-            const int oi = __shfl_xor(idx, off);
-            if (om > mg || (om == mg && oi < idx)) {
-                mg = om;
-                idx = oi;
-            }
-        }
-        const int p = __builtin_amdgcn_readfirstlane(idx);
+        const int p = wave_amax(mg, lane);
+        __syncthreads();  // every wave has read column k
         if (p != k) {
-            for (int j = lane; j < n0; j += 64) {
+            for (int j = tid; j < n0; j += 256) {
                 const double2 t = sa[k * ld + j];
                 sa[k * ld + j] = sa[p * ld + j];
                 sa[p * ld + j] = t;
             }
-            const double2 xk = rl2(x, k), xp = rl2(x, p);
-            if (lane == k) x = xp;
-            if (lane == p) x = xk;
+            if (tid == 0) {
+                const double2 t = sx[k];
+                sx[k] = sx[p];
+                sx[p] = t;
+            }
         }
-        wave_sync();
+        __syncthreads();
         const double2 dk = sa[k * ld + k];
         if (!(dk.x != 0.0 || dk.y != 0.0)) flag |= COSIM_SYS_SINGULAR;
-        const double2 inv = zinv(dk);
-        const double2 xk = rl2(x, k);
-        if (lane > k && lane < n0) {
-            const int i = lane;
-            const double2 l = zmul(sa[i * ld + k], inv);
-            x = zfms(x, l, xk);
-            for (int j = k + 1; j < n0; ++j) sa[i * ld + j] = zfms(sa[i * ld + j], l, sa[k * ld + j]);
+        const int i = k + 1 + ur;
+        if (i < n0) {
+            const double2 l = zmul(sa[i * ld + k], zinv(dk));
+            if (uq == 0) sx[i] = zfms(sx[i], l, sx[k]);
+            // this thread's columns j = k + 1 + uq + 4t, four at a time with every
+            // load issued before the stores (the LDS round trips overlap)
+            int j = k + 1 + uq;
+            for (; j + 12 < n0; j += 16) {
+                double2 a[4], u[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    a[t] = sa[i * ld + j + 4 * t];
+                    u[t] = sa[k * ld + j + 4 * t];
+                }
+#pragma unroll
+                for (int t = 0; t < 4; ++t) sa[i * ld + j + 4 * t] = zfms(a[t], l, u[t]);
+            }
+            for (; j < n0; j += 4) sa[i * ld + j] = zfms(sa[i * ld + j], l, sa[k * ld + j]);
         }
-        wave_sync();
+        __syncthreads();
     }
+    if (tid >= 64) return;  // wave 0 finishes alone (no barrier below)
+    x = lane < n0 ? sx[lane] : make_double2(0.0, 0.0);
     for (int k = n0 - 1; k >= 0; --k) {
         const double2 xk = zmul(rl2(x, k), zinv(sa[k * ld + k]));
         if (lane == k) x = xk;
@@ -232,23 +291,34 @@ __global__ __launch_bounds__(64) void k_sp_solve(SpDev d, int B, const double2 *
     // gradient: 2 lam_r conj(exc_j) for S_C12 entries (r, n0 + j), 2 lam_r
     // conj((S0 x)_c) for S_C11 entries (r, c), 0 for S_C21 / S_C22 entries
     if (lane == 0 && flag) status[s] |= flag;
+    // y = S0 x once (lane c: row c, x broadcast from the forward solution)
     const double2 xs = lane < n0 ? X[(size_t)s * n0 + lane] : make_double2(0.0, 0.0);
-    for (int e = 0; e < nvar; ++e) {
-        const int r = d.ix[e], c = d.iy[e];
-        double2 g = make_double2(0.0, 0.0);
-        if (r < n0) {
-            const double2 lam = rl2(x, r);
-            double2 y;
-            if (c >= n0) {
-                y = d.exc[c - n0];
-            } else {
-                const double2 t = lane < n0 ? zmul(S0f[(size_t)c * n0 + lane], xs) : make_double2(0.0, 0.0);
-                y = make_double2(wsum(t.x), wsum(t.y));
-            }
-            const double2 gv = zmulc(lam, y);
-            g = make_double2(2.0 * gv.x, 2.0 * gv.y);
+    double2 y = make_double2(0.0, 0.0);
+    if (lane < n0) {
+        const double2 *row = S0f + (size_t)lane * n0;
+#pragma unroll 8
+        for (int k = 0; k < n0; ++k) {
+            const double2 a = row[k], xk = rl2(xs, k);
+            y.x = fma(a.x, xk.x, fma(-a.y, xk.y, y.x));
+            y.y = fma(a.x, xk.y, fma(a.y, xk.x, y.y));
         }
-        if (lane == 0) grad[(size_t)s * nvar + e] = g;
+    }
+    // lane e % 64 forms entry e
+    for (int e0 = 0; e0 < nvar; e0 += 64) {
+        const int e = e0 + lane;
+        const int r = e < nvar ? d.ix[e] : n0, c = e < nvar ? d.iy[e] : 0;
+        // gathers from other lanes: every lane takes part in the shuffles
+        const int rs = r < n0 ? r : 0, cs = c < n0 ? c : 0;
+        const double2 lam = make_double2(__shfl(x.x, rs), __shfl(x.y, rs));
+        const double2 yv = make_double2(__shfl(y.x, cs), __shfl(y.y, cs));
+        if (e < nvar) {
+            double2 g = make_double2(0.0, 0.0);
+            if (r < n0) {
+                const double2 gv = zmulc(lam, c >= n0 ? d.exc[c - n0] : yv);
+                g = make_double2(2.0 * gv.x, 2.0 * gv.y);
+            }
+            grad[(size_t)s * nvar + e] = g;
+        }
     }
 }
 
@@ -357,14 +427,14 @@ hipError_t cgemm(rocblas_handle h, int prec, rocblas_operation ta, int m, int n,
         (rocblas_float_complex *)C, ldc, (rocblas_stride)sC, batch));
 }
 
-size_t lds_bytes(int n0) { return (size_t)n0 * (n0 + 1) * sizeof(double2); }
+size_t lds_bytes(int n0) { return ((size_t)n0 * sp_ld(n0) + 64) * sizeof(double2); }
 
 template <bool ADJ, int PREC>
 hipError_t launch_solve(const SpDev &d, int B, const double2 *values, double2 *X, void *Xg,
                         const void *Rp, int nchunk, double rscale, double2 *grad, int32_t *status,
                         hipStream_t st) {
     const int S = B * d.F;
-    hipLaunchKernelGGL((k_sp_solve<ADJ, PREC>), dim3(S), dim3(64), lds_bytes(d.n0), st, d, B, values,
+    hipLaunchKernelGGL((k_sp_solve<ADJ, PREC>), dim3(S), dim3(256), lds_bytes(d.n0), st, d, B, values,
                        X, Xg, Rp, nchunk, rscale, grad, status);
     return hipGetLastError();
 }

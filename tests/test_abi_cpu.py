@@ -208,3 +208,17 @@ def test_sparam_argument_errors(lib):
     assert lib.cosim_sp_rc(0, 1, 2, None, None, None, 50.0, None, 2, None) == 0  # empty batch
     assert lib.cosim_sp_rc_backward(1, 1, 2, fake, fake, fake, 50.0, fake, 2, None, None) == EINVAL
     assert lib.cosim_sp_rc_backward(0, 1, 2, None, None, None, 50.0, None, 2, None, None) == 0
+
+
+def test_parameter_calls_argument_errors(lib):
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.cosim_loss_and_grad_params(None, 1, 1, fake, fake, fake, 0, 0, fake, fake, None, None,
+                                          None, fake, None) == EINVAL
+    assert lib.cosim_resonant_capacitance(None, 1, fake, 1, fake, None) == EINVAL
+    assert lib.cosim_tanh_projection(-1, fake, 0.0, 1.0, fake, None, None) == EINVAL
+    assert lib.cosim_tanh_projection(4, fake, 1.0, 1.0, fake, None, None) == EINVAL   # empty range
+    assert lib.cosim_tanh_projection(4, None, 0.0, 1.0, fake, None, None) == EINVAL
+    assert lib.cosim_tanh_projection(0, None, 0.0, 1.0, None, None, None) == 0
+    assert lib.cosim_clip(4, fake, 2.0, 1.0, None) == EINVAL
+    assert lib.cosim_clip(-1, fake, 0.0, 1.0, None) == EINVAL
+    assert lib.cosim_clip(0, None, 0.0, 1.0, None) == 0

@@ -705,3 +705,113 @@ def test_assembly_mask_refuses_missing_copies(dev):
                  lambda: plan.field(plan.solve(C, om)[0], 2)):
         with pytest.raises(CosimError):
             call()
+
+
+# ------------------------------------------- the other circuit variables (R, L, w), Eq. 13, projection
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("name", ["n25", "n64", "circle", "n81"])
+def test_parameter_gradients_match_oracle(dev, name, prec):
+    """dL/dR, dL/dL (series inductance per loop) and dL/dw from
+    cosim_loss_and_grad_params against the oracle's adjoint form (itself pinned
+    to forward sensitivity and differences); dL/dC and the loss as in
+    cosim_loss_and_grad."""
+    c = _case(name)
+    _say(f"[params] {name} prec={prec}")
+    loss, gC, gR, gL, gw, st = c.plan.loss_and_grad_params(c.C, c.om, c.T, precision=prec)
+    torch.cuda.synchronize()
+    assert int(st.abs().sum()) == 0
+    g = c.wl.geom
+    rR, rL, rw = O.grad_params_adjoint(c.G, c.M, g.R, c.Phi, c.wl.C, c.wl.omega, c.wl.target)
+    tol = TOL[prec]
+    assert np.max(_nrel(gC.cpu().numpy(), c.oracle_grad(), axis=1)) < tol
+    assert np.max(_nrel(gR.cpu().numpy(), rR, axis=1)) < tol
+    assert np.max(_nrel(gL.cpu().numpy(), rL, axis=1)) < tol
+    assert np.max(_nrel(gw.cpu().numpy(), rw, axis=1)) < tol
+    l2, g2, _ = c.plan.loss_and_grad(c.C, c.om, c.T, precision=prec)
+    torch.cuda.synchronize()
+    assert torch.equal(l2, loss) and torch.equal(g2, gC)
+
+
+def test_parameter_gradients_without_resistance(dev):
+    """R = 0: the pivoted path (Gauss-Jordan record) supplies the adjoint."""
+    wl, G, M, Phi, plan = _custom_case(dev, 0.0)
+    C = torch.tensor(wl.C, device=dev); om = torch.tensor(wl.omega, device=dev)
+    T = torch.tensor(wl.target, device=dev)
+    loss, gC, gR, gL, gw, st = plan.loss_and_grad_params(C, om, T, precision=0)
+    torch.cuda.synchronize()
+    assert int(st.abs().sum()) == 0
+    rR, rL, rw = O.grad_params_adjoint(G, M, wl.geom.R, Phi, wl.C, wl.omega, wl.target)
+    # without resistance Z = jX (X real symmetric): I is real, mu imaginary, so
+    # dL/dR = -2 Re(mu_k I_k) vanishes; compare on the scale |dL/dL| / w
+    scale = np.abs(rL).max() / wl.omega.max()
+    assert np.abs(rR).max() < 1e-12 * scale
+    assert np.abs(gR.cpu().numpy() - rR).max() < 1e-9 * scale
+    assert np.max(_nrel(gL.cpu().numpy(), rL, axis=1)) < 1e-9
+    assert np.max(_nrel(gw.cpu().numpy(), rw, axis=1)) < 1e-9
+
+
+@pytest.mark.parametrize("name", ["n25", "circle", "n81"])
+def test_resonant_capacitance_matches_oracle(dev, name):
+    c = _case(name)
+    for coupled in (False, True):
+        Cr = c.plan.resonant_capacitance(c.om, coupled)
+        torch.cuda.synchronize()
+        ref = np.stack([O.resonant_capacitance(c.M, w, coupled) for w in c.wl.omega])
+        assert _nrel(Cr.cpu().numpy(), ref) < 1e-12
+
+
+def test_tanh_projection_and_clip(dev):
+    from paper_2503_18479_amd import tanh_projection, clip_
+    th = np.linspace(-7, 7, 1001)
+    C, dC = tanh_projection(torch.tensor(th, device=dev), 10e-12, 300e-12, derivative=True)
+    rC, rdC = O.tanh_projection(th, 10e-12, 300e-12)
+    assert _nrel(C.cpu().numpy(), rC) < 1e-15 and _nrel(dC.cpu().numpy(), rdC) < 1e-14
+    x = torch.tensor(np.linspace(-1.0, 2.0, 301), device=dev)
+    clip_(x, 0.0, 1.0)
+    torch.cuda.synchronize()
+    assert np.array_equal(x.cpu().numpy(), np.clip(np.linspace(-1.0, 2.0, 301), 0.0, 1.0))
+
+
+def test_multi_start_sweep_is_the_batch_of_single_starts(dev):
+    """A batched multi-start sweep (many initial C in one batch, Sec. V-A) runs
+    every start independently: each trajectory equals the one optimised alone,
+    and Eq. 13's capacitance is a start like any other."""
+    c = _case("circle")
+    w = c.wl.omega
+    Cr = c.plan.resonant_capacitance(c.om, coupled=False)[0]
+    starts = torch.linspace(2e-12, 30e-12, 7, dtype=torch.float64, device=dev)[:, None]
+    starts = torch.cat([starts, Cr[None, :]], dim=0).contiguous()
+    T = c.T
+    Cb = starts.clone()
+    hb, _ = c.plan.optimize(Cb, c.om, T, steps=20, precision=0, lr=2e-13)
+    for i in (0, 3, 7):
+        Ci = starts[i:i + 1].clone()
+        hi, _ = c.plan.optimize(Ci, c.om, T, steps=20, precision=0, lr=2e-13)
+        torch.cuda.synchronize()
+        assert _nrel(Ci.cpu().numpy(), Cb[i:i + 1].cpu().numpy()) < 1e-12
+        assert _nrel(hi[:, 0].cpu().numpy(), hb[:, i].cpu().numpy()) < 1e-12
+
+
+def test_parameter_gradients_on_a_fresh_plan_with_growing_batches(dev):
+    """Regression: on a fresh plan the first cosim_loss_and_grad_params call
+    grows the regular workspace after its own adjoint-solution workspace was
+    allocated; the latter must survive that growth.  Two calls with growing
+    batches, results against the oracle."""
+    from paper_2503_18479_amd import Geometry, Plan
+    wl = W.small_array(3, 3, batch=5, grid=7, n_freq=2, seed=31)
+    g = wl.geom
+    G = O.field_matrix(g.verts, g.seg_off, wl.pts)
+    M = O.inductance_matrix_fast(g.verts, g.seg_off, g.wire_a)
+    Phi = O.flux(g.verts, g.seg_off, wl.bext_z)
+    plan = Plan(Geometry.from_workload(g), torch.tensor(wl.pts, device=dev), wl.bext_z)
+    om = torch.tensor(wl.omega, device=dev); T = torch.tensor(wl.target, device=dev)
+    for nb in (1, 5):
+        C = torch.tensor(wl.C[:nb], device=dev)
+        loss, gC, gR, gL, gw, st = plan.loss_and_grad_params(C, om, T, precision=0)
+        torch.cuda.synchronize()
+        assert int(st.abs().sum()) == 0
+        rR, rL, rw = O.grad_params_adjoint(G, M, g.R, Phi, wl.C[:nb], wl.omega, wl.target)
+        assert np.max(_nrel(gR.cpu().numpy(), rR, axis=1)) < 1e-9
+        assert np.max(_nrel(gL.cpu().numpy(), rL, axis=1)) < 1e-9
+        assert np.max(_nrel(gw.cpu().numpy(), rw, axis=1)) < 1e-9

@@ -217,3 +217,44 @@ def test_empty_batch_and_reuse(dev):
     # the GEMMs may take other kernels at another batch size: equal to rounding
     assert np.allclose(l5[:2].cpu().numpy(), l2.cpu().numpy(), rtol=1e-13, atol=0)
     assert _nrel(g5[:2].cpu().numpy(), g2.cpu().numpy()) < 1e-12
+
+
+def test_full_size_8x8_shape_sampled(dev):
+    """The launch configuration of the benchmark (64 ports, 65,536 points, 21
+    frequencies, 4,096 configurations: 86,016 systems, several P-chunks):
+    seeded random exports, RC reflections of the 8x8 workload's capacitances as
+    the variable S_C11 diagonal; loss and gradient of sampled configurations
+    against the oracle in FP64 and FP32."""
+    from paper_2503_18479_amd import sp_rc
+    wl = W.config3_array8x8(batch=4096)
+    n0, F, P = 64, wl.F, wl.P
+    rng = np.random.default_rng(11)
+    S0 = rng.normal(size=(F, n0, n0)) + 1j * rng.normal(size=(F, n0, n0))
+    S0 *= 0.8 / np.linalg.norm(S0, 2, axis=(1, 2))[:, None, None]
+    _say("[sp] full-size exports")
+    fields = (rng.standard_normal((F, P, 1, n0), dtype=np.float32)
+              + 1j * rng.standard_normal((F, P, 1, n0), dtype=np.float32)).astype(np.complex128)
+    scc = np.zeros((F, n0 + 1, n0 + 1), complex)
+    scc[:, :n0, n0] = 0.1
+    ix = np.arange(n0, dtype=np.int32)
+    pl = _plan(dev, S0, fields, scc, ix, ix, np.array([np.sqrt(50.0) + 0j]))
+    R = np.full(n0, 0.3)
+    vals = torch.empty((wl.B, F, n0), dtype=torch.complex128, device=dev)
+    sp_rc(torch.tensor(R, device=dev), torch.tensor(wl.C, device=dev), torch.tensor(wl.omega, device=dev),
+          50.0, out=vals)
+    T = np.abs(rng.normal(size=P)) * 0.05
+    Tt = torch.tensor(T, device=dev)
+    sel = [0, 1777, 4095]
+    gam = SO.rc_reflection(R, wl.C[sel], wl.omega)
+    SC = SO.assemble_network(scc, gam, ix, ix)
+    Lr = SO.loss(SO.combine(S0, fields, SC, n0, np.array([np.sqrt(50.0)]))[1], T)
+    gr = SO.grad_adjoint(S0, fields, SC, n0, np.array([np.sqrt(50.0)]), ix, ix, T)
+    for prec in (0, 1):
+        _say(f"[sp] full size prec={prec}")
+        loss, g, st = pl.loss_and_grad(vals, Tt, 0, 0, prec)
+        torch.cuda.synchronize()
+        assert int(st.abs().sum()) == 0
+        el = np.max(np.abs(loss.cpu().numpy()[sel] - Lr) / Lr)
+        eg = _nrel(g.cpu().numpy()[sel], gr)
+        _say(f"[sp] full size prec={prec}: loss {el:.2e} grad {eg:.2e}")
+        assert el < TOL[prec] and eg < TOL[prec]
