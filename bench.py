@@ -61,6 +61,10 @@ def parse():
     ap.add_argument("--large-adam", type=int, default=200,
                     help="the 32x32 array (1,024 loops, 262,144 points, batch 256): this many "
                          "Adam steps after the per-step timing (0: skip the line)")
+    ap.add_argument("--sparam", type=int, default=3,
+                    help="timed steps of the S-parameter pipeline on the 8x8 shape (0: skip)")
+    ap.add_argument("--profile-sparam", type=int, default=None,
+                    help="only the S-parameter line: this many steps per precision, for a profiler run")
     ap.add_argument("--profile-large", type=int, default=None,
                     help="only the 32x32 array: time this many steps per mode (no Adam, no "
                          "8x8 line), for a profiler run")
@@ -176,6 +180,86 @@ def ragged_line(n_inst: int, mixed: str, steps: int, torch) -> dict:
             "setup_s": t_setup, "precision": mixed}
 
 
+def sparam_line(steps: int, torch, batch: int = 4096) -> dict:
+    """The S-parameter pipeline (cosim_sp_*) on the 8x8 shape: 64 ports, 65,536
+    points, 21 frequencies, batch 4,096.  The exports stand in for full-wave
+    data and come from the quasi-static model of the same array: S0 of the
+    structure j w M, the field per unit incident wave of each port
+    G (I - S0) / Z0.  The paper's one-port loads: the RC reflections (Eq. 2-3)
+    are the variable entries, on the S_C11 diagonal; one drive port couples to
+    every loop through a constant S_C12 (proportional to the loops' flux of a
+    uniform field) and is fed with 1 W behind 50 ohm.  A step is
+    cosim_sp_rc + cosim_sp_loss_and_grad + cosim_sp_rc_backward (C -> loss,
+    dL/dC)."""
+    import workloads as W
+    from paper_2503_18479_amd import Geometry, Plan, SParamPlan, sp_rc, sp_rc_backward
+    dev = torch.device("cuda:0")
+    wl = W.config3_array8x8(batch=batch)
+    g = wl.geom
+    t0 = time.perf_counter()
+    zp = Plan(Geometry.from_workload(g), torch.tensor(wl.pts, device=dev), wl.bext_z,
+              precisions=["fp64"])
+    Gd = zp.G().to(torch.complex128)                          # [P][n]
+    M, phi = zp.M(), zp.phi()
+    del zp
+    n, F, P, Z0 = g.n, wl.F, wl.P, 50.0
+    om = torch.tensor(wl.omega, device=dev)
+    S0h = np.empty((F, n, n), dtype=np.complex128)
+    for f in range(F):
+        Zs = 1j * wl.omega[f] * M
+        S0h[f] = (Zs - Z0 * np.eye(n)) @ np.linalg.inv(Zs + Z0 * np.eye(n))
+    S0 = torch.tensor(S0h, device=dev)
+    fields = torch.empty((F, P, 1, n), dtype=torch.complex128, device=dev)
+    for f in range(F):
+        fields[f, :, 0, :] = Gd @ torch.tensor((np.eye(n) - S0h[f]) / Z0, device=dev)
+    del Gd
+    N = n + 1
+    sch = np.zeros((F, N, N), dtype=np.complex128)
+    kap = 0.5 * phi / np.linalg.norm(phi)
+    sch[:, :n, n] = kap
+    sch[:, n, :n] = kap
+    scc = torch.tensor(sch, device=dev)
+    ix = np.arange(n, dtype=np.int32)
+    sp = SParamPlan(S0, fields, ix, ix, np.array([np.sqrt(Z0 * 1.0)]), sc_const=scc)
+    del fields
+    B = wl.B
+    sp.reserve(B)
+    C = torch.tensor(wl.C, device=dev)
+    R = torch.tensor(g.R, device=dev)
+    T = torch.tensor(wl.target, device=dev)
+    vals = torch.empty((B, F, n), dtype=torch.complex128, device=dev)
+    loss = torch.empty((B,), dtype=torch.float64, device=dev)
+    gv = torch.empty((B, F, n), dtype=torch.complex128, device=dev)
+    st = torch.empty((B, F), dtype=torch.int32, device=dev)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    out = {"workload": wl.name, "ports": n, "points": P, "freqs": F, "batch": B,
+           "systems": B * F, "setup_s": t_setup, "modes": {}}
+    # complex contractions: 8 real flops per complex multiply-add, forward and adjoint
+    flops = 2 * 8.0 * P * n * B * F
+    for prec in ("fp32", "fp64"):
+        def step():
+            sp_rc(R, C, om, Z0, out=vals)
+            sp.loss_and_grad(vals, T, 0, 0, prec, out=(loss, gv, st))
+            return sp_rc_backward(R, C, om, gv, Z0)
+        step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            gC = step()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        out["modes"][prec] = {"ms_per_step": 1e3 * dt, "evals_per_s": B / dt, "steps": steps,
+                              "contraction_tflops_step_bound": flops / dt / 1e12,
+                              "flagged_systems": int((st != 0).sum()),
+                              "finite_grad": bool(torch.isfinite(gC).all())}
+        print(f"[bench] S-parameter pipeline {prec}: {1e3 * dt:.1f} ms per step", file=sys.stderr,
+              flush=True)
+    out["flops_per_step"] = flops
+    out["fp32_vs_fp64"] = out["modes"]["fp64"]["ms_per_step"] / out["modes"]["fp32"]["ms_per_step"]
+    return out
+
+
 def reference_copy(torch, dev):
     """A device copy of known size (256 MiB read + 256 MiB written) that
     calibrates the HBM byte counters of a profiler run."""
@@ -262,6 +346,11 @@ def main():
         print("bench.py needs a HIP device", file=sys.stderr)
         sys.exit(1)
     dev = torch.device("cuda:0")
+    if args.profile_sparam is not None:
+        out = sparam_line(args.profile_sparam, torch)
+        reference_copy(torch, dev)
+        print(f"[bench] profiled the S-parameter pipeline: {out['modes']}", file=sys.stderr, flush=True)
+        return
     if args.profile_large is not None:
         out = large_line(0, args.mixed, args.profile_large, torch)
         reference_copy(torch, dev)
@@ -374,6 +463,19 @@ def main():
             "phases": phases,
         },
     }
+    # gradients with respect to R, L and w on the same batch (mixed precision)
+    plan.loss_and_grad_params(C, om, T, precision=PREC_CODE[args.mixed])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out_p = plan.loss_and_grad_params(C, om, T, precision=PREC_CODE[args.mixed])
+    torch.cuda.synchronize()
+    dtp = (time.perf_counter() - t0) / args.steps
+    line["params"] = {"ms_per_step": 1e3 * dtp, "steps": args.steps,
+                      "overhead_vs_loss_and_grad": dtp * 1e3 / head["ms_per_step"] - 1.0,
+                      "outputs": "loss, dL/dC, dL/dR, dL/dL (series inductance), dL/dw",
+                      "finite": bool(all(torch.isfinite(t).all() for t in out_p[:5]))}
+    print(f"[bench] with R, L, w gradients: {1e3 * dtp:.2f} ms/step", file=sys.stderr, flush=True)
     del plan
     torch.cuda.empty_cache()
     if args.ragged > 0:
@@ -385,6 +487,10 @@ def main():
         print("[bench] 32x32 array", file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
         line["large"] = large_line(args.large_adam, args.mixed, 3, torch)
+    if args.sparam > 0:
+        print("[bench] S-parameter pipeline", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+        line["sparam"] = sparam_line(args.sparam, torch)
     if args.cpu_configs > 0:
         print("[bench] timing the oracle on the host", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(wl, args.cpu_configs)
