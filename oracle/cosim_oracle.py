@@ -48,6 +48,7 @@ MU0_4PI = MU0 / (4.0 * math.pi)
 
 LOSS_MAG = 0
 LOSS_COMPLEX = 1
+LOSS_RATIO = 2  # enhancement factor of the total field (Sec. IV-B); needs bext
 
 
 # ---------------------------------------------------------------------------
@@ -299,9 +300,15 @@ def field(G: np.ndarray, I: np.ndarray) -> np.ndarray:
 # 7. loss
 # ---------------------------------------------------------------------------
 
-def loss(Bz: np.ndarray, T: np.ndarray, mode: int = LOSS_MAG) -> np.ndarray:
-    """Per-configuration loss, mean over (f,p)."""
+def loss(Bz: np.ndarray, T: np.ndarray, mode: int = LOSS_MAG, bext: float = 0.0) -> np.ndarray:
+    """Per-configuration loss, mean over (f,p).  LOSS_RATIO: the enhancement
+    factor of Sec. IV-B, beta = |H_with structure| / |H_reference|, here
+    |bext + B_z| / |bext| (the reference is the incident field alone), against
+    the targets T: mean of (beta - T)^2."""
     F, P = Bz.shape[1], Bz.shape[2]
+    if mode == LOSS_RATIO:
+        e = np.abs(bext + Bz) / abs(bext) - T[None, None, :]
+        return np.sum(e * e, axis=(1, 2)) / (F * P)
     if mode == LOSS_MAG:
         e = np.abs(Bz) - T[None, None, :]
         return np.sum(e * e, axis=(1, 2)) / (F * P)
@@ -309,10 +316,19 @@ def loss(Bz: np.ndarray, T: np.ndarray, mode: int = LOSS_MAG) -> np.ndarray:
     return np.sum((e * np.conj(e)).real, axis=(1, 2)) / (F * P)
 
 
-def loss_weights(Bz: np.ndarray, T: np.ndarray, mode: int = LOSS_MAG) -> np.ndarray:
+def loss_weights(Bz: np.ndarray, T: np.ndarray, mode: int = LOSS_MAG,
+                 bext: float = 0.0) -> np.ndarray:
     """w = dL/d conj(B_z): the loss is real, so dL = 2 Re(sum conj(w) dB).
-    Magnitude mode: w = (|B|-T) B/|B| / (F P), taken as 0 where B = 0."""
+    Magnitude mode: w = (|B|-T) B/|B| / (F P), taken as 0 where B = 0.
+    Ratio mode: with Bt = bext + B_z, d(|Bt|/|bext| - T)^2 / dconj(B_z) =
+    (|Bt|/|bext| - T) Bt / (|bext| |Bt|), over (F P)."""
     F, P = Bz.shape[1], Bz.shape[2]
+    if mode == LOSS_RATIO:
+        Bt = bext + Bz
+        mag = np.abs(Bt)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            unit = np.where(mag > 0, Bt / np.where(mag > 0, mag, 1.0), 0.0)
+        return (mag / abs(bext) - T[None, None, :]) * unit / abs(bext) / (F * P)
     if mode == LOSS_MAG:
         mag = np.abs(Bz)
         with np.errstate(divide="ignore", invalid="ignore"):
@@ -321,24 +337,24 @@ def loss_weights(Bz: np.ndarray, T: np.ndarray, mode: int = LOSS_MAG) -> np.ndar
     return (Bz - T[None, None, :]) / (F * P)
 
 
-def evaluate(G, M, R, Phi, C, omega, T, mode: int = LOSS_MAG):
+def evaluate(G, M, R, Phi, C, omega, T, mode: int = LOSS_MAG, bext: float = 0.0):
     I = currents(M, R, Phi, C, omega)
     Bz = field(G, I)
-    return I, Bz, loss(Bz, T, mode)
+    return I, Bz, loss(Bz, T, mode, bext)
 
 
 # ---------------------------------------------------------------------------
 # 8. gradient
 # ---------------------------------------------------------------------------
 
-def grad_forward_sensitivity(G, M, R, Phi, C, omega, T, mode: int = LOSS_MAG) -> np.ndarray:
+def grad_forward_sensitivity(G, M, R, Phi, C, omega, T, mode: int = LOSS_MAG, bext: float = 0.0) -> np.ndarray:
     """dL/dC by differentiating the solve column by column (Eq. 9 with
     dZ/dC_k = -e_k e_k^T / (j w C_k^2)):  dI/dC_k = Z^-1 e_k I_k / (j w C_k^2),
     dL/dC_k = 2 Re sum_{f,p} conj(w) (G dI/dC_k)."""
     C = np.atleast_2d(C)
     omega = np.atleast_1d(omega)
     I = currents(M, R, Phi, C, omega)
-    W = loss_weights(field(G, I), T, mode)
+    W = loss_weights(field(G, I), T, mode, bext)
     n = M.shape[0]
     g = np.zeros(C.shape)
     for b in range(C.shape[0]):
@@ -353,13 +369,13 @@ def grad_forward_sensitivity(G, M, R, Phi, C, omega, T, mode: int = LOSS_MAG) ->
     return g
 
 
-def grad_adjoint(G, M, R, Phi, C, omega, T, mode: int = LOSS_MAG) -> np.ndarray:
+def grad_adjoint(G, M, R, Phi, C, omega, T, mode: int = LOSS_MAG, bext: float = 0.0) -> np.ndarray:
     """dL/dC by the adjoint: r = G^T conj(w); Z^T mu = r;
     dL/dC_k = 2 Re sum_f mu_k I_k / (j w C_k^2)."""
     C = np.atleast_2d(C)
     omega = np.atleast_1d(omega)
     I = currents(M, R, Phi, C, omega)
-    W = loss_weights(field(G, I), T, mode)
+    W = loss_weights(field(G, I), T, mode, bext)
     g = np.zeros(C.shape)
     for b in range(C.shape[0]):
         for f, w in enumerate(omega):
@@ -370,7 +386,8 @@ def grad_adjoint(G, M, R, Phi, C, omega, T, mode: int = LOSS_MAG) -> np.ndarray:
     return g
 
 
-def grad_fd(G, M, R, Phi, C, omega, T, h: float = 1e-15, mode: int = LOSS_MAG) -> np.ndarray:
+def grad_fd(G, M, R, Phi, C, omega, T, h: float = 1e-15, mode: int = LOSS_MAG,
+            bext: float = 0.0) -> np.ndarray:
     """Central finite differences of the loss, step h farads."""
     C = np.atleast_2d(np.asarray(C, float))
     g = np.zeros(C.shape)
@@ -378,13 +395,13 @@ def grad_fd(G, M, R, Phi, C, omega, T, h: float = 1e-15, mode: int = LOSS_MAG) -
         for k in range(C.shape[1]):
             cp = C[b:b + 1].copy(); cp[0, k] += h
             cm = C[b:b + 1].copy(); cm[0, k] -= h
-            lp = evaluate(G, M, R, Phi, cp, omega, T, mode)[2][0]
-            lm = evaluate(G, M, R, Phi, cm, omega, T, mode)[2][0]
+            lp = evaluate(G, M, R, Phi, cp, omega, T, mode, bext)[2][0]
+            lm = evaluate(G, M, R, Phi, cm, omega, T, mode, bext)[2][0]
             g[b, k] = (lp - lm) / (2 * h)
     return g
 
 
-def grad_params_forward_sensitivity(G, M, R, Phi, C, omega, T, mode: int = LOSS_MAG):
+def grad_params_forward_sensitivity(G, M, R, Phi, C, omega, T, mode: int = LOSS_MAG, bext: float = 0.0):
     """Gradients of each configuration's loss with respect to the other circuit
     parameters of Eq. 11 (the variables of Fig. 2 besides C), by perturbing one
     parameter at a time through the solve (Eq. 9): dI = Z^-1 (dV - dZ I) with
@@ -396,7 +413,7 @@ def grad_params_forward_sensitivity(G, M, R, Phi, C, omega, T, mode: int = LOSS_
     C = np.atleast_2d(C)
     omega = np.atleast_1d(omega)
     I = currents(M, R, Phi, C, omega)
-    W = loss_weights(field(G, I), T, mode)
+    W = loss_weights(field(G, I), T, mode, bext)
     B, n, F = C.shape[0], M.shape[0], omega.shape[0]
     gR = np.zeros((B, n))
     gL = np.zeros((B, n))
@@ -421,7 +438,7 @@ def grad_params_forward_sensitivity(G, M, R, Phi, C, omega, T, mode: int = LOSS_
     return gR, gL, gw
 
 
-def grad_params_adjoint(G, M, R, Phi, C, omega, T, mode: int = LOSS_MAG):
+def grad_params_adjoint(G, M, R, Phi, C, omega, T, mode: int = LOSS_MAG, bext: float = 0.0):
     """The same gradients through the adjoint of each system: with
     Z mu = G^T conj(w) (Z is complex symmetric), dL = 2 Re(mu^T (dV - dZ I)):
       dL/dR_k = -2 Re(mu_k I_k),  dL/dL_k = 2 w Im(mu_k I_k),
@@ -429,7 +446,7 @@ def grad_params_adjoint(G, M, R, Phi, C, omega, T, mode: int = LOSS_MAG):
     C = np.atleast_2d(C)
     omega = np.atleast_1d(omega)
     I = currents(M, R, Phi, C, omega)
-    W = loss_weights(field(G, I), T, mode)
+    W = loss_weights(field(G, I), T, mode, bext)
     B, n, F = C.shape[0], M.shape[0], omega.shape[0]
     gR = np.zeros((B, n))
     gL = np.zeros((B, n))

@@ -408,3 +408,46 @@ def test_tanh_projection_range_and_derivative():
     fd = (O.tanh_projection(th + h, 10e-12, 300e-12)[0] - O.tanh_projection(th - h, 10e-12, 300e-12)[0]) / (2 * h)
     # differences of values of order 1e-10 with step 1e-6 round at about 1e-20
     np.testing.assert_allclose(dC, fd, rtol=1e-7, atol=1e-9 * np.abs(dC).max())
+
+
+# ------------------------------------------- enhancement factor (Sec. IV-B)
+
+def test_ratio_loss_definition_cases():
+    """beta = |bext + B| / |bext|: no scattered field gives beta = 1, a field that
+    cancels the incident one gives beta = 0; the loss is the mean of
+    (beta - T)^2."""
+    bext = 1e-6
+    T = np.array([0.5, 1.0, 2.0])
+    z = np.zeros((1, 1, 3), complex)
+    np.testing.assert_allclose(O.loss(z, T, O.LOSS_RATIO, bext), [np.mean((1 - T) ** 2)], rtol=1e-15)
+    c = np.full((1, 1, 3), -bext + 0j)
+    np.testing.assert_allclose(O.loss(c, T, O.LOSS_RATIO, bext), [np.mean(T ** 2)], rtol=1e-15)
+    # doubled field, purely imaginary scattered field: beta = sqrt(1 + 1)
+    q = np.full((1, 1, 3), 1j * bext)
+    np.testing.assert_allclose(O.loss(q, T, O.LOSS_RATIO, bext), [np.mean((np.sqrt(2) - T) ** 2)],
+                               rtol=1e-14)
+
+
+def test_ratio_loss_weights_are_conjugate_derivative():
+    rng = np.random.default_rng(8)
+    bext = 1e-6
+    B = (rng.normal(size=(1, 2, 7)) + 1j * rng.normal(size=(1, 2, 7))) * 4e-7
+    T = rng.uniform(0.5, 2.0, 7)
+    w = O.loss_weights(B, T, O.LOSS_RATIO, bext)
+    h = 1e-13
+    for idx in [(0, 0, 0), (0, 1, 4)]:
+        e = np.zeros_like(B); e[idx] = h
+        dre = (O.loss(B + e, T, O.LOSS_RATIO, bext) - O.loss(B - e, T, O.LOSS_RATIO, bext))[0] / (2 * h)
+        dim = (O.loss(B + 1j * e, T, O.LOSS_RATIO, bext) - O.loss(B - 1j * e, T, O.LOSS_RATIO, bext))[0] / (2 * h)
+        np.testing.assert_allclose([dre, dim], [2 * w[idx].real, 2 * w[idx].imag], rtol=1e-6)
+
+
+def test_ratio_gradient_adjoint_sensitivity_fd():
+    G, M, R, Phi, C, om, T = _small_problem(B=2, F=2)
+    bext = 1e-6
+    beta = np.linspace(0.8, 1.6, len(T))
+    ga = O.grad_adjoint(G, M, R, Phi, C, om, beta, O.LOSS_RATIO, bext)
+    gf = O.grad_forward_sensitivity(G, M, R, Phi, C, om, beta, O.LOSS_RATIO, bext)
+    assert _rel(ga, gf) < 1e-12
+    gd = O.grad_fd(G, M, R, Phi, C, om, beta, h=1e-15, mode=O.LOSS_RATIO, bext=bext)
+    assert _rel(ga, gd) < 1e-5
