@@ -66,7 +66,13 @@ enum { COSIM_PREC_ALL = (1 << COSIM_FP64) | (1 << COSIM_FP32) | (1 << COSIM_BF16
 /* Loss of Eq. 1 per configuration b, mean over frequencies f and points p:
  *   MAG:     L_b = 1/(F P) sum_{f,p} (|B_z| - T_p)^2   (magnitude targets)
  *   COMPLEX: L_b = 1/(F P) sum_{f,p} |B_z - T_p|^2                          */
-enum cosim_loss { COSIM_LOSS_MAG = 0, COSIM_LOSS_COMPLEX = 1 };
+enum cosim_loss {
+    COSIM_LOSS_MAG = 0,      /* mean over (f, p) of (|B_z| - T_p)^2 (Eq. 1 on magnitudes) */
+    COSIM_LOSS_COMPLEX = 1,  /* mean of |B_z - T_p|^2 */
+    COSIM_LOSS_RATIO = 2     /* enhancement factor of Sec. IV-B: beta = |bext_z + B_z| / |bext_z|
+                                (the total field over the incident one), mean of (beta - T_p)^2
+                                with T_p the target factors; needs bext_z != 0 at assembly */
+};
 
 /* Per-system status bits written to status_d[b*F + f]. */
 enum cosim_sys_status {

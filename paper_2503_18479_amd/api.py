@@ -15,7 +15,7 @@ import torch
 from ._lib import check, load_library
 
 FP64, FP32, BF16X3 = 0, 1, 2
-LOSS_MAG, LOSS_COMPLEX = 0, 1
+LOSS_MAG, LOSS_COMPLEX, LOSS_RATIO = 0, 1, 2
 SYS_BAD_INPUT, SYS_SINGULAR, SYS_NONFINITE, SYS_NEGATIVE_C = 1, 2, 4, 8
 
 _PREC_NAMES = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}

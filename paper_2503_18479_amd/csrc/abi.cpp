@@ -110,6 +110,16 @@ BigFactor big_factor_args(const cosim_plan *p) {
     return bf;
 }
 
+int check_loss_mode(const cosim_plan *p, int loss_mode) {
+    if (loss_mode != COSIM_LOSS_MAG && loss_mode != COSIM_LOSS_COMPLEX &&
+        loss_mode != COSIM_LOSS_RATIO)
+        return fail(COSIM_EINVAL, "unknown loss mode %d", loss_mode);
+    if (loss_mode == COSIM_LOSS_RATIO && !(p->bext_z != 0.0))
+        return fail(COSIM_EINVAL, "the enhancement-factor loss needs a nonzero incident field "
+                                  "(the plan was assembled with bext_z = 0)");
+    return COSIM_OK;
+}
+
 int check_device(const cosim_plan *p) {
     int dev = -1;
     HIP_TRY(hipGetDevice(&dev));
@@ -416,6 +426,7 @@ int cosim_assemble_ex(cosim_geom_t g, int P, const double *pts_d, double bext_z,
         hipMalloc((void **)&p->M_d, n * n * sizeof(double)) != hipSuccess ||
         hipMalloc((void **)&p->phi_d, n * sizeof(double)) != hipSuccess ||
         hipMalloc((void **)&p->R_d, n * sizeof(double)) != hipSuccess ||
+        hipMalloc((void **)&p->T_ratio, (size_t)P * sizeof(double)) != hipSuccess ||
         hipMalloc((void **)&seg_d, (n + 1) * sizeof(int32_t)) != hipSuccess ||
         hipMalloc((void **)&verts_d, 3 * (size_t)g->V * sizeof(double)) != hipSuccess ||
         hipMalloc((void **)&wa_d, n * sizeof(double)) != hipSuccess)
@@ -458,6 +469,7 @@ int cosim_plan_destroy(cosim_plan_t p) {
     dfree(p->M_d);
     dfree(p->phi_d);
     dfree(p->R_d);
+    dfree(p->T_ratio);
     plan_free_workspace(p);
     // the parameter-gradient workspace has its own lifetime: a growing regular
     // workspace must not free it while a call still holds its address
@@ -608,8 +620,7 @@ static int loss_and_grad_impl(cosim_plan_t p, int B, int F, const double *C_d, c
     if (B == 0 || F == 0) return COSIM_OK;  // empty batch: nothing to do
     if ((rc = check_prec(precision))) return rc;
     if ((rc = check_assembled(p, precision))) return rc;
-    if (loss_mode != COSIM_LOSS_MAG && loss_mode != COSIM_LOSS_COMPLEX)
-        return fail(COSIM_EINVAL, "unknown loss mode %d", loss_mode);
+    if ((rc = check_loss_mode(p, loss_mode))) return rc;
     if (!C_d || !omega_d || !T_d || !loss_d || !status_d)
         return fail(COSIM_EINVAL, "null device pointer");
     if ((rc = check_device(p))) return rc;
@@ -628,7 +639,15 @@ static int loss_and_grad_impl(cosim_plan_t p, int B, int F, const double *C_d, c
     // unpivoted LDL^T path runs and hands systems with a small pivot to the
     // pivoted Gauss-Jordan fallback; otherwise Gauss-Jordan runs for all.
     const bool grad = grad_d != nullptr;
-    const double scale = 1.0 / ((double)F * (double)p->P);
+    double scale = 1.0 / ((double)F * (double)p->P);
+    // enhancement factor: the magnitude loss of the total field bext_z + B_z
+    // against beta |bext_z|, scaled by 1 / bext_z^2
+    const bool ratio = loss_mode == COSIM_LOSS_RATIO;
+    if (ratio) {
+        HIP_TRY(launch_scale((size_t)p->P, std::fabs(p->bext_z), T_d, p->T_ratio, st));
+        T_d = p->T_ratio;
+        scale /= p->bext_z * p->bext_z;
+    }
     if (big_plan(p->NP)) {
         // pivoted LU, GEMM contractions with the loss epilogue between, LU solve
         HIP_TRY(big_factor(big_factor_args(p), p->NP, p->n, (int)S, F, p->M_d, p->R_d,
@@ -638,6 +657,7 @@ static int loss_and_grad_impl(cosim_plan_t p, int B, int F, const double *C_d, c
                                 status_d, st));
         if (ev) HIP_TRY(hipEventRecord(ev[1], st));
         BigArgs a = big_args(p, prec, (int)S, nchunk, p->I_ws, T_d);
+        a.inc = ratio ? p->bext_z : 0.0;
         HIP_TRY(big_contract(p->blas, prec, loss_mode, grad, a, st));
         if (ev) HIP_TRY(hipEventRecord(ev[2], st));
         if (grad)
@@ -671,6 +691,7 @@ static int loss_and_grad_impl(cosim_plan_t p, int B, int F, const double *C_d, c
     a.GThi = p->GThi;
     a.GTlo = p->GTlo;
     a.T = T_d;
+    a.inc = ratio ? p->bext_z : 0.0;
     a.P = p->P;
     a.P_pad = p->P_pad;
     a.nchunk = nchunk;
@@ -794,8 +815,11 @@ int cosim_loss_and_grad_many(int count, const cosim_plan_t *plans, const int *B,
         return fail(COSIM_EINVAL, "null host array");
     int rc = check_prec(precision);
     if (rc) return rc;
-    if (loss_mode != COSIM_LOSS_MAG && loss_mode != COSIM_LOSS_COMPLEX)
+    if (loss_mode != COSIM_LOSS_MAG && loss_mode != COSIM_LOSS_COMPLEX &&
+        loss_mode != COSIM_LOSS_RATIO)
         return fail(COSIM_EINVAL, "unknown loss mode %d", loss_mode);
+    for (int i = 0; i < count; ++i)
+        if (plans[i] && (rc = check_loss_mode(plans[i], loss_mode))) return fail_instance(rc, i);
     // every instance is checked before anything is enqueued
     for (int i = 0; i < count; ++i) {
         if ((rc = check_batch(plans[i], B[i], F[i])))

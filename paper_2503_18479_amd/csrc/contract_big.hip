@@ -65,7 +65,7 @@ template <int PREC, int LOSS, bool GRAD>
 __global__ __launch_bounds__(256) void k_epilogue_big(int P, int P_pad, int S, int rows,
                                                       const void *Y, const double *__restrict__ T,
                                                       void *W, uint16_t *Wlo,
-                                                      double *__restrict__ lpart) {
+                                                      double *__restrict__ lpart, double inc) {
     __shared__ double red[4];
     const int s = blockIdx.x, c = blockIdx.y;
     const int p0 = c * rows, p1 = min(P_pad, p0 + rows);
@@ -74,16 +74,16 @@ __global__ __launch_bounds__(256) void k_epilogue_big(int P, int P_pad, int S, i
     for (int p = p0 + (int)threadIdx.x; p < p1; p += 256) {
         if (PREC == 0) {
             double x = ((const double *)Y)[o0 + p], y = ((const double *)Y)[o1 + p];
-            const double t = p < P ? T[p] : 0.0;
-            acc += epilogue<LOSS>(x, y, t);
+            const double t = p < P ? T[p] : fabs(inc);  // padded rows: residual 0
+            acc += epilogue<LOSS>(x, y, t, inc);
             if (GRAD) {
                 ((double *)W)[o0 + p] = x;
                 ((double *)W)[o1 + p] = y;
             }
         } else {
             float x = ((const float *)Y)[o0 + p], y = ((const float *)Y)[o1 + p];
-            const float t = p < P ? (float)T[p] : 0.0f;
-            acc += (double)epilogue_f<LOSS>(x, y, t);
+            const float t = p < P ? (float)T[p] : (float)fabs(inc);
+            acc += (double)epilogue_f<LOSS>(x, y, t, (float)inc);
             if (GRAD) {
                 if (PREC == 1) {
                     ((float *)W)[o0 + p] = x;
@@ -143,13 +143,14 @@ hipError_t gemm(rocblas_handle h, Prec prec, rocblas_operation ta, int m, int nn
 
 template <int PREC, int LOSS>
 hipError_t launch_epi(bool grad, dim3 grid, hipStream_t st, int P, int P_pad, int S, int rows,
-                      const void *Y, const double *T, void *W, uint16_t *Wlo, double *lpart) {
+                      const void *Y, const double *T, void *W, uint16_t *Wlo, double *lpart,
+                      double inc) {
     if (grad)
         hipLaunchKernelGGL((k_epilogue_big<PREC, LOSS, true>), grid, dim3(256), 0, st, P, P_pad, S,
-                           rows, Y, T, W, Wlo, lpart);
+                           rows, Y, T, W, Wlo, lpart, inc);
     else
         hipLaunchKernelGGL((k_epilogue_big<PREC, LOSS, false>), grid, dim3(256), 0, st, P, P_pad,
-                           S, rows, Y, T, W, Wlo, lpart);
+                           S, rows, Y, T, W, Wlo, lpart, inc);
     return hipGetLastError();
 }
 
@@ -211,9 +212,12 @@ hipError_t big_contract(void *handle, Prec prec, int loss_mode, bool grad, const
 #define COSIM_EPI(PR)                                                                          \
     (loss_mode == COSIM_LOSS_MAG                                                               \
          ? launch_epi<PR, COSIM_LOSS_MAG>(grad, ge, st, a.P, P_pad, S, a.rows, a.Y, a.T, a.W,  \
-                                          Wlo, a.lpart)                                         \
+                                          Wlo, a.lpart, a.inc)                                  \
+     : loss_mode == COSIM_LOSS_RATIO                                                           \
+         ? launch_epi<PR, COSIM_LOSS_RATIO>(grad, ge, st, a.P, P_pad, S, a.rows, a.Y, a.T,     \
+                                            a.W, Wlo, a.lpart, a.inc)                           \
          : launch_epi<PR, COSIM_LOSS_COMPLEX>(grad, ge, st, a.P, P_pad, S, a.rows, a.Y, a.T,   \
-                                              a.W, Wlo, a.lpart))
+                                              a.W, Wlo, a.lpart, a.inc))
     e = pr == 0 ? COSIM_EPI(0) : (pr == 1 ? COSIM_EPI(1) : COSIM_EPI(2));
 #undef COSIM_EPI
     if (e != hipSuccess || !grad) return e;

@@ -2,7 +2,11 @@
 // for one complex field value B = (x, y) and its target t, the loss term of
 // Eq. 1 and, in place of B, the weight w = dL/d conj(B) of the adjoint.
 //   MAG:     term (|B| - t)^2, w = (1 - t/|B|) B;
-//   COMPLEX: term |B - t|^2,   w = B - t.
+//   COMPLEX: term |B - t|^2,   w = B - t;
+//   RATIO:   MAG of the total field B + inc (inc: the incident field, real),
+//            w = (1 - t/|B + inc|) (B + inc); with t = beta |inc| and the
+//            caller's scale 1/inc^2 this is the enhancement-factor loss
+//            (beta_hat - beta)^2, beta_hat = |B + inc| / |inc| (Sec. IV-B).
 #pragma once
 #include "internal.h"
 
@@ -13,8 +17,9 @@ namespace cosim {
 // FP32 form: with s = 1/sqrt(|B|^2) (hardware rsq, ~1 ulp), |B| = |B|^2 s and
 // e/|B| = 1 - T s, which needs neither a square root nor a division.
 template <int LOSS>
-__device__ inline float epilogue_f(float &x, float &y, float t) {
-    if (LOSS == COSIM_LOSS_MAG) {
+__device__ inline float epilogue_f(float &x, float &y, float t, float inc = 0.0f) {
+    if (LOSS == COSIM_LOSS_RATIO) x += inc;
+    if (LOSS == COSIM_LOSS_MAG || LOSS == COSIM_LOSS_RATIO) {
         // |B|^2 is clamped to a normal floor before rsq: at B = 0 this gives
         // e = -t (loss t^2) and w = c B = 0 without a branch; below |B| ~ 1e-18
         // the magnitude's derivative is singular anyway.
@@ -33,10 +38,11 @@ __device__ inline float epilogue_f(float &x, float &y, float t) {
 }
 
 template <int LOSS, typename T>
-__device__ inline double epilogue(T &x, T &y, T t) {
+__device__ inline double epilogue(T &x, T &y, T t, T inc = T(0)) {
     if constexpr (sizeof(T) == 4) {
-        return (double)epilogue_f<LOSS>(x, y, t);
-    } else if (LOSS == COSIM_LOSS_MAG) {
+        return (double)epilogue_f<LOSS>(x, y, t, inc);
+    } else if (LOSS == COSIM_LOSS_MAG || LOSS == COSIM_LOSS_RATIO) {
+        if (LOSS == COSIM_LOSS_RATIO) x += inc;
         const T mag = sqrt(x * x + y * y);
         const T e = mag - t;
         const T c = mag > T(0) ? e / mag : T(0);

@@ -132,7 +132,9 @@ __global__ __launch_bounds__(256) void k_fused(FusedArgs a) {
         }
         if (threadIdx.x < PT) {
             const int p = p0 + threadIdx.x;
-            sT[threadIdx.x] = p < a.P ? tcast<T>(a.T[p]) : T(0);
+            // a padded row's field is the incident field alone: the target |inc|
+            // makes its residual zero (inc = 0 outside the ratio mode)
+            sT[threadIdx.x] = p < a.P ? tcast<T>(a.T[p]) : tcast<T>(fabs(a.inc));
         }
         __syncthreads();
 #pragma unroll 1
@@ -157,7 +159,7 @@ __global__ __launch_bounds__(256) void k_fused(FusedArgs a) {
 #pragma unroll
                 for (int b = 0; b < NB; ++b) {
                     T x = br[b][m], y = bi[b][m];
-                    lacc[b] += epilogue<LOSS>(x, y, t);
+                    lacc[b] += epilogue<LOSS>(x, y, t, (T)a.inc);
                     br[b][m] = x;
                     bi[b][m] = y;
                 }
@@ -314,7 +316,7 @@ struct Bf3Stage {
         // every thread holds the target of row threadIdx.x % PT, so that the
         // store below needs no branch (equal values to equal addresses)
         const int p = p0 + (int)(threadIdx.x & (PT - 1));
-        t = p < a.P ? (float)a.T[p] : 0.0f;
+        t = p < a.P ? (float)a.T[p] : (float)fabs(a.inc);  // padded rows: see k_fused
     }
     __device__ __forceinline__ void stash(uint16_t *sH, uint16_t *sL, uint16_t *tH, uint16_t *tL,
                                           float *sT) const {
@@ -378,7 +380,7 @@ __device__ __forceinline__ void bf3_epilogue(const float *__restrict__ sT, int r
                                              const f32x4 (&br)[2][NB], const f32x4 (&bi)[2][NB],
                                              bf16x8 (&wrh)[NB], bf16x8 (&wrl)[NB],
                                              bf16x8 (&wih)[NB], bf16x8 (&wil)[NB],
-                                             double (&lacc)[NB]) {
+                                             double (&lacc)[NB], float inc) {
     u32x4 rh[NB], rl[NB], ih[NB], il[NB];  // packed pairs of rows
     float lsub[NB];
 #pragma unroll
@@ -392,7 +394,7 @@ __device__ __forceinline__ void bf3_epilogue(const float *__restrict__ sT, int r
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
                 float xm = x[m], ym = y[m];
-                lsub[b] += epilogue_f<LOSS>(xm, ym, t4[m]);
+                lsub[b] += epilogue_f<LOSS>(xm, ym, t4[m], inc);
                 x[m] = xm;
                 y[m] = ym;
             }
@@ -533,7 +535,7 @@ __global__ __launch_bounds__(256, 2) void k_fused_bf16x3(FusedArgs a) {
             f32x4 br[2][NB], bi[2][NB];
             bf3_forward<NP, NB>(sH[cur], sL[cur], 32 * sp, r16, q, Ih, Il, br, bi);
             bf16x8 wrh[NB], wrl[NB], wih[NB], wil[NB];
-            bf3_epilogue<NB, LOSS>(sTg[cur], 32 * sp, q, br, bi, wrh, wrl, wih, wil, lacc);
+            bf3_epilogue<NB, LOSS>(sTg[cur], 32 * sp, q, br, bi, wrh, wrl, wih, wil, lacc, (float)a.inc);
             if (GRAD) bf3_adjoint<NP, NB, LDT>(tH[cur], tL[cur], 32 * sp, r16, q, wrh, wrl, wih, wil, racc);
         }
         if (DB) {
@@ -606,7 +608,7 @@ __global__ __launch_bounds__(256, 2) void k_fused_bf16x3_pipe(FusedArgs a) {
             f32x4 brn[2][NB], bin[2][NB];
             bf3_forward<NP, NB>(sH[t1 & 1], sL[t1 & 1], 32 * s1, r16, q, Ih, Il, brn, bin);
             bf16x8 wrh[NB], wrl[NB], wih[NB], wil[NB];
-            bf3_epilogue<NB, LOSS>(sTg[t & 1], 32 * s, q, br, bi, wrh, wrl, wih, wil, lacc);
+            bf3_epilogue<NB, LOSS>(sTg[t & 1], 32 * s, q, br, bi, wrh, wrl, wih, wil, lacc, (float)a.inc);
             if (GRAD) bf3_adjoint<NP, NB, LDT>(tH[t & 1], tL[t & 1], 32 * s, r16, q, wrh, wrl, wih, wil, racc);
 #pragma unroll
             for (int h = 0; h < 2; ++h)
@@ -730,6 +732,10 @@ hipError_t launch_fused(Prec prec, int NP, int variant, int loss_mode, bool grad
     if (loss_mode == COSIM_LOSS_MAG) {
         return grad ? go_loss<COSIM_LOSS_MAG, true>(prec, NP, variant, a, st)
                     : go_loss<COSIM_LOSS_MAG, false>(prec, NP, variant, a, st);
+    }
+    if (loss_mode == COSIM_LOSS_RATIO) {
+        return grad ? go_loss<COSIM_LOSS_RATIO, true>(prec, NP, variant, a, st)
+                    : go_loss<COSIM_LOSS_RATIO, false>(prec, NP, variant, a, st);
     }
     return grad ? go_loss<COSIM_LOSS_COMPLEX, true>(prec, NP, variant, a, st)
                 : go_loss<COSIM_LOSS_COMPLEX, false>(prec, NP, variant, a, st);

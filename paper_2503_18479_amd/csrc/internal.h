@@ -126,6 +126,7 @@ struct FusedArgs {
     int S, n;
     double2 *rpart;       // [nchunk][S][NP] (rr, ri); may be null when !grad
     double *lpart;        // [nchunk][S]
+    double inc = 0.0;     // incident field added before the loss (COSIM_LOSS_RATIO)
 };
 hipError_t launch_fused(Prec prec, int NP, int variant, int loss_mode, bool grad,
                         const FusedArgs &a, hipStream_t st);
@@ -179,6 +180,7 @@ struct BigArgs {
     void *W;     // P_pad x 2S planes of w (BF16X3: hi, then lo)
     void *R;     // nchunk blocks of NP x 2S planes (double for F64, float otherwise)
     double *lpart;  // [nchunk][S]
+    double inc = 0.0;  // incident field added before the loss (COSIM_LOSS_RATIO)
 };
 hipError_t big_blas_create(void **handle);
 void big_blas_destroy(void *handle);
@@ -211,6 +213,8 @@ hipError_t launch_resonant_c(int n, int F, const double *M, const double *omega,
 hipError_t launch_tanh_project(size_t count, const double *theta, double cmin, double cmax,
                                double *C, double *dC, hipStream_t st);
 hipError_t launch_clip(size_t count, double *x, double lo, double hi, hipStream_t st);
+// y = a x for count elements
+hipError_t launch_scale(size_t count, double a, const double *x, double *y, hipStream_t st);
 
 // ---- S-parameter pipeline (sparam.hip)
 constexpr int kSpMaxPorts = 64;
@@ -265,6 +269,7 @@ struct cosim_plan {
     int device = 0;
     int n = 0, NP = 0, P = 0, P_pad = 0;
     double bext_z = 0.0;
+    double *T_ratio = nullptr;  // [P] targets beta |bext_z| of the enhancement-factor loss
     std::vector<double> M_h, phi_h;
     // operators (device)
     double *G64 = nullptr;

@@ -106,6 +106,12 @@ __global__ void k_clip(size_t count, double *__restrict__ x, double lo, double h
     x[t] = fmin(fmax(x[t], lo), hi);
 }
 
+__global__ void k_scale(size_t count, double a, const double *__restrict__ x,
+                        double *__restrict__ y) {
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < count) y[t] = a * x[t];
+}
+
 unsigned blocks(size_t count) { return (unsigned)((count + 255) / 256); }
 
 }  // namespace
@@ -144,6 +150,12 @@ hipError_t launch_tanh_project(size_t count, const double *theta, double cmin, d
 hipError_t launch_clip(size_t count, double *x, double lo, double hi, hipStream_t st) {
     if (count == 0) return hipSuccess;
     hipLaunchKernelGGL(k_clip, dim3(blocks(count)), dim3(256), 0, st, count, x, lo, hi);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale(size_t count, double a, const double *x, double *y, hipStream_t st) {
+    if (count == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scale, dim3(blocks(count)), dim3(256), 0, st, count, a, x, y);
     return hipGetLastError();
 }
 

@@ -815,3 +815,35 @@ def test_parameter_gradients_on_a_fresh_plan_with_growing_batches(dev):
         assert np.max(_nrel(gR.cpu().numpy(), rR, axis=1)) < 1e-9
         assert np.max(_nrel(gL.cpu().numpy(), rL, axis=1)) < 1e-9
         assert np.max(_nrel(gw.cpu().numpy(), rw, axis=1)) < 1e-9
+
+
+# ------------------------------------------- enhancement factor (Sec. IV-B)
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("name", ["n25", "n64", "n81"])
+def test_ratio_loss_and_grad_matches_oracle(dev, name, prec):
+    """COSIM_LOSS_RATIO: beta = |bext + B_z| / |bext| against target factors,
+    loss and dL/dC against the oracle (fused kernels and the GEMM path)."""
+    c = _case(name)
+    rng = np.random.default_rng(41)
+    beta = rng.uniform(0.8, 1.6, c.wl.P)
+    Tb = torch.tensor(beta, device=dev)
+    loss, grad, st = c.plan.loss_and_grad(c.C, c.om, Tb, loss_mode=2, precision=prec)
+    torch.cuda.synchronize()
+    assert int(st.abs().sum()) == 0
+    g = c.wl.geom
+    Lr = O.evaluate(c.G, c.M, g.R, c.Phi, c.wl.C, c.wl.omega, beta, O.LOSS_RATIO, c.wl.bext_z)[2]
+    gr = O.grad_adjoint(c.G, c.M, g.R, c.Phi, c.wl.C, c.wl.omega, beta, O.LOSS_RATIO, c.wl.bext_z)
+    el = np.max(np.abs(loss.cpu().numpy() - Lr) / Lr)
+    eg = np.max(_nrel(grad.cpu().numpy(), gr, axis=1))
+    _say(f"[ratio] {name} prec={prec}: loss {el:.2e} grad {eg:.2e}")
+    assert el < TOL[prec] and eg < TOL[prec]
+
+
+def test_ratio_loss_needs_an_incident_field(dev):
+    from paper_2503_18479_amd import Geometry, Plan, CosimError
+    wl = W.small_array(2, 2, batch=1, grid=5, n_freq=1, seed=3)
+    plan = Plan(Geometry.from_workload(wl.geom), torch.tensor(wl.pts, device=dev), 0.0)
+    C = torch.tensor(wl.C, device=dev); om = torch.tensor(wl.omega, device=dev)
+    with pytest.raises(CosimError):
+        plan.loss_and_grad(C, om, torch.ones(wl.P, dtype=torch.float64, device=dev), loss_mode=2)
