@@ -11,15 +11,19 @@ combined with the Biot-Savart law"; Sec. II states the forward problem C -> B
 and the MSE inverse problem, Eq. 1; Sec. III gives the RC load, Eq. 2, and the
 S-parameter cosimulation, Eq. 3-7; Sec. IV-A gives the loop impedance, Eq. 11):
 
-1. G[p,k]   z-field at point p per ampere in loop k (Biot-Savart, straight
-            filaments, closed form of Hanson & Hirshman 2002).
+1. G[p,k]   field at point p per ampere in loop k (Biot-Savart, straight
+            filaments, closed form of Hanson & Hirshman 2002); the z-component
+            (normal to the structure) by default, x or y on request (Sec. I-B
+            asks for all three Cartesian components).
 2. M[k,l]   Neumann mutual inductance between loop filaments; the diagonal
             uses the reduced kernel 1/sqrt(|r-r'|^2 + a^2) with wire radius a.
 3. Phi[k]   flux of the uniform incident field B_ext,z through loop k
             (z-component of the vector area, shoelace formula).
 4. Z        R + j w M + 1/(j w C) per (configuration, frequency) (Eq. 2, 11).
-5. I        Z I = -j w Phi   (Eq. 6 in impedance form; see ``sform_currents``
-            for the literal S-parameter route, which reaches the same I).
+5. I        Z I = emf - j w Phi   (Eq. 6 in impedance form; see
+            ``sform_currents`` for the literal S-parameter route, which reaches
+            the same I).  emf: source EMF of driven ports (Eq. 4 through
+            ``drive_emf``); a loop without a capacitor has C = +inf.
 6. B_z      G I               (Eq. 7, z-component of the superposition).
 7. loss     mean over (f,p) of (|B_z| - T)^2 (Eq. 1 on magnitudes), or
             mean |B_z - T|^2 (complex mode).
@@ -77,8 +81,9 @@ def vector_area_z(verts: np.ndarray, seg_off: np.ndarray) -> np.ndarray:
 # 1. Biot-Savart field matrix
 # ---------------------------------------------------------------------------
 
-def bz_segment(p: np.ndarray, x1: np.ndarray, x2: np.ndarray) -> np.ndarray:
-    """z-field per ampere of the straight filament x1 -> x2 at points p [...,3].
+def b_segment(p: np.ndarray, x1: np.ndarray, x2: np.ndarray, comp: int = 2) -> np.ndarray:
+    """Cartesian component `comp` (0 x, 1 y, 2 z) of the field per ampere of the
+    straight filament x1 -> x2 at points p [...,3].
 
     With a = x1 - p, b = x2 - p the field of a finite straight filament is
     mu0/(4 pi) * (a x b) (|a| + |b|) / (|a| |b| (|a| |b| + a.b)).
@@ -89,7 +94,7 @@ def bz_segment(p: np.ndarray, x1: np.ndarray, x2: np.ndarray) -> np.ndarray:
     la = np.sqrt(np.sum(a * a, axis=-1))
     lb = np.sqrt(np.sum(b * b, axis=-1))
     c = np.cross(a, b)
-    cz = c[..., 2]
+    cz = c[..., comp]
     dot = np.sum(a * b, axis=-1)
     ab = la * lb
     c2 = np.sum(c * c, axis=-1)
@@ -98,22 +103,29 @@ def bz_segment(p: np.ndarray, x1: np.ndarray, x2: np.ndarray) -> np.ndarray:
     return MU0_4PI * cz * (la + lb) * inv / ab
 
 
-def field_matrix(verts: np.ndarray, seg_off: np.ndarray, pts: np.ndarray) -> np.ndarray:
-    """G[p,k] = sum over the segments of loop k of bz_segment (T/A)."""
+def bz_segment(p: np.ndarray, x1: np.ndarray, x2: np.ndarray) -> np.ndarray:
+    """z-component of ``b_segment``."""
+    return b_segment(p, x1, x2, 2)
+
+
+def field_matrix(verts: np.ndarray, seg_off: np.ndarray, pts: np.ndarray,
+                 comp: int = 2) -> np.ndarray:
+    """G[p,k] = sum over the segments of loop k of b_segment (T/A), field
+    component `comp` (0 x, 1 y, 2 z)."""
     n = len(seg_off) - 1
     G = np.zeros((pts.shape[0], n))
     for k in range(n):
         a, b = segments(verts, seg_off, k)
         for s in range(a.shape[0]):
-            G[:, k] += bz_segment(pts, a[s], b[s])
+            G[:, k] += b_segment(pts, a[s], b[s], comp)
     return G
 
 
 def bz_segment_quadrature(p: np.ndarray, x1: np.ndarray, x2: np.ndarray,
-                          order: int = 64, panels: int = 8) -> np.ndarray:
+                          order: int = 64, panels: int = 8, comp: int = 2) -> np.ndarray:
     """Same quantity by composite Gauss-Legendre quadrature of the
     Biot-Savart integrand (dl x r)/|r|^3 along the filament (a brute-force
-    check of the closed form)."""
+    check of the closed form); component `comp` of dl x r."""
     xg, wg = np.polynomial.legendre.leggauss(order)
     d = x2 - x1
     out = np.zeros(p.shape[:-1])
@@ -124,7 +136,8 @@ def bz_segment_quadrature(p: np.ndarray, x1: np.ndarray, x2: np.ndarray,
             src = x1 + ti * d
             r = p - src
             r3 = np.sum(r * r, axis=-1) ** 1.5
-            out += wi * (d[0] * r[..., 1] - d[1] * r[..., 0]) / r3
+            u, v = (comp + 1) % 3, (comp + 2) % 3
+            out += wi * (d[u] * r[..., v] - d[v] * r[..., u]) / r3
     return MU0_4PI * out
 
 
@@ -273,21 +286,41 @@ def flux(verts, seg_off, bext_z: float) -> np.ndarray:
 
 
 def impedance(M: np.ndarray, R: np.ndarray, C: np.ndarray, omega: float) -> np.ndarray:
-    """Z = diag(R) + j w M + diag(1/(j w C)) for one configuration (Eq. 2, 11)."""
+    """Z = diag(R) + j w M + diag(1/(j w C)) for one configuration (Eq. 2, 11).
+    The capacitor term is written -j/(w C) so that C = +inf (a loop without a
+    series capacitor, e.g. a drive coil) gives the short-circuit limit 0."""
     Z = 1j * omega * M.astype(np.complex128)
-    Z[np.diag_indices_from(Z)] += R + 1.0 / (1j * omega * C)
+    Z[np.diag_indices_from(Z)] += R - 1j / (omega * C)
     return Z
 
 
-def currents(M, R, Phi, C, omega) -> np.ndarray:
-    """I[b,f,:] solving Z I = -j w Phi with LAPACK (zgesv) per system."""
+def drive_emf(power: float = 1.0, z0: float = 50.0, phase: float = 0.0) -> complex:
+    """Source EMF of a port driven as in Eq. 4: the excitation sends the wave
+    sqrt(Z0 P) toward the port through its characteristic impedance Z0; a
+    source of internal impedance Z0 emitting that wave has the Thevenin EMF
+    2 sqrt(Z0 P).  In the loop equations the port adds Z0 to the loop's
+    series resistance and this EMF (times exp(j phase)) to its voltage."""
+    return 2.0 * math.sqrt(z0 * power) * complex(math.cos(phase), math.sin(phase))
+
+
+def excitation(Phi, omega: float, emf=None) -> np.ndarray:
+    """Loop voltages V = emf - j w Phi: the EMF of the incident flux plus any
+    source EMF in series with a loop (frequency independent)."""
+    V = -1j * omega * np.asarray(Phi, dtype=np.complex128)
+    if emf is not None:
+        V = V + np.asarray(emf, dtype=np.complex128)
+    return V
+
+
+def currents(M, R, Phi, C, omega, emf=None) -> np.ndarray:
+    """I[b,f,:] solving Z I = emf - j w Phi with LAPACK (zgesv) per system."""
     C = np.atleast_2d(C)
     omega = np.atleast_1d(omega)
     out = np.zeros((C.shape[0], omega.shape[0], M.shape[0]), dtype=np.complex128)
     for b in range(C.shape[0]):
         for f, w in enumerate(omega):
             Z = impedance(M, R, C[b], w)
-            out[b, f] = np.linalg.solve(Z, -1j * w * Phi)
+            out[b, f] = np.linalg.solve(Z, excitation(Phi, w, emf))
     return out
 
 
@@ -337,8 +370,8 @@ def loss_weights(Bz: np.ndarray, T: np.ndarray, mode: int = LOSS_MAG,
     return (Bz - T[None, None, :]) / (F * P)
 
 
-def evaluate(G, M, R, Phi, C, omega, T, mode: int = LOSS_MAG, bext: float = 0.0):
-    I = currents(M, R, Phi, C, omega)
+def evaluate(G, M, R, Phi, C, omega, T, mode: int = LOSS_MAG, bext: float = 0.0, emf=None):
+    I = currents(M, R, Phi, C, omega, emf)
     Bz = field(G, I)
     return I, Bz, loss(Bz, T, mode, bext)
 
@@ -347,13 +380,14 @@ def evaluate(G, M, R, Phi, C, omega, T, mode: int = LOSS_MAG, bext: float = 0.0)
 # 8. gradient
 # ---------------------------------------------------------------------------
 
-def grad_forward_sensitivity(G, M, R, Phi, C, omega, T, mode: int = LOSS_MAG, bext: float = 0.0) -> np.ndarray:
+def grad_forward_sensitivity(G, M, R, Phi, C, omega, T, mode: int = LOSS_MAG, bext: float = 0.0,
+                             emf=None) -> np.ndarray:
     """dL/dC by differentiating the solve column by column (Eq. 9 with
     dZ/dC_k = -e_k e_k^T / (j w C_k^2)):  dI/dC_k = Z^-1 e_k I_k / (j w C_k^2),
     dL/dC_k = 2 Re sum_{f,p} conj(w) (G dI/dC_k)."""
     C = np.atleast_2d(C)
     omega = np.atleast_1d(omega)
-    I = currents(M, R, Phi, C, omega)
+    I = currents(M, R, Phi, C, omega, emf)
     W = loss_weights(field(G, I), T, mode, bext)
     n = M.shape[0]
     g = np.zeros(C.shape)
@@ -363,18 +397,19 @@ def grad_forward_sensitivity(G, M, R, Phi, C, omega, T, mode: int = LOSS_MAG, be
             for k in range(n):
                 e = np.zeros(n, dtype=np.complex128)
                 e[k] = 1.0
-                dI = np.linalg.solve(Z, e) * I[b, f, k] / (1j * w * C[b, k] ** 2)
+                dI = np.linalg.solve(Z, e) * I[b, f, k] * (-1j / (w * C[b, k] ** 2))
                 dB = G @ dI
                 g[b, k] += 2.0 * float(np.real(np.sum(np.conj(W[b, f]) * dB)))
     return g
 
 
-def grad_adjoint(G, M, R, Phi, C, omega, T, mode: int = LOSS_MAG, bext: float = 0.0) -> np.ndarray:
+def grad_adjoint(G, M, R, Phi, C, omega, T, mode: int = LOSS_MAG, bext: float = 0.0,
+                 emf=None) -> np.ndarray:
     """dL/dC by the adjoint: r = G^T conj(w); Z^T mu = r;
     dL/dC_k = 2 Re sum_f mu_k I_k / (j w C_k^2)."""
     C = np.atleast_2d(C)
     omega = np.atleast_1d(omega)
-    I = currents(M, R, Phi, C, omega)
+    I = currents(M, R, Phi, C, omega, emf)
     W = loss_weights(field(G, I), T, mode, bext)
     g = np.zeros(C.shape)
     for b in range(C.shape[0]):
@@ -382,12 +417,12 @@ def grad_adjoint(G, M, R, Phi, C, omega, T, mode: int = LOSS_MAG, bext: float = 
             Z = impedance(M, R, C[b], w)
             r = G.T @ np.conj(W[b, f])
             mu = np.linalg.solve(Z.T, r)
-            g[b] += 2.0 * np.real(mu * I[b, f] / (1j * w * C[b] ** 2))
+            g[b] += 2.0 * np.real(mu * I[b, f] * (-1j / (w * C[b] ** 2)))
     return g
 
 
 def grad_fd(G, M, R, Phi, C, omega, T, h: float = 1e-15, mode: int = LOSS_MAG,
-            bext: float = 0.0) -> np.ndarray:
+            bext: float = 0.0, emf=None) -> np.ndarray:
     """Central finite differences of the loss, step h farads."""
     C = np.atleast_2d(np.asarray(C, float))
     g = np.zeros(C.shape)
@@ -395,24 +430,25 @@ def grad_fd(G, M, R, Phi, C, omega, T, h: float = 1e-15, mode: int = LOSS_MAG,
         for k in range(C.shape[1]):
             cp = C[b:b + 1].copy(); cp[0, k] += h
             cm = C[b:b + 1].copy(); cm[0, k] -= h
-            lp = evaluate(G, M, R, Phi, cp, omega, T, mode, bext)[2][0]
-            lm = evaluate(G, M, R, Phi, cm, omega, T, mode, bext)[2][0]
+            lp = evaluate(G, M, R, Phi, cp, omega, T, mode, bext, emf)[2][0]
+            lm = evaluate(G, M, R, Phi, cm, omega, T, mode, bext, emf)[2][0]
             g[b, k] = (lp - lm) / (2 * h)
     return g
 
 
-def grad_params_forward_sensitivity(G, M, R, Phi, C, omega, T, mode: int = LOSS_MAG, bext: float = 0.0):
+def grad_params_forward_sensitivity(G, M, R, Phi, C, omega, T, mode: int = LOSS_MAG, bext: float = 0.0,
+                                    emf=None):
     """Gradients of each configuration's loss with respect to the other circuit
     parameters of Eq. 11 (the variables of Fig. 2 besides C), by perturbing one
     parameter at a time through the solve (Eq. 9): dI = Z^-1 (dV - dZ I) with
-    V = -j w Phi, and dL = 2 Re sum_p conj(w_p) (G dI)_p.
+    V = emf - j w Phi (emf does not depend on w), and dL = 2 Re sum_p conj(w_p) (G dI)_p.
       R_k:  dZ = e_k e_k^T;
       L_k (a series inductance added to loop k): dZ = j w e_k e_k^T;
       w_f:  dZ = j M - diag(1 / (j w^2 C)) and dV = -j Phi (G does not depend on w).
     Returns (dL/dR [B][n], dL/dL [B][n], dL/dw [B][F])."""
     C = np.atleast_2d(C)
     omega = np.atleast_1d(omega)
-    I = currents(M, R, Phi, C, omega)
+    I = currents(M, R, Phi, C, omega, emf)
     W = loss_weights(field(G, I), T, mode, bext)
     B, n, F = C.shape[0], M.shape[0], omega.shape[0]
     gR = np.zeros((B, n))
@@ -433,19 +469,20 @@ def grad_params_forward_sensitivity(G, M, R, Phi, C, omega, T, mode: int = LOSS_
                 E[k, k] = 1.0
                 gR[b, k] += dL(E, zero)
                 gL[b, k] += dL(1j * w * E, zero)
-            dZw = 1j * M - np.diag(1.0 / (1j * w * w * C[b]))
+            dZw = 1j * M + np.diag(1j / (w * w * C[b]))
             gw[b, f] = dL(dZw, -1j * Phi)
     return gR, gL, gw
 
 
-def grad_params_adjoint(G, M, R, Phi, C, omega, T, mode: int = LOSS_MAG, bext: float = 0.0):
+def grad_params_adjoint(G, M, R, Phi, C, omega, T, mode: int = LOSS_MAG, bext: float = 0.0,
+                        emf=None):
     """The same gradients through the adjoint of each system: with
     Z mu = G^T conj(w) (Z is complex symmetric), dL = 2 Re(mu^T (dV - dZ I)):
       dL/dR_k = -2 Re(mu_k I_k),  dL/dL_k = 2 w Im(mu_k I_k),
       dL/dw = 2 Re(-j mu^T Phi - j mu^T M I + sum_k mu_k I_k / (j w^2 C_k))."""
     C = np.atleast_2d(C)
     omega = np.atleast_1d(omega)
-    I = currents(M, R, Phi, C, omega)
+    I = currents(M, R, Phi, C, omega, emf)
     W = loss_weights(field(G, I), T, mode, bext)
     B, n, F = C.shape[0], M.shape[0], omega.shape[0]
     gR = np.zeros((B, n))
@@ -458,13 +495,13 @@ def grad_params_adjoint(G, M, R, Phi, C, omega, T, mode: int = LOSS_MAG, bext: f
             i = I[b, f]
             gR[b] += -2.0 * np.real(mu * i)
             gL[b] += 2.0 * w * np.imag(mu * i)
-            t = -1j * (mu @ Phi) - 1j * (mu @ (M @ i)) + np.sum(mu * i / (1j * w * w * C[b]))
+            t = -1j * (mu @ Phi) - 1j * (mu @ (M @ i)) + np.sum(mu * i * (-1j / (w * w * C[b])))
             gw[b, f] = 2.0 * np.real(t)
     return gR, gL, gw
 
 
 def grad_params_fd(G, M, R, Phi, C, omega, T, mode: int = LOSS_MAG, hR: float = 1e-7,
-                   hL: float = 1e-15, hw: float = 1.0):
+                   hL: float = 1e-15, hw: float = 1.0, bext: float = 0.0, emf=None):
     """Central differences of the loss for the same parameters (steps in ohm,
     henry and rad/s); a series inductance L_k enters as M_kk + L_k."""
     C = np.atleast_2d(C)
@@ -476,7 +513,7 @@ def grad_params_fd(G, M, R, Phi, C, omega, T, mode: int = LOSS_MAG, hR: float = 
     L0 = evaluate  # local alias
 
     def loss_of(Mv, Rv, om):
-        return L0(G, Mv, Rv, Phi, C, om, T, mode)[2]
+        return L0(G, Mv, Rv, Phi, C, om, T, mode, bext, emf)[2]
 
     for k in range(n):
         Rp, Rm = R.copy(), R.copy()
@@ -521,7 +558,7 @@ def backward_from_field_grad(G, M, R, C, omega, I, gBz) -> np.ndarray:
             Z = impedance(M, R, C[b], w)
             r = G.T @ np.conj(0.5 * gBz[b, f])
             mu = np.linalg.solve(Z.T, r)
-            g[b] += 2.0 * np.real(mu * I[b, f] / (1j * w * C[b] ** 2))
+            g[b] += 2.0 * np.real(mu * I[b, f] * (-1j / (w * C[b] ** 2)))
     return g
 
 

@@ -451,3 +451,175 @@ def test_ratio_gradient_adjoint_sensitivity_fd():
     assert _rel(ga, gf) < 1e-12
     gd = O.grad_fd(G, M, R, Phi, C, om, beta, h=1e-15, mode=O.LOSS_RATIO, bext=bext)
     assert _rel(ga, gd) < 1e-5
+
+
+# ------------------------------------------ field components (Sec. I-B: B_x, B_y, B_z)
+
+@pytest.mark.parametrize("comp", [0, 1, 2])
+def test_field_component_closed_form_vs_quadrature(comp):
+    rng = np.random.default_rng(7 + comp)
+    for _ in range(10):
+        x1 = rng.uniform(-0.02, 0.02, 3); x2 = rng.uniform(-0.02, 0.02, 3)
+        p = rng.uniform(-0.05, 0.05, (16, 3)); p[:, 2] += 0.03 * np.sign(p[:, 2] + 1e-9)
+        cf = O.b_segment(p, x1, x2, comp)
+        q = O.bz_segment_quadrature(p, x1, x2, order=48, panels=16, comp=comp)
+        np.testing.assert_allclose(cf, q, rtol=1e-10, atol=1e-12 * np.abs(q).max())
+
+
+def test_field_components_far_field_is_a_dipole():
+    # a small planar loop far away: B = mu0/(4 pi r^3) (3 (m.rhat) rhat - m), m = I A z
+    g = W.square_array(1, 1, 0.01, 0.0, 64)
+    A = O.vector_area_z(g.verts, g.seg_off)[0]
+    rng = np.random.default_rng(3)
+    d = rng.normal(size=(12, 3)); d /= np.linalg.norm(d, axis=1, keepdims=True)
+    pts = 2.0 * d
+    Gc = np.stack([O.field_matrix(g.verts, g.seg_off, pts, c)[:, 0] for c in range(3)], axis=1)
+    m = np.array([0.0, 0.0, A])
+    r = np.linalg.norm(pts, axis=1, keepdims=True)
+    rh = pts / r
+    dip = O.MU0_4PI * (3.0 * (rh @ m)[:, None] * rh - m[None, :]) / r ** 3
+    # next multipole term is (size / r)^2 ~ 1e-5 smaller
+    np.testing.assert_allclose(Gc, dip, atol=1e-4 * np.abs(dip).max())
+
+
+def test_field_is_divergence_and_curl_free_off_the_wires():
+    g = W.square_array(2, 1, 0.03, 0.035, 16)
+    rng = np.random.default_rng(5)
+    pts = np.column_stack([rng.uniform(-0.04, 0.04, 8), rng.uniform(-0.03, 0.03, 8),
+                           rng.uniform(0.008, 0.02, 8)])
+    h = 1e-6  # truncation ~ (h / distance)^2, rounding ~ eps distance / h
+
+    def B(p):  # [P,3] field of loop 0 + 0.7 loop 1 (any current vector will do)
+        return np.stack([O.field_matrix(g.verts, g.seg_off, p, c) @ np.array([1.0, 0.7])
+                         for c in range(3)], axis=1)
+
+    J = np.zeros((pts.shape[0], 3, 3))  # J[p, i, j] = dB_i / dx_j
+    for j in range(3):
+        e = np.zeros(3); e[j] = h
+        J[:, :, j] = (B(pts + e) - B(pts - e)) / (2 * h)
+    scale = np.abs(J).reshape(len(pts), -1).max(axis=1)   # per point
+    div = J[:, 0, 0] + J[:, 1, 1] + J[:, 2, 2]
+    curl = np.stack([J[:, 2, 1] - J[:, 1, 2], J[:, 0, 2] - J[:, 2, 0], J[:, 1, 0] - J[:, 0, 1]], 1)
+    assert np.all(np.abs(div) < 1e-7 * scale)
+    assert np.all(np.abs(curl).max(axis=1) < 1e-7 * scale)
+
+
+def test_field_transverse_components_vanish_on_the_axis():
+    c = W.single_circle(0.05, 64)
+    pts = np.array([[0.0, 0.0, z] for z in (-0.03, 0.0, 0.01, 0.2)])
+    bz = O.field_matrix(c.verts, c.seg_off, pts, 2)[:, 0]
+    for comp in (0, 1):
+        b = O.field_matrix(c.verts, c.seg_off, pts, comp)[:, 0]
+        assert np.abs(b).max() < 1e-12 * np.abs(bz).max()
+
+
+# ------------------------------------------------ drive port (Sec. IV-A, Eq. 4)
+
+def _drive_setup(g, omega=123.5e6 * 2 * math.pi, seed=0, z0=50.0):
+    M = O.inductance_matrix_fast(g.verts, g.seg_off, g.wire_a)
+    n = g.n
+    rng = np.random.default_rng(seed)
+    C = rng.uniform(20e-12, 150e-12, (2, n))
+    C[:, -1] = np.inf          # the coil has no capacitor
+    R = g.R.copy(); R[-1] += z0  # the source impedance in series with the coil
+    return M, R, C, np.array([omega])
+
+
+def test_short_circuit_limit_of_a_missing_capacitor():
+    g = W.with_drive_coil(W.single_circle(0.03, 64))
+    M, R, C, om = _drive_setup(g)
+    emf = np.array([0.0, O.drive_emf(1.0)])
+    Phi = np.zeros(g.n)
+    Cbig = C.copy(); Cbig[:, -1] = 1e30
+    np.testing.assert_allclose(O.currents(M, R, Phi, C, om, emf),
+                               O.currents(M, R, Phi, Cbig, om, emf), rtol=1e-13)
+
+
+def test_drive_two_loop_closed_form():
+    # coil d driven by E, loop 1 coupled through M12: Cramer's rule on the 2x2 system
+    g = W.with_drive_coil(W.single_circle(0.03, 64))
+    M, R, C, om = _drive_setup(g)
+    w = om[0]
+    E = O.drive_emf(1.0, 50.0, 0.3)
+    Z11 = R[0] + 1j * w * M[0, 0] - 1j / (w * C[0, 0])
+    Zdd = R[1] + 1j * w * M[1, 1]
+    Zm = 1j * w * M[0, 1]
+    det = Z11 * Zdd - Zm * Zm
+    I = O.currents(M, R, np.zeros(2), C[:1], om, np.array([0.0, E]))[0, 0]
+    np.testing.assert_allclose(I, [-Zm * E / det, Z11 * E / det], rtol=1e-13)
+    np.testing.assert_allclose(abs(E), 2.0 * math.sqrt(50.0), rtol=1e-15)
+
+
+def test_drive_power_balance():
+    # sources deliver what the resistors dissipate: Re(I^H V) = sum R |I|^2
+    g = W.with_drive_coil(W.square_array(3, 3, 0.03, 0.035, 16), radius=0.06, z=0.015)
+    M, R, C, om = _drive_setup(g, seed=2)
+    Phi = O.flux(g.verts, g.seg_off, 1e-6)
+    emf = np.zeros(g.n, complex); emf[-1] = O.drive_emf(1.0, 50.0, 0.5)
+    I = O.currents(M, R, Phi, C, om, emf)
+    for b in range(C.shape[0]):
+        V = O.excitation(Phi, om[0], emf)
+        lhs = np.real(np.vdot(I[b, 0], V))
+        rhs = np.sum(R * np.abs(I[b, 0]) ** 2)
+        np.testing.assert_allclose(lhs, rhs, rtol=1e-12)
+
+
+@pytest.mark.parametrize("phase", [0.0, math.pi / 2])
+def test_drive_port_matches_the_sparameter_pipeline(phase):
+    """The same driven structure through Eq. 3-7: every loop is a port of the
+    lossless structure j w M (S0 = (Zs - Z0)(Zs + Z0)^-1); the RC loads
+    reflect with Gamma (Eq. 3); the coil's port is joined straight through to
+    one external port (S_C12 = 1, S_C11 = 0 there) that sends sqrt(Z0 P)
+    (Eq. 4).  Per-port fields with the other ports matched are G (1 - S0)/Z0,
+    so Eq. 7 gives B = G I of the loop equations with the Thevenin EMF
+    2 sqrt(Z0 P) and Z0 in series with the coil."""
+    import oracle.sparam_oracle as SO
+    z0, P = 50.0, 1.0
+    g = W.with_drive_coil(W.square_array(2, 2, 0.03, 0.035, 16), radius=0.05, z=0.012)
+    M, R, C, om = _drive_setup(g, seed=4, z0=z0)
+    w = om[0]
+    n0 = g.n
+    pts = W.grid_points(4, 0.07, [0.01])
+    Gm = O.field_matrix(g.verts, g.seg_off, pts)
+    eye = np.eye(n0)
+    Zs = 1j * w * M
+    S0 = (Zs - z0 * eye) @ np.linalg.inv(Zs + z0 * eye)
+    fields = (Gm @ (eye - S0) / z0)[None, :, None, :]          # [F][P][1][n0]
+    N = n0 + 1
+    SC = np.zeros((C.shape[0], 1, N, N), complex)
+    gam = SO.rc_reflection(R[:-1], C[:, :-1], om, z0)           # [B][F][n0-1]
+    for b in range(C.shape[0]):
+        SC[b, 0, np.arange(n0 - 1), np.arange(n0 - 1)] = gam[b, 0]
+        SC[b, 0, n0 - 1, n0] = 1.0
+        SC[b, 0, n0, n0 - 1] = 1.0
+    exc = np.array([math.sqrt(z0 * P) * complex(math.cos(phase), math.sin(phase))])
+    x, Bc = SO.combine(S0[None], fields, SC, n0, exc)
+    emf = np.zeros(n0, complex); emf[-1] = O.drive_emf(P, z0, phase)
+    I = O.currents(M, R, np.zeros(n0), C, om, emf)
+    np.testing.assert_allclose(Bc[..., 0], O.field(Gm, I), rtol=1e-10, atol=1e-12 * np.abs(Bc).max())
+    np.testing.assert_allclose(np.einsum("ij,bfj->bfi", eye - S0, x) / z0, I, rtol=1e-10,
+                               atol=1e-12 * np.abs(I).max())
+
+
+def test_drive_gradients_adjoint_vs_differences():
+    g = W.with_drive_coil(W.square_array(2, 1, 0.03, 0.035, 16), radius=0.045, z=0.015)
+    M, R, C, om = _drive_setup(g, seed=6)
+    pts = W.grid_points(5, 0.06, [0.01])
+    G = O.field_matrix(g.verts, g.seg_off, pts)
+    Phi = np.zeros(g.n)
+    emf = np.zeros(g.n, complex); emf[-1] = O.drive_emf(1.0, 50.0, 0.2)
+    I = O.currents(M, R, Phi, C, om, emf)
+    T = 0.8 * np.abs(O.field(G, I))[0, 0]
+    ga = O.grad_adjoint(G, M, R, Phi, C, om, T, emf=emf)
+    gs = O.grad_forward_sensitivity(G, M, R, Phi, C, om, T, emf=emf)
+    Cf = C.copy(); Cf[:, -1] = 1e30   # differences need a finite value; the limit is the same
+    gd = O.grad_fd(G, M, R, Phi, Cf, om, T, h=1e-16, emf=emf)
+    assert np.all(ga[:, -1] == 0.0)
+    np.testing.assert_allclose(ga, gs, rtol=1e-9, atol=1e-12 * np.abs(ga).max())
+    np.testing.assert_allclose(ga[:, :-1], gd[:, :-1], rtol=1e-5)
+    pa = O.grad_params_adjoint(G, M, R, Phi, C, om, T, emf=emf)
+    ps = O.grad_params_forward_sensitivity(G, M, R, Phi, C, om, T, emf=emf)
+    pd = O.grad_params_fd(G, M, R, Phi, C, om, T, emf=emf)
+    for a, s_, d in zip(pa, ps, pd):
+        np.testing.assert_allclose(a, s_, rtol=1e-9, atol=1e-12 * np.abs(a).max())
+        np.testing.assert_allclose(a, d, rtol=2e-5, atol=1e-6 * np.abs(a).max())
