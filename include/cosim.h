@@ -134,6 +134,15 @@ int cosim_assemble(cosim_geom_t g, int P, const double *pts_d, double bext_z, vo
  * plans at once (independent instances). */
 int cosim_assemble_ex(cosim_geom_t g, int P, const double *pts_d, double bext_z, int precisions,
                       void *stream, cosim_plan_t *out);
+/* The same with G holding another Cartesian component of the field
+ * (Sec. I-B: all three components are available): component 0 = B_x,
+ * 1 = B_y, 2 = B_z (what cosim_assemble_ex builds).  Everything below that
+ * reads G (fields, losses, gradients) then works on that component; to
+ * shape several components, use one plan per component with the same
+ * geometry, points and excitation.  COSIM_LOSS_RATIO needs component 2.
+ * Errors: those of cosim_assemble_ex; COSIM_EINVAL for a component outside 0..2. */
+int cosim_assemble_component(cosim_geom_t g, int P, const double *pts_d, double bext_z,
+                             int precisions, int component, void *stream, cosim_plan_t *out);
 int cosim_plan_destroy(cosim_plan_t p);
 /* Loops n, points P of a plan. */
 int cosim_plan_size(cosim_plan_t p, int *n_loops, int *n_points);
@@ -148,9 +157,31 @@ int cosim_plan_copy_M(cosim_plan_t p, double *M);
 int cosim_plan_copy_phi(cosim_plan_t p, double *phi);
 
 /* --------------------------------------------------------------------------
+ * Driven ports (Sec. III, Eq. 4; the excitation coil of Sec. IV-A).  A port
+ * in series with loop loop[i] is fed by an excitation that sends the voltage
+ * wave sqrt(z0 power[i]) exp(j phase[i]) toward it through the characteristic
+ * impedance z0 (the paper takes 1 W and 50 ohm).  In the loop equations that
+ * source is its Thevenin equivalent: z0 is added to the loop's series
+ * resistance and the EMF E = 2 sqrt(z0 power[i]) exp(j phase[i]) to its
+ * voltage, so every solve below becomes
+ *     (diag(R + z0 [driven]) + j w M + diag(1/(j w C))) I = E - j w Phi.
+ * E does not depend on w.  A driven coil without a capacitor passes
+ * C = +INFINITY for its loop (the short-circuit limit; its gradient is 0).
+ *   nport 0..n (0 removes all ports); loop [nport] host int32, distinct loops;
+ *   power [nport] host double >= 0 (watts); phase [nport] host double
+ *   (radians) or NULL for 0; z0 > 0 (ohms; ignored when nport = 0).
+ * Replaces the previous port set.  Parameter gradients with respect to R
+ * (cosim_loss_and_grad_params) are then taken with respect to the loop's
+ * total series resistance.  Synchronises `stream`.  Errors: COSIM_EINVAL. */
+int cosim_plan_set_drive(cosim_plan_t p, int nport, const int32_t *loop, const double *power,
+                         const double *phase, double z0, void *stream);
+
+/* --------------------------------------------------------------------------
  * Currents (Eq. 6 in impedance form).  For every configuration b < B and
  * frequency f < F solves
- *     (diag(R) + j w_f M + diag(1/(j w_f C_b))) I_{b,f} = -j w_f Phi
+ *     (diag(R) + j w_f M + diag(1/(j w_f C_b))) I_{b,f} = E - j w_f Phi
+ * (E: the EMF of driven ports, zero unless cosim_plan_set_drive set some;
+ * C = +INFINITY is a loop without a capacitor)
  * by Gauss-Jordan elimination with partial pivoting in FP64.
  *   C_d      [B][n] double, device (farads)
  *   omega_d  [F] double, device (rad/s)

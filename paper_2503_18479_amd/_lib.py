@@ -36,6 +36,10 @@ SIGNATURES = {
     "cosim_loss_and_grad": (c_int, [c_void_p, c_int, c_int, c_void_p, c_void_p, c_void_p, c_int,
                                     c_int, c_void_p, c_void_p, c_void_p, c_void_p]),
     "cosim_assemble_ex": (c_int, [c_void_p, c_int, c_void_p, c_double, c_int, c_void_p, P(c_void_p)]),
+    "cosim_assemble_component": (c_int, [c_void_p, c_int, c_void_p, c_double, c_int, c_int, c_void_p,
+                                         P(c_void_p)]),
+    "cosim_plan_set_drive": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_double,
+                                     c_void_p]),
     "cosim_loss_and_grad_many": (c_int, [c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                          c_void_p, c_int, c_int, c_void_p, c_void_p, c_void_p,
                                          c_void_p]),

@@ -89,24 +89,23 @@ class Plan:
     """Assembled operators G, M, Phi for one geometry and point set.
 
     precisions: None for every precision, or an iterable of precisions whose
-    copies of G the plan keeps (cosim_assemble_ex)."""
+    copies of G the plan keeps (cosim_assemble_ex).  component: the Cartesian
+    component of the field that G holds, 0 (x), 1 (y) or 2 (z)
+    (cosim_assemble_component)."""
 
     def __init__(self, geom: Geometry, pts: torch.Tensor, bext_z: float = 1e-6,
-                 precisions=None):
+                 precisions=None, component: int = 2):
         self._lib = load_library()
         P = int(pts.shape[0])
         ptr = _dev(pts, torch.float64, (P, 3), "pts")
         h = ctypes.c_void_p()
-        if precisions is None:
-            check(self._lib.cosim_assemble(geom.handle, P, ptr, float(bext_z), _stream(),
-                                           ctypes.byref(h)))
-        else:
-            mask = 0
-            for pr in precisions:
-                mask |= 1 << precision_code(pr)
-            check(self._lib.cosim_assemble_ex(geom.handle, P, ptr, float(bext_z), mask, _stream(),
-                                              ctypes.byref(h)))
+        mask = 0
+        for pr in (precisions if precisions is not None else (FP64, FP32, BF16X3)):
+            mask |= 1 << precision_code(pr)
+        check(self._lib.cosim_assemble_component(geom.handle, P, ptr, float(bext_z), mask,
+                                                 int(component), _stream(), ctypes.byref(h)))
         self._h = h
+        self.component = int(component)
         self.n = geom.n
         self.P = P
         self.device = pts.device
@@ -119,6 +118,16 @@ class Plan:
             self._h = None
 
     # -- operators ------------------------------------------------------------
+    def set_drive(self, loops, power=1.0, phase=0.0, z0: float = 50.0) -> None:
+        """Driven ports in series with `loops` (cosim_plan_set_drive): each sends
+        sqrt(z0 power) exp(j phase) (Eq. 4; scalars broadcast); [] removes them."""
+        loops = np.ascontiguousarray(np.atleast_1d(np.asarray(loops, dtype=np.int32)))
+        k = loops.shape[0]
+        pw = np.ascontiguousarray(np.broadcast_to(np.asarray(power, dtype=np.float64), (k,)))
+        ph = np.ascontiguousarray(np.broadcast_to(np.asarray(phase, dtype=np.float64), (k,)))
+        check(self._lib.cosim_plan_set_drive(self._h, k, _host(loops), _host(pw), _host(ph),
+                                             float(z0), _stream()))
+
     def reserve(self, max_batch: int, max_freq: int) -> None:
         check(self._lib.cosim_plan_reserve(self._h, int(max_batch), int(max_freq)))
 

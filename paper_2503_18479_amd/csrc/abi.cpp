@@ -114,9 +114,17 @@ int check_loss_mode(const cosim_plan *p, int loss_mode) {
     if (loss_mode != COSIM_LOSS_MAG && loss_mode != COSIM_LOSS_COMPLEX &&
         loss_mode != COSIM_LOSS_RATIO)
         return fail(COSIM_EINVAL, "unknown loss mode %d", loss_mode);
-    if (loss_mode == COSIM_LOSS_RATIO && !(p->bext_z != 0.0))
-        return fail(COSIM_EINVAL, "the enhancement-factor loss needs a nonzero incident field "
-                                  "(the plan was assembled with bext_z = 0)");
+    if (loss_mode == COSIM_LOSS_RATIO) {
+        if (!(p->bext_z != 0.0))
+            return fail(COSIM_EINVAL, "the enhancement-factor loss needs a nonzero incident field "
+                                      "(the plan was assembled with bext_z = 0)");
+        if (p->component != 2)
+            return fail(COSIM_EINVAL, "the enhancement-factor loss is defined on the z-component "
+                                      "(the uniform incident field has no x or y part)");
+        if (p->n_drive > 0)
+            return fail(COSIM_EINVAL, "the enhancement-factor loss is defined against the uniform "
+                                      "incident field; this plan has a driven port");
+    }
     return COSIM_OK;
 }
 
@@ -373,12 +381,19 @@ int cosim_assemble(cosim_geom_t g, int P, const double *pts_d, double bext_z, vo
 
 int cosim_assemble_ex(cosim_geom_t g, int P, const double *pts_d, double bext_z, int precisions,
                       void *stream, cosim_plan_t *out) {
+    return cosim_assemble_component(g, P, pts_d, bext_z, precisions, 2, stream, out);
+}
+
+int cosim_assemble_component(cosim_geom_t g, int P, const double *pts_d, double bext_z,
+                             int precisions, int component, void *stream, cosim_plan_t *out) {
     if (!out) return fail(COSIM_EINVAL, "out is null");
     *out = nullptr;
     if (!g) return fail(COSIM_EINVAL, "null geometry");
     if (P < 1) return fail(COSIM_EINVAL, "P must be >= 1 (got %d)", P);
     if (!pts_d) return fail(COSIM_EINVAL, "pts_d is null");
     if (!std::isfinite(bext_z)) return fail(COSIM_EINVAL, "bext_z is not finite");
+    if (component < 0 || component > 2)
+        return fail(COSIM_EINVAL, "field component %d is not 0 (x), 1 (y) or 2 (z)", component);
     if (precisions <= 0 || (precisions & ~COSIM_PREC_ALL))
         return fail(COSIM_EINVAL, "precision mask %d is not a non-empty subset of %d", precisions,
                     COSIM_PREC_ALL);
@@ -393,8 +408,13 @@ int cosim_assemble_ex(cosim_geom_t g, int P, const double *pts_d, double bext_z,
     p->P = P;
     p->P_pad = (P + kPTile - 1) / kPTile * kPTile;
     p->bext_z = bext_z;
+    p->component = component;
     p->phi_h.resize(g->n);
     for (int k = 0; k < g->n; ++k) p->phi_h[k] = bext_z * g->area_z[k];
+    p->exc_h.assign(3 * (size_t)g->n, 0.0);
+    std::copy(p->phi_h.begin(), p->phi_h.end(), p->exc_h.begin());
+    p->R_geom = g->R;
+    p->R_h = g->R;
     p->ldl_ok = true;
     for (int k = 0; k < g->n; ++k) p->ldl_ok = p->ldl_ok && g->R[k] > 0.0;
     p->prec_mask = precisions;
@@ -424,7 +444,7 @@ int cosim_assemble_ex(cosim_geom_t g, int P, const double *pts_d, double bext_z,
          (hipMalloc((void **)&p->GThi, gsz * sizeof(uint16_t)) != hipSuccess ||
           hipMalloc((void **)&p->GTlo, gsz * sizeof(uint16_t)) != hipSuccess)) ||
         hipMalloc((void **)&p->M_d, n * n * sizeof(double)) != hipSuccess ||
-        hipMalloc((void **)&p->phi_d, n * sizeof(double)) != hipSuccess ||
+        hipMalloc((void **)&p->phi_d, 3 * n * sizeof(double)) != hipSuccess ||
         hipMalloc((void **)&p->R_d, n * sizeof(double)) != hipSuccess ||
         hipMalloc((void **)&p->T_ratio, (size_t)P * sizeof(double)) != hipSuccess ||
         hipMalloc((void **)&seg_d, (n + 1) * sizeof(int32_t)) != hipSuccess ||
@@ -442,8 +462,8 @@ int cosim_assemble_ex(cosim_geom_t g, int P, const double *pts_d, double bext_z,
     ASM_TRY(hipMemcpyAsync(verts_d, g->verts.data(), 3 * (size_t)g->V * sizeof(double), hipMemcpyHostToDevice, st));
     ASM_TRY(hipMemcpyAsync(wa_d, g->wire_a.data(), n * sizeof(double), hipMemcpyHostToDevice, st));
     ASM_TRY(hipMemcpyAsync(p->R_d, g->R.data(), n * sizeof(double), hipMemcpyHostToDevice, st));
-    ASM_TRY(hipMemcpyAsync(p->phi_d, p->phi_h.data(), n * sizeof(double), hipMemcpyHostToDevice, st));
-    ASM_TRY(launch_assemble_G(g->n, p->NP, P, p->P_pad, seg_d, verts_d, pts_d, p->G64, p->G32,
+    ASM_TRY(hipMemcpyAsync(p->phi_d, p->exc_h.data(), 3 * n * sizeof(double), hipMemcpyHostToDevice, st));
+    ASM_TRY(launch_assemble_G(g->n, p->NP, P, p->P_pad, component, seg_d, verts_d, pts_d, p->G64, p->G32,
                               p->Ghi, p->Glo, p->GThi, p->GTlo, st));
     ASM_TRY(launch_assemble_M(g->n, seg_d, verts_d, wa_d, make_gl_rule(), p->M_d, st));
     p->M_h.resize(n * n);
@@ -525,6 +545,48 @@ int cosim_plan_copy_phi(cosim_plan_t p, double *phi) {
     if (!p) return fail(COSIM_EINVAL, "null plan");
     if (!phi) return fail(COSIM_EINVAL, "phi is null");
     std::memcpy(phi, p->phi_h.data(), p->phi_h.size() * sizeof(double));
+    return COSIM_OK;
+}
+
+int cosim_plan_set_drive(cosim_plan_t p, int nport, const int32_t *loop, const double *power,
+                         const double *phase, double z0, void *stream) {
+    if (!p) return fail(COSIM_EINVAL, "null plan");
+    const int n = p->n;
+    if (nport < 0 || nport > n) return fail(COSIM_EINVAL, "nport %d is not in [0, %d]", nport, n);
+    if (nport > 0 && (!loop || !power)) return fail(COSIM_EINVAL, "loop or power is null");
+    if (nport > 0 && !(std::isfinite(z0) && z0 > 0.0))
+        return fail(COSIM_EINVAL, "z0 must be finite and > 0");
+    std::vector<double> R = p->R_geom, exc(3 * (size_t)n, 0.0);
+    std::copy(p->phi_h.begin(), p->phi_h.end(), exc.begin());
+    std::vector<char> seen(n, 0);
+    for (int i = 0; i < nport; ++i) {
+        const int k = loop[i];
+        if (k < 0 || k >= n) return fail(COSIM_EINVAL, "port %d: loop %d is not in [0, %d)", i, k, n);
+        if (seen[k]) return fail(COSIM_EINVAL, "port %d: loop %d is driven twice", i, k);
+        seen[k] = 1;
+        const double pw = power[i], ph = phase ? phase[i] : 0.0;
+        if (!(std::isfinite(pw) && pw >= 0.0))
+            return fail(COSIM_EINVAL, "port %d: power must be finite and >= 0", i);
+        if (!std::isfinite(ph)) return fail(COSIM_EINVAL, "port %d: phase is not finite", i);
+        // the wave sqrt(z0 P) of Eq. 4 from a source of internal impedance z0:
+        // Thevenin EMF 2 sqrt(z0 P) with z0 in series with the loop
+        const double a = 2.0 * std::sqrt(z0 * pw);
+        R[k] += z0;
+        exc[(size_t)n + k] = a * std::cos(ph);
+        exc[2 * (size_t)n + k] = a * std::sin(ph);
+    }
+    int rc;
+    if ((rc = check_device(p))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(hipMemcpyAsync(p->R_d, R.data(), (size_t)n * sizeof(double), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(p->phi_d, exc.data(), 3 * (size_t)n * sizeof(double),
+                           hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    p->R_h = std::move(R);
+    p->exc_h = std::move(exc);
+    p->n_drive = nport;
+    p->ldl_ok = true;
+    for (int k = 0; k < n; ++k) p->ldl_ok = p->ldl_ok && p->R_h[k] > 0.0;
     return COSIM_OK;
 }
 

@@ -16,12 +16,13 @@ __device__ inline uint16_t bf16_rne(float x) {
 }
 __device__ inline float bf16_to_f(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 
-// z-field per ampere of the straight filament v1 -> v2 at point p.  With
-// a = v1 - p, b = v2 - p:  mu0/(4pi) (a x b)_z (|a|+|b|) / (|a||b| (|a||b| + a.b)).
+// Cartesian component `comp` (0 x, 1 y, 2 z) of the field per ampere of the
+// straight filament v1 -> v2 at point p.  With a = v1 - p, b = v2 - p:
+//   mu0/(4pi) (a x b)_comp (|a|+|b|) / (|a||b| (|a||b| + a.b)).
 // For a.b < 0 the last factor is evaluated as (|a||b| - a.b)/|a x b|^2, its
 // equal that does not cancel beside the filament.
-__device__ inline double bz_filament(double ax, double ay, double az, double la, double bx,
-                                     double by, double bz, double lb) {
+__device__ inline double b_filament(int comp, double ax, double ay, double az, double la,
+                                    double bx, double by, double bz, double lb) {
     double cx = ay * bz - az * by;
     double cy = az * bx - ax * bz;
     double cz = ax * by - ay * bx;
@@ -33,7 +34,8 @@ __device__ inline double bz_filament(double ax, double ay, double az, double la,
     } else {
         inv = (ab - dot) / (cx * cx + cy * cy + cz * cz);
     }
-    return cz * (la + lb) * inv / ab;
+    const double cc = comp == 2 ? cz : comp == 1 ? cy : cx;
+    return cc * (la + lb) * inv / ab;
 }
 
 // Block: 64 points x 4 waves.  Wave w evaluates loops w, w+4, ... for the 64
@@ -45,7 +47,7 @@ __device__ inline double bz_filament(double ax, double ay, double az, double la,
 constexpr int kGPts = 64;
 constexpr int kGLoops = 64;
 
-__global__ __launch_bounds__(256) void k_assemble_G(int n, int NP, int P, int P_pad,
+__global__ __launch_bounds__(256) void k_assemble_G(int n, int NP, int P, int P_pad, int comp,
                                                     const int32_t *__restrict__ seg_off,
                                                     const double *__restrict__ verts,
                                                     const double *__restrict__ pts,
@@ -88,7 +90,7 @@ __global__ __launch_bounds__(256) void k_assemble_G(int n, int NP, int P, int P_
                     } else {  // closing segment back to the first vertex
                         bx = fx; by = fy; bz = fz; lb = fl;
                     }
-                    acc += bz_filament(ax, ay, az, la, bx, by, bz, lb);
+                    acc += b_filament(comp, ax, ay, az, la, bx, by, bz, lb);
                     ax = bx; ay = by; az = bz; la = lb;
                 }
                 acc *= kMu0Over4Pi;
@@ -258,12 +260,12 @@ __global__ __launch_bounds__(256) void k_assemble_M(int n, const int32_t *__rest
 
 }  // namespace
 
-hipError_t launch_assemble_G(int n, int NP, int P, int P_pad, const int32_t *seg_off_d,
+hipError_t launch_assemble_G(int n, int NP, int P, int P_pad, int comp, const int32_t *seg_off_d,
                              const double *verts_d, const double *pts_d, double *G64,
                              float *G32, uint16_t *Ghi, uint16_t *Glo, uint16_t *GThi,
                              uint16_t *GTlo, hipStream_t st) {
     const int blocks = (P_pad + kGPts - 1) / kGPts;
-    hipLaunchKernelGGL(k_assemble_G, dim3(blocks), dim3(256), 0, st, n, NP, P, P_pad, seg_off_d,
+    hipLaunchKernelGGL(k_assemble_G, dim3(blocks), dim3(256), 0, st, n, NP, P, P_pad, comp, seg_off_d,
                        verts_d, pts_d, G64, G32, Ghi, Glo, GThi, GTlo);
     return hipGetLastError();
 }

@@ -25,6 +25,14 @@ struct GLRule {
     double w[kGLOrder];  // weights
 };
 
+// Loop excitation on the device, [3][n] doubles: the flux Phi_k of the
+// uniform incident field, then Re and Im of a source EMF E_k in series with
+// the loop (a driven port; zero elsewhere).  The loop voltage is
+// V_k = E_k - j w Phi_k.
+__device__ inline double2 loop_voltage(const double *exc, int n, int k, double w) {
+    return make_double2(exc[n + k], exc[2 * n + k] - w * exc[k]);
+}
+
 // Matrix-core precision of the superposition (mirrors cosim_precision).
 enum class Prec { F64 = 0, F32 = 1, BF16X3 = 2 };
 
@@ -43,7 +51,7 @@ constexpr int kBigRows = 2048;      // P-chunk of the adjoint GEMMs above 64 loo
 // ---------------------------------------------------------------------------
 // kernel launchers (implemented in the .hip files); all return hipError_t
 // ---------------------------------------------------------------------------
-hipError_t launch_assemble_G(int n, int NP, int P, int P_pad, const int32_t *seg_off_d,
+hipError_t launch_assemble_G(int n, int NP, int P, int P_pad, int comp, const int32_t *seg_off_d,
                              const double *verts_d, const double *pts_d, double *G64,
                              float *G32, uint16_t *Ghi, uint16_t *Glo, uint16_t *GThi,
                              uint16_t *GTlo, hipStream_t st);
@@ -269,14 +277,20 @@ struct cosim_plan {
     int device = 0;
     int n = 0, NP = 0, P = 0, P_pad = 0;
     double bext_z = 0.0;
+    int component = 2;          // Cartesian component of the field that G holds (0 x, 1 y, 2 z)
+    int n_drive = 0;            // loops with a source EMF (cosim_plan_set_drive)
     double *T_ratio = nullptr;  // [P] targets beta |bext_z| of the enhancement-factor loss
     std::vector<double> M_h, phi_h;
+    std::vector<double> R_geom;  // series resistances of the geometry (without port impedances)
+    std::vector<double> R_h;     // what R_d holds
+    std::vector<double> exc_h;   // what phi_d holds: [3][n], see loop_voltage
     // operators (device)
     double *G64 = nullptr;
     float *G32 = nullptr;
     uint16_t *Ghi = nullptr, *Glo = nullptr;
     uint16_t *GThi = nullptr, *GTlo = nullptr;  // transposed copies [NP][P_pad]
-    double *M_d = nullptr, *phi_d = nullptr, *R_d = nullptr;
+    double *M_d = nullptr, *R_d = nullptr;
+    double *phi_d = nullptr;  // [3][n] loop excitation, see loop_voltage
     // workspace (device)
     size_t cap_systems = 0;
     int cap_chunks = 0;

@@ -150,7 +150,7 @@ __global__ __launch_bounds__(GJShape<NP>::BLOCK) void k_gj(
             if (i < n) {
                 const double c = Cb[i];
                 if (tj == 0) {
-                    if (!isfinite(c) || c == 0.0 || !isfinite(w) || w == 0.0) flag |= COSIM_SYS_BAD_INPUT;
+                    if (isnan(c) || c == 0.0 || !isfinite(w) || w == 0.0) flag |= COSIM_SYS_BAD_INPUT;
                     else if (c < 0.0) flag |= COSIM_SYS_NEGATIVE_C;
                 }
                 dre = Rv[i];
@@ -174,7 +174,7 @@ __global__ __launch_bounds__(GJShape<NP>::BLOCK) void k_gj(
             rhs[r] = make_double2(0.0, 0.0);
             if (tj == tb && i < n) {
                 if (!ADJ) {
-                    rhs[r] = make_double2(0.0, -w * phi[i]);
+                    rhs[r] = loop_voltage(phi, n, i, w);
                 } else {
                     double rr = 0.0, ri = 0.0;
                     for (int c = 0; c < nchunk; ++c) {
@@ -565,7 +565,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     float zdiag = 0.0f;
     if (lane < n) {
         const double c = Cb[lane];
-        if (!isfinite(c) || c == 0.0 || !isfinite(w) || w == 0.0) flag = COSIM_SYS_BAD_INPUT;
+        if (isnan(c) || c == 0.0 || !isfinite(w) || w == 0.0) flag = COSIM_SYS_BAD_INPUT;
         else if (c < 0.0) flag = COSIM_SYS_NEGATIVE_C;
         zdiag = (float)(fabs(Rv[lane]) + fabs(w * M[(size_t)lane * n + lane] - 1.0 / (w * c)));
     }
@@ -575,9 +575,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         zdiag = fmaxf(zdiag, __shfl_xor(zdiag, off));
     }
     double dmin = __builtin_inf();
-    // right-hand side b = -j w Phi (lane i holds b_i), turned into y = L^-1 b
+    // right-hand side b = E - j w Phi (lane i holds b_i), turned into y = L^-1 b
     // column by column as L is formed; dl = D_i^-1 of the lane's own column
-    double2 y = make_double2(0.0, lane < n ? -w * phi[lane] : 0.0);
+    double2 y = lane < n ? loop_voltage(phi, n, lane, w) : make_double2(0.0, 0.0);
     double2 dl = make_double2(1.0, 0.0);
 
     double2 (*pan)[5] = sPan[wv];

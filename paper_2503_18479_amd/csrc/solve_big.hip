@@ -113,7 +113,7 @@ __global__ __launch_bounds__(kTB) void k_lu_big(int n, int NP, int S, int F,
     __syncthreads();
     for (int k = tid; k < n; k += kTB) {
         const double c = Cb[k];
-        if (!isfinite(c) || c == 0.0 || !isfinite(w) || w == 0.0) atomicOr(&sFlag, COSIM_SYS_BAD_INPUT);
+        if (isnan(c) || c == 0.0 || !isfinite(w) || w == 0.0) atomicOr(&sFlag, COSIM_SYS_BAD_INPUT);
         else if (c < 0.0) atomicOr(&sFlag, COSIM_SYS_NEGATIVE_C);
     }
     // Z = diag(R) + j w M + diag(1/(j w C)), identity padding
@@ -239,7 +239,7 @@ __global__ __launch_bounds__(kTB) void k_big_assemble(int n, int NP, int S, int 
     const bool first = blockIdx.y == 0;
     for (int k = tid; first && k < n; k += kTB) {
         const double c = Cb[k];
-        if (!isfinite(c) || c == 0.0 || !isfinite(w) || w == 0.0) atomicOr(&sFlag, COSIM_SYS_BAD_INPUT);
+        if (isnan(c) || c == 0.0 || !isfinite(w) || w == 0.0) atomicOr(&sFlag, COSIM_SYS_BAD_INPUT);
         else if (c < 0.0) atomicOr(&sFlag, COSIM_SYS_NEGATIVE_C);
         zm = fmax(zm, fabs(Rv[k]) + fabs(w * M[(size_t)k * n + k] - 1.0 / (w * c)));
     }
@@ -525,7 +525,7 @@ __global__ __launch_bounds__(kTB) void k_lu_solve(int n, int NP, int S, int F,
         double2 x = make_double2(0.0, 0.0);
         if (k < n) {
             if (RHS == kRhsExcitation) {
-                x = make_double2(0.0, -w * phi[k]);
+                x = loop_voltage(phi, n, k, w);
             } else {
                 double rr = 0.0, ri = 0.0;
                 for (int c = 0; c < nchunk; ++c) {

@@ -222,3 +222,17 @@ def test_parameter_calls_argument_errors(lib):
     assert lib.cosim_clip(4, fake, 2.0, 1.0, None) == EINVAL
     assert lib.cosim_clip(-1, fake, 0.0, 1.0, None) == EINVAL
     assert lib.cosim_clip(0, None, 0.0, 1.0, None) == 0
+
+
+def test_component_and_drive_argument_errors(lib):
+    fake = ctypes.c_void_p(0x1000)
+    h = ctypes.c_void_p()
+    rc, g = _create(lib, 2, *_geom_args())
+    assert rc == 0
+    for comp in (-1, 3):
+        assert lib.cosim_assemble_component(g, 4, fake, 1e-6, 7, comp, None, ctypes.byref(h)) == EINVAL
+        assert not h.value
+    lib.cosim_geometry_destroy(g)
+    one = np.array([0], dtype=np.int32)
+    pw = np.array([1.0])
+    assert lib.cosim_plan_set_drive(None, 1, one.ctypes.data, pw.ctypes.data, None, 50.0, None) == EINVAL

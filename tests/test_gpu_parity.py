@@ -847,3 +847,168 @@ def test_ratio_loss_needs_an_incident_field(dev):
     C = torch.tensor(wl.C, device=dev); om = torch.tensor(wl.omega, device=dev)
     with pytest.raises(CosimError):
         plan.loss_and_grad(C, om, torch.ones(wl.P, dtype=torch.float64, device=dev), loss_mode=2)
+
+
+# --------------------------------------- field components (Sec. I-B: B_x, B_y)
+
+@functools.lru_cache(maxsize=None)
+def _component_plan(name, comp):
+    from paper_2503_18479_amd import Plan
+    c = _case(name)
+    g = c.wl.geom
+    return Plan(c.geom, c.pts, c.wl.bext_z, component=comp), O.field_matrix(g.verts, g.seg_off, c.wl.pts, comp)
+
+
+@pytest.mark.parametrize("comp", [0, 1])
+@pytest.mark.parametrize("name", ["n25", "circle", "n81"])
+def test_field_component_matches_oracle(dev, name, comp):
+    """G of B_x / B_y, the field from the solved currents, and the loss and
+    dL/dC on that component in every precision."""
+    c = _case(name)
+    plan, Gc = _component_plan(name, comp)
+    _say(f"[component] {name} comp={comp}")
+    assert _nrel(plan.G().cpu().numpy(), Gc) < 1e-12
+    g = c.wl.geom
+    I, st = plan.solve(c.C, c.om)
+    B = plan.field(I).cpu().numpy()
+    Ir = O.currents(c.M, g.R, c.Phi, c.wl.C, c.wl.omega)
+    assert _nrel(B, O.field(Gc, Ir)) < 1e-10
+    T = 0.7 * np.abs(O.field(Gc, Ir)).mean(axis=(0, 1))   # any magnitudes will do
+    Tt = torch.tensor(T, device=dev)
+    Lr = O.evaluate(Gc, c.M, g.R, c.Phi, c.wl.C, c.wl.omega, T)[2]
+    gr = O.grad_adjoint(Gc, c.M, g.R, c.Phi, c.wl.C, c.wl.omega, T)
+    for prec in (0, 1, 2):
+        loss, grad, st = plan.loss_and_grad(c.C, c.om, Tt, precision=prec)
+        torch.cuda.synchronize()
+        assert int(st.abs().sum()) == 0
+        el = np.max(np.abs(loss.cpu().numpy() - Lr) / Lr)
+        eg = np.max(_nrel(grad.cpu().numpy(), gr, axis=1))
+        _say(f"  prec={prec}: loss {el:.2e} grad {eg:.2e}")
+        assert el < TOL[prec] and eg < TOL[prec]
+
+
+def test_ratio_loss_needs_the_z_component(dev):
+    from paper_2503_18479_amd import CosimError
+    c = _case("n25")
+    plan, _ = _component_plan("n25", 0)
+    with pytest.raises(CosimError):
+        plan.loss_and_grad(c.C, c.om, torch.ones_like(c.T), loss_mode=2)
+
+
+# -------------------------------------------- drive port (Sec. IV-A, Eq. 4)
+
+class DriveCase:
+    """An array with an excitation coil as its last loop, driven through a
+    50 ohm port with 1 W; the coil has no capacitor (C = +inf)."""
+
+    def __init__(self, geom, pts, batch, freqs, bext, seed, dev, phase=0.4, array_M=False):
+        from paper_2503_18479_amd import Geometry, Plan
+        self.g = geom
+        rng = np.random.default_rng([7, seed])
+        n = geom.n
+        self.n = n
+        self.pts_h = pts
+        self.omega = 2 * np.pi * np.asarray(freqs, float)
+        C = rng.uniform(20e-12, 150e-12, (batch, n))
+        C[:, -1] = np.inf
+        self.C_h = C
+        self.G = O.field_matrix(geom.verts, geom.seg_off, pts)
+        self.M = O.inductance_matrix_fast(geom.verts, geom.seg_off, geom.wire_a)
+        self.Phi = O.flux(geom.verts, geom.seg_off, bext)
+        self.R = geom.R.copy(); self.R[-1] += 50.0
+        self.emf = np.zeros(n, complex); self.emf[-1] = O.drive_emf(1.0, 50.0, phase)
+        I = O.currents(self.M, self.R, self.Phi, C[:1], self.omega[:1], self.emf)
+        self.T_h = 0.8 * np.abs(O.field(self.G, I))[0, 0] + 1e-7 * rng.uniform(size=len(pts))
+        self.plan = Plan(Geometry.from_workload(geom), torch.tensor(pts, device=dev), bext)
+        self.plan.set_drive([n - 1], power=1.0, phase=phase, z0=50.0)
+        self.C = torch.tensor(C, device=dev)
+        self.om = torch.tensor(self.omega, device=dev)
+        self.T = torch.tensor(self.T_h, device=dev)
+
+    def args(self):
+        return self.G, self.M, self.R, self.Phi, self.C_h, self.omega, self.T_h
+
+
+@functools.lru_cache(maxsize=None)
+def _drive(name):
+    dev = torch.device("cuda:0")
+    if name == "drive1":   # single cell r = 30 mm and its coil (Sec. IV-A): NP = 32
+        geom = W.with_drive_coil(W.single_circle(0.03, 64, 1e-3, 0.5), radius=0.0445, z=0.01)
+        return DriveCase(geom, W.grid_points(13, 0.08, [-0.0224]), 6, [123.5e6, 128e6], 0.0, 1, dev)
+    if name == "drive9":   # 3x3 array, coil and a uniform incident field together
+        geom = W.with_drive_coil(W.square_array(3, 3, 0.03, 0.035, 16), radius=0.06, z=0.015)
+        return DriveCase(geom, W.grid_points(15, 0.1, [0.01]), 4, [118e6, 128e6, 138e6], 1e-6, 2,
+                         dev, phase=1.1)
+    if name == "drive81":  # 9x9 array and a square coil: 82 loops, the large-loop path
+        geom = W.with_drive_coil(W.square_array(9, 9, 0.03, 0.035, 32), radius=0.17, z=0.02,
+                                 square=True)
+        return DriveCase(geom, W.grid_points(40, 0.3, [0.01]), 3, [123.5e6, 128e6], 0.0, 3, dev)
+    raise KeyError(name)
+
+
+DRIVES = ["drive1", "drive9", "drive81"]
+
+
+@pytest.mark.parametrize("name", DRIVES)
+def test_drive_solve_matches_oracle(dev, name):
+    d = _drive(name)
+    _say(f"[drive solve] {name}")
+    I, st = d.plan.solve(d.C, d.om)
+    torch.cuda.synchronize()
+    assert int(st.abs().sum()) == 0
+    Ir = O.currents(d.M, d.R, d.Phi, d.C_h, d.omega, d.emf)
+    assert np.max(_nrel(I.cpu().numpy(), Ir, axis=2)) < 1e-10
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("name", DRIVES)
+def test_drive_loss_and_grad_matches_oracle(dev, name, prec):
+    d = _drive(name)
+    _say(f"[drive loss] {name} prec={prec}")
+    loss, grad, st = d.plan.loss_and_grad(d.C, d.om, d.T, precision=prec)
+    torch.cuda.synchronize()
+    assert int(st.abs().sum()) == 0
+    Lr = O.evaluate(*d.args(), emf=d.emf)[2]
+    gr = O.grad_adjoint(*d.args(), emf=d.emf)
+    g = grad.cpu().numpy()
+    assert np.all(g[:, -1] == 0.0)       # the coil has no capacitor
+    assert np.max(np.abs(loss.cpu().numpy() - Lr) / Lr) < TOL[prec]
+    assert np.max(_nrel(g, gr, axis=1)) < TOL[prec]
+
+
+@pytest.mark.parametrize("name", DRIVES)
+def test_drive_parameter_gradients_match_oracle(dev, name):
+    d = _drive(name)
+    _say(f"[drive params] {name}")
+    loss, gC, gR, gL, gw, st = d.plan.loss_and_grad_params(d.C, d.om, d.T, precision=0)
+    torch.cuda.synchronize()
+    assert int(st.abs().sum()) == 0
+    rR, rL, rw = O.grad_params_adjoint(*d.args(), emf=d.emf)
+    assert np.max(_nrel(gR.cpu().numpy(), rR, axis=1)) < 1e-9
+    assert np.max(_nrel(gL.cpu().numpy(), rL, axis=1)) < 1e-9
+    assert np.max(_nrel(gw.cpu().numpy(), rw, axis=1)) < 1e-9
+
+
+def test_drive_ports_replace_and_clear(dev):
+    """set_drive replaces the port set; an empty set restores the plan."""
+    from paper_2503_18479_amd import CosimError
+    d = _drive("drive9")
+    d.plan.set_drive([d.n - 1], power=4.0, phase=1.1)     # 4 W: twice the EMF
+    I4, _ = d.plan.solve(d.C, d.om)
+    d.plan.set_drive([])
+    Ic, _ = d.plan.solve(d.C, d.om)
+    d.plan.set_drive([d.n - 1], power=1.0, phase=1.1)     # back to the case's ports
+    torch.cuda.synchronize()
+    R0 = d.g.R.copy()
+    Ir4 = O.currents(d.M, d.R, d.Phi, d.C_h, d.omega, 2.0 * d.emf)
+    assert np.max(_nrel(I4.cpu().numpy(), Ir4, axis=2)) < 1e-10
+    # without ports the coil has R = 0 and, with C = inf, no impedance but
+    # j w L: the flux still drives it
+    Ic_ref = O.currents(d.M, R0, d.Phi, d.C_h, d.omega)
+    assert np.max(_nrel(Ic.cpu().numpy(), Ic_ref, axis=2)) < 1e-10
+    with pytest.raises(CosimError):
+        d.plan.set_drive([0, 0])
+    with pytest.raises(CosimError):
+        d.plan.set_drive([d.n])
+    with pytest.raises(CosimError):
+        d.plan.loss_and_grad(d.C, d.om, torch.ones_like(d.T), loss_mode=2)

@@ -286,12 +286,15 @@ def small_array(nx: int, ny: int, batch: int, grid: int, n_freq: int = 3,
 
 
 def with_drive_coil(g: Geometry, radius: float = 0.0445, z: float = 0.02, n_seg: int = 64,
-                    wire_a: float = 0.5e-3) -> Geometry:
-    """g plus one coaxial circular excitation coil, appended as the last loop
-    (a perfect conductor: R = 0; its port is described separately).  The
-    default is a 1 mm wire on a 45 mm outer radius, as in the single-cell
-    setup of Sec. IV-A, at an axial offset z (the paper gives none)."""
-    loops = [g.loop(k) for k in range(g.n)] + [regular_polygon(radius, n_seg, (0.0, 0.0, z))]
+                    wire_a: float = 0.5e-3, square: bool = False) -> Geometry:
+    """g plus one coaxial excitation coil, appended as the last loop (a
+    perfect conductor: R = 0; its port is described separately).  The
+    default is a circular 1 mm wire on a 45 mm outer radius, as in the
+    single-cell setup of Sec. IV-A, at an axial offset z (the paper gives
+    none); `square` makes it a square of side 2 radius instead."""
+    coil = (square_loop(2.0 * radius, n_seg, (0.0, 0.0, z)) if square
+            else regular_polygon(radius, n_seg, (0.0, 0.0, z)))
+    loops = [g.loop(k) for k in range(g.n)] + [coil]
     wa = np.concatenate([g.wire_a, [wire_a]])
     rr = np.concatenate([g.R, [0.0]])
     return _pack(loops, wa, rr, g.nx, g.ny, g.pitch)
