@@ -177,6 +177,28 @@ int cosim_plan_set_drive(cosim_plan_t p, int nport, const int32_t *loop, const d
                          const double *phase, double z0, void *stream);
 
 /* --------------------------------------------------------------------------
+ * FP32 factorisation with FP64 iterative refinement for plans of more than
+ * 64 loops whose every series resistance is > 0 (the blocked LDL^T path; the
+ * pivoted paths and plans of up to 64 loops stay FP64 and ignore this).
+ * With enable != 0 every call that solves (cosim_solve, cosim_field_backward,
+ * cosim_loss_and_grad and cosim_loss_and_grad_params, forward and adjoint)
+ * factors Z in complex64 on FP32 matrix cores and refines each solution in
+ * FP64: x = F^-1 b, then r = b - Z x with Z formed in FP64 from M, R, C and
+ * w, x += F^-1 r, until the error left (estimated from the geometric
+ * shrinking of the corrections) is at most tol |x| in the max norm.  A system
+ * that is not done after max_iter steps (or whose FP32 pivot is small) gets
+ * the pivoted FP64 factorisation instead, so results keep the accuracy of
+ * the FP64 path whatever the conditioning.
+ *   max_iter 1..64; tol in [0, 1): 0 chooses it from the precision of the
+ *   call's contraction (FP64 1e-12, FP32 1e-9, BF16X3 1e-7; cosim_solve and
+ *   cosim_field_backward 1e-12).
+ * Changing the mode frees the plan's workspace (the next call allocates an
+ * extra 8 NP^2 bytes per system for the FP32 factor); it waits for the device
+ * first.  HIP graphs captured before hold the freed addresses and must be
+ * captured again.  Errors: COSIM_EINVAL. */
+int cosim_plan_set_refinement(cosim_plan_t p, int enable, int max_iter, double tol);
+
+/* --------------------------------------------------------------------------
  * Currents (Eq. 6 in impedance form).  For every configuration b < B and
  * frequency f < F solves
  *     (diag(R) + j w_f M + diag(1/(j w_f C_b))) I_{b,f} = E - j w_f Phi

@@ -40,6 +40,7 @@ SIGNATURES = {
                                          P(c_void_p)]),
     "cosim_plan_set_drive": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_double,
                                      c_void_p]),
+    "cosim_plan_set_refinement": (c_int, [c_void_p, c_int, c_int, c_double]),
     "cosim_loss_and_grad_many": (c_int, [c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                          c_void_p, c_int, c_int, c_void_p, c_void_p, c_void_p,
                                          c_void_p]),

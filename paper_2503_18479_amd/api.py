@@ -128,6 +128,12 @@ class Plan:
         check(self._lib.cosim_plan_set_drive(self._h, k, _host(loops), _host(pw), _host(ph),
                                              float(z0), _stream()))
 
+    def set_refinement(self, enable: bool = True, max_iter: int = 8, tol: float = 0.0) -> None:
+        """FP32 factorisation with FP64 refinement above 64 loops
+        (cosim_plan_set_refinement); tol 0 chooses it per precision."""
+        check(self._lib.cosim_plan_set_refinement(self._h, int(bool(enable)), int(max_iter),
+                                                  float(tol)))
+
     def reserve(self, max_batch: int, max_freq: int) -> None:
         check(self._lib.cosim_plan_reserve(self._h, int(max_batch), int(max_freq)))
 

@@ -87,6 +87,7 @@ void plan_free_workspace(cosim_plan *p) {
     dfree(p->bWt);
     dfree(p->bZmax);
     dfree(p->bTinv);
+    dfree(p->bA32);
     dfree(p->I_ws);
     dfree(p->rpart);
     dfree(p->lpart);
@@ -97,6 +98,21 @@ void plan_free_workspace(cosim_plan *p) {
     dfree(p->fac.fmt);
     p->cap_systems = 0;
     p->cap_chunks = 0;
+}
+
+// FP32 records with FP64 refinement when the plan asks for them and the
+// blocked LDL^T applies.  The default tolerance follows the precision of the
+// contraction that consumes the solution: well below its own error.
+BigRefine big_refine_args(const cosim_plan *p, int precision) {
+    BigRefine rf;
+    rf.on = p->refine && p->ldl_ok && big_plan(p->NP);
+    rf.A32 = p->bA32;
+    rf.max_iter = p->refine_iter;
+    rf.tol = p->refine_tol > 0.0            ? p->refine_tol
+             : precision == COSIM_FP64      ? 1e-12
+             : precision == COSIM_FP32      ? 1e-9
+                                            : 1e-7;
+    return rf;
 }
 
 // The blocked LDL^T above 64 loops when every R_k > 0, else pivoted LU.
@@ -161,6 +177,12 @@ int ensure_workspace(cosim_plan *p, size_t systems, int chunks) {
         plan_free_workspace(p);
         (void)hipGetLastError();
         return fail(COSIM_ENOMEM, "LDL^T panel workspace for %zu systems failed", ns);
+    }
+    if (big && p->ldl_ok && p->refine &&
+        hipMalloc(&p->bA32, ns * NP * NP * sizeof(float2)) != hipSuccess) {
+        plan_free_workspace(p);
+        (void)hipGetLastError();
+        return fail(COSIM_ENOMEM, "FP32 factor workspace for %zu systems failed", ns);
     }
     if (hipMalloc((void **)&p->I_ws, ns * n * sizeof(double2)) != hipSuccess ||
         hipMalloc((void **)&p->rpart, (size_t)nc * ns * NP * sizeof(double2)) != hipSuccess ||
@@ -585,8 +607,30 @@ int cosim_plan_set_drive(cosim_plan_t p, int nport, const int32_t *loop, const d
     p->R_h = std::move(R);
     p->exc_h = std::move(exc);
     p->n_drive = nport;
+    const bool was = p->ldl_ok;
     p->ldl_ok = true;
     for (int k = 0; k < n; ++k) p->ldl_ok = p->ldl_ok && p->R_h[k] > 0.0;
+    // the blocked LDL^T workspace exists only for plans that can use it
+    if (p->ldl_ok != was) plan_free_workspace(p);
+    return COSIM_OK;
+}
+
+int cosim_plan_set_refinement(cosim_plan_t p, int enable, int max_iter, double tol) {
+    if (!p) return fail(COSIM_EINVAL, "null plan");
+    if (enable && (max_iter < 1 || max_iter > 64))
+        return fail(COSIM_EINVAL, "max_iter %d is not in [1, 64]", max_iter);
+    if (enable && !(tol >= 0.0 && tol < 1.0))
+        return fail(COSIM_EINVAL, "tol must be in [0, 1) (0: chosen per precision)");
+    int rc;
+    if ((rc = check_device(p))) return rc;
+    const bool on = enable != 0;
+    if (on != p->refine) {
+        HIP_TRY(hipDeviceSynchronize());  // no call of this plan may still use the workspace
+        plan_free_workspace(p);           // the next call allocates what the mode needs
+    }
+    p->refine = on;
+    p->refine_iter = on ? max_iter : 0;
+    p->refine_tol = on ? tol : 0.0;
     return COSIM_OK;
 }
 
@@ -601,11 +645,13 @@ int cosim_solve(cosim_plan_t p, int B, int F, const double *C_d, const double *o
     if (big_plan(p->NP)) {
         if ((rc = ensure_workspace(p, (size_t)S, 1))) return rc;
         hipStream_t st = (hipStream_t)stream;
-        HIP_TRY(big_factor(big_factor_args(p), p->NP, p->n, S, F, p->M_d, p->R_d,
-                           C_d, omega_d, p->fac.L, p->fac.piv_row, status_d, st));
-        HIP_TRY(launch_lu_solve(p->NP, p->n, S, F, p->fac.L, p->fac.piv_row, p->phi_d, C_d,
-                                omega_d, (double2 *)I_d, kRhsExcitation, nullptr, 0, 0.0, nullptr,
-                                status_d, st));
+        const BigFactor bf = big_factor_args(p);
+        const BigRefine rf = big_refine_args(p, COSIM_FP64);
+        HIP_TRY(big_factor(bf, rf, p->NP, p->n, S, F, p->M_d, p->R_d, C_d, omega_d, p->fac.L,
+                           p->fac.piv_row, status_d, st));
+        HIP_TRY(big_solve(bf, rf, p->NP, p->n, S, F, p->M_d, p->R_d, p->phi_d, C_d, omega_d,
+                          p->fac.L, p->fac.piv_row, (double2 *)I_d, kRhsExcitation, nullptr, 0,
+                          0.0, nullptr, status_d, st));
         return COSIM_OK;
     }
     HIP_TRY(launch_solve_forward(p->NP, p->n, S, F, p->M_d, p->R_d, p->phi_d, C_d, omega_d,
@@ -653,11 +699,13 @@ int cosim_field_backward(cosim_plan_t p, int B, int F, const double *C_d, const 
         HIP_TRY(launch_pack_w64(p->P, p->P_pad, (int)S, (const double2 *)gBz_d, (double *)p->bW, st));
         BigArgs a = big_args(p, Prec::F64, (int)S, nchunk, nullptr, nullptr);
         HIP_TRY(big_adjoint(p->blas, Prec::F64, a, st));
-        HIP_TRY(big_factor(big_factor_args(p), p->NP, p->n, (int)S, F, p->M_d, p->R_d,
-                           C_d, omega_d, p->fac.L, p->fac.piv_row, status_d, st));
-        HIP_TRY(launch_lu_solve(p->NP, p->n, (int)S, F, p->fac.L, p->fac.piv_row, p->phi_d, C_d,
-                                omega_d, (double2 *)I_d, kRhsPlanarF64, p->rpart, nchunk, 0.5,
-                                p->gsys, status_d, st));
+        const BigFactor bf = big_factor_args(p);
+        const BigRefine rf = big_refine_args(p, COSIM_FP64);
+        HIP_TRY(big_factor(bf, rf, p->NP, p->n, (int)S, F, p->M_d, p->R_d, C_d, omega_d,
+                           p->fac.L, p->fac.piv_row, status_d, st));
+        HIP_TRY(big_solve(bf, rf, p->NP, p->n, (int)S, F, p->M_d, p->R_d, p->phi_d, C_d, omega_d,
+                          p->fac.L, p->fac.piv_row, (double2 *)I_d, kRhsPlanarF64, p->rpart,
+                          nchunk, 0.5, p->gsys, status_d, st));
         HIP_TRY(launch_reduce(p->n, B, F, 0, p->gsys, nullptr, 0.0, gC_d, nullptr, st));
         return COSIM_OK;
     }
@@ -711,22 +759,24 @@ static int loss_and_grad_impl(cosim_plan_t p, int B, int F, const double *C_d, c
         scale /= p->bext_z * p->bext_z;
     }
     if (big_plan(p->NP)) {
-        // pivoted LU, GEMM contractions with the loss epilogue between, LU solve
-        HIP_TRY(big_factor(big_factor_args(p), p->NP, p->n, (int)S, F, p->M_d, p->R_d,
-                           C_d, omega_d, p->fac.L, p->fac.piv_row, status_d, st));
-        HIP_TRY(launch_lu_solve(p->NP, p->n, (int)S, F, p->fac.L, p->fac.piv_row, p->phi_d, C_d,
-                                omega_d, p->I_ws, kRhsExcitation, nullptr, 0, 0.0, nullptr,
-                                status_d, st));
+        // factor, GEMM contractions with the loss epilogue between, solves
+        const BigFactor bf = big_factor_args(p);
+        const BigRefine rf = big_refine_args(p, precision);
+        HIP_TRY(big_factor(bf, rf, p->NP, p->n, (int)S, F, p->M_d, p->R_d, C_d, omega_d,
+                           p->fac.L, p->fac.piv_row, status_d, st));
+        HIP_TRY(big_solve(bf, rf, p->NP, p->n, (int)S, F, p->M_d, p->R_d, p->phi_d, C_d, omega_d,
+                          p->fac.L, p->fac.piv_row, p->I_ws, kRhsExcitation, nullptr, 0, 0.0,
+                          nullptr, status_d, st));
         if (ev) HIP_TRY(hipEventRecord(ev[1], st));
         BigArgs a = big_args(p, prec, (int)S, nchunk, p->I_ws, T_d);
         a.inc = ratio ? p->bext_z : 0.0;
         HIP_TRY(big_contract(p->blas, prec, loss_mode, grad, a, st));
         if (ev) HIP_TRY(hipEventRecord(ev[2], st));
         if (grad)
-            HIP_TRY(launch_lu_solve(p->NP, p->n, (int)S, F, p->fac.L, p->fac.piv_row, p->phi_d,
-                                    C_d, omega_d, p->I_ws,
-                                    prec == Prec::F64 ? kRhsPlanarF64 : kRhsPlanarF32, p->rpart,
-                                    nchunk, scale, p->gsys, status_d, st, mu));
+            HIP_TRY(big_solve(bf, rf, p->NP, p->n, (int)S, F, p->M_d, p->R_d, p->phi_d, C_d,
+                              omega_d, p->fac.L, p->fac.piv_row, p->I_ws,
+                              prec == Prec::F64 ? kRhsPlanarF64 : kRhsPlanarF32, p->rpart,
+                              nchunk, scale, p->gsys, status_d, st, mu));
         if (ev) HIP_TRY(hipEventRecord(ev[3], st));
         HIP_TRY(launch_reduce(p->n, B, F, nchunk, grad ? p->gsys : nullptr, p->lpart, scale,
                               grad_d, loss_d, st));

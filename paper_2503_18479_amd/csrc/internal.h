@@ -73,6 +73,9 @@ struct GJFactor {
     int *fmt = nullptr;
 };
 constexpr int kFmtLDL = 0, kFmtGJ = 1, kFmtNeedsPivot = 2;
+// above 64 loops with refinement on: the FP32 record did not converge in the
+// forward (or only in the adjoint) solve, so the system holds a pivoted FP64 record
+constexpr int kFmtRefineFailed = 3, kFmtRefineFailedAdj = 4;
 // first element of column k in the packed LDL^T record (columns of NP - 1 - k)
 __host__ __device__ constexpr int ldl_col(int NP, int k) { return k * (2 * NP - k - 1) / 2; }
 constexpr int kFlagPivot = 1 << 16;  // kernel-internal status bit, never returned
@@ -166,12 +169,29 @@ struct BigFactor {
     double2 *wt = nullptr;    // [S][64][NP] L21 of the current panel, column-major
     double2 *tinv = nullptr;  // [S][64][64] L11^-T of the current panel
 };
-// Factor of the S systems in the launch_lu_solve format: blocked LDL^T with
-// pivoted LU for the marked systems when bf.ldl, else pivoted LU throughout.
-hipError_t big_factor(const BigFactor &bf, int NP, int n, int S, int F,
+// FP32 factorisation with FP64 iterative refinement (above 64 loops, every
+// R_k > 0): the blocked LDL^T runs on a complex64 record A32 [S][NP][NP].
+struct BigRefine {
+    bool on = false;
+    void *A32 = nullptr;  // float2 [S][NP][NP]
+    int max_iter = 0;     // refinement steps before the FP64 fallback
+    double tol = 0.0;     // estimated relative error at which a system is done
+};
+// Factor of the S systems: blocked LDL^T (in FP32 into rf.A32 when rf.on) with
+// pivoted FP64 LU into A_d for the marked systems when bf.ldl, else pivoted
+// LU throughout.
+hipError_t big_factor(const BigFactor &bf, const BigRefine &rf, int NP, int n, int S, int F,
                       const double *M_d, const double *R_d, const double *C_d,
                       const double *omega_d, double2 *A_d, int *piv_d, int32_t *status_d,
                       hipStream_t st);
+// Solves with the records big_factor left (arguments as launch_lu_solve): the
+// FP64 records directly; with refinement, the FP32 records refined in FP64
+// and FP64 fallbacks for the systems that do not converge.
+hipError_t big_solve(const BigFactor &bf, const BigRefine &rf, int NP, int n, int S, int F,
+                     const double *M_d, const double *R_d, const double *phi_d, const double *C_d,
+                     const double *omega_d, double2 *A_d, int *piv_d, double2 *I_d, int rhs_kind,
+                     const void *rhs_d, int nchunk, double rscale, double *gsys_d,
+                     int32_t *status_d, hipStream_t st, double2 *mu_d = nullptr);
 hipError_t launch_lu_solve(int NP, int n, int S, int F, const double2 *A_d, const int *piv_d,
                            const double *phi_d, const double *C_d, const double *omega_d,
                            double2 *I_d, int rhs_kind, const void *rhs_d, int nchunk,
@@ -308,6 +328,10 @@ struct cosim_plan {
     double2 *bWt = nullptr;   // blocked LDL^T panel copy ([S][64][NP], see BigFactor)
     double2 *bTinv = nullptr; // blocked LDL^T L11^-T ([S][64][64])
     double *bZmax = nullptr;  // [S] largest diagonal |Z_kk| (blocked LDL^T)
+    void *bA32 = nullptr;     // [S][NP][NP] complex64 records of the refined solves
+    bool refine = false;      // FP32 factorisation + FP64 refinement (cosim_plan_set_refinement)
+    int refine_iter = 0;
+    double refine_tol = 0.0;  // 0: chosen per precision
     double2 *mu_ws = nullptr; // [S][n] adjoint solutions (gradients of R, L, w)
     double *gpar_ws = nullptr; // [2][S][n] per-system R and L terms
     size_t par_cap = 0;       // systems mu_ws / gpar_ws hold

@@ -31,6 +31,15 @@
 // is an LU factor and k_lu_solve serves both.  Systems whose smallest pivot is
 // below 1e-5 of the largest |Z_kk| (or not finite), or whose input is invalid,
 // are marked and re-factored by k_lu_big with pivoting.
+//
+// With refinement on, steps 1-4 run on a complex64 copy of Z (diagonal block
+// still eliminated in FP64 in LDS; panel and trailing update on FP32 matrix
+// cores, half the bytes and twice the peak of FP64), and k_solve_refined
+// turns the FP32 factor F into FP64 solutions by iterative refinement:
+// x = F^-1 b, then r = b - Z x in FP64 (Z formed on the fly from M, R, C and
+// w; it is never stored in FP64) and x += F^-1 r until the next correction is
+// predicted below tol |x|.  A system that does not converge is re-factored in
+// FP64 with pivoting and solved again.
 #include "internal.h"
 
 namespace cosim {
@@ -54,6 +63,58 @@ __device__ inline double2 zfma(double2 acc, double2 l, double2 u) {
 __device__ inline double2 zinv(double2 a) {
     const double d = 1.0 / (a.x * a.x + a.y * a.y);
     return make_double2(a.x * d, -a.y * d);
+}
+
+// Factor storage: complex128 (FP64 path) or complex64 (FP32 factor of the
+// refined path); arithmetic outside the matrix cores is FP64 either way.
+__device__ inline double2 ld2(double2 v) { return v; }
+__device__ inline double2 ld2(float2 v) { return make_double2((double)v.x, (double)v.y); }
+template <typename T2>
+__device__ inline T2 st2(double2 v);
+template <>
+__device__ inline double2 st2<double2>(double2 v) {
+    return v;
+}
+template <>
+__device__ inline float2 st2<float2>(double2 v) {
+    return make_float2((float)v.x, (float)v.y);
+}
+template <typename T2>
+struct Scal;
+template <>
+struct Scal<double2> {
+    typedef double type;
+};
+template <>
+struct Scal<float2> {
+    typedef float type;
+};
+
+// One 16x16x4 matrix-core step on FP64 or FP32 operands.  Operand lanes are
+// laid out alike (A: row l % 16, k = l / 16; B: k = l / 16, column l % 16);
+// accumulator element m of lane group g = l / 16 sits in row g + 4m (FP64)
+// or 4g + m (FP32), column l % 16.
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+__device__ inline f64x4 mfma4(double a, double b, f64x4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ inline f32x4 mfma4(float a, float b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+template <typename T>
+struct Acc4;
+template <>
+struct Acc4<double> {
+    typedef f64x4 type;
+};
+template <>
+struct Acc4<float> {
+    typedef f32x4 type;
+};
+template <typename T>
+__device__ inline int acc_row(int g, int m) {
+    return sizeof(T) == 8 ? g + 4 * m : 4 * g + m;
 }
 
 // Arg-max of (m, idx) over the workgroup, ties to the lower index; every
@@ -91,7 +152,7 @@ __global__ __launch_bounds__(kTB) void k_lu_big(int n, int NP, int S, int F,
                                                 const double *__restrict__ C,
                                                 const double *__restrict__ omega,
                                                 double2 *__restrict__ Aall, int *__restrict__ pivall,
-                                                const int *__restrict__ only,
+                                                const int *__restrict__ only, int want,
                                                 int32_t *__restrict__ status) {
     __shared__ double sm[kTB / 64];
     __shared__ int si[kTB / 64];
@@ -102,7 +163,7 @@ __global__ __launch_bounds__(kTB) void k_lu_big(int n, int NP, int S, int F,
     __shared__ double2 sUt[kPW][16 + 1];
     const int s = blockIdx.x;
     if (s >= S) return;  // whole workgroup
-    if (only && only[s] != kFmtNeedsPivot) return;  // re-factor marked systems only
+    if (only && only[s] != want) return;  // re-factor marked systems only
     const int tid = threadIdx.x;
     double2 *A = Aall + (size_t)s * NP * NP;
     int *piv = pivall + (size_t)s * NP;
@@ -214,12 +275,13 @@ __global__ __launch_bounds__(kTB) void k_lu_big(int n, int NP, int S, int F,
 // grid (S, NP/16): workgroup y writes rows 16y .. 16y + 15; the one with
 // y = 0 also sets the input flags, fmt = kFmtLDL (kFmtNeedsPivot for invalid
 // input) and the largest |re| + |im| of a diagonal entry.
+template <typename T2>
 __global__ __launch_bounds__(kTB) void k_big_assemble(int n, int NP, int S, int F,
                                                       const double *__restrict__ M,
                                                       const double *__restrict__ Rv,
                                                       const double *__restrict__ C,
                                                       const double *__restrict__ omega,
-                                                      double2 *__restrict__ Aall,
+                                                      T2 *__restrict__ Aall,
                                                       int *__restrict__ fmt,
                                                       double *__restrict__ zmax,
                                                       int32_t *__restrict__ status) {
@@ -229,7 +291,7 @@ __global__ __launch_bounds__(kTB) void k_big_assemble(int n, int NP, int S, int 
     const int s = blockIdx.x;
     if (s >= S) return;  // whole workgroup
     const int tid = threadIdx.x;
-    double2 *A = Aall + (size_t)s * NP * NP;
+    T2 *A = Aall + (size_t)s * NP * NP;
     const int b = s / F, f = s - b * F;
     const double w = omega[f];
     const double *Cb = C + (size_t)b * n;
@@ -256,7 +318,7 @@ __global__ __launch_bounds__(kTB) void k_big_assemble(int n, int NP, int S, int 
             } else if (i == j) {
                 zr = 1.0;
             }
-            A[(size_t)i * NP + j] = make_double2(zr, zi);
+            A[(size_t)i * NP + j] = st2<T2>(make_double2(zr, zi));
         }
     }
     if (!first) return;  // whole workgroup
@@ -276,22 +338,25 @@ __global__ __launch_bounds__(kTB) void k_big_assemble(int n, int NP, int S, int 
 //   x_rc2 -= l_rc x_cc2  for c2 <= c < r.
 // Written back: L_rc = v_rc / d_c below the diagonal, d_c on it, U_cr = v_rc
 // above it, identity swaps, and T = X^T = L11^-T ([64][64] per system) for
-// step 2; a pivot below 1e-5 zmax marks the system.
+// step 2; a pivot below 1e-5 zmax marks the system.  The elimination is FP64
+// for either storage type.
+template <typename T2>
 __global__ __launch_bounds__(kTB) void k_ldl_big_diag(int NP, int k0, int S,
-                                                      double2 *__restrict__ Aall,
+                                                      T2 *__restrict__ Aall,
                                                       int *__restrict__ pivall,
                                                       int *__restrict__ fmt,
                                                       const double *__restrict__ zmax,
-                                                      double2 *__restrict__ tinv) {
+                                                      T2 *__restrict__ tinv) {
     __shared__ double2 sa[64][65];
     __shared__ double2 sx[64][65];
     const int s = blockIdx.x;
     if (s >= S) return;  // whole workgroup
+    if (fmt[s] != kFmtLDL) return;  // invalid input: left to the pivoted LU
     const int tid = threadIdx.x;
-    double2 *A = Aall + (size_t)s * NP * NP + (size_t)k0 * NP + k0;
+    T2 *A = Aall + (size_t)s * NP * NP + (size_t)k0 * NP + k0;
     for (int e = tid; e < 64 * 64; e += kTB) {
         const int r = e >> 6, c = e & 63;
-        sa[r][c] = c <= r ? A[(size_t)r * NP + c] : make_double2(0.0, 0.0);
+        sa[r][c] = c <= r ? ld2(A[(size_t)r * NP + c]) : make_double2(0.0, 0.0);
         sx[r][c] = make_double2(r == c ? 1.0 : 0.0, 0.0);
     }
     __syncthreads();
@@ -305,20 +370,20 @@ __global__ __launch_bounds__(kTB) void k_ldl_big_diag(int NP, int k0, int S,
         }
         __syncthreads();
     }
-    double2 *T = tinv + (size_t)s * 64 * 64;
-    for (int e = tid; e < 64 * 64; e += kTB) T[e] = sx[e & 63][e >> 6];  // T[k][c] = X[c][k]
+    T2 *T = tinv + (size_t)s * 64 * 64;
+    for (int e = tid; e < 64 * 64; e += kTB) T[e] = st2<T2>(sx[e & 63][e >> 6]);  // T[k][c] = X[c][k]
     double dmin = __builtin_inf();
     for (int e = tid; e < 64 * 64; e += kTB) {
         const int r = e >> 6, c = e & 63;  // lower part and diagonal by rows
-        if (c < r) A[(size_t)r * NP + c] = zmul(sa[r][c], zinv(sa[c][c]));
+        if (c < r) A[(size_t)r * NP + c] = st2<T2>(zmul(sa[r][c], zinv(sa[c][c])));
         else if (c == r) {
             const double2 d = sa[r][r];
-            A[(size_t)r * NP + r] = d;
+            A[(size_t)r * NP + r] = st2<T2>(d);
             const double ad = fabs(d.x) + fabs(d.y);
             dmin = ad == ad ? fmin(dmin, ad) : 0.0;  // a NaN pivot counts as zero
         }
         const int c2 = e >> 6, r2 = e & 63;  // upper part by rows: U_c2,r2 = v_r2,c2
-        if (r2 > c2) A[(size_t)c2 * NP + r2] = sa[r2][c2];
+        if (r2 > c2) A[(size_t)c2 * NP + r2] = st2<T2>(sa[r2][c2]);
     }
     if (tid < 64) pivall[(size_t)s * NP + k0 + tid] = k0 + tid;
     int dummy = 0;
@@ -337,19 +402,23 @@ __global__ __launch_bounds__(kTB) void k_ldl_big_diag(int NP, int k0, int S,
 // a 32x32 quarter as 2x2 blocks of 16x16 (the layout of k_ldl_big_update,
 // with the contraction index k = 16 g + ks); V goes back through the same
 // LDS tile so that every HBM write is a run of consecutive entries.
+template <typename T2>
 __global__ __launch_bounds__(kTB) void k_ldl_big_panel(int NP, int k0, int S,
-                                                       double2 *__restrict__ Aall,
-                                                       const double2 *__restrict__ tinv,
-                                                       double2 *__restrict__ wt) {
-    typedef double f64x4 __attribute__((ext_vector_type(4)));
-    __shared__ double2 sv[64][65];
+                                                       const int *__restrict__ fmt,
+                                                       T2 *__restrict__ Aall,
+                                                       const T2 *__restrict__ tinv,
+                                                       T2 *__restrict__ wt) {
+    typedef typename Scal<T2>::type T;
+    typedef typename Acc4<T>::type V4;
+    __shared__ T2 sv[64][65];
     __shared__ double2 dinv[64];
     const int s = blockIdx.x;
     if (s >= S) return;  // whole workgroup
+    if (fmt[s] != kFmtLDL) return;
     const int tid = threadIdx.x;
-    double2 *A = Aall + (size_t)s * NP * NP;
+    T2 *A = Aall + (size_t)s * NP * NP;
     const int i0 = k0 + 64 + 64 * blockIdx.y;  // first row of this block
-    if (tid < 64) dinv[tid] = zinv(A[(size_t)(k0 + tid) * NP + k0 + tid]);
+    if (tid < 64) dinv[tid] = zinv(ld2(A[(size_t)(k0 + tid) * NP + k0 + tid]));
     for (int e = tid; e < 64 * 64; e += kTB) {
         const int r = e >> 6, c = e & 63;
         sv[r][c] = A[(size_t)(i0 + r) * NP + k0 + c];
@@ -358,31 +427,31 @@ __global__ __launch_bounds__(kTB) void k_ldl_big_panel(int NP, int k0, int S,
     const int lane = tid & 63, wv = tid >> 6;
     const int g = lane >> 4, r16 = lane & 15;
     const int wr = 32 * (wv >> 1), wc = 32 * (wv & 1);
-    const double2 *T = tinv + (size_t)s * 64 * 64 + (size_t)(16 * g) * 64 + wc + r16;
-    f64x4 Vr[2][2], Vi[2][2];
+    const T2 *Tm = tinv + (size_t)s * 64 * 64 + (size_t)(16 * g) * 64 + wc + r16;
+    V4 Vr[2][2], Vi[2][2];
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj) {
-            Vr[bi][bj] = f64x4{0.0, 0.0, 0.0, 0.0};
-            Vi[bi][bj] = f64x4{0.0, 0.0, 0.0, 0.0};
+            Vr[bi][bj] = V4{0, 0, 0, 0};
+            Vi[bi][bj] = V4{0, 0, 0, 0};
         }
 #pragma unroll 4
     for (int ks = 0; ks < 16; ++ks) {
-        double2 a[2], t[2];
+        T2 a[2], t[2];
 #pragma unroll
         for (int b2 = 0; b2 < 2; ++b2) {
             a[b2] = sv[wr + 16 * b2 + r16][16 * g + ks];
-            t[b2] = T[ks * 64 + 16 * b2];
+            t[b2] = Tm[ks * 64 + 16 * b2];
         }
 #pragma unroll
         for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
             for (int bj = 0; bj < 2; ++bj) {
-                Vr[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi].x, t[bj].x, Vr[bi][bj], 0, 0, 0);
-                Vr[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[bi].y, t[bj].y, Vr[bi][bj], 0, 0, 0);
-                Vi[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi].x, t[bj].y, Vi[bi][bj], 0, 0, 0);
-                Vi[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi].y, t[bj].x, Vi[bi][bj], 0, 0, 0);
+                Vr[bi][bj] = mfma4(a[bi].x, t[bj].x, Vr[bi][bj]);
+                Vr[bi][bj] = mfma4(-a[bi].y, t[bj].y, Vr[bi][bj]);
+                Vi[bi][bj] = mfma4(a[bi].x, t[bj].y, Vi[bi][bj]);
+                Vi[bi][bj] = mfma4(a[bi].y, t[bj].x, Vi[bi][bj]);
             }
     }
     __syncthreads();  // every wave is done reading A21
@@ -391,17 +460,20 @@ __global__ __launch_bounds__(kTB) void k_ldl_big_panel(int NP, int k0, int S,
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
-            for (int m = 0; m < 4; ++m)
-                sv[wr + 16 * bi + g + 4 * m][wc + 16 * bj + r16] =
-                    make_double2(Vr[bi][bj][m], Vi[bi][bj][m]);
+            for (int m = 0; m < 4; ++m) {
+                T2 v;
+                v.x = Vr[bi][bj][m];
+                v.y = Vi[bi][bj][m];
+                sv[wr + 16 * bi + acc_row<T>(g, m)][wc + 16 * bj + r16] = v;
+            }
     __syncthreads();
-    double2 *W = wt + (size_t)s * 64 * NP;
+    T2 *W = wt + (size_t)s * 64 * NP;
     for (int e = tid; e < 64 * 64; e += kTB) {
         const int r = e >> 6, c = e & 63;
-        A[(size_t)(i0 + r) * NP + k0 + c] = zmul(sv[r][c], dinv[c]);
+        A[(size_t)(i0 + r) * NP + k0 + c] = st2<T2>(zmul(ld2(sv[r][c]), dinv[c]));
         const int c2 = e >> 6, r2 = e & 63;  // transposed: consecutive threads along rows
         A[(size_t)(k0 + c2) * NP + i0 + r2] = sv[r2][c2];
-        W[(size_t)c2 * NP + (i0 - k0 - 64) + r2] = zmul(sv[r2][c2], dinv[c2]);
+        W[(size_t)c2 * NP + (i0 - k0 - 64) + r2] = st2<T2>(zmul(ld2(sv[r2][c2]), dinv[c2]));
     }
 }
 
@@ -420,13 +492,17 @@ __global__ __launch_bounds__(kTB) void k_ldl_big_panel(int NP, int k0, int S,
 // both operands, so each lane's operand is one 16-byte load and the 16 lanes
 // of a group read 256 consecutive bytes: the A operand from wt (rows of
 // L21^T), the B operand from U12 (rows of V21^T).
+template <typename T2>
 __global__ __launch_bounds__(kTB) void k_ldl_big_update(int NP, int k0, int S,
-                                                        double2 *__restrict__ Aall,
-                                                        const double2 *__restrict__ wt, int T) {
-    typedef double f64x4 __attribute__((ext_vector_type(4)));
+                                                        const int *__restrict__ fmt,
+                                                        T2 *__restrict__ Aall,
+                                                        const T2 *__restrict__ wt, int T) {
+    typedef typename Scal<T2>::type Ts;
+    typedef typename Acc4<Ts>::type V4;
     const int kx = blockIdx.x >> 3;
     const int s = 8 * (kx / T) + (blockIdx.x & 7);
     if (s >= S) return;  // whole workgroup
+    if (fmt[s] != kFmtLDL) return;
     const int t = kx % T;
     int ti = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
     while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
@@ -437,21 +513,21 @@ __global__ __launch_bounds__(kTB) void k_ldl_big_update(int NP, int k0, int S,
     const int g = lane >> 4, r16 = lane & 15;
     const int wi = base + 64 * ti + 32 * (wv >> 1);  // first row of this wave's quarter
     const int wj = base + 64 * tj + 32 * (wv & 1);   // first column
-    double2 *A = Aall + (size_t)s * NP * NP;
+    T2 *A = Aall + (size_t)s * NP * NP;
     // lane's operand streams: L21[wi + 16 bi + r16][16 g + ks] and V21[wj + 16 bj + r16][16 g + ks]
-    const double2 *La = wt + (size_t)s * 64 * NP + (size_t)(16 * g) * NP + (wi - base) + r16;
-    const double2 *Vb = A + (size_t)(k0 + 16 * g) * NP + wj + r16;
-    f64x4 Cr[2][2], Ci[2][2];
+    const T2 *La = wt + (size_t)s * 64 * NP + (size_t)(16 * g) * NP + (wi - base) + r16;
+    const T2 *Vb = A + (size_t)(k0 + 16 * g) * NP + wj + r16;
+    V4 Cr[2][2], Ci[2][2];
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj) {
-            Cr[bi][bj] = f64x4{0.0, 0.0, 0.0, 0.0};
-            Ci[bi][bj] = f64x4{0.0, 0.0, 0.0, 0.0};
+            Cr[bi][bj] = V4{0, 0, 0, 0};
+            Ci[bi][bj] = V4{0, 0, 0, 0};
         }
 #pragma unroll 4
     for (int ks = 0; ks < 16; ++ks) {
-        double2 l[2], v[2];
+        T2 l[2], v[2];
 #pragma unroll
         for (int b2 = 0; b2 < 2; ++b2) {
             l[b2] = La[(size_t)ks * NP + 16 * b2];
@@ -462,10 +538,10 @@ __global__ __launch_bounds__(kTB) void k_ldl_big_update(int NP, int k0, int S,
 #pragma unroll
             for (int bj = 0; bj < 2; ++bj) {
                 // (lr + j li)(vr + j vi): re = lr vr - li vi, im = lr vi + li vr
-                Cr[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(l[bi].x, v[bj].x, Cr[bi][bj], 0, 0, 0);
-                Cr[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(-l[bi].y, v[bj].y, Cr[bi][bj], 0, 0, 0);
-                Ci[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(l[bi].x, v[bj].y, Ci[bi][bj], 0, 0, 0);
-                Ci[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(l[bi].y, v[bj].x, Ci[bi][bj], 0, 0, 0);
+                Cr[bi][bj] = mfma4(l[bi].x, v[bj].x, Cr[bi][bj]);
+                Cr[bi][bj] = mfma4(-l[bi].y, v[bj].y, Cr[bi][bj]);
+                Ci[bi][bj] = mfma4(l[bi].x, v[bj].y, Ci[bi][bj]);
+                Ci[bi][bj] = mfma4(l[bi].y, v[bj].x, Ci[bi][bj]);
             }
     }
 #pragma unroll
@@ -474,97 +550,106 @@ __global__ __launch_bounds__(kTB) void k_ldl_big_update(int NP, int k0, int S,
         for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
-                double2 *c = A + (size_t)(wi + 16 * bi + g + 4 * m) * NP + wj + 16 * bj + r16;
-                const double2 a = *c;
-                *c = make_double2(a.x - Cr[bi][bj][m], a.y - Ci[bi][bj][m]);
+                T2 *c = A + (size_t)(wi + 16 * bi + acc_row<Ts>(g, m)) * NP + wj + 16 * bj + r16;
+                T2 a = *c;
+                a.x -= Cr[bi][bj][m];
+                a.y -= Ci[bi][bj][m];
+                *c = a;
             }
 }
 
 // sum of row[j] x[j] over j = j0, j0 + 16, ... < j1, as four independent
 // partial sums (stride 64) so that four row loads are in flight at once
-__device__ inline double2 dot_run(const double2 *__restrict__ row, const double2 *x, int j0,
-                                  int j1) {
+template <typename T2>
+__device__ inline double2 dot_run(const T2 *__restrict__ row, const double2 *x, int j0, int j1) {
     double2 a0 = make_double2(0.0, 0.0), a1 = a0, a2 = a0, a3 = a0;
     int j = j0;
     for (; j + 48 < j1; j += 64) {
-        const double2 r0 = row[j], r1 = row[j + 16], r2 = row[j + 32], r3 = row[j + 48];
+        const double2 r0 = ld2(row[j]), r1 = ld2(row[j + 16]), r2 = ld2(row[j + 32]),
+                      r3 = ld2(row[j + 48]);
         a0 = zfma(a0, r0, x[j]);
         a1 = zfma(a1, r1, x[j + 16]);
         a2 = zfma(a2, r2, x[j + 32]);
         a3 = zfma(a3, r3, x[j + 48]);
     }
-    for (; j < j1; j += 16) a0 = zfma(a0, row[j], x[j]);
+    for (; j < j1; j += 16) a0 = zfma(a0, ld2(row[j]), x[j]);
     return make_double2((a0.x + a1.x) + (a2.x + a3.x), (a0.y + a1.y) + (a2.y + a3.y));
 }
 
-// Adjoint right-hand side: rscale * conj(sum over chunks of (rr + j ri)).
-// Forward: I[s][k]; adjoint: gsys[s][k] = 2 Re(mu_k I_k / (j w C_k^2)).
+// The same for a real row (a row of M) against a complex vector.
+__device__ inline double2 dot_real_run(const double *__restrict__ row, const double2 *x, int j0,
+                                       int j1) {
+    double r0 = 0.0, i0 = 0.0, r1 = 0.0, i1 = 0.0;
+    int j = j0;
+    for (; j + 16 < j1; j += 32) {
+        const double m0 = row[j], m1 = row[j + 16];
+        const double2 x0 = x[j], x1 = x[j + 16];
+        r0 = fma(m0, x0.x, r0);
+        i0 = fma(m0, x0.y, i0);
+        r1 = fma(m1, x1.x, r1);
+        i1 = fma(m1, x1.y, i1);
+    }
+    for (; j < j1; j += 16) {
+        const double m0 = row[j];
+        const double2 x0 = x[j];
+        r0 = fma(m0, x0.x, r0);
+        i0 = fma(m0, x0.y, i0);
+    }
+    return make_double2(r0 + r1, i0 + i1);
+}
+
+// Right-hand side of row k < n of system s: the loop voltage (forward) or
+// rscale * conj(sum over chunks of (rr + j ri)) (adjoint).
 template <int RHS>
-__global__ __launch_bounds__(kTB) void k_lu_solve(int n, int NP, int S, int F,
-                                                  const double2 *__restrict__ Aall,
-                                                  const int *__restrict__ pivall,
-                                                  const double *__restrict__ phi,
-                                                  const double *__restrict__ C,
-                                                  const double *__restrict__ omega,
-                                                  double2 *__restrict__ I, const void *rhs,
-                                                  int nchunk, double rscale,
-                                                  double *__restrict__ gsys,
-                                                  double2 *__restrict__ mu,
-                                                  int32_t *__restrict__ status) {
-    __shared__ double2 sx[kMaxLoopsBig];
-    __shared__ double2 st[16];
-    __shared__ int sFlag;
-    const int s = blockIdx.x;
-    if (s >= S) return;
+__device__ inline double2 rhs_entry(int k, int n, int NP, int S, int s, double w,
+                                    const double *__restrict__ phi, const void *rhs, int nchunk,
+                                    double rscale) {
+    if (RHS == kRhsExcitation) return loop_voltage(phi, n, k, w);
+    double rr = 0.0, ri = 0.0;
+    for (int c = 0; c < nchunk; ++c) {
+        if (RHS == kRhsPairs) {
+            const double2 v = ((const double2 *)rhs)[((size_t)c * S + s) * NP + k];
+            rr += v.x;
+            ri += v.y;
+        } else if (RHS == kRhsPlanarF32) {
+            const float *R = (const float *)rhs + (size_t)c * NP * 2 * S;
+            rr += (double)R[(size_t)(2 * s) * NP + k];
+            ri += (double)R[(size_t)(2 * s + 1) * NP + k];
+        } else {
+            const double *R = (const double *)rhs + (size_t)c * NP * 2 * S;
+            rr += R[(size_t)(2 * s) * NP + k];
+            ri += R[(size_t)(2 * s + 1) * NP + k];
+        }
+    }
+    return make_double2(rscale * rr, -rscale * ri);
+}
+
+// sx <- U^-1 L^-1 P sx for one system's LU record A (unit lower L below the
+// diagonal, U on and above it; the row swaps piv first when PIV), the vector
+// in LDS, every thread of the workgroup taking part: blocks of 16 rows, dot
+// products against the solved rows (16 threads per row), then the 16x16
+// diagonal block inside one wave.  st: 16 entries of LDS scratch.
+template <typename T2, bool PIV>
+__device__ void lu_apply_inverse(const T2 *__restrict__ A, const int *__restrict__ piv, int NP,
+                                 double2 *sx, double2 *st) {
     const int tid = threadIdx.x;
-    const double2 *A = Aall + (size_t)s * NP * NP;
-    const int *piv = pivall + (size_t)s * NP;
-    const int b = s / F, f = s - b * F;
-    const double w = omega[f];
-    for (int k = tid; k < NP; k += kTB) {
-        double2 x = make_double2(0.0, 0.0);
-        if (k < n) {
-            if (RHS == kRhsExcitation) {
-                x = loop_voltage(phi, n, k, w);
-            } else {
-                double rr = 0.0, ri = 0.0;
-                for (int c = 0; c < nchunk; ++c) {
-                    if (RHS == kRhsPairs) {
-                        const double2 v = ((const double2 *)rhs)[((size_t)c * S + s) * NP + k];
-                        rr += v.x;
-                        ri += v.y;
-                    } else if (RHS == kRhsPlanarF32) {
-                        const float *R = (const float *)rhs + (size_t)c * NP * 2 * S;
-                        rr += (double)R[(size_t)(2 * s) * NP + k];
-                        ri += (double)R[(size_t)(2 * s + 1) * NP + k];
-                    } else {
-                        const double *R = (const double *)rhs + (size_t)c * NP * 2 * S;
-                        rr += R[(size_t)(2 * s) * NP + k];
-                        ri += R[(size_t)(2 * s + 1) * NP + k];
-                    }
+    if (PIV) {
+        if (tid == 0) {
+            for (int j = 0; j < NP; ++j) {
+                const int p = piv[j];
+                if (p != j) {
+                    const double2 t = sx[j];
+                    sx[j] = sx[p];
+                    sx[p] = t;
                 }
-                x = make_double2(rscale * rr, -rscale * ri);
             }
         }
-        sx[k] = x;
+        __syncthreads();
     }
-    if (tid == 0) sFlag = 0;
-    __syncthreads();
-    if (tid == 0) {
-        for (int j = 0; j < NP; ++j) {
-            const int p = piv[j];
-            if (p != j) {
-                const double2 t = sx[j];
-                sx[j] = sx[p];
-                sx[p] = t;
-            }
-        }
-    }
-    __syncthreads();
     const int r = tid >> 4, q = tid & 15;
     // forward: L y = P b, L unit lower
     for (int r0 = 0; r0 < NP; r0 += 16) {
-        const double2 *row = A + (size_t)(r0 + r) * NP;
+        const T2 *row = A + (size_t)(r0 + r) * NP;
         double2 acc = dot_run(row, sx, q, r0);
 #pragma unroll
         for (int off = 8; off >= 1; off >>= 1) {
@@ -578,7 +663,8 @@ __global__ __launch_bounds__(kTB) void k_lu_solve(int n, int NP, int S, int F,
             double2 t = st[l];
             for (int k = 0; k < 15; ++k) {
                 const double2 yk = make_double2(__shfl(t.x, k), __shfl(t.y, k));
-                const double2 lk = l > k ? A[(size_t)(r0 + l) * NP + r0 + k] : make_double2(0.0, 0.0);
+                const double2 lk =
+                    l > k ? ld2(A[(size_t)(r0 + l) * NP + r0 + k]) : make_double2(0.0, 0.0);
                 t = zfms(t, lk, yk);
             }
             if (tid < 16) sx[r0 + l] = t;
@@ -587,7 +673,7 @@ __global__ __launch_bounds__(kTB) void k_lu_solve(int n, int NP, int S, int F,
     }
     // backward: U x = y
     for (int r0 = NP - 16; r0 >= 0; r0 -= 16) {
-        const double2 *row = A + (size_t)(r0 + r) * NP;
+        const T2 *row = A + (size_t)(r0 + r) * NP;
         double2 acc = dot_run(row, sx, r0 + 16 + q, NP);
 #pragma unroll
         for (int off = 8; off >= 1; off >>= 1) {
@@ -601,15 +687,26 @@ __global__ __launch_bounds__(kTB) void k_lu_solve(int n, int NP, int S, int F,
             double2 t = st[l];
             for (int k = 15; k >= 0; --k) {
                 // lane k finishes x_k; the lanes of the rows above subtract its term
-                if (l == k) t = zmul(t, zinv(A[(size_t)(r0 + k) * NP + r0 + k]));
+                if (l == k) t = zmul(t, zinv(ld2(A[(size_t)(r0 + k) * NP + r0 + k])));
                 const double2 xk = make_double2(__shfl(t.x, k), __shfl(t.y, k));
-                const double2 uk = l < k ? A[(size_t)(r0 + l) * NP + r0 + k] : make_double2(0.0, 0.0);
+                const double2 uk =
+                    l < k ? ld2(A[(size_t)(r0 + l) * NP + r0 + k]) : make_double2(0.0, 0.0);
                 t = zfms(t, uk, xk);
             }
             if (tid < 16) sx[r0 + l] = t;
         }
         __syncthreads();
     }
+}
+
+// Outputs of a solved system: forward I[s][k]; adjoint gsys[s][k] =
+// 2 Re(mu_k I_k / (j w C_k^2)) (and mu when asked for); status bits.
+template <int RHS>
+__device__ void write_solution(int n, int s, double w, const double *__restrict__ Cb,
+                               const double2 *sx, double2 *__restrict__ I,
+                               double *__restrict__ gsys, double2 *__restrict__ mu,
+                               int32_t *__restrict__ status, int *sFlag) {
+    const int tid = threadIdx.x;
     const int flag = status[s];
     const bool bad = (flag & (COSIM_SYS_BAD_INPUT | COSIM_SYS_SINGULAR)) != 0;
     int oflag = 0;
@@ -621,16 +718,175 @@ __global__ __launch_bounds__(kTB) void k_lu_solve(int n, int NP, int S, int F,
             if (!bad && !(isfinite(x.x) && isfinite(x.y))) oflag = COSIM_SYS_NONFINITE;
         } else {
             const double2 Ik = I[(size_t)s * n + k];
-            const double ck = C[(size_t)b * n + k];
+            const double ck = Cb[k];
+            // 2 Re(mu I / (j w C^2)) = 2 Im(mu I) / (w C^2)
             const double g = 2.0 * (x.x * Ik.y + x.y * Ik.x) / (w * ck * ck);
             gsys[(size_t)s * n + k] = g;
             if (mu) mu[(size_t)s * n + k] = x;
             if (!bad && !isfinite(g)) oflag = COSIM_SYS_NONFINITE;
         }
     }
-    if (oflag) atomicOr(&sFlag, oflag);
+    if (oflag) atomicOr(sFlag, oflag);
     __syncthreads();
-    if (tid == 0 && sFlag) status[s] = flag | sFlag;
+    if (tid == 0 && *sFlag) status[s] = flag | *sFlag;
+}
+
+// One workgroup per system (only those with only[s] == want when `only` is
+// set): right-hand side, the two triangular solves with the FP64 record,
+// outputs.
+template <int RHS>
+__global__ __launch_bounds__(kTB) void k_lu_solve(int n, int NP, int S, int F,
+                                                  const double2 *__restrict__ Aall,
+                                                  const int *__restrict__ pivall,
+                                                  const double *__restrict__ phi,
+                                                  const double *__restrict__ C,
+                                                  const double *__restrict__ omega,
+                                                  double2 *__restrict__ I, const void *rhs,
+                                                  int nchunk, double rscale,
+                                                  double *__restrict__ gsys,
+                                                  double2 *__restrict__ mu,
+                                                  int32_t *__restrict__ status,
+                                                  const int *__restrict__ only, int want) {
+    __shared__ double2 sx[kMaxLoopsBig];
+    __shared__ double2 st[16];
+    __shared__ int sFlag;
+    const int s = blockIdx.x;
+    if (s >= S) return;
+    if (only && only[s] != want) return;
+    const int tid = threadIdx.x;
+    const int b = s / F, f = s - b * F;
+    const double w = omega[f];
+    for (int k = tid; k < NP; k += kTB)
+        sx[k] = k < n ? rhs_entry<RHS>(k, n, NP, S, s, w, phi, rhs, nchunk, rscale)
+                      : make_double2(0.0, 0.0);
+    if (tid == 0) sFlag = 0;
+    __syncthreads();
+    lu_apply_inverse<double2, true>(Aall + (size_t)s * NP * NP, pivall + (size_t)s * NP, NP, sx, st);
+    write_solution<RHS>(n, s, w, C + (size_t)b * n, sx, I, gsys, mu, status, &sFlag);
+}
+
+// Largest of a and b over the workgroup, NaN taken as +inf; every thread
+// returns with both.  sm: 2 kTB/64 entries of LDS scratch.
+__device__ inline void block_max2(double &a, double &b, double *sm) {
+    if (!(a == a)) a = __builtin_inf();
+    if (!(b == b)) b = __builtin_inf();
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        a = fmax(a, __shfl_xor(a, off));
+        b = fmax(b, __shfl_xor(b, off));
+    }
+    const int wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sm[2 * wv] = a;
+        sm[2 * wv + 1] = b;
+    }
+    __syncthreads();
+    a = sm[0];
+    b = sm[1];
+#pragma unroll
+    for (int v = 1; v < kTB / 64; ++v) {
+        a = fmax(a, sm[2 * v]);
+        b = fmax(b, sm[2 * v + 1]);
+    }
+    __syncthreads();
+}
+
+// Refined solve of the systems factored in FP32 (fmt kFmtLDL, record A32 of
+// the blocked LDL^T): x = F^-1 b, then up to max_iter times
+//   r = b - Z x   in FP64: (R_k - j/(w C_k)) x_k + j w (M x)_k, rows of M read
+//                 by 16 threads each as in the triangular solves;
+//   d = F^-1 r,   x += d.
+// With d_0 = x_0 the corrections shrink geometrically by about
+// |d_i| / |d_(i-1)|, so the error left after step i is estimated as
+// |d_i|^2 / |d_(i-1)|; the system is done once that is at most tol |x| and
+// |d_i| <= |d_(i-1)| / 2 (max norms).  A system that is not done after
+// max_iter steps is marked fail_fmt, writes nothing and is left to the
+// pivoted FP64 fallback.
+template <int RHS>
+__global__ __launch_bounds__(kTB) void k_solve_refined(
+    int n, int NP, int S, int F, const float2 *__restrict__ A32all,
+    const double *__restrict__ M, const double *__restrict__ Rv, const double *__restrict__ phi,
+    const double *__restrict__ C, const double *__restrict__ omega, double2 *__restrict__ I,
+    const void *rhs, int nchunk, double rscale, double *__restrict__ gsys,
+    double2 *__restrict__ mu, int32_t *__restrict__ status, int *__restrict__ fmt, int fail_fmt,
+    int max_iter, double tol) {
+    __shared__ double2 sb[kMaxLoopsBig];
+    __shared__ double2 sx[kMaxLoopsBig];
+    __shared__ double2 sr[kMaxLoopsBig];
+    __shared__ double2 st[16];
+    __shared__ double sm[2 * (kTB / 64)];
+    __shared__ int sFlag;
+    const int s = blockIdx.x;
+    if (s >= S) return;
+    if (fmt[s] != kFmtLDL) return;  // whole workgroup: handled by the FP64 record
+    const int tid = threadIdx.x;
+    const int b = s / F, f = s - b * F;
+    const double w = omega[f];
+    const double *Cb = C + (size_t)b * n;
+    const float2 *A = A32all + (size_t)s * NP * NP;
+    for (int k = tid; k < NP; k += kTB) {
+        const double2 v = k < n ? rhs_entry<RHS>(k, n, NP, S, s, w, phi, rhs, nchunk, rscale)
+                                : make_double2(0.0, 0.0);
+        sb[k] = v;
+        sr[k] = v;
+    }
+    if (tid == 0) sFlag = 0;
+    __syncthreads();
+    lu_apply_inverse<float2, false>(A, nullptr, NP, sr, st);
+    double prev = 0.0, xm = 0.0;
+    for (int k = tid; k < NP; k += kTB) {
+        const double2 x = sr[k];
+        sx[k] = x;
+        prev = fmax(prev, fabs(x.x) + fabs(x.y));
+    }
+    block_max2(prev, xm, sm);  // |d_0| = |x_0|
+    const int r = tid >> 4, q = tid & 15;
+    bool done = false;
+    for (int it = 0; it < max_iter && !done; ++it) {
+        for (int r0 = 0; r0 < NP; r0 += 16) {
+            const int i = r0 + r;
+            double2 acc = make_double2(0.0, 0.0);
+            if (i < n) acc = dot_real_run(M + (size_t)i * n, sx, q, n);
+#pragma unroll
+            for (int off = 8; off >= 1; off >>= 1) {
+                acc.x += __shfl_xor(acc.x, off);
+                acc.y += __shfl_xor(acc.y, off);
+            }
+            if (q == 0) {
+                double2 v = make_double2(0.0, 0.0);
+                if (i < n) {
+                    const double2 xi = sx[i], bi = sb[i];
+                    const double zr = Rv[i], zi = -1.0 / (w * Cb[i]);
+                    // b - z_ii x_i - j w (M x)_i
+                    v.x = bi.x - (zr * xi.x - zi * xi.y) + w * acc.y;
+                    v.y = bi.y - (zr * xi.y + zi * xi.x) - w * acc.x;
+                }
+                sr[i] = v;
+            }
+        }
+        __syncthreads();
+        lu_apply_inverse<float2, false>(A, nullptr, NP, sr, st);
+        double dm = 0.0;
+        xm = 0.0;
+        for (int k = tid; k < NP; k += kTB) {
+            const double2 d = sr[k];
+            double2 x = sx[k];
+            x.x += d.x;
+            x.y += d.y;
+            sx[k] = x;
+            dm = fmax(dm, fabs(d.x) + fabs(d.y));
+            xm = fmax(xm, fabs(x.x) + fabs(x.y));
+            if (!(d.x == d.x && d.y == d.y)) dm = __builtin_inf();
+        }
+        block_max2(dm, xm, sm);
+        done = dm < __builtin_inf() && dm * dm <= tol * xm * prev && dm <= 0.5 * prev;
+        prev = dm;
+    }
+    if (!done) {
+        if (tid == 0) fmt[s] = fail_fmt;
+        return;  // whole workgroup
+    }
+    write_solution<RHS>(n, s, w, Cb, sx, I, gsys, mu, status, &sFlag);
 }
 
 }  // namespace
@@ -640,39 +896,141 @@ hipError_t launch_lu_big(int NP, int n, int S, int F, const double *M_d, const d
                          int32_t *status_d, hipStream_t st) {
     if (NP % 64 != 0 || NP > kMaxLoopsBig) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_lu_big, dim3(S), dim3(kTB), 0, st, n, NP, S, F, M_d, R_d, C_d, omega_d,
-                       A_d, piv_d, nullptr, status_d);
+                       A_d, piv_d, nullptr, 0, status_d);
     return hipGetLastError();
 }
 
-hipError_t big_factor(const BigFactor &bf, int NP, int n, int S, int F,
+namespace {
+
+// Blocked LDL^T of the systems marked kFmtLDL, in the storage type T2.
+template <typename T2>
+hipError_t blocked_ldl(const BigFactor &bf, int NP, int n, int S, int F, const double *M_d,
+                       const double *R_d, const double *C_d, const double *omega_d, T2 *A_d,
+                       int *piv_d, int32_t *status_d, hipStream_t st) {
+    T2 *wt = (T2 *)bf.wt, *tinv = (T2 *)bf.tinv;
+    hipLaunchKernelGGL(k_big_assemble<T2>, dim3(S, NP / 16), dim3(kTB), 0, st, n, NP, S, F, M_d,
+                       R_d, C_d, omega_d, A_d, bf.fmt, bf.zmax, status_d);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    for (int k0 = 0; k0 < NP; k0 += 64) {
+        hipLaunchKernelGGL(k_ldl_big_diag<T2>, dim3(S), dim3(kTB), 0, st, NP, k0, S, A_d, piv_d,
+                           bf.fmt, bf.zmax, tinv);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        const int m = NP - k0 - 64;
+        if (m == 0) break;
+        hipLaunchKernelGGL(k_ldl_big_panel<T2>, dim3(S, m / 64), dim3(kTB), 0, st, NP, k0, S,
+                           (const int *)bf.fmt, A_d, (const T2 *)tinv, wt);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        const int nt = m / 64, T = nt * (nt + 1) / 2;
+        hipLaunchKernelGGL(k_ldl_big_update<T2>, dim3(8 * ((S + 7) / 8) * T), dim3(kTB), 0, st,
+                           NP, k0, S, (const int *)bf.fmt, A_d, (const T2 *)wt, T);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template <int RHS>
+hipError_t lu_solve_launch(int NP, int n, int S, int F, const double2 *A_d, const int *piv_d,
+                           const double *phi_d, const double *C_d, const double *omega_d,
+                           double2 *I_d, const void *rhs_d, int nchunk, double rscale,
+                           double *gsys_d, double2 *mu_d, int32_t *status_d, const int *only,
+                           int want, hipStream_t st) {
+    hipLaunchKernelGGL(k_lu_solve<RHS>, dim3(S), dim3(kTB), 0, st, n, NP, S, F, A_d, piv_d, phi_d,
+                       C_d, omega_d, I_d, rhs_d, nchunk, rscale, gsys_d, mu_d, status_d, only,
+                       want);
+    return hipGetLastError();
+}
+
+hipError_t lu_solve_any(int rhs_kind, int NP, int n, int S, int F, const double2 *A_d,
+                        const int *piv_d, const double *phi_d, const double *C_d,
+                        const double *omega_d, double2 *I_d, const void *rhs_d, int nchunk,
+                        double rscale, double *gsys_d, double2 *mu_d, int32_t *status_d,
+                        const int *only, int want, hipStream_t st) {
+#define COSIM_LU_SOLVE(K)                                                                       \
+    lu_solve_launch<K>(NP, n, S, F, A_d, piv_d, phi_d, C_d, omega_d, I_d, rhs_d, nchunk, rscale, \
+                       gsys_d, mu_d, status_d, only, want, st)
+    switch (rhs_kind) {
+        case kRhsExcitation: return COSIM_LU_SOLVE(kRhsExcitation);
+        case kRhsPairs: return COSIM_LU_SOLVE(kRhsPairs);
+        case kRhsPlanarF32: return COSIM_LU_SOLVE(kRhsPlanarF32);
+        case kRhsPlanarF64: return COSIM_LU_SOLVE(kRhsPlanarF64);
+        default: return hipErrorInvalidValue;
+    }
+#undef COSIM_LU_SOLVE
+}
+
+template <int RHS>
+hipError_t refined_launch(const BigRefine &rf, int NP, int n, int S, int F, const double *M_d,
+                          const double *R_d, const double *phi_d, const double *C_d,
+                          const double *omega_d, double2 *I_d, const void *rhs_d, int nchunk,
+                          double rscale, double *gsys_d, double2 *mu_d, int32_t *status_d,
+                          int *fmt, int fail_fmt, hipStream_t st) {
+    hipLaunchKernelGGL(k_solve_refined<RHS>, dim3(S), dim3(kTB), 0, st, n, NP, S, F,
+                       (const float2 *)rf.A32, M_d, R_d, phi_d, C_d, omega_d, I_d, rhs_d, nchunk,
+                       rscale, gsys_d, mu_d, status_d, fmt, fail_fmt, rf.max_iter, rf.tol);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t big_factor(const BigFactor &bf, const BigRefine &rf, int NP, int n, int S, int F,
                       const double *M_d, const double *R_d, const double *C_d,
                       const double *omega_d, double2 *A_d, int *piv_d, int32_t *status_d,
                       hipStream_t st) {
     if (!bf.ldl) return launch_lu_big(NP, n, S, F, M_d, R_d, C_d, omega_d, A_d, piv_d, status_d, st);
     if (NP % 64 != 0 || NP > kMaxLoopsBig || !bf.fmt || !bf.zmax || !bf.wt || !bf.tinv)
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_big_assemble, dim3(S, NP / 16), dim3(kTB), 0, st, n, NP, S, F, M_d,
-                       R_d, C_d, omega_d, A_d, bf.fmt, bf.zmax, status_d);
-    hipError_t e = hipGetLastError();
+    if (rf.on && !rf.A32) return hipErrorInvalidValue;
+    hipError_t e = rf.on ? blocked_ldl<float2>(bf, NP, n, S, F, M_d, R_d, C_d, omega_d,
+                                               (float2 *)rf.A32, piv_d, status_d, st)
+                         : blocked_ldl<double2>(bf, NP, n, S, F, M_d, R_d, C_d, omega_d, A_d,
+                                                piv_d, status_d, st);
     if (e != hipSuccess) return e;
-    for (int k0 = 0; k0 < NP; k0 += 64) {
-        hipLaunchKernelGGL(k_ldl_big_diag, dim3(S), dim3(kTB), 0, st, NP, k0, S, A_d, piv_d,
-                           bf.fmt, bf.zmax, bf.tinv);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        const int m = NP - k0 - 64;
-        if (m == 0) break;
-        hipLaunchKernelGGL(k_ldl_big_panel, dim3(S, m / 64), dim3(kTB), 0, st, NP, k0, S, A_d,
-                           bf.tinv, bf.wt);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        const int nt = m / 64, T = nt * (nt + 1) / 2;
-        hipLaunchKernelGGL(k_ldl_big_update, dim3(8 * ((S + 7) / 8) * T), dim3(kTB), 0, st, NP,
-                           k0, S, A_d, bf.wt, T);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
-    // pivoted LU (from a fresh Z) for the systems marked on the way
+    // pivoted FP64 LU (from a fresh Z) for the systems marked on the way
     hipLaunchKernelGGL(k_lu_big, dim3(S), dim3(kTB), 0, st, n, NP, S, F, M_d, R_d, C_d, omega_d,
-                       A_d, piv_d, bf.fmt, status_d);
+                       A_d, piv_d, (const int *)bf.fmt, kFmtNeedsPivot, status_d);
     return hipGetLastError();
+}
+
+hipError_t big_solve(const BigFactor &bf, const BigRefine &rf, int NP, int n, int S, int F,
+                     const double *M_d, const double *R_d, const double *phi_d, const double *C_d,
+                     const double *omega_d, double2 *A_d, int *piv_d, double2 *I_d, int rhs_kind,
+                     const void *rhs_d, int nchunk, double rscale, double *gsys_d,
+                     int32_t *status_d, hipStream_t st, double2 *mu_d) {
+    if (NP % 64 != 0 || NP > kMaxLoopsBig) return hipErrorInvalidValue;
+    if (!(bf.ldl && rf.on))
+        return lu_solve_any(rhs_kind, NP, n, S, F, A_d, piv_d, phi_d, C_d, omega_d, I_d, rhs_d,
+                            nchunk, rscale, gsys_d, mu_d, status_d, nullptr, 0, st);
+    const bool fwd = rhs_kind == kRhsExcitation;
+    const int fail = fwd ? kFmtRefineFailed : kFmtRefineFailedAdj;
+    hipError_t e;
+    // 1. the FP32 records, refined
+#define COSIM_REFINED(K)                                                                         \
+    refined_launch<K>(rf, NP, n, S, F, M_d, R_d, phi_d, C_d, omega_d, I_d, rhs_d, nchunk, rscale, \
+                      gsys_d, mu_d, status_d, bf.fmt, fail, st)
+    switch (rhs_kind) {
+        case kRhsExcitation: e = COSIM_REFINED(kRhsExcitation); break;
+        case kRhsPairs: e = COSIM_REFINED(kRhsPairs); break;
+        case kRhsPlanarF32: e = COSIM_REFINED(kRhsPlanarF32); break;
+        case kRhsPlanarF64: e = COSIM_REFINED(kRhsPlanarF64); break;
+        default: return hipErrorInvalidValue;
+    }
+#undef COSIM_REFINED
+    if (e != hipSuccess) return e;
+    // 2. systems that already hold an FP64 record
+    const int have[2] = {kFmtNeedsPivot, kFmtRefineFailed};
+    for (int h = 0; h < (fwd ? 1 : 2); ++h)
+        if ((e = lu_solve_any(rhs_kind, NP, n, S, F, A_d, piv_d, phi_d, C_d, omega_d, I_d, rhs_d,
+                              nchunk, rscale, gsys_d, mu_d, status_d, bf.fmt, have[h], st)) !=
+            hipSuccess)
+            return e;
+    // 3. systems whose refinement did not converge just now: pivoted FP64
+    // record from a fresh Z, then the FP64 solve
+    hipLaunchKernelGGL(k_lu_big, dim3(S), dim3(kTB), 0, st, n, NP, S, F, M_d, R_d, C_d, omega_d,
+                       A_d, piv_d, (const int *)bf.fmt, fail, status_d);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return lu_solve_any(rhs_kind, NP, n, S, F, A_d, piv_d, phi_d, C_d, omega_d, I_d, rhs_d,
+                        nchunk, rscale, gsys_d, mu_d, status_d, bf.fmt, fail, st);
 }
 
 hipError_t launch_lu_solve(int NP, int n, int S, int F, const double2 *A_d, const int *piv_d,
@@ -681,30 +1039,8 @@ hipError_t launch_lu_solve(int NP, int n, int S, int F, const double2 *A_d, cons
                            double rscale, double *gsys_d, int32_t *status_d, hipStream_t st,
                            double2 *mu_d) {
     if (NP % 64 != 0 || NP > kMaxLoopsBig) return hipErrorInvalidValue;
-    const dim3 grid(S), blk(kTB);
-    switch (rhs_kind) {
-        case kRhsExcitation:
-            hipLaunchKernelGGL(k_lu_solve<kRhsExcitation>, grid, blk, 0, st, n, NP, S, F, A_d, piv_d,
-                               phi_d, C_d, omega_d, I_d, rhs_d, nchunk, rscale, gsys_d, mu_d, status_d);
-            break;
-        case kRhsPairs:
-            hipLaunchKernelGGL(k_lu_solve<kRhsPairs>, grid, blk, 0, st, n, NP, S, F, A_d, piv_d,
-                               phi_d, C_d, omega_d, I_d, rhs_d, nchunk, rscale, gsys_d, mu_d, status_d);
-            break;
-        case kRhsPlanarF32:
-            hipLaunchKernelGGL(k_lu_solve<kRhsPlanarF32>, grid, blk, 0, st, n, NP, S, F, A_d,
-                               piv_d, phi_d, C_d, omega_d, I_d, rhs_d, nchunk, rscale, gsys_d,
-                               mu_d, status_d);
-            break;
-        case kRhsPlanarF64:
-            hipLaunchKernelGGL(k_lu_solve<kRhsPlanarF64>, grid, blk, 0, st, n, NP, S, F, A_d,
-                               piv_d, phi_d, C_d, omega_d, I_d, rhs_d, nchunk, rscale, gsys_d,
-                               mu_d, status_d);
-            break;
-        default:
-            return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    return lu_solve_any(rhs_kind, NP, n, S, F, A_d, piv_d, phi_d, C_d, omega_d, I_d, rhs_d, nchunk,
+                        rscale, gsys_d, mu_d, status_d, nullptr, 0, st);
 }
 
 }  // namespace cosim

@@ -236,3 +236,7 @@ def test_component_and_drive_argument_errors(lib):
     one = np.array([0], dtype=np.int32)
     pw = np.array([1.0])
     assert lib.cosim_plan_set_drive(None, 1, one.ctypes.data, pw.ctypes.data, None, 50.0, None) == EINVAL
+
+
+def test_refinement_argument_errors(lib):
+    assert lib.cosim_plan_set_refinement(None, 1, 8, 0.0) == EINVAL

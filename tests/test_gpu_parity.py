@@ -1012,3 +1012,129 @@ def test_drive_ports_replace_and_clear(dev):
         d.plan.set_drive([d.n])
     with pytest.raises(CosimError):
         d.plan.loss_and_grad(d.C, d.om, torch.ones_like(d.T), loss_mode=2)
+
+
+# ----------------------- FP32 factorisation with FP64 iterative refinement
+
+@functools.lru_cache(maxsize=None)
+def _refined(name, max_iter=8, tol=0.0):
+    from paper_2503_18479_amd import Plan
+    c = _case(name)
+    plan = Plan(c.geom, c.pts, c.wl.bext_z)
+    plan.set_refinement(True, max_iter, tol)
+    return plan
+
+
+@pytest.mark.parametrize("name", BIG)
+def test_refined_solve_matches_oracle(dev, name):
+    c = _case(name)
+    _say(f"[refined solve] {name}")
+    I, st = _refined(name).solve(c.C, c.om)
+    torch.cuda.synchronize()
+    assert int(st.abs().sum()) == 0
+    assert np.max(_nrel(I.cpu().numpy(), c.oracle_eval()[0], axis=2)) < 1e-10
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("name", BIG)
+def test_refined_loss_and_grad_matches_oracle(dev, name, prec):
+    c = _case(name)
+    _say(f"[refined loss] {name} prec={prec}")
+    loss, grad, st = _refined(name).loss_and_grad(c.C, c.om, c.T, precision=prec)
+    torch.cuda.synchronize()
+    assert int(st.abs().sum()) == 0
+    Lr = c.oracle_eval()[2]
+    el = np.max(np.abs(loss.cpu().numpy() - Lr) / Lr)
+    eg = np.max(_nrel(grad.cpu().numpy(), c.oracle_grad(), axis=1))
+    _say(f"  loss {el:.2e} grad {eg:.2e}")
+    assert el < TOL[prec] and eg < TOL[prec]
+
+
+def test_refined_parameter_gradients_match_oracle(dev):
+    c = _case("n81")
+    loss, gC, gR, gL, gw, st = _refined("n81").loss_and_grad_params(c.C, c.om, c.T, precision=0)
+    torch.cuda.synchronize()
+    assert int(st.abs().sum()) == 0
+    g = c.wl.geom
+    rR, rL, rw = O.grad_params_adjoint(c.G, c.M, g.R, c.Phi, c.wl.C, c.wl.omega, c.wl.target)
+    for a, r in ((gC, c.oracle_grad()), (gR, rR), (gL, rL), (gw, rw)):
+        assert np.max(_nrel(a.cpu().numpy(), r, axis=1)) < 1e-9
+
+
+def test_refined_autograd_backward_matches_oracle(dev):
+    from paper_2503_18479_amd import cosim_field
+    c = _case("n81")
+    C = c.C.clone().requires_grad_(True)
+    Bz = cosim_field(C, _refined("n81"), c.om, 0)
+    L = ((Bz.abs() - c.T.to(torch.float64)) ** 2).mean(dim=(1, 2))
+    L.sum().backward()
+    torch.cuda.synchronize()
+    assert _nrel(C.grad.cpu().numpy(), c.oracle_grad()) < 1e-9
+
+
+def test_refined_fallback_when_refinement_does_not_converge(dev):
+    """A tolerance no system can meet sends every system to the pivoted FP64
+    factorisation, forward and adjoint; results still match the oracle."""
+    c = _case("n144")
+    plan = _refined("n144", 1, 1e-300)
+    I, st = plan.solve(c.C, c.om)
+    loss, grad, st2 = plan.loss_and_grad(c.C, c.om, c.T, precision=0)
+    torch.cuda.synchronize()
+    assert int(st.abs().sum()) == 0 and int(st2.abs().sum()) == 0
+    assert np.max(_nrel(I.cpu().numpy(), c.oracle_eval()[0], axis=2)) < 1e-10
+    Lr = c.oracle_eval()[2]
+    assert np.max(np.abs(loss.cpu().numpy() - Lr) / Lr) < 1e-9
+    assert np.max(_nrel(grad.cpu().numpy(), c.oracle_grad(), axis=1)) < 1e-9
+
+
+def test_refined_small_pivot_falls_back(dev):
+    """Tiny R with one loop at its own resonance: that system's FP32 factor
+    meets a tiny pivot and takes the FP64 fallback; the others refine."""
+    from paper_2503_18479_amd import Geometry, Plan
+    from array_oracle import oracle_M_array
+    wl = W.small_array(9, 9, batch=3, grid=9, n_freq=2, seed=23)
+    g = wl.geom
+    g.R[:] = 1e-6
+    M = oracle_M_array(g)
+    wl.C[1, 0] = 1.0 / (wl.omega[0] ** 2 * M[0, 0])
+    G = O.field_matrix(g.verts, g.seg_off, wl.pts)
+    Phi = O.flux(g.verts, g.seg_off, wl.bext_z)
+    plan = Plan(Geometry.from_workload(g), torch.tensor(wl.pts, device=dev), wl.bext_z)
+    plan.set_refinement(True)
+    C = torch.tensor(wl.C, device=dev); om = torch.tensor(wl.omega, device=dev)
+    loss, grad, st = plan.loss_and_grad(C, om, torch.tensor(wl.target, device=dev), precision=0)
+    torch.cuda.synchronize()
+    assert int(st.abs().sum()) == 0
+    Lr = O.evaluate(G, M, g.R, Phi, wl.C, wl.omega, wl.target)[2]
+    gr = O.grad_adjoint(G, M, g.R, Phi, wl.C, wl.omega, wl.target)
+    assert np.max(np.abs(loss.cpu().numpy() - Lr) / Lr) < 1e-9
+    assert np.max(_nrel(grad.cpu().numpy(), gr, axis=1)) < 1e-9
+
+
+def test_refined_1024_loops(dev):
+    """The 32x32 array's 1,024 loops (16 panels) with refinement, few
+    configurations and points: currents, loss and dL/dC against the oracle."""
+    from paper_2503_18479_amd import Geometry, Plan
+    from array_oracle import oracle_M_array
+    wl = W.config5_array32x32(batch=3, grid=24)
+    g = wl.geom
+    _say(f"[refined 1024] n={g.n} P={wl.P}")
+    M = oracle_M_array(g)
+    G = O.field_matrix(g.verts, g.seg_off, wl.pts)
+    Phi = O.flux(g.verts, g.seg_off, wl.bext_z)
+    plan = Plan(Geometry.from_workload(g), torch.tensor(wl.pts, device=dev), wl.bext_z)
+    plan.set_refinement(True)
+    C = torch.tensor(wl.C, device=dev); om = torch.tensor(wl.omega, device=dev)
+    T = torch.tensor(wl.target, device=dev)
+    I, st = plan.solve(C, om)
+    torch.cuda.synchronize()
+    assert int(st.abs().sum()) == 0
+    Ir, _, Lr = O.evaluate(G, M, g.R, Phi, wl.C, wl.omega, wl.target)
+    assert np.max(_nrel(I.cpu().numpy(), Ir, axis=2)) < 1e-10
+    gr = O.grad_adjoint(G, M, g.R, Phi, wl.C, wl.omega, wl.target)
+    for prec in (0, 2):
+        loss, grad, st = plan.loss_and_grad(C, om, T, precision=prec)
+        torch.cuda.synchronize()
+        assert int(st.abs().sum()) == 0
+        assert np.max(np.abs(loss.cpu().numpy() - Lr) / Lr) < TOL[prec]
+        assert np.max(_nrel(grad.cpu().numpy(), gr, axis=1)) < TOL[prec]
