@@ -291,25 +291,39 @@ def large_line(adam_steps: int, mixed: str, steps: int, torch) -> dict:
     t_setup = time.perf_counter() - t0
     n, S = wl.geom.n, wl.B * wl.F
     modes, vals = {}, {}
-    for m in (mixed, "fp64"):
-        dt, ph, bad, _ = time_mode(plan, C, om, T, m, steps, 1, torch, tune=False)
-        loss, grad, _ = plan.loss_and_grad(C, om, T, precision=PREC_CODE[m])
-        vals[m] = (loss.cpu().numpy(), grad.cpu().numpy())
-        pm = {name: float(np.mean(ph[:, i])) for i, name in enumerate(Plan.PHASES)}
-        # pivoted LU: (8/3) n^3 real flops per complex system; the contraction
-        # phase: 8 P n flops per system (forward and adjoint, real-split)
-        lu_tf = S * 8.0 / 3.0 * n ** 3 / (pm["solve_forward"] * 1e-3) / 1e12
-        modes[m] = {"ms_per_step": 1e3 * dt / steps, "evals_per_s": wl.B * steps / dt,
-                    "steps": steps, "phase_ms": pm, "flagged_systems": bad,
-                    "solve_forward_fp64_tflops": lu_tf,
-                    "contraction_tflops": 8.0 * wl.P * n * S / (pm["fused_contraction"] * 1e-3) / 1e12}
-        print(f"[bench] 32x32 {m}: {modes[m]['ms_per_step']:.1f} ms/step, phases {pm}",
-              file=sys.stderr, flush=True)
-    lm, gm = vals[mixed]
-    l64, g64 = vals["fp64"]
-    err = {"loss_rel_max": float(np.max(np.abs(lm - l64) / np.abs(l64))),
-           "grad_normwise_rel_max": float(np.max(np.linalg.norm(gm - g64, axis=1)
-                                                 / np.linalg.norm(g64, axis=1)))}
+
+    def rel_err(a, b):
+        (la, ga), (lb, gb) = a, b
+        return {"loss_rel_max": float(np.max(np.abs(la - lb) / np.abs(lb))),
+                "grad_normwise_rel_max": float(np.max(np.linalg.norm(ga - gb, axis=1)
+                                                      / np.linalg.norm(gb, axis=1)))}
+
+    # FP64 factor first, then the FP32 factor with FP64 refinement
+    for refined in (False, True):
+        plan.set_refinement(refined)
+        plan.reserve(wl.B, wl.F)
+        for m in (mixed, "fp64"):
+            key = m + ("+refined" if refined else "")
+            dt, ph, bad, _ = time_mode(plan, C, om, T, m, steps, 1, torch, tune=False)
+            loss, grad, _ = plan.loss_and_grad(C, om, T, precision=PREC_CODE[m])
+            vals[key] = (loss.cpu().numpy(), grad.cpu().numpy())
+            pm = {name: float(np.mean(ph[:, i])) for i, name in enumerate(Plan.PHASES)}
+            # complex-symmetric LDL^T: (4/3) n^3 real flops per system (the
+            # solve_forward phase also holds the assembly and forward solve);
+            # the contraction phase: 8 P n flops per system (forward and
+            # adjoint, real-split)
+            ldl_tf = S * 4.0 / 3.0 * n ** 3 / (pm["solve_forward"] * 1e-3) / 1e12
+            modes[key] = {"ms_per_step": 1e3 * dt / steps, "evals_per_s": wl.B * steps / dt,
+                          "steps": steps, "phase_ms": pm, "flagged_systems": bad,
+                          "solve_forward_ldl_tflops": ldl_tf,
+                          "contraction_tflops": 8.0 * wl.P * n * S
+                          / (pm["fused_contraction"] * 1e-3) / 1e12}
+            if refined:
+                modes[key]["vs_fp64_factor"] = rel_err(vals[key], vals[m])
+            print(f"[bench] 32x32 {key}: {modes[key]['ms_per_step']:.1f} ms/step, phases {pm}",
+                  file=sys.stderr, flush=True)
+    plan.set_refinement(False)
+    err = rel_err(vals[mixed], vals["fp64"])
     adam = None
     if adam_steps > 0:
         C1 = C.clone()
@@ -328,7 +342,11 @@ def large_line(adam_steps: int, mixed: str, steps: int, torch) -> dict:
     return {"workload": wl.name, "loops": n, "points": wl.P, "batch": wl.B, "freqs": wl.F,
             "setup_s": t_setup, "modes": modes, "mixed_vs_fp64_error": err,
             "mixed_vs_fp64_speed": modes["fp64"]["ms_per_step"] / modes[mixed]["ms_per_step"],
-            "adam": adam, "solve": "fp64 pivoted LU (blocked, one workgroup per system)"}
+            "refined_speedup": {m: modes[m]["ms_per_step"] / modes[m + "+refined"]["ms_per_step"]
+                                for m in (mixed, "fp64")},
+            "adam": adam,
+            "solve": "blocked complex-symmetric LDL^T, FP64 matrix cores; '+refined': complex64 "
+                     "factor on FP32 matrix cores with FP64 iterative refinement"}
 
 
 def main():

@@ -46,8 +46,9 @@ namespace cosim {
 
 namespace {
 
-constexpr int kPW = 16;   // panel width
-constexpr int kTB = 256;  // threads per workgroup
+constexpr int kPW = 16;    // panel width
+constexpr int kTB = 256;   // threads per workgroup
+constexpr int kTS = 1024;  // threads per workgroup of the solves: one wave per row of a 16-row block
 
 __device__ inline double2 zmul(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -558,44 +559,73 @@ __global__ __launch_bounds__(kTB) void k_ldl_big_update(int NP, int k0, int S,
             }
 }
 
-// sum of row[j] x[j] over j = j0, j0 + 16, ... < j1, as four independent
-// partial sums (stride 64) so that four row loads are in flight at once
+// sum of row[j] x[j] over j = j0, j0 + 64, ... < j1 (one lane of the wave
+// that owns the row).  Rows have at most kMaxLoopsBig = 16 x 64 entries, so a
+// lane has at most 16, loaded in two batches of 8 issued at once: the solves
+// walk their blocks of rows one after another and each block is
+// latency-bound; a batch is what fits the 128 registers a lane has in a
+// 1,024-thread workgroup without spilling.
+static_assert(kMaxLoopsBig <= 16 * 64, "at most 16 entries of a row per lane");
+// Entries past j1 are loaded from column 0 (always inside the row) and both
+// factors replaced by zero, so that the loads need no branches.
 template <typename T2>
 __device__ inline double2 dot_run(const T2 *__restrict__ row, const double2 *x, int j0, int j1) {
-    double2 a0 = make_double2(0.0, 0.0), a1 = a0, a2 = a0, a3 = a0;
-    int j = j0;
-    for (; j + 48 < j1; j += 64) {
-        const double2 r0 = ld2(row[j]), r1 = ld2(row[j + 16]), r2 = ld2(row[j + 32]),
-                      r3 = ld2(row[j + 48]);
-        a0 = zfma(a0, r0, x[j]);
-        a1 = zfma(a1, r1, x[j + 16]);
-        a2 = zfma(a2, r2, x[j + 32]);
-        a3 = zfma(a3, r3, x[j + 48]);
+    constexpr int D = 8;
+    const double2 z = make_double2(0.0, 0.0);
+    double2 a0 = z, a1 = z;
+#pragma unroll 1
+    for (int e0 = 0; e0 < 16 && j0 + 64 * e0 < j1; e0 += D) {
+        T2 v[D];
+#pragma unroll
+        for (int e = 0; e < D; ++e) {
+            const int j = j0 + 64 * (e0 + e);
+            v[e] = row[j < j1 ? j : 0];
+        }
+#pragma unroll
+        for (int e = 0; e < D; e += 2) {
+            const int j = j0 + 64 * (e0 + e);
+            const bool in0 = j < j1, in1 = j + 64 < j1;
+            a0 = zfma(a0, in0 ? ld2(v[e]) : z, x[in0 ? j : 0]);
+            a1 = zfma(a1, in1 ? ld2(v[e + 1]) : z, x[in1 ? j + 64 : 0]);
+        }
     }
-    for (; j < j1; j += 16) a0 = zfma(a0, ld2(row[j]), x[j]);
-    return make_double2((a0.x + a1.x) + (a2.x + a3.x), (a0.y + a1.y) + (a2.y + a3.y));
+    return make_double2(a0.x + a1.x, a0.y + a1.y);
 }
 
-// The same for a real row (a row of M) against a complex vector.
+// The same for a real row (a row of M) against a complex vector, in two
+// batches of 8 loads.
 __device__ inline double2 dot_real_run(const double *__restrict__ row, const double2 *x, int j0,
                                        int j1) {
-    double r0 = 0.0, i0 = 0.0, r1 = 0.0, i1 = 0.0;
-    int j = j0;
-    for (; j + 16 < j1; j += 32) {
-        const double m0 = row[j], m1 = row[j + 16];
-        const double2 x0 = x[j], x1 = x[j + 16];
-        r0 = fma(m0, x0.x, r0);
-        i0 = fma(m0, x0.y, i0);
-        r1 = fma(m1, x1.x, r1);
-        i1 = fma(m1, x1.y, i1);
+    double r0 = 0.0, i0 = 0.0;
+#pragma unroll 1
+    for (int e0 = 0; e0 < 16 && j0 + 64 * e0 < j1; e0 += 8) {
+        double v[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int j = j0 + 64 * (e0 + e);
+            v[e] = row[j < j1 ? j : 0];
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int j = j0 + 64 * (e0 + e);
+            const bool in = j < j1;
+            const double m = in ? v[e] : 0.0;
+            const double2 xv = x[in ? j : 0];
+            r0 = fma(m, xv.x, r0);
+            i0 = fma(m, xv.y, i0);
+        }
     }
-    for (; j < j1; j += 16) {
-        const double m0 = row[j];
-        const double2 x0 = x[j];
-        r0 = fma(m0, x0.x, r0);
-        i0 = fma(m0, x0.y, i0);
+    return make_double2(r0, i0);
+}
+
+// Sum over the 64 lanes of a wave; every lane returns with it.
+__device__ inline double2 wave_sum(double2 a) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        a.x += __shfl_xor(a.x, off);
+        a.y += __shfl_xor(a.y, off);
     }
-    return make_double2(r0 + r1, i0 + i1);
+    return a;
 }
 
 // Right-hand side of row k < n of system s: the loop voltage (forward) or
@@ -626,12 +656,13 @@ __device__ inline double2 rhs_entry(int k, int n, int NP, int S, int s, double w
 
 // sx <- U^-1 L^-1 P sx for one system's LU record A (unit lower L below the
 // diagonal, U on and above it; the row swaps piv first when PIV), the vector
-// in LDS, every thread of the workgroup taking part: blocks of 16 rows, dot
-// products against the solved rows (16 threads per row), then the 16x16
-// diagonal block inside one wave.  st: 16 entries of LDS scratch.
+// in LDS, the kTS threads of the workgroup taking part: blocks of 16 rows,
+// dot products against the solved rows (wave r takes row r of the block and
+// stages its diagonal-block entries in LDS), then the 16x16 diagonal block
+// inside wave 0.  st: 16 entries, sd: 16 x 17 entries of LDS scratch.
 template <typename T2, bool PIV>
-__device__ void lu_apply_inverse(const T2 *__restrict__ A, const int *__restrict__ piv, int NP,
-                                 double2 *sx, double2 *st) {
+__device__ __forceinline__ void lu_apply_inverse(const T2 *__restrict__ A, const int *__restrict__ piv, int NP,
+                                 double2 *sx, double2 *st, double2 (*sd)[17]) {
     const int tid = threadIdx.x;
     if (PIV) {
         if (tid == 0) {
@@ -646,25 +677,21 @@ __device__ void lu_apply_inverse(const T2 *__restrict__ A, const int *__restrict
         }
         __syncthreads();
     }
-    const int r = tid >> 4, q = tid & 15;
+    const int r = tid >> 6, q = tid & 63;
     // forward: L y = P b, L unit lower
     for (int r0 = 0; r0 < NP; r0 += 16) {
         const T2 *row = A + (size_t)(r0 + r) * NP;
-        double2 acc = dot_run(row, sx, q, r0);
-#pragma unroll
-        for (int off = 8; off >= 1; off >>= 1) {
-            acc.x += __shfl_xor(acc.x, off);
-            acc.y += __shfl_xor(acc.y, off);
-        }
+        if (q < 16) sd[r][q] = ld2(row[r0 + q]);
+        const double2 acc = wave_sum(dot_run(row, sx, q, r0));
         if (q == 0) st[r] = make_double2(sx[r0 + r].x - acc.x, sx[r0 + r].y - acc.y);
         __syncthreads();
         if (tid < 64) {
             const int l = tid & 15;
             double2 t = st[l];
+#pragma unroll
             for (int k = 0; k < 15; ++k) {
                 const double2 yk = make_double2(__shfl(t.x, k), __shfl(t.y, k));
-                const double2 lk =
-                    l > k ? ld2(A[(size_t)(r0 + l) * NP + r0 + k]) : make_double2(0.0, 0.0);
+                const double2 lk = l > k ? sd[l][k] : make_double2(0.0, 0.0);
                 t = zfms(t, lk, yk);
             }
             if (tid < 16) sx[r0 + l] = t;
@@ -674,23 +701,19 @@ __device__ void lu_apply_inverse(const T2 *__restrict__ A, const int *__restrict
     // backward: U x = y
     for (int r0 = NP - 16; r0 >= 0; r0 -= 16) {
         const T2 *row = A + (size_t)(r0 + r) * NP;
-        double2 acc = dot_run(row, sx, r0 + 16 + q, NP);
-#pragma unroll
-        for (int off = 8; off >= 1; off >>= 1) {
-            acc.x += __shfl_xor(acc.x, off);
-            acc.y += __shfl_xor(acc.y, off);
-        }
+        if (q < 16) sd[r][q] = ld2(row[r0 + q]);
+        const double2 acc = wave_sum(dot_run(row, sx, r0 + 16 + q, NP));
         if (q == 0) st[r] = make_double2(sx[r0 + r].x - acc.x, sx[r0 + r].y - acc.y);
         __syncthreads();
         if (tid < 64) {
             const int l = tid & 15;
             double2 t = st[l];
+#pragma unroll
             for (int k = 15; k >= 0; --k) {
                 // lane k finishes x_k; the lanes of the rows above subtract its term
-                if (l == k) t = zmul(t, zinv(ld2(A[(size_t)(r0 + k) * NP + r0 + k])));
+                if (l == k) t = zmul(t, zinv(sd[k][k]));
                 const double2 xk = make_double2(__shfl(t.x, k), __shfl(t.y, k));
-                const double2 uk =
-                    l < k ? ld2(A[(size_t)(r0 + l) * NP + r0 + k]) : make_double2(0.0, 0.0);
+                const double2 uk = l < k ? sd[l][k] : make_double2(0.0, 0.0);
                 t = zfms(t, uk, xk);
             }
             if (tid < 16) sx[r0 + l] = t;
@@ -702,7 +725,7 @@ __device__ void lu_apply_inverse(const T2 *__restrict__ A, const int *__restrict
 // Outputs of a solved system: forward I[s][k]; adjoint gsys[s][k] =
 // 2 Re(mu_k I_k / (j w C_k^2)) (and mu when asked for); status bits.
 template <int RHS>
-__device__ void write_solution(int n, int s, double w, const double *__restrict__ Cb,
+__device__ __forceinline__ void write_solution(int n, int s, double w, const double *__restrict__ Cb,
                                const double2 *sx, double2 *__restrict__ I,
                                double *__restrict__ gsys, double2 *__restrict__ mu,
                                int32_t *__restrict__ status, int *sFlag) {
@@ -710,7 +733,7 @@ __device__ void write_solution(int n, int s, double w, const double *__restrict_
     const int flag = status[s];
     const bool bad = (flag & (COSIM_SYS_BAD_INPUT | COSIM_SYS_SINGULAR)) != 0;
     int oflag = 0;
-    for (int k = tid; k < n; k += kTB) {
+    for (int k = tid; k < n; k += kTS) {
         double2 x = sx[k];
         if (bad) x = make_double2(__builtin_nan(""), __builtin_nan(""));
         if (RHS == kRhsExcitation) {
@@ -735,7 +758,7 @@ __device__ void write_solution(int n, int s, double w, const double *__restrict_
 // set): right-hand side, the two triangular solves with the FP64 record,
 // outputs.
 template <int RHS>
-__global__ __launch_bounds__(kTB) void k_lu_solve(int n, int NP, int S, int F,
+__global__ __launch_bounds__(kTS) void k_lu_solve(int n, int NP, int S, int F,
                                                   const double2 *__restrict__ Aall,
                                                   const int *__restrict__ pivall,
                                                   const double *__restrict__ phi,
@@ -749,6 +772,7 @@ __global__ __launch_bounds__(kTB) void k_lu_solve(int n, int NP, int S, int F,
                                                   const int *__restrict__ only, int want) {
     __shared__ double2 sx[kMaxLoopsBig];
     __shared__ double2 st[16];
+    __shared__ double2 sd[16][17];
     __shared__ int sFlag;
     const int s = blockIdx.x;
     if (s >= S) return;
@@ -756,17 +780,18 @@ __global__ __launch_bounds__(kTB) void k_lu_solve(int n, int NP, int S, int F,
     const int tid = threadIdx.x;
     const int b = s / F, f = s - b * F;
     const double w = omega[f];
-    for (int k = tid; k < NP; k += kTB)
+    for (int k = tid; k < NP; k += kTS)
         sx[k] = k < n ? rhs_entry<RHS>(k, n, NP, S, s, w, phi, rhs, nchunk, rscale)
                       : make_double2(0.0, 0.0);
     if (tid == 0) sFlag = 0;
     __syncthreads();
-    lu_apply_inverse<double2, true>(Aall + (size_t)s * NP * NP, pivall + (size_t)s * NP, NP, sx, st);
+    lu_apply_inverse<double2, true>(Aall + (size_t)s * NP * NP, pivall + (size_t)s * NP, NP, sx, st,
+                                    sd);
     write_solution<RHS>(n, s, w, C + (size_t)b * n, sx, I, gsys, mu, status, &sFlag);
 }
 
-// Largest of a and b over the workgroup, NaN taken as +inf; every thread
-// returns with both.  sm: 2 kTB/64 entries of LDS scratch.
+// Largest of a and b over the kTS threads, NaN taken as +inf; every thread
+// returns with both.  sm: 2 kTS/64 entries of LDS scratch.
 __device__ inline void block_max2(double &a, double &b, double *sm) {
     if (!(a == a)) a = __builtin_inf();
     if (!(b == b)) b = __builtin_inf();
@@ -784,7 +809,7 @@ __device__ inline void block_max2(double &a, double &b, double *sm) {
     a = sm[0];
     b = sm[1];
 #pragma unroll
-    for (int v = 1; v < kTB / 64; ++v) {
+    for (int v = 1; v < kTS / 64; ++v) {
         a = fmax(a, sm[2 * v]);
         b = fmax(b, sm[2 * v + 1]);
     }
@@ -803,7 +828,7 @@ __device__ inline void block_max2(double &a, double &b, double *sm) {
 // max_iter steps is marked fail_fmt, writes nothing and is left to the
 // pivoted FP64 fallback.
 template <int RHS>
-__global__ __launch_bounds__(kTB) void k_solve_refined(
+__global__ __launch_bounds__(kTS) void k_solve_refined(
     int n, int NP, int S, int F, const float2 *__restrict__ A32all,
     const double *__restrict__ M, const double *__restrict__ Rv, const double *__restrict__ phi,
     const double *__restrict__ C, const double *__restrict__ omega, double2 *__restrict__ I,
@@ -814,7 +839,8 @@ __global__ __launch_bounds__(kTB) void k_solve_refined(
     __shared__ double2 sx[kMaxLoopsBig];
     __shared__ double2 sr[kMaxLoopsBig];
     __shared__ double2 st[16];
-    __shared__ double sm[2 * (kTB / 64)];
+    __shared__ double2 sd[16][17];
+    __shared__ double sm[2 * (kTS / 64)];
     __shared__ int sFlag;
     const int s = blockIdx.x;
     if (s >= S) return;
@@ -824,7 +850,7 @@ __global__ __launch_bounds__(kTB) void k_solve_refined(
     const double w = omega[f];
     const double *Cb = C + (size_t)b * n;
     const float2 *A = A32all + (size_t)s * NP * NP;
-    for (int k = tid; k < NP; k += kTB) {
+    for (int k = tid; k < NP; k += kTS) {
         const double2 v = k < n ? rhs_entry<RHS>(k, n, NP, S, s, w, phi, rhs, nchunk, rscale)
                                 : make_double2(0.0, 0.0);
         sb[k] = v;
@@ -832,26 +858,33 @@ __global__ __launch_bounds__(kTB) void k_solve_refined(
     }
     if (tid == 0) sFlag = 0;
     __syncthreads();
-    lu_apply_inverse<float2, false>(A, nullptr, NP, sr, st);
-    double prev = 0.0, xm = 0.0;
-    for (int k = tid; k < NP; k += kTB) {
-        const double2 x = sr[k];
-        sx[k] = x;
-        prev = fmax(prev, fabs(x.x) + fabs(x.y));
-    }
-    block_max2(prev, xm, sm);  // |d_0| = |x_0|
-    const int r = tid >> 4, q = tid & 15;
+    const int r = tid >> 6, q = tid & 63;  // wave r takes row r0 + r of each block
     bool done = false;
-    for (int it = 0; it < max_iter && !done; ++it) {
+    double prev = 0.0;
+    // step 0 solves for x_0 (d_0 = x_0); step i >= 1 for the correction d_i
+    for (int it = 0; it <= max_iter; ++it) {
+        lu_apply_inverse<float2, false>(A, nullptr, NP, sr, st, sd);
+        double dm = 0.0, xm = 0.0;
+        for (int k = tid; k < NP; k += kTS) {
+            const double2 d = sr[k];
+            double2 x = it == 0 ? make_double2(0.0, 0.0) : sx[k];
+            x.x += d.x;
+            x.y += d.y;
+            sx[k] = x;
+            dm = fmax(dm, fabs(d.x) + fabs(d.y));
+            xm = fmax(xm, fabs(x.x) + fabs(x.y));
+            if (!(d.x == d.x && d.y == d.y)) dm = __builtin_inf();
+        }
+        block_max2(dm, xm, sm);  // also orders the x updates before the residual
+        if (it > 0) done = dm < __builtin_inf() && dm * dm <= tol * xm * prev && dm <= 0.5 * prev;
+        prev = dm;
+        if (done || it == max_iter) break;
+        // r = b - Z x
         for (int r0 = 0; r0 < NP; r0 += 16) {
             const int i = r0 + r;
             double2 acc = make_double2(0.0, 0.0);
             if (i < n) acc = dot_real_run(M + (size_t)i * n, sx, q, n);
-#pragma unroll
-            for (int off = 8; off >= 1; off >>= 1) {
-                acc.x += __shfl_xor(acc.x, off);
-                acc.y += __shfl_xor(acc.y, off);
-            }
+            acc = wave_sum(acc);
             if (q == 0) {
                 double2 v = make_double2(0.0, 0.0);
                 if (i < n) {
@@ -865,22 +898,6 @@ __global__ __launch_bounds__(kTB) void k_solve_refined(
             }
         }
         __syncthreads();
-        lu_apply_inverse<float2, false>(A, nullptr, NP, sr, st);
-        double dm = 0.0;
-        xm = 0.0;
-        for (int k = tid; k < NP; k += kTB) {
-            const double2 d = sr[k];
-            double2 x = sx[k];
-            x.x += d.x;
-            x.y += d.y;
-            sx[k] = x;
-            dm = fmax(dm, fabs(d.x) + fabs(d.y));
-            xm = fmax(xm, fabs(x.x) + fabs(x.y));
-            if (!(d.x == d.x && d.y == d.y)) dm = __builtin_inf();
-        }
-        block_max2(dm, xm, sm);
-        done = dm < __builtin_inf() && dm * dm <= tol * xm * prev && dm <= 0.5 * prev;
-        prev = dm;
     }
     if (!done) {
         if (tid == 0) fmt[s] = fail_fmt;
@@ -935,7 +952,7 @@ hipError_t lu_solve_launch(int NP, int n, int S, int F, const double2 *A_d, cons
                            double2 *I_d, const void *rhs_d, int nchunk, double rscale,
                            double *gsys_d, double2 *mu_d, int32_t *status_d, const int *only,
                            int want, hipStream_t st) {
-    hipLaunchKernelGGL(k_lu_solve<RHS>, dim3(S), dim3(kTB), 0, st, n, NP, S, F, A_d, piv_d, phi_d,
+    hipLaunchKernelGGL(k_lu_solve<RHS>, dim3(S), dim3(kTS), 0, st, n, NP, S, F, A_d, piv_d, phi_d,
                        C_d, omega_d, I_d, rhs_d, nchunk, rscale, gsys_d, mu_d, status_d, only,
                        want);
     return hipGetLastError();
@@ -965,7 +982,7 @@ hipError_t refined_launch(const BigRefine &rf, int NP, int n, int S, int F, cons
                           const double *omega_d, double2 *I_d, const void *rhs_d, int nchunk,
                           double rscale, double *gsys_d, double2 *mu_d, int32_t *status_d,
                           int *fmt, int fail_fmt, hipStream_t st) {
-    hipLaunchKernelGGL(k_solve_refined<RHS>, dim3(S), dim3(kTB), 0, st, n, NP, S, F,
+    hipLaunchKernelGGL(k_solve_refined<RHS>, dim3(S), dim3(kTS), 0, st, n, NP, S, F,
                        (const float2 *)rf.A32, M_d, R_d, phi_d, C_d, omega_d, I_d, rhs_d, nchunk,
                        rscale, gsys_d, mu_d, status_d, fmt, fail_fmt, rf.max_iter, rf.tol);
     return hipGetLastError();
