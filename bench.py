@@ -170,10 +170,22 @@ def ragged_line(n_inst: int, mixed: str, steps: int, torch) -> dict:
         loss_and_grad_many(plans, Cs, Os, Ts, precision=PREC_CODE[mixed], outs=outs)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
+    # the same call captured once in a HIP graph and replayed
+    from paper_2503_18479_amd import capture_loss_and_grad_many
+    gr, gouts = capture_loss_and_grad_many(plans, Cs, Os, Ts, precision=PREC_CODE[mixed])
+    gr.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        gr.replay()
+    torch.cuda.synchronize()
+    dt_graph = (time.perf_counter() - t0) / steps
+    same = all(torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]) for a, b in zip(outs, gouts))
     bad = sum(int((o[2] != 0).sum()) for o in outs)
     systems = sum(wl.B * wl.F for wl in wls)
     flops = sum(8.0 * wl.P * wl.geom.n * wl.B * wl.F for wl in wls)
     return {"instances": n_inst, "instance_evals_per_s": n_inst / dt, "ms_per_step": 1e3 * dt,
+            "ms_per_step_graph": 1e3 * dt_graph, "graph_equals_eager": same,
             "steps": steps, "systems": systems, "contraction_tflops": flops / dt / 1e12,
             "loops": sorted(set(wl.geom.n for wl in wls)), "points_min": min(wl.P for wl in wls),
             "points_max": max(wl.P for wl in wls), "flagged_systems": bad,
@@ -499,7 +511,8 @@ def main():
     if args.ragged > 0:
         print(f"[bench] ragged configuration: {args.ragged} instances", file=sys.stderr, flush=True)
         line["ragged"] = ragged_line(args.ragged, args.mixed, 3, torch)
-        print(f"[bench] ragged: {line['ragged']['ms_per_step']:.1f} ms per step", file=sys.stderr,
+        print(f"[bench] ragged: {line['ragged']['ms_per_step']:.1f} ms per step, "
+              f"{line['ragged']['ms_per_step_graph']:.1f} ms replayed from a graph", file=sys.stderr,
               flush=True)
     if args.large_adam > 0:
         print("[bench] 32x32 array", file=sys.stderr, flush=True)

@@ -344,6 +344,26 @@ def loss_and_grad_many(plans, Cs, omegas, Ts, loss_mode: int = LOSS_MAG, precisi
     return outs
 
 
+def capture_loss_and_grad_many(plans, Cs, omegas, Ts, loss_mode: int = LOSS_MAG,
+                               precision=FP32, grad: bool = True):
+    """One loss_and_grad_many call over the instances captured in a HIP graph.
+    Each plan's workspace is reserved for its batch and a first call runs
+    outside the capture (on a side stream).  Returns (graph, outs): replaying
+    the graph recomputes outs from the current contents of Cs, omegas and Ts
+    (update them in place); a call of many small launches becomes one launch."""
+    for pl, C, o in zip(plans, Cs, omegas):
+        pl.reserve(int(C.shape[0]), int(o.shape[0]))
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        outs = loss_and_grad_many(plans, Cs, omegas, Ts, loss_mode, precision, grad)
+    torch.cuda.current_stream().wait_stream(side)
+    gr = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(gr):
+        loss_and_grad_many(plans, Cs, omegas, Ts, loss_mode, precision, grad, outs=outs)
+    return gr, outs
+
+
 def adam_step(C: torch.Tensor, grad: torch.Tensor, m: torch.Tensor, v: torch.Tensor,
               step: torch.Tensor, lr: float = 1e-13, betas=(0.9, 0.999), eps: float = 1e-8) -> None:
     """One cosim_adam_step on C (in place); m, v, step are the caller's state."""

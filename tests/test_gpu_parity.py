@@ -1138,3 +1138,34 @@ def test_refined_1024_loops(dev):
         assert int(st.abs().sum()) == 0
         assert np.max(np.abs(loss.cpu().numpy() - Lr) / Lr) < TOL[prec]
         assert np.max(_nrel(grad.cpu().numpy(), gr, axis=1)) < TOL[prec]
+
+
+# ------------------------------------------- ragged instances in a HIP graph
+
+def test_ragged_graph_replay_matches_eager(dev):
+    """cosim_loss_and_grad_many captured once (6, 25 and 81 loops: fused
+    kernels, side streams and the GEMM path) and replayed three times, each
+    after eager work with new capacitances; every replay equals the eager
+    call bit for bit."""
+    from paper_2503_18479_amd import (Geometry, Plan, loss_and_grad_many,
+                                      capture_loss_and_grad_many)
+    wls = [W.small_array(3, 2, batch=5, grid=20, n_freq=3, seed=31),
+           W.small_array(5, 5, batch=4, grid=17, n_freq=2, seed=32),
+           W.small_array(9, 9, batch=3, grid=40, n_freq=2, seed=33)]
+    plans = [Plan(Geometry.from_workload(w.geom), torch.tensor(w.pts, device=dev), w.bext_z)
+             for w in wls]
+    Cs = [torch.tensor(w.C, device=dev) for w in wls]
+    Os = [torch.tensor(w.omega, device=dev) for w in wls]
+    Ts = [torch.tensor(w.target, device=dev) for w in wls]
+    for prec in (0, 2):
+        gr, gouts = capture_loss_and_grad_many(plans, Cs, Os, Ts, precision=prec)
+        for rep in range(3):
+            for C in Cs:
+                C.mul_(1.0 + 0.01 * (rep + 1))
+            ref = loss_and_grad_many(plans, Cs, Os, Ts, precision=prec)
+            torch.cuda.synchronize()
+            gr.replay()
+            torch.cuda.synchronize()
+            for (l, g, s), (lr, g_r, sr) in zip(gouts, ref):
+                assert torch.equal(l, lr) and torch.equal(g, g_r) and torch.equal(s, sr), (prec, rep)
+        del gr
