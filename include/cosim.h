@@ -309,8 +309,9 @@ int cosim_adam_step(int count, double *C_d, const double *grad_d, double *m_d, d
  * and the device pointers of instance i with the meaning and shapes of
  * cosim_loss_and_grad (grad_d may be NULL for loss only, or hold NULL
  * entries).  Every instance is validated before anything is enqueued; an
- * error names the instance.  The instances run on 8 library-owned side
- * streams (default priority) that wait for `stream` and that `stream` waits
+ * error names the instance.  The instances run on 16 library-owned side
+ * streams (default priority; the largest instances first, each to the stream
+ * with the least work so far) that wait for `stream` and that `stream` waits
  * for when the call returns, so the work is ordered on `stream` as one
  * operation and can be captured with it.  Each plan's own workspace is used:
  * reserve every plan beforehand to keep the call allocation-free. */

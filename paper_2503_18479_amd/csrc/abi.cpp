@@ -277,7 +277,7 @@ struct StreamPool {
     std::vector<hipEvent_t> done;
     hipEvent_t start = nullptr;
 };
-constexpr int kPoolStreams = 8;
+constexpr int kPoolStreams = 16;
 
 int stream_pool(int device, StreamPool **out) {
     static std::mutex mu;
@@ -956,11 +956,25 @@ int cosim_loss_and_grad_many(int count, const cosim_plan_t *plans, const int *B,
     HIP_TRY(hipEventRecord(pool->start, st));
     const int ns = std::min(kPoolStreams, count);
     for (int k = 0; k < ns; ++k) HIP_TRY(hipStreamWaitEvent(pool->streams[k], pool->start, 0));
+    // largest instances first, each to the stream with the least work so far
+    // (work ~ systems x (NP^3 for the solves + P NP for the contraction))
+    std::vector<double> cost(count);
+    std::vector<int> order(count);
+    for (int i = 0; i < count; ++i) {
+        const double S = (double)B[i] * F[i], np = (double)plans[i]->NP;
+        cost[i] = S * (np * np * np + (double)plans[i]->P * np);
+        order[i] = i;
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    std::vector<double> load(ns, 0.0);
     int first_rc = COSIM_OK;
-    for (int i = 0; i < count && first_rc == COSIM_OK; ++i) {
+    for (int j = 0; j < count && first_rc == COSIM_OK; ++j) {
+        const int i = order[j];
+        const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        load[k] += cost[i];
         if ((rc = cosim_loss_and_grad(plans[i], B[i], F[i], C_d[i], omega_d[i], T_d[i], loss_mode,
                                       precision, loss_d[i], grad_d ? grad_d[i] : nullptr,
-                                      status_d[i], pool->streams[i % ns])))
+                                      status_d[i], pool->streams[k])))
             first_rc = fail_instance(rc, i);
     }
     for (int k = 0; k < ns; ++k) {  // join even after an error
