@@ -254,8 +254,8 @@ int cosim_loss_and_grad(cosim_plan_t p, int B, int F, const double *C_d, const d
  *   gL_d     [B][n] or NULL: dL_b/dL_k of a series inductance added to loop k
  *            (Z_kk += j w L_k), 2 sum_f w Im(mu_k I_k);
  *   gomega_d [B][F] or NULL: dL_b/dw_f = 2 [Im(mu^T Phi) + Im(mu^T M I)
- *            + sum_k Im(mu_k I_k) / (w^2 C_k)] (V = -j w Phi and Z both depend
- *            on w; G does not);
+ *            + sum_k Im(mu_k I_k) / (w^2 C_k)] (V = E - j w Phi and Z both
+ *            depend on w; G and the EMF E of driven ports do not);
  * with mu the adjoint solution of each system (Z mu = G^T conj(w), Eq. 8-10;
  * Z is complex symmetric).  gC_d is required (the adjoint always runs).
  * Allocates a [S][n] workspace for mu on first use at a new size.  Systems with

@@ -81,7 +81,7 @@ __host__ __device__ constexpr int ldl_col(int NP, int k) { return k * (2 * NP - 
 constexpr int kFlagPivot = 1 << 16;  // kernel-internal status bit, never returned
 
 // LDL^T fast path (all R_k > 0): factorises and records, leaves
-// z = D^-1 L^-1 (-j w Phi) in I_d for launch_replay_forward; marks systems
+// z = D^-1 L^-1 (E - j w Phi) in I_d for launch_replay_forward; marks systems
 // that need pivoting (fmt = kFmtNeedsPivot) for launch_solve_fallback.
 hipError_t launch_ldl(int NP, int n, int S, int F, const double *M_d, const double *R_d,
                       const double *C_d, const double *omega_d, const double *phi_d, GJFactor fac,
@@ -91,7 +91,7 @@ hipError_t launch_solve_fallback(int NP, int n, int S, int F, const double *M_d,
                                  const double *R_d, const double *phi_d, const double *C_d,
                                  const double *omega_d, double2 *I_d, int32_t *status_d,
                                  GJFactor fac, hipStream_t st);
-// Forward solve I = Z^-1 (-j w Phi) of the kFmtLDL systems: the backward
+// Forward solve I = Z^-1 (E - j w Phi) of the kFmtLDL systems: the backward
 // substitution from the z that launch_ldl left in I_d.
 hipError_t launch_replay_forward(int NP, int n, int S, int F, GJFactor fac,
                                  const double *omega_d, double2 *I_d, int32_t *status_d,
@@ -103,7 +103,7 @@ hipError_t launch_replay_adjoint(int NP, int n, int S, int F, GJFactor fac, cons
                                  int nchunk, double rscale, double *gsys_d, double2 *mu_d,
                                  int32_t *status_d, hipStream_t st);
 
-// Forward solve by pivoted Gauss-Jordan: Z I = -j w Phi for S = B*F systems
+// Forward solve by pivoted Gauss-Jordan: Z I = E - j w Phi for S = B*F systems
 // (s = b*F + f); records the elimination (kFmtGJ) in `fac` when fac.L is set.
 hipError_t launch_solve_forward(int NP, int n, int S, int F, const double *M_d,
                                 const double *R_d, const double *phi_d, const double *C_d,
@@ -153,7 +153,7 @@ int fused_systems_per_block(Prec prec, int NP, int variant);
 // and GEMM-based contractions (contract_big.hip).
 // Right-hand side of launch_lu_solve.
 enum BigRhs {
-    kRhsExcitation = 0,  // -j w Phi, writes I
+    kRhsExcitation = 0,  // E - j w Phi (loop_voltage), writes I
     kRhsPairs = 1,       // rpart[c][s][k] (rr, ri) FP64 pairs, writes gsys
     kRhsPlanarF32 = 2,   // R[c] NP x 2S FP32 planes, writes gsys
     kRhsPlanarF64 = 3    // R[c] NP x 2S FP64 planes, writes gsys

@@ -2,7 +2,8 @@
 // helpers of the optimisation around C (Sec. IV-A, Sec. V):
 //   k_param_sys    per system, from the currents I and the adjoint solution mu
 //                  (Z mu = G^T conj(w); Z is complex symmetric, so
-//                  dL = 2 Re(mu^T (dV - dZ I)) with V = -j w Phi):
+//                  dL = 2 Re(mu^T (dV - dZ I)) with V = E - j w Phi, E the
+//                  source EMF of driven ports, independent of w):
 //                    dL/dR_k = -2 Re(mu_k I_k)          (dZ = e_k e_k^T),
 //                    dL/dL_k =  2 w Im(mu_k I_k)        (a series inductance
 //                                                        added to loop k: dZ = j w e_k e_k^T),

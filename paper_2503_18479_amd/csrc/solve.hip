@@ -88,7 +88,7 @@ __device__ inline double readlane_d(double x, int src) {
     return __hiloint2double(hi, lo);
 }
 
-// ADJ = false: rhs = -j w Phi, writes I[s][k].
+// ADJ = false: rhs = E - j w Phi (loop_voltage), writes I[s][k].
 // ADJ = true : rhs = rscale * sum_c (rr - j ri) of rpart[c][s][:], writes
 //              gsys[s][k] = 2 Re(mu_k I_k / (j w C_k^2)).
 //
@@ -495,7 +495,7 @@ __device__ inline double wave_sum16(const double (&v)[16], int lane) {
 //      A -= L21 V21^T as four 16x16x4 FP64 MFMAs (complex = 4 real products).
 // Columns left of the trailing part also receive updates; they are finished
 // and never read again.  The factor is recorded (L by columns, D^-1) for the
-// replay kernels, and the forward right-hand side b = -j w Phi rides along:
+// replay kernels, and the forward right-hand side b = E - j w Phi rides along:
 // y = L^-1 b is formed panel by panel and z = D^-1 y is written to Z, so that
 // the forward replay only runs the backward substitution.  A system whose smallest pivot is below 1e-5 of its largest
 // impedance diagonal (or is not finite) is marked for the pivoted fallback.

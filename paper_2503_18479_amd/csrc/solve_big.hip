@@ -1,5 +1,5 @@
 // Batched FP64 complex solves for more than 64 loops (NP a multiple of 64, up
-// to kMaxLoopsBig): Z I = -j w Phi (Eq. 6 in impedance form) and, Z being
+// to kMaxLoopsBig): Z I = E - j w Phi (Eq. 6 in impedance form) and, Z being
 // complex symmetric, the adjoint Z mu = r with the same factor.
 //
 // One workgroup per (configuration, frequency) system; Z and its factor live
