@@ -76,7 +76,8 @@ enum cosim_loss {
 
 /* Per-system status bits written to status_d[b*F + f]. */
 enum cosim_sys_status {
-    COSIM_SYS_BAD_INPUT = 1,  /* C_k or omega is zero or not finite (outputs NaN) */
+    COSIM_SYS_BAD_INPUT = 1,  /* C_k zero or NaN, or omega zero or not finite (outputs NaN);
+                                 C_k = +INFINITY is a loop without a capacitor */
     COSIM_SYS_SINGULAR = 2,   /* zero pivot in the elimination (outputs NaN) */
     COSIM_SYS_NONFINITE = 4,  /* result not finite */
     COSIM_SYS_NEGATIVE_C = 8  /* some C_k < 0: accepted (the feasible set is unbounded), flagged */
