@@ -334,12 +334,14 @@ __global__ __launch_bounds__(kTB) void k_big_assemble(int n, int NP, int S, int 
 
 // Step 1 of the blocked LDL^T: the diagonal block at k0 (lower triangle in
 // HBM) factored in LDS by columns, V (= L D, unscaled) kept in place:
-//   a_rc2 -= v_r v_c2 / d_c  for c < c2 <= r,
-// while the same eliminations turn an identity into X = L11^-1:
-//   x_rc2 -= l_rc x_cc2  for c2 <= c < r.
+//   a_rc2 -= v_r v_c2 / d_c  for c < c2 <= r.
+// Then X = L11^-1 of the unit lower L = V D^-1 in 16x16 blocks: the diagonal
+// blocks column by column (64 independent substitutions of length 16), then
+// X_ij = -X_ii sum_(j <= k < i) L_ik X_kj block by block, for i - j = 1, 2, 3
+// (whole blocks at once, one entry per thread).
 // Written back: L_rc = v_rc / d_c below the diagonal, d_c on it, U_cr = v_rc
 // above it, identity swaps, and T = X^T = L11^-T ([64][64] per system) for
-// step 2; a pivot below 1e-5 zmax marks the system.  The elimination is FP64
+// step 2; a pivot below 1e-5 zmax marks the system.  The arithmetic is FP64
 // for either storage type.
 template <typename T2>
 __global__ __launch_bounds__(kTB) void k_ldl_big_diag(int NP, int k0, int S,
@@ -367,7 +369,49 @@ __global__ __launch_bounds__(kTB) void k_ldl_big_diag(int NP, int k0, int S,
             const double2 dinv = zinv(sa[c][c]);
             const double2 l = zmul(sa[rr][c], dinv);
             for (int c2 = c + 1 + q; c2 <= rr; c2 += 4) sa[rr][c2] = zfms(sa[rr][c2], l, sa[c2][c]);
-            for (int c2 = q; c2 <= c; c2 += 4) sx[rr][c2] = zfms(sx[rr][c2], l, sx[c][c2]);
+        }
+        __syncthreads();
+    }
+    // X = L^-1, L_rc = v_rc / d_c (sx holds the identity, so the blocks above
+    // the diagonal stay zero)
+    __shared__ double2 sdi[64];
+    __shared__ double2 sw[3][16][17];
+    if (tid < 64) sdi[tid] = zinv(sa[tid][tid]);
+    __syncthreads();
+    if (tid < 64) {  // diagonal block j, column k
+        const int j = tid >> 4, k = tid & 15, b0 = 16 * j;
+        double2 x[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            double2 acc = make_double2(i == k ? 1.0 : 0.0, 0.0);
+#pragma unroll
+            for (int m = 0; m < i; ++m)
+                if (m >= k) acc = zfms(acc, zmul(sa[b0 + i][b0 + m], sdi[b0 + m]), x[m]);
+            x[i] = i < k ? make_double2(0.0, 0.0) : acc;
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) sx[b0 + i][b0 + k] = x[i];
+    }
+    __syncthreads();
+    for (int d = 1; d < 4; ++d) {
+        const int npair = 4 - d;  // blocks (j + d, j), j < npair
+        for (int e = tid; e < npair * 256; e += kTB) {  // W = sum_k L_ik X_kj
+            const int j = e >> 8, r = (e >> 4) & 15, c = e & 15, i = j + d;
+            double2 acc = make_double2(0.0, 0.0);
+            for (int kb = j; kb < i; ++kb)
+#pragma unroll 4
+                for (int m = 0; m < 16; ++m)
+                    acc = zfma(acc, zmul(sa[16 * i + r][16 * kb + m], sdi[16 * kb + m]),
+                               sx[16 * kb + m][16 * j + c]);
+            sw[j][r][c] = acc;
+        }
+        __syncthreads();
+        for (int e = tid; e < npair * 256; e += kTB) {  // X_ij = -X_ii W
+            const int j = e >> 8, r = (e >> 4) & 15, c = e & 15, i = j + d;
+            double2 acc = make_double2(0.0, 0.0);
+#pragma unroll 4
+            for (int m = 0; m < 16; ++m) acc = zfms(acc, sx[16 * i + r][16 * i + m], sw[j][m][c]);
+            sx[16 * i + r][16 * j + c] = acc;
         }
         __syncthreads();
     }
