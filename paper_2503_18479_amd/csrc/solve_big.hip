@@ -333,8 +333,11 @@ __global__ __launch_bounds__(kTB) void k_big_assemble(int n, int NP, int S, int 
 }
 
 // Step 1 of the blocked LDL^T: the diagonal block at k0 (lower triangle in
-// HBM) factored in LDS by columns, V (= L D, unscaled) kept in place:
-//   a_rc2 -= v_r v_c2 / d_c  for c < c2 <= r.
+// HBM) factored in LDS, V (= L D, unscaled) kept in place,
+//   a_rc2 -= v_r v_c2 / d_c  for c < c2 <= r,
+// in four sub-panels of 16 columns: column by column inside the sub-panel
+// (each step touches at most 15 columns), then the rest of the block at once,
+// 16 terms per entry with the thread's own row of the sub-panel in registers.
 // Then X = L11^-1 of the unit lower L = V D^-1 in 16x16 blocks: the diagonal
 // blocks column by column (64 independent substitutions of length 16), then
 // X_ij = -X_ii sum_(j <= k < i) L_ik X_kj block by block, for i - j = 1, 2, 3
@@ -364,20 +367,35 @@ __global__ __launch_bounds__(kTB) void k_ldl_big_diag(int NP, int k0, int S,
     }
     __syncthreads();
     const int rr = tid >> 2, q = tid & 3;  // four threads per row
-    for (int c = 0; c < 63; ++c) {
-        if (rr > c) {
-            const double2 dinv = zinv(sa[c][c]);
-            const double2 l = zmul(sa[rr][c], dinv);
-            for (int c2 = c + 1 + q; c2 <= rr; c2 += 4) sa[rr][c2] = zfms(sa[rr][c2], l, sa[c2][c]);
+    __shared__ double2 sdi[64];          // D^-1
+    __shared__ double2 sw[3][16][17];
+    for (int c0 = 0; c0 < 64; c0 += 16) {
+        const int ce = c0 + 15;  // last column of the sub-panel
+        for (int c = c0; c < c0 + 16; ++c) {
+            if (rr > c) {
+                const double2 l = zmul(sa[rr][c], zinv(sa[c][c]));
+                const int hi = min(rr, ce);
+                for (int c2 = c + 1 + q; c2 <= hi; c2 += 4) sa[rr][c2] = zfms(sa[rr][c2], l, sa[c2][c]);
+            }
+            __syncthreads();
+        }
+        if (tid < 16) sdi[c0 + tid] = zinv(sa[c0 + tid][c0 + tid]);
+        __syncthreads();
+        if (c0 + 16 < 64 && rr >= c0 + 16) {
+            double2 w[16];  // row rr of the sub-panel, scaled by D^-1
+#pragma unroll
+            for (int m = 0; m < 16; ++m) w[m] = zmul(sa[rr][c0 + m], sdi[c0 + m]);
+            for (int c2 = c0 + 16 + q; c2 <= rr; c2 += 4) {
+                double2 acc = sa[rr][c2];
+#pragma unroll
+                for (int m = 0; m < 16; ++m) acc = zfms(acc, w[m], sa[c2][c0 + m]);
+                sa[rr][c2] = acc;
+            }
         }
         __syncthreads();
     }
     // X = L^-1, L_rc = v_rc / d_c (sx holds the identity, so the blocks above
     // the diagonal stay zero)
-    __shared__ double2 sdi[64];
-    __shared__ double2 sw[3][16][17];
-    if (tid < 64) sdi[tid] = zinv(sa[tid][tid]);
-    __syncthreads();
     if (tid < 64) {  // diagonal block j, column k
         const int j = tid >> 4, k = tid & 15, b0 = 16 * j;
         double2 x[16];
