@@ -276,8 +276,64 @@ struct StreamPool {
     std::vector<hipStream_t> streams;
     std::vector<hipEvent_t> done;
     hipEvent_t start = nullptr;
+    std::vector<hipEvent_t> extra;  // ordering of grouped instances
+    // factor records of grouped instances, sized for the largest call so far
+    double2 *gA = nullptr, *gWt = nullptr, *gTinv = nullptr;
+    int *gPiv = nullptr, *gFmt = nullptr;
+    double *gZmax = nullptr;
+    size_t capA = 0, capWt = 0, capTinv = 0, capPiv = 0, capSys = 0;
 };
 constexpr int kPoolStreams = 16;
+
+// At least `count` events in pool->extra.
+int pool_events(StreamPool *pool, size_t count) {
+    while (pool->extra.size() < count) {
+        hipEvent_t ev = nullptr;
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(COSIM_EDEVICE, "creating events failed");
+        }
+        pool->extra.push_back(ev);
+    }
+    return COSIM_OK;
+}
+
+// Group workspace of at least the given sizes (elements).  Growing it waits
+// for the device first: earlier calls may still be using the old buffers.
+int pool_group_ws(StreamPool *pool, size_t nA, size_t nWt, size_t nTinv, size_t nPiv, size_t nSys) {
+    if (nA <= pool->capA && nWt <= pool->capWt && nTinv <= pool->capTinv && nPiv <= pool->capPiv &&
+        nSys <= pool->capSys)
+        return COSIM_OK;
+    HIP_TRY(hipDeviceSynchronize());
+    dfree(pool->gA);
+    dfree(pool->gWt);
+    dfree(pool->gTinv);
+    dfree(pool->gPiv);
+    dfree(pool->gFmt);
+    dfree(pool->gZmax);
+    pool->capA = pool->capWt = pool->capTinv = pool->capPiv = pool->capSys = 0;
+    if (hipMalloc((void **)&pool->gA, nA * sizeof(double2)) != hipSuccess ||
+        hipMalloc((void **)&pool->gWt, nWt * sizeof(double2)) != hipSuccess ||
+        hipMalloc((void **)&pool->gTinv, nTinv * sizeof(double2)) != hipSuccess ||
+        hipMalloc((void **)&pool->gPiv, nPiv * sizeof(int)) != hipSuccess ||
+        hipMalloc((void **)&pool->gFmt, nSys * sizeof(int)) != hipSuccess ||
+        hipMalloc((void **)&pool->gZmax, nSys * sizeof(double)) != hipSuccess) {
+        dfree(pool->gA);
+        dfree(pool->gWt);
+        dfree(pool->gTinv);
+        dfree(pool->gPiv);
+        dfree(pool->gFmt);
+        dfree(pool->gZmax);
+        (void)hipGetLastError();
+        return fail(COSIM_ENOMEM, "group workspace allocation failed");
+    }
+    pool->capA = nA;
+    pool->capWt = nWt;
+    pool->capTinv = nTinv;
+    pool->capPiv = nPiv;
+    pool->capSys = nSys;
+    return COSIM_OK;
+}
 
 int stream_pool(int device, StreamPool **out) {
     static std::mutex mu;
@@ -948,34 +1004,197 @@ int cosim_loss_and_grad_many(int count, const cosim_plan_t *plans, const int *B,
         if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
             return fail(COSIM_EINVAL, "a plan appears more than once");
     }
-    // instances run on side streams (round robin) that wait for `stream` and
-    // that `stream` waits for afterwards
+    // instances run on side streams that wait for `stream` and that `stream`
+    // waits for afterwards
     StreamPool *pool = nullptr;
     if ((rc = stream_pool(plans[0]->device, &pool))) return rc;
     hipStream_t st = (hipStream_t)stream;
-    HIP_TRY(hipEventRecord(pool->start, st));
     const int ns = std::min(kPoolStreams, count);
+    // Instances above 64 loops on the blocked LDL^T path (no refinement, no
+    // phase timing) are factored and solved together, up to kGroupMax of one
+    // padded size per group: one launch per step for all their systems, in
+    // place of one per instance.  Their contractions stay per instance.
+    // Not while the stream is captured: ending a capture that held the grouped
+    // launches crashed the HIP runtime (the cause is not known), so a captured
+    // call runs every instance on its own.
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(st, &cap));
+    std::vector<std::vector<int>> groups;
+    std::vector<char> grouped(count, 0);
+    if (cap == hipStreamCaptureStatusNone) {
+        std::vector<std::pair<int, int>> cand;  // (NP, instance)
+        for (int i = 0; i < count; ++i) {
+            const cosim_plan *p = plans[i];
+            if ((size_t)B[i] * F[i] == 0 || !big_plan(p->NP) || !p->ldl_ok) continue;
+            if (big_refine_args(p, precision).on || p->timing_used < p->timing_cap) continue;
+            cand.emplace_back(p->NP, i);
+        }
+        std::stable_sort(cand.begin(), cand.end(),
+                         [](const std::pair<int, int> &a, const std::pair<int, int> &b) {
+                             return a.first < b.first;
+                         });
+        for (size_t j = 0; j < cand.size();) {
+            size_t e = j;
+            while (e < cand.size() && cand[e].first == cand[j].first) ++e;
+            if (e - j >= 2)  // a class of one instance gains nothing
+                for (size_t k = j; k < e; k += kGroupMax) {
+                    std::vector<int> g;
+                    for (size_t m = k; m < std::min(e, k + (size_t)kGroupMax); ++m) {
+                        g.push_back(cand[m].second);
+                        grouped[cand[m].second] = 1;
+                    }
+                    groups.push_back(g);
+                }
+            j = e;
+        }
+    }
+    // workspaces first (allocation, when growing, happens before anything is enqueued)
+    size_t nA = 0, nWt = 0, nTinv = 0, nPiv = 0, nSys = 0;
+    std::vector<int> chunks(count, 0);
+    for (const std::vector<int> &g : groups)
+        for (int i : g) {
+            const size_t S = (size_t)B[i] * F[i], NP = (size_t)plans[i]->NP;
+            chunks[i] = chunks_for(plans[i], (Prec)precision, S, plans[i]->variant[precision]);
+            if ((rc = ensure_workspace(plans[i], S, chunks[i]))) return fail_instance(rc, i);
+            nA += S * NP * NP;
+            nWt += S * 64 * NP;
+            nTinv += S * 64 * 64;
+            nPiv += S * NP;
+            nSys += S;
+        }
+    if (!groups.empty()) {
+        if ((rc = pool_group_ws(pool, nA, nWt, nTinv, nPiv, nSys))) return rc;
+        if ((rc = pool_events(pool, groups.size() + count))) return rc;
+    }
+    HIP_TRY(hipEventRecord(pool->start, st));
     for (int k = 0; k < ns; ++k) HIP_TRY(hipStreamWaitEvent(pool->streams[k], pool->start, 0));
-    // largest instances first, each to the stream with the least work so far
-    // (work ~ systems x (NP^3 for the solves + P NP for the contraction))
+    // largest work first, each item to the stream with the least work so far
+    // (work ~ systems x (NP^3 for the solves + P NP for the contraction); a
+    // group counts as its largest member)
     std::vector<double> cost(count);
-    std::vector<int> order(count);
     for (int i = 0; i < count; ++i) {
         const double S = (double)B[i] * F[i], np = (double)plans[i]->NP;
         cost[i] = S * (np * np * np + (double)plans[i]->P * np);
-        order[i] = i;
     }
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    struct Item {
+        double cost;
+        int inst, group;  // one of them is -1
+    };
+    std::vector<Item> items;
+    for (int g = 0; g < (int)groups.size(); ++g) {
+        double c = 0.0;
+        for (int i : groups[g]) c = std::max(c, cost[i]);
+        items.push_back({c, -1, g});
+    }
+    for (int i = 0; i < count; ++i)
+        if (!grouped[i]) items.push_back({cost[i], i, -1});
+    std::stable_sort(items.begin(), items.end(),
+                     [](const Item &a, const Item &b) { return a.cost > b.cost; });
     std::vector<double> load(ns, 0.0);
+    const bool grad = grad_d != nullptr;
+    const bool ratio = loss_mode == COSIM_LOSS_RATIO;
+    const Prec prec = (Prec)precision;
+    size_t off[5] = {0, 0, 0, 0, 0};  // running offsets into the group workspace
     int first_rc = COSIM_OK;
-    for (int j = 0; j < count && first_rc == COSIM_OK; ++j) {
-        const int i = order[j];
+    int next_ev = (int)groups.size();
+    for (const Item &it : items) {
+        if (first_rc != COSIM_OK) break;
         const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-        load[k] += cost[i];
-        if ((rc = cosim_loss_and_grad(plans[i], B[i], F[i], C_d[i], omega_d[i], T_d[i], loss_mode,
-                                      precision, loss_d[i], grad_d ? grad_d[i] : nullptr,
-                                      status_d[i], pool->streams[k])))
-            first_rc = fail_instance(rc, i);
+        load[k] += it.cost;
+        hipStream_t gs = pool->streams[k];
+        if (it.inst >= 0) {
+            const int i = it.inst;
+            if ((rc = cosim_loss_and_grad(plans[i], B[i], F[i], C_d[i], omega_d[i], T_d[i],
+                                          loss_mode, precision, loss_d[i],
+                                          grad_d ? grad_d[i] : nullptr, status_d[i], gs)))
+                first_rc = fail_instance(rc, i);
+            continue;
+        }
+        // a group: factor and forward solve on gs, contractions spread over the
+        // pool, then adjoint solve and reductions on gs
+        const std::vector<int> &g = groups[it.group];
+        const int NP = plans[g[0]]->NP;
+        GroupArgs ga{};
+        ga.count = (int)g.size();
+        int Sg = 0;
+        std::vector<double> scale(g.size());
+        std::vector<const double *> Teff(g.size());
+        for (size_t m = 0; m < g.size(); ++m) {
+            const int i = g[m];
+            cosim_plan *p = plans[i];
+            scale[m] = 1.0 / ((double)F[i] * (double)p->P);
+            Teff[m] = T_d[i];
+            if (ratio) scale[m] /= p->bext_z * p->bext_z;
+            GroupInst &e = ga.in[m];
+            e.M = p->M_d;
+            e.R = p->R_d;
+            e.phi = p->phi_d;
+            e.C = C_d[i];
+            e.omega = omega_d[i];
+            e.I = p->I_ws;
+            e.rhs = p->rpart;
+            e.gsys = p->gsys;
+            e.mu = nullptr;
+            e.status = status_d[i];
+            e.n = p->n;
+            e.F = F[i];
+            e.S = B[i] * F[i];
+            e.nchunk = chunks[i];
+            e.s0 = Sg;
+            e.rscale = scale[m];
+            Sg += e.S;
+        }
+        BigFactor bf;
+        bf.ldl = true;
+        bf.fmt = pool->gFmt + off[4];
+        bf.zmax = pool->gZmax + off[4];
+        bf.wt = pool->gWt + off[1];
+        bf.tinv = pool->gTinv + off[2];
+        double2 *A = pool->gA + off[0];
+        int *piv = pool->gPiv + off[3];
+        off[0] += (size_t)Sg * NP * NP;
+        off[1] += (size_t)Sg * 64 * NP;
+        off[2] += (size_t)Sg * 64 * 64;
+        off[3] += (size_t)Sg * NP;
+        off[4] += (size_t)Sg;
+        hipEvent_t ev_fwd = pool->extra[it.group];
+        if (big_group_factor(bf, ga, NP, Sg, A, piv, gs) != hipSuccess ||
+            big_group_solve(ga, NP, Sg, A, piv, kRhsExcitation, gs) != hipSuccess ||
+            hipEventRecord(ev_fwd, gs) != hipSuccess) {
+            first_rc = fail(COSIM_EDEVICE, "grouped solve launch failed");
+            break;
+        }
+        for (size_t m = 0; m < g.size() && first_rc == COSIM_OK; ++m) {
+            const int i = g[m];
+            cosim_plan *p = plans[i];
+            hipStream_t cs = pool->streams[(k + 1 + m) % ns];
+            hipEvent_t ev_c = pool->extra[next_ev++];
+            BigArgs a = big_args(p, prec, B[i] * F[i], chunks[i], p->I_ws, Teff[m]);
+            bool ok = hipStreamWaitEvent(cs, ev_fwd, 0) == hipSuccess;
+            if (ok && ratio) {
+                ok = launch_scale((size_t)p->P, std::fabs(p->bext_z), T_d[i], p->T_ratio, cs) ==
+                     hipSuccess;
+                a.T = p->T_ratio;
+                a.inc = p->bext_z;
+            }
+            ok = ok && big_contract(p->blas, prec, loss_mode, grad, a, cs) == hipSuccess &&
+                 hipEventRecord(ev_c, cs) == hipSuccess && hipStreamWaitEvent(gs, ev_c, 0) == hipSuccess;
+            if (!ok) first_rc = fail_instance(fail(COSIM_EDEVICE, "contraction launch failed"), i);
+        }
+        if (first_rc != COSIM_OK) break;
+        if (grad &&
+            big_group_solve(ga, NP, Sg, A, piv, prec == Prec::F64 ? kRhsPlanarF64 : kRhsPlanarF32,
+                            gs) != hipSuccess) {
+            first_rc = fail(COSIM_EDEVICE, "grouped adjoint launch failed");
+            break;
+        }
+        for (size_t m = 0; m < g.size() && first_rc == COSIM_OK; ++m) {
+            const int i = g[m];
+            cosim_plan *p = plans[i];
+            if (launch_reduce(p->n, B[i], F[i], chunks[i], grad ? p->gsys : nullptr, p->lpart,
+                              scale[m], grad ? grad_d[i] : nullptr, loss_d[i], gs) != hipSuccess)
+                first_rc = fail_instance(fail(COSIM_EDEVICE, "reduction launch failed"), i);
+        }
     }
     for (int k = 0; k < ns; ++k) {  // join even after an error
         HIP_TRY(hipEventRecord(pool->done[k], pool->streams[k]));

@@ -192,6 +192,30 @@ hipError_t big_solve(const BigFactor &bf, const BigRefine &rf, int NP, int n, in
                      const double *omega_d, double2 *A_d, int *piv_d, double2 *I_d, int rhs_kind,
                      const void *rhs_d, int nchunk, double rscale, double *gsys_d,
                      int32_t *status_d, hipStream_t st, double2 *mu_d = nullptr);
+// Instances of one padded size above 64 loops factored and solved together,
+// each system as it would be alone (GroupArgs travels by value in the kernel
+// arguments; s0 numbers the systems instance after instance).
+constexpr int kGroupMax = 24;
+struct GroupInst {
+    const double *M, *R, *phi, *C, *omega;
+    double2 *I;        // [S][n] currents
+    const void *rhs;   // adjoint sums, as for launch_lu_solve
+    double *gsys;      // [S][n] adjoint gradient terms
+    double2 *mu;       // [S][n] adjoint solutions or null
+    int32_t *status;   // [S]
+    int n, F, S, nchunk, s0;
+    double rscale;
+};
+struct GroupArgs {
+    int count;
+    GroupInst in[kGroupMax];
+};
+// Blocked LDL^T (pivoted LU for marked systems) of the group's systems into A_d.
+hipError_t big_group_factor(const BigFactor &bf, const GroupArgs &g, int NP, int S,
+                            double2 *A_d, int *piv_d, hipStream_t st);
+// Forward (kRhsExcitation, writes I) or adjoint solves of the group's systems.
+hipError_t big_group_solve(const GroupArgs &g, int NP, int S, const double2 *A_d,
+                           const int *piv_d, int rhs_kind, hipStream_t st);
 hipError_t launch_lu_solve(int NP, int n, int S, int F, const double2 *A_d, const int *piv_d,
                            const double *phi_d, const double *C_d, const double *omega_d,
                            double2 *I_d, int rhs_kind, const void *rhs_d, int nchunk,

@@ -118,6 +118,52 @@ __device__ inline int acc_row(int g, int m) {
     return sizeof(T) == 8 ? g + 4 * m : 4 * g + m;
 }
 
+// One system's view of its instance: the operands of Z and of the right-hand
+// side, and where its outputs go.  s is the system's index in its instance.
+struct SysRef {
+    int n, S, s;
+    double w;
+    const double *M, *R, *phi, *Cb;  // Cb: the capacitances of the system's configuration
+    double2 *I;                      // the instance's [S][n] currents
+    const void *rhs;                 // the instance's adjoint sums
+    int nchunk;
+    double rscale;
+    double *gsys;
+    double2 *mu;
+    int32_t *status;  // the instance's [S] status
+};
+
+// The systems of one instance (grid index = system index).
+struct OneInst {
+    const double *M, *R, *phi, *C, *omega;
+    double2 *I;
+    const void *rhs;
+    double *gsys;
+    double2 *mu;
+    int32_t *status;
+    int n, F, S, nchunk;
+    double rscale;
+    __device__ SysRef ref(int g) const {
+        const int b = g / F, f = g - b * F;
+        return SysRef{n, S, g, omega[f], M, R, phi, C + (size_t)b * n, I, rhs, nchunk, rscale,
+                      gsys, mu, status};
+    }
+};
+
+// The systems of up to kGroupMax instances of one padded size, numbered
+// instance after instance (GroupArgs, passed by value).
+struct GroupSrc {
+    GroupArgs g;
+    __device__ SysRef ref(int gs) const {
+        int j = 0;
+        while (j + 1 < g.count && gs >= g.in[j + 1].s0) ++j;
+        const GroupInst &e = g.in[j];
+        const int s = gs - e.s0, b = s / e.F, f = s - b * e.F;
+        return SysRef{e.n, e.S, s, e.omega[f], e.M, e.R, e.phi, e.C + (size_t)b * e.n, e.I, e.rhs,
+                      e.nchunk, e.rscale, e.gsys, e.mu, e.status};
+    }
+};
+
 // Arg-max of (m, idx) over the workgroup, ties to the lower index; every
 // thread returns with the result.  sm/si: 4-entry LDS scratch.
 __device__ inline void block_amax(double &m, int &idx, double *sm, int *si) {
@@ -147,14 +193,10 @@ __device__ inline void block_amax(double &m, int &idx, double *sm, int *si) {
     __syncthreads();
 }
 
-__global__ __launch_bounds__(kTB) void k_lu_big(int n, int NP, int S, int F,
-                                                const double *__restrict__ M,
-                                                const double *__restrict__ Rv,
-                                                const double *__restrict__ C,
-                                                const double *__restrict__ omega,
+template <class Src>
+__global__ __launch_bounds__(kTB) void k_lu_big(int NP, int S, Src src,
                                                 double2 *__restrict__ Aall, int *__restrict__ pivall,
-                                                const int *__restrict__ only, int want,
-                                                int32_t *__restrict__ status) {
+                                                const int *__restrict__ only, int want) {
     __shared__ double sm[kTB / 64];
     __shared__ int si[kTB / 64];
     __shared__ int sFlag;
@@ -168,9 +210,12 @@ __global__ __launch_bounds__(kTB) void k_lu_big(int n, int NP, int S, int F,
     const int tid = threadIdx.x;
     double2 *A = Aall + (size_t)s * NP * NP;
     int *piv = pivall + (size_t)s * NP;
-    const int b = s / F, f = s - b * F;
-    const double w = omega[f];
-    const double *Cb = C + (size_t)b * n;
+    const SysRef r = src.ref(s);
+    const int n = r.n;
+    const double w = r.w;
+    const double *__restrict__ M = r.M;
+    const double *__restrict__ Rv = r.R;
+    const double *__restrict__ Cb = r.Cb;
     if (tid == 0) sFlag = 0;
     __syncthreads();
     for (int k = tid; k < n; k += kTB) {
@@ -269,23 +314,18 @@ __global__ __launch_bounds__(kTB) void k_lu_big(int n, int NP, int S, int F,
             __syncthreads();
         }
     }
-    if (tid == 0) status[s] = sFlag;
+    if (tid == 0) r.status[r.s] = sFlag;
 }
 
 // Lower triangle of Z = diag(R) + j w M + diag(1/(j w C)) (identity padding),
 // grid (S, NP/16): workgroup y writes rows 16y .. 16y + 15; the one with
 // y = 0 also sets the input flags, fmt = kFmtLDL (kFmtNeedsPivot for invalid
 // input) and the largest |re| + |im| of a diagonal entry.
-template <typename T2>
-__global__ __launch_bounds__(kTB) void k_big_assemble(int n, int NP, int S, int F,
-                                                      const double *__restrict__ M,
-                                                      const double *__restrict__ Rv,
-                                                      const double *__restrict__ C,
-                                                      const double *__restrict__ omega,
+template <typename T2, class Src>
+__global__ __launch_bounds__(kTB) void k_big_assemble(int NP, int S, Src src,
                                                       T2 *__restrict__ Aall,
                                                       int *__restrict__ fmt,
-                                                      double *__restrict__ zmax,
-                                                      int32_t *__restrict__ status) {
+                                                      double *__restrict__ zmax) {
     __shared__ double sm[kTB / 64];
     __shared__ int si[kTB / 64];
     __shared__ int sFlag;
@@ -293,9 +333,12 @@ __global__ __launch_bounds__(kTB) void k_big_assemble(int n, int NP, int S, int 
     if (s >= S) return;  // whole workgroup
     const int tid = threadIdx.x;
     T2 *A = Aall + (size_t)s * NP * NP;
-    const int b = s / F, f = s - b * F;
-    const double w = omega[f];
-    const double *Cb = C + (size_t)b * n;
+    const SysRef r = src.ref(s);
+    const int n = r.n;
+    const double w = r.w;
+    const double *__restrict__ M = r.M;
+    const double *__restrict__ Rv = r.R;
+    const double *__restrict__ Cb = r.Cb;
     if (tid == 0) sFlag = 0;
     __syncthreads();
     double zm = 0.0;
@@ -326,7 +369,7 @@ __global__ __launch_bounds__(kTB) void k_big_assemble(int n, int NP, int S, int 
     int dummy = 0;
     block_amax(zm, dummy, sm, si);  // max over the workgroup (index unused)
     if (tid == 0) {
-        status[s] = sFlag;
+        r.status[r.s] = sFlag;
         fmt[s] = (sFlag & COSIM_SYS_BAD_INPUT) ? kFmtNeedsPivot : kFmtLDL;
         zmax[s] = zm;
     }
@@ -690,15 +733,15 @@ __device__ inline double2 wave_sum(double2 a) {
     return a;
 }
 
-// Right-hand side of row k < n of system s: the loop voltage (forward) or
+// Right-hand side of row k < n of system r: the loop voltage (forward) or
 // rscale * conj(sum over chunks of (rr + j ri)) (adjoint).
 template <int RHS>
-__device__ inline double2 rhs_entry(int k, int n, int NP, int S, int s, double w,
-                                    const double *__restrict__ phi, const void *rhs, int nchunk,
-                                    double rscale) {
-    if (RHS == kRhsExcitation) return loop_voltage(phi, n, k, w);
+__device__ inline double2 rhs_entry(int k, int NP, const SysRef &r) {
+    if (RHS == kRhsExcitation) return loop_voltage(r.phi, r.n, k, r.w);
+    const int S = r.S, s = r.s;
+    const void *rhs = r.rhs;
     double rr = 0.0, ri = 0.0;
-    for (int c = 0; c < nchunk; ++c) {
+    for (int c = 0; c < r.nchunk; ++c) {
         if (RHS == kRhsPairs) {
             const double2 v = ((const double2 *)rhs)[((size_t)c * S + s) * NP + k];
             rr += v.x;
@@ -713,7 +756,7 @@ __device__ inline double2 rhs_entry(int k, int n, int NP, int S, int s, double w
             ri += R[(size_t)(2 * s + 1) * NP + k];
         }
     }
-    return make_double2(rscale * rr, -rscale * ri);
+    return make_double2(r.rscale * rr, -r.rscale * ri);
 }
 
 // sx <- U^-1 L^-1 P sx for one system's LU record A (unit lower L below the
@@ -787,11 +830,15 @@ __device__ __forceinline__ void lu_apply_inverse(const T2 *__restrict__ A, const
 // Outputs of a solved system: forward I[s][k]; adjoint gsys[s][k] =
 // 2 Re(mu_k I_k / (j w C_k^2)) (and mu when asked for); status bits.
 template <int RHS>
-__device__ __forceinline__ void write_solution(int n, int s, double w, const double *__restrict__ Cb,
-                               const double2 *sx, double2 *__restrict__ I,
-                               double *__restrict__ gsys, double2 *__restrict__ mu,
-                               int32_t *__restrict__ status, int *sFlag) {
+__device__ __forceinline__ void write_solution(const SysRef &r, const double2 *sx, int *sFlag) {
     const int tid = threadIdx.x;
+    const int n = r.n, s = r.s;
+    const double w = r.w;
+    const double *__restrict__ Cb = r.Cb;
+    double2 *__restrict__ I = r.I;
+    double *__restrict__ gsys = r.gsys;
+    double2 *__restrict__ mu = r.mu;
+    int32_t *__restrict__ status = r.status;
     const int flag = status[s];
     const bool bad = (flag & (COSIM_SYS_BAD_INPUT | COSIM_SYS_SINGULAR)) != 0;
     int oflag = 0;
@@ -819,18 +866,10 @@ __device__ __forceinline__ void write_solution(int n, int s, double w, const dou
 // One workgroup per system (only those with only[s] == want when `only` is
 // set): right-hand side, the two triangular solves with the FP64 record,
 // outputs.
-template <int RHS>
-__global__ __launch_bounds__(kTS) void k_lu_solve(int n, int NP, int S, int F,
+template <int RHS, class Src>
+__global__ __launch_bounds__(kTS) void k_lu_solve(int NP, int S, Src src,
                                                   const double2 *__restrict__ Aall,
                                                   const int *__restrict__ pivall,
-                                                  const double *__restrict__ phi,
-                                                  const double *__restrict__ C,
-                                                  const double *__restrict__ omega,
-                                                  double2 *__restrict__ I, const void *rhs,
-                                                  int nchunk, double rscale,
-                                                  double *__restrict__ gsys,
-                                                  double2 *__restrict__ mu,
-                                                  int32_t *__restrict__ status,
                                                   const int *__restrict__ only, int want) {
     __shared__ double2 sx[kMaxLoopsBig];
     __shared__ double2 st[16];
@@ -840,16 +879,14 @@ __global__ __launch_bounds__(kTS) void k_lu_solve(int n, int NP, int S, int F,
     if (s >= S) return;
     if (only && only[s] != want) return;
     const int tid = threadIdx.x;
-    const int b = s / F, f = s - b * F;
-    const double w = omega[f];
+    const SysRef r = src.ref(s);
     for (int k = tid; k < NP; k += kTS)
-        sx[k] = k < n ? rhs_entry<RHS>(k, n, NP, S, s, w, phi, rhs, nchunk, rscale)
-                      : make_double2(0.0, 0.0);
+        sx[k] = k < r.n ? rhs_entry<RHS>(k, NP, r) : make_double2(0.0, 0.0);
     if (tid == 0) sFlag = 0;
     __syncthreads();
     lu_apply_inverse<double2, true>(Aall + (size_t)s * NP * NP, pivall + (size_t)s * NP, NP, sx, st,
                                     sd);
-    write_solution<RHS>(n, s, w, C + (size_t)b * n, sx, I, gsys, mu, status, &sFlag);
+    write_solution<RHS>(r, sx, &sFlag);
 }
 
 // Largest of a and b over the kTS threads, NaN taken as +inf; every thread
@@ -890,13 +927,10 @@ __device__ inline void block_max2(double &a, double &b, double *sm) {
 // max_iter steps is marked fail_fmt, writes nothing and is left to the
 // pivoted FP64 fallback.
 template <int RHS>
-__global__ __launch_bounds__(kTS) void k_solve_refined(
-    int n, int NP, int S, int F, const float2 *__restrict__ A32all,
-    const double *__restrict__ M, const double *__restrict__ Rv, const double *__restrict__ phi,
-    const double *__restrict__ C, const double *__restrict__ omega, double2 *__restrict__ I,
-    const void *rhs, int nchunk, double rscale, double *__restrict__ gsys,
-    double2 *__restrict__ mu, int32_t *__restrict__ status, int *__restrict__ fmt, int fail_fmt,
-    int max_iter, double tol) {
+__global__ __launch_bounds__(kTS) void k_solve_refined(int NP, int S, OneInst src,
+                                                       const float2 *__restrict__ A32all,
+                                                       int *__restrict__ fmt, int fail_fmt,
+                                                       int max_iter, double tol) {
     __shared__ double2 sb[kMaxLoopsBig];
     __shared__ double2 sx[kMaxLoopsBig];
     __shared__ double2 sr[kMaxLoopsBig];
@@ -908,13 +942,15 @@ __global__ __launch_bounds__(kTS) void k_solve_refined(
     if (s >= S) return;
     if (fmt[s] != kFmtLDL) return;  // whole workgroup: handled by the FP64 record
     const int tid = threadIdx.x;
-    const int b = s / F, f = s - b * F;
-    const double w = omega[f];
-    const double *Cb = C + (size_t)b * n;
+    const SysRef sys = src.ref(s);
+    const int n = sys.n;
+    const double w = sys.w;
+    const double *__restrict__ M = sys.M;
+    const double *__restrict__ Rv = sys.R;
+    const double *__restrict__ Cb = sys.Cb;
     const float2 *A = A32all + (size_t)s * NP * NP;
     for (int k = tid; k < NP; k += kTS) {
-        const double2 v = k < n ? rhs_entry<RHS>(k, n, NP, S, s, w, phi, rhs, nchunk, rscale)
-                                : make_double2(0.0, 0.0);
+        const double2 v = k < n ? rhs_entry<RHS>(k, NP, sys) : make_double2(0.0, 0.0);
         sb[k] = v;
         sr[k] = v;
     }
@@ -965,30 +1001,49 @@ __global__ __launch_bounds__(kTS) void k_solve_refined(
         if (tid == 0) fmt[s] = fail_fmt;
         return;  // whole workgroup
     }
-    write_solution<RHS>(n, s, w, Cb, sx, I, gsys, mu, status, &sFlag);
+    write_solution<RHS>(sys, sx, &sFlag);
 }
 
 }  // namespace
 
-hipError_t launch_lu_big(int NP, int n, int S, int F, const double *M_d, const double *R_d,
-                         const double *C_d, const double *omega_d, double2 *A_d, int *piv_d,
-                         int32_t *status_d, hipStream_t st) {
-    if (NP % 64 != 0 || NP > kMaxLoopsBig) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_lu_big, dim3(S), dim3(kTB), 0, st, n, NP, S, F, M_d, R_d, C_d, omega_d,
-                       A_d, piv_d, nullptr, 0, status_d);
+namespace {
+
+OneInst one_inst(int n, int F, int S, const double *M, const double *R, const double *phi,
+                 const double *C, const double *omega, double2 *I, const void *rhs, int nchunk,
+                 double rscale, double *gsys, double2 *mu, int32_t *status) {
+    OneInst o;
+    o.M = M;
+    o.R = R;
+    o.phi = phi;
+    o.C = C;
+    o.omega = omega;
+    o.I = I;
+    o.rhs = rhs;
+    o.gsys = gsys;
+    o.mu = mu;
+    o.status = status;
+    o.n = n;
+    o.F = F;
+    o.S = S;
+    o.nchunk = nchunk;
+    o.rscale = rscale;
+    return o;
+}
+
+template <class Src>
+hipError_t lu_big_launch(int NP, int S, const Src &src, double2 *A_d, int *piv_d,
+                         const int *only, int want, hipStream_t st) {
+    hipLaunchKernelGGL(k_lu_big<Src>, dim3(S), dim3(kTB), 0, st, NP, S, src, A_d, piv_d, only, want);
     return hipGetLastError();
 }
 
-namespace {
-
 // Blocked LDL^T of the systems marked kFmtLDL, in the storage type T2.
-template <typename T2>
-hipError_t blocked_ldl(const BigFactor &bf, int NP, int n, int S, int F, const double *M_d,
-                       const double *R_d, const double *C_d, const double *omega_d, T2 *A_d,
-                       int *piv_d, int32_t *status_d, hipStream_t st) {
+template <typename T2, class Src>
+hipError_t blocked_ldl(const BigFactor &bf, int NP, int S, const Src &src, T2 *A_d, int *piv_d,
+                       hipStream_t st) {
     T2 *wt = (T2 *)bf.wt, *tinv = (T2 *)bf.tinv;
-    hipLaunchKernelGGL(k_big_assemble<T2>, dim3(S, NP / 16), dim3(kTB), 0, st, n, NP, S, F, M_d,
-                       R_d, C_d, omega_d, A_d, bf.fmt, bf.zmax, status_d);
+    hipLaunchKernelGGL((k_big_assemble<T2, Src>), dim3(S, NP / 16), dim3(kTB), 0, st, NP, S, src,
+                       A_d, bf.fmt, bf.zmax);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     for (int k0 = 0; k0 < NP; k0 += 64) {
@@ -1008,49 +1063,51 @@ hipError_t blocked_ldl(const BigFactor &bf, int NP, int n, int S, int F, const d
     return hipSuccess;
 }
 
-template <int RHS>
-hipError_t lu_solve_launch(int NP, int n, int S, int F, const double2 *A_d, const int *piv_d,
-                           const double *phi_d, const double *C_d, const double *omega_d,
-                           double2 *I_d, const void *rhs_d, int nchunk, double rscale,
-                           double *gsys_d, double2 *mu_d, int32_t *status_d, const int *only,
-                           int want, hipStream_t st) {
-    hipLaunchKernelGGL(k_lu_solve<RHS>, dim3(S), dim3(kTS), 0, st, n, NP, S, F, A_d, piv_d, phi_d,
-                       C_d, omega_d, I_d, rhs_d, nchunk, rscale, gsys_d, mu_d, status_d, only,
-                       want);
-    return hipGetLastError();
-}
-
-hipError_t lu_solve_any(int rhs_kind, int NP, int n, int S, int F, const double2 *A_d,
-                        const int *piv_d, const double *phi_d, const double *C_d,
-                        const double *omega_d, double2 *I_d, const void *rhs_d, int nchunk,
-                        double rscale, double *gsys_d, double2 *mu_d, int32_t *status_d,
-                        const int *only, int want, hipStream_t st) {
-#define COSIM_LU_SOLVE(K)                                                                       \
-    lu_solve_launch<K>(NP, n, S, F, A_d, piv_d, phi_d, C_d, omega_d, I_d, rhs_d, nchunk, rscale, \
-                       gsys_d, mu_d, status_d, only, want, st)
+template <class Src>
+hipError_t lu_solve_any(int rhs_kind, int NP, int S, const Src &src, const double2 *A_d,
+                        const int *piv_d, const int *only, int want, hipStream_t st) {
+#define COSIM_LU_SOLVE(K)                                                                    \
+    hipLaunchKernelGGL((k_lu_solve<K, Src>), dim3(S), dim3(kTS), 0, st, NP, S, src, A_d, piv_d, \
+                       only, want);                                                          \
+    break
     switch (rhs_kind) {
-        case kRhsExcitation: return COSIM_LU_SOLVE(kRhsExcitation);
-        case kRhsPairs: return COSIM_LU_SOLVE(kRhsPairs);
-        case kRhsPlanarF32: return COSIM_LU_SOLVE(kRhsPlanarF32);
-        case kRhsPlanarF64: return COSIM_LU_SOLVE(kRhsPlanarF64);
+        case kRhsExcitation: COSIM_LU_SOLVE(kRhsExcitation);
+        case kRhsPairs: COSIM_LU_SOLVE(kRhsPairs);
+        case kRhsPlanarF32: COSIM_LU_SOLVE(kRhsPlanarF32);
+        case kRhsPlanarF64: COSIM_LU_SOLVE(kRhsPlanarF64);
         default: return hipErrorInvalidValue;
     }
 #undef COSIM_LU_SOLVE
+    return hipGetLastError();
 }
 
-template <int RHS>
-hipError_t refined_launch(const BigRefine &rf, int NP, int n, int S, int F, const double *M_d,
-                          const double *R_d, const double *phi_d, const double *C_d,
-                          const double *omega_d, double2 *I_d, const void *rhs_d, int nchunk,
-                          double rscale, double *gsys_d, double2 *mu_d, int32_t *status_d,
-                          int *fmt, int fail_fmt, hipStream_t st) {
-    hipLaunchKernelGGL(k_solve_refined<RHS>, dim3(S), dim3(kTS), 0, st, n, NP, S, F,
-                       (const float2 *)rf.A32, M_d, R_d, phi_d, C_d, omega_d, I_d, rhs_d, nchunk,
-                       rscale, gsys_d, mu_d, status_d, fmt, fail_fmt, rf.max_iter, rf.tol);
+hipError_t refined_any(int rhs_kind, const BigRefine &rf, int NP, int S, const OneInst &src,
+                       int *fmt, int fail_fmt, hipStream_t st) {
+#define COSIM_REFINED(K)                                                                      \
+    hipLaunchKernelGGL(k_solve_refined<K>, dim3(S), dim3(kTS), 0, st, NP, S, src,              \
+                       (const float2 *)rf.A32, fmt, fail_fmt, rf.max_iter, rf.tol);           \
+    break
+    switch (rhs_kind) {
+        case kRhsExcitation: COSIM_REFINED(kRhsExcitation);
+        case kRhsPairs: COSIM_REFINED(kRhsPairs);
+        case kRhsPlanarF32: COSIM_REFINED(kRhsPlanarF32);
+        case kRhsPlanarF64: COSIM_REFINED(kRhsPlanarF64);
+        default: return hipErrorInvalidValue;
+    }
+#undef COSIM_REFINED
     return hipGetLastError();
 }
 
 }  // namespace
+
+hipError_t launch_lu_big(int NP, int n, int S, int F, const double *M_d, const double *R_d,
+                         const double *C_d, const double *omega_d, double2 *A_d, int *piv_d,
+                         int32_t *status_d, hipStream_t st) {
+    if (NP % 64 != 0 || NP > kMaxLoopsBig) return hipErrorInvalidValue;
+    const OneInst src = one_inst(n, F, S, M_d, R_d, nullptr, C_d, omega_d, nullptr, nullptr, 0,
+                                 0.0, nullptr, nullptr, status_d);
+    return lu_big_launch(NP, S, src, A_d, piv_d, nullptr, 0, st);
+}
 
 hipError_t big_factor(const BigFactor &bf, const BigRefine &rf, int NP, int n, int S, int F,
                       const double *M_d, const double *R_d, const double *C_d,
@@ -1060,15 +1117,13 @@ hipError_t big_factor(const BigFactor &bf, const BigRefine &rf, int NP, int n, i
     if (NP % 64 != 0 || NP > kMaxLoopsBig || !bf.fmt || !bf.zmax || !bf.wt || !bf.tinv)
         return hipErrorInvalidValue;
     if (rf.on && !rf.A32) return hipErrorInvalidValue;
-    hipError_t e = rf.on ? blocked_ldl<float2>(bf, NP, n, S, F, M_d, R_d, C_d, omega_d,
-                                               (float2 *)rf.A32, piv_d, status_d, st)
-                         : blocked_ldl<double2>(bf, NP, n, S, F, M_d, R_d, C_d, omega_d, A_d,
-                                                piv_d, status_d, st);
+    const OneInst src = one_inst(n, F, S, M_d, R_d, nullptr, C_d, omega_d, nullptr, nullptr, 0,
+                                 0.0, nullptr, nullptr, status_d);
+    hipError_t e = rf.on ? blocked_ldl<float2>(bf, NP, S, src, (float2 *)rf.A32, piv_d, st)
+                         : blocked_ldl<double2>(bf, NP, S, src, A_d, piv_d, st);
     if (e != hipSuccess) return e;
     // pivoted FP64 LU (from a fresh Z) for the systems marked on the way
-    hipLaunchKernelGGL(k_lu_big, dim3(S), dim3(kTB), 0, st, n, NP, S, F, M_d, R_d, C_d, omega_d,
-                       A_d, piv_d, (const int *)bf.fmt, kFmtNeedsPivot, status_d);
-    return hipGetLastError();
+    return lu_big_launch(NP, S, src, A_d, piv_d, bf.fmt, kFmtNeedsPivot, st);
 }
 
 hipError_t big_solve(const BigFactor &bf, const BigRefine &rf, int NP, int n, int S, int F,
@@ -1077,39 +1132,23 @@ hipError_t big_solve(const BigFactor &bf, const BigRefine &rf, int NP, int n, in
                      const void *rhs_d, int nchunk, double rscale, double *gsys_d,
                      int32_t *status_d, hipStream_t st, double2 *mu_d) {
     if (NP % 64 != 0 || NP > kMaxLoopsBig) return hipErrorInvalidValue;
-    if (!(bf.ldl && rf.on))
-        return lu_solve_any(rhs_kind, NP, n, S, F, A_d, piv_d, phi_d, C_d, omega_d, I_d, rhs_d,
-                            nchunk, rscale, gsys_d, mu_d, status_d, nullptr, 0, st);
+    const OneInst src = one_inst(n, F, S, M_d, R_d, phi_d, C_d, omega_d, I_d, rhs_d, nchunk,
+                                 rscale, gsys_d, mu_d, status_d);
+    if (!(bf.ldl && rf.on)) return lu_solve_any(rhs_kind, NP, S, src, A_d, piv_d, nullptr, 0, st);
     const bool fwd = rhs_kind == kRhsExcitation;
     const int fail = fwd ? kFmtRefineFailed : kFmtRefineFailedAdj;
     hipError_t e;
     // 1. the FP32 records, refined
-#define COSIM_REFINED(K)                                                                         \
-    refined_launch<K>(rf, NP, n, S, F, M_d, R_d, phi_d, C_d, omega_d, I_d, rhs_d, nchunk, rscale, \
-                      gsys_d, mu_d, status_d, bf.fmt, fail, st)
-    switch (rhs_kind) {
-        case kRhsExcitation: e = COSIM_REFINED(kRhsExcitation); break;
-        case kRhsPairs: e = COSIM_REFINED(kRhsPairs); break;
-        case kRhsPlanarF32: e = COSIM_REFINED(kRhsPlanarF32); break;
-        case kRhsPlanarF64: e = COSIM_REFINED(kRhsPlanarF64); break;
-        default: return hipErrorInvalidValue;
-    }
-#undef COSIM_REFINED
-    if (e != hipSuccess) return e;
+    if ((e = refined_any(rhs_kind, rf, NP, S, src, bf.fmt, fail, st)) != hipSuccess) return e;
     // 2. systems that already hold an FP64 record
     const int have[2] = {kFmtNeedsPivot, kFmtRefineFailed};
     for (int h = 0; h < (fwd ? 1 : 2); ++h)
-        if ((e = lu_solve_any(rhs_kind, NP, n, S, F, A_d, piv_d, phi_d, C_d, omega_d, I_d, rhs_d,
-                              nchunk, rscale, gsys_d, mu_d, status_d, bf.fmt, have[h], st)) !=
-            hipSuccess)
+        if ((e = lu_solve_any(rhs_kind, NP, S, src, A_d, piv_d, bf.fmt, have[h], st)) != hipSuccess)
             return e;
     // 3. systems whose refinement did not converge just now: pivoted FP64
     // record from a fresh Z, then the FP64 solve
-    hipLaunchKernelGGL(k_lu_big, dim3(S), dim3(kTB), 0, st, n, NP, S, F, M_d, R_d, C_d, omega_d,
-                       A_d, piv_d, (const int *)bf.fmt, fail, status_d);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    return lu_solve_any(rhs_kind, NP, n, S, F, A_d, piv_d, phi_d, C_d, omega_d, I_d, rhs_d,
-                        nchunk, rscale, gsys_d, mu_d, status_d, bf.fmt, fail, st);
+    if ((e = lu_big_launch(NP, S, src, A_d, piv_d, bf.fmt, fail, st)) != hipSuccess) return e;
+    return lu_solve_any(rhs_kind, NP, S, src, A_d, piv_d, bf.fmt, fail, st);
 }
 
 hipError_t launch_lu_solve(int NP, int n, int S, int F, const double2 *A_d, const int *piv_d,
@@ -1118,8 +1157,28 @@ hipError_t launch_lu_solve(int NP, int n, int S, int F, const double2 *A_d, cons
                            double rscale, double *gsys_d, int32_t *status_d, hipStream_t st,
                            double2 *mu_d) {
     if (NP % 64 != 0 || NP > kMaxLoopsBig) return hipErrorInvalidValue;
-    return lu_solve_any(rhs_kind, NP, n, S, F, A_d, piv_d, phi_d, C_d, omega_d, I_d, rhs_d, nchunk,
-                        rscale, gsys_d, mu_d, status_d, nullptr, 0, st);
+    const OneInst src = one_inst(n, F, S, nullptr, nullptr, phi_d, C_d, omega_d, I_d, rhs_d,
+                                 nchunk, rscale, gsys_d, mu_d, status_d);
+    return lu_solve_any(rhs_kind, NP, S, src, A_d, piv_d, nullptr, 0, st);
+}
+
+hipError_t big_group_factor(const BigFactor &bf, const GroupArgs &g, int NP, int S,
+                            double2 *A_d, int *piv_d, hipStream_t st) {
+    if (NP % 64 != 0 || NP > kMaxLoopsBig || g.count < 1 || g.count > kGroupMax || !bf.fmt ||
+        !bf.zmax || !bf.wt || !bf.tinv)
+        return hipErrorInvalidValue;
+    const GroupSrc src{g};
+    hipError_t e = blocked_ldl<double2>(bf, NP, S, src, A_d, piv_d, st);
+    if (e != hipSuccess) return e;
+    return lu_big_launch(NP, S, src, A_d, piv_d, bf.fmt, kFmtNeedsPivot, st);
+}
+
+hipError_t big_group_solve(const GroupArgs &g, int NP, int S, const double2 *A_d,
+                           const int *piv_d, int rhs_kind, hipStream_t st) {
+    if (NP % 64 != 0 || NP > kMaxLoopsBig || g.count < 1 || g.count > kGroupMax)
+        return hipErrorInvalidValue;
+    const GroupSrc src{g};
+    return lu_solve_any(rhs_kind, NP, S, src, A_d, piv_d, nullptr, 0, st);
 }
 
 }  // namespace cosim

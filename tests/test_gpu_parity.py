@@ -1169,3 +1169,47 @@ def test_ragged_graph_replay_matches_eager(dev):
             for (l, g, s), (lr, g_r, sr) in zip(gouts, ref):
                 assert torch.equal(l, lr) and torch.equal(g, g_r) and torch.equal(s, sr), (prec, rep)
         del gr
+
+
+def test_grouped_large_instances_match_single_calls(dev):
+    """Instances above 64 loops of one size are factored and solved together
+    by cosim_loss_and_grad_many: three of 81 loops (different batches,
+    frequency counts and points), two of 144 and two small ones.  Every
+    result equals the instance's own cosim_loss_and_grad call bit for bit,
+    in three precisions.  Under stream capture the call runs the instances
+    one by one (capturing the grouped launches crashed the HIP runtime at the
+    end of the capture); graph replays of it equal the single calls too."""
+    from paper_2503_18479_amd import (Geometry, Plan, loss_and_grad_many,
+                                      capture_loss_and_grad_many)
+    wls = [W.small_array(9, 9, batch=2, grid=30, n_freq=3, seed=41),
+           W.small_array(9, 9, batch=1, grid=45, n_freq=1, seed=42),
+           W.small_array(12, 12, batch=2, grid=20, n_freq=2, seed=43),
+           W.small_array(3, 2, batch=3, grid=16, n_freq=2, seed=44),
+           W.small_array(9, 9, batch=3, grid=24, n_freq=2, seed=45),
+           W.small_array(12, 12, batch=1, grid=28, n_freq=3, seed=46),
+           W.small_array(5, 5, batch=2, grid=18, n_freq=1, seed=47)]
+    plans = [Plan(Geometry.from_workload(w.geom), torch.tensor(w.pts, device=dev), w.bext_z)
+             for w in wls]
+    Cs = [torch.tensor(w.C, device=dev) for w in wls]
+    Os = [torch.tensor(w.omega, device=dev) for w in wls]
+    Ts = [torch.tensor(w.target, device=dev) for w in wls]
+    for prec in (0, 1, 2):
+        _say(f"[grouped] prec={prec}")
+        many = loss_and_grad_many(plans, Cs, Os, Ts, precision=prec)
+        torch.cuda.synchronize()
+        for pl, C, o, T, (l, g, s) in zip(plans, Cs, Os, Ts, many):
+            l1, g1, s1 = pl.loss_and_grad(C, o, T, precision=prec)
+            torch.cuda.synchronize()
+            assert torch.equal(l, l1) and torch.equal(g, g1) and torch.equal(s, s1), prec
+            assert int(s.abs().sum()) == 0
+    gr, gouts = capture_loss_and_grad_many(plans, Cs, Os, Ts, precision=0)
+    for rep in range(3):
+        for C in Cs:
+            C.mul_(1.0 + 0.02 * (rep + 1))
+        ref = [pl.loss_and_grad(C, o, T, precision=0) for pl, C, o, T in zip(plans, Cs, Os, Ts)]
+        torch.cuda.synchronize()
+        gr.replay()
+        torch.cuda.synchronize()
+        for (l, g, s), (l1, g1, s1) in zip(gouts, ref):
+            assert torch.equal(l, l1) and torch.equal(g, g1) and torch.equal(s, s1), rep
+    del gr
