@@ -68,6 +68,9 @@ def parse():
     ap.add_argument("--profile-large", type=int, default=None,
                     help="only the 32x32 array: time this many steps per mode (no Adam, no "
                          "8x8 line), for a profiler run")
+    ap.add_argument("--profile-assembly", type=int, default=None,
+                    help="only the one-time assembly (G in every precision, M) of the 8x8 and 32x32 "
+                         "arrays, this many times each, for a profiler run")
     ap.add_argument("--variant", type=int, default=None,
                     help="with --profile-steps: use this fused-kernel variant instead of tuning")
     return ap.parse_args()
@@ -380,6 +383,20 @@ def main():
         out = sparam_line(args.profile_sparam, torch)
         reference_copy(torch, dev)
         print(f"[bench] profiled the S-parameter pipeline: {out['modes']}", file=sys.stderr, flush=True)
+        return
+    if args.profile_assembly is not None:
+        for wl in (W.config3_array8x8(batch=1), W.config5_array32x32(batch=1)):
+            geom = Geometry.from_workload(wl.geom)
+            pts = torch.tensor(wl.pts, device=dev)
+            for _ in range(args.profile_assembly):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                Plan(geom, pts, wl.bext_z, precisions=["fp64", "fp32", "bf16x3"])
+                torch.cuda.synchronize()
+                print(f"[bench] assembled {wl.summary()} in {time.perf_counter() - t0:.3f} s",
+                      file=sys.stderr, flush=True)
+        reference_copy(torch, dev)
+        print("[bench] profiled the assembly and a 256 MiB copy", file=sys.stderr, flush=True)
         return
     if args.profile_large is not None:
         out = large_line(0, args.mixed, args.profile_large, torch)
