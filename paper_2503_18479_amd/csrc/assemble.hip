@@ -39,8 +39,8 @@ __device__ inline double b_filament(int comp, double ax, double ay, double az, d
 }
 
 // Block: 64 points x 4 waves.  Wave w evaluates loops w, w+4, ... for the 64
-// points of its lanes (every lane of a wave walks the same vertices, which
-// the scalar unit broadcasts), one chunk of 64 loops at a time; each chunk of
+// points of its lanes (every lane of a wave walks the same vertices, so each
+// vertex load is one cache line for the whole wave), one chunk of 64 loops at a time; each chunk of
 // the block tile [64][64] is staged in LDS and written out row-major, so that
 // a row segment of G is one contiguous store.  The transposed bf16 copies
 // (fused kernels only) are skipped when GThi is null.
