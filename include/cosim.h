@@ -315,7 +315,17 @@ int cosim_adam_step(int count, double *C_d, const double *grad_d, double *m_d, d
  * with the least work so far) that wait for `stream` and that `stream` waits
  * for when the call returns, so the work is ordered on `stream` as one
  * operation and can be captured with it.  Each plan's own workspace is used:
- * reserve every plan beforehand to keep the call allocation-free. */
+ * reserve every plan beforehand.
+ * Outside stream capture, instances above 64 loops with every R_k > 0 (no
+ * refinement, no phase timing) that share a padded size are factored and
+ * solved in shared launches, up to 24 per launch; their results equal their
+ * own calls bit for bit.  Their factor records live in a library-owned
+ * workspace per device, grown (after a device synchronisation) when a call
+ * needs more, so the first such call, or a larger one, allocates.  Calls on
+ * one device may overlap (other streams, other host threads): the enqueueing
+ * is serialised, and the side streams of a call that groups instances wait
+ * for the previous such call to finish.  Under capture every instance runs on
+ * its own and the shared workspace is not touched. */
 int cosim_loss_and_grad_many(int count, const cosim_plan_t *plans, const int *B, const int *F,
                              const double *const *C_d, const double *const *omega_d,
                              const double *const *T_d, int loss_mode, int precision,

@@ -277,6 +277,13 @@ struct StreamPool {
     std::vector<hipEvent_t> done;
     hipEvent_t start = nullptr;
     std::vector<hipEvent_t> extra;  // ordering of grouped instances
+    // One multi-instance call at a time enqueues on the pool (host side).
+    std::mutex mu;
+    // Recorded on the caller's stream at the end of every call that used the
+    // group workspace; the next such call's side streams wait for it, so the
+    // grouped work of calls on different streams never overlaps.
+    hipEvent_t ws_free = nullptr;
+    bool ws_used = false;
     // factor records of grouped instances, sized for the largest call so far
     double2 *gA = nullptr, *gWt = nullptr, *gTinv = nullptr;
     int *gPiv = nullptr, *gFmt = nullptr;
@@ -347,7 +354,8 @@ int stream_pool(int device, StreamPool **out) {
     StreamPool *p = new (std::nothrow) StreamPool;
     if (!p) return fail(COSIM_ENOMEM, "host allocation failed");
     p->device = device;
-    bool ok = hipEventCreateWithFlags(&p->start, hipEventDisableTiming) == hipSuccess;
+    bool ok = hipEventCreateWithFlags(&p->start, hipEventDisableTiming) == hipSuccess &&
+              hipEventCreateWithFlags(&p->ws_free, hipEventDisableTiming) == hipSuccess;
     for (int i = 0; ok && i < kPoolStreams; ++i) {
         hipStream_t st = nullptr;
         hipEvent_t ev = nullptr;
@@ -360,6 +368,7 @@ int stream_pool(int device, StreamPool **out) {
         for (hipStream_t st : p->streams) (void)hipStreamDestroy(st);
         for (hipEvent_t ev : p->done) (void)hipEventDestroy(ev);
         if (p->start) (void)hipEventDestroy(p->start);
+        if (p->ws_free) (void)hipEventDestroy(p->ws_free);
         delete p;
         (void)hipGetLastError();
         return fail(COSIM_EDEVICE, "creating the side streams failed");
@@ -1008,6 +1017,7 @@ int cosim_loss_and_grad_many(int count, const cosim_plan_t *plans, const int *B,
     // waits for afterwards
     StreamPool *pool = nullptr;
     if ((rc = stream_pool(plans[0]->device, &pool))) return rc;
+    std::lock_guard<std::mutex> pool_lock(pool->mu);
     hipStream_t st = (hipStream_t)stream;
     const int ns = std::min(kPoolStreams, count);
     // Instances above 64 loops on the blocked LDL^T path (no refinement, no
@@ -1067,7 +1077,14 @@ int cosim_loss_and_grad_many(int count, const cosim_plan_t *plans, const int *B,
         if ((rc = pool_events(pool, groups.size() + count))) return rc;
     }
     HIP_TRY(hipEventRecord(pool->start, st));
-    for (int k = 0; k < ns; ++k) HIP_TRY(hipStreamWaitEvent(pool->streams[k], pool->start, 0));
+    for (int k = 0; k < ns; ++k) {
+        HIP_TRY(hipStreamWaitEvent(pool->streams[k], pool->start, 0));
+        // the group workspace is shared by every call on the device: wait
+        // until the previous call that used it has finished (never under
+        // capture, where nothing is grouped)
+        if (!groups.empty() && pool->ws_used)
+            HIP_TRY(hipStreamWaitEvent(pool->streams[k], pool->ws_free, 0));
+    }
     // largest work first, each item to the stream with the least work so far
     // (work ~ systems x (NP^3 for the solves + P NP for the contraction); a
     // group counts as its largest member)
@@ -1199,6 +1216,10 @@ int cosim_loss_and_grad_many(int count, const cosim_plan_t *plans, const int *B,
     for (int k = 0; k < ns; ++k) {  // join even after an error
         HIP_TRY(hipEventRecord(pool->done[k], pool->streams[k]));
         HIP_TRY(hipStreamWaitEvent(st, pool->done[k], 0));
+    }
+    if (!groups.empty()) {
+        HIP_TRY(hipEventRecord(pool->ws_free, st));
+        pool->ws_used = true;
     }
     return first_rc;
 }

@@ -1213,3 +1213,39 @@ def test_grouped_large_instances_match_single_calls(dev):
         for (l, g, s), (l1, g1, s1) in zip(gouts, ref):
             assert torch.equal(l, l1) and torch.equal(g, g1) and torch.equal(s, s1), rep
     del gr
+
+
+@pytest.mark.gpu
+def test_grouped_calls_on_two_streams(dev):
+    """Two cosim_loss_and_grad_many calls enqueued back to back on two streams,
+    each with grouped instances of the same padded size: they share the
+    library's per-device group workspace, so the second call's grouped work
+    must wait for the first call's.  Both equal the instances' own calls bit
+    for bit, twice over."""
+    from paper_2503_18479_amd import Geometry, Plan, loss_and_grad_many
+    shapes = [(9, 9, 2, 30, 3), (9, 9, 1, 45, 1), (9, 9, 3, 24, 2)]
+    sets = []
+    for base in (61, 71):
+        wls = [W.small_array(nx, ny, batch=b, grid=gd, n_freq=nf, seed=base + j)
+               for j, (nx, ny, b, gd, nf) in enumerate(shapes)]
+        plans = [Plan(Geometry.from_workload(w.geom), torch.tensor(w.pts, device=dev), w.bext_z)
+                 for w in wls]
+        Cs = [torch.tensor(w.C, device=dev) for w in wls]
+        Os = [torch.tensor(w.omega, device=dev) for w in wls]
+        Ts = [torch.tensor(w.target, device=dev) for w in wls]
+        ref = [pl.loss_and_grad(C, o, T, precision=2) for pl, C, o, T in zip(plans, Cs, Os, Ts)]
+        sets.append((plans, Cs, Os, Ts, ref))
+    torch.cuda.synchronize()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    for rep in range(2):
+        _say(f"[two streams] rep={rep}")
+        outs = []
+        for (plans, Cs, Os, Ts, _), s in zip(sets, (s1, s2)):
+            s.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(s):
+                outs.append(loss_and_grad_many(plans, Cs, Os, Ts, precision=2))
+        torch.cuda.synchronize()
+        for (_, _, _, _, ref), many in zip(sets, outs):
+            for (l, g, st), (l1, g1, s1r) in zip(many, ref):
+                assert torch.equal(l, l1) and torch.equal(g, g1) and torch.equal(st, s1r), rep
+                assert int(st.abs().sum()) == 0
