@@ -787,6 +787,30 @@ int cosim_field_backward(cosim_plan_t p, int B, int F, const double *C_d, const 
 
 // The body of cosim_loss_and_grad; mu (optional, [S][n]) receives the adjoint
 // solutions for the gradients of the other circuit variables.
+// Operands of the fused contraction (64 loops or fewer) for S systems.
+static FusedArgs fused_args(const cosim_plan *p, int precision, int S, int nchunk, int tpc,
+                            const double *T_d, double inc) {
+    FusedArgs a;
+    a.G = precision == COSIM_FP64 ? (const void *)p->G64
+          : precision == COSIM_FP32 ? (const void *)p->G32
+                                    : (const void *)p->Ghi;
+    a.Glo = p->Glo;
+    a.GThi = p->GThi;
+    a.GTlo = p->GTlo;
+    a.T = T_d;
+    a.inc = inc;
+    a.P = p->P;
+    a.P_pad = p->P_pad;
+    a.nchunk = nchunk;
+    a.rows_per_chunk = tpc * kPTile;
+    a.I = p->I_ws;
+    a.S = S;
+    a.n = p->n;
+    a.rpart = p->rpart;
+    a.lpart = p->lpart;
+    return a;
+}
+
 static int loss_and_grad_impl(cosim_plan_t p, int B, int F, const double *C_d, const double *omega_d,
                        const double *T_d, int loss_mode, int precision, double *loss_d,
                        double *grad_d, int32_t *status_d, void *stream, double2 *mu) {
@@ -860,24 +884,7 @@ static int loss_and_grad_impl(cosim_plan_t p, int B, int F, const double *C_d, c
                                      omega_d, p->I_ws, status_d, p->fac, st));
     }
     if (ev) HIP_TRY(hipEventRecord(ev[1], st));
-    FusedArgs a;
-    a.G = precision == COSIM_FP64 ? (const void *)p->G64
-          : precision == COSIM_FP32 ? (const void *)p->G32
-                                    : (const void *)p->Ghi;
-    a.Glo = p->Glo;
-    a.GThi = p->GThi;
-    a.GTlo = p->GTlo;
-    a.T = T_d;
-    a.inc = ratio ? p->bext_z : 0.0;
-    a.P = p->P;
-    a.P_pad = p->P_pad;
-    a.nchunk = nchunk;
-    a.rows_per_chunk = tpc * kPTile;
-    a.I = p->I_ws;
-    a.S = (int)S;
-    a.n = p->n;
-    a.rpart = p->rpart;
-    a.lpart = p->lpart;
+    const FusedArgs a = fused_args(p, precision, (int)S, nchunk, tpc, T_d, ratio ? p->bext_z : 0.0);
     HIP_TRY(launch_fused(prec, p->NP, variant, loss_mode, grad, a, st));
     if (ev) HIP_TRY(hipEventRecord(ev[2], st));
     if (grad)
@@ -1020,10 +1027,11 @@ int cosim_loss_and_grad_many(int count, const cosim_plan_t *plans, const int *B,
     std::lock_guard<std::mutex> pool_lock(pool->mu);
     hipStream_t st = (hipStream_t)stream;
     const int ns = std::min(kPoolStreams, count);
-    // Instances above 64 loops on the blocked LDL^T path (no refinement, no
-    // phase timing) are factored and solved together, up to kGroupMax of one
-    // padded size per group: one launch per step for all their systems, in
-    // place of one per instance.  Their contractions stay per instance.
+    // Instances with every R_k > 0 (no refinement, no phase timing) are
+    // factored and solved together, up to kGroupMax (above 64 loops) or
+    // kSmallGroupMax (64 or fewer) of one padded size per group: one launch per
+    // solver step for all their systems, in place of one per instance.  Their
+    // contractions stay per instance.
     // Not while the stream is captured: ending a capture that held the grouped
     // launches crashed the HIP runtime (the cause is not known), so a captured
     // call runs every instance on its own.
@@ -1035,7 +1043,7 @@ int cosim_loss_and_grad_many(int count, const cosim_plan_t *plans, const int *B,
         std::vector<std::pair<int, int>> cand;  // (NP, instance)
         for (int i = 0; i < count; ++i) {
             const cosim_plan *p = plans[i];
-            if ((size_t)B[i] * F[i] == 0 || !big_plan(p->NP) || !p->ldl_ok) continue;
+            if ((size_t)B[i] * F[i] == 0 || !p->ldl_ok) continue;
             if (big_refine_args(p, precision).on || p->timing_used < p->timing_cap) continue;
             cand.emplace_back(p->NP, i);
         }
@@ -1046,10 +1054,11 @@ int cosim_loss_and_grad_many(int count, const cosim_plan_t *plans, const int *B,
         for (size_t j = 0; j < cand.size();) {
             size_t e = j;
             while (e < cand.size() && cand[e].first == cand[j].first) ++e;
+            const size_t gmax = big_plan(cand[j].first) ? kGroupMax : kSmallGroupMax;
             if (e - j >= 2)  // a class of one instance gains nothing
-                for (size_t k = j; k < e; k += kGroupMax) {
+                for (size_t k = j; k < e; k += gmax) {
                     std::vector<int> g;
-                    for (size_t m = k; m < std::min(e, k + (size_t)kGroupMax); ++m) {
+                    for (size_t m = k; m < std::min(e, k + gmax); ++m) {
                         g.push_back(cand[m].second);
                         grouped[cand[m].second] = 1;
                     }
@@ -1060,29 +1069,31 @@ int cosim_loss_and_grad_many(int count, const cosim_plan_t *plans, const int *B,
     }
     // workspaces first (allocation, when growing, happens before anything is enqueued)
     size_t nA = 0, nWt = 0, nTinv = 0, nPiv = 0, nSys = 0;
-    std::vector<int> chunks(count, 0);
+    std::vector<int> chunks(count, 0), tpcs(count, 1);
+    bool big_groups = false;
     for (const std::vector<int> &g : groups)
         for (int i : g) {
             const size_t S = (size_t)B[i] * F[i], NP = (size_t)plans[i]->NP;
-            chunks[i] = chunks_for(plans[i], (Prec)precision, S, plans[i]->variant[precision]);
+            chunks[i] = chunks_for(plans[i], (Prec)precision, S, plans[i]->variant[precision],
+                                   &tpcs[i]);
             if ((rc = ensure_workspace(plans[i], S, chunks[i]))) return fail_instance(rc, i);
+            if (!big_plan((int)NP)) continue;  // its own factor record
+            big_groups = true;
             nA += S * NP * NP;
             nWt += S * 64 * NP;
             nTinv += S * 64 * 64;
             nPiv += S * NP;
             nSys += S;
         }
-    if (!groups.empty()) {
-        if ((rc = pool_group_ws(pool, nA, nWt, nTinv, nPiv, nSys))) return rc;
-        if ((rc = pool_events(pool, groups.size() + count))) return rc;
-    }
+    if (big_groups && (rc = pool_group_ws(pool, nA, nWt, nTinv, nPiv, nSys))) return rc;
+    if (!groups.empty() && (rc = pool_events(pool, groups.size() + count))) return rc;
     HIP_TRY(hipEventRecord(pool->start, st));
     for (int k = 0; k < ns; ++k) {
         HIP_TRY(hipStreamWaitEvent(pool->streams[k], pool->start, 0));
         // the group workspace is shared by every call on the device: wait
         // until the previous call that used it has finished (never under
         // capture, where nothing is grouped)
-        if (!groups.empty() && pool->ws_used)
+        if (big_groups && pool->ws_used)
             HIP_TRY(hipStreamWaitEvent(pool->streams[k], pool->ws_free, 0));
     }
     // largest work first, each item to the stream with the least work so far
@@ -1131,6 +1142,79 @@ int cosim_loss_and_grad_many(int count, const cosim_plan_t *plans, const int *B,
         // pool, then adjoint solve and reductions on gs
         const std::vector<int> &g = groups[it.group];
         const int NP = plans[g[0]]->NP;
+        if (!big_plan(NP)) {
+            SmallGroup sg{};
+            sg.count = (int)g.size();
+            int Sg = 0;
+            for (size_t m = 0; m < g.size(); ++m) {
+                const int i = g[m];
+                cosim_plan *p = plans[i];
+                double sc = 1.0 / ((double)F[i] * (double)p->P);
+                if (ratio) sc /= p->bext_z * p->bext_z;
+                SmallInst &e = sg.in[m];
+                e.M = p->M_d;
+                e.R = p->R_d;
+                e.phi = p->phi_d;
+                e.C = C_d[i];
+                e.omega = omega_d[i];
+                e.I = p->I_ws;
+                e.rpart = p->rpart;
+                e.gsys = p->gsys;
+                e.mu = nullptr;
+                e.status = status_d[i];
+                e.fac = p->fac;
+                e.n = p->n;
+                e.F = F[i];
+                e.S = B[i] * F[i];
+                e.nchunk = chunks[i];
+                e.s0 = Sg;
+                e.rscale = sc;
+                Sg += e.S;
+            }
+            hipEvent_t ev_fwd = pool->extra[it.group];
+            if (launch_small_group(NP, sg, Sg, SmallPhase::Factor, gs) != hipSuccess ||
+                launch_small_group(NP, sg, Sg, SmallPhase::Fallback, gs) != hipSuccess ||
+                launch_small_group(NP, sg, Sg, SmallPhase::Forward, gs) != hipSuccess ||
+                hipEventRecord(ev_fwd, gs) != hipSuccess) {
+                first_rc = fail(COSIM_EDEVICE, "grouped solve launch failed");
+                break;
+            }
+            for (size_t m = 0; m < g.size() && first_rc == COSIM_OK; ++m) {
+                const int i = g[m];
+                cosim_plan *p = plans[i];
+                hipStream_t cs = pool->streams[(k + 1 + m) % ns];
+                hipEvent_t ev_c = pool->extra[next_ev++];
+                const double *Ti = T_d[i];
+                bool ok = hipStreamWaitEvent(cs, ev_fwd, 0) == hipSuccess;
+                if (ok && ratio) {
+                    ok = launch_scale((size_t)p->P, std::fabs(p->bext_z), T_d[i], p->T_ratio, cs) ==
+                         hipSuccess;
+                    Ti = p->T_ratio;
+                }
+                const FusedArgs a = fused_args(p, precision, B[i] * F[i], chunks[i], tpcs[i], Ti,
+                                               ratio ? p->bext_z : 0.0);
+                ok = ok &&
+                     launch_fused(prec, NP, p->variant[precision], loss_mode, grad, a, cs) ==
+                         hipSuccess &&
+                     hipEventRecord(ev_c, cs) == hipSuccess &&
+                     hipStreamWaitEvent(gs, ev_c, 0) == hipSuccess;
+                if (!ok) first_rc = fail_instance(fail(COSIM_EDEVICE, "contraction launch failed"), i);
+            }
+            if (first_rc != COSIM_OK) break;
+            if (grad && launch_small_group(NP, sg, Sg, SmallPhase::Adjoint, gs) != hipSuccess) {
+                first_rc = fail(COSIM_EDEVICE, "grouped adjoint launch failed");
+                break;
+            }
+            for (size_t m = 0; m < g.size() && first_rc == COSIM_OK; ++m) {
+                const int i = g[m];
+                cosim_plan *p = plans[i];
+                if (launch_reduce(p->n, B[i], F[i], chunks[i], grad ? p->gsys : nullptr, p->lpart,
+                                  sg.in[m].rscale, grad ? grad_d[i] : nullptr, loss_d[i],
+                                  gs) != hipSuccess)
+                    first_rc = fail_instance(fail(COSIM_EDEVICE, "reduction launch failed"), i);
+            }
+            continue;
+        }
         GroupArgs ga{};
         ga.count = (int)g.size();
         int Sg = 0;
@@ -1217,7 +1301,7 @@ int cosim_loss_and_grad_many(int count, const cosim_plan_t *plans, const int *B,
         HIP_TRY(hipEventRecord(pool->done[k], pool->streams[k]));
         HIP_TRY(hipStreamWaitEvent(st, pool->done[k], 0));
     }
-    if (!groups.empty()) {
+    if (big_groups) {
         HIP_TRY(hipEventRecord(pool->ws_free, st));
         pool->ws_used = true;
     }

@@ -210,6 +210,30 @@ struct GroupArgs {
     int count;
     GroupInst in[kGroupMax];
 };
+// Plans of 64 loops or fewer with every R_k > 0, grouped the same way: each
+// member keeps its own factor record (fac) and workspace; members are stored
+// in order of their first system s0 within the group.
+constexpr int kSmallGroupMax = 16;
+struct SmallInst {
+    const double *M, *R, *phi, *C, *omega;
+    double2 *I;            // [S][n] currents (z from the factorisation, then I)
+    const double2 *rpart;  // [nchunk][S][NP] partial adjoint sums
+    double *gsys;          // [S][n] adjoint gradient terms
+    double2 *mu;           // [S][n] adjoint solutions or null
+    int32_t *status;       // [S]
+    GJFactor fac;
+    int n, F, S, nchunk, s0;
+    double rscale;
+};
+struct SmallGroup {
+    int count;
+    SmallInst in[kSmallGroupMax];
+};
+enum class SmallPhase { Factor, Fallback, Forward, Adjoint };
+// One phase of the small-plan solver path (k_ldl, the pivoted fallback of
+// marked systems, the forward and the adjoint replay) over a group's S systems.
+hipError_t launch_small_group(int NP, const SmallGroup &g, int S, SmallPhase phase,
+                              hipStream_t st);
 // Blocked LDL^T (pivoted LU for marked systems) of the group's systems into A_d.
 hipError_t big_group_factor(const BigFactor &bf, const GroupArgs &g, int NP, int S,
                             double2 *A_d, int *piv_d, hipStream_t st);

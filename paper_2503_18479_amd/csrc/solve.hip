@@ -103,9 +103,11 @@ __device__ inline double readlane_d(double x, int src) {
 // with W = (I + N)^-1, N[c][c'] = l_{c'}[p_c]; the panel group publishes W.
 // Column groups left of the panel hold only eliminated columns and skip the
 // update.
+// One system s (block-uniform) of a plan with n loops, S systems, F
+// frequencies; the kernels below call it for their own system index.
 template <int NP, bool ADJ>
-__global__ __launch_bounds__(GJShape<NP>::BLOCK) void k_gj(
-    int n, int S, int F, const double *__restrict__ M, const double *__restrict__ Rv,
+__device__ __forceinline__ void gj_system(
+    int s, int n, int S, int F, const double *__restrict__ M, const double *__restrict__ Rv,
     const double *__restrict__ phi, const double *__restrict__ C,
     const double *__restrict__ omega, const double2 *__restrict__ Iin,
     const double2 *__restrict__ rpart, int nchunk, double rscale, double2 *__restrict__ Iout,
@@ -113,7 +115,6 @@ __global__ __launch_bounds__(GJShape<NP>::BLOCK) void k_gj(
     GJFactor fac, bool fallback_only) {
     constexpr int NT = GJShape<NP>::NT;
     constexpr int NTHR = GJShape<NP>::NTHR;
-    const int s = blockIdx.x;
     // fallback launch: only systems the LDL^T fast path handed over
     if (fallback_only && fac.fmt[s] != kFmtNeedsPivot) return;  // uniform per block
     const int t = threadIdx.x;
@@ -425,6 +426,37 @@ __global__ __launch_bounds__(GJShape<NP>::BLOCK) void k_gj(
     }
 }
 
+// One block per system.
+template <int NP, bool ADJ>
+__global__ __launch_bounds__(GJShape<NP>::BLOCK) void k_gj(
+    int n, int S, int F, const double *__restrict__ M, const double *__restrict__ Rv,
+    const double *__restrict__ phi, const double *__restrict__ C,
+    const double *__restrict__ omega, const double2 *__restrict__ Iin,
+    const double2 *__restrict__ rpart, int nchunk, double rscale, double2 *__restrict__ Iout,
+    double *__restrict__ gsys, int32_t *__restrict__ status, bool or_status,
+    GJFactor fac, bool fallback_only) {
+    gj_system<NP, ADJ>(blockIdx.x, n, S, F, M, Rv, phi, C, omega, Iin, rpart, nchunk, rscale,
+                       Iout, gsys, status, or_status, fac, fallback_only);
+}
+
+// Member of a group that holds global system sg (wave-uniform): members are
+// stored in order of their first system s0.
+__device__ __forceinline__ int group_member(const SmallGroup &g, int sg) {
+    int i = 0;
+    while (i + 1 < g.count && sg >= g.in[i + 1].s0) ++i;
+    return i;
+}
+
+// The forward fallback of a group's systems: one block per system, only those
+// the factorisation marked.
+template <int NP>
+__global__ __launch_bounds__(GJShape<NP>::BLOCK) void k_gj_group(SmallGroup g) {
+    const int sg = blockIdx.x;
+    const SmallInst &e = g.in[group_member(g, sg)];
+    gj_system<NP, false>(sg - e.s0, e.n, e.S, e.F, e.M, e.R, e.phi, e.C, e.omega, nullptr, nullptr,
+                         0, 0.0, e.I, nullptr, e.status, false, e.fac, true);
+}
+
 // Sum of a complex value over the 64 lanes of a wave (all lanes active):
 // DPP butterflies inside each row of 16, then the four row sums.
 template <int CTRL>
@@ -502,8 +534,8 @@ __device__ inline double wave_sum16(const double (&v)[16], int lane) {
 // The accumulators and the row state fit 256 registers, so two systems share
 // a SIMD: one wave's panel elimination runs while the other's MFMAs do.
 template <int NP>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_ldl(
-    int n, int S, int F, const double *__restrict__ M, const double *__restrict__ Rv,
+__device__ __forceinline__ void ldl_system(
+    int s, int n, int F, const double *__restrict__ M, const double *__restrict__ Rv,
     const double *__restrict__ C, const double *__restrict__ omega,
     const double *__restrict__ phi, GJFactor fac, double2 *__restrict__ Z,
     int32_t *__restrict__ status) {
@@ -516,8 +548,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     // consecutive lanes fall on disjoint LDS banks
     __shared__ double2 sPan[4][NP][5];
     __shared__ double2 sV[4][NP][5];
-    const int s = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + wv));
-    if (s >= S) return;  // whole wave; the block never synchronises
     const int b = s / F, f = s - b * F;
     const double w = omega[f];
     const double *Cb = C + (size_t)b * n;
@@ -676,6 +706,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     }
 }
 
+// One wave per system, four per block.
+template <int NP>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_ldl(
+    int n, int S, int F, const double *__restrict__ M, const double *__restrict__ Rv,
+    const double *__restrict__ C, const double *__restrict__ omega,
+    const double *__restrict__ phi, GJFactor fac, double2 *__restrict__ Z,
+    int32_t *__restrict__ status) {
+    const int s = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
+    if (s >= S) return;  // whole wave; the block never synchronises
+    ldl_system<NP>(s, n, F, M, Rv, C, omega, phi, fac, Z, status);
+}
+
+// The same over the S systems of a group of plans (each wave resolves its own
+// member, so the waves of a block may serve different plans).
+template <int NP>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_ldl_group(
+    SmallGroup g, int S) {
+    const int sg = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
+    if (sg >= S) return;
+    const SmallInst &e = g.in[group_member(g, sg)];
+    ldl_system<NP>(sg - e.s0, e.n, e.F, e.M, e.R, e.C, e.omega, e.phi, e.fac, e.I, e.status);
+}
+
 // Solves with a recorded factorisation, one wave per system, lane i holds
 // component i.  Format kFmtLDL: y = L^-1 b by columns (readlane broadcast of
 // y_k, one coalesced column load), z = D^-1 y, then L^T x = z by
@@ -687,19 +740,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 // ADJ = true : b = rscale * sum_c (rr - j ri); writes
 //              gsys[s][k] = 2 Re(mu_k I_k / (j w C_k^2)).
 template <int NP, bool ADJ>
-__global__ __launch_bounds__(256) void k_replay(int n, int S, int F, GJFactor fac,
-                                                const double *__restrict__ phi,
-                                                const double *__restrict__ C,
-                                                const double *__restrict__ omega,
-                                                double2 *__restrict__ I,
-                                                const double2 *__restrict__ rpart, int nchunk,
-                                                double rscale, double *__restrict__ gsys,
-                                                double2 *__restrict__ mu,
-                                                int32_t *__restrict__ status) {
+__device__ __forceinline__ void replay_system(int s, int n, int S, int F, GJFactor fac,
+                                              const double *__restrict__ phi,
+                                              const double *__restrict__ C,
+                                              const double *__restrict__ omega,
+                                              double2 *__restrict__ I,
+                                              const double2 *__restrict__ rpart, int nchunk,
+                                              double rscale, double *__restrict__ gsys,
+                                              double2 *__restrict__ mu,
+                                              int32_t *__restrict__ status) {
     __shared__ double2 sTr[4][64];  // per wave: an 8x8 block of L, transposed
     const int lane = threadIdx.x & 63;
-    const int s = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
-    if (s >= S) return;  // whole wave; no block-level synchronisation below
     const int fmt = __builtin_amdgcn_readfirstlane(fac.fmt[s]);
     if (!ADJ && fmt == kFmtGJ) return;
     const int b = s / F, f = s - b * F;
@@ -856,6 +907,31 @@ __global__ __launch_bounds__(256) void k_replay(int n, int S, int F, GJFactor fa
     if (__ballot(nonfinite) != 0 && lane == 0) status[s] = flag | COSIM_SYS_NONFINITE;
 }
 
+template <int NP, bool ADJ>
+__global__ __launch_bounds__(256) void k_replay(int n, int S, int F, GJFactor fac,
+                                                const double *__restrict__ phi,
+                                                const double *__restrict__ C,
+                                                const double *__restrict__ omega,
+                                                double2 *__restrict__ I,
+                                                const double2 *__restrict__ rpart, int nchunk,
+                                                double rscale, double *__restrict__ gsys,
+                                                double2 *__restrict__ mu,
+                                                int32_t *__restrict__ status) {
+    const int s = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
+    if (s >= S) return;  // whole wave; no block-level synchronisation below
+    replay_system<NP, ADJ>(s, n, S, F, fac, phi, C, omega, I, rpart, nchunk, rscale, gsys, mu,
+                           status);
+}
+
+template <int NP, bool ADJ>
+__global__ __launch_bounds__(256) void k_replay_group(SmallGroup g, int S) {
+    const int sg = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
+    if (sg >= S) return;
+    const SmallInst &e = g.in[group_member(g, sg)];
+    replay_system<NP, ADJ>(sg - e.s0, e.n, e.S, e.F, e.fac, e.phi, e.C, e.omega, e.I, e.rpart,
+                           e.nchunk, e.rscale, e.gsys, e.mu, e.status);
+}
+
 __global__ __launch_bounds__(256) void k_reduce(int n, int B, int F, int nchunk,
                                                 const double *__restrict__ gsys,
                                                 const double *__restrict__ lpart, double lscale,
@@ -988,6 +1064,39 @@ hipError_t launch_reduce(int n, int B, int F, int nchunk, const double *gsys_d,
                          hipStream_t st) {
     hipLaunchKernelGGL(k_reduce, dim3(B), dim3(64), 0, st, n, B, F, nchunk, gsys_d, lpart_d,
                        lscale, grad_d, loss_d);
+    return hipGetLastError();
+}
+
+hipError_t launch_small_group(int NP, const SmallGroup &g, int S, SmallPhase phase,
+                              hipStream_t st) {
+    if (S <= 0) return hipSuccess;
+    const dim3 wave_grid((S + 3) / 4);
+#define COSIM_SMALL_GROUP(NPC)                                                                   \
+    switch (phase) {                                                                             \
+        case SmallPhase::Factor:                                                                 \
+            hipLaunchKernelGGL(k_ldl_group<NPC>, wave_grid, dim3(256), 0, st, g, S);             \
+            break;                                                                               \
+        case SmallPhase::Fallback:                                                               \
+            hipLaunchKernelGGL(k_gj_group<NPC>, dim3(S), dim3(GJShape<NPC>::BLOCK), 0, st, g);   \
+            break;                                                                               \
+        case SmallPhase::Forward:                                                                \
+            hipLaunchKernelGGL((k_replay_group<NPC, false>), wave_grid, dim3(256), 0, st, g, S); \
+            break;                                                                               \
+        case SmallPhase::Adjoint:                                                                \
+            hipLaunchKernelGGL((k_replay_group<NPC, true>), wave_grid, dim3(256), 0, st, g, S);  \
+            break;                                                                               \
+    }
+    switch (NP) {
+        case 32:
+            COSIM_SMALL_GROUP(32)
+            break;
+        case 64:
+            COSIM_SMALL_GROUP(64)
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+#undef COSIM_SMALL_GROUP
     return hipGetLastError();
 }
 

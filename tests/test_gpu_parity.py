@@ -1249,3 +1249,46 @@ def test_grouped_calls_on_two_streams(dev):
             for (l, g, st), (l1, g1, s1r) in zip(many, ref):
                 assert torch.equal(l, l1) and torch.equal(g, g1) and torch.equal(st, s1r), rep
                 assert int(st.abs().sum()) == 0
+
+
+@pytest.mark.gpu
+def test_grouped_small_instances_match_single_calls(dev):
+    """Instances of 64 loops or fewer of one padded size are factored and
+    solved together by cosim_loss_and_grad_many (their contractions stay per
+    instance): two of 64 loops and one of 36 (padded to 64), two of 25 and
+    one of 16 (padded to 32), one of 81 alone.  Every result equals the
+    instance's own call bit for bit, for the magnitude, complex and
+    enhancement-ratio losses, with and without the gradient, in three
+    precisions."""
+    from paper_2503_18479_amd import (Geometry, Plan, loss_and_grad_many, LOSS_MAG,
+                                      LOSS_COMPLEX, LOSS_RATIO)
+    wls = [W.small_array(8, 8, batch=2, grid=20, n_freq=3, seed=81),
+           W.small_array(6, 6, batch=3, grid=18, n_freq=2, seed=82),
+           W.small_array(5, 5, batch=1, grid=25, n_freq=1, seed=83),
+           W.small_array(8, 8, batch=1, grid=33, n_freq=2, seed=84),
+           W.small_array(4, 4, batch=4, grid=16, n_freq=3, seed=85),
+           W.small_array(5, 5, batch=2, grid=12, n_freq=2, seed=86),
+           W.small_array(9, 9, batch=1, grid=16, n_freq=1, seed=87)]
+    plans = [Plan(Geometry.from_workload(w.geom), torch.tensor(w.pts, device=dev), w.bext_z)
+             for w in wls]
+    Cs = [torch.tensor(w.C, device=dev) for w in wls]
+    Os = [torch.tensor(w.omega, device=dev) for w in wls]
+    Ts = [torch.tensor(w.target, device=dev) for w in wls]
+    # ratio targets: enhancement factors near 1
+    Rs = [1.0 + 0.5 * torch.tensor(w.target, device=dev) / float(np.max(w.target)) for w in wls]
+    for mode, tg in ((LOSS_MAG, Ts), (LOSS_COMPLEX, Ts), (LOSS_RATIO, Rs)):
+        for prec in (0, 1, 2):
+            for grad in (True, False):
+                _say(f"[small groups] mode={mode} prec={prec} grad={grad}")
+                many = loss_and_grad_many(plans, Cs, Os, tg, loss_mode=mode, precision=prec,
+                                          grad=grad)
+                torch.cuda.synchronize()
+                for pl, C, o, T, (l, g, s) in zip(plans, Cs, Os, tg, many):
+                    l1, g1, s1 = pl.loss_and_grad(C, o, T, loss_mode=mode, precision=prec,
+                                                  grad=grad)
+                    torch.cuda.synchronize()
+                    assert torch.equal(l, l1) and torch.equal(s, s1), (mode, prec, grad)
+                    assert (g is None) == (not grad)
+                    if grad:
+                        assert torch.equal(g, g1), (mode, prec)
+                    assert int(s.abs().sum()) == 0
