@@ -71,6 +71,9 @@ def parse():
     ap.add_argument("--profile-assembly", type=int, default=None,
                     help="only the one-time assembly (G in every precision, M) of the 8x8 and 32x32 "
                          "arrays, this many times each, for a profiler run")
+    ap.add_argument("--profile-ragged", type=int, default=None,
+                    help="only the ragged line (eager steps and graph replays), this many steps "
+                         "each, for a profiler run")
     ap.add_argument("--variant", type=int, default=None,
                     help="with --profile-steps: use this fused-kernel variant instead of tuning")
     return ap.parse_args()
@@ -383,6 +386,11 @@ def main():
         out = sparam_line(args.profile_sparam, torch)
         reference_copy(torch, dev)
         print(f"[bench] profiled the S-parameter pipeline: {out['modes']}", file=sys.stderr, flush=True)
+        return
+    if args.profile_ragged is not None:
+        out = ragged_line(args.ragged, args.mixed, args.profile_ragged, torch)
+        print(f"[bench] profiled the ragged line: {out['ms_per_step']:.1f} ms eager, "
+              f"{out['ms_per_step_graph']:.1f} ms graph", file=sys.stderr, flush=True)
         return
     if args.profile_assembly is not None:
         for wl in (W.config3_array8x8(batch=1), W.config5_array32x32(batch=1)):

@@ -761,7 +761,8 @@ __device__ __forceinline__ void replay_system(int s, int n, int S, int F, GJFact
             x = I[(size_t)s * n + lane];  // z = D^-1 L^-1 b from the factorisation
         } else {
             double rr = 0.0, ri = 0.0;
-            for (int c = 0; c < nchunk; ++c) {
+#pragma unroll 8
+            for (int c = 0; c < nchunk; ++c) {  // loads ahead, sums in chunk order
                 const double2 v = rpart[((size_t)c * S + s) * NP + lane];
                 rr += v.x;
                 ri += v.y;
@@ -932,7 +933,11 @@ __global__ __launch_bounds__(256) void k_replay_group(SmallGroup g, int S) {
                            e.nchunk, e.rscale, e.gsys, e.mu, e.status);
 }
 
-__global__ __launch_bounds__(256) void k_reduce(int n, int B, int F, int nchunk,
+// One 64-lane block per configuration b: dL/dC_b summed over frequencies per
+// loop, and the loss over frequencies and P-chunks, each lane taking every
+// 64th partial loss and the lanes combined by a fixed shuffle tree (both
+// orders are fixed, so repeated calls agree bit for bit).
+__global__ __launch_bounds__(64) void k_reduce(int n, int B, int F, int nchunk,
                                                 const double *__restrict__ gsys,
                                                 const double *__restrict__ lpart, double lscale,
                                                 double *__restrict__ grad,
@@ -946,11 +951,16 @@ __global__ __launch_bounds__(256) void k_reduce(int n, int B, int F, int nchunk,
             grad[(size_t)b * n + k] = acc;
         }
     }
-    if (threadIdx.x == 0 && loss) {
+    if (loss) {
+        const int m = F * nchunk;
         double acc = 0.0;
-        for (int f = 0; f < F; ++f)
-            for (int c = 0; c < nchunk; ++c) acc += lpart[(size_t)c * S + (size_t)b * F + f];
-        loss[b] = lscale * acc;
+        for (int e = threadIdx.x; e < m; e += 64) {
+            const int c = e / F, f = e - c * F;  // consecutive lanes: consecutive f
+            acc += lpart[(size_t)c * S + (size_t)b * F + f];
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+        if (threadIdx.x == 0) loss[b] = lscale * acc;
     }
 }
 
