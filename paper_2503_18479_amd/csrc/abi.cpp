@@ -97,7 +97,7 @@ void plan_free_workspace(cosim_plan *p) {
     dfree(p->fac.piv_val);
     dfree(p->fac.fmt);
     p->cap_systems = 0;
-    p->cap_chunks = 0;
+    p->cap_parts = 0;
 }
 
 // FP32 records with FP64 refinement when the plan asks for them and the
@@ -154,10 +154,13 @@ int check_device(const cosim_plan *p) {
 }
 
 // Make room for `systems` systems and `chunks` P-chunks of partial sums.
-int ensure_workspace(cosim_plan *p, size_t systems, int chunks) {
-    if (systems <= p->cap_systems && chunks <= p->cap_chunks) return COSIM_OK;
+// Workspace for `systems` systems whose partial sums use `chunks` P-chunks
+// (and at least `parts` (chunk, system) slots).
+int ensure_workspace(cosim_plan *p, size_t systems, int chunks, size_t parts = 0) {
+    parts = std::max(parts, systems * (size_t)chunks);
+    if (systems <= p->cap_systems && parts <= p->cap_parts) return COSIM_OK;
     const size_t ns = std::max(systems, p->cap_systems);
-    const int nc = std::max(chunks, p->cap_chunks);
+    const size_t np_parts = std::max(parts, p->cap_parts);
     plan_free_workspace(p);
     const size_t n = (size_t)p->n, NP = (size_t)p->NP;
     const bool big = big_plan(p->NP);
@@ -185,8 +188,8 @@ int ensure_workspace(cosim_plan *p, size_t systems, int chunks) {
         return fail(COSIM_ENOMEM, "FP32 factor workspace for %zu systems failed", ns);
     }
     if (hipMalloc((void **)&p->I_ws, ns * n * sizeof(double2)) != hipSuccess ||
-        hipMalloc((void **)&p->rpart, (size_t)nc * ns * NP * sizeof(double2)) != hipSuccess ||
-        hipMalloc((void **)&p->lpart, (size_t)nc * ns * sizeof(double)) != hipSuccess ||
+        hipMalloc((void **)&p->rpart, np_parts * NP * sizeof(double2)) != hipSuccess ||
+        hipMalloc((void **)&p->lpart, np_parts * sizeof(double)) != hipSuccess ||
         hipMalloc((void **)&p->gsys, ns * n * sizeof(double)) != hipSuccess ||
         hipMalloc((void **)&p->fac.L, ns * NP * NP * sizeof(double2)) != hipSuccess ||
         hipMalloc((void **)&p->fac.piv_row, ns * NP * sizeof(int)) != hipSuccess ||
@@ -194,26 +197,42 @@ int ensure_workspace(cosim_plan *p, size_t systems, int chunks) {
         hipMalloc((void **)&p->fac.fmt, ns * sizeof(int)) != hipSuccess) {
         plan_free_workspace(p);
         (void)hipGetLastError();
-        return fail(COSIM_ENOMEM, "workspace allocation for %zu systems x %d chunks failed", ns,
-                    nc);
+        return fail(COSIM_ENOMEM, "workspace allocation for %zu systems, %zu partial sums failed",
+                    ns, np_parts);
     }
     p->cap_systems = ns;
-    p->cap_chunks = nc;
+    p->cap_parts = np_parts;
     return COSIM_OK;
 }
 
-// P-chunk count of the fused kernels: enough workgroups to fill the chip
-// several times over, bounded by the number of 64-row tiles.
+// P-chunk count of the fused kernels (at most one per 64-row tile, at most 64).
 int choose_chunks(const cosim_plan *p, Prec prec, size_t S, int variant) {
+    // The launch has bx x c workgroups of equal work (c P-chunks of the
+    // systems' blocks) and the chip holds `slots` of them at once.  Take the
+    // fewest chunks whose workgroups fill the last round of resident
+    // workgroups to at least 95% (fewer chunks, fewer partial sums to write
+    // and read back); if none does (small batches), the best fill.
     const size_t per_block = (size_t)fused_systems_per_block(prec, p->NP, variant);
     const size_t bx = (S + per_block - 1) / per_block;
-    const size_t target = 2048;  // >= 8 workgroups per CU on 256 CUs
-    size_t c = (target + bx - 1) / bx;
-    const size_t tiles = (size_t)p->P_pad / kPTile;
-    c = std::min(c, tiles);
-    c = std::max<size_t>(c, 1);
-    c = std::min<size_t>(c, 64);
-    return (int)c;
+    const int tiles = p->P_pad / kPTile;
+    const int cmax = std::max(1, std::min(tiles, 64));
+    const size_t slots =
+        (size_t)std::max(1, p->cus) * (size_t)fused_blocks_per_cu(prec, p->NP, variant);
+    int best = cmax;
+    double best_fill = -1.0;
+    for (int c = 1; c <= cmax; ++c) {
+        const int tpc = (tiles + c - 1) / c;
+        const int cc = (tiles + tpc - 1) / tpc;  // chunks the tiles actually form
+        const size_t blocks = bx * (size_t)cc;
+        const size_t rounds = (blocks + slots - 1) / slots;
+        const double fill = (double)blocks / (double)(rounds * slots);
+        if (fill >= 0.95) return cc;
+        if (fill > best_fill) {
+            best_fill = fill;
+            best = cc;
+        }
+    }
+    return best;
 }
 
 // chunks of whole 64-row tiles, every chunk non-empty; *tiles_per_chunk out
@@ -520,7 +539,9 @@ int cosim_assemble_component(cosim_geom_t g, int P, const double *pts_d, double 
         }
         return code;
     };
-    if (hipGetDevice(&p->device) != hipSuccess) return cleanup(fail(COSIM_EDEVICE, "hipGetDevice failed"));
+    if (hipGetDevice(&p->device) != hipSuccess ||
+        hipDeviceGetAttribute(&p->cus, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess)
+        return cleanup(fail(COSIM_EDEVICE, "hipGetDevice failed"));
     const size_t gsz = (size_t)p->P_pad * p->NP;
     const size_t n = (size_t)g->n;
     if ((want64 && hipMalloc((void **)&p->G64, gsz * sizeof(double)) != hipSuccess) ||
@@ -601,11 +622,23 @@ int cosim_plan_reserve(cosim_plan_t p, int max_batch, int max_freq) {
     if (rc) return rc;
     if ((rc = check_device(p))) return rc;
     const size_t S = (size_t)max_batch * max_freq;
-    int chunks = 1;
+    // partial-sum slots for every batch up to S: a smaller batch may use more
+    // P-chunks (the fused kernels split P further to fill the chip)
+    size_t parts = S;
     for (int pr = COSIM_FP64; pr <= COSIM_BF16X3; ++pr)
-        for (int v = 0; v < plan_variants(p, (Prec)pr); ++v)
-            chunks = std::max(chunks, chunks_for(p, (Prec)pr, S, v));
-    return ensure_workspace(p, S, chunks);
+        for (int v = 0; v < plan_variants(p, (Prec)pr); ++v) {
+            if (big_plan(p->NP)) {
+                parts = std::max(parts, S * (size_t)chunks_for(p, (Prec)pr, S, v));
+                continue;
+            }
+            const size_t per_block = (size_t)fused_systems_per_block((Prec)pr, p->NP, v);
+            const size_t bxmax = (S + per_block - 1) / per_block;
+            for (size_t bx = 1; bx <= bxmax; ++bx) {
+                const size_t Sb = std::min(S, bx * per_block);
+                parts = std::max(parts, Sb * (size_t)chunks_for(p, (Prec)pr, Sb, v));
+            }
+        }
+    return ensure_workspace(p, S, 1, parts);
 }
 
 int cosim_plan_copy_G(cosim_plan_t p, double *G_d, void *stream) {

@@ -24,6 +24,8 @@
 // BF16X3: G = Gh + Gl and I = Ih + Il with bf16 hi/lo parts; the product is
 // Gh Ih + Gh Il + Gl Ih accumulated in FP32 with 16x16x32 bf16 MFMA; w is split
 // the same way for the adjoint.
+#include <atomic>
+
 #include "internal.h"
 #include "epilogue.h"
 
@@ -637,8 +639,16 @@ constexpr Variant kVarBF16[] = {{2, 64, false, 0}, {2, 32, false, 0}, {1, 64, fa
                                 {1, 64, true, 1},  {1, 32, true, 1},  {2, 32, true, 1},
                                 {2, 64, true, 1}};
 
+// With `occ` set, the resident-workgroup count per compute unit of the
+// kernel is written there and nothing is launched.
+template <typename K>
+hipError_t occupancy_of(K kernel, int *occ) {
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, kernel, 256, 0);
+}
+
 template <typename T, int NP, int NB, int LOSS, bool GRAD>
-hipError_t go_typed(const FusedArgs &a, hipStream_t st) {
+hipError_t go_typed(const FusedArgs &a, hipStream_t st, int *occ) {
+    if (occ) return occupancy_of(k_fused<T, NP, NB, LOSS, GRAD>, occ);
     const int per_block = 4 * 16 * NB;
     dim3 grid((a.S + per_block - 1) / per_block, a.nchunk);
     hipLaunchKernelGGL((k_fused<T, NP, NB, LOSS, GRAD>), grid, dim3(256), 0, st, a);
@@ -646,7 +656,11 @@ hipError_t go_typed(const FusedArgs &a, hipStream_t st) {
 }
 
 template <int NP, int NB, int PT, bool DB, int PIPE, int LOSS, bool GRAD>
-hipError_t go_bf16(const FusedArgs &a, hipStream_t st) {
+hipError_t go_bf16(const FusedArgs &a, hipStream_t st, int *occ) {
+    if (occ) {
+        if constexpr (PIPE == 1) return occupancy_of(k_fused_bf16x3_pipe<NP, NB, PT, LOSS, GRAD>, occ);
+        else return occupancy_of(k_fused_bf16x3<NP, NB, PT, DB, LOSS, GRAD>, occ);
+    }
     const int per_block = 4 * 16 * NB;
     dim3 grid((a.S + per_block - 1) / per_block, a.nchunk);
     if constexpr (PIPE == 1)
@@ -657,18 +671,18 @@ hipError_t go_bf16(const FusedArgs &a, hipStream_t st) {
 }
 
 template <int NP, int LOSS, bool GRAD>
-hipError_t go_np(Prec prec, int variant, const FusedArgs &a, hipStream_t st) {
+hipError_t go_np(Prec prec, int variant, const FusedArgs &a, hipStream_t st, int *occ) {
     switch (prec) {
         case Prec::F64:
             switch (variant) {
-                case 0: return go_typed<double, NP, 1, LOSS, GRAD>(a, st);
-                case 1: return go_typed<double, NP, 2, LOSS, GRAD>(a, st);
+                case 0: return go_typed<double, NP, 1, LOSS, GRAD>(a, st, occ);
+                case 1: return go_typed<double, NP, 2, LOSS, GRAD>(a, st, occ);
             }
             break;
         case Prec::F32:
             switch (variant) {
-                case 0: return go_typed<float, NP, 2, LOSS, GRAD>(a, st);
-                case 1: return go_typed<float, NP, 1, LOSS, GRAD>(a, st);
+                case 0: return go_typed<float, NP, 2, LOSS, GRAD>(a, st, occ);
+                case 1: return go_typed<float, NP, 1, LOSS, GRAD>(a, st, occ);
             }
             break;
         case Prec::BF16X3:
@@ -677,7 +691,7 @@ hipError_t go_np(Prec prec, int variant, const FusedArgs &a, hipStream_t st) {
 #define COSIM_BF16_CASE(i)                                                               \
     case i:                                                                              \
         return go_bf16<NP, kVarBF16[i].nb, kVarBF16[i].pt, kVarBF16[i].db, kVarBF16[i].pipe, \
-                       LOSS, GRAD>(a, st);
+                       LOSS, GRAD>(a, st, occ);
                     COSIM_BF16_CASE(0)
                     COSIM_BF16_CASE(1)
                     COSIM_BF16_CASE(2)
@@ -697,10 +711,11 @@ hipError_t go_np(Prec prec, int variant, const FusedArgs &a, hipStream_t st) {
 }
 
 template <int LOSS, bool GRAD>
-hipError_t go_loss(Prec prec, int NP, int variant, const FusedArgs &a, hipStream_t st) {
+hipError_t go_loss(Prec prec, int NP, int variant, const FusedArgs &a, hipStream_t st,
+                   int *occ = nullptr) {
     switch (NP) {
-        case 32: return go_np<32, LOSS, GRAD>(prec, variant, a, st);
-        case 64: return go_np<64, LOSS, GRAD>(prec, variant, a, st);
+        case 32: return go_np<32, LOSS, GRAD>(prec, variant, a, st, occ);
+        case 64: return go_np<64, LOSS, GRAD>(prec, variant, a, st, occ);
     }
     return hipErrorInvalidValue;
 }
@@ -724,6 +739,24 @@ int fused_systems_per_block(Prec prec, int NP, int variant) {
         case Prec::BF16X3: return 64 * kVarBF16[variant].nb;
     }
     return 64;
+}
+
+int fused_blocks_per_cu(Prec prec, int NP, int variant) {
+    // per (precision, NP 32 / 64, variant); the magnitude loss with gradient
+    // stands for every loss mode (their register and LDS use agree)
+    static std::atomic<int> cache[3][2][16];
+    const int pi = (int)prec, ni = NP == 32 ? 0 : 1;
+    if (pi < 0 || pi > 2 || (NP != 32 && NP != 64) || variant < 0 || variant >= 16) return 1;
+    int v = cache[pi][ni][variant].load(std::memory_order_relaxed);
+    if (v > 0) return v;
+    int occ = 0;
+    if (go_loss<COSIM_LOSS_MAG, true>(prec, NP, variant, FusedArgs{}, nullptr, &occ) != hipSuccess ||
+        occ < 1) {
+        (void)hipGetLastError();
+        occ = 1;
+    }
+    cache[pi][ni][variant].store(occ, std::memory_order_relaxed);
+    return occ;
 }
 
 hipError_t launch_fused(Prec prec, int NP, int variant, int loss_mode, bool grad,

@@ -148,6 +148,8 @@ hipError_t launch_adam(int count, double *C_d, const double *grad_d, double *m_d
                        hipStream_t st);
 int fused_variant_count(Prec prec);
 int fused_systems_per_block(Prec prec, int NP, int variant);
+// Workgroups of the variant's fused kernel that one compute unit holds at once.
+int fused_blocks_per_cu(Prec prec, int NP, int variant);
 
 // ---- more than 64 loops: blocked LU with partial pivoting (solve_big.hip)
 // and GEMM-based contractions (contract_big.hip).
@@ -343,6 +345,7 @@ struct cosim_geom {
 
 struct cosim_plan {
     int device = 0;
+    int cus = 0;  // compute units of the device
     int n = 0, NP = 0, P = 0, P_pad = 0;
     double bext_z = 0.0;
     int component = 2;          // Cartesian component of the field that G holds (0 x, 1 y, 2 z)
@@ -361,7 +364,7 @@ struct cosim_plan {
     double *phi_d = nullptr;  // [3][n] loop excitation, see loop_voltage
     // workspace (device)
     size_t cap_systems = 0;
-    int cap_chunks = 0;
+    size_t cap_parts = 0;  // (P-chunk, system) slots of the partial sums rpart / lpart
     double2 *I_ws = nullptr;
     double2 *rpart = nullptr;
     double *lpart = nullptr;
