@@ -1292,3 +1292,38 @@ def test_grouped_small_instances_match_single_calls(dev):
                     if grad:
                         assert torch.equal(g, g1), (mode, prec)
                     assert int(s.abs().sum()) == 0
+
+
+@pytest.mark.gpu
+def test_reserved_plan_captures_smaller_batch(dev):
+    """cosim_plan_reserve(B, F) covers every smaller batch: a batch of one
+    system splits P into more chunks (64) than the reserved batch of 8,192
+    systems does, and its first call, captured straight into a HIP graph,
+    must allocate nothing (an allocation inside the capture fails it).
+    Replays with new capacitances equal eager calls bit for bit."""
+    from paper_2503_18479_amd import Geometry, Plan
+    wl = W.small_array(5, 5, batch=1, grid=64, n_freq=1, seed=93)
+    pl = Plan(Geometry.from_workload(wl.geom), torch.tensor(wl.pts, device=dev), wl.bext_z)
+    pl.reserve(512, 16)
+    C = torch.tensor(wl.C, device=dev)
+    o = torch.tensor(wl.omega, device=dev)
+    T = torch.tensor(wl.target, device=dev)
+    out = (torch.empty((1,), dtype=torch.float64, device=dev),
+           torch.empty((1, wl.geom.n), dtype=torch.float64, device=dev),
+           torch.empty((1, 1), dtype=torch.int32, device=dev))
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    _say("[reserve] capture of a 1-system call after reserving 8,192 systems")
+    with torch.cuda.graph(g, stream=side):
+        pl.loss_and_grad(C, o, T, precision=2, out=out)
+    for rep in range(3):
+        C.mul_(1.0 + 0.03 * (rep + 1))
+        g.replay()
+        torch.cuda.synchronize()
+        l1, g1, s1 = pl.loss_and_grad(C, o, T, precision=2)
+        torch.cuda.synchronize()
+        assert torch.equal(out[0], l1) and torch.equal(out[1], g1) and torch.equal(out[2], s1), rep
+        assert int(s1.abs().sum()) == 0
+    del g
