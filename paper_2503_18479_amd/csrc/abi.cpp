@@ -512,7 +512,11 @@ int cosim_assemble_component(cosim_geom_t g, int P, const double *pts_d, double 
     p->n = g->n;
     p->NP = padded_loops(g->n);
     p->P = P;
-    p->P_pad = (P + kPTile - 1) / kPTile * kPTile;
+    // rows of G padded with zeros: whole 64-row tiles of the fused kernels, or,
+    // above 64 loops, whole P-chunks of the adjoint GEMMs (no shorter last
+    // chunk, so each product is one strided-batched call)
+    const int prow = big_plan(p->NP) ? kBigRows : kPTile;
+    p->P_pad = (P + prow - 1) / prow * prow;
     p->bext_z = bext_z;
     p->component = component;
     p->phi_h.resize(g->n);
