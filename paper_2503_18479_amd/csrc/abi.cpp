@@ -1242,14 +1242,18 @@ int cosim_loss_and_grad_many(int count, const cosim_plan_t *plans, const int *B,
                 first_rc = fail(COSIM_EDEVICE, "grouped adjoint launch failed");
                 break;
             }
-            for (size_t m = 0; m < g.size() && first_rc == COSIM_OK; ++m) {
+            ReduceGroup rg{};
+            rg.count = (int)g.size();
+            int Bg = 0;
+            for (size_t m = 0; m < g.size(); ++m) {
                 const int i = g[m];
-                cosim_plan *p = plans[i];
-                if (launch_reduce(p->n, B[i], F[i], chunks[i], grad ? p->gsys : nullptr, p->lpart,
-                                  sg.in[m].rscale, grad ? grad_d[i] : nullptr, loss_d[i],
-                                  gs) != hipSuccess)
-                    first_rc = fail_instance(fail(COSIM_EDEVICE, "reduction launch failed"), i);
+                rg.in[m] = {grad ? plans[i]->gsys : nullptr, plans[i]->lpart,
+                            grad ? grad_d[i] : nullptr, loss_d[i], sg.in[m].rscale,
+                            plans[i]->n, B[i], F[i], chunks[i], Bg};
+                Bg += B[i];
             }
+            if (launch_reduce_group(rg, Bg, gs) != hipSuccess)
+                first_rc = fail(COSIM_EDEVICE, "grouped reduction launch failed");
             continue;
         }
         GroupArgs ga{};
@@ -1326,13 +1330,18 @@ int cosim_loss_and_grad_many(int count, const cosim_plan_t *plans, const int *B,
             first_rc = fail(COSIM_EDEVICE, "grouped adjoint launch failed");
             break;
         }
-        for (size_t m = 0; m < g.size() && first_rc == COSIM_OK; ++m) {
+        ReduceGroup rg{};
+        rg.count = (int)g.size();
+        int Bg = 0;
+        for (size_t m = 0; m < g.size(); ++m) {
             const int i = g[m];
-            cosim_plan *p = plans[i];
-            if (launch_reduce(p->n, B[i], F[i], chunks[i], grad ? p->gsys : nullptr, p->lpart,
-                              scale[m], grad ? grad_d[i] : nullptr, loss_d[i], gs) != hipSuccess)
-                first_rc = fail_instance(fail(COSIM_EDEVICE, "reduction launch failed"), i);
+            rg.in[m] = {grad ? plans[i]->gsys : nullptr, plans[i]->lpart,
+                        grad ? grad_d[i] : nullptr, loss_d[i], scale[m],
+                        plans[i]->n, B[i], F[i], chunks[i], Bg};
+            Bg += B[i];
         }
+        if (launch_reduce_group(rg, Bg, gs) != hipSuccess)
+            first_rc = fail(COSIM_EDEVICE, "grouped reduction launch failed");
     }
     for (int k = 0; k < ns; ++k) {  // join even after an error
         HIP_TRY(hipEventRecord(pool->done[k], pool->streams[k]));

@@ -232,6 +232,19 @@ struct SmallGroup {
     SmallInst in[kSmallGroupMax];
 };
 enum class SmallPhase { Factor, Fallback, Forward, Adjoint };
+// The final sums (k_reduce) of a group's members in one launch; member i owns
+// configurations [b0, b0 + B) of the launch.
+struct ReduceInst {
+    const double *gsys, *lpart;
+    double *grad, *loss;
+    double lscale;
+    int n, B, F, nchunk, b0;
+};
+struct ReduceGroup {
+    int count;
+    ReduceInst in[kGroupMax];
+};
+hipError_t launch_reduce_group(const ReduceGroup &g, int Btot, hipStream_t st);
 // One phase of the small-plan solver path (k_ldl, the pivoted fallback of
 // marked systems, the forward and the adjoint replay) over a group's S systems.
 hipError_t launch_small_group(int NP, const SmallGroup &g, int S, SmallPhase phase,

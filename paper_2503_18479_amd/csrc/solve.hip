@@ -937,12 +937,11 @@ __global__ __launch_bounds__(256) void k_replay_group(SmallGroup g, int S) {
 // loop, and the loss over frequencies and P-chunks, each lane taking every
 // 64th partial loss and the lanes combined by a fixed shuffle tree (both
 // orders are fixed, so repeated calls agree bit for bit).
-__global__ __launch_bounds__(64) void k_reduce(int n, int B, int F, int nchunk,
-                                                const double *__restrict__ gsys,
-                                                const double *__restrict__ lpart, double lscale,
-                                                double *__restrict__ grad,
-                                                double *__restrict__ loss) {
-    const int b = blockIdx.x;
+__device__ __forceinline__ void reduce_config(int b, int n, int B, int F, int nchunk,
+                                              const double *__restrict__ gsys,
+                                              const double *__restrict__ lpart, double lscale,
+                                              double *__restrict__ grad,
+                                              double *__restrict__ loss) {
     const int S = B * F;
     if (grad) {
         for (int k = threadIdx.x; k < n; k += blockDim.x) {
@@ -962,6 +961,22 @@ __global__ __launch_bounds__(64) void k_reduce(int n, int B, int F, int nchunk,
         for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
         if (threadIdx.x == 0) loss[b] = lscale * acc;
     }
+}
+
+__global__ __launch_bounds__(64) void k_reduce(int n, int B, int F, int nchunk,
+                                               const double *__restrict__ gsys,
+                                               const double *__restrict__ lpart, double lscale,
+                                               double *__restrict__ grad,
+                                               double *__restrict__ loss) {
+    reduce_config(blockIdx.x, n, B, F, nchunk, gsys, lpart, lscale, grad, loss);
+}
+
+__global__ __launch_bounds__(64) void k_reduce_group(ReduceGroup g) {
+    const int bg = blockIdx.x;
+    int i = 0;
+    while (i + 1 < g.count && bg >= g.in[i + 1].b0) ++i;
+    const ReduceInst &e = g.in[i];
+    reduce_config(bg - e.b0, e.n, e.B, e.F, e.nchunk, e.gsys, e.lpart, e.lscale, e.grad, e.loss);
 }
 
 template <bool ADJ>
@@ -1074,6 +1089,12 @@ hipError_t launch_reduce(int n, int B, int F, int nchunk, const double *gsys_d,
                          hipStream_t st) {
     hipLaunchKernelGGL(k_reduce, dim3(B), dim3(64), 0, st, n, B, F, nchunk, gsys_d, lpart_d,
                        lscale, grad_d, loss_d);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_group(const ReduceGroup &g, int Btot, hipStream_t st) {
+    if (Btot <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reduce_group, dim3(Btot), dim3(64), 0, st, g);
     return hipGetLastError();
 }
 
