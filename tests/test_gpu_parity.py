@@ -1202,6 +1202,21 @@ def test_grouped_large_instances_match_single_calls(dev):
             torch.cuda.synchronize()
             assert torch.equal(l, l1) and torch.equal(g, g1) and torch.equal(s, s1), prec
             assert int(s.abs().sum()) == 0
+    # the complex and enhancement-ratio losses, and loss-only calls, in BF16X3
+    from paper_2503_18479_amd import LOSS_COMPLEX, LOSS_RATIO
+    Rs = [1.0 + 0.5 * T / T.max() for T in Ts]
+    for mode, tg in ((LOSS_COMPLEX, Ts), (LOSS_RATIO, Rs)):
+        for grad in (True, False):
+            _say(f"[grouped] mode={mode} grad={grad}")
+            many = loss_and_grad_many(plans, Cs, Os, tg, loss_mode=mode, precision=2, grad=grad)
+            torch.cuda.synchronize()
+            for pl, C, o, T, (l, g, s) in zip(plans, Cs, Os, tg, many):
+                l1, g1, s1 = pl.loss_and_grad(C, o, T, loss_mode=mode, precision=2, grad=grad)
+                torch.cuda.synchronize()
+                assert torch.equal(l, l1) and torch.equal(s, s1), (mode, grad)
+                assert (g is None) == (not grad)
+                if grad:
+                    assert torch.equal(g, g1), mode
     gr, gouts = capture_loss_and_grad_many(plans, Cs, Os, Ts, precision=0)
     for rep in range(3):
         for C in Cs:
