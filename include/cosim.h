@@ -316,12 +316,14 @@ int cosim_adam_step(int count, double *C_d, const double *grad_d, double *m_d, d
  * for when the call returns, so the work is ordered on `stream` as one
  * operation and can be captured with it.  Each plan's own workspace is used:
  * reserve every plan beforehand.
- * Outside stream capture, instances above 64 loops with every R_k > 0 (no
- * refinement, no phase timing) that share a padded size are factored and
- * solved in shared launches, up to 24 per launch; their results equal their
- * own calls bit for bit.  Their factor records live in a library-owned
- * workspace per device, grown (after a device synchronisation) when a call
- * needs more, so the first such call, or a larger one, allocates.  Calls on
+ * Outside stream capture, instances with every R_k > 0 (no refinement, no
+ * phase timing) that share a padded loop count are factored and solved in
+ * shared launches (up to 16 per launch for 64 loops or fewer, 24 above), and
+ * their final sums run in one launch per group; their results equal their
+ * own calls bit for bit.  Above 64 loops their factor records live in a
+ * library-owned workspace per device, grown (after a device
+ * synchronisation) when a call needs more, so the first such call, or a
+ * larger one, allocates.  Calls on
  * one device may overlap (other streams, other host threads): the enqueueing
  * is serialised, and the side streams of a call that groups instances wait
  * for the previous such call to finish.  Under capture every instance runs on
