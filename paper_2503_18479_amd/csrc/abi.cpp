@@ -1216,7 +1216,37 @@ int cosim_loss_and_grad_many(int count, const cosim_plan_t *plans, const int *B,
                 first_rc = fail(COSIM_EDEVICE, "grouped solve launch failed");
                 break;
             }
-            for (size_t m = 0; m < g.size() && first_rc == COSIM_OK; ++m) {
+            // contractions: one launch for the group when every member uses the
+            // default variant, else one per member on the other side streams
+            bool one = true;
+            for (int i : g) one = one && plans[i]->variant[precision] == 0;
+            if (one) {
+                FusedGroup fg{};
+                fg.count = (int)g.size();
+                const int per_block = fused_systems_per_block(prec, NP, 0);
+                int blocks = 0;
+                bool ok = true;
+                for (size_t m = 0; m < g.size() && ok; ++m) {
+                    const int i = g[m];
+                    cosim_plan *p = plans[i];
+                    const double *Ti = T_d[i];
+                    if (ratio) {
+                        ok = launch_scale((size_t)p->P, std::fabs(p->bext_z), T_d[i], p->T_ratio,
+                                          gs) == hipSuccess;
+                        Ti = p->T_ratio;
+                    }
+                    fg.in[m] = fused_args(p, precision, B[i] * F[i], chunks[i], tpcs[i], Ti,
+                                          ratio ? p->bext_z : 0.0);
+                    fg.first[m] = blocks;
+                    fg.bx[m] = (B[i] * F[i] + per_block - 1) / per_block;
+                    blocks += fg.bx[m] * chunks[i];
+                }
+                if (!ok || launch_fused_group(prec, NP, loss_mode, grad, fg, blocks, gs) != hipSuccess) {
+                    first_rc = fail(COSIM_EDEVICE, "grouped contraction launch failed");
+                    break;
+                }
+            }
+            for (size_t m = 0; !one && m < g.size() && first_rc == COSIM_OK; ++m) {
                 const int i = g[m];
                 cosim_plan *p = plans[i];
                 hipStream_t cs = pool->streams[(k + 1 + m) % ns];

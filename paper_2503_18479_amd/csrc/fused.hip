@@ -65,8 +65,9 @@ __device__ inline T tcast(double x) {
     return (T)x;
 }
 
+// One workgroup: system block bx (4 waves of 16 NB systems) of P-chunk `chunk`.
 template <typename T, int NP, int NB, int LOSS, bool GRAD>
-__global__ __launch_bounds__(256) void k_fused(FusedArgs a) {
+__device__ __forceinline__ void fused_block(const FusedArgs &a, int bx, int chunk) {
     typedef typename Mma<T>::V V;
     constexpr int KS = NP / 4;   // forward k-steps of 4
     constexpr int IB = NP / 16;  // 16-row blocks of the adjoint output
@@ -78,8 +79,7 @@ __global__ __launch_bounds__(256) void k_fused(FusedArgs a) {
     const T *__restrict__ G = (const T *)a.G;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int r16 = lane & 15, q = lane >> 4;
-    const int sys0 = (blockIdx.x * 4 + wave) * (16 * NB);
-    const int chunk = blockIdx.y;
+    const int sys0 = (bx * 4 + wave) * (16 * NB);
     const int pb = chunk * a.rows_per_chunk;
     const int pe = min(a.P_pad, pb + a.rows_per_chunk);
 
@@ -219,6 +219,11 @@ __global__ __launch_bounds__(256) void k_fused(FusedArgs a) {
             }
         }
     }
+}
+
+template <typename T, int NP, int NB, int LOSS, bool GRAD>
+__global__ __launch_bounds__(256) void k_fused(FusedArgs a) {
+    fused_block<T, NP, NB, LOSS, GRAD>(a, blockIdx.x, blockIdx.y);
 }
 
 // ---------------------------------------------------------------------------
@@ -482,7 +487,7 @@ __device__ __forceinline__ void bf3_store(const FusedArgs &a, int chunk, int sys
 // while the current tile is computed (one barrier per tile); otherwise one
 // buffer, loaded between two barriers (half the LDS, so more blocks per CU).
 template <int NP, int NB, int PT, bool DB, int LOSS, bool GRAD>
-__global__ __launch_bounds__(256, 2) void k_fused_bf16x3(FusedArgs a) {
+__device__ __forceinline__ void bf3_block(const FusedArgs &a, int bx, int chunk) {
     static_assert(NP % 32 == 0, "bf16x3 path needs NP multiple of 32");
     static_assert(kPTile % PT == 0, "tile rows must divide the 64-row padding of G");
     constexpr int IB = NP / 16;
@@ -497,8 +502,7 @@ __global__ __launch_bounds__(256, 2) void k_fused_bf16x3(FusedArgs a) {
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int r16 = lane & 15, q = lane >> 4;
-    const int sys0 = (blockIdx.x * 4 + wave) * (16 * NB);
-    const int chunk = blockIdx.y;
+    const int sys0 = (bx * 4 + wave) * (16 * NB);
     const int pb = chunk * a.rows_per_chunk;
     const int pe = min(a.P_pad, pb + a.rows_per_chunk);
 
@@ -546,6 +550,32 @@ __global__ __launch_bounds__(256, 2) void k_fused_bf16x3(FusedArgs a) {
         }
     }
     bf3_store<NP, NB, GRAD>(a, chunk, sys0, r16, q, lacc, racc);
+}
+
+template <int NP, int NB, int PT, bool DB, int LOSS, bool GRAD>
+__global__ __launch_bounds__(256, 2) void k_fused_bf16x3(FusedArgs a) {
+    bf3_block<NP, NB, PT, DB, LOSS, GRAD>(a, blockIdx.x, blockIdx.y);
+}
+
+// The default variant (0) of each precision over the members of a group of
+// plans: workgroup b belongs to the member with first[m] <= b < first[m + 1]
+// and is its workgroup b - first[m] in (system block, chunk) order, system
+// blocks fastest.
+template <typename T, int NP, int LOSS, bool GRAD>
+__global__ __launch_bounds__(256) void k_fused_group(FusedGroup g) {
+    const int b = blockIdx.x;
+    int m = 0;
+    while (m + 1 < g.count && b >= g.first[m + 1]) ++m;
+    const int loc = b - g.first[m], bxn = g.bx[m];
+    fused_block<T, NP, (sizeof(T) == 8 ? 1 : 2), LOSS, GRAD>(g.in[m], loc % bxn, loc / bxn);
+}
+template <int NP, int LOSS, bool GRAD>
+__global__ __launch_bounds__(256, 2) void k_fused_bf16x3_group(FusedGroup g) {
+    const int b = blockIdx.x;
+    int m = 0;
+    while (m + 1 < g.count && b >= g.first[m + 1]) ++m;
+    const int loc = b - g.first[m], bxn = g.bx[m];
+    bf3_block<NP, 2, 64, false, LOSS, GRAD>(g.in[m], loc % bxn, loc / bxn);
 }
 
 // Software-pipelined form: the forward MFMAs of sub-tile j+1 are issued in the
@@ -638,6 +668,10 @@ constexpr Variant kVarBF16[] = {{2, 64, false, 0}, {2, 32, false, 0}, {1, 64, fa
                                 {1, 32, false, 0}, {2, 64, true, 0},  {2, 32, true, 0},
                                 {1, 64, true, 1},  {1, 32, true, 1},  {2, 32, true, 1},
                                 {2, 64, true, 1}};
+// the group kernels hard-wire variant 0 of each precision
+static_assert(kVarF64[0].nb == 1 && kVarF32[0].nb == 2 && kVarBF16[0].nb == 2 &&
+                  kVarBF16[0].pt == 64 && !kVarBF16[0].db && kVarBF16[0].pipe == 0,
+              "k_fused_group / k_fused_bf16x3_group follow variant 0");
 
 // With `occ` set, the resident-workgroup count per compute unit of the
 // kernel is written there and nothing is launched.
@@ -757,6 +791,52 @@ int fused_blocks_per_cu(Prec prec, int NP, int variant) {
     }
     cache[pi][ni][variant].store(occ, std::memory_order_relaxed);
     return occ;
+}
+
+namespace {
+template <int LOSS, bool GRAD>
+hipError_t go_group(Prec prec, int NP, const FusedGroup &g, int blocks, hipStream_t st) {
+#define COSIM_FUSED_GROUP(NPC)                                                                      \
+    switch (prec) {                                                                                \
+        case Prec::F64:                                                                            \
+            hipLaunchKernelGGL((k_fused_group<double, NPC, LOSS, GRAD>), dim3(blocks), dim3(256),  \
+                               0, st, g);                                                          \
+            break;                                                                                 \
+        case Prec::F32:                                                                            \
+            hipLaunchKernelGGL((k_fused_group<float, NPC, LOSS, GRAD>), dim3(blocks), dim3(256),   \
+                               0, st, g);                                                          \
+            break;                                                                                 \
+        case Prec::BF16X3:                                                                         \
+            hipLaunchKernelGGL((k_fused_bf16x3_group<NPC, LOSS, GRAD>), dim3(blocks), dim3(256),   \
+                               0, st, g);                                                          \
+            break;                                                                                 \
+    }
+    switch (NP) {
+        case 32:
+            COSIM_FUSED_GROUP(32)
+            break;
+        case 64:
+            COSIM_FUSED_GROUP(64)
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+#undef COSIM_FUSED_GROUP
+    return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_fused_group(Prec prec, int NP, int loss_mode, bool grad, const FusedGroup &g,
+                              int blocks, hipStream_t st) {
+    if (blocks <= 0) return hipSuccess;
+    if (loss_mode == COSIM_LOSS_MAG)
+        return grad ? go_group<COSIM_LOSS_MAG, true>(prec, NP, g, blocks, st)
+                    : go_group<COSIM_LOSS_MAG, false>(prec, NP, g, blocks, st);
+    if (loss_mode == COSIM_LOSS_RATIO)
+        return grad ? go_group<COSIM_LOSS_RATIO, true>(prec, NP, g, blocks, st)
+                    : go_group<COSIM_LOSS_RATIO, false>(prec, NP, g, blocks, st);
+    return grad ? go_group<COSIM_LOSS_COMPLEX, true>(prec, NP, g, blocks, st)
+                : go_group<COSIM_LOSS_COMPLEX, false>(prec, NP, g, blocks, st);
 }
 
 hipError_t launch_fused(Prec prec, int NP, int variant, int loss_mode, bool grad,

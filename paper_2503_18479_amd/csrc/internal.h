@@ -150,6 +150,18 @@ int fused_variant_count(Prec prec);
 int fused_systems_per_block(Prec prec, int NP, int variant);
 // Workgroups of the variant's fused kernel that one compute unit holds at once.
 int fused_blocks_per_cu(Prec prec, int NP, int variant);
+// The fused contraction of several plans (64 loops or fewer, one precision,
+// variant 0) in one launch: member m owns workgroups [first[m], first[m + 1])
+// (the last up to the launch's total), bx[m] system blocks times its chunks.
+constexpr int kFusedGroupMax = 16;
+struct FusedGroup {
+    int count;
+    int first[kFusedGroupMax];
+    int bx[kFusedGroupMax];
+    FusedArgs in[kFusedGroupMax];
+};
+hipError_t launch_fused_group(Prec prec, int NP, int loss_mode, bool grad, const FusedGroup &g,
+                              int blocks, hipStream_t st);
 
 // ---- more than 64 loops: blocked LU with partial pivoting (solve_big.hip)
 // and GEMM-based contractions (contract_big.hip).
@@ -216,6 +228,7 @@ struct GroupArgs {
 // member keeps its own factor record (fac) and workspace; members are stored
 // in order of their first system s0 within the group.
 constexpr int kSmallGroupMax = 16;
+static_assert(kSmallGroupMax <= kFusedGroupMax, "a small group's contractions fit one FusedGroup");
 struct SmallInst {
     const double *M, *R, *phi, *C, *omega;
     double2 *I;            // [S][n] currents (z from the factorisation, then I)
