@@ -1025,6 +1025,250 @@ int cosim_adam_step(int count, double *C_d, const double *grad_d, double *m_d, d
     return COSIM_OK;
 }
 
+// Arguments of one cosim_loss_and_grad_many call, for the group helpers.
+struct ManyCall {
+    const cosim_plan_t *plans;
+    const int *B, *F;
+    const double *const *C_d, *const *omega_d, *const *T_d;
+    double *const *loss_d, *const *grad_d;
+    int32_t *const *status_d;
+    int loss_mode, precision, ns;
+    StreamPool *pool;
+    const std::vector<int> &chunks, &tpcs;
+};
+
+// Instances of 64 loops or fewer of one padded size (group `group`, stream k of
+// the pool): factorisation, fallback and forward replay in shared launches on
+// stream k, the contractions in one shared launch there too (or, unless every
+// member uses variant 0, one per member on the other side streams), then the
+// adjoint replay and the final sums.
+static int enqueue_small_group(const ManyCall &mc, const std::vector<int> &g, int group, int k,
+                               int &next_ev) {
+    const cosim_plan_t *plans = mc.plans;
+    const int *B = mc.B, *F = mc.F;
+    const double *const *C_d = mc.C_d, *const *omega_d = mc.omega_d, *const *T_d = mc.T_d;
+    double *const *loss_d = mc.loss_d, *const *grad_d = mc.grad_d;
+    int32_t *const *status_d = mc.status_d;
+    const std::vector<int> &chunks = mc.chunks;
+    const int loss_mode = mc.loss_mode, precision = mc.precision, ns = mc.ns;
+    const Prec prec = (Prec)precision;
+    const bool grad = grad_d != nullptr, ratio = loss_mode == COSIM_LOSS_RATIO;
+    StreamPool *pool = mc.pool;
+    hipStream_t gs = pool->streams[k];
+    const int NP = plans[g[0]]->NP;
+    int first_rc = COSIM_OK;
+    const std::vector<int> &tpcs = mc.tpcs;
+    SmallGroup sg{};
+    sg.count = (int)g.size();
+    int Sg = 0;
+    for (size_t m = 0; m < g.size(); ++m) {
+        const int i = g[m];
+        cosim_plan *p = plans[i];
+        double sc = 1.0 / ((double)F[i] * (double)p->P);
+        if (ratio) sc /= p->bext_z * p->bext_z;
+        SmallInst &e = sg.in[m];
+        e.M = p->M_d;
+        e.R = p->R_d;
+        e.phi = p->phi_d;
+        e.C = C_d[i];
+        e.omega = omega_d[i];
+        e.I = p->I_ws;
+        e.rpart = p->rpart;
+        e.gsys = p->gsys;
+        e.mu = nullptr;
+        e.status = status_d[i];
+        e.fac = p->fac;
+        e.n = p->n;
+        e.F = F[i];
+        e.S = B[i] * F[i];
+        e.nchunk = chunks[i];
+        e.s0 = Sg;
+        e.rscale = sc;
+        Sg += e.S;
+    }
+    hipEvent_t ev_fwd = pool->extra[group];
+    if (launch_small_group(NP, sg, Sg, SmallPhase::Factor, gs) != hipSuccess ||
+        launch_small_group(NP, sg, Sg, SmallPhase::Fallback, gs) != hipSuccess ||
+        launch_small_group(NP, sg, Sg, SmallPhase::Forward, gs) != hipSuccess ||
+        hipEventRecord(ev_fwd, gs) != hipSuccess) {
+        return fail(COSIM_EDEVICE, "grouped solve launch failed");
+    }
+    // contractions: one launch for the group when every member uses the
+    // default variant, else one per member on the other side streams
+    bool one = true;
+    for (int i : g) one = one && plans[i]->variant[precision] == 0;
+    if (one) {
+        FusedGroup fg{};
+        fg.count = (int)g.size();
+        const int per_block = fused_systems_per_block(prec, NP, 0);
+        int blocks = 0;
+        bool ok = true;
+        for (size_t m = 0; m < g.size() && ok; ++m) {
+            const int i = g[m];
+            cosim_plan *p = plans[i];
+            const double *Ti = T_d[i];
+            if (ratio) {
+                ok = launch_scale((size_t)p->P, std::fabs(p->bext_z), T_d[i], p->T_ratio,
+                                  gs) == hipSuccess;
+                Ti = p->T_ratio;
+            }
+            fg.in[m] = fused_args(p, precision, B[i] * F[i], chunks[i], tpcs[i], Ti,
+                                  ratio ? p->bext_z : 0.0);
+            fg.first[m] = blocks;
+            fg.bx[m] = (B[i] * F[i] + per_block - 1) / per_block;
+            blocks += fg.bx[m] * chunks[i];
+        }
+        if (!ok || launch_fused_group(prec, NP, loss_mode, grad, fg, blocks, gs) != hipSuccess) {
+            return fail(COSIM_EDEVICE, "grouped contraction launch failed");
+        }
+    }
+    for (size_t m = 0; !one && m < g.size() && first_rc == COSIM_OK; ++m) {
+        const int i = g[m];
+        cosim_plan *p = plans[i];
+        hipStream_t cs = pool->streams[(k + 1 + m) % ns];
+        hipEvent_t ev_c = pool->extra[next_ev++];
+        const double *Ti = T_d[i];
+        bool ok = hipStreamWaitEvent(cs, ev_fwd, 0) == hipSuccess;
+        if (ok && ratio) {
+            ok = launch_scale((size_t)p->P, std::fabs(p->bext_z), T_d[i], p->T_ratio, cs) ==
+                 hipSuccess;
+            Ti = p->T_ratio;
+        }
+        const FusedArgs a = fused_args(p, precision, B[i] * F[i], chunks[i], tpcs[i], Ti,
+                                       ratio ? p->bext_z : 0.0);
+        ok = ok &&
+             launch_fused(prec, NP, p->variant[precision], loss_mode, grad, a, cs) ==
+                 hipSuccess &&
+             hipEventRecord(ev_c, cs) == hipSuccess &&
+             hipStreamWaitEvent(gs, ev_c, 0) == hipSuccess;
+        if (!ok) first_rc = fail_instance(fail(COSIM_EDEVICE, "contraction launch failed"), i);
+    }
+    if (first_rc != COSIM_OK) return first_rc;
+    if (grad && launch_small_group(NP, sg, Sg, SmallPhase::Adjoint, gs) != hipSuccess) {
+        return fail(COSIM_EDEVICE, "grouped adjoint launch failed");
+    }
+    ReduceGroup rg{};
+    rg.count = (int)g.size();
+    int Bg = 0;
+    for (size_t m = 0; m < g.size(); ++m) {
+        const int i = g[m];
+        rg.in[m] = {grad ? plans[i]->gsys : nullptr, plans[i]->lpart,
+                    grad ? grad_d[i] : nullptr, loss_d[i], sg.in[m].rscale,
+                    plans[i]->n, B[i], F[i], chunks[i], Bg};
+        Bg += B[i];
+    }
+    if (launch_reduce_group(rg, Bg, gs) != hipSuccess)
+        first_rc = fail(COSIM_EDEVICE, "grouped reduction launch failed");
+    return first_rc;
+}
+
+// Instances above 64 loops of one padded size (group `group`, stream k of the
+// pool): blocked LDL^T and forward solve in shared launches on stream k with
+// factor records in the pool's group workspace (running offsets `off`), the
+// GEMM contractions per member on the other side streams, then the adjoint
+// solve and the final sums on stream k.
+static int enqueue_big_group(const ManyCall &mc, const std::vector<int> &g, int group, int k,
+                             int &next_ev, size_t (&off)[5]) {
+    const cosim_plan_t *plans = mc.plans;
+    const int *B = mc.B, *F = mc.F;
+    const double *const *C_d = mc.C_d, *const *omega_d = mc.omega_d, *const *T_d = mc.T_d;
+    double *const *loss_d = mc.loss_d, *const *grad_d = mc.grad_d;
+    int32_t *const *status_d = mc.status_d;
+    const std::vector<int> &chunks = mc.chunks;
+    const int loss_mode = mc.loss_mode, precision = mc.precision, ns = mc.ns;
+    const Prec prec = (Prec)precision;
+    const bool grad = grad_d != nullptr, ratio = loss_mode == COSIM_LOSS_RATIO;
+    StreamPool *pool = mc.pool;
+    hipStream_t gs = pool->streams[k];
+    const int NP = plans[g[0]]->NP;
+    int first_rc = COSIM_OK;
+    GroupArgs ga{};
+    ga.count = (int)g.size();
+    int Sg = 0;
+    std::vector<double> scale(g.size());
+    std::vector<const double *> Teff(g.size());
+    for (size_t m = 0; m < g.size(); ++m) {
+        const int i = g[m];
+        cosim_plan *p = plans[i];
+        scale[m] = 1.0 / ((double)F[i] * (double)p->P);
+        Teff[m] = T_d[i];
+        if (ratio) scale[m] /= p->bext_z * p->bext_z;
+        GroupInst &e = ga.in[m];
+        e.M = p->M_d;
+        e.R = p->R_d;
+        e.phi = p->phi_d;
+        e.C = C_d[i];
+        e.omega = omega_d[i];
+        e.I = p->I_ws;
+        e.rhs = p->rpart;
+        e.gsys = p->gsys;
+        e.mu = nullptr;
+        e.status = status_d[i];
+        e.n = p->n;
+        e.F = F[i];
+        e.S = B[i] * F[i];
+        e.nchunk = chunks[i];
+        e.s0 = Sg;
+        e.rscale = scale[m];
+        Sg += e.S;
+    }
+    BigFactor bf;
+    bf.ldl = true;
+    bf.fmt = pool->gFmt + off[4];
+    bf.zmax = pool->gZmax + off[4];
+    bf.wt = pool->gWt + off[1];
+    bf.tinv = pool->gTinv + off[2];
+    double2 *A = pool->gA + off[0];
+    int *piv = pool->gPiv + off[3];
+    off[0] += (size_t)Sg * NP * NP;
+    off[1] += (size_t)Sg * 64 * NP;
+    off[2] += (size_t)Sg * 64 * 64;
+    off[3] += (size_t)Sg * NP;
+    off[4] += (size_t)Sg;
+    hipEvent_t ev_fwd = pool->extra[group];
+    if (big_group_factor(bf, ga, NP, Sg, A, piv, gs) != hipSuccess ||
+        big_group_solve(ga, NP, Sg, A, piv, kRhsExcitation, gs) != hipSuccess ||
+        hipEventRecord(ev_fwd, gs) != hipSuccess) {
+        return fail(COSIM_EDEVICE, "grouped solve launch failed");
+    }
+    for (size_t m = 0; m < g.size() && first_rc == COSIM_OK; ++m) {
+        const int i = g[m];
+        cosim_plan *p = plans[i];
+        hipStream_t cs = pool->streams[(k + 1 + m) % ns];
+        hipEvent_t ev_c = pool->extra[next_ev++];
+        BigArgs a = big_args(p, prec, B[i] * F[i], chunks[i], p->I_ws, Teff[m]);
+        bool ok = hipStreamWaitEvent(cs, ev_fwd, 0) == hipSuccess;
+        if (ok && ratio) {
+            ok = launch_scale((size_t)p->P, std::fabs(p->bext_z), T_d[i], p->T_ratio, cs) ==
+                 hipSuccess;
+            a.T = p->T_ratio;
+            a.inc = p->bext_z;
+        }
+        ok = ok && big_contract(p->blas, prec, loss_mode, grad, a, cs) == hipSuccess &&
+             hipEventRecord(ev_c, cs) == hipSuccess && hipStreamWaitEvent(gs, ev_c, 0) == hipSuccess;
+        if (!ok) first_rc = fail_instance(fail(COSIM_EDEVICE, "contraction launch failed"), i);
+    }
+    if (first_rc != COSIM_OK) return first_rc;
+    if (grad &&
+        big_group_solve(ga, NP, Sg, A, piv, prec == Prec::F64 ? kRhsPlanarF64 : kRhsPlanarF32,
+                        gs) != hipSuccess) {
+        return fail(COSIM_EDEVICE, "grouped adjoint launch failed");
+    }
+    ReduceGroup rg{};
+    rg.count = (int)g.size();
+    int Bg = 0;
+    for (size_t m = 0; m < g.size(); ++m) {
+        const int i = g[m];
+        rg.in[m] = {grad ? plans[i]->gsys : nullptr, plans[i]->lpart,
+                    grad ? grad_d[i] : nullptr, loss_d[i], scale[m],
+                    plans[i]->n, B[i], F[i], chunks[i], Bg};
+        Bg += B[i];
+    }
+    if (launch_reduce_group(rg, Bg, gs) != hipSuccess)
+        first_rc = fail(COSIM_EDEVICE, "grouped reduction launch failed");
+    return first_rc;
+}
+
 int cosim_loss_and_grad_many(int count, const cosim_plan_t *plans, const int *B, const int *F,
                              const double *const *C_d, const double *const *omega_d,
                              const double *const *T_d, int loss_mode, int precision,
@@ -1156,12 +1400,11 @@ int cosim_loss_and_grad_many(int count, const cosim_plan_t *plans, const int *B,
     std::stable_sort(items.begin(), items.end(),
                      [](const Item &a, const Item &b) { return a.cost > b.cost; });
     std::vector<double> load(ns, 0.0);
-    const bool grad = grad_d != nullptr;
-    const bool ratio = loss_mode == COSIM_LOSS_RATIO;
-    const Prec prec = (Prec)precision;
     size_t off[5] = {0, 0, 0, 0, 0};  // running offsets into the group workspace
     int first_rc = COSIM_OK;
     int next_ev = (int)groups.size();
+    const ManyCall mc{plans, B, F, C_d, omega_d, T_d, loss_d, grad_d, status_d,
+                      loss_mode, precision, ns, pool, chunks, tpcs};
     for (const Item &it : items) {
         if (first_rc != COSIM_OK) break;
         const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
@@ -1178,200 +1421,8 @@ int cosim_loss_and_grad_many(int count, const cosim_plan_t *plans, const int *B,
         // a group: factor and forward solve on gs, contractions spread over the
         // pool, then adjoint solve and reductions on gs
         const std::vector<int> &g = groups[it.group];
-        const int NP = plans[g[0]]->NP;
-        if (!big_plan(NP)) {
-            SmallGroup sg{};
-            sg.count = (int)g.size();
-            int Sg = 0;
-            for (size_t m = 0; m < g.size(); ++m) {
-                const int i = g[m];
-                cosim_plan *p = plans[i];
-                double sc = 1.0 / ((double)F[i] * (double)p->P);
-                if (ratio) sc /= p->bext_z * p->bext_z;
-                SmallInst &e = sg.in[m];
-                e.M = p->M_d;
-                e.R = p->R_d;
-                e.phi = p->phi_d;
-                e.C = C_d[i];
-                e.omega = omega_d[i];
-                e.I = p->I_ws;
-                e.rpart = p->rpart;
-                e.gsys = p->gsys;
-                e.mu = nullptr;
-                e.status = status_d[i];
-                e.fac = p->fac;
-                e.n = p->n;
-                e.F = F[i];
-                e.S = B[i] * F[i];
-                e.nchunk = chunks[i];
-                e.s0 = Sg;
-                e.rscale = sc;
-                Sg += e.S;
-            }
-            hipEvent_t ev_fwd = pool->extra[it.group];
-            if (launch_small_group(NP, sg, Sg, SmallPhase::Factor, gs) != hipSuccess ||
-                launch_small_group(NP, sg, Sg, SmallPhase::Fallback, gs) != hipSuccess ||
-                launch_small_group(NP, sg, Sg, SmallPhase::Forward, gs) != hipSuccess ||
-                hipEventRecord(ev_fwd, gs) != hipSuccess) {
-                first_rc = fail(COSIM_EDEVICE, "grouped solve launch failed");
-                break;
-            }
-            // contractions: one launch for the group when every member uses the
-            // default variant, else one per member on the other side streams
-            bool one = true;
-            for (int i : g) one = one && plans[i]->variant[precision] == 0;
-            if (one) {
-                FusedGroup fg{};
-                fg.count = (int)g.size();
-                const int per_block = fused_systems_per_block(prec, NP, 0);
-                int blocks = 0;
-                bool ok = true;
-                for (size_t m = 0; m < g.size() && ok; ++m) {
-                    const int i = g[m];
-                    cosim_plan *p = plans[i];
-                    const double *Ti = T_d[i];
-                    if (ratio) {
-                        ok = launch_scale((size_t)p->P, std::fabs(p->bext_z), T_d[i], p->T_ratio,
-                                          gs) == hipSuccess;
-                        Ti = p->T_ratio;
-                    }
-                    fg.in[m] = fused_args(p, precision, B[i] * F[i], chunks[i], tpcs[i], Ti,
-                                          ratio ? p->bext_z : 0.0);
-                    fg.first[m] = blocks;
-                    fg.bx[m] = (B[i] * F[i] + per_block - 1) / per_block;
-                    blocks += fg.bx[m] * chunks[i];
-                }
-                if (!ok || launch_fused_group(prec, NP, loss_mode, grad, fg, blocks, gs) != hipSuccess) {
-                    first_rc = fail(COSIM_EDEVICE, "grouped contraction launch failed");
-                    break;
-                }
-            }
-            for (size_t m = 0; !one && m < g.size() && first_rc == COSIM_OK; ++m) {
-                const int i = g[m];
-                cosim_plan *p = plans[i];
-                hipStream_t cs = pool->streams[(k + 1 + m) % ns];
-                hipEvent_t ev_c = pool->extra[next_ev++];
-                const double *Ti = T_d[i];
-                bool ok = hipStreamWaitEvent(cs, ev_fwd, 0) == hipSuccess;
-                if (ok && ratio) {
-                    ok = launch_scale((size_t)p->P, std::fabs(p->bext_z), T_d[i], p->T_ratio, cs) ==
-                         hipSuccess;
-                    Ti = p->T_ratio;
-                }
-                const FusedArgs a = fused_args(p, precision, B[i] * F[i], chunks[i], tpcs[i], Ti,
-                                               ratio ? p->bext_z : 0.0);
-                ok = ok &&
-                     launch_fused(prec, NP, p->variant[precision], loss_mode, grad, a, cs) ==
-                         hipSuccess &&
-                     hipEventRecord(ev_c, cs) == hipSuccess &&
-                     hipStreamWaitEvent(gs, ev_c, 0) == hipSuccess;
-                if (!ok) first_rc = fail_instance(fail(COSIM_EDEVICE, "contraction launch failed"), i);
-            }
-            if (first_rc != COSIM_OK) break;
-            if (grad && launch_small_group(NP, sg, Sg, SmallPhase::Adjoint, gs) != hipSuccess) {
-                first_rc = fail(COSIM_EDEVICE, "grouped adjoint launch failed");
-                break;
-            }
-            ReduceGroup rg{};
-            rg.count = (int)g.size();
-            int Bg = 0;
-            for (size_t m = 0; m < g.size(); ++m) {
-                const int i = g[m];
-                rg.in[m] = {grad ? plans[i]->gsys : nullptr, plans[i]->lpart,
-                            grad ? grad_d[i] : nullptr, loss_d[i], sg.in[m].rscale,
-                            plans[i]->n, B[i], F[i], chunks[i], Bg};
-                Bg += B[i];
-            }
-            if (launch_reduce_group(rg, Bg, gs) != hipSuccess)
-                first_rc = fail(COSIM_EDEVICE, "grouped reduction launch failed");
-            continue;
-        }
-        GroupArgs ga{};
-        ga.count = (int)g.size();
-        int Sg = 0;
-        std::vector<double> scale(g.size());
-        std::vector<const double *> Teff(g.size());
-        for (size_t m = 0; m < g.size(); ++m) {
-            const int i = g[m];
-            cosim_plan *p = plans[i];
-            scale[m] = 1.0 / ((double)F[i] * (double)p->P);
-            Teff[m] = T_d[i];
-            if (ratio) scale[m] /= p->bext_z * p->bext_z;
-            GroupInst &e = ga.in[m];
-            e.M = p->M_d;
-            e.R = p->R_d;
-            e.phi = p->phi_d;
-            e.C = C_d[i];
-            e.omega = omega_d[i];
-            e.I = p->I_ws;
-            e.rhs = p->rpart;
-            e.gsys = p->gsys;
-            e.mu = nullptr;
-            e.status = status_d[i];
-            e.n = p->n;
-            e.F = F[i];
-            e.S = B[i] * F[i];
-            e.nchunk = chunks[i];
-            e.s0 = Sg;
-            e.rscale = scale[m];
-            Sg += e.S;
-        }
-        BigFactor bf;
-        bf.ldl = true;
-        bf.fmt = pool->gFmt + off[4];
-        bf.zmax = pool->gZmax + off[4];
-        bf.wt = pool->gWt + off[1];
-        bf.tinv = pool->gTinv + off[2];
-        double2 *A = pool->gA + off[0];
-        int *piv = pool->gPiv + off[3];
-        off[0] += (size_t)Sg * NP * NP;
-        off[1] += (size_t)Sg * 64 * NP;
-        off[2] += (size_t)Sg * 64 * 64;
-        off[3] += (size_t)Sg * NP;
-        off[4] += (size_t)Sg;
-        hipEvent_t ev_fwd = pool->extra[it.group];
-        if (big_group_factor(bf, ga, NP, Sg, A, piv, gs) != hipSuccess ||
-            big_group_solve(ga, NP, Sg, A, piv, kRhsExcitation, gs) != hipSuccess ||
-            hipEventRecord(ev_fwd, gs) != hipSuccess) {
-            first_rc = fail(COSIM_EDEVICE, "grouped solve launch failed");
-            break;
-        }
-        for (size_t m = 0; m < g.size() && first_rc == COSIM_OK; ++m) {
-            const int i = g[m];
-            cosim_plan *p = plans[i];
-            hipStream_t cs = pool->streams[(k + 1 + m) % ns];
-            hipEvent_t ev_c = pool->extra[next_ev++];
-            BigArgs a = big_args(p, prec, B[i] * F[i], chunks[i], p->I_ws, Teff[m]);
-            bool ok = hipStreamWaitEvent(cs, ev_fwd, 0) == hipSuccess;
-            if (ok && ratio) {
-                ok = launch_scale((size_t)p->P, std::fabs(p->bext_z), T_d[i], p->T_ratio, cs) ==
-                     hipSuccess;
-                a.T = p->T_ratio;
-                a.inc = p->bext_z;
-            }
-            ok = ok && big_contract(p->blas, prec, loss_mode, grad, a, cs) == hipSuccess &&
-                 hipEventRecord(ev_c, cs) == hipSuccess && hipStreamWaitEvent(gs, ev_c, 0) == hipSuccess;
-            if (!ok) first_rc = fail_instance(fail(COSIM_EDEVICE, "contraction launch failed"), i);
-        }
-        if (first_rc != COSIM_OK) break;
-        if (grad &&
-            big_group_solve(ga, NP, Sg, A, piv, prec == Prec::F64 ? kRhsPlanarF64 : kRhsPlanarF32,
-                            gs) != hipSuccess) {
-            first_rc = fail(COSIM_EDEVICE, "grouped adjoint launch failed");
-            break;
-        }
-        ReduceGroup rg{};
-        rg.count = (int)g.size();
-        int Bg = 0;
-        for (size_t m = 0; m < g.size(); ++m) {
-            const int i = g[m];
-            rg.in[m] = {grad ? plans[i]->gsys : nullptr, plans[i]->lpart,
-                        grad ? grad_d[i] : nullptr, loss_d[i], scale[m],
-                        plans[i]->n, B[i], F[i], chunks[i], Bg};
-            Bg += B[i];
-        }
-        if (launch_reduce_group(rg, Bg, gs) != hipSuccess)
-            first_rc = fail(COSIM_EDEVICE, "grouped reduction launch failed");
+        first_rc = big_plan(plans[g[0]]->NP) ? enqueue_big_group(mc, g, it.group, k, next_ev, off)
+                                             : enqueue_small_group(mc, g, it.group, k, next_ev);
     }
     for (int k = 0; k < ns; ++k) {  // join even after an error
         HIP_TRY(hipEventRecord(pool->done[k], pool->streams[k]));
