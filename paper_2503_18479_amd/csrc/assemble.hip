@@ -56,7 +56,8 @@ __global__ __launch_bounds__(256) void k_assemble_G(int n, int NP, int P, int P_
                                                     uint16_t *__restrict__ Ghi,
                                                     uint16_t *__restrict__ Glo,
                                                     uint16_t *__restrict__ GThi,
-                                                    uint16_t *__restrict__ GTlo) {
+                                                    uint16_t *__restrict__ GTlo,
+                                                    uint16_t *__restrict__ G3) {
     __shared__ double tile[kGPts][kGLoops + 1];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -109,8 +110,15 @@ __global__ __launch_bounds__(256) void k_assemble_G(int n, int NP, int P, int P_
             if (G32) G32[o] = g32;
             if (Ghi) {
                 const uint16_t hi = bf16_rne(g32);
+                const uint16_t lo = bf16_rne(g32 - bf16_to_f(hi));
                 Ghi[o] = hi;
-                Glo[o] = bf16_rne(g32 - bf16_to_f(hi));
+                Glo[o] = lo;
+                if (G3) {  // row pr of [P_pad][3 NP]: hi | hi | lo
+                    uint16_t *r3 = G3 + (size_t)pr * 3 * NP + k0 + kk;
+                    r3[0] = hi;
+                    r3[NP] = hi;
+                    r3[2 * NP] = lo;
+                }
             }
         }
         // transposed bf16 copies [NP][P_pad]: each loop's column is contiguous in p
@@ -263,10 +271,10 @@ __global__ __launch_bounds__(256) void k_assemble_M(int n, const int32_t *__rest
 hipError_t launch_assemble_G(int n, int NP, int P, int P_pad, int comp, const int32_t *seg_off_d,
                              const double *verts_d, const double *pts_d, double *G64,
                              float *G32, uint16_t *Ghi, uint16_t *Glo, uint16_t *GThi,
-                             uint16_t *GTlo, hipStream_t st) {
+                             uint16_t *GTlo, uint16_t *G3, hipStream_t st) {
     const int blocks = (P_pad + kGPts - 1) / kGPts;
     hipLaunchKernelGGL(k_assemble_G, dim3(blocks), dim3(256), 0, st, n, NP, P, P_pad, comp, seg_off_d,
-                       verts_d, pts_d, G64, G32, Ghi, Glo, GThi, GTlo);
+                       verts_d, pts_d, G64, G32, Ghi, Glo, GThi, GTlo, G3);
     return hipGetLastError();
 }
 

@@ -12,8 +12,10 @@
 //   R_c = G_c^T W_c    per P-chunk c of kBigRows rows (K = rows of the chunk),
 //                      NP x 2S planes, summed over chunks in FP64 by the solve.
 // BF16X3 splits both operands into bf16 hi / lo and adds the three products
-// hi hi + hi lo + lo hi into FP32 (beta = 1).  G is stored [P_pad][NP]
-// row-major, i.e. column-major NP x P_pad, so both GEMMs read it in place.
+// hi hi + hi lo + lo hi into FP32: the forward product as one GEMM over
+// K = 3 NP ((hi | hi | lo) rows of G against (hi; lo; hi) planes of I), the
+// adjoint as three GEMMs per chunk batch (beta = 1).  G is stored [P_pad][NP]
+// row-major, i.e. column-major NP x P_pad, so the GEMMs read it in place.
 #include <rocblas/rocblas.h>
 
 #include <algorithm>
@@ -33,11 +35,11 @@ __device__ inline float bf16_float(uint16_t h) {
 }
 
 // X[(2s + c) NP + k] = (Re, Im)_c of I[s][k], 0 for k >= n.
-// PREC 0: double planes; 1: float; 2: bf16 hi planes in X, lo planes in Xlo.
+// PREC 0: double planes; 1: float; 2: bf16 planes of 3 NP rows, each plane
+// (hi; lo; hi) of its values (the operand of the one-GEMM forward product).
 template <int PREC>
 __global__ __launch_bounds__(256) void k_pack_x(int n, int NP, int S,
-                                                const double2 *__restrict__ I, void *X,
-                                                uint16_t *Xlo) {
+                                                const double2 *__restrict__ I, void *X) {
     const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
     if (e >= (size_t)S * NP) return;
     const int s = (int)(e / NP), k = (int)(e - (size_t)s * NP);
@@ -52,10 +54,14 @@ __global__ __launch_bounds__(256) void k_pack_x(int n, int NP, int S,
     } else {
         const float re = (float)v.x, im = (float)v.y;
         const uint16_t hr = bf16_bits(re), hi = bf16_bits(im);
-        ((uint16_t *)X)[o0] = hr;
-        ((uint16_t *)X)[o1] = hi;
-        Xlo[o0] = bf16_bits(re - bf16_float(hr));
-        Xlo[o1] = bf16_bits(im - bf16_float(hi));
+        uint16_t *pr = (uint16_t *)X + (size_t)(2 * s) * 3 * NP + k;  // plane 2s
+        uint16_t *pi = pr + 3 * NP;                                   // plane 2s + 1
+        pr[0] = hr;
+        pr[NP] = bf16_bits(re - bf16_float(hr));
+        pr[2 * NP] = hr;
+        pi[0] = hi;
+        pi[NP] = bf16_bits(im - bf16_float(hi));
+        pi[2 * NP] = hi;
     }
 }
 
@@ -178,16 +184,15 @@ hipError_t big_contract(void *handle, Prec prec, int loss_mode, bool grad, const
     // 1. X planes
     const size_t nx = (size_t)S * NP;
     const dim3 gx((unsigned)((nx + 255) / 256));
-    uint16_t *Xlo = (uint16_t *)a.X + planes * NP;  // bf16 only: lo planes after the hi planes
     switch (prec) {
         case Prec::F64:
-            hipLaunchKernelGGL(k_pack_x<0>, gx, dim3(256), 0, st, a.n, NP, S, a.I, a.X, nullptr);
+            hipLaunchKernelGGL(k_pack_x<0>, gx, dim3(256), 0, st, a.n, NP, S, a.I, a.X);
             break;
         case Prec::F32:
-            hipLaunchKernelGGL(k_pack_x<1>, gx, dim3(256), 0, st, a.n, NP, S, a.I, a.X, nullptr);
+            hipLaunchKernelGGL(k_pack_x<1>, gx, dim3(256), 0, st, a.n, NP, S, a.I, a.X);
             break;
         case Prec::BF16X3:
-            hipLaunchKernelGGL(k_pack_x<2>, gx, dim3(256), 0, st, a.n, NP, S, a.I, a.X, Xlo);
+            hipLaunchKernelGGL(k_pack_x<2>, gx, dim3(256), 0, st, a.n, NP, S, a.I, a.X);
             break;
     }
     hipError_t e = hipGetLastError();
@@ -195,11 +200,9 @@ hipError_t big_contract(void *handle, Prec prec, int loss_mode, bool grad, const
     // 2. Y = G X
     const rocblas_operation T_ = rocblas_operation_transpose;
     if (prec == Prec::BF16X3) {
-        if ((e = gemm(h, prec, T_, P_pad, (int)planes, NP, a.Ghi, NP, a.X, NP, 0.0f, a.Y, P_pad)))
-            return e;
-        if ((e = gemm(h, prec, T_, P_pad, (int)planes, NP, a.Ghi, NP, Xlo, NP, 1.0f, a.Y, P_pad)))
-            return e;
-        if ((e = gemm(h, prec, T_, P_pad, (int)planes, NP, a.Glo, NP, a.X, NP, 1.0f, a.Y, P_pad)))
+        // (hi | hi | lo) rows of G times (hi; lo; hi) planes of I: Gh Ih + Gh Il + Gl Ih
+        if ((e = gemm(h, prec, T_, P_pad, (int)planes, 3 * NP, a.G3, 3 * NP, a.X, 3 * NP, 0.0f,
+                      a.Y, P_pad)))
             return e;
     } else {
         if ((e = gemm(h, prec, T_, P_pad, (int)planes, NP, a.G, NP, a.X, NP, 0.0f, a.Y, P_pad)))
