@@ -270,6 +270,7 @@ BigArgs big_args(const cosim_plan *p, Prec prec, int S, int nchunk, const double
     a.Ghi = p->Ghi;
     a.Glo = p->Glo;
     a.G3 = p->G3;
+    a.GA3 = p->GA3;
     a.I = I;
     a.T = T;
     a.X = p->bX;
@@ -557,7 +558,8 @@ int cosim_assemble_component(cosim_geom_t g, int P, const double *pts_d, double 
          (hipMalloc((void **)&p->GThi, gsz * sizeof(uint16_t)) != hipSuccess ||
           hipMalloc((void **)&p->GTlo, gsz * sizeof(uint16_t)) != hipSuccess)) ||
         (want16 && big_plan(p->NP) &&
-         hipMalloc((void **)&p->G3, 3 * gsz * sizeof(uint16_t)) != hipSuccess) ||
+         (hipMalloc((void **)&p->G3, 3 * gsz * sizeof(uint16_t)) != hipSuccess ||
+          hipMalloc((void **)&p->GA3, 3 * gsz * sizeof(uint16_t)) != hipSuccess)) ||
         hipMalloc((void **)&p->M_d, n * n * sizeof(double)) != hipSuccess ||
         hipMalloc((void **)&p->phi_d, 3 * n * sizeof(double)) != hipSuccess ||
         hipMalloc((void **)&p->R_d, n * sizeof(double)) != hipSuccess ||
@@ -579,7 +581,7 @@ int cosim_assemble_component(cosim_geom_t g, int P, const double *pts_d, double 
     ASM_TRY(hipMemcpyAsync(p->R_d, g->R.data(), n * sizeof(double), hipMemcpyHostToDevice, st));
     ASM_TRY(hipMemcpyAsync(p->phi_d, p->exc_h.data(), 3 * n * sizeof(double), hipMemcpyHostToDevice, st));
     ASM_TRY(launch_assemble_G(g->n, p->NP, P, p->P_pad, component, seg_d, verts_d, pts_d, p->G64, p->G32,
-                              p->Ghi, p->Glo, p->GThi, p->GTlo, p->G3, st));
+                              p->Ghi, p->Glo, p->GThi, p->GTlo, p->G3, p->GA3, st));
     ASM_TRY(launch_assemble_M(g->n, seg_d, verts_d, wa_d, make_gl_rule(), p->M_d, st));
     p->M_h.resize(n * n);
     ASM_TRY(hipMemcpyAsync(p->M_h.data(), p->M_d, n * n * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -602,6 +604,7 @@ int cosim_plan_destroy(cosim_plan_t p) {
     dfree(p->GThi);
     dfree(p->GTlo);
     dfree(p->G3);
+    dfree(p->GA3);
     dfree(p->M_d);
     dfree(p->phi_d);
     dfree(p->R_d);

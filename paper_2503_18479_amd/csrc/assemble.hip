@@ -57,7 +57,8 @@ __global__ __launch_bounds__(256) void k_assemble_G(int n, int NP, int P, int P_
                                                     uint16_t *__restrict__ Glo,
                                                     uint16_t *__restrict__ GThi,
                                                     uint16_t *__restrict__ GTlo,
-                                                    uint16_t *__restrict__ G3) {
+                                                    uint16_t *__restrict__ G3,
+                                                    uint16_t *__restrict__ GA3) {
     __shared__ double tile[kGPts][kGLoops + 1];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -118,6 +119,13 @@ __global__ __launch_bounds__(256) void k_assemble_G(int n, int NP, int P, int P_
                     r3[0] = hi;
                     r3[NP] = hi;
                     r3[2 * NP] = lo;
+                }
+                if (GA3) {  // chunk c = pr / kBigRows: [3][kBigRows][NP], hi, hi, lo
+                    const int c = pr / kBigRows, r = pr - c * kBigRows;
+                    uint16_t *a3 = GA3 + ((size_t)3 * c * kBigRows + r) * NP + k0 + kk;
+                    a3[0] = hi;
+                    a3[(size_t)kBigRows * NP] = hi;
+                    a3[(size_t)2 * kBigRows * NP] = lo;
                 }
             }
         }
@@ -271,10 +279,10 @@ __global__ __launch_bounds__(256) void k_assemble_M(int n, const int32_t *__rest
 hipError_t launch_assemble_G(int n, int NP, int P, int P_pad, int comp, const int32_t *seg_off_d,
                              const double *verts_d, const double *pts_d, double *G64,
                              float *G32, uint16_t *Ghi, uint16_t *Glo, uint16_t *GThi,
-                             uint16_t *GTlo, uint16_t *G3, hipStream_t st) {
+                             uint16_t *GTlo, uint16_t *G3, uint16_t *GA3, hipStream_t st) {
     const int blocks = (P_pad + kGPts - 1) / kGPts;
     hipLaunchKernelGGL(k_assemble_G, dim3(blocks), dim3(256), 0, st, n, NP, P, P_pad, comp, seg_off_d,
-                       verts_d, pts_d, G64, G32, Ghi, Glo, GThi, GTlo, G3);
+                       verts_d, pts_d, G64, G32, Ghi, Glo, GThi, GTlo, G3, GA3);
     return hipGetLastError();
 }
 

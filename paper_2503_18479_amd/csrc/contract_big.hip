@@ -12,10 +12,11 @@
 //   R_c = G_c^T W_c    per P-chunk c of kBigRows rows (K = rows of the chunk),
 //                      NP x 2S planes, summed over chunks in FP64 by the solve.
 // BF16X3 splits both operands into bf16 hi / lo and adds the three products
-// hi hi + hi lo + lo hi into FP32: the forward product as one GEMM over
-// K = 3 NP ((hi | hi | lo) rows of G against (hi; lo; hi) planes of I), the
-// adjoint as three GEMMs per chunk batch (beta = 1).  G is stored [P_pad][NP]
-// row-major, i.e. column-major NP x P_pad, so the GEMMs read it in place.
+// hi hi + hi lo + lo hi into FP32, each contraction as one GEMM: the forward
+// over K = 3 NP ((hi | hi | lo) rows of G against (hi; lo; hi) planes of I),
+// the adjoint per chunk over K = 3 rows (the chunk's hi, hi, lo rows of G
+// against (hi; lo; hi) rows of w).  G is stored [P_pad][NP] row-major, i.e.
+// column-major NP x P_pad, so the FP64 / FP32 GEMMs read it in place.
 #include <rocblas/rocblas.h>
 
 #include <algorithm>
@@ -70,7 +71,7 @@ __global__ __launch_bounds__(256) void k_pack_x(int n, int NP, int S,
 template <int PREC, int LOSS, bool GRAD>
 __global__ __launch_bounds__(256) void k_epilogue_big(int P, int P_pad, int S, int rows,
                                                       const void *Y, const double *__restrict__ T,
-                                                      void *W, uint16_t *Wlo,
+                                                      void *W,
                                                       double *__restrict__ lpart, double inc) {
     __shared__ double red[4];
     const int s = blockIdx.x, c = blockIdx.y;
@@ -94,12 +95,17 @@ __global__ __launch_bounds__(256) void k_epilogue_big(int P, int P_pad, int S, i
                 if (PREC == 1) {
                     ((float *)W)[o0 + p] = x;
                     ((float *)W)[o1 + p] = y;
-                } else {
+                } else {  // chunk c, planes 2s and 2s + 1: 3 rows (hi; lo; hi) each
                     const uint16_t hx = bf16_bits(x), hy = bf16_bits(y);
-                    ((uint16_t *)W)[o0 + p] = hx;
-                    ((uint16_t *)W)[o1 + p] = hy;
-                    Wlo[o0 + p] = bf16_bits(x - bf16_float(hx));
-                    Wlo[o1 + p] = bf16_bits(y - bf16_float(hy));
+                    const size_t w0 = ((size_t)c * 2 * S + 2 * s) * 3 * rows + (p - p0);
+                    const size_t w1 = w0 + (size_t)3 * rows;
+                    uint16_t *Wb = (uint16_t *)W;
+                    Wb[w0] = hx;
+                    Wb[w0 + rows] = bf16_bits(x - bf16_float(hx));
+                    Wb[w0 + 2 * rows] = hx;
+                    Wb[w1] = hy;
+                    Wb[w1 + rows] = bf16_bits(y - bf16_float(hy));
+                    Wb[w1 + 2 * rows] = hy;
                 }
             }
         }
@@ -149,14 +155,14 @@ hipError_t gemm(rocblas_handle h, Prec prec, rocblas_operation ta, int m, int nn
 
 template <int PREC, int LOSS>
 hipError_t launch_epi(bool grad, dim3 grid, hipStream_t st, int P, int P_pad, int S, int rows,
-                      const void *Y, const double *T, void *W, uint16_t *Wlo, double *lpart,
+                      const void *Y, const double *T, void *W, double *lpart,
                       double inc) {
     if (grad)
         hipLaunchKernelGGL((k_epilogue_big<PREC, LOSS, true>), grid, dim3(256), 0, st, P, P_pad, S,
-                           rows, Y, T, W, Wlo, lpart, inc);
+                           rows, Y, T, W, lpart, inc);
     else
         hipLaunchKernelGGL((k_epilogue_big<PREC, LOSS, false>), grid, dim3(256), 0, st, P, P_pad,
-                           S, rows, Y, T, W, Wlo, lpart, inc);
+                           S, rows, Y, T, W, lpart, inc);
     return hipGetLastError();
 }
 
@@ -210,17 +216,16 @@ hipError_t big_contract(void *handle, Prec prec, int loss_mode, bool grad, const
     }
     // 3. loss partials and w planes
     const dim3 ge(S, a.nchunk);
-    uint16_t *Wlo = (uint16_t *)a.W + planes * P_pad;
     const int pr = prec == Prec::F64 ? 0 : (prec == Prec::F32 ? 1 : 2);
 #define COSIM_EPI(PR)                                                                          \
     (loss_mode == COSIM_LOSS_MAG                                                               \
          ? launch_epi<PR, COSIM_LOSS_MAG>(grad, ge, st, a.P, P_pad, S, a.rows, a.Y, a.T, a.W,  \
-                                          Wlo, a.lpart, a.inc)                                  \
+                                          a.lpart, a.inc)                                  \
      : loss_mode == COSIM_LOSS_RATIO                                                           \
          ? launch_epi<PR, COSIM_LOSS_RATIO>(grad, ge, st, a.P, P_pad, S, a.rows, a.Y, a.T,     \
-                                            a.W, Wlo, a.lpart, a.inc)                           \
+                                            a.W, a.lpart, a.inc)                           \
          : launch_epi<PR, COSIM_LOSS_COMPLEX>(grad, ge, st, a.P, P_pad, S, a.rows, a.Y, a.T,   \
-                                              a.W, Wlo, a.lpart, a.inc))
+                                              a.W, a.lpart, a.inc))
     e = pr == 0 ? COSIM_EPI(0) : (pr == 1 ? COSIM_EPI(1) : COSIM_EPI(2));
 #undef COSIM_EPI
     if (e != hipSuccess || !grad) return e;
@@ -257,17 +262,30 @@ hipError_t gemm_chunks(rocblas_handle h, Prec prec, int NP, int planes, int rows
 }
 
 // Adjoint GEMMs only (W already holds the planes of w): the full chunks in one
-// strided-batched call per product, a shorter last chunk in another.
+// strided-batched call, a shorter last chunk in another.  BF16X3: the three
+// products of a chunk are one GEMM over K = 3 rows ((hi, hi, lo) rows of G in
+// GA3 against the (hi; lo; hi) w rows the epilogue wrote), whole chunks only.
 hipError_t big_adjoint(void *handle, Prec prec, const BigArgs &a, hipStream_t st) {
     rocblas_handle h = (rocblas_handle)handle;
     if (rocblas_set_stream(h, st) != rocblas_status_success) return hipErrorInvalidValue;
     const int S = a.S, NP = a.NP, P_pad = a.P_pad;
     const int planes = 2 * S;
     const size_t esz = prec == Prec::F64 ? sizeof(double) : sizeof(float);
-    const size_t gsz = prec == Prec::F64 ? sizeof(double) : (prec == Prec::F32 ? sizeof(float) : sizeof(uint16_t));
-    const uint16_t *Wlo = (const uint16_t *)a.W + (size_t)planes * P_pad;
+    const size_t gsz = prec == Prec::F64 ? sizeof(double) : sizeof(float);
     const int full = P_pad / a.rows;                   // whole chunks
     const int tail = P_pad - full * a.rows;            // rows of a last, shorter chunk
+    if (prec == Prec::BF16X3) {
+        if (tail != 0 || !a.GA3) return hipErrorInvalidValue;  // P_pad is whole chunks here
+        const int K = 3 * a.rows;
+        const float one = 1.0f, zero = 0.0f;
+        const rocblas_operation N_ = rocblas_operation_none;
+        return blas_status(rocblas_gemm_strided_batched_ex(
+            h, N_, N_, NP, planes, K, &one, a.GA3, rocblas_datatype_bf16_r, NP,
+            (rocblas_stride)K * NP, a.W, rocblas_datatype_bf16_r, K, (rocblas_stride)K * planes,
+            &zero, a.R, rocblas_datatype_f32_r, NP, (rocblas_stride)NP * planes, a.R,
+            rocblas_datatype_f32_r, NP, (rocblas_stride)NP * planes, full, rocblas_datatype_f32_r,
+            rocblas_gemm_algo_standard, 0, 0));
+    }
     hipError_t e = hipSuccess;
     for (int part = 0; part < 2; ++part) {
         const int nb = part == 0 ? full : (tail > 0 ? 1 : 0);
@@ -275,19 +293,9 @@ hipError_t big_adjoint(void *handle, Prec prec, const BigArgs &a, hipStream_t st
         if (nb == 0) continue;
         const size_t p0 = part == 0 ? 0 : (size_t)full * a.rows;
         char *R = (char *)a.R + (part == 0 ? 0 : (size_t)full * NP * planes * esz);
-        if (prec == Prec::BF16X3) {
-            const char *gh = (const char *)a.Ghi + p0 * NP * gsz;
-            const char *gl = (const char *)a.Glo + p0 * NP * gsz;
-            const char *wh = (const char *)a.W + p0 * gsz;
-            const char *wl = (const char *)Wlo + p0 * gsz;
-            if ((e = gemm_chunks(h, prec, NP, planes, rows, nb, P_pad, gh, gsz, wh, gsz, 0.0f, R, esz))) return e;
-            if ((e = gemm_chunks(h, prec, NP, planes, rows, nb, P_pad, gh, gsz, wl, gsz, 1.0f, R, esz))) return e;
-            if ((e = gemm_chunks(h, prec, NP, planes, rows, nb, P_pad, gl, gsz, wh, gsz, 1.0f, R, esz))) return e;
-        } else {
-            const char *g = (const char *)a.G + p0 * NP * gsz;
-            const char *w = (const char *)a.W + p0 * gsz;
-            if ((e = gemm_chunks(h, prec, NP, planes, rows, nb, P_pad, g, gsz, w, gsz, 0.0f, R, esz))) return e;
-        }
+        const char *g = (const char *)a.G + p0 * NP * gsz;
+        const char *w = (const char *)a.W + p0 * gsz;
+        if ((e = gemm_chunks(h, prec, NP, planes, rows, nb, P_pad, g, gsz, w, gsz, 0.0f, R, esz))) return e;
     }
     return e;
 }

@@ -54,7 +54,7 @@ constexpr int kBigRows = 2048;      // P-chunk of the adjoint GEMMs above 64 loo
 hipError_t launch_assemble_G(int n, int NP, int P, int P_pad, int comp, const int32_t *seg_off_d,
                              const double *verts_d, const double *pts_d, double *G64,
                              float *G32, uint16_t *Ghi, uint16_t *Glo, uint16_t *GThi,
-                             uint16_t *GTlo, uint16_t *G3, hipStream_t st);
+                             uint16_t *GTlo, uint16_t *G3, uint16_t *GA3, hipStream_t st);
 
 hipError_t launch_assemble_M(int n, const int32_t *seg_off_d, const double *verts_d,
                              const double *wire_a_d, const GLRule &gl, double *M_d,
@@ -280,11 +280,15 @@ struct BigArgs {
     // [P_pad][3 NP] rows (hi | hi | lo) of G: with X = (hi; lo; hi) planes of I the
     // three bf16 products of the forward contraction are one GEMM over K = 3 NP
     const uint16_t *G3;
+    // per P-chunk c of `rows` rows, [3][rows][NP]: the chunk's rows of G hi, hi
+    // again and lo, i.e. column-major NP x 3 rows; with the chunk's w planes as
+    // (hi; lo; hi) over 3 rows the adjoint's three bf16 products are one GEMM
+    const uint16_t *GA3;
     const double2 *I;                      // [S][n]
     const double *T;                       // [P]
     void *X;     // NP x 2S planes of I (BF16X3: 3 NP x 2S, each plane hi, lo, hi)
     void *Y;     // P_pad x 2S planes of B
-    void *W;     // P_pad x 2S planes of w (BF16X3: hi, then lo)
+    void *W;     // P_pad x 2S planes of w (BF16X3: per chunk c and plane j, 3 rows (hi; lo; hi))
     void *R;     // nchunk blocks of NP x 2S planes (double for F64, float otherwise)
     double *lpart;  // [nchunk][S]
     double inc = 0.0;  // incident field added before the loss (COSIM_LOSS_RATIO)
@@ -390,6 +394,7 @@ struct cosim_plan {
     uint16_t *Ghi = nullptr, *Glo = nullptr;
     uint16_t *GThi = nullptr, *GTlo = nullptr;  // transposed copies [NP][P_pad]
     uint16_t *G3 = nullptr;  // above 64 loops: [P_pad][3 NP] rows (hi | hi | lo), see BigArgs
+    uint16_t *GA3 = nullptr; // above 64 loops: per adjoint chunk [3][kBigRows][NP] (hi, hi, lo)
     double *M_d = nullptr, *R_d = nullptr;
     double *phi_d = nullptr;  // [3][n] loop excitation, see loop_voltage
     // workspace (device)
