@@ -267,8 +267,6 @@ BigArgs big_args(const cosim_plan *p, Prec prec, int S, int nchunk, const double
     a.nchunk = nchunk;
     a.rows = kBigRows;
     a.G = prec == Prec::F64 ? (const void *)p->G64 : (const void *)p->G32;
-    a.Ghi = p->Ghi;
-    a.Glo = p->Glo;
     a.G3 = p->G3;
     a.GA3 = p->GA3;
     a.I = I;
@@ -552,8 +550,9 @@ int cosim_assemble_component(cosim_geom_t g, int P, const double *pts_d, double 
     const size_t n = (size_t)g->n;
     if ((want64 && hipMalloc((void **)&p->G64, gsz * sizeof(double)) != hipSuccess) ||
         (want32 && hipMalloc((void **)&p->G32, gsz * sizeof(float)) != hipSuccess) ||
-        (want16 && hipMalloc((void **)&p->Ghi, gsz * sizeof(uint16_t)) != hipSuccess) ||
-        (want16 && hipMalloc((void **)&p->Glo, gsz * sizeof(uint16_t)) != hipSuccess) ||
+        (want16 && !big_plan(p->NP) &&
+         (hipMalloc((void **)&p->Ghi, gsz * sizeof(uint16_t)) != hipSuccess ||
+          hipMalloc((void **)&p->Glo, gsz * sizeof(uint16_t)) != hipSuccess)) ||
         (want16 && !big_plan(p->NP) &&
          (hipMalloc((void **)&p->GThi, gsz * sizeof(uint16_t)) != hipSuccess ||
           hipMalloc((void **)&p->GTlo, gsz * sizeof(uint16_t)) != hipSuccess)) ||

@@ -109,11 +109,13 @@ __global__ __launch_bounds__(256) void k_assemble_G(int n, int NP, int P, int P_
             const float g32 = (float)g;
             if (G64) G64[o] = g;  // copies the plan did not ask for are null
             if (G32) G32[o] = g32;
-            if (Ghi) {
+            if (Ghi || G3) {
                 const uint16_t hi = bf16_rne(g32);
                 const uint16_t lo = bf16_rne(g32 - bf16_to_f(hi));
-                Ghi[o] = hi;
-                Glo[o] = lo;
+                if (Ghi) {
+                    Ghi[o] = hi;
+                    Glo[o] = lo;
+                }
                 if (G3) {  // row pr of [P_pad][3 NP]: hi | hi | lo
                     uint16_t *r3 = G3 + (size_t)pr * 3 * NP + k0 + kk;
                     r3[0] = hi;

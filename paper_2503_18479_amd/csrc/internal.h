@@ -276,7 +276,6 @@ hipError_t launch_lu_solve(int NP, int n, int S, int F, const double2 *A_d, cons
 struct BigArgs {
     int n, NP, P, P_pad, S, nchunk, rows;  // rows: P-chunk of the adjoint GEMMs
     const void *G;                         // [P_pad][NP] FP64 or FP32 (F64 / F32)
-    const uint16_t *Ghi, *Glo;             // [P_pad][NP] bf16 hi / lo (BF16X3)
     // [P_pad][3 NP] rows (hi | hi | lo) of G: with X = (hi; lo; hi) planes of I the
     // three bf16 products of the forward contraction are one GEMM over K = 3 NP
     const uint16_t *G3;
@@ -391,7 +390,7 @@ struct cosim_plan {
     // operators (device)
     double *G64 = nullptr;
     float *G32 = nullptr;
-    uint16_t *Ghi = nullptr, *Glo = nullptr;
+    uint16_t *Ghi = nullptr, *Glo = nullptr;  // [P_pad][NP] bf16 hi / lo, 64 loops or fewer
     uint16_t *GThi = nullptr, *GTlo = nullptr;  // transposed copies [NP][P_pad]
     uint16_t *G3 = nullptr;  // above 64 loops: [P_pad][3 NP] rows (hi | hi | lo), see BigArgs
     uint16_t *GA3 = nullptr; // above 64 loops: per adjoint chunk [3][kBigRows][NP] (hi, hi, lo)
