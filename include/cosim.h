@@ -38,6 +38,7 @@
 #ifndef COSIM_H
 #define COSIM_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -248,6 +249,30 @@ int cosim_field_backward(cosim_plan_t p, int B, int F, const double *C_d, const 
 int cosim_loss_and_grad(cosim_plan_t p, int B, int F, const double *C_d, const double *omega_d,
                         const double *T_d, int loss_mode, int precision, double *loss_d,
                         double *grad_d, int32_t *status_d, void *stream);
+
+/* cosim_loss_and_grad for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): same arguments, same results (bit for bit), but the call's
+ * device buffers -- currents, factor records, partial sums and per-system
+ * gradient terms -- live in a library-owned device array of
+ * cosim_noalloc_scratch_bytes() bytes (64 MiB) per device instead of the
+ * plan's workspace, so the call never allocates, frees or reserves memory
+ * and leaves the plan's workspace untouched.  The array is taken on a
+ * device's first call and held until the process ends.  Every call on one
+ * device shares that device's array: calls that overlap on one device (other
+ * streams, other threads) race and must be ordered by the caller.  The array
+ * keeps the last call's contents; nothing in it needs to start at zero.
+ * Plans of at most 64 loops (else COSIM_EUNSUPPORTED).  A call whose
+ * buffers do not fit -- about 16 NP^2 + 16 NP nchunk + 40 NP bytes per
+ * system with NP = 32 or 64 the padded loop count and nchunk the P-chunks of
+ * the fused contraction, i.e. several hundred 64-loop systems -- returns
+ * COSIM_EINVAL naming the size.  No phase timing. */
+int cosim_loss_and_grad_noalloc(cosim_plan_t p, int B, int F, const double *C_d,
+                                const double *omega_d, const double *T_d, int loss_mode,
+                                int precision, double *loss_d, double *grad_d, int32_t *status_d,
+                                void *stream);
+/* Bytes of the per-device array behind cosim_loss_and_grad_noalloc. */
+size_t cosim_noalloc_scratch_bytes(void);
 
 /* Loss, dL/dC and the gradients with respect to the other circuit variables of
  * Fig. 2 / Eq. 11, for the same call as cosim_loss_and_grad (which it runs):

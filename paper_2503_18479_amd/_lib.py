@@ -35,6 +35,9 @@ SIGNATURES = {
                                      c_void_p, c_void_p, c_void_p]),
     "cosim_loss_and_grad": (c_int, [c_void_p, c_int, c_int, c_void_p, c_void_p, c_void_p, c_int,
                                     c_int, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "cosim_loss_and_grad_noalloc": (c_int, [c_void_p, c_int, c_int, c_void_p, c_void_p, c_void_p,
+                                            c_int, c_int, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "cosim_noalloc_scratch_bytes": (ctypes.c_size_t, []),
     "cosim_assemble_ex": (c_int, [c_void_p, c_int, c_void_p, c_double, c_int, c_void_p, P(c_void_p)]),
     "cosim_assemble_component": (c_int, [c_void_p, c_int, c_void_p, c_double, c_int, c_int, c_void_p,
                                          P(c_void_p)]),

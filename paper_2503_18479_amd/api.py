@@ -242,6 +242,22 @@ class Plan:
         return loss, g, st
 
 
+    def loss_and_grad_noalloc(self, C: torch.Tensor, omega: torch.Tensor, T: torch.Tensor,
+                              out: Tuple[torch.Tensor, Optional[torch.Tensor], torch.Tensor],
+                              loss_mode: int = LOSS_MAG, precision=FP32) -> None:
+        """cosim_loss_and_grad_noalloc into caller-allocated outputs
+        (loss [B], dL/dC [B][n] or None, status [B][F]): the call itself
+        allocates no device memory (64 loops or fewer, bounded size)."""
+        prec = precision_code(precision)
+        B, F = int(C.shape[0]), int(omega.shape[0])
+        loss, g, st = out
+        gp = (_dev(g, torch.float64, (B, self.n), "grad") if g is not None else ctypes.c_void_p())
+        check(self._lib.cosim_loss_and_grad_noalloc(
+            self._h, B, F, _dev(C, torch.float64, (B, self.n), "C"),
+            _dev(omega, torch.float64, (F,), "omega"), _dev(T, torch.float64, (self.P,), "T"),
+            int(loss_mode), prec, _dev(loss, torch.float64, (B,), "loss"), gp,
+            _dev(st, torch.int32, (B, F), "status"), _stream()))
+
     # -- optimisation driver ----------------------------------------------------
     def loss_and_grad_params(self, C: torch.Tensor, omega: torch.Tensor, T: torch.Tensor,
                              loss_mode: int = LOSS_MAG, precision=FP32):

@@ -854,9 +854,36 @@ static FusedArgs fused_args(const cosim_plan *p, int precision, int S, int nchun
     return a;
 }
 
+// Device buffers of one call on the path of 64 loops or fewer: the plan's
+// own workspace, or views into caller-provided scratch memory.
+struct SmallWs {
+    double2 *I = nullptr;      // [S][n] currents
+    double2 *rpart = nullptr;  // [nchunk][S][NP] adjoint partial sums
+    double *lpart = nullptr;   // [nchunk][S] loss partial sums
+    double *gsys = nullptr;    // [S][n] per-system gradient terms
+    GJFactor fac;              // factor records
+};
+
+// Bytes of scratch memory that a call of S systems with nchunk P-chunks uses
+// on the path of 64 loops or fewer, each view aligned to 256 bytes.
+static size_t small_ws_bytes(const cosim_plan *p, size_t S, int nchunk, size_t *off) {
+    const size_t NP = (size_t)p->NP, n = (size_t)p->n;
+    const size_t sz[8] = {S * n * sizeof(double2),       S * nchunk * NP * sizeof(double2),
+                          S * nchunk * sizeof(double),   S * n * sizeof(double),
+                          S * NP * NP * sizeof(double2), S * NP * sizeof(int),
+                          S * NP * sizeof(double2),      S * sizeof(int)};
+    size_t at = 0;
+    for (int i = 0; i < 8; ++i) {
+        if (off) off[i] = at;
+        at += (sz[i] + 255) / 256 * 256;
+    }
+    return at;
+}
+
 static int loss_and_grad_impl(cosim_plan_t p, int B, int F, const double *C_d, const double *omega_d,
                        const double *T_d, int loss_mode, int precision, double *loss_d,
-                       double *grad_d, int32_t *status_d, void *stream, double2 *mu) {
+                       double *grad_d, int32_t *status_d, void *stream, double2 *mu,
+                       void *scratch = nullptr, size_t scratch_bytes = 0) {
     int rc = check_batch(p, B, F);
     if (rc) return rc;
     if (B == 0 || F == 0) return COSIM_OK;  // empty batch: nothing to do
@@ -871,10 +898,39 @@ static int loss_and_grad_impl(cosim_plan_t p, int B, int F, const double *C_d, c
     const int variant = p->variant[precision];
     int tpc = 1;
     const int nchunk = chunks_for(p, prec, S, variant, &tpc);
-    if ((rc = ensure_workspace(p, S, nchunk))) return rc;
+    SmallWs w;
+    if (scratch) {
+        // caller-provided memory: nothing is allocated, the plan's workspace is
+        // not touched, no phase timing
+        if (big_plan(p->NP))
+            return fail(COSIM_EUNSUPPORTED, "the scratch-memory call covers plans of at most %d "
+                                            "loops (this plan has %d)", kMaxLoops, p->n);
+        size_t off[8];
+        const size_t need = small_ws_bytes(p, S, nchunk, off);
+        if (need > scratch_bytes)
+            return fail(COSIM_EINVAL, "%zu systems of %d loops need %zu bytes of scratch memory; "
+                                      "the limit is %zu", S, p->n, need, scratch_bytes);
+        char *b = (char *)scratch;
+        w.I = (double2 *)(b + off[0]);
+        w.rpart = (double2 *)(b + off[1]);
+        w.lpart = (double *)(b + off[2]);
+        w.gsys = (double *)(b + off[3]);
+        w.fac.L = (double2 *)(b + off[4]);
+        w.fac.piv_row = (int *)(b + off[5]);
+        w.fac.piv_val = (double2 *)(b + off[6]);
+        w.fac.fmt = (int *)(b + off[7]);
+    } else {
+        if ((rc = ensure_workspace(p, S, nchunk))) return rc;
+        w.I = p->I_ws;
+        w.rpart = p->rpart;
+        w.lpart = p->lpart;
+        w.gsys = p->gsys;
+        w.fac = p->fac;
+    }
     hipStream_t st = (hipStream_t)stream;
     hipEvent_t *ev = nullptr;
-    if (p->timing_used < p->timing_cap) ev = &p->events[(size_t)p->timing_used++ * (COSIM_PHASES + 1)];
+    if (!scratch && p->timing_used < p->timing_cap)
+        ev = &p->events[(size_t)p->timing_used++ * (COSIM_PHASES + 1)];
     if (ev) HIP_TRY(hipEventRecord(ev[0], st));
     // Z is factorised once and the factorisation recorded; the forward solve and
     // the adjoint solve both replay the record.  With every R_k > 0 the
@@ -917,24 +973,27 @@ static int loss_and_grad_impl(cosim_plan_t p, int B, int F, const double *C_d, c
     }
     if (p->ldl_ok) {
         HIP_TRY(launch_ldl(p->NP, p->n, (int)S, F, p->M_d, p->R_d, C_d, omega_d, p->phi_d,
-                           p->fac, p->I_ws, status_d, st));
+                           w.fac, w.I, status_d, st));
         HIP_TRY(launch_solve_fallback(p->NP, p->n, (int)S, F, p->M_d, p->R_d, p->phi_d, C_d,
-                                      omega_d, p->I_ws, status_d, p->fac, st));
-        HIP_TRY(launch_replay_forward(p->NP, p->n, (int)S, F, p->fac, omega_d, p->I_ws, status_d,
+                                      omega_d, w.I, status_d, w.fac, st));
+        HIP_TRY(launch_replay_forward(p->NP, p->n, (int)S, F, w.fac, omega_d, w.I, status_d,
                                       st));
     } else {
         HIP_TRY(launch_solve_forward(p->NP, p->n, (int)S, F, p->M_d, p->R_d, p->phi_d, C_d,
-                                     omega_d, p->I_ws, status_d, p->fac, st));
+                                     omega_d, w.I, status_d, w.fac, st));
     }
     if (ev) HIP_TRY(hipEventRecord(ev[1], st));
-    const FusedArgs a = fused_args(p, precision, (int)S, nchunk, tpc, T_d, ratio ? p->bext_z : 0.0);
+    FusedArgs a = fused_args(p, precision, (int)S, nchunk, tpc, T_d, ratio ? p->bext_z : 0.0);
+    a.I = w.I;
+    a.rpart = w.rpart;
+    a.lpart = w.lpart;
     HIP_TRY(launch_fused(prec, p->NP, variant, loss_mode, grad, a, st));
     if (ev) HIP_TRY(hipEventRecord(ev[2], st));
     if (grad)
-        HIP_TRY(launch_replay_adjoint(p->NP, p->n, (int)S, F, p->fac, C_d, omega_d, p->I_ws,
-                                      p->rpart, nchunk, scale, p->gsys, mu, status_d, st));
+        HIP_TRY(launch_replay_adjoint(p->NP, p->n, (int)S, F, w.fac, C_d, omega_d, w.I,
+                                      w.rpart, nchunk, scale, w.gsys, mu, status_d, st));
     if (ev) HIP_TRY(hipEventRecord(ev[3], st));
-    HIP_TRY(launch_reduce(p->n, B, F, nchunk, grad ? p->gsys : nullptr, p->lpart, scale, grad_d,
+    HIP_TRY(launch_reduce(p->n, B, F, nchunk, grad ? w.gsys : nullptr, w.lpart, scale, grad_d,
                           loss_d, st));
     if (ev) HIP_TRY(hipEventRecord(ev[4], st));
     return COSIM_OK;
@@ -946,6 +1005,29 @@ int cosim_loss_and_grad(cosim_plan_t p, int B, int F, const double *C_d, const d
     return loss_and_grad_impl(p, B, F, C_d, omega_d, T_d, loss_mode, precision, loss_d, grad_d,
                               status_d, stream, nullptr);
 }
+
+}  // extern "C"
+
+int cosim::loss_and_grad_scratch(cosim_plan_t p, int B, int F, const double *C_d,
+                                 const double *omega_d, const double *T_d, int loss_mode,
+                                 int precision, double *loss_d, double *grad_d, int32_t *status_d,
+                                 void *stream, void *scratch, size_t scratch_bytes) {
+    if (!scratch) return fail(COSIM_EINVAL, "no scratch memory");
+    return loss_and_grad_impl(p, B, F, C_d, omega_d, T_d, loss_mode, precision, loss_d, grad_d,
+                              status_d, stream, nullptr, scratch, scratch_bytes);
+}
+
+int cosim::set_error(int code, const char *msg) { return fail(code, "%s", msg); }
+
+int cosim::plan_device(const cosim_plan *p, int *device) {
+    if (!p) return fail(COSIM_EINVAL, "null plan");
+    int rc = check_device(p);
+    if (rc) return rc;
+    *device = p->device;
+    return COSIM_OK;
+}
+
+extern "C" {
 
 int cosim_loss_and_grad_params(cosim_plan_t p, int B, int F, const double *C_d,
                                const double *omega_d, const double *T_d, int loss_mode,

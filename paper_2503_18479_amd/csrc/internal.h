@@ -366,6 +366,20 @@ hipError_t sp_rc(int B, int F, int n, const double *R, const double *C, const do
 hipError_t sp_rc_backward(int B, int F, int n, const double *R, const double *C, const double *omega,
                           double z0, const double2 *g, int ld, double *gC, hipStream_t st);
 
+// cosim_loss_and_grad with the call's device buffers (currents, factor
+// records, partial sums, per-system gradient terms) carved from `scratch`
+// (scratch_bytes long, 256-byte aligned) instead of the plan's workspace:
+// allocates nothing.  Plans of 64 loops or fewer; COSIM_EINVAL when the call
+// needs more than scratch_bytes.
+int loss_and_grad_scratch(cosim_plan_t p, int B, int F, const double *C_d, const double *omega_d,
+                          const double *T_d, int loss_mode, int precision, double *loss_d,
+                          double *grad_d, int32_t *status_d, void *stream, void *scratch,
+                          size_t scratch_bytes);
+// Sets the message cosim_last_error returns; returns code.
+int set_error(int code, const char *msg);
+// The plan's device, which must be the current one (else COSIM_EINVAL).
+int plan_device(const cosim_plan *p, int *device);
+
 }  // namespace cosim
 
 // Library-owned objects behind the opaque handles.

@@ -110,6 +110,11 @@ def test_hot_call_argument_errors(lib):
     assert lib.cosim_plan_destroy(None) == 0
     assert lib.cosim_geometry_destroy(None) == 0
     assert lib.cosim_last_error() != b""
+    # the allocation-free call: null plan, and the size of its per-device array
+    assert lib.cosim_loss_and_grad_noalloc(None, 1, 1, dummy, dummy, dummy, 0, 1, dummy, dummy,
+                                           dummy, None) == EINVAL
+    assert b"null plan" in lib.cosim_last_error()
+    assert lib.cosim_noalloc_scratch_bytes() == 64 << 20
 
 
 def test_tuning_argument_errors(lib):
