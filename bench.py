@@ -74,6 +74,9 @@ def parse():
     ap.add_argument("--profile-ragged", type=int, default=None,
                     help="only the ragged line (eager steps and graph replays), this many steps "
                          "each, for a profiler run")
+    ap.add_argument("--lines", default="single_loop,line_8x1,two_planes",
+                    help="further workload lines (comma list of single_loop, line_8x1, "
+                         "two_planes; empty: none)")
     ap.add_argument("--variant", type=int, default=None,
                     help="with --profile-steps: use this fused-kernel variant instead of tuning")
     return ap.parse_args()
@@ -106,7 +109,28 @@ def time_mode(plan, C, om, T, prec: str, steps: int, warmup: int, torch, tune: b
     phases = plan.timing_read()
     plan.timing(0)
     bad = int((st != 0).sum())
+    time_mode.last = (loss.cpu().numpy(), grad.cpu().numpy())
     return dt, phases, bad, tuned
+
+
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+
+def golden(name: str) -> dict:
+    """Stored FP64 oracle values (written by tests/golden/make_fullsize_golden.py)."""
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+def vs_oracle(loss, grad, ref: dict) -> dict:
+    """Loss (relative) and dL/dC (normwise relative) of the stored
+    configurations against the FP64 oracle's values."""
+    cfg = ref["configs"]
+    rl, rg = np.asarray(ref["loss"]), np.asarray(ref["grad"])
+    el = np.abs(np.asarray(loss)[cfg] - rl) / np.abs(rl)
+    eg = np.linalg.norm(np.asarray(grad)[cfg] - rg, axis=1) / np.linalg.norm(rg, axis=1)
+    return {"configs": len(cfg), "loss_rel_max": float(el.max()),
+            "grad_normwise_rel_max": float(eg.max())}
 
 
 def cpu_baseline(wl, n_configs: int):
@@ -120,7 +144,8 @@ def cpu_baseline(wl, n_configs: int):
     g = wl.geom
     t0 = time.perf_counter()
     G = O.field_matrix(g.verts, g.seg_off, wl.pts)
-    M = O.inductance_matrix_fast(g.verts, g.seg_off, g.wire_a)
+    M = (O.inductance_matrix_lattice(g.verts, g.seg_off, g.wire_a, g.nx, g.ny) if g.n > 1
+         else O.inductance_matrix(g.verts, g.seg_off, g.wire_a))
     Phi = O.flux(g.verts, g.seg_off, wl.bext_z)
     t_asm = time.perf_counter() - t0
     C = wl.C[:n_configs]
@@ -278,6 +303,48 @@ def sparam_line(steps: int, torch, batch: int = 4096) -> dict:
     return out
 
 
+def workload_line(wl, ref: dict, mixed: str, steps: int, warmup: int, cpu_configs: int,
+                  torch) -> dict:
+    """One workload of the path at its own shape: cosim_loss_and_grad per step
+    in the mixed precision and in FP64 (evaluations per second, phases), the
+    fused contraction's fraction of its precision's matrix-core peak, the
+    error against stored oracle values, and the oracle's own time on a sample
+    of the same workload."""
+    from paper_2503_18479_amd import Geometry, Plan
+    dev = torch.device("cuda:0")
+    g = wl.geom
+    plan = Plan(Geometry.from_workload(g), torch.tensor(wl.pts, device=dev), wl.bext_z,
+                precisions=[mixed, "fp64"])
+    C = torch.tensor(wl.C, device=dev)
+    om = torch.tensor(wl.omega, device=dev)
+    T = torch.tensor(wl.target, device=dev)
+    plan.reserve(wl.B, wl.F)
+    S = wl.B * wl.F
+    flops = 8.0 * wl.P * g.n * S
+    out = {"workload": wl.name, "loops": g.n, "points": wl.P, "freqs": wl.F, "batch": wl.B,
+           "systems": S, "modes": {}}
+    for m in (mixed, "fp64"):
+        dt, ph, bad, tuned = time_mode(plan, C, om, T, m, steps, warmup, torch)
+        fused = float(np.mean(ph[:, 1]))
+        ach = flops / (fused * 1e-3) / 1e12
+        out["modes"][m] = {
+            "evals_per_s": wl.B * steps / dt, "ms_per_step": 1e3 * dt / steps, "steps": steps,
+            "phase_ms": {name: float(np.mean(ph[:, i])) for i, name in enumerate(Plan.PHASES)},
+            "flagged_systems": bad, "variant": (tuned or {}).get("variant"),
+            "roofline": {"bound": "mfma", "kernel": "fused contraction", "achieved": ach,
+                         "peak": PEAK_TFLOPS[m], "unit": "TFLOP/s", "frac": ach / PEAK_TFLOPS[m],
+                         "flops_per_launch": flops, "avg_launch_ms": fused},
+            "vs_oracle": vs_oracle(*time_mode.last, ref)}
+        print(f"[bench] {wl.name} {m}: {out['modes'][m]['evals_per_s']:.0f} evals/s, "
+              f"{out['modes'][m]['ms_per_step']:.3f} ms/step, vs oracle "
+              f"{out['modes'][m]['vs_oracle']}", file=sys.stderr, flush=True)
+    out["mixed_vs_fp64"] = out["modes"][mixed]["evals_per_s"] / out["modes"]["fp64"]["evals_per_s"]
+    del plan
+    if cpu_configs > 0:
+        out["cpu_baseline"] = cpu_baseline(wl, min(cpu_configs, wl.B))
+    return out
+
+
 def reference_copy(torch, dev):
     """A device copy of known size (256 MiB read + 256 MiB written) that
     calibrates the HBM byte counters of a profiler run."""
@@ -342,6 +409,8 @@ def large_line(adam_steps: int, mixed: str, steps: int, torch) -> dict:
                   file=sys.stderr, flush=True)
     plan.set_refinement(False)
     err = rel_err(vals[mixed], vals["fp64"])
+    ref = golden("array_32x32_full.json")
+    oracle_err = {key: vs_oracle(v[0], v[1], ref) for key, v in vals.items()}
     adam = None
     if adam_steps > 0:
         C1 = C.clone()
@@ -359,6 +428,7 @@ def large_line(adam_steps: int, mixed: str, steps: int, torch) -> dict:
               flush=True)
     return {"workload": wl.name, "loops": n, "points": wl.P, "batch": wl.B, "freqs": wl.F,
             "setup_s": t_setup, "modes": modes, "mixed_vs_fp64_error": err,
+            "vs_oracle": oracle_err,
             "mixed_vs_fp64_speed": modes["fp64"]["ms_per_step"] / modes[mixed]["ms_per_step"],
             "refined_speedup": {m: modes[m]["ms_per_step"] / modes[m + "+refined"]["ms_per_step"]
                                 for m in (mixed, "fp64")},
@@ -453,6 +523,8 @@ def main():
             "flagged_systems": bad,
             "autotune": tuned,
         }
+        if wl.B == 4096 and wl.F == 21 and wl.P == 65536:
+            res[m]["vs_oracle"] = vs_oracle(*time_mode.last, golden("array_8x8_full.json"))
         print(f"[bench] {m}: {res[m]['evals_per_s']:.0f} evals/s, {res[m]['ms_per_step']:.2f} ms/step, "
               f"phases {res[m]['phase_ms']}", file=sys.stderr, flush=True)
 
@@ -533,6 +605,28 @@ def main():
     print(f"[bench] with R, L, w gradients: {1e3 * dtp:.2f} ms/step", file=sys.stderr, flush=True)
     del plan
     torch.cuda.empty_cache()
+    wanted = [x for x in args.lines.split(",") if x]
+    line["lines"] = {}
+    for name in wanted:
+        print(f"[bench] workload line {name}", file=sys.stderr, flush=True)
+        if name == "single_loop":
+            wl1 = W.config1_single_loop(batch=64, grid=32)
+            ref = golden("single_loop_full.json")
+        elif name == "line_8x1":
+            wl1 = W.config2_line8(batch=1024, grid=64)
+            ref = golden("line_8x1_full.json")
+        elif name == "two_planes":
+            wl1 = W.config3_array8x8(batch=4096, two_planes=True)
+            ref = golden("array_8x8_full.json")["two_planes"]
+        else:
+            raise SystemExit(f"unknown line {name}")
+        # the oracle's time beside each line; the two-plane array is the
+        # headline's array with twice the points (its oracle G alone takes
+        # minutes on the host), so its oracle time is the headline's
+        cpu = {"single_loop": 64, "line_8x1": 1024, "two_planes": 0}[name]
+        line["lines"][name] = workload_line(wl1, ref, args.mixed, args.steps, args.warmup,
+                                            cpu if args.cpu_configs > 0 else 0, torch)
+        torch.cuda.empty_cache()
     if args.ragged > 0:
         print(f"[bench] ragged configuration: {args.ragged} instances", file=sys.stderr, flush=True)
         line["ragged"] = ragged_line(args.ragged, args.mixed, 3, torch)

@@ -244,6 +244,48 @@ def inductance_matrix_fast(verts, seg_off, wire_a) -> np.ndarray:
     return M
 
 
+def inductance_matrix_lattice(verts, seg_off, wire_a, nx: int, ny: int) -> np.ndarray:
+    """M of an nx-by-ny lattice of identical loops (loop k = iy*nx + ix, the
+    same polygon translated, one wire radius), with the values of
+    ``inductance_matrix_fast``: the Neumann integral between two loops is
+    unchanged when both are translated together, so M[k, l] depends only on
+    the lattice offset of l from k.  Each distinct offset is evaluated once
+    on a two-loop geometry, the diagonal on a one-loop geometry; equal values
+    are reused, nothing else differs."""
+    n = nx * ny
+    so = np.asarray(seg_off)
+    wa = np.asarray(wire_a, dtype=np.float64)
+    if len(so) != n + 1:
+        raise ValueError("seg_off does not describe nx * ny loops")
+    if np.any(wa != wa[0]):
+        raise ValueError("a lattice needs one wire radius")
+
+    def loop(k):
+        return np.asarray(verts[so[k]:so[k + 1]], dtype=np.float64)
+
+    cache = {}
+    M = np.empty((n, n))
+    for k in range(n):
+        iyk, ixk = divmod(k, nx)
+        for l in range(n):
+            iyl, ixl = divmod(l, nx)
+            key = (ixl - ixk, iyl - iyk)
+            v = cache.get(key)
+            if v is None:
+                vk = loop(k)
+                if k == l:
+                    v = inductance_matrix_fast(vk, np.array([0, len(vk)], dtype=np.int32),
+                                               wa[k:k + 1])[0, 0]
+                else:
+                    vl = loop(l)
+                    two = np.concatenate([vk, vl])
+                    off = np.array([0, len(vk), len(vk) + len(vl)], dtype=np.int32)
+                    v = inductance_matrix_fast(two, off, np.array([wa[k], wa[l]]))[0, 1]
+                cache[key] = v
+            M[k, l] = v
+    return M
+
+
 def _axis_aligned_block(ak, bk, al, bl, a):
     du = bk - ak
     dv = bl - al

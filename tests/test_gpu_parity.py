@@ -284,38 +284,20 @@ def test_autograd_gradcheck(dev):
 
 # ----------------------------------------------------------------- full-size sampled parity
 
-def test_full_size_array8x8_sampled(dev):
-    """The 8x8 array at 65,536 points and 21 frequencies, in the launch
-    configuration the benchmark times (batch 4096): sampled configurations
-    against the oracle."""
+def test_full_size_array8x8_operators(dev):
+    """The 8x8 array at 65,536 points: M in full and G at sampled rows against
+    the oracle (loss and gradient at this size: tests/test_gpu_fullsize.py)."""
     from paper_2503_18479_amd import Geometry, Plan
-    wl = W.config3_array8x8(batch=4096)
+    wl = W.config3_array8x8(batch=1)
     g = wl.geom
     _say("[full] assembling 8x8 / 65536 points")
     plan = Plan(Geometry.from_workload(g), torch.tensor(wl.pts, device=dev), wl.bext_z)
-    C = torch.tensor(wl.C, device=dev)
-    om = torch.tensor(wl.omega, device=dev)
-    T = torch.tensor(wl.target, device=dev)
     rng = np.random.default_rng(11)
-    sample = np.sort(rng.choice(wl.B, 3, replace=False))
-    Gr = O.field_matrix(g.verts, g.seg_off, wl.pts)
-    Mr = O.inductance_matrix_fast(g.verts, g.seg_off, g.wire_a)
-    Phi = O.flux(g.verts, g.seg_off, wl.bext_z)
-    Gd = plan.G().cpu().numpy()
+    prow = np.sort(rng.choice(wl.P, 1024, replace=False))
+    Gr = O.field_matrix(g.verts, g.seg_off, wl.pts[prow])
+    Gd = plan.G()[torch.tensor(prow, device=dev)].cpu().numpy()
     assert _nrel(Gd, Gr) < 1e-12
-    assert _nrel(plan.M(), Mr) < 1e-12
-    Cs = wl.C[sample]
-    Lr = O.evaluate(Gr, Mr, g.R, Phi, Cs, wl.omega, wl.target)[2]
-    gr = O.grad_adjoint(Gr, Mr, g.R, Phi, Cs, wl.omega, wl.target)
-    for prec in (0, 1, 2):
-        _say(f"[full] precision {prec}")
-        loss, grad, st = plan.loss_and_grad(C, om, T, precision=prec)
-        torch.cuda.synchronize()
-        assert int(st.abs().sum()) == 0
-        el = np.abs(loss.cpu().numpy()[sample] - Lr) / Lr
-        eg = _nrel(grad.cpu().numpy()[sample], gr, axis=1)
-        _say(f"[full] precision {prec}: loss err {el.max():.2e} grad err {eg.max():.2e}")
-        assert el.max() < TOL[prec] and eg.max() < TOL[prec]
+    assert _nrel(plan.M(), O.inductance_matrix_fast(g.verts, g.seg_off, g.wire_a)) < 1e-12
 
 
 # ----------------------------------------------------------------- solver paths
@@ -594,19 +576,17 @@ def test_big_bad_input_flags(dev):
 
 def test_full_size_array32x32_sampled(dev):
     """The 32x32 array (1,024 loops) at 262,144 points: M in full, G at
-    sampled points and I for sampled configurations against the oracle; B_z
-    at sampled points against the oracle's; the fused loss against the mean
-    over all points of the FP64 materialised field; the FP64 gradient against
-    central differences of the FP64 loss; FP32 and BF16X3 against FP64."""
+    sampled points, I for sampled configurations and B_z at sampled points
+    against the oracle (loss and gradient at this size against stored oracle
+    values: tests/test_gpu_fullsize.py)."""
     from paper_2503_18479_amd import Geometry, Plan
     from array_oracle import oracle_M_array
     wl = W.config5_array32x32(batch=8)
     g = wl.geom
     _say("[c5] assembling 32x32 / 262144 points")
     pts = torch.tensor(wl.pts, device=dev)
-    plan = Plan(Geometry.from_workload(g), pts, wl.bext_z)
+    plan = Plan(Geometry.from_workload(g), pts, wl.bext_z, precisions=["fp64"])
     C = torch.tensor(wl.C, device=dev); om = torch.tensor(wl.omega, device=dev)
-    T = torch.tensor(wl.target, device=dev)
     _say("[c5] oracle M (1,024 loops)")
     Mr = oracle_M_array(g)
     assert _nrel(plan.M(), Mr) < 1e-12
@@ -627,27 +607,6 @@ def test_full_size_array32x32_sampled(dev):
     Bz = plan.field(I, 0)
     torch.cuda.synchronize()
     assert _nrel(Bz.cpu().numpy()[cs][:, :, prow], O.field(Gr, Ir)) < 1e-9
-    Lfield = ((Bz.abs() - T) ** 2).mean(dim=(1, 2)).cpu().numpy()
-    del Bz
-    res = {}
-    for prec in (0, 1, 2):
-        _say(f"[c5] loss_and_grad precision {prec}")
-        loss, grad, st = plan.loss_and_grad(C, om, T, precision=prec)
-        torch.cuda.synchronize()
-        assert int(st.abs().sum()) == 0
-        res[prec] = (loss.cpu().numpy(), grad.cpu().numpy())
-        assert np.max(np.abs(res[prec][0] - Lfield) / Lfield) < TOL[prec], prec
-    for prec in (1, 2):
-        assert np.max(_nrel(res[prec][1], res[0][1], axis=1)) < TOL[prec], prec
-    h = 1e-15
-    for k in (17, 600):
-        Cp = C.clone(); Cp[0, k] += h
-        Cm = C.clone(); Cm[0, k] -= h
-        lp = plan.loss_and_grad(Cp, om, T, precision=0, grad=False)[0][0].item()
-        lm = plan.loss_and_grad(Cm, om, T, precision=0, grad=False)[0][0].item()
-        fd = (lp - lm) / (2 * h)
-        _say(f"[c5] FD k={k}: {fd:.6e} vs {res[0][1][0, k]:.6e}")
-        assert abs(fd - res[0][1][0, k]) < 1e-4 * np.abs(res[0][1][0]).max()
 
 
 # ------------------------------------------------- ragged instances (one call, many plans)
