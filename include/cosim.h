@@ -129,11 +129,11 @@ int cosim_assemble(cosim_geom_t g, int P, const double *pts_d, double bext_z, vo
                    cosim_plan_t *out);
 /* The same, keeping only the copies of G that the precisions in the mask
  * `precisions` (bits 1 << COSIM_FP64 / FP32 / BF16X3, non-empty subset of
- * COSIM_PREC_ALL) need: 8, 4 and 8 bytes per entry of G.  Calls that read a
- * missing copy return COSIM_EINVAL: cosim_loss_and_grad and
- * cosim_plan_autotune in a precision outside the mask, and cosim_field,
- * cosim_field_backward and cosim_plan_copy_G without the FP64 bit.  For many
- * plans at once (independent instances). */
+ * COSIM_PREC_ALL) need: 16, 8 and 8 bytes per entry of G (each precision keeps
+ * G and its transpose).  Calls that read a missing copy return COSIM_EINVAL:
+ * cosim_loss_and_grad, cosim_field, cosim_field_backward and
+ * cosim_plan_autotune in a precision outside the mask, and cosim_plan_copy_G
+ * without the FP64 bit.  For many plans at once (independent instances). */
 int cosim_assemble_ex(cosim_geom_t g, int P, const double *pts_d, double bext_z, int precisions,
                       void *stream, cosim_plan_t *out);
 /* The same with G holding another Cartesian component of the field
@@ -148,6 +148,11 @@ int cosim_assemble_component(cosim_geom_t g, int P, const double *pts_d, double 
 int cosim_plan_destroy(cosim_plan_t p);
 /* Loops n, points P of a plan. */
 int cosim_plan_size(cosim_plan_t p, int *n_loops, int *n_points);
+/* Number of batches whose impedance matrices the plan's calls have
+ * factorised so far (cosim_solve, cosim_loss_and_grad and its variants, one
+ * per instance of cosim_loss_and_grad_many, cosim_field_backward with
+ * reuse = 0); a cosim_field_backward that replays a record adds none. */
+int cosim_plan_factorisations(cosim_plan_t p, long long *count);
 /* Pre-allocate the workspace for batches up to max_batch configurations of
  * max_freq frequencies, so that later calls with B*F <= max_batch*max_freq
  * allocate nothing.  Calls that need more grow the workspace themselves. */
@@ -205,8 +210,18 @@ int cosim_plan_set_refinement(cosim_plan_t p, int enable, int max_iter, double t
  * frequency f < F solves
  *     (diag(R) + j w_f M + diag(1/(j w_f C_b))) I_{b,f} = E - j w_f Phi
  * (E: the EMF of driven ports, zero unless cosim_plan_set_drive set some;
- * C = +INFINITY is a loop without a capacitor)
- * by Gauss-Jordan elimination with partial pivoting in FP64.
+ * C = +INFINITY is a loop without a capacitor) in FP64: up to 64 loops by a
+ * complex-symmetric LDL^T on FP64 matrix cores (every R_k > 0) with pivoted
+ * Gauss-Jordan elimination for systems with a small pivot, or pivoted
+ * Gauss-Jordan throughout (some R_k = 0); above 64 loops by a blocked LDL^T
+ * (or, with cosim_plan_set_refinement, its FP32 form refined in FP64) with
+ * pivoted LU for systems with a small pivot, or pivoted LU throughout.
+ * The factorisation is recorded in the plan's workspace, with the status of
+ * every system, for cosim_field_backward with reuse != 0; the record lasts
+ * until another call uses the workspace (cosim_loss_and_grad, _params,
+ * _many, cosim_plan_autotune, cosim_field_backward with reuse = 0,
+ * cosim_plan_set_drive, cosim_plan_set_refinement, or a larger cosim_solve).
+ * Grows the workspace (allocates) when B*F systems need more room.
  *   C_d      [B][n] double, device (farads)
  *   omega_d  [F] double, device (rad/s)
  *   I_d      [B][F][n] complex128, device (output, amperes)
@@ -215,23 +230,39 @@ int cosim_plan_set_refinement(cosim_plan_t p, int enable, int max_iter, double t
 int cosim_solve(cosim_plan_t p, int B, int F, const double *C_d, const double *omega_d,
                 double *I_d, int32_t *status_d, void *stream);
 
-/* Field superposition B_z[b][f][p] = sum_k G[p][k] I[b][f][k] (Eq. 7).
+/* Field superposition B_z[b][f][p] = sum_k G[p][k] I[b][f][k] (Eq. 7) on the
+ * matrix cores in `precision` (the plan must hold that copy of G), plus the
+ * incident field bext_z when add_incident != 0 (the total field of the
+ * forward problem, Sec. II; z-component plans only).
  *   I_d  [B][F][n] complex128, device
  *   Bz_d [B][F][P] complex128 (precision FP64) or complex64 (FP32, BF16X3),
- *        device, output.                                                      */
-int cosim_field(cosim_plan_t p, int B, int F, const double *I_d, int precision, void *Bz_d,
-                void *stream);
+ *        device, output.
+ * Allocates nothing.                                                          */
+int cosim_field(cosim_plan_t p, int B, int F, const double *I_d, int precision, int add_incident,
+                void *Bz_d, void *stream);
 
 /* Vector-Jacobian product of C -> B_z (Eq. 8-10 through the adjoint solve).
- *   gBz_d [B][F][P] complex128, device: upstream gradient in PyTorch's
- *         convention for a real loss L, gBz = dL/dRe(B) + j dL/dIm(B)
- *         (= 2 dL/d conj(B));
- *   gC_d  [B][n] double, device, output: dL/dC.
- * The contraction G^T conj(gBz) runs in FP64; the impedance is re-factorised
- * (Z is complex symmetric, so the same elimination serves Z^T). */
+ *   gBz_d  [B][F][P] complex128, device: upstream gradient in PyTorch's
+ *          convention for a real loss L, gBz = dL/dRe(B) + j dL/dIm(B)
+ *          (= 2 dL/d conj(B)); an added incident field does not change it;
+ *   precision  arithmetic of the contraction r = G^T conj(gBz) / 2 on the
+ *          matrix cores (the plan must hold that copy of G); the solve and
+ *          the gradient are FP64;
+ *   reuse  != 0: the adjoint solve Z^T mu = r replays the factor record of
+ *          the plan's last cosim_solve (Z is complex symmetric, so the
+ *          forward factorisation serves Z^T), which must be of the same B
+ *          and F and still intact (see cosim_solve), else COSIM_EINVAL;
+ *          C_d, omega_d and I_d must be that solve's.  0: Z is factorised
+ *          again (and any record is lost);
+ *   gC_d   [B][n] double, device, output: dL/dC;
+ *   status_d [B][F] int32, device, output: the system status (with reuse,
+ *          that of the recorded solve plus COSIM_SYS_NONFINITE if mu is not
+ *          finite).
+ * With reuse = 0 the workspace grows (allocates) when B*F systems need more
+ * room. */
 int cosim_field_backward(cosim_plan_t p, int B, int F, const double *C_d, const double *omega_d,
-                         const double *I_d, const double *gBz_d, double *gC_d,
-                         int32_t *status_d, void *stream);
+                         const double *I_d, const double *gBz_d, int precision, int reuse,
+                         double *gC_d, int32_t *status_d, void *stream);
 
 /* Fused forward + loss + gradient (the optimisation step's evaluation).
  *   T_d      [P] double, device: target field magnitudes (tesla)

@@ -25,14 +25,15 @@ SIGNATURES = {
     "cosim_assemble": (c_int, [c_void_p, c_int, c_void_p, c_double, c_void_p, P(c_void_p)]),
     "cosim_plan_destroy": (c_int, [c_void_p]),
     "cosim_plan_size": (c_int, [c_void_p, P(c_int), P(c_int)]),
+    "cosim_plan_factorisations": (c_int, [c_void_p, P(ctypes.c_longlong)]),
     "cosim_plan_reserve": (c_int, [c_void_p, c_int, c_int]),
     "cosim_plan_copy_G": (c_int, [c_void_p, c_void_p, c_void_p]),
     "cosim_plan_copy_M": (c_int, [c_void_p, c_void_p]),
     "cosim_plan_copy_phi": (c_int, [c_void_p, c_void_p]),
     "cosim_solve": (c_int, [c_void_p, c_int, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
-    "cosim_field": (c_int, [c_void_p, c_int, c_int, c_void_p, c_int, c_void_p, c_void_p]),
+    "cosim_field": (c_int, [c_void_p, c_int, c_int, c_void_p, c_int, c_int, c_void_p, c_void_p]),
     "cosim_field_backward": (c_int, [c_void_p, c_int, c_int, c_void_p, c_void_p, c_void_p, c_void_p,
-                                     c_void_p, c_void_p, c_void_p]),
+                                     c_int, c_int, c_void_p, c_void_p, c_void_p]),
     "cosim_loss_and_grad": (c_int, [c_void_p, c_int, c_int, c_void_p, c_void_p, c_void_p, c_int,
                                     c_int, c_void_p, c_void_p, c_void_p, c_void_p]),
     "cosim_loss_and_grad_noalloc": (c_int, [c_void_p, c_int, c_int, c_void_p, c_void_p, c_void_p,

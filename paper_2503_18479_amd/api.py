@@ -110,6 +110,10 @@ class Plan:
         self.P = P
         self.device = pts.device
         self.bext_z = float(bext_z)
+        # counts the calls that use the plan's workspace (and so end the
+        # factor record of the last solve): a record made at generation g is
+        # intact while the count is still g
+        self._gen = 0
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -127,15 +131,18 @@ class Plan:
         ph = np.ascontiguousarray(np.broadcast_to(np.asarray(phase, dtype=np.float64), (k,)))
         check(self._lib.cosim_plan_set_drive(self._h, k, _host(loops), _host(pw), _host(ph),
                                              float(z0), _stream()))
+        self._gen += 1
 
     def set_refinement(self, enable: bool = True, max_iter: int = 8, tol: float = 0.0) -> None:
         """FP32 factorisation with FP64 refinement above 64 loops
         (cosim_plan_set_refinement); tol 0 chooses it per precision."""
         check(self._lib.cosim_plan_set_refinement(self._h, int(bool(enable)), int(max_iter),
                                                   float(tol)))
+        self._gen += 1
 
     def reserve(self, max_batch: int, max_freq: int) -> None:
         check(self._lib.cosim_plan_reserve(self._h, int(max_batch), int(max_freq)))
+        self._gen += 1
 
     def G(self) -> torch.Tensor:
         out = torch.empty((self.P, self.n), dtype=torch.float64, device=self.device)
@@ -168,6 +175,7 @@ class Plan:
         prec = precision_code(precision)
         B, F = int(C.shape[0]), int(omega.shape[0])
         _, nv = self.variants(prec)
+        self._gen += 1
         ms = np.zeros(nv)
         check(self._lib.cosim_plan_autotune(
             self._h, B, F, _dev(C, torch.float64, (B, self.n), "C"),
@@ -191,7 +199,10 @@ class Plan:
 
     # -- path -----------------------------------------------------------------
     def solve(self, C: torch.Tensor, omega: torch.Tensor) -> Tuple[torch.Tensor, torch.Tensor]:
+        """Currents I [B][F][n] and status [B][F] (cosim_solve); the plan keeps
+        the factor record for field_backward(reuse=True)."""
         B, F = int(C.shape[0]), int(omega.shape[0])
+        self._gen += 1
         I = torch.empty((B, F, self.n), dtype=torch.complex128, device=self.device)
         st = torch.empty((B, F), dtype=torch.int32, device=self.device)
         check(self._lib.cosim_solve(self._h, B, F, _dev(C, torch.float64, (B, self.n), "C"),
@@ -200,16 +211,34 @@ class Plan:
                                     _stream()))
         return I, st
 
-    def field(self, I: torch.Tensor, precision=FP64) -> torch.Tensor:
+    def field(self, I: torch.Tensor, precision=FP64, add_incident: bool = False) -> torch.Tensor:
+        """B [B][F][P] = G I (+ bext_z with add_incident), complex128 in FP64,
+        complex64 otherwise (cosim_field)."""
         prec = precision_code(precision)
         B, F = int(I.shape[0]), int(I.shape[1])
         dt = torch.complex128 if prec == FP64 else torch.complex64
         Bz = torch.empty((B, F, self.P), dtype=dt, device=self.device)
         check(self._lib.cosim_field(self._h, B, F, _dev(I, torch.complex128, (B, F, self.n), "I"),
-                                    prec, ctypes.c_void_p(Bz.data_ptr()), _stream()))
+                                    prec, int(bool(add_incident)), ctypes.c_void_p(Bz.data_ptr()),
+                                    _stream()))
         return Bz
 
-    def field_backward(self, C, omega, I, gBz) -> Tuple[torch.Tensor, torch.Tensor]:
+    def factorisations(self) -> int:
+        """Batches whose Z this plan has factorised (cosim_plan_factorisations)."""
+        v = ctypes.c_longlong()
+        check(self._lib.cosim_plan_factorisations(self._h, ctypes.byref(v)))
+        return v.value
+
+    def record_generation(self) -> int:
+        """The current workspace generation (see field_backward)."""
+        return self._gen
+
+    def field_backward(self, C, omega, I, gBz, precision=FP64,
+                       reuse: bool = False) -> Tuple[torch.Tensor, torch.Tensor]:
+        """dL/dC [B][n] and status [B][F] from the upstream gradient gBz
+        (cosim_field_backward).  reuse=True replays the factor record of the
+        last solve (which must be of these C and omega, with no call that uses
+        the workspace since); False factorises again."""
         B, F = int(C.shape[0]), int(omega.shape[0])
         gC = torch.empty((B, self.n), dtype=torch.float64, device=self.device)
         st = torch.empty((B, F), dtype=torch.int32, device=self.device)
@@ -217,8 +246,11 @@ class Plan:
             self._h, B, F, _dev(C, torch.float64, (B, self.n), "C"),
             _dev(omega, torch.float64, (F,), "omega"),
             _dev(I, torch.complex128, (B, F, self.n), "I"),
-            _dev(gBz, torch.complex128, (B, F, self.P), "gBz"),
-            ctypes.c_void_p(gC.data_ptr()), ctypes.c_void_p(st.data_ptr()), _stream()))
+            _dev(gBz, torch.complex128, (B, F, self.P), "gBz"), precision_code(precision),
+            int(bool(reuse)), ctypes.c_void_p(gC.data_ptr()), ctypes.c_void_p(st.data_ptr()),
+            _stream()))
+        if not reuse:
+            self._gen += 1
         return gC, st
 
     def loss_and_grad(self, C: torch.Tensor, omega: torch.Tensor, T: torch.Tensor,
@@ -227,6 +259,7 @@ class Plan:
         """Per-configuration loss, dL/dC (or None) and per-system status."""
         prec = precision_code(precision)
         B, F = int(C.shape[0]), int(omega.shape[0])
+        self._gen += 1
         if out is None:
             loss = torch.empty((B,), dtype=torch.float64, device=self.device)
             g = torch.empty((B, self.n), dtype=torch.float64, device=self.device) if grad else None
@@ -264,6 +297,7 @@ class Plan:
         """cosim_loss_and_grad_params: (loss [B], dL/dC [B][n], dL/dR [B][n],
         dL/dL [B][n] of a series inductance per loop, dL/dw [B][F], status [B][F])."""
         B, F = int(C.shape[0]), int(omega.shape[0])
+        self._gen += 1
         dev = self.device
         loss = torch.empty((B,), dtype=torch.float64, device=dev)
         gC = torch.empty((B, self.n), dtype=torch.float64, device=dev)
@@ -337,6 +371,8 @@ def loss_and_grad_many(plans, Cs, omegas, Ts, loss_mode: int = LOSS_MAG, precisi
     lib = load_library()
     k = len(plans)
     prec = precision_code(precision)
+    for pl in plans:
+        pl._gen += 1
     Bs = [int(C.shape[0]) for C in Cs]
     Fs = [int(o.shape[0]) for o in omegas]
     if outs is None:
@@ -423,15 +459,21 @@ def clip_(x: torch.Tensor, lo: float, hi: float) -> torch.Tensor:
 class CosimField(torch.autograd.Function):
     """B_z = f(C) with the library's hand-written adjoint as backward.
 
-    forward: cosim_solve + cosim_field; backward: cosim_field_backward, which
-    re-factorises Z (complex symmetric) and returns the real dL/dC."""
+    forward: cosim_solve (which keeps the factor record in the plan) +
+    cosim_field on the matrix cores in `precision`, plus the incident field
+    with add_incident; backward: cosim_field_backward in the same precision,
+    replaying the forward factorisation (Z is complex symmetric, so it serves
+    Z^T) when no other call has used the plan's workspace since the forward,
+    else factorising again; it returns the real dL/dC."""
 
     @staticmethod
-    def forward(ctx, C, plan: Plan, omega, precision=FP64):
+    def forward(ctx, C, plan: Plan, omega, precision=FP64, add_incident=False):
         Cd = C.detach().contiguous()
         I, _ = plan.solve(Cd, omega)
-        Bz = plan.field(I, precision)
+        ctx.gen = plan.record_generation()
+        Bz = plan.field(I, precision, add_incident)
         ctx.plan = plan
+        ctx.precision = precision
         ctx.save_for_backward(Cd, omega, I)
         return Bz
 
@@ -439,12 +481,14 @@ class CosimField(torch.autograd.Function):
     def backward(ctx, gBz):
         C, omega, I = ctx.saved_tensors
         g = gBz.to(torch.complex128).contiguous()
-        gC, _ = ctx.plan.field_backward(C, omega, I, g)
-        return gC, None, None, None
+        reuse = ctx.plan.record_generation() == ctx.gen
+        gC, _ = ctx.plan.field_backward(C, omega, I, g, ctx.precision, reuse=reuse)
+        return gC, None, None, None, None
 
 
-def cosim_field(C: torch.Tensor, plan: Plan, omega: torch.Tensor, precision=FP64) -> torch.Tensor:
-    return CosimField.apply(C, plan, omega, precision_code(precision))
+def cosim_field(C: torch.Tensor, plan: Plan, omega: torch.Tensor, precision=FP64,
+                add_incident: bool = False) -> torch.Tensor:
+    return CosimField.apply(C, plan, omega, precision_code(precision), bool(add_incident))
 
 
 # ---------------------------------------------------------------------------

@@ -20,9 +20,8 @@ LIB = os.path.join(PKG, "libcosim.so")
 ARCH = os.environ.get("COSIM_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["abi.cpp", "assemble.hip", "solve.hip", "solve_big.hip", "fused.hip",
-           "contract_big.hip", "field.hip", "optim.hip", "sparam.hip", "params.hip",
-           "noalloc.hip"]
-# plain GEMMs of the path above 64 loops run on rocBLAS
+           "contract_mfma.hip", "optim.hip", "sparam.hip", "params.hip", "noalloc.hip"]
+# the S-parameter pipeline's complex GEMMs run on rocBLAS
 LIBS = ["-L/opt/rocm/lib", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
 
 COMMON = [

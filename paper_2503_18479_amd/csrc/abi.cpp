@@ -81,9 +81,6 @@ void dfree(T *&p) {
 }
 
 void plan_free_workspace(cosim_plan *p) {
-    dfree(p->bX);
-    dfree(p->bY);
-    dfree(p->bW);
     dfree(p->bWt);
     dfree(p->bZmax);
     dfree(p->bTinv);
@@ -92,12 +89,14 @@ void plan_free_workspace(cosim_plan *p) {
     dfree(p->rpart);
     dfree(p->lpart);
     dfree(p->gsys);
+    dfree(p->rec_status);
     dfree(p->fac.L);
     dfree(p->fac.piv_row);
     dfree(p->fac.piv_val);
     dfree(p->fac.fmt);
     p->cap_systems = 0;
     p->cap_parts = 0;
+    p->rec_S = 0;
 }
 
 // FP32 records with FP64 refinement when the plan asks for them and the
@@ -164,15 +163,6 @@ int ensure_workspace(cosim_plan *p, size_t systems, int chunks, size_t parts = 0
     plan_free_workspace(p);
     const size_t n = (size_t)p->n, NP = (size_t)p->NP;
     const bool big = big_plan(p->NP);
-    // more than 64 loops: GEMM operand planes (8 bytes per element covers FP64,
-    // FP32 and the two bf16 planes)
-    if (big && (hipMalloc(&p->bX, 2 * ns * NP * sizeof(double)) != hipSuccess ||
-                hipMalloc(&p->bY, 2 * ns * (size_t)p->P_pad * sizeof(double)) != hipSuccess ||
-                hipMalloc(&p->bW, 2 * ns * (size_t)p->P_pad * sizeof(double)) != hipSuccess)) {
-        plan_free_workspace(p);
-        (void)hipGetLastError();
-        return fail(COSIM_ENOMEM, "GEMM workspace for %zu systems failed", ns);
-    }
     if (big && p->ldl_ok &&
         (hipMalloc((void **)&p->bWt, ns * 64 * NP * sizeof(double2)) != hipSuccess ||
          hipMalloc((void **)&p->bZmax, ns * sizeof(double)) != hipSuccess ||
@@ -191,6 +181,7 @@ int ensure_workspace(cosim_plan *p, size_t systems, int chunks, size_t parts = 0
         hipMalloc((void **)&p->rpart, np_parts * NP * sizeof(double2)) != hipSuccess ||
         hipMalloc((void **)&p->lpart, np_parts * sizeof(double)) != hipSuccess ||
         hipMalloc((void **)&p->gsys, ns * n * sizeof(double)) != hipSuccess ||
+        hipMalloc((void **)&p->rec_status, ns * sizeof(int32_t)) != hipSuccess ||
         hipMalloc((void **)&p->fac.L, ns * NP * NP * sizeof(double2)) != hipSuccess ||
         hipMalloc((void **)&p->fac.piv_row, ns * NP * sizeof(int)) != hipSuccess ||
         hipMalloc((void **)&p->fac.piv_val, ns * NP * sizeof(double2)) != hipSuccess ||
@@ -238,10 +229,9 @@ int choose_chunks(const cosim_plan *p, Prec prec, size_t S, int variant) {
 // chunks of whole 64-row tiles, every chunk non-empty; *tiles_per_chunk out
 int chunks_for(const cosim_plan *p, Prec prec, size_t S, int variant, int *tiles_per_chunk = nullptr) {
     const int tiles = p->P_pad / kPTile;
-    if (big_plan(p->NP)) {  // adjoint GEMM chunks of kBigRows rows
-        const int tpc = kBigRows / kPTile;
-        if (tiles_per_chunk) *tiles_per_chunk = tpc;
-        return (tiles + tpc - 1) / tpc;
+    if (big_plan(p->NP)) {  // chunks of the matrix-core contraction kernel
+        if (tiles_per_chunk) *tiles_per_chunk = 0;
+        return mfma_shape(prec, p->NP, (int)S, p->P_pad, p->cus).nchunk;
     }
     const int want = choose_chunks(p, prec, S, variant);
     const int tpc = (tiles + want - 1) / want;
@@ -255,26 +245,25 @@ int plan_variants(const cosim_plan *p, Prec prec) {
     return big_plan(p->NP) ? 1 : fused_variant_count(prec);
 }
 
-// Operands of the GEMM path (more than 64 loops) for S systems.
-BigArgs big_args(const cosim_plan *p, Prec prec, int S, int nchunk, const double2 *I,
-                 const double *T) {
-    BigArgs a;
+// Operands of the matrix-core contraction kernel in `prec` for S systems.
+MfmaArgs mfma_args(const cosim_plan *p, Prec prec, int S, const MfmaShape &sh) {
+    MfmaArgs a;
+    switch (prec) {
+        case Prec::F64: a.G = p->G64; a.GT = p->GT64; break;
+        case Prec::F32: a.G = p->G32; a.GT = p->GT32; break;
+        case Prec::BF16X3:
+            a.G = p->Ghi; a.Glo = p->Glo; a.GT = p->GThi; a.GTlo = p->GTlo;
+            break;
+    }
     a.n = p->n;
     a.NP = p->NP;
     a.P = p->P;
     a.P_pad = p->P_pad;
     a.S = S;
-    a.nchunk = nchunk;
-    a.rows = kBigRows;
-    a.G = prec == Prec::F64 ? (const void *)p->G64 : (const void *)p->G32;
-    a.G3 = p->G3;
-    a.GA3 = p->GA3;
-    a.I = I;
-    a.T = T;
-    a.X = p->bX;
-    a.Y = p->bY;
-    a.W = p->bW;
-    a.R = p->rpart;
+    a.rows_per_chunk = sh.rows_per_chunk;
+    a.nchunk = sh.nchunk;
+    a.nsb = sh.nsb;
+    a.rpart = p->rpart;
     a.lpart = p->lpart;
     return a;
 }
@@ -512,11 +501,9 @@ int cosim_assemble_component(cosim_geom_t g, int P, const double *pts_d, double 
     p->n = g->n;
     p->NP = padded_loops(g->n);
     p->P = P;
-    // rows of G padded with zeros: whole 64-row tiles of the fused kernels, or,
-    // above 64 loops, whole P-chunks of the adjoint GEMMs (no shorter last
-    // chunk, so each product is one strided-batched call)
-    const int prow = big_plan(p->NP) ? kBigRows : kPTile;
-    p->P_pad = (P + prow - 1) / prow * prow;
+    // rows of G padded with zeros to whole 64-row tiles of the fused kernels
+    // (and whole 32-point sub-tiles of the matrix-core contraction kernel)
+    p->P_pad = (P + kPTile - 1) / kPTile * kPTile;
     p->bext_z = bext_z;
     p->component = component;
     p->phi_h.resize(g->n);
@@ -548,17 +535,17 @@ int cosim_assemble_component(cosim_geom_t g, int P, const double *pts_d, double 
         return cleanup(fail(COSIM_EDEVICE, "hipGetDevice failed"));
     const size_t gsz = (size_t)p->P_pad * p->NP;
     const size_t n = (size_t)g->n;
-    if ((want64 && hipMalloc((void **)&p->G64, gsz * sizeof(double)) != hipSuccess) ||
-        (want32 && hipMalloc((void **)&p->G32, gsz * sizeof(float)) != hipSuccess) ||
-        (want16 && !big_plan(p->NP) &&
-         (hipMalloc((void **)&p->Ghi, gsz * sizeof(uint16_t)) != hipSuccess ||
-          hipMalloc((void **)&p->Glo, gsz * sizeof(uint16_t)) != hipSuccess)) ||
-        (want16 && !big_plan(p->NP) &&
-         (hipMalloc((void **)&p->GThi, gsz * sizeof(uint16_t)) != hipSuccess ||
-          hipMalloc((void **)&p->GTlo, gsz * sizeof(uint16_t)) != hipSuccess)) ||
-        (want16 && big_plan(p->NP) &&
-         (hipMalloc((void **)&p->G3, 3 * gsz * sizeof(uint16_t)) != hipSuccess ||
-          hipMalloc((void **)&p->GA3, 3 * gsz * sizeof(uint16_t)) != hipSuccess)) ||
+    // every precision keeps G row-major and transposed: the fused kernels read
+    // the bf16 transposed copy, the matrix-core contraction kernel every
+    // precision's (the adjoint's operands are runs of points of one loop)
+    if ((want64 && (hipMalloc((void **)&p->G64, gsz * sizeof(double)) != hipSuccess ||
+                    hipMalloc((void **)&p->GT64, gsz * sizeof(double)) != hipSuccess)) ||
+        (want32 && (hipMalloc((void **)&p->G32, gsz * sizeof(float)) != hipSuccess ||
+                    hipMalloc((void **)&p->GT32, gsz * sizeof(float)) != hipSuccess)) ||
+        (want16 && (hipMalloc((void **)&p->Ghi, gsz * sizeof(uint16_t)) != hipSuccess ||
+                    hipMalloc((void **)&p->Glo, gsz * sizeof(uint16_t)) != hipSuccess ||
+                    hipMalloc((void **)&p->GThi, gsz * sizeof(uint16_t)) != hipSuccess ||
+                    hipMalloc((void **)&p->GTlo, gsz * sizeof(uint16_t)) != hipSuccess)) ||
         hipMalloc((void **)&p->M_d, n * n * sizeof(double)) != hipSuccess ||
         hipMalloc((void **)&p->phi_d, 3 * n * sizeof(double)) != hipSuccess ||
         hipMalloc((void **)&p->R_d, n * sizeof(double)) != hipSuccess ||
@@ -579,13 +566,12 @@ int cosim_assemble_component(cosim_geom_t g, int P, const double *pts_d, double 
     ASM_TRY(hipMemcpyAsync(wa_d, g->wire_a.data(), n * sizeof(double), hipMemcpyHostToDevice, st));
     ASM_TRY(hipMemcpyAsync(p->R_d, g->R.data(), n * sizeof(double), hipMemcpyHostToDevice, st));
     ASM_TRY(hipMemcpyAsync(p->phi_d, p->exc_h.data(), 3 * n * sizeof(double), hipMemcpyHostToDevice, st));
-    ASM_TRY(launch_assemble_G(g->n, p->NP, P, p->P_pad, component, seg_d, verts_d, pts_d, p->G64, p->G32,
-                              p->Ghi, p->Glo, p->GThi, p->GTlo, p->G3, p->GA3, st));
+    ASM_TRY(launch_assemble_G(g->n, p->NP, P, p->P_pad, component, seg_d, verts_d, pts_d, p->G64,
+                              p->G32, p->Ghi, p->Glo, p->GT64, p->GT32, p->GThi, p->GTlo, st));
     ASM_TRY(launch_assemble_M(g->n, seg_d, verts_d, wa_d, make_gl_rule(), p->M_d, st));
     p->M_h.resize(n * n);
     ASM_TRY(hipMemcpyAsync(p->M_h.data(), p->M_d, n * n * sizeof(double), hipMemcpyDeviceToHost, st));
     ASM_TRY(hipStreamSynchronize(st));
-    if (big_plan(p->NP)) ASM_TRY(big_blas_create(&p->blas));
 #undef ASM_TRY
     cleanup(COSIM_OK);
     *out = p;
@@ -597,13 +583,13 @@ int cosim_plan_destroy(cosim_plan_t p) {
     for (hipEvent_t e : p->events) (void)hipEventDestroy(e);
     p->events.clear();
     dfree(p->G64);
+    dfree(p->GT64);
     dfree(p->G32);
+    dfree(p->GT32);
     dfree(p->Ghi);
     dfree(p->Glo);
     dfree(p->GThi);
     dfree(p->GTlo);
-    dfree(p->G3);
-    dfree(p->GA3);
     dfree(p->M_d);
     dfree(p->phi_d);
     dfree(p->R_d);
@@ -614,9 +600,14 @@ int cosim_plan_destroy(cosim_plan_t p) {
     dfree(p->mu_ws);
     dfree(p->gpar_ws);
     p->par_cap = 0;
-    big_blas_destroy(p->blas);
-    p->blas = nullptr;
     delete p;
+    return COSIM_OK;
+}
+
+int cosim_plan_factorisations(cosim_plan_t p, long long *count) {
+    if (!p) return fail(COSIM_EINVAL, "null plan");
+    if (!count) return fail(COSIM_EINVAL, "count is null");
+    *count = p->factorisations;
     return COSIM_OK;
 }
 
@@ -637,8 +628,12 @@ int cosim_plan_reserve(cosim_plan_t p, int max_batch, int max_freq) {
     size_t parts = S;
     for (int pr = COSIM_FP64; pr <= COSIM_BF16X3; ++pr)
         for (int v = 0; v < plan_variants(p, (Prec)pr); ++v) {
-            if (big_plan(p->NP)) {
-                parts = std::max(parts, S * (size_t)chunks_for(p, (Prec)pr, S, v));
+            if (big_plan(p->NP)) {  // a smaller batch may split the points further
+                const size_t ns = (size_t)mfma_systems_per_block((Prec)pr);
+                for (size_t sb = 1; sb <= (S + ns - 1) / ns; ++sb) {
+                    const size_t Sb = std::min(S, sb * ns);
+                    parts = std::max(parts, Sb * (size_t)chunks_for(p, (Prec)pr, Sb, v));
+                }
                 continue;
             }
             const size_t per_block = (size_t)fused_systems_per_block((Prec)pr, p->NP, v);
@@ -715,6 +710,7 @@ int cosim_plan_set_drive(cosim_plan_t p, int nport, const int32_t *loop, const d
     p->R_h = std::move(R);
     p->exc_h = std::move(exc);
     p->n_drive = nport;
+    p->rec_S = 0;  // a factor record of the old circuit no longer applies
     const bool was = p->ldl_ok;
     p->ldl_ok = true;
     for (int k = 0; k < n; ++k) p->ldl_ok = p->ldl_ok && p->R_h[k] > 0.0;
@@ -742,6 +738,15 @@ int cosim_plan_set_refinement(cosim_plan_t p, int enable, int max_iter, double t
     return COSIM_OK;
 }
 
+// Partial-sum slots that cosim_field_backward needs for S systems in any
+// precision (chunks of the matrix-core kernel times S).
+static size_t vjp_parts(const cosim_plan *p, size_t S) {
+    size_t parts = S;
+    for (int pr = COSIM_FP64; pr <= COSIM_BF16X3; ++pr)
+        parts = std::max(parts, S * (size_t)mfma_shape((Prec)pr, p->NP, (int)S, p->P_pad, p->cus).nchunk);
+    return parts;
+}
+
 int cosim_solve(cosim_plan_t p, int B, int F, const double *C_d, const double *omega_d,
                 double *I_d, int32_t *status_d, void *stream) {
     int rc = check_batch(p, B, F);
@@ -750,80 +755,121 @@ int cosim_solve(cosim_plan_t p, int B, int F, const double *C_d, const double *o
     if (!C_d || !omega_d || !I_d || !status_d) return fail(COSIM_EINVAL, "null device pointer");
     if ((rc = check_device(p))) return rc;
     const int S = B * F;
+    // room for the record and for a later cosim_field_backward that replays it
+    if ((rc = ensure_workspace(p, (size_t)S, 1, vjp_parts(p, (size_t)S)))) return rc;
+    p->rec_S = 0;
+    p->factorisations++;
+    hipStream_t st = (hipStream_t)stream;
+    double2 *I = (double2 *)I_d;
     if (big_plan(p->NP)) {
-        if ((rc = ensure_workspace(p, (size_t)S, 1))) return rc;
-        hipStream_t st = (hipStream_t)stream;
         const BigFactor bf = big_factor_args(p);
         const BigRefine rf = big_refine_args(p, COSIM_FP64);
         HIP_TRY(big_factor(bf, rf, p->NP, p->n, S, F, p->M_d, p->R_d, C_d, omega_d, p->fac.L,
                            p->fac.piv_row, status_d, st));
         HIP_TRY(big_solve(bf, rf, p->NP, p->n, S, F, p->M_d, p->R_d, p->phi_d, C_d, omega_d,
-                          p->fac.L, p->fac.piv_row, (double2 *)I_d, kRhsExcitation, nullptr, 0,
-                          0.0, nullptr, status_d, st));
-        return COSIM_OK;
+                          p->fac.L, p->fac.piv_row, I, kRhsExcitation, nullptr, 0, 0.0, nullptr,
+                          status_d, st));
+    } else if (p->ldl_ok) {
+        HIP_TRY(launch_ldl(p->NP, p->n, S, F, p->M_d, p->R_d, C_d, omega_d, p->phi_d, p->fac, I,
+                           status_d, st));
+        HIP_TRY(launch_solve_fallback(p->NP, p->n, S, F, p->M_d, p->R_d, p->phi_d, C_d, omega_d,
+                                      I, status_d, p->fac, st));
+        HIP_TRY(launch_replay_forward(p->NP, p->n, S, F, p->fac, omega_d, I, status_d, st));
+    } else {
+        HIP_TRY(launch_solve_forward(p->NP, p->n, S, F, p->M_d, p->R_d, p->phi_d, C_d, omega_d,
+                                     I, status_d, p->fac, st));
     }
-    HIP_TRY(launch_solve_forward(p->NP, p->n, S, F, p->M_d, p->R_d, p->phi_d, C_d, omega_d,
-                                 (double2 *)I_d, status_d, GJFactor{}, (hipStream_t)stream));
+    // the forward status travels with the record: the adjoint replay starts from it
+    HIP_TRY(hipMemcpyAsync(p->rec_status, status_d, (size_t)S * sizeof(int32_t),
+                           hipMemcpyDeviceToDevice, st));
+    p->rec_B = B;
+    p->rec_F = F;
+    p->rec_S = (size_t)S;
     return COSIM_OK;
 }
 
-int cosim_field(cosim_plan_t p, int B, int F, const double *I_d, int precision, void *Bz_d,
-                void *stream) {
+int cosim_field(cosim_plan_t p, int B, int F, const double *I_d, int precision, int add_incident,
+                void *Bz_d, void *stream) {
     int rc = check_batch(p, B, F);
     if (rc) return rc;
     if (B == 0 || F == 0) return COSIM_OK;  // empty batch: nothing to do
     if ((rc = check_prec(precision))) return rc;
-    if ((rc = check_assembled(p, COSIM_FP64))) return rc;  // every precision reads the FP64 copy
+    if ((rc = check_assembled(p, precision))) return rc;
+    if (add_incident && p->component != 2)
+        return fail(COSIM_EINVAL, "the uniform incident field has no x or y part (this plan holds "
+                                  "component %d)", p->component);
     if (!I_d || !Bz_d) return fail(COSIM_EINVAL, "null device pointer");
     if ((rc = check_device(p))) return rc;
     const int S = B * F;
-    const size_t esz = precision == COSIM_FP64 ? sizeof(double2) : sizeof(float2);
-    // grid.y is limited to 65535 systems per launch
-    for (int s0 = 0; s0 < S; s0 += 65535) {
-        const int ns = std::min(65535, S - s0);
-        HIP_TRY(launch_field((Prec)precision, p->NP, p->P, ns, p->n, p->G64,
-                             (const double2 *)I_d + (size_t)s0 * p->n,
-                             (char *)Bz_d + (size_t)s0 * p->P * esz, (hipStream_t)stream));
-    }
+    const Prec prec = (Prec)precision;
+    const MfmaShape sh = mfma_shape(prec, p->NP, S, p->P_pad, p->cus);
+    MfmaArgs a = mfma_args(p, prec, S, sh);
+    a.I = (const double2 *)I_d;
+    a.Bout = Bz_d;
+    a.inc = add_incident ? p->bext_z : 0.0;
+    HIP_TRY(launch_mfma(prec, kMfmaField, 0, a, sh.waves, (hipStream_t)stream));
     return COSIM_OK;
 }
 
 int cosim_field_backward(cosim_plan_t p, int B, int F, const double *C_d, const double *omega_d,
-                         const double *I_d, const double *gBz_d, double *gC_d,
-                         int32_t *status_d, void *stream) {
+                         const double *I_d, const double *gBz_d, int precision, int reuse,
+                         double *gC_d, int32_t *status_d, void *stream) {
     int rc = check_batch(p, B, F);
     if (rc) return rc;
     if (B == 0 || F == 0) return COSIM_OK;  // empty batch: nothing to do
-    if ((rc = check_assembled(p, COSIM_FP64))) return rc;
+    if ((rc = check_prec(precision))) return rc;
+    if ((rc = check_assembled(p, precision))) return rc;
     if (!C_d || !omega_d || !I_d || !gBz_d || !gC_d || !status_d)
         return fail(COSIM_EINVAL, "null device pointer");
-    if ((rc = check_device(p))) return rc;
     const size_t S = (size_t)B * F;
+    if (reuse && !(p->rec_S == S && p->rec_B == B && p->rec_F == F))
+        return fail(COSIM_EINVAL, "no factor record of a %d x %d cosim_solve to reuse (another "
+                                  "call has used the plan's workspace since, or the shape "
+                                  "differs)", B, F);
+    if ((rc = check_device(p))) return rc;
     hipStream_t st = (hipStream_t)stream;
-    if (big_plan(p->NP)) {
-        // G^T conj(gBz) as FP64 GEMMs over P-chunks, then the pivoted LU solve
-        const int nchunk = chunks_for(p, Prec::F64, S, 0);
-        if ((rc = ensure_workspace(p, S, nchunk))) return rc;
-        HIP_TRY(launch_pack_w64(p->P, p->P_pad, (int)S, (const double2 *)gBz_d, (double *)p->bW, st));
-        BigArgs a = big_args(p, Prec::F64, (int)S, nchunk, nullptr, nullptr);
-        HIP_TRY(big_adjoint(p->blas, Prec::F64, a, st));
+    const Prec prec = (Prec)precision;
+    const MfmaShape sh = mfma_shape(prec, p->NP, (int)S, p->P_pad, p->cus);
+    if (!reuse) {
+        if ((rc = ensure_workspace(p, S, sh.nchunk))) return rc;
+        p->rec_S = 0;
+        p->factorisations++;
+    } else if (S * (size_t)sh.nchunk > p->cap_parts) {
+        return fail(COSIM_EINVAL, "the workspace lacks room for the partial sums");  // not reached
+    }
+    // r = G^T gBz per chunk of points; gBz = 2 dL/d conj(B), so conj(w) = conj(gBz) / 2
+    MfmaArgs a = mfma_args(p, prec, (int)S, sh);
+    a.gB = (const double2 *)gBz_d;
+    HIP_TRY(launch_mfma(prec, kMfmaVjp, 0, a, sh.waves, st));
+    double2 *I = (double2 *)I_d;  // read only by the adjoint solves
+    if (reuse) {
+        // the forward status is where the replay starts
+        HIP_TRY(hipMemcpyAsync(status_d, p->rec_status, S * sizeof(int32_t),
+                               hipMemcpyDeviceToDevice, st));
+        if (big_plan(p->NP)) {
+            const BigFactor bf = big_factor_args(p);
+            const BigRefine rf = big_refine_args(p, COSIM_FP64);
+            HIP_TRY(big_solve(bf, rf, p->NP, p->n, (int)S, F, p->M_d, p->R_d, p->phi_d, C_d,
+                              omega_d, p->fac.L, p->fac.piv_row, I, kRhsPairs, p->rpart,
+                              sh.nchunk, 0.5, p->gsys, status_d, st));
+        } else {
+            HIP_TRY(launch_replay_adjoint(p->NP, p->n, (int)S, F, p->fac, C_d, omega_d, I,
+                                          p->rpart, sh.nchunk, 0.5, p->gsys, nullptr, status_d,
+                                          st));
+        }
+    } else if (big_plan(p->NP)) {
         const BigFactor bf = big_factor_args(p);
         const BigRefine rf = big_refine_args(p, COSIM_FP64);
         HIP_TRY(big_factor(bf, rf, p->NP, p->n, (int)S, F, p->M_d, p->R_d, C_d, omega_d,
                            p->fac.L, p->fac.piv_row, status_d, st));
         HIP_TRY(big_solve(bf, rf, p->NP, p->n, (int)S, F, p->M_d, p->R_d, p->phi_d, C_d, omega_d,
-                          p->fac.L, p->fac.piv_row, (double2 *)I_d, kRhsPlanarF64, p->rpart,
-                          nchunk, 0.5, p->gsys, status_d, st));
-        HIP_TRY(launch_reduce(p->n, B, F, 0, p->gsys, nullptr, 0.0, gC_d, nullptr, st));
-        return COSIM_OK;
+                          p->fac.L, p->fac.piv_row, I, kRhsPairs, p->rpart, sh.nchunk, 0.5,
+                          p->gsys, status_d, st));
+    } else {
+        HIP_TRY(launch_solve_adjoint(p->NP, p->n, (int)S, F, p->M_d, p->R_d, C_d, omega_d, I,
+                                     p->rpart, sh.nchunk, 0.5, p->gsys, nullptr, status_d, false,
+                                     st));
     }
-    if ((rc = ensure_workspace(p, S, 1))) return rc;
-    HIP_TRY(launch_field_backward_contract(p->NP, p->P, (int)S, p->n, p->G64,
-                                           (const double2 *)gBz_d, p->rpart, st));
-    // gBz = 2 dL/d conj(B), so conj(w) = conj(gBz)/2
-    HIP_TRY(launch_solve_adjoint(p->NP, p->n, (int)S, F, p->M_d, p->R_d, C_d, omega_d,
-                                 (const double2 *)I_d, p->rpart, 1, 0.5, p->gsys, nullptr, status_d,
-                                 false, st));
     HIP_TRY(launch_reduce(p->n, B, F, 0, p->gsys, nullptr, 0.0, gC_d, nullptr, st));
     return COSIM_OK;
 }
@@ -921,12 +967,14 @@ static int loss_and_grad_impl(cosim_plan_t p, int B, int F, const double *C_d, c
         w.fac.fmt = (int *)(b + off[7]);
     } else {
         if ((rc = ensure_workspace(p, S, nchunk))) return rc;
+        p->rec_S = 0;  // the factor record of a cosim_solve is overwritten
         w.I = p->I_ws;
         w.rpart = p->rpart;
         w.lpart = p->lpart;
         w.gsys = p->gsys;
         w.fac = p->fac;
     }
+    p->factorisations++;
     hipStream_t st = (hipStream_t)stream;
     hipEvent_t *ev = nullptr;
     if (!scratch && p->timing_used < p->timing_cap)
@@ -956,14 +1004,16 @@ static int loss_and_grad_impl(cosim_plan_t p, int B, int F, const double *C_d, c
                           p->fac.L, p->fac.piv_row, p->I_ws, kRhsExcitation, nullptr, 0, 0.0,
                           nullptr, status_d, st));
         if (ev) HIP_TRY(hipEventRecord(ev[1], st));
-        BigArgs a = big_args(p, prec, (int)S, nchunk, p->I_ws, T_d);
+        const MfmaShape sh = mfma_shape(prec, p->NP, (int)S, p->P_pad, p->cus);
+        MfmaArgs a = mfma_args(p, prec, (int)S, sh);
+        a.I = p->I_ws;
+        a.T = T_d;
         a.inc = ratio ? p->bext_z : 0.0;
-        HIP_TRY(big_contract(p->blas, prec, loss_mode, grad, a, st));
+        HIP_TRY(launch_mfma(prec, grad ? kMfmaLossGrad : kMfmaLoss, loss_mode, a, sh.waves, st));
         if (ev) HIP_TRY(hipEventRecord(ev[2], st));
         if (grad)
             HIP_TRY(big_solve(bf, rf, p->NP, p->n, (int)S, F, p->M_d, p->R_d, p->phi_d, C_d,
-                              omega_d, p->fac.L, p->fac.piv_row, p->I_ws,
-                              prec == Prec::F64 ? kRhsPlanarF64 : kRhsPlanarF32, p->rpart,
+                              omega_d, p->fac.L, p->fac.piv_row, p->I_ws, kRhsPairs, p->rpart,
                               nchunk, scale, p->gsys, status_d, st, mu));
         if (ev) HIP_TRY(hipEventRecord(ev[3], st));
         HIP_TRY(launch_reduce(p->n, B, F, nchunk, grad ? p->gsys : nullptr, p->lpart, scale,
@@ -1152,6 +1202,7 @@ static int enqueue_small_group(const ManyCall &mc, const std::vector<int> &g, in
     for (size_t m = 0; m < g.size(); ++m) {
         const int i = g[m];
         cosim_plan *p = plans[i];
+        p->factorisations++;
         double sc = 1.0 / ((double)F[i] * (double)p->P);
         if (ratio) sc /= p->bext_z * p->bext_z;
         SmallInst &e = sg.in[m];
@@ -1281,6 +1332,7 @@ static int enqueue_big_group(const ManyCall &mc, const std::vector<int> &g, int 
         scale[m] = 1.0 / ((double)F[i] * (double)p->P);
         Teff[m] = T_d[i];
         if (ratio) scale[m] /= p->bext_z * p->bext_z;
+        p->factorisations++;
         GroupInst &e = ga.in[m];
         e.M = p->M_d;
         e.R = p->R_d;
@@ -1324,7 +1376,11 @@ static int enqueue_big_group(const ManyCall &mc, const std::vector<int> &g, int 
         cosim_plan *p = plans[i];
         hipStream_t cs = pool->streams[(k + 1 + m) % ns];
         hipEvent_t ev_c = pool->extra[next_ev++];
-        BigArgs a = big_args(p, prec, B[i] * F[i], chunks[i], p->I_ws, Teff[m]);
+        const int Si = B[i] * F[i];
+        const MfmaShape sh = mfma_shape(prec, NP, Si, p->P_pad, p->cus);
+        MfmaArgs a = mfma_args(p, prec, Si, sh);
+        a.I = p->I_ws;
+        a.T = Teff[m];
         bool ok = hipStreamWaitEvent(cs, ev_fwd, 0) == hipSuccess;
         if (ok && ratio) {
             ok = launch_scale((size_t)p->P, std::fabs(p->bext_z), T_d[i], p->T_ratio, cs) ==
@@ -1332,14 +1388,15 @@ static int enqueue_big_group(const ManyCall &mc, const std::vector<int> &g, int 
             a.T = p->T_ratio;
             a.inc = p->bext_z;
         }
-        ok = ok && big_contract(p->blas, prec, loss_mode, grad, a, cs) == hipSuccess &&
+        ok = ok &&
+             launch_mfma(prec, grad ? kMfmaLossGrad : kMfmaLoss, loss_mode, a, sh.waves, cs) ==
+                 hipSuccess &&
              hipEventRecord(ev_c, cs) == hipSuccess && hipStreamWaitEvent(gs, ev_c, 0) == hipSuccess;
         if (!ok) first_rc = fail_instance(fail(COSIM_EDEVICE, "contraction launch failed"), i);
     }
     if (first_rc != COSIM_OK) return first_rc;
     if (grad &&
-        big_group_solve(ga, NP, Sg, A, piv, prec == Prec::F64 ? kRhsPlanarF64 : kRhsPlanarF32,
-                        gs) != hipSuccess) {
+        big_group_solve(ga, NP, Sg, A, piv, kRhsPairs, gs) != hipSuccess) {
         return fail(COSIM_EDEVICE, "grouped adjoint launch failed");
     }
     ReduceGroup rg{};
@@ -1383,6 +1440,7 @@ int cosim_loss_and_grad_many(int count, const cosim_plan_t *plans, const int *B,
         if (!C_d[i] || !omega_d[i] || !T_d[i] || !loss_d[i] || !status_d[i])
             return fail(COSIM_EINVAL, "instance %d: null device pointer", i);
     }
+    for (int i = 0; i < count; ++i) plans[i]->rec_S = 0;  // workspaces are overwritten
     {  // a plan's workspace serves one instance at a time
         std::vector<cosim_plan_t> sorted(plans, plans + count);
         std::sort(sorted.begin(), sorted.end());
@@ -1673,7 +1731,7 @@ struct cosim_sp {
         dfree(w.Y);
         dfree(w.Rp);
         dfree(w.lpart);
-        big_blas_destroy(blas);
+        sp_blas_destroy(blas);
     }
 };
 
@@ -1807,7 +1865,7 @@ int cosim_sp_create(int n0, int n1, int F, int P, int ncomp, const double *S0_d,
     }
     if (d.fields32) SP_TRY(sp_to_c64(nf, d.fields64, d.fields32, st));
     SP_TRY(sp_prep(d, (const double2 *)sc_const_d, st));
-    SP_TRY(big_blas_create(&p->blas));
+    SP_TRY(sp_blas_create(&p->blas));
     SP_TRY(hipStreamSynchronize(st));  // host index copies and the caller's inputs are done with
 #undef SP_TRY
     *out = p;

@@ -42,8 +42,9 @@ __device__ inline double b_filament(int comp, double ax, double ay, double az, d
 // points of its lanes (every lane of a wave walks the same vertices, so each
 // vertex load is one cache line for the whole wave), one chunk of 64 loops at a time; each chunk of
 // the block tile [64][64] is staged in LDS and written out row-major, so that
-// a row segment of G is one contiguous store.  The transposed bf16 copies
-// (fused kernels only) are skipped when GThi is null.
+// a row segment of G is one contiguous store, and transposed, so that a
+// column segment of each transposed copy is one too.  Copies the plan did not
+// ask for are null and skipped.
 constexpr int kGPts = 64;
 constexpr int kGLoops = 64;
 
@@ -55,10 +56,10 @@ __global__ __launch_bounds__(256) void k_assemble_G(int n, int NP, int P, int P_
                                                     float *__restrict__ G32,
                                                     uint16_t *__restrict__ Ghi,
                                                     uint16_t *__restrict__ Glo,
+                                                    double *__restrict__ GT64,
+                                                    float *__restrict__ GT32,
                                                     uint16_t *__restrict__ GThi,
-                                                    uint16_t *__restrict__ GTlo,
-                                                    uint16_t *__restrict__ G3,
-                                                    uint16_t *__restrict__ GA3) {
+                                                    uint16_t *__restrict__ GTlo) {
     __shared__ double tile[kGPts][kGLoops + 1];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -109,39 +110,28 @@ __global__ __launch_bounds__(256) void k_assemble_G(int n, int NP, int P, int P_
             const float g32 = (float)g;
             if (G64) G64[o] = g;  // copies the plan did not ask for are null
             if (G32) G32[o] = g32;
-            if (Ghi || G3) {
+            if (Ghi) {
                 const uint16_t hi = bf16_rne(g32);
-                const uint16_t lo = bf16_rne(g32 - bf16_to_f(hi));
-                if (Ghi) {
-                    Ghi[o] = hi;
-                    Glo[o] = lo;
-                }
-                if (G3) {  // row pr of [P_pad][3 NP]: hi | hi | lo
-                    uint16_t *r3 = G3 + (size_t)pr * 3 * NP + k0 + kk;
-                    r3[0] = hi;
-                    r3[NP] = hi;
-                    r3[2 * NP] = lo;
-                }
-                if (GA3) {  // chunk c = pr / kBigRows: [3][kBigRows][NP], hi, hi, lo
-                    const int c = pr / kBigRows, r = pr - c * kBigRows;
-                    uint16_t *a3 = GA3 + ((size_t)3 * c * kBigRows + r) * NP + k0 + kk;
-                    a3[0] = hi;
-                    a3[(size_t)kBigRows * NP] = hi;
-                    a3[(size_t)2 * kBigRows * NP] = lo;
-                }
+                Ghi[o] = hi;
+                Glo[o] = bf16_rne(g32 - bf16_to_f(hi));
             }
         }
-        // transposed bf16 copies [NP][P_pad]: each loop's column is contiguous in p
-        if (GThi) {
+        // transposed copies [NP][P_pad]: each loop's column is contiguous in p
+        if (GT64 || GT32 || GThi) {
             for (int e = threadIdx.x; e < kGPts * kc; e += 256) {
                 const int kk = e / kGPts, r = e - kk * kGPts;
                 const int pr = prow0 + r;
                 if (pr >= P_pad) continue;
-                const float g32 = (float)tile[r][kk];
-                const uint16_t hi = bf16_rne(g32);
+                const double g = tile[r][kk];
+                const float g32 = (float)g;
                 const size_t o = (size_t)(k0 + kk) * P_pad + pr;
-                GThi[o] = hi;
-                GTlo[o] = bf16_rne(g32 - bf16_to_f(hi));
+                if (GT64) GT64[o] = g;
+                if (GT32) GT32[o] = g32;
+                if (GThi) {
+                    const uint16_t hi = bf16_rne(g32);
+                    GThi[o] = hi;
+                    GTlo[o] = bf16_rne(g32 - bf16_to_f(hi));
+                }
             }
         }
         __syncthreads();
@@ -280,11 +270,11 @@ __global__ __launch_bounds__(256) void k_assemble_M(int n, const int32_t *__rest
 
 hipError_t launch_assemble_G(int n, int NP, int P, int P_pad, int comp, const int32_t *seg_off_d,
                              const double *verts_d, const double *pts_d, double *G64,
-                             float *G32, uint16_t *Ghi, uint16_t *Glo, uint16_t *GThi,
-                             uint16_t *GTlo, uint16_t *G3, uint16_t *GA3, hipStream_t st) {
+                             float *G32, uint16_t *Ghi, uint16_t *Glo, double *GT64,
+                             float *GT32, uint16_t *GThi, uint16_t *GTlo, hipStream_t st) {
     const int blocks = (P_pad + kGPts - 1) / kGPts;
     hipLaunchKernelGGL(k_assemble_G, dim3(blocks), dim3(256), 0, st, n, NP, P, P_pad, comp, seg_off_d,
-                       verts_d, pts_d, G64, G32, Ghi, Glo, GThi, GTlo, G3, GA3);
+                       verts_d, pts_d, G64, G32, Ghi, Glo, GT64, GT32, GThi, GTlo);
     return hipGetLastError();
 }
 

@@ -45,16 +45,19 @@ inline int padded_loops(int n) {
     return n <= 32 ? 32 : (n + 63) / 64 * 64;
 }
 inline bool big_plan(int NP) { return NP > kMaxLoops; }
-constexpr int kPTile = 64;          // rows of G per LDS tile in the fused kernels
-constexpr int kBigRows = 2048;      // P-chunk of the adjoint GEMMs above 64 loops
+constexpr int kPTile = 64;          // rows of G per LDS tile in the fused kernels, and the
+                                    // padding of P in every plan
 
 // ---------------------------------------------------------------------------
 // kernel launchers (implemented in the .hip files); all return hipError_t
 // ---------------------------------------------------------------------------
+// G of Cartesian component `comp` at P points into the non-null copies:
+// [P_pad][NP] FP64 / FP32 / bf16 hi and lo, and the transposed [NP][P_pad]
+// copies of each (rows p >= P and columns k >= n are zero).
 hipError_t launch_assemble_G(int n, int NP, int P, int P_pad, int comp, const int32_t *seg_off_d,
                              const double *verts_d, const double *pts_d, double *G64,
-                             float *G32, uint16_t *Ghi, uint16_t *Glo, uint16_t *GThi,
-                             uint16_t *GTlo, uint16_t *G3, uint16_t *GA3, hipStream_t st);
+                             float *G32, uint16_t *Ghi, uint16_t *Glo, double *GT64,
+                             float *GT32, uint16_t *GThi, uint16_t *GTlo, hipStream_t st);
 
 hipError_t launch_assemble_M(int n, const int32_t *seg_off_d, const double *verts_d,
                              const double *wire_a_d, const GLRule &gl, double *M_d,
@@ -273,42 +276,38 @@ hipError_t launch_lu_solve(int NP, int n, int S, int F, const double2 *A_d, cons
                            double2 *I_d, int rhs_kind, const void *rhs_d, int nchunk,
                            double rscale, double *gsys_d, int32_t *status_d, hipStream_t st,
                            double2 *mu_d = nullptr);
-struct BigArgs {
-    int n, NP, P, P_pad, S, nchunk, rows;  // rows: P-chunk of the adjoint GEMMs
-    const void *G;                         // [P_pad][NP] FP64 or FP32 (F64 / F32)
-    // [P_pad][3 NP] rows (hi | hi | lo) of G: with X = (hi; lo; hi) planes of I the
-    // three bf16 products of the forward contraction are one GEMM over K = 3 NP
-    const uint16_t *G3;
-    // per P-chunk c of `rows` rows, [3][rows][NP]: the chunk's rows of G hi, hi
-    // again and lo, i.e. column-major NP x 3 rows; with the chunk's w planes as
-    // (hi; lo; hi) over 3 rows the adjoint's three bf16 products are one GEMM
-    const uint16_t *GA3;
-    const double2 *I;                      // [S][n]
-    const double *T;                       // [P]
-    void *X;     // NP x 2S planes of I (BF16X3: 3 NP x 2S, each plane hi, lo, hi)
-    void *Y;     // P_pad x 2S planes of B
-    void *W;     // P_pad x 2S planes of w (BF16X3: per chunk c and plane j, 3 rows (hi; lo; hi))
-    void *R;     // nchunk blocks of NP x 2S planes (double for F64, float otherwise)
-    double *lpart;  // [nchunk][S]
-    double inc = 0.0;  // incident field added before the loss (COSIM_LOSS_RATIO)
+// ---- matrix-core contractions for any padded loop count (contract_mfma.hip):
+// the loss path above 64 loops, the materialised field and its vector-Jacobian
+// product for every plan.
+enum MfmaMode {
+    kMfmaLoss = 0,      // B = G I, loss partials per (chunk, system)
+    kMfmaLossGrad = 1,  // and r = G^T w per (chunk, system)
+    kMfmaField = 2,     // B = G I written to Bout
+    kMfmaVjp = 3        // r = G^T g of the upstream gradient gB
 };
-hipError_t big_blas_create(void **handle);
-void big_blas_destroy(void *handle);
-hipError_t big_contract(void *handle, Prec prec, int loss_mode, bool grad, const BigArgs &a,
-                        hipStream_t st);
-hipError_t big_adjoint(void *handle, Prec prec, const BigArgs &a, hipStream_t st);
-// W planes (FP64) of an upstream field gradient g[s][p] for big_adjoint.
-hipError_t launch_pack_w64(int P, int P_pad, int S, const double2 *g_d, double *W_d,
-                           hipStream_t st);
-
-// Materialised field B[s][p] (complex128 for F64, complex64 otherwise).
-hipError_t launch_field(Prec prec, int NP, int P, int S, int n, const double *G64,
-                        const double2 *I_d, void *Bz_d, hipStream_t st);
-
-// r[s][i] = sum_p G[p][i] * gBz[s][p]  (rr, ri parts; FP64), stored in rpart[0].
-hipError_t launch_field_backward_contract(int NP, int P, int S, int n, const double *G64,
-                                          const double2 *gBz_d, double2 *rpart_d,
-                                          hipStream_t st);
+// FP32 accumulation of r covers at most this many points per chunk.
+constexpr int kMfmaRowsF32 = 2048;
+struct MfmaArgs {
+    const void *G = nullptr, *Glo = nullptr;    // [P_pad][NP] (Glo: bf16 lo part, BF16X3)
+    const void *GT = nullptr, *GTlo = nullptr;  // [NP][P_pad] transposed copies
+    const double2 *I = nullptr;                 // [S][n] currents (loss, field)
+    const double2 *gB = nullptr;                // [S][P] upstream gradient (vjp)
+    const double *T = nullptr;                  // [P] targets (loss)
+    double inc = 0.0;                           // incident field of COSIM_LOSS_RATIO
+    void *Bout = nullptr;  // [S][P] complex128 (FP64) or complex64 (field)
+    int n = 0, NP = 0, P = 0, P_pad = 0, S = 0;
+    int rows_per_chunk = 0, nchunk = 0, nsb = 0;  // chunks of points, system blocks
+    double2 *rpart = nullptr;  // [nchunk][S][NP] (rr, ri) of r = G^T w
+    double *lpart = nullptr;   // [nchunk][S] loss partial sums
+};
+struct MfmaShape {
+    int waves = 1, nsb = 1, rows_per_chunk = 0, nchunk = 0;
+};
+// Systems per workgroup, and the launch shape for S systems.
+int mfma_systems_per_block(Prec prec);
+MfmaShape mfma_shape(Prec prec, int NP, int S, int P_pad, int cus);
+hipError_t launch_mfma(Prec prec, int mode, int loss_mode, const MfmaArgs &a, int waves,
+                       hipStream_t st);
 
 // ---- the other circuit variables and the helpers around C (params.hip)
 // Per system from I and mu ([S][n]): the R and L terms to gRs, gLs ([S][n])
@@ -349,6 +348,9 @@ struct SpWork {
     void *Rp = nullptr;               // [nchunk][F][B][n0] conj(fields^H w) per chunk
     double *lpart = nullptr;          // [nchunk][F][B] loss partial sums
 };
+// The S-parameter pipeline's complex contractions run on rocBLAS; its handle.
+hipError_t sp_blas_create(void **handle);
+void sp_blas_destroy(void *handle);
 hipError_t sp_prep(const SpDev &d, const double2 *sc_const, hipStream_t st);
 hipError_t sp_set_lds_limit();
 hipError_t sp_to_c64(size_t count, const double2 *a, float2 *b, hipStream_t st);
@@ -402,12 +404,11 @@ struct cosim_plan {
     std::vector<double> R_h;     // what R_d holds
     std::vector<double> exc_h;   // what phi_d holds: [3][n], see loop_voltage
     // operators (device)
-    double *G64 = nullptr;
-    float *G32 = nullptr;
-    uint16_t *Ghi = nullptr, *Glo = nullptr;  // [P_pad][NP] bf16 hi / lo, 64 loops or fewer
-    uint16_t *GThi = nullptr, *GTlo = nullptr;  // transposed copies [NP][P_pad]
-    uint16_t *G3 = nullptr;  // above 64 loops: [P_pad][3 NP] rows (hi | hi | lo), see BigArgs
-    uint16_t *GA3 = nullptr; // above 64 loops: per adjoint chunk [3][kBigRows][NP] (hi, hi, lo)
+    // [P_pad][NP] row-major per precision, and transposed [NP][P_pad] copies
+    double *G64 = nullptr, *GT64 = nullptr;
+    float *G32 = nullptr, *GT32 = nullptr;
+    uint16_t *Ghi = nullptr, *Glo = nullptr;    // bf16 hi / lo
+    uint16_t *GThi = nullptr, *GTlo = nullptr;
     double *M_d = nullptr, *R_d = nullptr;
     double *phi_d = nullptr;  // [3][n] loop excitation, see loop_voltage
     // workspace (device)
@@ -417,13 +418,17 @@ struct cosim_plan {
     double2 *rpart = nullptr;
     double *lpart = nullptr;
     double *gsys = nullptr;
-    cosim::GJFactor fac;  // recorded forward eliminations (loss_and_grad)
+    cosim::GJFactor fac;  // recorded forward eliminations (loss_and_grad, solve)
+    // the factor record of the last cosim_solve, while no other call has
+    // overwritten the workspace: its B and F (rec_S = 0: none)
+    int rec_B = 0, rec_F = 0;
+    size_t rec_S = 0;
+    int32_t *rec_status = nullptr;  // [cap_systems] status of that solve
+    long long factorisations = 0;   // batches whose Z this plan has factorised
     // optional phase timing: (COSIM_PHASES + 1) events per recorded call
     std::vector<hipEvent_t> events;
     int timing_cap = 0, timing_used = 0;
-    // more than 64 loops: GEMM operands and the rocBLAS handle
-    void *blas = nullptr;
-    void *bX = nullptr, *bY = nullptr, *bW = nullptr;
+    // more than 64 loops: the blocked LDL^T and refinement workspace
     double2 *bWt = nullptr;   // blocked LDL^T panel copy ([S][64][NP], see BigFactor)
     double2 *bTinv = nullptr; // blocked LDL^T L11^-T ([S][64][64])
     double *bZmax = nullptr;  // [S] largest diagonal |Z_kk| (blocked LDL^T)

@@ -441,6 +441,17 @@ hipError_t launch_solve(const SpDev &d, int B, const double2 *values, double2 *X
 
 }  // namespace
 
+hipError_t sp_blas_create(void **handle) {
+    rocblas_handle h = nullptr;
+    if (rocblas_create_handle(&h) != rocblas_status_success) return hipErrorOutOfMemory;
+    *handle = h;
+    return hipSuccess;
+}
+
+void sp_blas_destroy(void *handle) {
+    if (handle) (void)rocblas_destroy_handle((rocblas_handle)handle);
+}
+
 hipError_t sp_prep(const SpDev &d, const double2 *scc, hipStream_t st) {
     hipLaunchKernelGGL(k_sp_prep, dim3(d.n0, d.F), dim3(64), 0, st, d.n0, d.n1, d.F, d.S0, scc,
                        d.exc, d.K, d.r0);

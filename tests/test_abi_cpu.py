@@ -103,8 +103,11 @@ def test_hot_call_argument_errors(lib):
     # null plan
     assert lib.cosim_solve(None, 1, 1, dummy, dummy, dummy, dummy, None) == EINVAL
     assert lib.cosim_loss_and_grad(None, 1, 1, dummy, dummy, dummy, 0, 1, dummy, dummy, dummy, None) == EINVAL
-    assert lib.cosim_field(None, 1, 1, dummy, 0, dummy, None) == EINVAL
-    assert lib.cosim_field_backward(None, 1, 1, dummy, dummy, dummy, dummy, dummy, dummy, None) == EINVAL
+    assert lib.cosim_field(None, 1, 1, dummy, 0, 0, dummy, None) == EINVAL
+    assert lib.cosim_field_backward(None, 1, 1, dummy, dummy, dummy, dummy, 0, 1, dummy, dummy,
+                                    None) == EINVAL
+    cnt = ctypes.c_longlong()
+    assert lib.cosim_plan_factorisations(None, ctypes.byref(cnt)) == EINVAL
     assert lib.cosim_plan_reserve(None, 1, 1) == EINVAL
     assert lib.cosim_plan_copy_M(None, dummy) == EINVAL
     assert lib.cosim_plan_destroy(None) == 0

@@ -658,10 +658,13 @@ def test_assembly_mask_refuses_missing_copies(dev):
     loss, grad, st = plan.loss_and_grad(C, om, T, precision=2)
     torch.cuda.synchronize()
     assert torch.isfinite(loss).all()
+    I, _ = plan.solve(C, om)
+    assert torch.isfinite(plan.field(I, 2)).all()  # the bf16 copies serve the bf16 field
     for call in (lambda: plan.loss_and_grad(C, om, T, precision=0),
                  lambda: plan.loss_and_grad(C, om, T, precision=1),
                  lambda: plan.G(),
-                 lambda: plan.field(plan.solve(C, om)[0], 2)):
+                 lambda: plan.field(I, 0),
+                 lambda: plan.field(I, 1)):
         with pytest.raises(CosimError):
             call()
 
