@@ -20,7 +20,7 @@ LIB = os.path.join(PKG, "libcosim.so")
 ARCH = os.environ.get("COSIM_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["abi.cpp", "assemble.hip", "solve.hip", "solve_big.hip", "fused.hip",
-           "contract_mfma.hip", "optim.hip", "sparam.hip", "params.hip", "noalloc.hip"]
+           "contract_mfma.hip", "gemm_big.hip", "optim.hip", "sparam.hip", "params.hip", "noalloc.hip"]
 # the S-parameter pipeline's complex GEMMs run on rocBLAS
 LIBS = ["-L/opt/rocm/lib", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
 

@@ -88,6 +88,7 @@ void plan_free_workspace(cosim_plan *p) {
     dfree(p->I_ws);
     dfree(p->rpart);
     dfree(p->lpart);
+    dfree(p->gws);
     dfree(p->gsys);
     dfree(p->rec_status);
     dfree(p->fac.L);
@@ -96,6 +97,8 @@ void plan_free_workspace(cosim_plan *p) {
     dfree(p->fac.fmt);
     p->cap_systems = 0;
     p->cap_parts = 0;
+    p->cap_lparts = 0;
+    p->cap_gws = 0;
     p->rec_S = 0;
 }
 
@@ -152,14 +155,24 @@ int check_device(const cosim_plan *p) {
     return COSIM_OK;
 }
 
-// Make room for `systems` systems and `chunks` P-chunks of partial sums.
 // Workspace for `systems` systems whose partial sums use `chunks` P-chunks
-// (and at least `parts` (chunk, system) slots).
-int ensure_workspace(cosim_plan *p, size_t systems, int chunks, size_t parts = 0) {
+// (and at least `parts` (chunk, system) slots of r, `lparts` of the loss),
+// with the GEMM passes' planes when a batch this large above 64 loops takes
+// them.
+int ensure_workspace(cosim_plan *p, size_t systems, int chunks, size_t parts = 0,
+                     size_t lparts = 0) {
     parts = std::max(parts, systems * (size_t)chunks);
-    if (systems <= p->cap_systems && parts <= p->cap_parts) return COSIM_OK;
+    lparts = std::max(lparts, parts);
+    const size_t gneed = big_plan(p->NP) && gemm_path(Prec::F64, p->NP, (int)systems)
+                             ? gemm_ws_bytes(p->NP, (int)systems, p->P_pad)
+                             : 0;
+    if (systems <= p->cap_systems && parts <= p->cap_parts && lparts <= p->cap_lparts &&
+        gneed <= p->cap_gws)
+        return COSIM_OK;
     const size_t ns = std::max(systems, p->cap_systems);
     const size_t np_parts = std::max(parts, p->cap_parts);
+    const size_t nl_parts = std::max(lparts, p->cap_lparts);
+    const size_t ngws = std::max(gneed, p->cap_gws);
     plan_free_workspace(p);
     const size_t n = (size_t)p->n, NP = (size_t)p->NP;
     const bool big = big_plan(p->NP);
@@ -179,7 +192,8 @@ int ensure_workspace(cosim_plan *p, size_t systems, int chunks, size_t parts = 0
     }
     if (hipMalloc((void **)&p->I_ws, ns * n * sizeof(double2)) != hipSuccess ||
         hipMalloc((void **)&p->rpart, np_parts * NP * sizeof(double2)) != hipSuccess ||
-        hipMalloc((void **)&p->lpart, np_parts * sizeof(double)) != hipSuccess ||
+        hipMalloc((void **)&p->lpart, nl_parts * sizeof(double)) != hipSuccess ||
+        (ngws > 0 && hipMalloc(&p->gws, ngws) != hipSuccess) ||
         hipMalloc((void **)&p->gsys, ns * n * sizeof(double)) != hipSuccess ||
         hipMalloc((void **)&p->rec_status, ns * sizeof(int32_t)) != hipSuccess ||
         hipMalloc((void **)&p->fac.L, ns * NP * NP * sizeof(double2)) != hipSuccess ||
@@ -193,6 +207,8 @@ int ensure_workspace(cosim_plan *p, size_t systems, int chunks, size_t parts = 0
     }
     p->cap_systems = ns;
     p->cap_parts = np_parts;
+    p->cap_lparts = nl_parts;
+    p->cap_gws = ngws;
     return COSIM_OK;
 }
 
@@ -229,14 +245,23 @@ int choose_chunks(const cosim_plan *p, Prec prec, size_t S, int variant) {
 // chunks of whole 64-row tiles, every chunk non-empty; *tiles_per_chunk out
 int chunks_for(const cosim_plan *p, Prec prec, size_t S, int variant, int *tiles_per_chunk = nullptr) {
     const int tiles = p->P_pad / kPTile;
-    if (big_plan(p->NP)) {  // chunks of the matrix-core contraction kernel
+    if (big_plan(p->NP)) {  // chunks of r of the contraction kernels
         if (tiles_per_chunk) *tiles_per_chunk = 0;
+        if (gemm_path(prec, p->NP, (int)S)) return gemm_shape(prec, p->NP, (int)S, p->P_pad).nkc;
         return mfma_shape(prec, p->NP, (int)S, p->P_pad, p->cus).nchunk;
     }
     const int want = choose_chunks(p, prec, S, variant);
     const int tpc = (tiles + want - 1) / want;
     if (tiles_per_chunk) *tiles_per_chunk = tpc;
     return (tiles + tpc - 1) / tpc;
+}
+
+// Loss partial sums per system of the contraction (the chunks of r, except
+// for the GEMM passes, which sum the loss per block of points).
+int loss_chunks(const cosim_plan *p, Prec prec, size_t S, int nchunk) {
+    if (big_plan(p->NP) && gemm_path(prec, p->NP, (int)S))
+        return gemm_shape(prec, p->NP, (int)S, p->P_pad).row_blocks;
+    return nchunk;
 }
 
 // Tuning variants of a plan: the fused kernels' for up to 64 loops, a single
@@ -266,6 +291,28 @@ MfmaArgs mfma_args(const cosim_plan *p, Prec prec, int S, const MfmaShape &sh) {
     a.rpart = p->rpart;
     a.lpart = p->lpart;
     return a;
+}
+
+// The loss (and gradient) contraction above 64 loops of S systems into the
+// plan's rpart / lpart: the GEMM passes for large batches, else the fused
+// kernel.
+hipError_t big_contract(cosim_plan *p, Prec prec, int loss_mode, bool grad, int S,
+                        const double2 *I, const double *T, double inc, hipStream_t st) {
+    if (gemm_path(prec, p->NP, S)) {
+        GemmLoss L;
+        const MfmaArgs m = mfma_args(p, prec, S, MfmaShape{});
+        L.G = m.G; L.Glo = m.Glo; L.GT = m.GT; L.GTlo = m.GTlo;
+        L.I = I; L.T = T; L.inc = inc;
+        L.n = p->n; L.NP = p->NP; L.P = p->P; L.P_pad = p->P_pad; L.S = S;
+        L.ws = p->gws; L.lpart = p->lpart; L.rpart = p->rpart;
+        return launch_gemm_loss(prec, loss_mode, grad, L, st);
+    }
+    const MfmaShape sh = mfma_shape(prec, p->NP, S, p->P_pad, p->cus);
+    MfmaArgs a = mfma_args(p, prec, S, sh);
+    a.I = I;
+    a.T = T;
+    a.inc = inc;
+    return launch_mfma(prec, grad ? kMfmaLossGrad : kMfmaLoss, loss_mode, a, sh.waves, st);
 }
 
 int check_batch(const cosim_plan *p, int B, int F) {
@@ -625,14 +672,16 @@ int cosim_plan_reserve(cosim_plan_t p, int max_batch, int max_freq) {
     const size_t S = (size_t)max_batch * max_freq;
     // partial-sum slots for every batch up to S: a smaller batch may use more
     // P-chunks (the fused kernels split P further to fill the chip)
-    size_t parts = S;
+    size_t parts = S, lparts = S;
     for (int pr = COSIM_FP64; pr <= COSIM_BF16X3; ++pr)
         for (int v = 0; v < plan_variants(p, (Prec)pr); ++v) {
             if (big_plan(p->NP)) {  // a smaller batch may split the points further
                 const size_t ns = (size_t)mfma_systems_per_block((Prec)pr);
                 for (size_t sb = 1; sb <= (S + ns - 1) / ns; ++sb) {
                     const size_t Sb = std::min(S, sb * ns);
-                    parts = std::max(parts, Sb * (size_t)chunks_for(p, (Prec)pr, Sb, v));
+                    const int c = chunks_for(p, (Prec)pr, Sb, v);
+                    parts = std::max(parts, Sb * (size_t)c);
+                    lparts = std::max(lparts, Sb * (size_t)loss_chunks(p, (Prec)pr, Sb, c));
                 }
                 continue;
             }
@@ -643,7 +692,7 @@ int cosim_plan_reserve(cosim_plan_t p, int max_batch, int max_freq) {
                 parts = std::max(parts, Sb * (size_t)chunks_for(p, (Prec)pr, Sb, v));
             }
         }
-    return ensure_workspace(p, S, 1, parts);
+    return ensure_workspace(p, S, 1, parts, lparts);
 }
 
 int cosim_plan_copy_G(cosim_plan_t p, double *G_d, void *stream) {
@@ -966,7 +1015,8 @@ static int loss_and_grad_impl(cosim_plan_t p, int B, int F, const double *C_d, c
         w.fac.piv_val = (double2 *)(b + off[6]);
         w.fac.fmt = (int *)(b + off[7]);
     } else {
-        if ((rc = ensure_workspace(p, S, nchunk))) return rc;
+        if ((rc = ensure_workspace(p, S, nchunk, 0, S * (size_t)loss_chunks(p, prec, S, nchunk))))
+            return rc;
         p->rec_S = 0;  // the factor record of a cosim_solve is overwritten
         w.I = p->I_ws;
         w.rpart = p->rpart;
@@ -1004,20 +1054,16 @@ static int loss_and_grad_impl(cosim_plan_t p, int B, int F, const double *C_d, c
                           p->fac.L, p->fac.piv_row, p->I_ws, kRhsExcitation, nullptr, 0, 0.0,
                           nullptr, status_d, st));
         if (ev) HIP_TRY(hipEventRecord(ev[1], st));
-        const MfmaShape sh = mfma_shape(prec, p->NP, (int)S, p->P_pad, p->cus);
-        MfmaArgs a = mfma_args(p, prec, (int)S, sh);
-        a.I = p->I_ws;
-        a.T = T_d;
-        a.inc = ratio ? p->bext_z : 0.0;
-        HIP_TRY(launch_mfma(prec, grad ? kMfmaLossGrad : kMfmaLoss, loss_mode, a, sh.waves, st));
+        HIP_TRY(big_contract(p, prec, loss_mode, grad, (int)S, p->I_ws, T_d,
+                             ratio ? p->bext_z : 0.0, st));
         if (ev) HIP_TRY(hipEventRecord(ev[2], st));
         if (grad)
             HIP_TRY(big_solve(bf, rf, p->NP, p->n, (int)S, F, p->M_d, p->R_d, p->phi_d, C_d,
                               omega_d, p->fac.L, p->fac.piv_row, p->I_ws, kRhsPairs, p->rpart,
                               nchunk, scale, p->gsys, status_d, st, mu));
         if (ev) HIP_TRY(hipEventRecord(ev[3], st));
-        HIP_TRY(launch_reduce(p->n, B, F, nchunk, grad ? p->gsys : nullptr, p->lpart, scale,
-                              grad_d, loss_d, st));
+        HIP_TRY(launch_reduce(p->n, B, F, loss_chunks(p, prec, S, nchunk),
+                              grad ? p->gsys : nullptr, p->lpart, scale, grad_d, loss_d, st));
         if (ev) HIP_TRY(hipEventRecord(ev[4], st));
         return COSIM_OK;
     }
@@ -1376,21 +1422,16 @@ static int enqueue_big_group(const ManyCall &mc, const std::vector<int> &g, int 
         cosim_plan *p = plans[i];
         hipStream_t cs = pool->streams[(k + 1 + m) % ns];
         hipEvent_t ev_c = pool->extra[next_ev++];
-        const int Si = B[i] * F[i];
-        const MfmaShape sh = mfma_shape(prec, NP, Si, p->P_pad, p->cus);
-        MfmaArgs a = mfma_args(p, prec, Si, sh);
-        a.I = p->I_ws;
-        a.T = Teff[m];
+        const double *Ti = Teff[m];
         bool ok = hipStreamWaitEvent(cs, ev_fwd, 0) == hipSuccess;
         if (ok && ratio) {
             ok = launch_scale((size_t)p->P, std::fabs(p->bext_z), T_d[i], p->T_ratio, cs) ==
                  hipSuccess;
-            a.T = p->T_ratio;
-            a.inc = p->bext_z;
+            Ti = p->T_ratio;
         }
         ok = ok &&
-             launch_mfma(prec, grad ? kMfmaLossGrad : kMfmaLoss, loss_mode, a, sh.waves, cs) ==
-                 hipSuccess &&
+             big_contract(p, prec, loss_mode, grad, B[i] * F[i], p->I_ws, Ti,
+                          ratio ? p->bext_z : 0.0, cs) == hipSuccess &&
              hipEventRecord(ev_c, cs) == hipSuccess && hipStreamWaitEvent(gs, ev_c, 0) == hipSuccess;
         if (!ok) first_rc = fail_instance(fail(COSIM_EDEVICE, "contraction launch failed"), i);
     }
@@ -1406,7 +1447,8 @@ static int enqueue_big_group(const ManyCall &mc, const std::vector<int> &g, int 
         const int i = g[m];
         rg.in[m] = {grad ? plans[i]->gsys : nullptr, plans[i]->lpart,
                     grad ? grad_d[i] : nullptr, loss_d[i], scale[m],
-                    plans[i]->n, B[i], F[i], chunks[i], Bg};
+                    plans[i]->n, B[i], F[i],
+                    loss_chunks(plans[i], prec, (size_t)B[i] * F[i], chunks[i]), Bg};
         Bg += B[i];
     }
     if (launch_reduce_group(rg, Bg, gs) != hipSuccess)
@@ -1503,7 +1545,10 @@ int cosim_loss_and_grad_many(int count, const cosim_plan_t *plans, const int *B,
             const size_t S = (size_t)B[i] * F[i], NP = (size_t)plans[i]->NP;
             chunks[i] = chunks_for(plans[i], (Prec)precision, S, plans[i]->variant[precision],
                                    &tpcs[i]);
-            if ((rc = ensure_workspace(plans[i], S, chunks[i]))) return fail_instance(rc, i);
+            if ((rc = ensure_workspace(plans[i], S, chunks[i], 0,
+                                       S * (size_t)loss_chunks(plans[i], (Prec)precision, S,
+                                                               chunks[i]))))
+                return fail_instance(rc, i);
             if (!big_plan((int)NP)) continue;  // its own factor record
             big_groups = true;
             nA += S * NP * NP;

@@ -309,6 +309,46 @@ MfmaShape mfma_shape(Prec prec, int NP, int S, int P_pad, int cus);
 hipError_t launch_mfma(Prec prec, int mode, int loss_mode, const MfmaArgs &a, int waves,
                        hipStream_t st);
 
+// ---- large batches above 64 loops: two GEMM passes (gemm_big.hip)
+// One pass: C (M x N) = A B^T with A [M][lda] and B [N][ldb] K-contiguous.
+struct GemmArgs {
+    const void *A = nullptr, *Alo = nullptr;  // Alo / Blo: bf16 lo planes (BF16X3)
+    const void *B = nullptr, *Blo = nullptr;
+    int M = 0, N = 0, K = 0, lda = 0, ldb = 0;
+    int kchunk = 0, nkc = 1;  // K in chunks (pass 2: one partial per chunk)
+    // pass 1: loss per (row block, system), w planes [N][ldw] when W is set
+    const double *T = nullptr;
+    double inc = 0.0;
+    int P = 0;
+    void *W = nullptr, *Wlo = nullptr;
+    int ldw = 0;
+    double *lpart = nullptr;
+    // pass 2: r per (chunk, system) as (rr, ri)
+    double2 *rpart = nullptr;
+    int S = 0, NP = 0;
+};
+struct GemmShape {
+    int N = 0;           // columns (2 S padded to the column block)
+    int row_blocks = 0;  // loss partials per system
+    int kchunk = 0, nkc = 0;  // adjoint chunks of points: r partials per system
+};
+// The loss and gradient contractions of S systems by the two passes.
+struct GemmLoss {
+    const void *G, *Glo, *GT, *GTlo;  // the precision's copies of G
+    const double2 *I;                 // [S][n]
+    const double *T;
+    double inc;
+    int n, NP, P, P_pad, S;
+    void *ws;         // gemm_ws_bytes: X^T and W^T planes
+    double *lpart;    // [row_blocks][S]
+    double2 *rpart;   // [nkc][S][NP]
+};
+bool gemm_path(Prec prec, int NP, int S);
+GemmShape gemm_shape(Prec prec, int NP, int S, int P_pad);
+size_t gemm_ws_bytes(int NP, int S, int P_pad);
+hipError_t launch_gemm_loss(Prec prec, int loss_mode, bool grad, const GemmLoss &L,
+                            hipStream_t st);
+
 // ---- the other circuit variables and the helpers around C (params.hip)
 // Per system from I and mu ([S][n]): the R and L terms to gRs, gLs ([S][n])
 // and dL/dw to gw ([B][F]); then, if gR / gL is set, their sums over
@@ -413,7 +453,10 @@ struct cosim_plan {
     double *phi_d = nullptr;  // [3][n] loop excitation, see loop_voltage
     // workspace (device)
     size_t cap_systems = 0;
-    size_t cap_parts = 0;  // (P-chunk, system) slots of the partial sums rpart / lpart
+    size_t cap_parts = 0;  // (P-chunk, system) slots of the partial sums rpart
+    size_t cap_lparts = 0; // (P-chunk, system) slots of the loss partial sums lpart
+    void *gws = nullptr;   // above 64 loops, large batches: the GEMM passes' planes
+    size_t cap_gws = 0;
     double2 *I_ws = nullptr;
     double2 *rpart = nullptr;
     double *lpart = nullptr;

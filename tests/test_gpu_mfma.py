@@ -146,3 +146,44 @@ def test_autograd_backward_replays_forward_factor(dev, name, prec):
         torch.cuda.synchronize()
         assert plan.factorisations() == n0 + (1 if interleave else 0)
         assert _nrel(C.grad.cpu().numpy(), gr, axis=1).max() < TOL[prec]
+
+
+@functools.lru_cache(maxsize=None)
+def _batch_case(name):
+    """Batches large enough for the two GEMM passes above 64 loops (at least
+    128 systems; 64 in FP64), with ragged row and column blocks."""
+    from paper_2503_18479_amd import Geometry, Plan
+    nx, batch, grid, nf, seed = {"n81": (9, 70, 21, 2, 76), "n144": (12, 33, 15, 4, 77)}[name]
+    wl = W.small_array(nx, nx, batch=batch, grid=grid, n_freq=nf, seed=seed)
+    g = wl.geom
+    dev = torch.device("cuda:0")
+    G = O.field_matrix(g.verts, g.seg_off, wl.pts)
+    M = O.inductance_matrix_lattice(g.verts, g.seg_off, g.wire_a, nx, nx)
+    Phi = O.flux(g.verts, g.seg_off, wl.bext_z)
+    plan = Plan(Geometry.from_workload(g), torch.tensor(wl.pts, device=dev), wl.bext_z)
+    return dict(wl=wl, G=G, M=M, Phi=Phi, plan=plan, C=torch.tensor(wl.C, device=dev),
+                om=torch.tensor(wl.omega, device=dev), T=torch.tensor(wl.target, device=dev))
+
+
+@pytest.mark.parametrize("mode", [O.LOSS_MAG, O.LOSS_COMPLEX])
+@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("name", ["n81", "n144"])
+def test_gemm_passes_loss_and_grad(dev, name, prec, mode):
+    c = _batch_case(name)
+    wl = c["wl"]
+    _say(f"[gemm] {name} S={wl.B * wl.F} prec={prec} mode={mode}")
+    loss, grad, st = c["plan"].loss_and_grad(c["C"], c["om"], c["T"], loss_mode=mode,
+                                             precision=prec)
+    torch.cuda.synchronize()
+    assert int(st.abs().sum()) == 0
+    Lr = O.evaluate(c["G"], c["M"], wl.geom.R, c["Phi"], wl.C, wl.omega, wl.target, mode)[2]
+    gr = O.grad_adjoint(c["G"], c["M"], wl.geom.R, c["Phi"], wl.C, wl.omega, wl.target, mode)
+    el = np.abs(loss.cpu().numpy() - Lr) / np.abs(Lr)
+    eg = _nrel(grad.cpu().numpy(), gr, axis=1)
+    _say(f"[gemm] {name} prec={prec} mode={mode}: loss {el.max():.2e} grad {eg.max():.2e}")
+    assert el.max() < TOL[prec] and eg.max() < TOL[prec]
+    # loss only: the same loss
+    l2, _, _ = c["plan"].loss_and_grad(c["C"], c["om"], c["T"], loss_mode=mode, precision=prec,
+                                       grad=False)
+    torch.cuda.synchronize()
+    assert torch.equal(l2, loss)
