@@ -55,7 +55,7 @@ def parse():
                     help="skip cosim_plan_autotune (use the default kernel variants)")
     ap.add_argument("--profile-steps", type=int, default=None,
                     help="run only this many steps of the headline mode (for rocprofv3)")
-    ap.add_argument("--ragged", type=int, default=256,
+    ap.add_argument("--ragged", type=int, default=2048,
                     help="also time this many independent instances of the ragged configuration "
                          "(16-256 loops, 16k-65k points, 1-8 frequencies; 2048 is the full set; 0: skip)")
     ap.add_argument("--large-adam", type=int, default=200,

@@ -382,8 +382,9 @@ int cosim_adam_step(int count, double *C_d, const double *grad_d, double *m_d, d
  * larger one, allocates.  Calls on
  * one device may overlap (other streams, other host threads): the enqueueing
  * is serialised, and the side streams of a call that groups instances wait
- * for the previous such call to finish.  Under capture every instance runs on
- * its own and the shared workspace is not touched. */
+ * for the previous such call to finish.  Under capture, instances of 64
+ * loops or fewer are grouped as outside it; instances above 64 loops run on
+ * their own and the shared workspace is not touched. */
 int cosim_loss_and_grad_many(int count, const cosim_plan_t *plans, const int *B, const int *F,
                              const double *const *C_d, const double *const *omega_d,
                              const double *const *T_d, int loss_mode, int precision,

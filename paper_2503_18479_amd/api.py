@@ -403,9 +403,8 @@ def capture_loss_and_grad_many(plans, Cs, omegas, Ts, loss_mode: int = LOSS_MAG,
     outside the capture (on a side stream).  Returns (graph, outs): replaying
     the graph recomputes outs from the current contents of Cs, omegas and Ts
     (update them in place); a call of many small launches becomes one launch.
-    Under capture every instance runs its own chain of launches (the shared
-    launches of instances of one size are not captured), so for many small
-    instances an eager call can be the faster of the two."""
+    Under capture, instances of 64 loops or fewer share launches per padded
+    size as in an eager call; instances above 64 loops run their own chains."""
     for pl, C, o in zip(plans, Cs, omegas):
         pl.reserve(int(C.shape[0]), int(o.shape[0]))
     side = torch.cuda.Stream()

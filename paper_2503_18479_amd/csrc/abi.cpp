@@ -1501,19 +1501,27 @@ int cosim_loss_and_grad_many(int count, const cosim_plan_t *plans, const int *B,
     // kSmallGroupMax (64 or fewer) of one padded size per group: one launch per
     // solver step for all their systems, in place of one per instance.  Their
     // contractions stay per instance.
-    // Not while the stream is captured: ending a capture that held the grouped
-    // launches crashed the HIP runtime (the cause is not known), so a captured
-    // call runs every instance on its own.
+    // While the stream is captured, instances above 64 loops are not grouped:
+    // ending a capture that held their grouped launches once crashed the HIP
+    // runtime on the host, with no cause found, and such a capture has not
+    // been run again.  Their groups would also keep factor records in the
+    // pool's shared workspace, whose reuse across calls is ordered by the event
+    // ws_free of the previous grouping call, recorded outside any capture.
+    // Groups of 64 loops or fewer use only their plans' workspaces and events
+    // recorded inside the call (and capture correctly), so they are grouped
+    // under capture too.
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     HIP_TRY(hipStreamIsCapturing(st, &cap));
+    const bool captured = cap != hipStreamCaptureStatusNone;
     std::vector<std::vector<int>> groups;
     std::vector<char> grouped(count, 0);
-    if (cap == hipStreamCaptureStatusNone) {
+    {
         std::vector<std::pair<int, int>> cand;  // (NP, instance)
         for (int i = 0; i < count; ++i) {
             const cosim_plan *p = plans[i];
             if ((size_t)B[i] * F[i] == 0 || !p->ldl_ok) continue;
             if (big_refine_args(p, precision).on || p->timing_used < p->timing_cap) continue;
+            if (captured && big_plan(p->NP)) continue;
             cand.emplace_back(p->NP, i);
         }
         std::stable_sort(cand.begin(), cand.end(),
@@ -1564,7 +1572,7 @@ int cosim_loss_and_grad_many(int count, const cosim_plan_t *plans, const int *B,
         HIP_TRY(hipStreamWaitEvent(pool->streams[k], pool->start, 0));
         // the group workspace is shared by every call on the device: wait
         // until the previous call that used it has finished (never under
-        // capture, where nothing is grouped)
+        // capture, where no group uses it)
         if (big_groups && pool->ws_used)
             HIP_TRY(hipStreamWaitEvent(pool->streams[k], pool->ws_free, 0));
     }

@@ -1139,8 +1139,9 @@ def test_grouped_large_instances_match_single_calls(dev):
     frequency counts and points), two of 144 and two small ones.  Every
     result equals the instance's own cosim_loss_and_grad call bit for bit,
     in three precisions.  Under stream capture the call runs the instances
-    one by one (capturing the grouped launches crashed the HIP runtime at the
-    end of the capture); graph replays of it equal the single calls too."""
+    above 64 loops one by one (a capture of their grouped launches once
+    crashed the HIP runtime, cause not found); graph replays of it equal the
+    single calls too."""
     from paper_2503_18479_amd import (Geometry, Plan, loss_and_grad_many,
                                       capture_loss_and_grad_many)
     wls = [W.small_array(9, 9, batch=2, grid=30, n_freq=3, seed=41),
@@ -1190,6 +1191,39 @@ def test_grouped_large_instances_match_single_calls(dev):
         for (l, g, s), (l1, g1, s1) in zip(gouts, ref):
             assert torch.equal(l, l1) and torch.equal(g, g1) and torch.equal(s, s1), rep
     del gr
+
+
+def test_grouped_small_instances_captured(dev):
+    """Instances of 64 loops or fewer of one padded size share launches also
+    under stream capture: nine instances of 16 to 64 loops (padded to 32 and
+    64) with other instances beside them, captured once and replayed three
+    times after eager work with new capacitances; every replay equals the
+    instances' own calls bit for bit."""
+    from paper_2503_18479_amd import Geometry, Plan, capture_loss_and_grad_many
+    shapes = [(4, 4, 2, 20, 3), (5, 5, 1, 25, 2), (6, 6, 2, 18, 1), (7, 7, 1, 22, 4),
+              (8, 8, 3, 16, 2), (4, 4, 1, 30, 1), (6, 6, 1, 24, 3), (8, 8, 1, 20, 2),
+              (5, 6, 2, 19, 2), (9, 9, 1, 21, 2)]
+    wls = [W.small_array(nx, ny, batch=b, grid=g, n_freq=f, seed=60 + i)
+           for i, (nx, ny, b, g, f) in enumerate(shapes)]
+    plans = [Plan(Geometry.from_workload(w.geom), torch.tensor(w.pts, device=dev), w.bext_z)
+             for w in wls]
+    Cs = [torch.tensor(w.C, device=dev) for w in wls]
+    Os = [torch.tensor(w.omega, device=dev) for w in wls]
+    Ts = [torch.tensor(w.target, device=dev) for w in wls]
+    for prec in (0, 2):
+        _say(f"[captured groups] prec={prec}")
+        gr, gouts = capture_loss_and_grad_many(plans, Cs, Os, Ts, precision=prec)
+        for rep in range(3):
+            for C in Cs:
+                C.mul_(1.0 + 0.01 * (rep + 1))
+            ref = [pl.loss_and_grad(C, o, T, precision=prec)
+                   for pl, C, o, T in zip(plans, Cs, Os, Ts)]
+            torch.cuda.synchronize()
+            gr.replay()
+            torch.cuda.synchronize()
+            for (l, g, s), (l1, g1, s1) in zip(gouts, ref):
+                assert torch.equal(l, l1) and torch.equal(g, g1) and torch.equal(s, s1), (prec, rep)
+        del gr
 
 
 @pytest.mark.gpu
