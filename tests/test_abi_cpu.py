@@ -29,6 +29,15 @@ def lib():
     return _lib.load_library()
 
 
+def test_library_under_test(lib):
+    """Under tests/test_abi_asan.py this module runs against the ASan build
+    with the ASan runtime preloaded: check that both are mapped."""
+    if os.environ.get("COSIM_EXPECT_ASAN") != "1":
+        return
+    maps = open("/proc/self/maps").read()
+    assert "libcosim_asan.so" in maps and "libclang_rt.asan" in maps
+
+
 def test_exports_every_declared_symbol(lib):
     names = _declared()
     assert len(names) >= 14
