@@ -13,12 +13,15 @@
 // hold the currents of too few systems for G to be read only a few times,
 // this pair reads G once per column block of BN = 64 to 128 columns instead.
 //
-// A workgroup (8 waves, 4 x 2) computes a BM x BN tile over K in steps of 32:
+// A workgroup (WM x WN waves) computes a BM x BN tile over K in steps of 32:
 // the next step's operands are loaded from memory into registers while the
 // current step's are multiplied from LDS (two LDS buffers, one barrier per
-// step).  Each wave multiplies a (BM / 4) x (BN / 2) block with 16x16
+// step).  Each wave multiplies a (BM / WM) x (BN / WN) block with 16x16
 // matrix-core tiles: BF16X3 (hi hi + hi lo + lo hi into FP32), FP32 or FP64,
-// the same products as the fused kernel.
+// the same products as the fused kernel.  BF16X3 and FP32 use 128 x 128 tiles
+// of 4 waves, so that two workgroups share a compute unit and one's barrier
+// waits overlap the other's products; FP64 (bound by its matrix-core rate)
+// 128 x 64 tiles of 8 waves.
 #include <algorithm>
 
 #include "epilogue.h"
@@ -50,7 +53,7 @@ __device__ inline void split_pair(float a, float b, unsigned &hi, unsigned &lo) 
 // Operands of one 16x16 tile and one step of 32 K: 8 consecutive K per lane
 // (lane group q = lane / 16 holds K entries 8q..8q+7).
 struct GBF3 {
-    static constexpr int ESZ = 2, PLANES = 2, BM = 256, BN = 128;
+    static constexpr int ESZ = 2, PLANES = 2, BM = 128, BN = 128, WM = 2, WN = 2;
     typedef float Acc;
     typedef f32x4 V;
     struct Op {
@@ -70,7 +73,8 @@ struct GBF3 {
 template <typename T>
 struct GScalar {
     static constexpr int ESZ = sizeof(T), PLANES = 1;
-    static constexpr int BM = sizeof(T) == 4 ? 256 : 128, BN = sizeof(T) == 4 ? 128 : 64;
+    static constexpr int BM = 128, BN = sizeof(T) == 4 ? 128 : 64;
+    static constexpr int WM = sizeof(T) == 4 ? 2 : 4, WN = 2;
     typedef T Acc;
     typedef T V __attribute__((ext_vector_type(4)));
     struct Op {
@@ -113,23 +117,30 @@ constexpr int stage_bytes() {
 }
 
 // EPI 0: pass 1 (loss; w planes when a.W is set).  EPI 1: pass 2 (r partials).
+template <class Pol>
+constexpr int threads() {
+    return 64 * Pol::WM * Pol::WN;
+}
+
 template <class Pol, int EPI, int LOSS>
-__global__ __launch_bounds__(512) void k_gemm(GemmArgs a) {
+__global__ __launch_bounds__(threads<Pol>()) void k_gemm(GemmArgs a) {
     typedef typename Pol::Acc Acc;
     typedef typename Pol::V V;
     typedef typename Pol::Op Op;
     constexpr int BM = Pol::BM, BN = Pol::BN, ESZ = Pol::ESZ, PL = Pol::PLANES;
-    constexpr int TM = BM / 4, TN = BN / 2;  // wave block
+    constexpr int WM = Pol::WM, WN = Pol::WN, NT = threads<Pol>();
+    constexpr int TM = BM / WM, TN = BN / WN;  // wave block
     constexpr int TI = TM / 16, TJ = TN / 16;
     constexpr int RB = row_bytes<Pol>();
     constexpr int CPR = kBK * ESZ / 16;      // 16-byte pieces per row and plane
-    constexpr int NA = BM * CPR * PL / 512, NB = BN * CPR * PL / 512;  // pieces per thread
-    static_assert(BM * CPR * PL % 512 == 0 && BN * CPR * PL % 512 == 0, "whole pieces per thread");
+    constexpr int NA = BM * CPR * PL / NT, NB = BN * CPR * PL / NT;  // pieces per thread
+    static_assert(BM * CPR * PL % NT == 0 && BN * CPR * PL % NT == 0, "whole pieces per thread");
+    static_assert(TN % 32 == 0, "a wave holds whole column groups");
     extern __shared__ __attribute__((aligned(16))) char smem[];
 
     const int tid = (int)threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int wm = wave >> 1, wn = wave & 1;
+    const int wm = wave / WN, wn = wave - wm * WN;
     const int r16 = lane & 15, q = lane >> 4;
     // work item: column blocks fastest, so that the column blocks of one row
     // block (which share its A tile) run side by side on one XCD
@@ -146,7 +157,7 @@ __global__ __launch_bounds__(512) void k_gemm(GemmArgs a) {
     auto fetch = [&](int kb) {
 #pragma unroll
         for (int u = 0; u < NA; ++u) {
-            const int e = tid + 512 * u;
+            const int e = tid + NT * u;
             const int pl = e / (BM * CPR), rem = e - pl * (BM * CPR);
             const int r = rem / CPR, c = rem - r * CPR;
             const int gr = row0 + r;
@@ -156,7 +167,7 @@ __global__ __launch_bounds__(512) void k_gemm(GemmArgs a) {
         }
 #pragma unroll
         for (int u = 0; u < NB; ++u) {
-            const int e = tid + 512 * u;
+            const int e = tid + NT * u;
             const int pl = e / (BN * CPR), rem = e - pl * (BN * CPR);
             const int r = rem / CPR, c = rem - r * CPR;
             const char *src = (const char *)(pl ? a.Blo : a.B);
@@ -167,14 +178,14 @@ __global__ __launch_bounds__(512) void k_gemm(GemmArgs a) {
         char *sa = st, *sb = st + BM * RB * PL;
 #pragma unroll
         for (int u = 0; u < NA; ++u) {
-            const int e = tid + 512 * u;
+            const int e = tid + NT * u;
             const int pl = e / (BM * CPR), rem = e - pl * (BM * CPR);
             const int r = rem / CPR, c = rem - r * CPR;
             *(u32x4 *)(sa + (pl * BM + r) * RB + 16 * c) = ga[u];
         }
 #pragma unroll
         for (int u = 0; u < NB; ++u) {
-            const int e = tid + 512 * u;
+            const int e = tid + NT * u;
             const int pl = e / (BN * CPR), rem = e - pl * (BN * CPR);
             const int r = rem / CPR, c = rem - r * CPR;
             *(u32x4 *)(sb + (pl * BN + r) * RB + 16 * c) = gb[u];
@@ -275,13 +286,13 @@ __global__ __launch_bounds__(512) void k_gemm(GemmArgs a) {
             double v = lacc[g];
             v += __shfl_xor(v, 16);
             v += __shfl_xor(v, 32);
-            if (q == 0) red[((wn * NG + g) * 4 + wm) * 16 + r16] = v;
+            if (q == 0) red[((wn * NG + g) * WM + wm) * 16 + r16] = v;
         }
         __syncthreads();
-        for (int e = tid; e < 2 * NG * 16; e += 512) {
+        for (int e = tid; e < WN * NG * 16; e += NT) {
             const int c16 = e & 15, wg = e >> 4;  // wg = wn * NG + g
-            const double v = (red[(wg * 4 + 0) * 16 + c16] + red[(wg * 4 + 1) * 16 + c16]) +
-                             (red[(wg * 4 + 2) * 16 + c16] + red[(wg * 4 + 3) * 16 + c16]);
+            double v = 0.0;
+            for (int r = 0; r < WM; ++r) v += red[(wg * WM + r) * 16 + c16];  // row waves in order
             const int s = (col0 + 32 * wg) / 2 + c16;
             if (s < a.S) a.lpart[(size_t)bm * a.S + s] = v;
         }
@@ -336,7 +347,7 @@ hipError_t go(const GemmArgs &a, hipStream_t st) {
         (const void *)k_gemm<Pol, EPI, LOSS>, hipFuncAttributeMaxDynamicSharedMemorySize,
         2 * stage_bytes<Pol>());
     if (attr != hipSuccess) return attr;
-    hipLaunchKernelGGL((k_gemm<Pol, EPI, LOSS>), dim3(blocks), dim3(512), 2 * stage_bytes<Pol>(),
+    hipLaunchKernelGGL((k_gemm<Pol, EPI, LOSS>), dim3(blocks), dim3(threads<Pol>()), 2 * stage_bytes<Pol>(),
                        st, a);
     return hipGetLastError();
 }
