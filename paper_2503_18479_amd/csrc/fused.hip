@@ -273,12 +273,17 @@ __device__ __forceinline__ void bf3_load_I(const FusedArgs &a, int sys0, int r16
     for (int b = 0; b < NB; ++b) {
         const int s = sys0 + 16 * b + r16;
 #pragma unroll
-        for (int kk = 0; kk < NP / 32; ++kk)
+        for (int kk = 0; kk < NP / 32; ++kk) {
+            // the block's 8 loads first (clamped, in bounds), then the splits,
+            // so that the loads are in flight together
+            double2 raw[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                raw[j] = a.I[(size_t)min(s, a.S - 1) * a.n + min(32 * kk + 8 * q + j, a.n - 1)];
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 const int k = 32 * kk + 8 * q + j;
-                double2 v = make_double2(0.0, 0.0);
-                if (s < a.S && k < a.n) v = a.I[(size_t)s * a.n + k];
+                const double2 v = s < a.S && k < a.n ? raw[j] : make_double2(0.0, 0.0);
                 __bf16 h, l;
                 split2((float)v.x, h, l);
                 Ih[b][0][kk][j] = h;
@@ -287,6 +292,7 @@ __device__ __forceinline__ void bf3_load_I(const FusedArgs &a, int sys0, int r16
                 Ih[b][1][kk][j] = h;
                 Il[b][1][kk][j] = l;
             }
+        }
     }
 }
 
@@ -300,7 +306,11 @@ struct Bf3Stage {
     static constexpr int VPT = (NV + 255) / 256;
     static constexpr int LDR = NP + 8, LDT = PT + 8;
     u32x4 gh[VPT], gl[VPT], th[VPT], tl[VPT];
-    float t = 0.0f;
+    // the target as loaded, converted at the stash so that the fetch does
+    // not wait for its own loads; padded rows take |inc| (see k_fused)
+    double t = 0.0;
+    float tpad = 0.0f;
+    bool pad = true;
 
     __device__ __forceinline__ void fetch(const FusedArgs &a, int p0) {
         const uint16_t *__restrict__ Gh = (const uint16_t *)a.G;
@@ -323,7 +333,9 @@ struct Bf3Stage {
         // every thread holds the target of row threadIdx.x % PT, so that the
         // store below needs no branch (equal values to equal addresses)
         const int p = p0 + (int)(threadIdx.x & (PT - 1));
-        t = p < a.P ? (float)a.T[p] : (float)fabs(a.inc);  // padded rows: see k_fused
+        pad = p >= a.P;
+        tpad = (float)fabs(a.inc);
+        t = a.T[min(p, a.P - 1)];
     }
     __device__ __forceinline__ void stash(uint16_t *sH, uint16_t *sL, uint16_t *tH, uint16_t *tL,
                                           float *sT) const {
@@ -340,7 +352,7 @@ struct Bf3Stage {
                 *(u32x4 *)(tL + trow * LDT + tcol) = tl[u];
             }
         }
-        sT[threadIdx.x & (PT - 1)] = t;
+        sT[threadIdx.x & (PT - 1)] = pad ? tpad : (float)t;
     }
 };
 
@@ -428,31 +440,43 @@ __device__ __forceinline__ void bf3_epilogue(const float *__restrict__ sT, int r
 }
 
 // Adjoint: racc += G^T w over the 32 rows starting at column col0 of the
-// transposed LDS tile (row stride LDT).
-template <int NP, int NB, int LDT>
+// transposed LDS tile (row stride LDT).  BATCH blocks of 16 loops have their
+// operands read from LDS together, before their products (BATCH > 1 trades
+// registers for fewer exposed LDS latencies).
+template <int NP, int NB, int LDT, int BATCH = 1>
 __device__ __forceinline__ void bf3_adjoint(const uint16_t *__restrict__ ctH,
                                             const uint16_t *__restrict__ ctL, int col0, int r16,
                                             int q, const bf16x8 (&wrh)[NB],
                                             const bf16x8 (&wrl)[NB], const bf16x8 (&wih)[NB],
                                             const bf16x8 (&wil)[NB],
                                             f32x4 (&racc)[NP / 16][NB][2]) {
+    static_assert((NP / 16) % BATCH == 0, "whole batches of loop blocks");
 #pragma unroll
-    for (int ib = 0; ib < NP / 16; ++ib) {
-        // A operand: Gt[i = 16 ib + r16][p = pi(8q + j)]
-        const int base = (16 * ib + r16) * LDT + col0 + 4 * q;
-        const s16x4 h0 = *(const s16x4 *)(ctH + base), h1 = *(const s16x4 *)(ctH + base + 16);
-        const s16x4 l0 = *(const s16x4 *)(ctL + base), l1 = *(const s16x4 *)(ctL + base + 16);
-        const bf16x8 th = __builtin_bit_cast(bf16x8, __builtin_shufflevector(h0, h1, 0, 1, 2, 3, 4, 5, 6, 7));
-        const bf16x8 tl = __builtin_bit_cast(bf16x8, __builtin_shufflevector(l0, l1, 0, 1, 2, 3, 4, 5, 6, 7));
+    for (int ib0 = 0; ib0 < NP / 16; ib0 += BATCH) {
+        bf16x8 th[BATCH], tl[BATCH];
 #pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            racc[ib][b][0] = mma_bf16(tl, wrh[b], racc[ib][b][0]);
-            racc[ib][b][0] = mma_bf16(th, wrl[b], racc[ib][b][0]);
-            racc[ib][b][0] = mma_bf16(th, wrh[b], racc[ib][b][0]);
-            racc[ib][b][1] = mma_bf16(tl, wih[b], racc[ib][b][1]);
-            racc[ib][b][1] = mma_bf16(th, wil[b], racc[ib][b][1]);
-            racc[ib][b][1] = mma_bf16(th, wih[b], racc[ib][b][1]);
+        for (int u = 0; u < BATCH; ++u) {
+            // A operand: Gt[i = 16 ib + r16][p = pi(8q + j)]
+            const int base = (16 * (ib0 + u) + r16) * LDT + col0 + 4 * q;
+            const s16x4 h0 = *(const s16x4 *)(ctH + base), h1 = *(const s16x4 *)(ctH + base + 16);
+            const s16x4 l0 = *(const s16x4 *)(ctL + base), l1 = *(const s16x4 *)(ctL + base + 16);
+            th[u] = __builtin_bit_cast(bf16x8, __builtin_shufflevector(h0, h1, 0, 1, 2, 3, 4, 5, 6, 7));
+            tl[u] = __builtin_bit_cast(bf16x8, __builtin_shufflevector(l0, l1, 0, 1, 2, 3, 4, 5, 6, 7));
         }
+        if constexpr (BATCH > 1) __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < BATCH; ++u)
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const int ib = ib0 + u;
+                racc[ib][b][0] = mma_bf16(tl[u], wrh[b], racc[ib][b][0]);
+                racc[ib][b][0] = mma_bf16(th[u], wrl[b], racc[ib][b][0]);
+                racc[ib][b][0] = mma_bf16(th[u], wrh[b], racc[ib][b][0]);
+                racc[ib][b][1] = mma_bf16(tl[u], wih[b], racc[ib][b][1]);
+                racc[ib][b][1] = mma_bf16(th[u], wil[b], racc[ib][b][1]);
+                racc[ib][b][1] = mma_bf16(th[u], wih[b], racc[ib][b][1]);
+            }
+        if constexpr (BATCH > 1) __builtin_amdgcn_sched_barrier(0);
     }
 }
 
@@ -654,20 +678,257 @@ __global__ __launch_bounds__(256, 2) void k_fused_bf16x3_pipe(FusedArgs a) {
     bf3_store<NP, NB, GRAD>(a, chunk, sys0, r16, q, lacc, racc);
 }
 
+// Ping-pong form: eight waves in two groups of four, waves w and w + 4 on one
+// SIMD.  A wave cannot run its own vector work beside its own matrix-core
+// products, but the two waves of a SIMD can run side by side; so the work is
+// cut into phases separated by workgroup barriers, and in every phase one
+// group runs matrix-core work (the adjoint of sub-tile j - 1 and the forward
+// product of sub-tile j) while the other runs the vector epilogue of its
+// current sub-tile.  Group 1 runs one phase behind group 0 (OFF = 1), so
+// the two waves of a SIMD swap roles at every barrier; with OFF = 0 both
+// groups run in step (every wave of a SIMD in the same kind of phase), the
+// form to compare against.
+//   Tile t (32-row sub-tiles 2t and 2t + 1) sits in LDS buffer t & 1 and is
+// read in phases 4t .. 4t + 4 + OFF.  The rows of G for tile u >= 2 are
+// written to LDS by group 1 in phase 4u - 1 - OFF, those of G^T and the
+// targets by group 0 in phase 4u - 1: each in that group's vector phase,
+// after the last read of the tile the buffer held before and before the
+// barrier that opens phase 4u.  Each group fetches its share of a tile into
+// registers right after storing the previous one, four phases ahead.
+// Barriers wait for LDS traffic only, so global loads stay in flight across
+// them.
+template <int NP, int PT, bool GRAD>
+struct PpStage {
+    static constexpr int NV = PT * NP / 8;  // 16-byte vectors per plane
+    static constexpr int VPT = (NV + 255) / 256;
+    static constexpr int LDR = NP + 8, LDT = PT + 8;
+    u32x4 h[VPT], l[VPT];
+    double t = 0.0;  // target as loaded (see Bf3Stage)
+    float tpad = 0.0f;
+    bool pad = true;
+
+    // group 1: rows of G; group 0: columns of G^T and the targets
+    __device__ __forceinline__ void fetch(const FusedArgs &a, int p0, int grp, int gtid) {
+#pragma unroll
+        for (int u = 0; u < VPT; ++u) {
+            const int e0 = (gtid + 256 * u) * 8;
+            if (NV % 256 != 0 && e0 >= 8 * NV) continue;
+            if (grp) {
+                const int row = e0 / NP, col = e0 - row * NP;
+                const size_t go = (size_t)(p0 + row) * NP + col;
+                h[u] = *(const u32x4 *)((const uint16_t *)a.G + go);
+                l[u] = *(const u32x4 *)((const uint16_t *)a.Glo + go);
+            } else if (GRAD) {
+                const int trow = e0 / PT, tcol = e0 - trow * PT;
+                const size_t to = (size_t)trow * a.P_pad + p0 + tcol;
+                h[u] = *(const u32x4 *)(a.GThi + to);
+                l[u] = *(const u32x4 *)(a.GTlo + to);
+            }
+        }
+        if (!grp) {
+            const int p = p0 + (gtid & (PT - 1));
+            pad = p >= a.P;
+            tpad = (float)fabs(a.inc);
+            t = a.T[min(p, a.P - 1)];
+        }
+    }
+    __device__ __forceinline__ void stash(uint16_t *sH, uint16_t *sL, uint16_t *tH, uint16_t *tL,
+                                          float *sT, int grp, int gtid) const {
+#pragma unroll
+        for (int u = 0; u < VPT; ++u) {
+            const int e0 = (gtid + 256 * u) * 8;
+            if (NV % 256 != 0 && e0 >= 8 * NV) continue;
+            if (grp) {
+                const int row = e0 / NP, col = e0 - row * NP;
+                *(u32x4 *)(sH + row * LDR + col) = h[u];
+                *(u32x4 *)(sL + row * LDR + col) = l[u];
+            } else if (GRAD) {
+                const int trow = e0 / PT, tcol = e0 - trow * PT;
+                *(u32x4 *)(tH + trow * LDT + tcol) = h[u];
+                *(u32x4 *)(tL + trow * LDT + tcol) = l[u];
+            }
+        }
+        if (!grp) sT[gtid & (PT - 1)] = pad ? tpad : (float)t;
+    }
+};
+
+// Barrier that waits for the wave's LDS operations only (global loads issued
+// before it stay in flight).  The scheduling barriers keep the compiler from
+// moving any instruction across it, so that each phase's matrix-core and
+// vector work stays in its phase.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+// An empty use of a register value: the value has to be computed before
+// this point, which keeps the compiler from sinking a phase's arithmetic past
+// the barrier that ends the phase (scheduling barriers act inside one basic
+// block only).
+template <typename T>
+__device__ __forceinline__ void keep(const T &v) {
+    asm volatile("" ::"v"(v));
+}
+
+template <int NP, int NB, int OFF, int LOSS, bool GRAD>
+__global__ __launch_bounds__(512, 1) void k_fused_bf16x3_pp(FusedArgs a) {
+    static_assert(NP % 32 == 0, "bf16x3 path needs NP multiple of 32");
+    constexpr int PT = 64, SPT = 2;  // tile rows, 32-row sub-tiles per tile
+    static_assert(kPTile % PT == 0, "tile rows must divide the 64-row padding of G");
+    constexpr int IB = NP / 16;
+    constexpr int LDR = NP + 8, LDT = PT + 8;
+    constexpr int TSZ = PT * LDR, TTSZ = GRAD ? NP * LDT : 8;
+    __shared__ __attribute__((aligned(16))) uint16_t sH[2][TSZ];
+    __shared__ __attribute__((aligned(16))) uint16_t sL[2][TSZ];
+    __shared__ __attribute__((aligned(16))) uint16_t tH[2][TTSZ];
+    __shared__ __attribute__((aligned(16))) uint16_t tL[2][TTSZ];
+    __shared__ __attribute__((aligned(16))) float sTg[2][PT];
+
+    const int tid = (int)threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int grp = wave >> 2, gtid = tid & 255;
+    const int sgrp = OFF ? grp : 0;  // phase lag of the group
+    const int r16 = lane & 15, q = lane >> 4;
+    const int sys0 = (blockIdx.x * 8 + wave) * (16 * NB);
+    const int chunk = blockIdx.y;
+    const int pb = chunk * a.rows_per_chunk;
+    const int pe = min(a.P_pad, pb + a.rows_per_chunk);
+    const int ntile = pe > pb ? (pe - pb) / PT : 0;
+    const int nsub = ntile * SPT;
+
+    bf16x8 Ih[NB][2][NP / 32], Il[NB][2][NP / 32];
+    bf3_load_I<NP, NB>(a, sys0, r16, q, Ih, Il);
+    f32x4 racc[IB][NB][2];
+#pragma unroll
+    for (int ib = 0; ib < IB; ++ib)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) racc[ib][b][0] = racc[ib][b][1] = f32x4{};
+    double lacc[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) lacc[b] = 0.0;
+
+    PpStage<NP, PT, GRAD> stg;
+    for (int u = 0; u < min(ntile, 2); ++u) {
+        stg.fetch(a, pb + u * PT, grp, gtid);
+        stg.stash(sH[u], sL[u], tH[u], tL[u], sTg[u], grp, gtid);
+    }
+    __syncthreads();
+
+    // Every wave runs (matrix-core phase j; barrier; vector phase j;
+    // barrier) for j = 0 .. nsub; with OFF, group 1 enters one barrier late
+    // and group 0 leaves one barrier late, so both pass the same barriers and
+    // the global phase of a group's local phase k is k + sgrp (its lag).  The
+    // first and last matrix-core phases are peeled, so that in the others the
+    // adjoint of sub-tile j - 1 and the forward product of sub-tile j sit in
+    // one block.
+    f32x4 br[2][NB], bi[2][NB];
+    bf16x8 wrh[NB], wrl[NB], wih[NB], wil[NB];
+    auto adjoint = [&](int jj) {
+        const int bf = (jj / SPT) & 1;
+        bf3_adjoint<NP, NB, LDT, 2>(tH[bf], tL[bf], 32 * (jj % SPT), r16, q, wrh, wrl, wih, wil,
+                                    racc);
+    };
+    auto forward = [&](int j) {
+        const int bf = (j / SPT) & 1;
+        bf3_forward<NP, NB>(sH[bf], sL[bf], 32 * (j % SPT), r16, q, Ih, Il, br, bi);
+    };
+    // Vector phase j (global phase 2j + 1 + sgrp): in every other one, those
+    // with j + sgrp odd, the group stores its share of tile u = (j + 1 +
+    // sgrp) / 2 in LDS (fetched four phases earlier) and then fetches its
+    // share of tile u + 1 into the same registers (the scheduling barrier
+    // keeps the loads after the stores, so that the registers are reused in
+    // place rather than copied, a copy waiting for the loads); then the
+    // epilogue of sub-tile j.
+    auto vector_phase = [&](int j) {
+        if ((j + sgrp) & 1) {
+            const int u = (j + 1 + sgrp) >> 1;
+            if (u >= 2 && u < ntile)
+                stg.stash(sH[u & 1], sL[u & 1], tH[u & 1], tL[u & 1], sTg[u & 1], grp, gtid);
+            __builtin_amdgcn_sched_barrier(0);
+            if (u + 1 >= 2 && u + 1 < ntile) stg.fetch(a, pb + (u + 1) * PT, grp, gtid);
+        }
+        if (j < nsub) {
+            const int bf = (j / SPT) & 1;
+            bf3_epilogue<NB, LOSS>(sTg[bf], 32 * (j % SPT), q, br, bi, wrh, wrl, wih, wil, lacc,
+                                   (float)a.inc);
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                keep(wrh[b]);
+                keep(wrl[b]);
+                keep(wih[b]);
+                keep(wil[b]);
+                keep(lacc[b]);
+            }
+
+        }
+    };
+    auto keep_forward = [&]() {
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                keep(br[h][b]);
+                keep(bi[h][b]);
+            }
+    };
+    auto keep_adjoint = [&]() {
+#pragma unroll
+        for (int ib = 0; ib < IB; ++ib)
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                keep(racc[ib][b][0]);
+                keep(racc[ib][b][1]);
+            }
+    };
+    if (OFF && grp) lds_barrier();
+    if (nsub > 0) {
+        forward(0);
+        keep_forward();
+        lds_barrier();
+        vector_phase(0);
+        lds_barrier();
+#pragma unroll 1
+        for (int j = 1; j < nsub; ++j) {
+            if (GRAD) adjoint(j - 1);
+            forward(j);
+            if (GRAD) keep_adjoint();
+            keep_forward();
+            lds_barrier();
+            vector_phase(j);
+            lds_barrier();
+        }
+        if (GRAD) {
+            adjoint(nsub - 1);
+            keep_adjoint();
+        }
+    }
+    lds_barrier();
+    vector_phase(nsub);  // staging only: nothing is left to reduce
+    lds_barrier();
+    if (OFF && !grp) lds_barrier();
+    bf3_store<NP, NB, GRAD>(a, chunk, sys0, r16, q, lacc, racc);
+}
+
 // Tuning variants of the fused kernels: systems per wave (16 * NB), rows per
 // LDS tile (PT) and, for BF16X3, single or double LDS buffering.  Variant 0 is
 // the default; cosim_plan_autotune picks per plan and precision.
 struct Variant {
     int nb, pt;
     bool db;
-    int pipe;  // 0: sub-tile by sub-tile, 1: look-ahead forward of the next sub-tile
+    int pipe;  // 0: sub-tile by sub-tile, 1: look-ahead forward of the next sub-tile,
+               // 2: ping-pong of two wave groups (eight waves, 32 NB systems per SIMD pair),
+               // 3: the same eight-wave kernel with both groups in step
 };
 constexpr Variant kVarF64[] = {{1, 64, false, 0}, {2, 64, false, 0}};
 constexpr Variant kVarF32[] = {{2, 64, false, 0}, {1, 64, false, 0}};
 constexpr Variant kVarBF16[] = {{2, 64, false, 0}, {2, 32, false, 0}, {1, 64, false, 0},
                                 {1, 32, false, 0}, {2, 64, true, 0},  {2, 32, true, 0},
                                 {1, 64, true, 1},  {1, 32, true, 1},  {2, 32, true, 1},
-                                {2, 64, true, 1}};
+                                {2, 64, true, 1}, {2, 64, true, 2}, {1, 64, true, 2},
+                                {2, 64, true, 3}};
 // the group kernels hard-wire variant 0 of each precision
 static_assert(kVarF64[0].nb == 1 && kVarF32[0].nb == 2 && kVarBF16[0].nb == 2 &&
                   kVarBF16[0].pt == 64 && !kVarBF16[0].db && kVarBF16[0].pipe == 0,
@@ -676,8 +937,8 @@ static_assert(kVarF64[0].nb == 1 && kVarF32[0].nb == 2 && kVarBF16[0].nb == 2 &&
 // With `occ` set, the resident-workgroup count per compute unit of the
 // kernel is written there and nothing is launched.
 template <typename K>
-hipError_t occupancy_of(K kernel, int *occ) {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, kernel, 256, 0);
+hipError_t occupancy_of(K kernel, int *occ, int threads = 256) {
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, kernel, threads, 0);
 }
 
 template <typename T, int NP, int NB, int LOSS, bool GRAD>
@@ -692,12 +953,15 @@ hipError_t go_typed(const FusedArgs &a, hipStream_t st, int *occ) {
 template <int NP, int NB, int PT, bool DB, int PIPE, int LOSS, bool GRAD>
 hipError_t go_bf16(const FusedArgs &a, hipStream_t st, int *occ) {
     if (occ) {
-        if constexpr (PIPE == 1) return occupancy_of(k_fused_bf16x3_pipe<NP, NB, PT, LOSS, GRAD>, occ);
+        if constexpr (PIPE >= 2) return occupancy_of(k_fused_bf16x3_pp<NP, NB, PIPE == 2, LOSS, GRAD>, occ, 512);
+        else if constexpr (PIPE == 1) return occupancy_of(k_fused_bf16x3_pipe<NP, NB, PT, LOSS, GRAD>, occ);
         else return occupancy_of(k_fused_bf16x3<NP, NB, PT, DB, LOSS, GRAD>, occ);
     }
-    const int per_block = 4 * 16 * NB;
+    const int per_block = (PIPE >= 2 ? 8 : 4) * 16 * NB;
     dim3 grid((a.S + per_block - 1) / per_block, a.nchunk);
-    if constexpr (PIPE == 1)
+    if constexpr (PIPE >= 2)
+        hipLaunchKernelGGL((k_fused_bf16x3_pp<NP, NB, PIPE == 2, LOSS, GRAD>), grid, dim3(512), 0, st, a);
+    else if constexpr (PIPE == 1)
         hipLaunchKernelGGL((k_fused_bf16x3_pipe<NP, NB, PT, LOSS, GRAD>), grid, dim3(256), 0, st, a);
     else
         hipLaunchKernelGGL((k_fused_bf16x3<NP, NB, PT, DB, LOSS, GRAD>), grid, dim3(256), 0, st, a);
@@ -736,6 +1000,9 @@ hipError_t go_np(Prec prec, int variant, const FusedArgs &a, hipStream_t st, int
                     COSIM_BF16_CASE(7)
                     COSIM_BF16_CASE(8)
                     COSIM_BF16_CASE(9)
+                    COSIM_BF16_CASE(10)
+                    COSIM_BF16_CASE(11)
+                    COSIM_BF16_CASE(12)
 #undef COSIM_BF16_CASE
                 }
             }
@@ -770,7 +1037,7 @@ int fused_systems_per_block(Prec prec, int NP, int variant) {
     switch (prec) {
         case Prec::F64: return 64 * kVarF64[variant].nb;
         case Prec::F32: return 64 * kVarF32[variant].nb;
-        case Prec::BF16X3: return 64 * kVarBF16[variant].nb;
+        case Prec::BF16X3: return (kVarBF16[variant].pipe >= 2 ? 128 : 64) * kVarBF16[variant].nb;
     }
     return 64;
 }

@@ -369,6 +369,36 @@ def test_every_fused_variant_matches_oracle(dev, prec):
         c.plan.set_variant(prec, 0)
 
 
+def test_every_fused_variant_multi_tile_chunks(dev):
+    """A batch large enough for the fused kernels' P-chunks to hold several
+    64-row tiles (at small batches every tile is a chunk of its own): 8x8
+    array at 1,600 points (25 tiles, split into one chunk or into chunks of
+    13 and 12 tiles depending on the variant's workgroup size), batch 8,191
+    x 4 frequencies (32,764 systems, the last system block ragged).  Every
+    variant in every precision against the oracle on sampled configurations,
+    among them both sides of the variants' system-block boundaries and the
+    last configuration."""
+    wl = W.small_array(8, 8, batch=8191, grid=40, n_freq=4, seed=9)
+    c = Case(wl, dev)
+    cfg = [0, 1, 7, 8, 31, 32, 63, 64, 2047, 4096, 8189, 8190]
+    Lr = O.evaluate(c.G, c.M, wl.geom.R, c.Phi, wl.C[cfg], wl.omega, wl.target)[2]
+    gr = O.grad_adjoint(c.G, c.M, wl.geom.R, c.Phi, wl.C[cfg], wl.omega, wl.target)
+    for prec in (0, 1, 2):
+        _, nv = c.plan.variants(prec)
+        try:
+            for v in range(nv):
+                _say(f"[variant, multi-tile chunks] prec={prec} variant={v}")
+                c.plan.set_variant(prec, v)
+                loss, grad, st = c.plan.loss_and_grad(c.C, c.om, c.T, precision=prec)
+                assert int(st.abs().sum()) == 0
+                l = loss.cpu().numpy()[cfg]
+                g = grad.cpu().numpy()[cfg]
+                assert np.max(np.abs(l - Lr) / Lr) < TOL[prec], (prec, v)
+                assert _nrel(g, gr, axis=1).max() < TOL[prec], (prec, v)
+        finally:
+            c.plan.set_variant(prec, 0)
+
+
 def test_autotune_picks_a_variant(dev):
     c = _case("n64")
     chosen, ms = c.plan.autotune(c.C, c.om, c.T, precision=2, reps=1)
