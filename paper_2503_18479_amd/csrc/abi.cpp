@@ -1417,12 +1417,38 @@ static int enqueue_big_group(const ManyCall &mc, const std::vector<int> &g, int 
         hipEventRecord(ev_fwd, gs) != hipSuccess) {
         return fail(COSIM_EDEVICE, "grouped solve launch failed");
     }
+    // Contractions: the members on the matrix-core kernel path in one launch
+    // on the group's stream, after its forward solve; members with enough
+    // systems for the GEMM passes each on a side stream, joined by events.
+    MfmaGroup mg;
+    int mblocks = 0, mwaves = 0;
     for (size_t m = 0; m < g.size() && first_rc == COSIM_OK; ++m) {
         const int i = g[m];
         cosim_plan *p = plans[i];
+        const int S = B[i] * F[i];
+        const double *Ti = Teff[m];
+        if (!gemm_path(prec, p->NP, S)) {
+            if (ratio) {
+                if (launch_scale((size_t)p->P, std::fabs(p->bext_z), T_d[i], p->T_ratio, gs) !=
+                    hipSuccess) {
+                    first_rc = fail_instance(fail(COSIM_EDEVICE, "target scaling failed"), i);
+                    break;
+                }
+                Ti = p->T_ratio;
+            }
+            const MfmaShape sh = mfma_shape(prec, p->NP, S, p->P_pad, p->cus);
+            MfmaArgs a = mfma_args(p, prec, S, sh);
+            a.I = p->I_ws;
+            a.T = Ti;
+            a.inc = ratio ? p->bext_z : 0.0;
+            mg.first[mg.count] = mblocks;
+            mg.in[mg.count++] = a;
+            mblocks += (sh.nchunk * sh.nsb + 7) / 8 * 8;
+            mwaves = sh.waves;  // a function of the padded loop count, shared by the group
+            continue;
+        }
         hipStream_t cs = pool->streams[(k + 1 + m) % ns];
         hipEvent_t ev_c = pool->extra[next_ev++];
-        const double *Ti = Teff[m];
         bool ok = hipStreamWaitEvent(cs, ev_fwd, 0) == hipSuccess;
         if (ok && ratio) {
             ok = launch_scale((size_t)p->P, std::fabs(p->bext_z), T_d[i], p->T_ratio, cs) ==
@@ -1430,11 +1456,14 @@ static int enqueue_big_group(const ManyCall &mc, const std::vector<int> &g, int 
             Ti = p->T_ratio;
         }
         ok = ok &&
-             big_contract(p, prec, loss_mode, grad, B[i] * F[i], p->I_ws, Ti,
-                          ratio ? p->bext_z : 0.0, cs) == hipSuccess &&
+             big_contract(p, prec, loss_mode, grad, S, p->I_ws, Ti, ratio ? p->bext_z : 0.0, cs) ==
+                 hipSuccess &&
              hipEventRecord(ev_c, cs) == hipSuccess && hipStreamWaitEvent(gs, ev_c, 0) == hipSuccess;
         if (!ok) first_rc = fail_instance(fail(COSIM_EDEVICE, "contraction launch failed"), i);
     }
+    if (first_rc == COSIM_OK && mg.count > 0 &&
+        launch_mfma_group(prec, grad, loss_mode, mg, mblocks, mwaves, gs) != hipSuccess)
+        first_rc = fail(COSIM_EDEVICE, "grouped contraction launch failed");
     if (first_rc != COSIM_OK) return first_rc;
     if (grad &&
         big_group_solve(ga, NP, Sg, A, piv, kRhsPairs, gs) != hipSuccess) {

@@ -186,8 +186,9 @@ constexpr size_t lds_bytes(int W) {
     return main > fin ? main : fin;
 }
 
+// The work of workgroup b of a launch for one set of arguments.
 template <class Pol, int MODE, int LOSS>
-__global__ __launch_bounds__(512) void k_mfma(MfmaArgs a) {
+__device__ __forceinline__ void mfma_block(const MfmaArgs &a, int b) {
     typedef typename Pol::Acc Acc;
     typedef typename Pol::V V;
     typedef typename Pol::Op Op;
@@ -204,7 +205,7 @@ __global__ __launch_bounds__(512) void k_mfma(MfmaArgs a) {
     const int r16 = lane & 15, q = lane >> 4;
     // (chunk, system block) of this workgroup: with the grid a multiple of 8,
     // consecutive work items go to one XCD (workgroup b runs on XCD b % 8)
-    const int N = a.nchunk * a.nsb, b = (int)blockIdx.x;
+    const int N = a.nchunk * a.nsb;
     const int item = (N & 7) == 0 ? (b & 7) * (N >> 3) + (b >> 3) : b;
     const int chunk = item / a.nsb, sb = item - chunk * a.nsb;
     const int s0 = sb * NS;
@@ -391,6 +392,32 @@ __global__ __launch_bounds__(512) void k_mfma(MfmaArgs a) {
 }
 
 template <class Pol, int MODE, int LOSS>
+__global__ __launch_bounds__(512) void k_mfma(MfmaArgs a) {
+    mfma_block<Pol, MODE, LOSS>(a, (int)blockIdx.x);
+}
+
+// Several plans of one padded loop count in one launch: member m owns the
+// workgroups [first[m], first[m + 1]) (the last up to the launch's total);
+// first[m] is a multiple of 8, so that the member's XCD-aware order holds,
+// and the workgroups past its own count exit at once.
+template <class Pol, int MODE, int LOSS>
+__global__ __launch_bounds__(512) void k_mfma_group(MfmaGroup g) {
+    const int b = (int)blockIdx.x;
+    int m = 0;
+    while (m + 1 < g.count && b >= g.first[m + 1]) ++m;
+    const int loc = b - g.first[m];
+    if (loc >= g.in[m].nchunk * g.in[m].nsb) return;
+    mfma_block<Pol, MODE, LOSS>(g.in[m], loc);
+}
+
+template <class Pol, int MODE, int LOSS>
+hipError_t go_group(const MfmaGroup &g, int blocks, int W, hipStream_t st) {
+    hipLaunchKernelGGL((k_mfma_group<Pol, MODE, LOSS>), dim3((unsigned)blocks), dim3(64 * W),
+                       lds_bytes<Pol>(W), st, g);
+    return hipGetLastError();
+}
+
+template <class Pol, int MODE, int LOSS>
 hipError_t go(const MfmaArgs &a, int W, hipStream_t st) {
     const size_t lds = lds_bytes<Pol>(W);
     const unsigned blocks = (unsigned)a.nchunk * (unsigned)a.nsb;
@@ -440,6 +467,39 @@ MfmaShape mfma_shape(Prec prec, int NP, int S, int P_pad, int cus) {
     sh.rows_per_chunk = per * kSub;
     sh.nchunk = (subs + per - 1) / per;
     return sh;
+}
+
+hipError_t launch_mfma_group(Prec prec, bool grad, int loss_mode, const MfmaGroup &g, int blocks,
+                             int waves, hipStream_t st) {
+    if (blocks <= 0 || g.count <= 0) return hipSuccess;
+    if (g.count > kGroupMax || waves < 1 || waves > 8) return hipErrorInvalidValue;
+    for (int m = 0; m < g.count; ++m) {
+        const MfmaArgs &a = g.in[m];
+        if (a.NP % 32 != 0 || a.NP / 32 > kMaxKs * waves || a.P_pad % kSub != 0 ||
+            a.rows_per_chunk % kSub != 0 || g.first[m] % 8 != 0 ||
+            (m + 1 < g.count ? g.first[m + 1] : blocks) - g.first[m] < a.nchunk * a.nsb)
+            return hipErrorInvalidValue;
+    }
+#define COSIM_MFMA_GROUP(POL)                                                                   \
+    switch (loss_mode) {                                                                        \
+        case COSIM_LOSS_MAG:                                                                    \
+            return grad ? go_group<POL, kMfmaLossGrad, COSIM_LOSS_MAG>(g, blocks, waves, st)    \
+                        : go_group<POL, kMfmaLoss, COSIM_LOSS_MAG>(g, blocks, waves, st);       \
+        case COSIM_LOSS_COMPLEX:                                                                \
+            return grad ? go_group<POL, kMfmaLossGrad, COSIM_LOSS_COMPLEX>(g, blocks, waves, st) \
+                        : go_group<POL, kMfmaLoss, COSIM_LOSS_COMPLEX>(g, blocks, waves, st);   \
+        case COSIM_LOSS_RATIO:                                                                  \
+            return grad ? go_group<POL, kMfmaLossGrad, COSIM_LOSS_RATIO>(g, blocks, waves, st)  \
+                        : go_group<POL, kMfmaLoss, COSIM_LOSS_RATIO>(g, blocks, waves, st);     \
+    }                                                                                           \
+    return hipErrorInvalidValue;
+    switch (prec) {
+        case Prec::BF16X3: COSIM_MFMA_GROUP(PolBF3)
+        case Prec::F32: COSIM_MFMA_GROUP(PolF32)
+        case Prec::F64: COSIM_MFMA_GROUP(PolF64)
+    }
+#undef COSIM_MFMA_GROUP
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_mfma(Prec prec, int mode, int loss_mode, const MfmaArgs &a, int waves,

@@ -308,6 +308,18 @@ int mfma_systems_per_block(Prec prec);
 MfmaShape mfma_shape(Prec prec, int NP, int S, int P_pad, int cus);
 hipError_t launch_mfma(Prec prec, int mode, int loss_mode, const MfmaArgs &a, int waves,
                        hipStream_t st);
+// The loss (and gradient) contraction of several plans of one padded loop
+// count in one launch (cosim_loss_and_grad_many): member m owns the
+// workgroups [first[m], first[m + 1]), first[m] a multiple of 8 and the range
+// at least its nchunk * nsb; all members launch with `waves` waves.
+struct MfmaGroup {
+    int count = 0;
+    int first[kGroupMax] = {};
+    MfmaArgs in[kGroupMax];
+};
+static_assert(sizeof(MfmaGroup) <= 4096, "kernel arguments are limited to 4 KB");
+hipError_t launch_mfma_group(Prec prec, bool grad, int loss_mode, const MfmaGroup &g, int blocks,
+                             int waves, hipStream_t st);
 
 // ---- large batches above 64 loops: two GEMM passes (gemm_big.hip)
 // One pass: C (M x N) = A B^T with A [M][lda] and B [N][ldb] K-contiguous.
