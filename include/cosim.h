@@ -199,10 +199,11 @@ int cosim_plan_set_drive(cosim_plan_t p, int nport, const int32_t *loop, const d
  *   max_iter 1..64; tol in [0, 1): 0 chooses it from the precision of the
  *   call's contraction (FP64 1e-12, FP32 1e-9, BF16X3 1e-7; cosim_solve and
  *   cosim_field_backward 1e-12).
- * Changing the mode frees the plan's workspace (the next call allocates an
- * extra 8 NP^2 bytes per system for the FP32 factor); it waits for the device
- * first.  HIP graphs captured before hold the freed addresses and must be
- * captured again.  Errors: COSIM_EINVAL. */
+ * Changing the mode keeps the plan's workspace: enabling adds 8 NP^2 bytes
+ * per reserved system for the FP32 factor at the next call that needs them
+ * (or at cosim_plan_reserve), beside the buffers already there, so HIP graphs
+ * captured before stay valid and replay the mode they were captured in.  The
+ * call itself enqueues and allocates nothing.  Errors: COSIM_EINVAL. */
 int cosim_plan_set_refinement(cosim_plan_t p, int enable, int max_iter, double tol);
 
 /* --------------------------------------------------------------------------

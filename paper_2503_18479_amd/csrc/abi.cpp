@@ -166,9 +166,22 @@ int ensure_workspace(cosim_plan *p, size_t systems, int chunks, size_t parts = 0
     const size_t gneed = big_plan(p->NP) && gemm_path(Prec::F64, p->NP, (int)systems)
                              ? gemm_ws_bytes(p->NP, (int)systems, p->P_pad)
                              : 0;
+    const bool need32 = big_plan(p->NP) && p->ldl_ok && p->refine;
     if (systems <= p->cap_systems && parts <= p->cap_parts && lparts <= p->cap_lparts &&
-        gneed <= p->cap_gws)
+        gneed <= p->cap_gws) {
+        if (need32 && !p->bA32) {
+            // the FP32 factor slots alone, beside the workspace (nothing else
+            // moves, so buffers that captured graphs use stay where they are)
+            const size_t NP = (size_t)p->NP;
+            if (hipMalloc(&p->bA32, p->cap_systems * NP * NP * sizeof(float2)) != hipSuccess) {
+                p->bA32 = nullptr;
+                (void)hipGetLastError();
+                return fail(COSIM_ENOMEM, "FP32 factor workspace for %zu systems failed",
+                            p->cap_systems);
+            }
+        }
         return COSIM_OK;
+    }
     const size_t ns = std::max(systems, p->cap_systems);
     const size_t np_parts = std::max(parts, p->cap_parts);
     const size_t nl_parts = std::max(lparts, p->cap_lparts);
@@ -184,8 +197,7 @@ int ensure_workspace(cosim_plan *p, size_t systems, int chunks, size_t parts = 0
         (void)hipGetLastError();
         return fail(COSIM_ENOMEM, "LDL^T panel workspace for %zu systems failed", ns);
     }
-    if (big && p->ldl_ok && p->refine &&
-        hipMalloc(&p->bA32, ns * NP * NP * sizeof(float2)) != hipSuccess) {
+    if (need32 && hipMalloc(&p->bA32, ns * NP * NP * sizeof(float2)) != hipSuccess) {
         plan_free_workspace(p);
         (void)hipGetLastError();
         return fail(COSIM_ENOMEM, "FP32 factor workspace for %zu systems failed", ns);
@@ -776,11 +788,9 @@ int cosim_plan_set_refinement(cosim_plan_t p, int enable, int max_iter, double t
         return fail(COSIM_EINVAL, "tol must be in [0, 1) (0: chosen per precision)");
     int rc;
     if ((rc = check_device(p))) return rc;
+    // The workspace is kept: the next call adds the FP32 factor slots if the
+    // mode needs them and they are missing, and moves nothing else.
     const bool on = enable != 0;
-    if (on != p->refine) {
-        HIP_TRY(hipDeviceSynchronize());  // no call of this plan may still use the workspace
-        plan_free_workspace(p);           // the next call allocates what the mode needs
-    }
     p->refine = on;
     p->refine_iter = on ? max_iter : 0;
     p->refine_tol = on ? tol : 0.0;

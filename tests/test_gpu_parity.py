@@ -1103,6 +1103,52 @@ def test_refined_small_pivot_falls_back(dev):
     assert np.max(_nrel(grad.cpu().numpy(), gr, axis=1)) < 1e-9
 
 
+def test_refinement_switch_keeps_captured_graphs_valid(dev):
+    """cosim_plan_set_refinement keeps the workspace: a graph of
+    cosim_loss_and_grad captured with the FP64 factor (81 loops) replays,
+    after switching refinement on and running eager calls in that mode (the
+    FP32 factor slots are added then), to the FP64-factor results bit for
+    bit, and again after switching back; the refined calls match the oracle."""
+    c = _case("n81")
+    plan = c.plan
+    plan.set_refinement(False)
+    plan.reserve(c.C.shape[0], c.om.shape[0])
+    loss = torch.empty((c.C.shape[0],), dtype=torch.float64, device=dev)
+    grad = torch.empty_like(c.C)
+    st = torch.empty((c.C.shape[0], c.om.shape[0]), dtype=torch.int32, device=dev)
+    out = (loss, grad, st)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        plan.loss_and_grad(c.C, c.om, c.T, precision=2, out=out)  # warm-up outside the capture
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=side):
+        plan.loss_and_grad(c.C, c.om, c.T, precision=2, out=out)
+    torch.cuda.synchronize()
+    ref = plan.loss_and_grad(c.C, c.om, c.T, precision=2)
+    torch.cuda.synchronize()
+    Lr = c.oracle_eval()[2]
+    gr = c.oracle_grad()
+    try:
+        for refine in (True, False):
+            plan.set_refinement(refine)
+            l1, g1, s1 = plan.loss_and_grad(c.C, c.om, c.T, precision=2)
+            torch.cuda.synchronize()
+            assert int(s1.abs().sum()) == 0
+            assert np.max(np.abs(l1.cpu().numpy() - Lr) / Lr) < TOL[2]
+            assert _nrel(g1.cpu().numpy(), gr, axis=1).max() < TOL[2]
+            loss.zero_(); grad.zero_(); st.fill_(-1)
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            assert torch.equal(loss, ref[0]) and torch.equal(grad, ref[1]) and torch.equal(st, ref[2]), refine
+    finally:
+        plan.set_refinement(False)
+        del g
+
+
 def test_refined_1024_loops(dev):
     """The 32x32 array's 1,024 loops (16 panels) with refinement, few
     configurations and points: currents, loss and dL/dC against the oracle."""
