@@ -14,9 +14,9 @@
 // this pair reads G once per column block of BN = 64 to 128 columns instead.
 //
 // A workgroup (WM x WN waves) computes a BM x BN tile over K in steps of 32:
-// the next step's operands are loaded from memory into registers while the
-// current step's are multiplied from LDS (two LDS buffers, one barrier per
-// step).  Each wave multiplies a (BM / WM) x (BN / WN) block with 16x16
+// each step's operands are loaded from memory into registers two steps ahead
+// and stored to LDS while the step before is multiplied (two LDS buffers, two
+// register sets, one barrier per step).  Each wave multiplies a (BM / WM) x (BN / WN) block with 16x16
 // matrix-core tiles: BF16X3 (hi hi + hi lo + lo hi into FP32), FP32 or FP64,
 // the same products as the fused kernel.  BF16X3 and FP32 use 128 x 128 tiles
 // of 4 waves, so that two workgroups share a compute unit and one's barrier
@@ -123,7 +123,7 @@ constexpr int threads() {
 }
 
 template <class Pol, int EPI, int LOSS>
-__global__ __launch_bounds__(threads<Pol>()) void k_gemm(GemmArgs a) {
+__global__ __launch_bounds__(threads<Pol>(), 2) void k_gemm(GemmArgs a) {
     typedef typename Pol::Acc Acc;
     typedef typename Pol::V V;
     typedef typename Pol::Op Op;
@@ -152,18 +152,19 @@ __global__ __launch_bounds__(threads<Pol>()) void k_gemm(GemmArgs a) {
     const int k0 = kc * a.kchunk, k1 = min(a.K, k0 + a.kchunk);
     const int nsteps = (k1 - k0) / kBK;
 
-    // global -> registers -> LDS staging of one step
-    u32x4 ga[NA], gb[NB];
-    auto fetch = [&](int kb) {
+    // global -> registers -> LDS staging of one step, two register sets
+    auto fetch = [&](int kb, u32x4 (&ga)[NA], u32x4 (&gb)[NB]) {
 #pragma unroll
         for (int u = 0; u < NA; ++u) {
             const int e = tid + NT * u;
             const int pl = e / (BM * CPR), rem = e - pl * (BM * CPR);
             const int r = rem / CPR, c = rem - r * CPR;
-            const int gr = row0 + r;
+            // rows past M: the last row is read (in bounds, unconditionally, so
+            // that no merge of register values waits on the load) and zeroed
+            // when stored
+            const int gr = min(row0 + r, a.M - 1);
             const char *src = (const char *)(pl ? a.Alo : a.A);
-            ga[u] = gr < a.M ? *(const u32x4 *)(src + ((size_t)gr * a.lda + kb) * ESZ + 16 * c)
-                             : u32x4{0u, 0u, 0u, 0u};
+            ga[u] = *(const u32x4 *)(src + ((size_t)gr * a.lda + kb) * ESZ + 16 * c);
         }
 #pragma unroll
         for (int u = 0; u < NB; ++u) {
@@ -174,14 +175,15 @@ __global__ __launch_bounds__(threads<Pol>()) void k_gemm(GemmArgs a) {
             gb[u] = *(const u32x4 *)(src + ((size_t)(col0 + r) * a.ldb + kb) * ESZ + 16 * c);
         }
     };
-    auto stash = [&](char *st) {
+    auto stash = [&](char *st, const u32x4 (&ga)[NA], const u32x4 (&gb)[NB]) {
         char *sa = st, *sb = st + BM * RB * PL;
 #pragma unroll
         for (int u = 0; u < NA; ++u) {
             const int e = tid + NT * u;
             const int pl = e / (BM * CPR), rem = e - pl * (BM * CPR);
             const int r = rem / CPR, c = rem - r * CPR;
-            *(u32x4 *)(sa + (pl * BM + r) * RB + 16 * c) = ga[u];
+            *(u32x4 *)(sa + (pl * BM + r) * RB + 16 * c) =
+                row0 + r < a.M ? ga[u] : u32x4{0u, 0u, 0u, 0u};
         }
 #pragma unroll
         for (int u = 0; u < NB; ++u) {
@@ -197,17 +199,8 @@ __global__ __launch_bounds__(threads<Pol>()) void k_gemm(GemmArgs a) {
     for (int i = 0; i < TI; ++i)
 #pragma unroll
         for (int j = 0; j < TJ; ++j) acc[i][j] = V{};
-
-    constexpr int SB = stage_bytes<Pol>();
-    if (nsteps > 0) {
-        fetch(k0);
-        stash(smem);
-    }
-    __syncthreads();
-    for (int s = 0; s < nsteps; ++s) {
-        const int cur = s & 1;
-        if (s + 1 < nsteps) fetch(k0 + (s + 1) * kBK);  // in flight during the products
-        const char *sa = smem + cur * SB, *sb = sa + BM * RB * PL;
+    auto compute = [&](const char *sa) {
+        const char *sb = sa + BM * RB * PL;
         Op bo[TJ];
 #pragma unroll
         for (int j = 0; j < TJ; ++j) {
@@ -221,7 +214,31 @@ __global__ __launch_bounds__(threads<Pol>()) void k_gemm(GemmArgs a) {
 #pragma unroll
             for (int j = 0; j < TJ; ++j) acc[i][j] = Pol::mma(ao, bo[j], acc[i][j]);
         }
-        if (s + 1 < nsteps) stash(smem + (cur ^ 1) * SB);
+    };
+
+    // Steps in pairs over two LDS buffers; each step's operands are loaded two
+    // steps ahead (register set 0 for even steps, 1 for odd), stored to LDS at
+    // the end of the step before theirs, one barrier per step.  The loads are
+    // unconditional (the step index clamped to the last step), so that each
+    // register set is filled by its loads alone and no copy waits on them.
+    constexpr int SB = stage_bytes<Pol>();
+    const int last = nsteps > 0 ? nsteps - 1 : 0;
+    u32x4 ga0[NA], gb0[NB], ga1[NA], gb1[NB];
+    if (nsteps > 0) {
+        fetch(k0, ga0, gb0);
+        stash(smem, ga0, gb0);
+        fetch(k0 + min(1, last) * kBK, ga1, gb1);
+    }
+    __syncthreads();
+    // nsteps is even: K and every chunk of it are multiples of 64
+    for (int s = 0; s < nsteps; s += 2) {
+        fetch(k0 + min(s + 2, last) * kBK, ga0, gb0);
+        compute(smem);
+        stash(smem + SB, ga1, gb1);
+        __syncthreads();
+        fetch(k0 + min(s + 3, last) * kBK, ga1, gb1);
+        compute(smem + SB);
+        if (s + 2 < nsteps) stash(smem, ga0, gb0);
         __syncthreads();
     }
 
@@ -342,6 +359,9 @@ hipError_t go(const GemmArgs &a, hipStream_t st) {
     const int nbn = a.N / Pol::BN, nbm = (a.M + Pol::BM - 1) / Pol::BM;
     const unsigned blocks = (unsigned)(nbn * nbm * a.nkc);
     if (blocks == 0) return hipSuccess;
+    // the kernel runs whole pairs of 32-deep steps
+    if (a.K % (2 * kBK) != 0 || a.kchunk % (2 * kBK) != 0 || a.N % Pol::BN != 0)
+        return hipErrorInvalidValue;
     // more dynamic LDS than the default limit: raised once per kernel
     static const hipError_t attr = hipFuncSetAttribute(
         (const void *)k_gemm<Pol, EPI, LOSS>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -386,9 +406,10 @@ GemmShape gemm_shape(Prec prec, int NP, int S, int P_pad) {
     if (prec == Prec::F64) {
         const int want = 512;
         int nk = std::max(1, want / std::max(1, col_blocks * k_blocks));
-        kchunk = (P_pad / nk + kBK - 1) / kBK * kBK;
+        kchunk = P_pad / nk;
     }
-    kchunk = std::max(kBK, std::min(kchunk, P_pad));
+    kchunk = (kchunk + 2 * kBK - 1) / (2 * kBK) * (2 * kBK);  // whole pairs of steps
+    kchunk = std::max(2 * kBK, std::min(kchunk, P_pad));
     g.kchunk = kchunk;
     g.nkc = (P_pad + kchunk - 1) / kchunk;
     return g;
