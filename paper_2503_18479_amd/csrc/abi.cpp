@@ -833,7 +833,6 @@ int cosim_solve(cosim_plan_t p, int B, int F, const double *C_d, const double *o
                            status_d, st));
         HIP_TRY(launch_solve_fallback(p->NP, p->n, S, F, p->M_d, p->R_d, p->phi_d, C_d, omega_d,
                                       I, status_d, p->fac, st));
-        HIP_TRY(launch_replay_forward(p->NP, p->n, S, F, p->fac, omega_d, I, status_d, st));
     } else {
         HIP_TRY(launch_solve_forward(p->NP, p->n, S, F, p->M_d, p->R_d, p->phi_d, C_d, omega_d,
                                      I, status_d, p->fac, st));
@@ -1082,8 +1081,6 @@ static int loss_and_grad_impl(cosim_plan_t p, int B, int F, const double *C_d, c
                            w.fac, w.I, status_d, st));
         HIP_TRY(launch_solve_fallback(p->NP, p->n, (int)S, F, p->M_d, p->R_d, p->phi_d, C_d,
                                       omega_d, w.I, status_d, w.fac, st));
-        HIP_TRY(launch_replay_forward(p->NP, p->n, (int)S, F, w.fac, omega_d, w.I, status_d,
-                                      st));
     } else {
         HIP_TRY(launch_solve_forward(p->NP, p->n, (int)S, F, p->M_d, p->R_d, p->phi_d, C_d,
                                      omega_d, w.I, status_d, w.fac, st));
@@ -1284,7 +1281,6 @@ static int enqueue_small_group(const ManyCall &mc, const std::vector<int> &g, in
     hipEvent_t ev_fwd = pool->extra[group];
     if (launch_small_group(NP, sg, Sg, SmallPhase::Factor, gs) != hipSuccess ||
         launch_small_group(NP, sg, Sg, SmallPhase::Fallback, gs) != hipSuccess ||
-        launch_small_group(NP, sg, Sg, SmallPhase::Forward, gs) != hipSuccess ||
         hipEventRecord(ev_fwd, gs) != hipSuccess) {
         return fail(COSIM_EDEVICE, "grouped solve launch failed");
     }

@@ -83,9 +83,9 @@ constexpr int kFmtRefineFailed = 3, kFmtRefineFailedAdj = 4;
 __host__ __device__ constexpr int ldl_col(int NP, int k) { return k * (2 * NP - k - 1) / 2; }
 constexpr int kFlagPivot = 1 << 16;  // kernel-internal status bit, never returned
 
-// LDL^T fast path (all R_k > 0): factorises and records, leaves
-// z = D^-1 L^-1 (E - j w Phi) in I_d for launch_replay_forward; marks systems
-// that need pivoting (fmt = kFmtNeedsPivot) for launch_solve_fallback.
+// LDL^T fast path (all R_k > 0): factorises, records and solves,
+// I = Z^-1 (E - j w Phi) in I_d; marks systems that need pivoting
+// (fmt = kFmtNeedsPivot, I_d left for it) for launch_solve_fallback.
 hipError_t launch_ldl(int NP, int n, int S, int F, const double *M_d, const double *R_d,
                       const double *C_d, const double *omega_d, const double *phi_d, GJFactor fac,
                       double2 *I_d, int32_t *status_d, hipStream_t st);
@@ -94,11 +94,6 @@ hipError_t launch_solve_fallback(int NP, int n, int S, int F, const double *M_d,
                                  const double *R_d, const double *phi_d, const double *C_d,
                                  const double *omega_d, double2 *I_d, int32_t *status_d,
                                  GJFactor fac, hipStream_t st);
-// Forward solve I = Z^-1 (E - j w Phi) of the kFmtLDL systems: the backward
-// substitution from the z that launch_ldl left in I_d.
-hipError_t launch_replay_forward(int NP, int n, int S, int F, GJFactor fac,
-                                 const double *omega_d, double2 *I_d, int32_t *status_d,
-                                 hipStream_t st);
 // Adjoint solve from the record and the per-system gradient terms.
 // mu_d (optional, [S][n]): the adjoint solution itself.
 hipError_t launch_replay_adjoint(int NP, int n, int S, int F, GJFactor fac, const double *C_d,
@@ -247,7 +242,7 @@ struct SmallGroup {
     int count;
     SmallInst in[kSmallGroupMax];
 };
-enum class SmallPhase { Factor, Fallback, Forward, Adjoint };
+enum class SmallPhase { Factor, Fallback, Adjoint };
 // The final sums (k_reduce) of a group's members in one launch; member i owns
 // configurations [b0, b0 + B) of the launch.
 struct ReduceInst {
@@ -261,8 +256,8 @@ struct ReduceGroup {
     ReduceInst in[kGroupMax];
 };
 hipError_t launch_reduce_group(const ReduceGroup &g, int Btot, hipStream_t st);
-// One phase of the small-plan solver path (k_ldl, the pivoted fallback of
-// marked systems, the forward and the adjoint replay) over a group's S systems.
+// One phase of the small-plan solver path (k_ldl with the forward solve, the
+// pivoted fallback of marked systems, the adjoint replay) over a group's S systems.
 hipError_t launch_small_group(int NP, const SmallGroup &g, int S, SmallPhase phase,
                               hipStream_t st);
 // Blocked LDL^T (pivoted LU for marked systems) of the group's systems into A_d.

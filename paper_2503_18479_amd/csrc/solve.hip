@@ -508,6 +508,106 @@ __device__ inline double wave_sum16(const double (&v)[16], int lane) {
     return t;
 }
 
+// Back substitution L^T x = z with the packed LDL^T record Ls of one system,
+// one wave, lane i holding z_i on entry and x_i on return (0 beyond n).
+// Columns go in blocks of U = 8, [k0, k1), from the bottom.  The terms with
+// i >= k1 (x_i final) of the block's 8 columns are summed over the lanes
+// through LDS: lane i stores its 8 products L_{i,k0+u} x_i as row i of red
+// (rows padded to 9 entries, so 16 consecutive lanes hit distinct banks),
+// lane l adds up column l % 8 over every 8th row starting at row l / 8, and
+// three butterfly steps combine the 8 partial sums.  The terms inside the
+// block use L's 8x8 diagonal block, transposed through LDS (tr) so that lane
+// k0 + u holds row entries L_{k0+ii, k0+u}, and x_{k0+ii} broadcast from its
+// lane as soon as it is final.  Each lane loads only its own row of L
+// (entries L_{lane,k}).  red: NP x 9 double2, tr: 64 double2 of the wave's LDS.
+template <int NP, int DEPTH>
+__device__ __forceinline__ double2 ldl_backward(double2 x, const double2 *__restrict__ Ls, int n,
+                                                int lane, double2 *red, double2 *tr) {
+    constexpr int U = 8, RS = U + 1;
+    auto lcol = [&](int k) {
+        return (lane > k && lane < n) ? Ls[ldl_col(NP, k) + lane - k - 1] : make_double2(0.0, 0.0);
+    };
+    // loads run DEPTH (1 or 2) groups ahead: a ring of DEPTH + 1 register
+    // sets, the group loop unrolled so that the sets rotate without copies
+    auto load_group = [&](double2(&l)[U], int k0) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) l[u] = lcol(k0 + u);
+    };
+    const int cu = lane & (U - 1), part = lane / U;  // column and first row this lane sums
+    int k1 = n;  // columns >= k1 are done
+    // block [k1 - U, k1) from l; loads the block DEPTH further down into fill
+    auto block = [&](const double2(&l)[U], double2(&fill)[U]) {
+        const int k0 = k1 - U;
+        const int ub = (lane - k0) & (U - 1);  // column of the block lane k0 + ub owns
+        if (k0 >= DEPTH * U) load_group(fill, k0 - DEPTH * U);
+        const bool ext = lane >= k1;
+        const double2 xe = make_double2(ext ? x.x : 0.0, ext ? x.y : 0.0);
+        if (lane < NP) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) red[lane * RS + u] = cmul(l[u], xe);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int r = 0; r < NP / U; ++r) {
+            const double2 t = red[(r * U + part) * RS + cu];
+            acc.x += t.x;
+            acc.y += t.y;
+        }
+#pragma unroll
+        for (int off = U; off < 64; off <<= 1) {
+            acc.x += __shfl_xor(acc.x, off);
+            acc.y += __shfl_xor(acc.y, off);
+        }
+        const double er = __shfl(acc.x, ub), ei = __shfl(acc.y, ub);
+        const bool blk = lane >= k0 && lane < k1;
+        if (blk) {
+            x = make_double2(x.x - er, x.y - ei);
+#pragma unroll
+            for (int u = 0; u < U; ++u) tr[ub * U + u] = l[u];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        double2 t[U];
+#pragma unroll
+        for (int ii = 1; ii < U; ++ii) t[ii] = blk ? tr[ii * U + ub] : make_double2(0.0, 0.0);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int ii = U - 1; ii >= 1; --ii) {
+            const double2 xk = make_double2(readlane_d(x.x, k0 + ii), readlane_d(x.y, k0 + ii));
+            x = cfms(x, t[ii], xk);  // t[ii] = 0 unless lane < k0 + ii in the block
+        }
+        k1 = k0;
+    };
+    static_assert(DEPTH == 1 || DEPTH == 2, "one or two groups ahead");
+    double2 s0[U], s1[U], s2[U];
+    if (n >= U) load_group(s0, n - U);
+    if (DEPTH == 2 && n >= 2 * U) load_group(s1, n - 2 * U);
+    while (k1 >= U) {
+        if constexpr (DEPTH == 1) {
+            block(s0, s1);
+            if (k1 < U) break;
+            block(s1, s0);
+        } else {
+            block(s0, s2);
+            if (k1 < U) break;
+            block(s1, s0);
+            if (k1 < U) break;
+            block(s2, s1);
+        }
+    }
+    for (int k = k1 - 1; k >= 0; --k) {
+        const double2 l = lcol(k);
+        const double pr = l.x * x.x - l.y * x.y;
+        const double pi = l.x * x.y + l.y * x.x;
+        const double sr = wave_sum(pr), si = wave_sum(pi);
+        if (lane == k) x = make_double2(x.x - sr, x.y - si);
+    }
+    return x;
+}
+
 // Complex-symmetric LDL^T factorisation without pivoting, Z = L D L^T.
 // The Hermitian part of Z is diag(R) (j w M and 1/(j w C) are skew-Hermitian),
 // so with every R_k > 0 each Schur complement keeps a positive-definite real
@@ -517,14 +617,16 @@ __device__ inline double wave_sum16(const double (&v)[16], int lane) {
 // One wave per system.  The lower triangle is held as NB(NB+1)/2 blocks of
 // 16x16 (NB = NP/16), each as two FP64 matrix-core accumulators (real and
 // imaginary part; lane l holds column l%16, rows g+4m, g = l/16, m = 0..3).
-// Panels of 4 columns:
+// Panels of 8 columns:
 //   1. the lanes holding the panel's columns copy them to LDS;
 //   2. lane r eliminates row r of the panel (diagonal block and below) column
 //      by column, with the diagonal-block rows broadcast by readlane, giving
-//      L and V = L D in registers;
-//   3. L21 and V21 go to LDS;
-//   4. every lower block right of the panel takes the rank-4 update
-//      A -= L21 V21^T as four 16x16x4 FP64 MFMAs (complex = 4 real products).
+//      L and V = L D; their rows replace the panel's rows in LDS;
+//   3. every lower block right of the panel takes the rank-8 update
+//      A -= L21 V21^T as eight 16x16x4 FP64 MFMAs (complex = 4 real products
+//      per 4 columns).
+// Wider panels halve the LDS round trips and wave barriers per column, which
+// with one wave per system are latency that the MFMAs do not hide.
 // Columns left of the trailing part also receive updates; they are finished
 // and never read again.  The factor is recorded (L by columns, D^-1) for the
 // replay kernels, and the forward right-hand side b = E - j w Phi rides along:
@@ -543,11 +645,12 @@ __device__ __forceinline__ void ldl_system(
     constexpr int NBLK = NB * (NB + 1) / 2;
     typedef double f64x4 __attribute__((ext_vector_type(4)));
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    // per wave: panel rows (A, then L21) and V21 rows; a row holds 4 entries
-    // padded to 5 (80 bytes), so that the row-per-lane accesses of 16
+    // per wave: panel rows (A, then L21) and V21 rows; a row holds 8 entries
+    // padded to 9 (144 bytes), so that the row-per-lane accesses of 16
     // consecutive lanes fall on disjoint LDS banks
-    __shared__ double2 sPan[4][NP][5];
-    __shared__ double2 sV[4][NP][5];
+    constexpr int PW = 8;  // panel width
+    __shared__ double2 sPan[4][NP][PW + 1];
+    __shared__ double2 sV[4][NP][PW + 1];
     const int b = s / F, f = s - b * F;
     const double w = omega[f];
     const double *Cb = C + (size_t)b * n;
@@ -604,104 +707,128 @@ __device__ __forceinline__ void ldl_system(
         flag |= __shfl_xor(flag, off);
         zdiag = fmaxf(zdiag, __shfl_xor(zdiag, off));
     }
-    double dmin = __builtin_inf();
     // right-hand side b = E - j w Phi (lane i holds b_i), turned into y = L^-1 b
-    // column by column as L is formed; dl = D_i^-1 of the lane's own column
+    // column by column as L is formed
     double2 y = lane < n ? loop_voltage(phi, n, lane, w) : make_double2(0.0, 0.0);
-    double2 dl = make_double2(1.0, 0.0);
+    double2 dk = make_double2(1.0, 0.0);  // D_i of the lane's own column
 
-    double2 (*pan)[5] = sPan[wv];
-    double2 (*vv)[5] = sV[wv];
+    double2 (*pan)[PW + 1] = sPan[wv];
+    double2 (*vv)[PW + 1] = sV[wv];
+    double2 *Ls = fac.L + (size_t)s * NP * NP;  // packed columns, see ldl_col
 #pragma unroll
     for (int bc = 0; bc < NB; ++bc) {
-        for (int pp = 0; pp < 4; ++pp) {
-            const int k0 = 16 * bc + 4 * pp;  // first column of the panel
+#pragma unroll
+        for (int h = 0; h < 16 / PW; ++h) {
+            const int k0 = 16 * bc + PW * h;  // first column of the panel
             if (k0 >= n) break;               // uniform
-            const int nc = min(4, n - k0);
             // 1. panel columns -> LDS (rows >= k0 matter)
-            if (c16 >= 4 * pp && c16 < 4 * pp + 4) {
-                const int c = c16 - 4 * pp;
+            if (c16 >= PW * h && c16 < PW * h + PW) {
+                const int c = c16 - PW * h;
 #pragma unroll
                 for (int bi = bc; bi < NB; ++bi) {
                     const int bx = bi * (bi + 1) / 2 + bc;
 #pragma unroll
-                    for (int m = 0; m < 4; ++m) pan[16 * bi + g + 4 * m][c] = make_double2(Xr[bx][m], Xi[bx][m]);
+                    for (int m = 0; m < 4; ++m) {  // two 8-byte stores: no register pairing
+                        double *e = &pan[16 * bi + g + 4 * m][c].x;
+                        e[0] = Xr[bx][m];
+                        e[1] = Xi[bx][m];
+                    }
                 }
             }
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
             // 2. lane r takes row r of the panel, column by column:
-            //      V_rc = A_rc - sum_{j<c} L_rj V_cj,  D_c = V_cc,  L_rc = V_rc / D_c;
-            //    row c of the diagonal block is held by lane k0 + c, and the
-            //    entries V_cj, D_c reach every lane by readlane broadcast
-            const int r = lane;
-            double2 v[4], l[4];
+            //      V_rc = A_rc - sum_{j<c} L_rj V_cj,  D_c = V_cc,  L_rc = V_rc / D_c.
+            //    Row c of V (entries j < c, stored by lane k0 + c in earlier
+            //    columns) reaches every lane as broadcast LDS reads, D_c by
+            //    readlane; V and L rows replace the panel rows in LDS as they
+            //    are formed.  Rows above the panel end in the upper triangle or
+            //    in eliminated columns, which are never read again, so every
+            //    row is stored as it comes.
+            const int r = lane, rr = min(r, NP - 1);
+            double2 l[PW];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) v[c] = pan[min(r, NP - 1)][c];
-            double2 *Ls = fac.L + (size_t)s * NP * NP;  // packed columns, see ldl_col
+            for (int c = 0; c < PW; ++c) {
+                double2 v = pan[rr][c];
+                double2 vc[PW];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
+                for (int j = 0; j < c; ++j) vc[j] = vv[k0 + c][j];
 #pragma unroll
-                for (int j = 0; j < c; ++j) {
-                    const double2 vcj = make_double2(readlane_d(v[j].x, k0 + c), readlane_d(v[j].y, k0 + c));
-                    v[c] = cfms(v[c], l[j], vcj);
-                }
-                const double2 d = make_double2(readlane_d(v[c].x, k0 + c), readlane_d(v[c].y, k0 + c));
-                if (c < nc) dmin = fmin(dmin, fabs(d.x) + fabs(d.y));
+                for (int j = 0; j < c; ++j) v = cfms(v, l[j], vc[j]);
+                const double2 d = make_double2(readlane_d(v.x, k0 + c), readlane_d(v.y, k0 + c));
                 const double2 dinv = cinv_nr(d);
-                l[c] = cmul(v[c], dinv);
-                // L below the diagonal (rows of the diagonal block and below it), D^-1
+                l[c] = cmul(v, dinv);
+                // L below the diagonal (rows of the diagonal block and below it)
                 if (r > k0 + c && r < NP) Ls[ldl_col(NP, k0 + c) + r - (k0 + c) - 1] = l[c];
-                if (lane == 0) fac.piv_val[(size_t)s * NP + k0 + c] = dinv;
-                if (lane == k0 + c) dl = dinv;
+                if (r < NP) {
+                    pan[r][c] = l[c];
+                    vv[r][c] = v;
+                }
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                __builtin_amdgcn_wave_barrier();
             }
+            // D_c = V_cc to the lane of column c
+            if (r >= k0 && r < k0 + PW) dk = vv[r][r - k0];
             // forward substitution for the panel's columns: y_r -= L_rc y_c (r > k0 + c)
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
+            for (int c = 0; c < PW; ++c) {
                 const double2 yc = make_double2(readlane_d(y.x, k0 + c), readlane_d(y.y, k0 + c));
                 const double2 yn = cfms(y, l[c], yc);
                 const bool below = r > k0 + c;
                 y.x = below ? yn.x : y.x;  // componentwise: a select of the
                 y.y = below ? yn.y : y.y;  // vector struct goes through memory
             }
-            // 3. L and V rows to LDS.  Only rows below the diagonal block (L21,
-            // V21) matter: an L row i < k0 + 4 changes only entries of row i
-            // right of column k0 + 3 (upper triangle), a V row j < k0 + 4 only
-            // column j (already eliminated); neither is read again, so rows
-            // above are stored as they come, without masking
-            if (r < NP) {
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    pan[r][c] = l[c];
-                    vv[r][c] = v[c];
-                }
-            }
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
-            // 4. rank-4 update of every lower block right of the panel; the
-            // operands of a block row are read from LDS just before its MFMAs
-            // (fewer live registers: two waves fit a SIMD)
+            // 3. rank-PW update of every lower block right of the panel, as
+            // PW / 4 steps of four 16x16x4 FP64 MFMAs; the operands of a block
+            // row are read from LDS just before its MFMAs.  The last panel of
+            // a block column leaves that column fully eliminated, so its
+            // blocks are skipped.
+            const int bj0 = h == 16 / PW - 1 ? bc + 1 : bc;
 #pragma unroll
-            for (int bi = bc; bi < NB; ++bi) {
-                const double2 La = pan[16 * bi + c16][g];  // A operand: row c16 of block bi, k = g
+            for (int bi = bj0; bi < NB; ++bi) {
+                double2 La[PW / 4];  // A operand: row c16 of block bi, k = g + 4 q
 #pragma unroll
-                for (int bj = bc; bj <= bi; ++bj) {
-                    const double2 Vb = vv[16 * bj + c16][g];  // B operand: column c16 of block bj, k = g
+                for (int q = 0; q < PW / 4; ++q) La[q] = pan[16 * bi + c16][g + 4 * q];
+#pragma unroll
+                for (int bj = bj0; bj <= bi; ++bj) {
                     const int bx = bi * (bi + 1) / 2 + bj;
-                    Xr[bx] = __builtin_amdgcn_mfma_f64_16x16x4f64(-La.x, Vb.x, Xr[bx], 0, 0, 0);
-                    Xr[bx] = __builtin_amdgcn_mfma_f64_16x16x4f64(La.y, Vb.y, Xr[bx], 0, 0, 0);
-                    Xi[bx] = __builtin_amdgcn_mfma_f64_16x16x4f64(-La.x, Vb.y, Xi[bx], 0, 0, 0);
-                    Xi[bx] = __builtin_amdgcn_mfma_f64_16x16x4f64(-La.y, Vb.x, Xi[bx], 0, 0, 0);
+#pragma unroll
+                    for (int q = 0; q < PW / 4; ++q) {
+                        const double2 Vb = vv[16 * bj + c16][g + 4 * q];  // B operand: column c16 of block bj
+                        Xr[bx] = __builtin_amdgcn_mfma_f64_16x16x4f64(-La[q].x, Vb.x, Xr[bx], 0, 0, 0);
+                        Xr[bx] = __builtin_amdgcn_mfma_f64_16x16x4f64(La[q].y, Vb.y, Xr[bx], 0, 0, 0);
+                        Xi[bx] = __builtin_amdgcn_mfma_f64_16x16x4f64(-La[q].x, Vb.y, Xi[bx], 0, 0, 0);
+                        Xi[bx] = __builtin_amdgcn_mfma_f64_16x16x4f64(-La[q].y, Vb.x, Xi[bx], 0, 0, 0);
+                    }
                 }
             }
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
         }
     }
-    if (lane < n) Z[(size_t)s * n + lane] = cmul(y, dl);  // z = D^-1 L^-1 b
+    const double2 dl = cinv_nr(dk);  // the D^-1 the elimination used
+    if (lane < NP) fac.piv_val[(size_t)s * NP + lane] = dl;  // D^-1 (1 on the padding)
+    // smallest |re| + |im| pivot of the real columns
+    double dmin = lane < n ? fabs(dk.x) + fabs(dk.y) : __builtin_inf();
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) dmin = fmin(dmin, __shfl_xor(dmin, off));
+    const bool pivot = (flag & COSIM_SYS_BAD_INPUT) || !(dmin >= 1e-5 * (double)zdiag);  // uniform
+    bool nonfinite = false;
+    if (!pivot) {
+        // x = L^-T z with z = D^-1 L^-1 b, from the L entries this lane stored;
+        // systems marked for the pivoted fallback get I from it instead
+        const double2 z = lane < n ? cmul(y, dl) : make_double2(0.0, 0.0);
+        const double2 x = ldl_backward<NP, NP >= 64 ? 2 : 1>(z, Ls, n, lane, &pan[0][0], &vv[0][0]);
+        if (lane < n) {
+            Z[(size_t)s * n + lane] = x;
+            nonfinite = !(isfinite(x.x) && isfinite(x.y));
+        }
+    }
+    const bool nf = __ballot(nonfinite) != 0;
     if (lane == 0) {
-        const bool pivot = (flag & COSIM_SYS_BAD_INPUT) || !(dmin >= 1e-5 * (double)zdiag);
-        status[s] = flag;
+        status[s] = flag | (nf ? COSIM_SYS_NONFINITE : 0);
         fac.fmt[s] = pivot ? kFmtNeedsPivot : kFmtLDL;
     }
 }
@@ -729,46 +856,38 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     ldl_system<NP>(sg - e.s0, e.n, e.F, e.M, e.R, e.C, e.omega, e.phi, e.fac, e.I, e.status);
 }
 
-// Solves with a recorded factorisation, one wave per system, lane i holds
-// component i.  Format kFmtLDL: y = L^-1 b by columns (readlane broadcast of
-// y_k, one coalesced column load), z = D^-1 y, then L^T x = z by
-// dot products (wave sums); the forward solve starts from z, which the
-// factorisation left in I.  Format kFmtGJ: replays the recorded Gauss-Jordan
-// row operations b <- b - l_k b_{p_k}, then x_k = b_{p_k} / piv_k.
-// ADJ = false: z in I, writes I (systems in the Gauss-Jordan format
-// already have I from the elimination and are skipped).
-// ADJ = true : b = rscale * sum_c (rr - j ri); writes
-//              gsys[s][k] = 2 Re(mu_k I_k / (j w C_k^2)).
-template <int NP, bool ADJ>
+// Adjoint solve with a recorded factorisation, one wave per system, lane i
+// holds component i; b = rscale * sum_c (rr - j ri) of rpart[c][s][:].
+// Format kFmtLDL: y = L^-1 b by columns (readlane broadcast of y_k, one
+// coalesced column load), z = D^-1 y, then L^T x = z (ldl_backward).
+// Format kFmtGJ: replays the recorded Gauss-Jordan row operations
+// b <- b - l_k b_{p_k}, then x_k = b_{p_k} / piv_k.
+// Writes gsys[s][k] = 2 Re(mu_k I_k / (j w C_k^2)) and, if given, mu.
+template <int NP>
 __device__ __forceinline__ void replay_system(int s, int n, int S, int F, GJFactor fac,
-                                              const double *__restrict__ phi,
                                               const double *__restrict__ C,
                                               const double *__restrict__ omega,
-                                              double2 *__restrict__ I,
+                                              const double2 *__restrict__ I,
                                               const double2 *__restrict__ rpart, int nchunk,
                                               double rscale, double *__restrict__ gsys,
                                               double2 *__restrict__ mu,
                                               int32_t *__restrict__ status) {
-    __shared__ double2 sTr[4][64];  // per wave: an 8x8 block of L, transposed
+    __shared__ double2 sRed[4][NP * 9];  // per wave: the lane products of ldl_backward
+    __shared__ double2 sTr[4][64];       // per wave: an 8x8 block of L, transposed
     const int lane = threadIdx.x & 63;
     const int fmt = __builtin_amdgcn_readfirstlane(fac.fmt[s]);
-    if (!ADJ && fmt == kFmtGJ) return;
     const int b = s / F, f = s - b * F;
     const double w = omega[f];
     double2 x = make_double2(0.0, 0.0);
     if (lane < n) {
-        if (!ADJ) {
-            x = I[(size_t)s * n + lane];  // z = D^-1 L^-1 b from the factorisation
-        } else {
-            double rr = 0.0, ri = 0.0;
+        double rr = 0.0, ri = 0.0;
 #pragma unroll 8
-            for (int c = 0; c < nchunk; ++c) {  // loads ahead, sums in chunk order
-                const double2 v = rpart[((size_t)c * S + s) * NP + lane];
-                rr += v.x;
-                ri += v.y;
-            }
-            x = make_double2(rscale * rr, -rscale * ri);
+        for (int c = 0; c < nchunk; ++c) {  // loads ahead, sums in chunk order
+            const double2 v = rpart[((size_t)c * S + s) * NP + lane];
+            rr += v.x;
+            ri += v.y;
         }
+        x = make_double2(rscale * rr, -rscale * ri);
     }
     const double2 *__restrict__ Ls = fac.L + (size_t)s * NP * NP;
     constexpr int U = 8;
@@ -784,84 +903,27 @@ __device__ __forceinline__ void replay_system(int s, int n, int S, int F, GJFact
 #pragma unroll
             for (int u = 0; u < U; ++u) l[u] = lcol(k0 + u);
         };
-        if (ADJ) {
-            // forward: y_i -= L_ik y_k for i > k (the forward solve had it
-            // done by the factorisation)
-            const int nfg = n / U;  // full groups
-            if (nfg > 0) load_group(cur, 0);
-            int k0 = 0;
-            for (; k0 + U <= n; k0 += U) {
-                if (k0 + 2 * U <= n) load_group(nxt, k0 + U);
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const double2 yk = make_double2(readlane_d(x.x, k0 + u), readlane_d(x.y, k0 + u));
-                    x = cfms(x, cur[u], yk);
-                }
-#pragma unroll
-                for (int u = 0; u < U; ++u) cur[u] = nxt[u];
-            }
-            for (; k0 < n; ++k0) {
-                const double2 l = lcol(k0);
-                const double2 yk = make_double2(readlane_d(x.x, k0), readlane_d(x.y, k0));
-                x = cfms(x, l, yk);
-            }
-            if (lane < n) x = cmul(x, fac.piv_val[(size_t)s * NP + lane]);  // D^-1
-        }
-        // backward: x_k = z_k - sum_{i > k} L_ik x_i, in blocks of U = 8
-        // columns [k0, k1) from the bottom.  The terms with i >= k1 (x_i final)
-        // of all 8 columns are summed by one 16-value reduction; the terms
-        // inside the block use L's 8x8 diagonal block, transposed through LDS
-        // so that lane k0 + u holds row entries L_{k0+ii, k0+u}, and x_{k0+ii}
-        // broadcast from its lane as soon as it is final.
-        static_assert(U == 8, "the block reduction handles 8 complex columns");
-        double2 *tr = sTr[threadIdx.x >> 6];
-        int k1 = n;  // columns >= k1 are done
-        if (n >= U) load_group(cur, n - U);
-        for (; k1 >= U; k1 -= U) {
-            const int k0 = k1 - U;
-            const int ub = (lane - k0) & (U - 1);  // column of the block lane k0 + ub owns
-            if (k0 >= U) load_group(nxt, k0 - U);
-            double2 l[U];
+        // forward: y_i -= L_ik y_k for i > k
+        const int nfg = n / U;  // full groups
+        if (nfg > 0) load_group(cur, 0);
+        int k0 = 0;
+        for (; k0 + U <= n; k0 += U) {
+            if (k0 + 2 * U <= n) load_group(nxt, k0 + U);
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                l[u] = cur[u];
-                cur[u] = nxt[u];
+                const double2 yk = make_double2(readlane_d(x.x, k0 + u), readlane_d(x.y, k0 + u));
+                x = cfms(x, cur[u], yk);
             }
-            const bool ext = lane >= k1;
-            double v[2 * U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                v[2 * u] = ext ? l[u].x * x.x - l[u].y * x.y : 0.0;
-                v[2 * u + 1] = ext ? l[u].x * x.y + l[u].y * x.x : 0.0;
-            }
-            const double tot = wave_sum16(v, lane);
-            const bool blk = lane >= k0 && lane < k1;
-            const double er = __shfl(tot, 2 * ub), ei = __shfl(tot, 2 * ub + 1);
-            if (blk) {
-                x = make_double2(x.x - er, x.y - ei);
-#pragma unroll
-                for (int u = 0; u < U; ++u) tr[ub * U + u] = l[u];
-            }
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            double2 t[U];
-#pragma unroll
-            for (int ii = 1; ii < U; ++ii) t[ii] = blk ? tr[ii * U + ub] : make_double2(0.0, 0.0);
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-#pragma unroll
-            for (int ii = U - 1; ii >= 1; --ii) {
-                const double2 xk = make_double2(readlane_d(x.x, k0 + ii), readlane_d(x.y, k0 + ii));
-                x = cfms(x, t[ii], xk);  // t[ii] = 0 unless lane < k0 + ii in the block
-            }
+            for (int u = 0; u < U; ++u) cur[u] = nxt[u];
         }
-        for (int k = k1 - 1; k >= 0; --k) {
-            const double2 l = lcol(k);
-            const double pr = l.x * x.x - l.y * x.y;
-            const double pi = l.x * x.y + l.y * x.x;
-            const double sr = wave_sum(pr), si = wave_sum(pi);
-            if (lane == k) x = make_double2(x.x - sr, x.y - si);
+        for (; k0 < n; ++k0) {
+            const double2 l = lcol(k0);
+            const double2 yk = make_double2(readlane_d(x.x, k0), readlane_d(x.y, k0));
+            x = cfms(x, l, yk);
         }
+        if (lane < n) x = cmul(x, fac.piv_val[(size_t)s * NP + lane]);  // D^-1
+        x = ldl_backward<NP, 1>(x, Ls, n, lane, sRed[threadIdx.x >> 6], sTr[threadIdx.x >> 6]);
     } else {
         const int *__restrict__ Ps = fac.piv_row + (size_t)s * NP;
         int k0 = 0;
@@ -892,45 +954,39 @@ __device__ __forceinline__ void replay_system(int s, int n, int S, int F, GJFact
     bool nonfinite = false;
     if (lane < n) {
         if (bad) x = make_double2(__builtin_nan(""), __builtin_nan(""));
-        if (!ADJ) {
-            I[(size_t)s * n + lane] = x;
-            nonfinite = !bad && !(isfinite(x.x) && isfinite(x.y));
-        } else {
-            const double2 Ik = I[(size_t)s * n + lane];
-            const double ck = C[(size_t)b * n + lane];
-            // 2 Re(mu I / (j w C^2)) = 2 Im(mu I) / (w C^2)
-            const double g = 2.0 * (x.x * Ik.y + x.y * Ik.x) / (w * ck * ck);
-            gsys[(size_t)s * n + lane] = g;
-            if (mu) mu[(size_t)s * n + lane] = x;
-            nonfinite = !bad && !isfinite(g);
-        }
+        const double2 Ik = I[(size_t)s * n + lane];
+        const double ck = C[(size_t)b * n + lane];
+        // 2 Re(mu I / (j w C^2)) = 2 Im(mu I) / (w C^2)
+        const double g = 2.0 * (x.x * Ik.y + x.y * Ik.x) / (w * ck * ck);
+        gsys[(size_t)s * n + lane] = g;
+        if (mu) mu[(size_t)s * n + lane] = x;
+        nonfinite = !bad && !isfinite(g);
     }
     if (__ballot(nonfinite) != 0 && lane == 0) status[s] = flag | COSIM_SYS_NONFINITE;
 }
 
-template <int NP, bool ADJ>
-__global__ __launch_bounds__(256) void k_replay(int n, int S, int F, GJFactor fac,
-                                                const double *__restrict__ phi,
-                                                const double *__restrict__ C,
-                                                const double *__restrict__ omega,
-                                                double2 *__restrict__ I,
-                                                const double2 *__restrict__ rpart, int nchunk,
-                                                double rscale, double *__restrict__ gsys,
-                                                double2 *__restrict__ mu,
-                                                int32_t *__restrict__ status) {
+template <int NP>
+__global__ __launch_bounds__(256) void k_replay_adjoint(int n, int S, int F, GJFactor fac,
+                                                        const double *__restrict__ C,
+                                                        const double *__restrict__ omega,
+                                                        const double2 *__restrict__ I,
+                                                        const double2 *__restrict__ rpart,
+                                                        int nchunk, double rscale,
+                                                        double *__restrict__ gsys,
+                                                        double2 *__restrict__ mu,
+                                                        int32_t *__restrict__ status) {
     const int s = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
     if (s >= S) return;  // whole wave; no block-level synchronisation below
-    replay_system<NP, ADJ>(s, n, S, F, fac, phi, C, omega, I, rpart, nchunk, rscale, gsys, mu,
-                           status);
+    replay_system<NP>(s, n, S, F, fac, C, omega, I, rpart, nchunk, rscale, gsys, mu, status);
 }
 
-template <int NP, bool ADJ>
-__global__ __launch_bounds__(256) void k_replay_group(SmallGroup g, int S) {
+template <int NP>
+__global__ __launch_bounds__(256) void k_replay_adjoint_group(SmallGroup g, int S) {
     const int sg = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
     if (sg >= S) return;
     const SmallInst &e = g.in[group_member(g, sg)];
-    replay_system<NP, ADJ>(sg - e.s0, e.n, e.S, e.F, e.fac, e.phi, e.C, e.omega, e.I, e.rpart,
-                           e.nchunk, e.rscale, e.gsys, e.mu, e.status);
+    replay_system<NP>(sg - e.s0, e.n, e.S, e.F, e.fac, e.C, e.omega, e.I, e.rpart, e.nchunk,
+                      e.rscale, e.gsys, e.mu, e.status);
 }
 
 // One 64-lane block per configuration b: dL/dC_b summed over frequencies per
@@ -1039,40 +1095,24 @@ hipError_t launch_solve_fallback(int NP, int n, int S, int F, const double *M_d,
                             I_d, nullptr, status_d, false, fac, true, st);
 }
 
-template <bool ADJ>
-hipError_t launch_replay_t(int NP, int n, int S, int F, GJFactor fac, const double *phi_d,
-                           const double *C_d, const double *omega_d, double2 *I_d,
-                           const double2 *rpart_d, int nchunk, double rscale, double *gsys_d,
-                           double2 *mu_d, int32_t *status_d, hipStream_t st) {
+hipError_t launch_replay_adjoint(int NP, int n, int S, int F, GJFactor fac, const double *C_d,
+                                 const double *omega_d, double2 *I_d, const double2 *rpart_d,
+                                 int nchunk, double rscale, double *gsys_d, double2 *mu_d,
+                                 int32_t *status_d, hipStream_t st) {
     const dim3 grid((S + 3) / 4);
     switch (NP) {
         case 32:
-            hipLaunchKernelGGL((k_replay<32, ADJ>), grid, dim3(256), 0, st, n, S, F, fac, phi_d,
-                               C_d, omega_d, I_d, rpart_d, nchunk, rscale, gsys_d, mu_d, status_d);
+            hipLaunchKernelGGL(k_replay_adjoint<32>, grid, dim3(256), 0, st, n, S, F, fac, C_d,
+                               omega_d, I_d, rpart_d, nchunk, rscale, gsys_d, mu_d, status_d);
             break;
         case 64:
-            hipLaunchKernelGGL((k_replay<64, ADJ>), grid, dim3(256), 0, st, n, S, F, fac, phi_d,
-                               C_d, omega_d, I_d, rpart_d, nchunk, rscale, gsys_d, mu_d, status_d);
+            hipLaunchKernelGGL(k_replay_adjoint<64>, grid, dim3(256), 0, st, n, S, F, fac, C_d,
+                               omega_d, I_d, rpart_d, nchunk, rscale, gsys_d, mu_d, status_d);
             break;
         default:
             return hipErrorInvalidValue;
     }
     return hipGetLastError();
-}
-
-hipError_t launch_replay_forward(int NP, int n, int S, int F, GJFactor fac,
-                                 const double *omega_d, double2 *I_d, int32_t *status_d,
-                                 hipStream_t st) {
-    return launch_replay_t<false>(NP, n, S, F, fac, nullptr, nullptr, omega_d, I_d, nullptr, 0,
-                                  0.0, nullptr, nullptr, status_d, st);
-}
-
-hipError_t launch_replay_adjoint(int NP, int n, int S, int F, GJFactor fac, const double *C_d,
-                                 const double *omega_d, double2 *I_d, const double2 *rpart_d,
-                                 int nchunk, double rscale, double *gsys_d, double2 *mu_d,
-                                 int32_t *status_d, hipStream_t st) {
-    return launch_replay_t<true>(NP, n, S, F, fac, nullptr, C_d, omega_d, I_d, rpart_d, nchunk,
-                                 rscale, gsys_d, mu_d, status_d, st);
 }
 
 hipError_t launch_solve_adjoint(int NP, int n, int S, int F, const double *M_d,
@@ -1110,11 +1150,8 @@ hipError_t launch_small_group(int NP, const SmallGroup &g, int S, SmallPhase pha
         case SmallPhase::Fallback:                                                               \
             hipLaunchKernelGGL(k_gj_group<NPC>, dim3(S), dim3(GJShape<NPC>::BLOCK), 0, st, g);   \
             break;                                                                               \
-        case SmallPhase::Forward:                                                                \
-            hipLaunchKernelGGL((k_replay_group<NPC, false>), wave_grid, dim3(256), 0, st, g, S); \
-            break;                                                                               \
         case SmallPhase::Adjoint:                                                                \
-            hipLaunchKernelGGL((k_replay_group<NPC, true>), wave_grid, dim3(256), 0, st, g, S);  \
+            hipLaunchKernelGGL(k_replay_adjoint_group<NPC>, wave_grid, dim3(256), 0, st, g, S);   \
             break;                                                                               \
     }
     switch (NP) {
