@@ -518,88 +518,85 @@ __device__ inline double wave_sum16(const double (&v)[16], int lane) {
 // three butterfly steps combine the 8 partial sums.  The terms inside the
 // block use L's 8x8 diagonal block, transposed through LDS (tr) so that lane
 // k0 + u holds row entries L_{k0+ii, k0+u}, and x_{k0+ii} broadcast from its
-// lane as soon as it is final.  Each lane loads only its own row of L
-// (entries L_{lane,k}).  red: NP x 9 double2, tr: 64 double2 of the wave's LDS.
-template <int NP, int DEPTH>
-__device__ __forceinline__ double2 ldl_backward(double2 x, const double2 *__restrict__ Ls, int n,
-                                                int lane, double2 *red, double2 *tr) {
-    constexpr int U = 8, RS = U + 1;
-    auto lcol = [&](int k) {
-        return (lane > k && lane < n) ? Ls[ldl_col(NP, k) + lane - k - 1] : make_double2(0.0, 0.0);
-    };
-    // loads run DEPTH (1 or 2) groups ahead: a ring of DEPTH + 1 register
-    // sets, the group loop unrolled so that the sets rotate without copies
-    auto load_group = [&](double2(&l)[U], int k0) {
+// lane as soon as it is final.  Each lane reads only its own row of L
+// (entries L_{lane,k}, 0 unless k < lane < n).  red: NP x 9 double2, tr: 64
+// (NP = 64) or 128 double2 of the wave's LDS.
+constexpr int kBsU = 8;
+template <int NP>
+__device__ __forceinline__ void bs_load(double2 (&l)[kBsU], const double2 *__restrict__ Ls, int n,
+                                        int lane, int k0) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) l[u] = lcol(k0 + u);
-    };
-    const int cu = lane & (U - 1), part = lane / U;  // column and first row this lane sums
-    int k1 = n;  // columns >= k1 are done
-    // block [k1 - U, k1) from l; loads the block DEPTH further down into fill
-    auto block = [&](const double2(&l)[U], double2(&fill)[U]) {
-        const int k0 = k1 - U;
-        const int ub = (lane - k0) & (U - 1);  // column of the block lane k0 + ub owns
-        if (k0 >= DEPTH * U) load_group(fill, k0 - DEPTH * U);
-        const bool ext = lane >= k1;
-        const double2 xe = make_double2(ext ? x.x : 0.0, ext ? x.y : 0.0);
-        if (lane < NP) {
-#pragma unroll
-            for (int u = 0; u < U; ++u) red[lane * RS + u] = cmul(l[u], xe);
-        }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        double2 acc = make_double2(0.0, 0.0);
-#pragma unroll
-        for (int r = 0; r < NP / U; ++r) {
-            const double2 t = red[(r * U + part) * RS + cu];
-            acc.x += t.x;
-            acc.y += t.y;
-        }
-#pragma unroll
-        for (int off = U; off < 64; off <<= 1) {
-            acc.x += __shfl_xor(acc.x, off);
-            acc.y += __shfl_xor(acc.y, off);
-        }
-        const double er = __shfl(acc.x, ub), ei = __shfl(acc.y, ub);
-        const bool blk = lane >= k0 && lane < k1;
-        if (blk) {
-            x = make_double2(x.x - er, x.y - ei);
-#pragma unroll
-            for (int u = 0; u < U; ++u) tr[ub * U + u] = l[u];
-        }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        double2 t[U];
-#pragma unroll
-        for (int ii = 1; ii < U; ++ii) t[ii] = blk ? tr[ii * U + ub] : make_double2(0.0, 0.0);
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-#pragma unroll
-        for (int ii = U - 1; ii >= 1; --ii) {
-            const double2 xk = make_double2(readlane_d(x.x, k0 + ii), readlane_d(x.y, k0 + ii));
-            x = cfms(x, t[ii], xk);  // t[ii] = 0 unless lane < k0 + ii in the block
-        }
-        k1 = k0;
-    };
-    static_assert(DEPTH == 1 || DEPTH == 2, "one or two groups ahead");
-    double2 s0[U], s1[U], s2[U];
-    if (n >= U) load_group(s0, n - U);
-    if (DEPTH == 2 && n >= 2 * U) load_group(s1, n - 2 * U);
-    while (k1 >= U) {
-        if constexpr (DEPTH == 1) {
-            block(s0, s1);
-            if (k1 < U) break;
-            block(s1, s0);
-        } else {
-            block(s0, s2);
-            if (k1 < U) break;
-            block(s1, s0);
-            if (k1 < U) break;
-            block(s2, s1);
-        }
+    for (int u = 0; u < kBsU; ++u) {
+        const int k = k0 + u;
+        l[u] = (lane > k && lane < n) ? Ls[ldl_col(NP, k) + lane - k - 1] : make_double2(0.0, 0.0);
     }
+}
+// One block [k1 - U, k1) from l (the lanes' row entries of its columns);
+// then k1 -= U.  Two LDS exchanges: (1) every lane stores its products and
+// the block's lanes their rows of the diagonal block; (2) lane l stores the
+// sum of column l % 8 over rows l / 8, l / 8 + 8, ..., and the block's lanes
+// read their transposed row entries; then each block lane adds up the 8
+// partial sums of its own column.
+template <int NP>
+__device__ __forceinline__ void bs_block(double2 &x, int &k1, const double2 (&l)[kBsU], int lane,
+                                         double2 *red, double2 *tr) {
+    constexpr int U = kBsU, RS = U + 1;
+    const int cu = lane & (U - 1), part = lane / U;  // column and first row this lane sums
+    const int k0 = k1 - U;
+    const int ub = (lane - k0) & (U - 1);  // column of the block lane k0 + ub owns
+    const bool ext = lane >= k1, blk = lane >= k0 && lane < k1;
+    const double2 xe = make_double2(ext ? x.x : 0.0, ext ? x.y : 0.0);
+    // U x U partial sums: in the pad column of red when it has 64 rows
+    auto psum = [&](int i) -> double2 & { return NP >= 64 ? red[i * RS + U] : tr[U * U + i]; };
+    if (lane < NP) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) red[lane * RS + u] = cmul(l[u], xe);
+    }
+    if (blk) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) tr[ub * U + u] = l[u];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int r = 0; r < NP / U; ++r) {
+        const double2 t = red[(r * U + part) * RS + cu];
+        acc.x += t.x;
+        acc.y += t.y;
+    }
+    psum(part * U + cu) = acc;
+    double2 t[U];
+#pragma unroll
+    for (int ii = 1; ii < U; ++ii) t[ii] = blk ? tr[ii * U + ub] : make_double2(0.0, 0.0);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    if (blk) {
+        double er = 0.0, ei = 0.0;
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            const double2 e = psum(q * U + ub);
+            er += e.x;
+            ei += e.y;
+        }
+        x = make_double2(x.x - er, x.y - ei);
+    }
+#pragma unroll
+    for (int ii = U - 1; ii >= 1; --ii) {
+        const double2 xk = make_double2(readlane_d(x.x, k0 + ii), readlane_d(x.y, k0 + ii));
+        x = cfms(x, t[ii], xk);  // t[ii] = 0 unless lane < k0 + ii in the block
+    }
+    // the next block's stores wait for this block's reads
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    k1 = k0;
+}
+// The columns left of the last whole block, one at a time by wave sums.
+__device__ __forceinline__ double2 bs_tail(double2 x, int k1, const double2 *__restrict__ Ls,
+                                           int NP, int n, int lane) {
     for (int k = k1 - 1; k >= 0; --k) {
-        const double2 l = lcol(k);
+        const double2 l = (lane > k && lane < n) ? Ls[ldl_col(NP, k) + lane - k - 1]
+                                                 : make_double2(0.0, 0.0);
         const double pr = l.x * x.x - l.y * x.y;
         const double pi = l.x * x.y + l.y * x.x;
         const double sr = wave_sum(pr), si = wave_sum(pi);
@@ -607,7 +604,36 @@ __device__ __forceinline__ double2 ldl_backward(double2 x, const double2 *__rest
     }
     return x;
 }
-
+// Any n: loads run DEPTH (1 or 2) blocks ahead, from a ring of DEPTH + 1
+// register sets that rotate without copies (the block loop is unrolled).
+template <int NP, int DEPTH>
+__device__ __forceinline__ double2 ldl_backward(double2 x, const double2 *__restrict__ Ls, int n,
+                                                int lane, double2 *red, double2 *tr) {
+    constexpr int U = kBsU;
+    static_assert(DEPTH == 1 || DEPTH == 2, "one or two blocks ahead");
+    int k1 = n;  // columns >= k1 are done
+    double2 s0[U], s1[U], s2[U];
+    if (n >= U) bs_load<NP>(s0, Ls, n, lane, n - U);
+    if (DEPTH == 2 && n >= 2 * U) bs_load<NP>(s1, Ls, n, lane, n - 2 * U);
+    auto step = [&](const double2(&l)[U], double2(&fill)[U]) {
+        if (k1 - U >= DEPTH * U) bs_load<NP>(fill, Ls, n, lane, k1 - U - DEPTH * U);
+        bs_block<NP>(x, k1, l, lane, red, tr);
+    };
+    while (k1 >= U) {
+        if constexpr (DEPTH == 1) {
+            step(s0, s1);
+            if (k1 < U) break;
+            step(s1, s0);
+        } else {
+            step(s0, s2);
+            if (k1 < U) break;
+            step(s1, s0);
+            if (k1 < U) break;
+            step(s2, s1);
+        }
+    }
+    return bs_tail(x, k1, Ls, NP, n, lane);
+}
 // Complex-symmetric LDL^T factorisation without pivoting, Z = L D L^T.
 // The Hermitian part of Z is diag(R) (j w M and 1/(j w C) are skew-Hermitian),
 // so with every R_k > 0 each Schur complement keeps a positive-definite real
@@ -814,23 +840,41 @@ __device__ __forceinline__ void ldl_system(
     double dmin = lane < n ? fabs(dk.x) + fabs(dk.y) : __builtin_inf();
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) dmin = fmin(dmin, __shfl_xor(dmin, off));
-    const bool pivot = (flag & COSIM_SYS_BAD_INPUT) || !(dmin >= 1e-5 * (double)zdiag);  // uniform
-    bool nonfinite = false;
-    if (!pivot) {
-        // x = L^-T z with z = D^-1 L^-1 b, from the L entries this lane stored;
-        // systems marked for the pivoted fallback get I from it instead
-        const double2 z = lane < n ? cmul(y, dl) : make_double2(0.0, 0.0);
-        const double2 x = ldl_backward<NP, NP >= 64 ? 2 : 1>(z, Ls, n, lane, &pan[0][0], &vv[0][0]);
-        if (lane < n) {
-            Z[(size_t)s * n + lane] = x;
-            nonfinite = !(isfinite(x.x) && isfinite(x.y));
-        }
-    }
-    const bool nf = __ballot(nonfinite) != 0;
+    if (lane < n) Z[(size_t)s * n + lane] = cmul(y, dl);  // z = D^-1 L^-1 b
     if (lane == 0) {
-        status[s] = flag | (nf ? COSIM_SYS_NONFINITE : 0);
+        const bool pivot = (flag & COSIM_SYS_BAD_INPUT) || !(dmin >= 1e-5 * (double)zdiag);
+        status[s] = flag;
         fac.fmt[s] = pivot ? kFmtNeedsPivot : kFmtLDL;
     }
+}
+
+// Forward solve of a system in the LDL^T format from the z the factorisation
+// left in I: x = L^-T z, written over it (systems handed to the pivoted
+// fallback are skipped; it writes their I).
+template <int NP>
+__device__ __forceinline__ void forward_system(int s, int n, GJFactor fac, double2 *__restrict__ I,
+                                               int32_t *__restrict__ status) {
+    __shared__ double2 sRed[4][NP * 9];
+    __shared__ double2 sTr[4][NP >= 64 ? 64 : 128];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (__builtin_amdgcn_readfirstlane(fac.fmt[s]) != kFmtLDL) return;
+    double2 x = lane < n ? I[(size_t)s * n + lane] : make_double2(0.0, 0.0);
+    x = ldl_backward<NP, 2>(x, fac.L + (size_t)s * NP * NP, n, lane, sRed[wv], sTr[wv]);
+    bool nonfinite = false;
+    if (lane < n) {
+        I[(size_t)s * n + lane] = x;
+        nonfinite = !(isfinite(x.x) && isfinite(x.y));
+    }
+    if (__ballot(nonfinite) != 0 && lane == 0) status[s] |= COSIM_SYS_NONFINITE;
+}
+
+template <int NP>
+__global__ __launch_bounds__(256) void k_forward(int n, int S, GJFactor fac,
+                                                 double2 *__restrict__ I,
+                                                 int32_t *__restrict__ status) {
+    const int s = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
+    if (s >= S) return;
+    forward_system<NP>(s, n, fac, I, status);
 }
 
 // One wave per system, four per block.
@@ -843,6 +887,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     const int s = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
     if (s >= S) return;  // whole wave; the block never synchronises
     ldl_system<NP>(s, n, F, M, Rv, C, omega, phi, fac, Z, status);
+}
+
+template <int NP>
+__global__ __launch_bounds__(256) void k_forward_group(SmallGroup g, int S) {
+    const int sg = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
+    if (sg >= S) return;
+    const SmallInst &e = g.in[group_member(g, sg)];
+    forward_system<NP>(sg - e.s0, e.n, e.fac, e.I, e.status);
 }
 
 // The same over the S systems of a group of plans (each wave resolves its own
@@ -873,7 +925,7 @@ __device__ __forceinline__ void replay_system(int s, int n, int S, int F, GJFact
                                               double2 *__restrict__ mu,
                                               int32_t *__restrict__ status) {
     __shared__ double2 sRed[4][NP * 9];  // per wave: the lane products of ldl_backward
-    __shared__ double2 sTr[4][64];       // per wave: an 8x8 block of L, transposed
+    __shared__ double2 sTr[4][NP >= 64 ? 64 : 128];  // per wave: an 8x8 block of L, transposed
     const int lane = threadIdx.x & 63;
     const int fmt = __builtin_amdgcn_readfirstlane(fac.fmt[s]);
     const int b = s / F, f = s - b * F;
@@ -1076,10 +1128,12 @@ hipError_t launch_ldl(int NP, int n, int S, int F, const double *M_d, const doub
         case 32:
             hipLaunchKernelGGL(k_ldl<32>, grid, dim3(256), 0, st, n, S, F, M_d, R_d, C_d, omega_d,
                                phi_d, fac, I_d, status_d);
+            hipLaunchKernelGGL(k_forward<32>, grid, dim3(256), 0, st, n, S, fac, I_d, status_d);
             break;
         case 64:
             hipLaunchKernelGGL(k_ldl<64>, grid, dim3(256), 0, st, n, S, F, M_d, R_d, C_d, omega_d,
                                phi_d, fac, I_d, status_d);
+            hipLaunchKernelGGL(k_forward<64>, grid, dim3(256), 0, st, n, S, fac, I_d, status_d);
             break;
         default:
             return hipErrorInvalidValue;
@@ -1146,6 +1200,7 @@ hipError_t launch_small_group(int NP, const SmallGroup &g, int S, SmallPhase pha
     switch (phase) {                                                                             \
         case SmallPhase::Factor:                                                                 \
             hipLaunchKernelGGL(k_ldl_group<NPC>, wave_grid, dim3(256), 0, st, g, S);             \
+            hipLaunchKernelGGL(k_forward_group<NPC>, wave_grid, dim3(256), 0, st, g, S);         \
             break;                                                                               \
         case SmallPhase::Fallback:                                                               \
             hipLaunchKernelGGL(k_gj_group<NPC>, dim3(S), dim3(GJShape<NPC>::BLOCK), 0, st, g);   \
