@@ -53,7 +53,7 @@ __device__ inline void split_pair(float a, float b, unsigned &hi, unsigned &lo) 
 // Operands of one 16x16 tile and one step of 32 K: 8 consecutive K per lane
 // (lane group q = lane / 16 holds K entries 8q..8q+7).
 struct GBF3 {
-    static constexpr int ESZ = 2, PLANES = 2, BM = 128, BN = 128, WM = 2, WN = 2;
+    static constexpr int ESZ = 2, PLANES = 2, BM = 256, BN = 128, WM = 4, WN = 2;
     typedef float Acc;
     typedef f32x4 V;
     struct Op {
@@ -394,8 +394,8 @@ hipError_t go_pair(int loss_mode, bool grad, const GemmArgs &fw, const GemmArgs 
 
 GemmShape gemm_shape(Prec prec, int NP, int S, int P_pad) {
     GemmShape g;
-    const int BM = prec == Prec::F64 ? GF64::BM : GBF3::BM;
-    const int BN = prec == Prec::F64 ? GF64::BN : GBF3::BN;
+    const int BM = prec == Prec::F64 ? GF64::BM : prec == Prec::F32 ? GF32::BM : GBF3::BM;
+    const int BN = prec == Prec::F64 ? GF64::BN : prec == Prec::F32 ? GF32::BN : GBF3::BN;
     g.N = (2 * S + BN - 1) / BN * BN;
     g.row_blocks = (P_pad + BM - 1) / BM;
     // adjoint chunks of points: FP32 accumulation over at most kMfmaRowsF32
