@@ -18,10 +18,11 @@
 // and stored to LDS while the step before is multiplied (two LDS buffers, two
 // register sets, one barrier per step).  Each wave multiplies a (BM / WM) x (BN / WN) block with 16x16
 // matrix-core tiles: BF16X3 (hi hi + hi lo + lo hi into FP32), FP32 or FP64,
-// the same products as the fused kernel.  BF16X3 and FP32 use 128 x 128 tiles
-// of 4 waves, so that two workgroups share a compute unit and one's barrier
-// waits overlap the other's products; FP64 (bound by its matrix-core rate)
-// 128 x 64 tiles of 8 waves.
+// the same products as the fused kernel.  BF16X3 uses 256 x 128 tiles of 8
+// waves (one workgroup per compute unit: fewer operand bytes per product),
+// FP32 128 x 128 tiles of 4 waves (two workgroups per compute unit, one's
+// barrier waits overlapping the other's products), FP64 (bound by its
+// matrix-core rate) 128 x 64 tiles of 8 waves.
 #include <algorithm>
 
 #include "epilogue.h"
