@@ -750,15 +750,21 @@ __device__ __forceinline__ void ldl_system(
             // 1. panel columns -> LDS (rows >= k0 matter)
             if (c16 >= PW * h && c16 < PW * h + PW) {
                 const int c = c16 - PW * h;
+                // real parts, then imaginary parts: 8-byte stores straight from
+                // the accumulators (the empty asm keeps the two halves from
+                // being merged into 16-byte stores, which need register copies)
 #pragma unroll
                 for (int bi = bc; bi < NB; ++bi) {
                     const int bx = bi * (bi + 1) / 2 + bc;
 #pragma unroll
-                    for (int m = 0; m < 4; ++m) {  // two 8-byte stores: no register pairing
-                        double *e = &pan[16 * bi + g + 4 * m][c].x;
-                        e[0] = Xr[bx][m];
-                        e[1] = Xi[bx][m];
-                    }
+                    for (int m = 0; m < 4; ++m) pan[16 * bi + g + 4 * m][c].x = Xr[bx][m];
+                }
+                asm volatile("" ::: "memory");
+#pragma unroll
+                for (int bi = bc; bi < NB; ++bi) {
+                    const int bx = bi * (bi + 1) / 2 + bc;
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) pan[16 * bi + g + 4 * m][c].y = Xi[bx][m];
                 }
             }
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -784,8 +790,11 @@ __device__ __forceinline__ void ldl_system(
                 const double2 d = make_double2(readlane_d(v.x, k0 + c), readlane_d(v.y, k0 + c));
                 const double2 dinv = cinv_nr(d);
                 l[c] = cmul(v, dinv);
-                // L below the diagonal (rows of the diagonal block and below it)
-                if (r > k0 + c && r < NP) Ls[ldl_col(NP, k0 + c) + r - (k0 + c) - 1] = l[c];
+                // L below the diagonal (rows of the diagonal block and below
+                // it); the column's base is wave-uniform, so the store takes a
+                // scalar base and the lane's constant offset
+                double2 *col = Ls + (ldl_col(NP, k0 + c) - (k0 + c) - 1);
+                if (r > k0 + c && r < NP) col[r] = l[c];
                 if (r < NP) {
                     pan[r][c] = l[c];
                     vv[r][c] = v;
