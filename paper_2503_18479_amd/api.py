@@ -364,36 +364,59 @@ class Plan:
         return hist, st
 
 
+class ManyCall:
+    """One cosim_loss_and_grad_many call over fixed lists of instances, with
+    the tensors checked and the pointer arrays built once: run() enqueues the
+    call again on the current stream and returns outs, recomputed from the
+    current contents of Cs, omegas and Ts (update them in place; the tensors
+    themselves must stay the ones given).  For repeated steps over many
+    instances this saves the per-call argument checks (about 6 per instance)."""
+
+    def __init__(self, plans, Cs, omegas, Ts, loss_mode: int = LOSS_MAG, precision=FP32,
+                 grad: bool = True, outs=None):
+        self.lib = load_library()
+        k = self.k = len(plans)
+        if not (len(Cs) == len(omegas) == len(Ts) == k):
+            raise ValueError("plans, Cs, omegas and Ts must have equal lengths")
+        self.prec = precision_code(precision)
+        self.loss_mode = int(loss_mode)
+        self.plans = list(plans)
+        Bs = [int(C.shape[0]) for C in Cs]
+        Fs = [int(o.shape[0]) for o in omegas]
+        if outs is None:
+            outs = []
+            for pl, B, F in zip(plans, Bs, Fs):
+                outs.append((torch.empty((B,), dtype=torch.float64, device=pl.device),
+                             torch.empty((B, pl.n), dtype=torch.float64, device=pl.device) if grad else None,
+                             torch.empty((B, F), dtype=torch.int32, device=pl.device)))
+        self.outs = outs
+        self._keep = (list(Cs), list(omegas), list(Ts))  # the arrays point into these
+        ptrs = lambda xs: (ctypes.c_void_p * k)(*[ctypes.c_void_p(x) for x in xs])
+        self.arr_p = (ctypes.c_void_p * k)(*[pl._h for pl in plans])
+        self.arr_B = (ctypes.c_int * k)(*Bs)
+        self.arr_F = (ctypes.c_int * k)(*Fs)
+        self.c_p = ptrs([_dev(C, torch.float64, (B, pl.n), "C").value for C, B, pl in zip(Cs, Bs, plans)])
+        self.o_p = ptrs([_dev(o, torch.float64, (F,), "omega").value for o, F in zip(omegas, Fs)])
+        self.t_p = ptrs([_dev(T, torch.float64, (pl.P,), "T").value for T, pl in zip(Ts, plans)])
+        self.l_p = ptrs([o[0].data_ptr() for o in outs])
+        self.g_p = ptrs([o[1].data_ptr() for o in outs]) if grad else None
+        self.s_p = ptrs([o[2].data_ptr() for o in outs])
+
+    def run(self):
+        for pl in self.plans:
+            pl._gen += 1
+        check(self.lib.cosim_loss_and_grad_many(self.k, self.arr_p, self.arr_B, self.arr_F, self.c_p,
+                                                self.o_p, self.t_p, self.loss_mode, self.prec,
+                                                self.l_p, self.g_p, self.s_p, _stream()))
+        return self.outs
+
+
 def loss_and_grad_many(plans, Cs, omegas, Ts, loss_mode: int = LOSS_MAG, precision=FP32,
                        grad: bool = True, outs=None):
     """cosim_loss_and_grad_many over independent instances (lists of equal
-    length).  Returns lists of per-instance (loss, grad or None, status)."""
-    lib = load_library()
-    k = len(plans)
-    prec = precision_code(precision)
-    for pl in plans:
-        pl._gen += 1
-    Bs = [int(C.shape[0]) for C in Cs]
-    Fs = [int(o.shape[0]) for o in omegas]
-    if outs is None:
-        outs = []
-        for pl, B, F in zip(plans, Bs, Fs):
-            outs.append((torch.empty((B,), dtype=torch.float64, device=pl.device),
-                         torch.empty((B, pl.n), dtype=torch.float64, device=pl.device) if grad else None,
-                         torch.empty((B, F), dtype=torch.int32, device=pl.device)))
-    ptrs = lambda xs: (ctypes.c_void_p * k)(*[ctypes.c_void_p(x) for x in xs])
-    arr_p = (ctypes.c_void_p * k)(*[pl._h for pl in plans])
-    arr_B = (ctypes.c_int * k)(*Bs)
-    arr_F = (ctypes.c_int * k)(*Fs)
-    c_p = ptrs([_dev(C, torch.float64, (B, pl.n), "C").value for C, B, pl in zip(Cs, Bs, plans)])
-    o_p = ptrs([_dev(o, torch.float64, (F,), "omega").value for o, F in zip(omegas, Fs)])
-    t_p = ptrs([_dev(T, torch.float64, (pl.P,), "T").value for T, pl in zip(Ts, plans)])
-    l_p = ptrs([o[0].data_ptr() for o in outs])
-    g_p = ptrs([o[1].data_ptr() for o in outs]) if grad else None
-    s_p = ptrs([o[2].data_ptr() for o in outs])
-    check(lib.cosim_loss_and_grad_many(k, arr_p, arr_B, arr_F, c_p, o_p, t_p, int(loss_mode), prec,
-                                       l_p, g_p, s_p, _stream()))
-    return outs
+    length).  Returns lists of per-instance (loss, grad or None, status).
+    For repeated calls over the same tensors, ManyCall checks them once."""
+    return ManyCall(plans, Cs, omegas, Ts, loss_mode, precision, grad, outs).run()
 
 
 def capture_loss_and_grad_many(plans, Cs, omegas, Ts, loss_mode: int = LOSS_MAG,

@@ -257,3 +257,11 @@ def test_component_and_drive_argument_errors(lib):
 
 def test_refinement_argument_errors(lib):
     assert lib.cosim_plan_set_refinement(None, 1, 8, 0.0) == EINVAL
+
+
+def test_many_call_checks_list_lengths():
+    """ManyCall refuses instance lists of unequal lengths before touching a
+    plan or tensor (no GPU needed)."""
+    from paper_2503_18479_amd import ManyCall
+    with pytest.raises(ValueError):
+        ManyCall([object()], [], [], [])

@@ -1209,6 +1209,32 @@ def test_ragged_graph_replay_matches_eager(dev):
         del gr
 
 
+def test_many_call_reruns_match_fresh_calls(dev):
+    """ManyCall checks its instances once; each run() after the capacitances
+    are updated in place equals a fresh loss_and_grad_many call bit for bit,
+    including the loss-only form."""
+    from paper_2503_18479_amd import Geometry, Plan, ManyCall, loss_and_grad_many
+    wls = [W.small_array(3, 2, batch=5, grid=20, n_freq=3, seed=41),
+           W.small_array(5, 5, batch=4, grid=17, n_freq=2, seed=42),
+           W.small_array(9, 9, batch=3, grid=40, n_freq=2, seed=43)]
+    plans = [Plan(Geometry.from_workload(w.geom), torch.tensor(w.pts, device=dev), w.bext_z)
+             for w in wls]
+    Cs = [torch.tensor(w.C, device=dev) for w in wls]
+    Os = [torch.tensor(w.omega, device=dev) for w in wls]
+    Ts = [torch.tensor(w.target, device=dev) for w in wls]
+    for prec, grad in ((0, True), (2, True), (2, False)):
+        call = ManyCall(plans, Cs, Os, Ts, precision=prec, grad=grad)
+        for rep in range(2):
+            for C in Cs:
+                C.mul_(1.0 + 0.02 * (rep + 1))
+            outs = call.run()
+            ref = loss_and_grad_many(plans, Cs, Os, Ts, precision=prec, grad=grad)
+            torch.cuda.synchronize()
+            for (l, g, st), (lr, g_r, sr) in zip(outs, ref):
+                assert torch.equal(l, lr) and torch.equal(st, sr), (prec, grad, rep)
+                assert (g is None and g_r is None) or torch.equal(g, g_r), (prec, grad, rep)
+
+
 def test_grouped_large_instances_match_single_calls(dev):
     """Instances above 64 loops of one size are factored and solved together
     by cosim_loss_and_grad_many: three of 81 loops (different batches,
