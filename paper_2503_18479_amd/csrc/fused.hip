@@ -443,25 +443,46 @@ __device__ __forceinline__ void bf3_epilogue(const float *__restrict__ sT, int r
 // transposed LDS tile (row stride LDT).  BATCH blocks of 16 loops have their
 // operands read from LDS together, before their products (BATCH > 1 trades
 // registers for fewer exposed LDS latencies).
-template <int NP, int NB, int LDT, int BATCH = 1>
+// A operands of the adjoint for loop blocks ib0 .. ib0 + BATCH - 1:
+// Gt[i = 16 ib + r16][p = pi(8q + j)] from the LDS tile.
+template <int LDT, int BATCH>
+__device__ __forceinline__ void bf3_adjoint_load(const uint16_t *__restrict__ ctH,
+                                                 const uint16_t *__restrict__ ctL, int col0,
+                                                 int r16, int q, int ib0, bf16x8 (&th)[BATCH],
+                                                 bf16x8 (&tl)[BATCH]) {
+#pragma unroll
+    for (int u = 0; u < BATCH; ++u) {
+        const int base = (16 * (ib0 + u) + r16) * LDT + col0 + 4 * q;
+        const s16x4 h0 = *(const s16x4 *)(ctH + base), h1 = *(const s16x4 *)(ctH + base + 16);
+        const s16x4 l0 = *(const s16x4 *)(ctL + base), l1 = *(const s16x4 *)(ctL + base + 16);
+        th[u] = __builtin_bit_cast(bf16x8, __builtin_shufflevector(h0, h1, 0, 1, 2, 3, 4, 5, 6, 7));
+        tl[u] = __builtin_bit_cast(bf16x8, __builtin_shufflevector(l0, l1, 0, 1, 2, 3, 4, 5, 6, 7));
+    }
+}
+
+// The adjoint's products of one 32-row sub-tile.  PRE: the first batch's
+// operands were loaded by the caller (pth, ptl).
+template <int NP, int NB, int LDT, int BATCH = 1, bool PRE = false>
 __device__ __forceinline__ void bf3_adjoint(const uint16_t *__restrict__ ctH,
                                             const uint16_t *__restrict__ ctL, int col0, int r16,
                                             int q, const bf16x8 (&wrh)[NB],
                                             const bf16x8 (&wrl)[NB], const bf16x8 (&wih)[NB],
                                             const bf16x8 (&wil)[NB],
-                                            f32x4 (&racc)[NP / 16][NB][2]) {
+                                            f32x4 (&racc)[NP / 16][NB][2],
+                                            const bf16x8 *pth = nullptr,
+                                            const bf16x8 *ptl = nullptr) {
     static_assert((NP / 16) % BATCH == 0, "whole batches of loop blocks");
 #pragma unroll
     for (int ib0 = 0; ib0 < NP / 16; ib0 += BATCH) {
         bf16x8 th[BATCH], tl[BATCH];
+        if (PRE && ib0 == 0) {
 #pragma unroll
-        for (int u = 0; u < BATCH; ++u) {
-            // A operand: Gt[i = 16 ib + r16][p = pi(8q + j)]
-            const int base = (16 * (ib0 + u) + r16) * LDT + col0 + 4 * q;
-            const s16x4 h0 = *(const s16x4 *)(ctH + base), h1 = *(const s16x4 *)(ctH + base + 16);
-            const s16x4 l0 = *(const s16x4 *)(ctL + base), l1 = *(const s16x4 *)(ctL + base + 16);
-            th[u] = __builtin_bit_cast(bf16x8, __builtin_shufflevector(h0, h1, 0, 1, 2, 3, 4, 5, 6, 7));
-            tl[u] = __builtin_bit_cast(bf16x8, __builtin_shufflevector(l0, l1, 0, 1, 2, 3, 4, 5, 6, 7));
+            for (int u = 0; u < BATCH; ++u) {
+                th[u] = pth[u];
+                tl[u] = ptl[u];
+            }
+        } else {
+            bf3_adjoint_load<LDT, BATCH>(ctH, ctL, col0, r16, q, ib0, th, tl);
         }
         if constexpr (BATCH > 1) __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -763,6 +784,20 @@ __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
     __builtin_amdgcn_sched_barrier(0);
 }
+// The same with `issue` (LDS loads of data that an earlier barrier already
+// published) placed after the release fence, so that they are in flight
+// while the wave waits at the barrier.
+template <typename F>
+__device__ __forceinline__ void lds_barrier_then(F &&issue) {
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_sched_barrier(0);
+    issue();
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+    __builtin_amdgcn_sched_barrier(0);
+}
 
 // An empty use of a register value: the value has to be computed before
 // this point, which keeps the compiler from sinking a phase's arithmetic past
@@ -826,10 +861,26 @@ __global__ __launch_bounds__(512, 1) void k_fused_bf16x3_pp(FusedArgs a) {
     // one block.
     f32x4 br[2][NB], bi[2][NB];
     bf16x8 wrh[NB], wrl[NB], wih[NB], wil[NB];
+    // The first operand batch of adjoint(jj) is loaded during the barrier
+    // that ends vector phase jj: its tile was published one matrix-core
+    // phase earlier (forward(jj) read it), and its buffer is not stored again
+    // before adjoint(jj) has run, so the loads wait for nothing and the
+    // matrix-core phase starts on operands already in registers.
+    bf16x8 pth[2], ptl[2];
+    auto preload = [&](int jj) {
+        const int bf = (jj / SPT) & 1;
+        bf3_adjoint_load<LDT, 2>(tH[bf], tL[bf], 32 * (jj % SPT), r16, q, 0, pth, ptl);
+    };
     auto adjoint = [&](int jj) {
         const int bf = (jj / SPT) & 1;
-        bf3_adjoint<NP, NB, LDT, 2>(tH[bf], tL[bf], 32 * (jj % SPT), r16, q, wrh, wrl, wih, wil,
-                                    racc);
+        bf3_adjoint<NP, NB, LDT, 2, true>(tH[bf], tL[bf], 32 * (jj % SPT), r16, q, wrh, wrl, wih,
+                                          wil, racc, pth, ptl);
+    };
+    auto end_vector_phase = [&](int j) {
+        if constexpr (GRAD)
+            lds_barrier_then([&] { preload(j); });
+        else
+            lds_barrier();
     };
     auto forward = [&](int j) {
         const int bf = (j / SPT) & 1;
@@ -889,7 +940,7 @@ __global__ __launch_bounds__(512, 1) void k_fused_bf16x3_pp(FusedArgs a) {
         keep_forward();
         lds_barrier();
         vector_phase(0);
-        lds_barrier();
+        end_vector_phase(0);
 #pragma unroll 1
         for (int j = 1; j < nsub; ++j) {
             if (GRAD) adjoint(j - 1);
@@ -898,7 +949,7 @@ __global__ __launch_bounds__(512, 1) void k_fused_bf16x3_pp(FusedArgs a) {
             keep_forward();
             lds_barrier();
             vector_phase(j);
-            lds_barrier();
+            end_vector_phase(j);
         }
         if (GRAD) {
             adjoint(nsub - 1);
