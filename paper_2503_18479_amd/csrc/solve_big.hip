@@ -542,14 +542,10 @@ __global__ __launch_bounds__(kTB) void k_ldl_big_panel(int NP, int k0, int S,
             Vr[bi][bj] = V4{0, 0, 0, 0};
             Vi[bi][bj] = V4{0, 0, 0, 0};
         }
-#pragma unroll 4
-    for (int ks = 0; ks < 16; ++ks) {
-        T2 a[2], t[2];
+    auto step = [&](int ks, const T2 (&t)[2]) {
+        T2 a[2];
 #pragma unroll
-        for (int b2 = 0; b2 < 2; ++b2) {
-            a[b2] = sv[wr + 16 * b2 + r16][16 * g + ks];
-            t[b2] = Tm[ks * 64 + 16 * b2];
-        }
+        for (int b2 = 0; b2 < 2; ++b2) a[b2] = sv[wr + 16 * b2 + r16][16 * g + ks];
 #pragma unroll
         for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
@@ -559,6 +555,35 @@ __global__ __launch_bounds__(kTB) void k_ldl_big_panel(int NP, int k0, int S,
                 Vi[bi][bj] = mfma4(a[bi].x, t[bj].y, Vi[bi][bj]);
                 Vi[bi][bj] = mfma4(a[bi].y, t[bj].x, Vi[bi][bj]);
             }
+    };
+    if constexpr (sizeof(T) == 8) {
+        // FP64: the T operands of two steps loaded one pair ahead into the
+        // other of two register sets (unrolled: the sets alternate in place)
+        T2 t0[2][2], t1[2][2];
+        auto load = [&](int ks, T2 (&t)[2][2]) {
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int b2 = 0; b2 < 2; ++b2) t[u][b2] = Tm[(ks + u) * 64 + 16 * b2];
+        };
+        load(0, t0);
+#pragma unroll
+        for (int ks = 0; ks < 16; ks += 4) {
+            load(ks + 2, t1);
+            step(ks, t0[0]);
+            step(ks + 1, t0[1]);
+            if (ks + 4 < 16) load(ks + 4, t0);
+            step(ks + 2, t1[0]);
+            step(ks + 3, t1[1]);
+        }
+    } else {
+#pragma unroll 4
+        for (int ks = 0; ks < 16; ++ks) {
+            T2 t[2];
+#pragma unroll
+            for (int b2 = 0; b2 < 2; ++b2) t[b2] = Tm[ks * 64 + 16 * b2];
+            step(ks, t);
+        }
     }
     __syncthreads();  // every wave is done reading A21
 #pragma unroll
