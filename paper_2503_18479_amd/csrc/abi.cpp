@@ -1229,7 +1229,7 @@ struct ManyCall {
 };
 
 // Instances of 64 loops or fewer of one padded size (group `group`, stream k of
-// the pool): factorisation, fallback and forward replay in shared launches on
+// the pool): factorisation with the forward solve, and the fallback, in shared launches on
 // stream k, the contractions in one shared launch there too (or, unless every
 // member uses variant 0, one per member on the other side streams), then the
 // adjoint replay and the final sums.

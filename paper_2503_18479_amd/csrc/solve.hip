@@ -654,11 +654,12 @@ __device__ __forceinline__ double2 ldl_backward(double2 x, const double2 *__rest
 // Wider panels halve the LDS round trips and wave barriers per column, which
 // with one wave per system are latency that the MFMAs do not hide.
 // Columns left of the trailing part also receive updates; they are finished
-// and never read again.  The factor is recorded (L by columns, D^-1) for the
-// replay kernels, and the forward right-hand side b = E - j w Phi rides along:
-// y = L^-1 b is formed panel by panel and z = D^-1 y is written to Z, so that
-// the forward replay only runs the backward substitution.  A system whose smallest pivot is below 1e-5 of its largest
-// impedance diagonal (or is not finite) is marked for the pivoted fallback.
+// and never read again.  The factor is recorded (L by columns, D^-1) for
+// k_forward and the adjoint, and the forward right-hand side b = E - j w Phi
+// rides along: y = L^-1 b is formed panel by panel and z = D^-1 y is written
+// to Z, so that k_forward only runs the backward substitution.  A system whose
+// smallest pivot is below 1e-5 of its largest impedance diagonal (or is not
+// finite) is marked for the pivoted fallback.
 // The accumulators and the row state fit 256 registers, so two systems share
 // a SIMD: one wave's panel elimination runs while the other's MFMAs do.
 template <int NP>
