@@ -439,10 +439,6 @@ __device__ __forceinline__ void bf3_epilogue(const float *__restrict__ sT, int r
     }
 }
 
-// Adjoint: racc += G^T w over the 32 rows starting at column col0 of the
-// transposed LDS tile (row stride LDT).  BATCH blocks of 16 loops have their
-// operands read from LDS together, before their products (BATCH > 1 trades
-// registers for fewer exposed LDS latencies).
 // A operands of the adjoint for loop blocks ib0 .. ib0 + BATCH - 1:
 // Gt[i = 16 ib + r16][p = pi(8q + j)] from the LDS tile.
 template <int LDT, int BATCH>
@@ -460,7 +456,10 @@ __device__ __forceinline__ void bf3_adjoint_load(const uint16_t *__restrict__ ct
     }
 }
 
-// The adjoint's products of one 32-row sub-tile.  PRE: the first batch's
+// Adjoint: racc += G^T w over the 32 rows starting at column col0 of the
+// transposed LDS tile (row stride LDT).  BATCH blocks of 16 loops have their
+// operands read from LDS together, before their products (BATCH > 1 trades
+// registers for fewer exposed LDS latencies).  PRE: the first batch's
 // operands were loaded by the caller (pth, ptl).
 template <int NP, int NB, int LDT, int BATCH = 1, bool PRE = false>
 __device__ __forceinline__ void bf3_adjoint(const uint16_t *__restrict__ ctH,
