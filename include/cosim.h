@@ -375,7 +375,7 @@ int cosim_adam_step(int count, double *C_d, const double *grad_d, double *m_d, d
  * reserve every plan beforehand.
  * Outside stream capture, instances with every R_k > 0 (no refinement, no
  * phase timing) that share a padded loop count are factored and solved in
- * shared launches (up to 16 per launch for 64 loops or fewer, 24 above), and
+ * shared launches (up to 24 per launch for 64 loops or fewer, 32 above), and
  * their final sums run in one launch per group; their results equal their
  * own calls bit for bit.  Above 64 loops their factor records live in a
  * library-owned workspace per device, grown (after a device

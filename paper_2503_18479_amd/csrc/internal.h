@@ -151,7 +151,7 @@ int fused_blocks_per_cu(Prec prec, int NP, int variant);
 // The fused contraction of several plans (64 loops or fewer, one precision,
 // variant 0) in one launch: member m owns workgroups [first[m], first[m + 1])
 // (the last up to the launch's total), bx[m] system blocks times its chunks.
-constexpr int kFusedGroupMax = 16;
+constexpr int kFusedGroupMax = 24;
 struct FusedGroup {
     int count;
     int first[kFusedGroupMax];
@@ -207,7 +207,7 @@ hipError_t big_solve(const BigFactor &bf, const BigRefine &rf, int NP, int n, in
 // Instances of one padded size above 64 loops factored and solved together,
 // each system as it would be alone (GroupArgs travels by value in the kernel
 // arguments; s0 numbers the systems instance after instance).
-constexpr int kGroupMax = 24;
+constexpr int kGroupMax = 32;
 struct GroupInst {
     const double *M, *R, *phi, *C, *omega;
     double2 *I;        // [S][n] currents
@@ -225,7 +225,7 @@ struct GroupArgs {
 // Plans of 64 loops or fewer with every R_k > 0, grouped the same way: each
 // member keeps its own factor record (fac) and workspace; members are stored
 // in order of their first system s0 within the group.
-constexpr int kSmallGroupMax = 16;
+constexpr int kSmallGroupMax = 24;
 static_assert(kSmallGroupMax <= kFusedGroupMax, "a small group's contractions fit one FusedGroup");
 struct SmallInst {
     const double *M, *R, *phi, *C, *omega;
@@ -312,7 +312,10 @@ struct MfmaGroup {
     int first[kGroupMax] = {};
     MfmaArgs in[kGroupMax];
 };
-static_assert(sizeof(MfmaGroup) <= 4096, "kernel arguments are limited to 4 KB");
+static_assert(sizeof(MfmaGroup) <= 4096 && sizeof(GroupArgs) <= 4096 &&
+                  sizeof(SmallGroup) <= 4096 && sizeof(FusedGroup) <= 4096 &&
+                  sizeof(ReduceGroup) <= 4096,
+              "group descriptors go by value: kernel arguments are limited to 4 KB");
 hipError_t launch_mfma_group(Prec prec, bool grad, int loss_mode, const MfmaGroup &g, int blocks,
                              int waves, hipStream_t st);
 
