@@ -31,7 +31,9 @@ if ROOT not in sys.path:
 
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}
 PREC_CODE = {"fp64": 0, "fp32": 1, "bf16x3": 2}
-FUSED_KERNEL_SRC = os.path.join(ROOT, "paper_2503_18479_amd", "csrc", "fused.hip")
+# the sources the fused kernel is compiled from (the traffic record names their hash)
+FUSED_KERNEL_SRCS = [os.path.join(ROOT, "paper_2503_18479_amd", "csrc", f)
+                     for f in ("fused.hip", "epilogue.h", "internal.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fused_traffic.json")
 
 
@@ -82,9 +84,12 @@ def parse():
     return ap.parse_args()
 
 
-def _src_hash(path: str) -> str:
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+def _src_hash(paths) -> str:
+    h = hashlib.sha256()
+    for path in paths:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def time_mode(plan, C, om, T, prec: str, steps: int, warmup: int, torch, tune: bool = True):
@@ -547,7 +552,7 @@ def main():
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as f:
             tr = json.load(f)
-        if (tr.get("kernel_src_sha256_16") == _src_hash(FUSED_KERNEL_SRC)
+        if (tr.get("kernel_src_sha256_16") == _src_hash(FUSED_KERNEL_SRCS)
                 and tr.get("precision") == args.mixed and tr.get("workload") == wl.name
                 and tr.get("batch") == wl.B and tr.get("points") == wl.P):
             traffic = (tr.get("variants") or {}).get(str(tuned_variant), {}).get("bytes_per_launch")

@@ -20,11 +20,13 @@ template <int LOSS>
 __device__ inline float epilogue_f(float &x, float &y, float t, float inc = 0.0f) {
     if (LOSS == COSIM_LOSS_RATIO) x += inc;
     if (LOSS == COSIM_LOSS_MAG || LOSS == COSIM_LOSS_RATIO) {
-        // |B|^2 is clamped to a normal floor before rsq: at B = 0 this gives
-        // e = -t (loss t^2) and w = c B = 0 without a branch; below |B| ~ 1e-18
-        // the magnitude's derivative is singular anyway.
-        const float m2 = fmaf(x, x, y * y);
-        const float rs = __builtin_amdgcn_rsqf(fmaxf(m2, 1e-36f));
+        // A normal floor of 1e-36 is added to |B|^2 (inside the products, at
+        // no extra instruction): at B = 0 this gives e = -t (loss t^2) and
+        // w = c B = 0 without a branch; above |B| ~ 1e-12 it is far below the
+        // rounding of |B|^2, and below |B| ~ 1e-18 the magnitude's derivative
+        // is singular anyway.
+        const float m2 = fmaf(x, x, fmaf(y, y, 1e-36f));
+        const float rs = __builtin_amdgcn_rsqf(m2);
         const float e = fmaf(m2, rs, -t);
         const float c = fmaf(-t, rs, 1.0f);
         x *= c;
