@@ -854,29 +854,75 @@ __device__ inline double2 rhs_entry(int k, int NP, const SysRef &r) {
 // dot products against the solved rows (wave r takes row r of the block and
 // stages its diagonal-block entries in LDS), then the 16x16 diagonal block
 // inside wave 0.  st: 16 entries, sd: 16 x 17 entries of LDS scratch.
-template <typename T2, bool PIV>
+//   The blocks follow one another, so each block's loads of its rows are
+// latency on the critical path.  With PF (rows of at most 64 kPf entries),
+// the next block's row entries (kPf per lane) and diagonal-block entries are
+// loaded while the current block's diagonal part is solved.  Identity swaps
+// (the records of the blocked LDL^T) are found by one vote and skipped.
+constexpr int kPf = 4;
+template <typename T2, bool PIV, bool PF>
 __device__ __forceinline__ void lu_apply_inverse(const T2 *__restrict__ A, const int *__restrict__ piv, int NP,
                                  double2 *sx, double2 *st, double2 (*sd)[17]) {
     const int tid = threadIdx.x;
     if (PIV) {
-        if (tid == 0) {
-            for (int j = 0; j < NP; ++j) {
-                const int p = piv[j];
-                if (p != j) {
-                    const double2 t = sx[j];
-                    sx[j] = sx[p];
-                    sx[p] = t;
+        int moved = 0;
+        for (int j = tid; j < NP; j += kTS) moved |= piv[j] != j;
+        if (__syncthreads_or(moved)) {
+            if (tid == 0) {
+                for (int j = 0; j < NP; ++j) {
+                    const int p = piv[j];
+                    if (p != j) {
+                        const double2 t = sx[j];
+                        sx[j] = sx[p];
+                        sx[p] = t;
+                    }
                 }
             }
+            __syncthreads();
         }
-        __syncthreads();
     }
     const int r = tid >> 6, q = tid & 63;
-    // forward: L y = P b, L unit lower
-    for (int r0 = 0; r0 < NP; r0 += 16) {
+    const double2 z = make_double2(0.0, 0.0);
+    // PF: entries j = j0 + 64 e (e < kPf) of row r0 + r inside [j0, j1)
+    // (others from column 0, always inside the row, and zeroed when used),
+    // and the diagonal-block entry of column r0 + (q & 15)
+    T2 pf[kPf], pd;
+    auto fetch = [&](int r0, int j0, int j1) {
         const T2 *row = A + (size_t)(r0 + r) * NP;
-        if (q < 16) sd[r][q] = ld2(row[r0 + q]);
-        const double2 acc = wave_sum(dot_run(row, sx, q, r0));
+#pragma unroll
+        for (int e = 0; e < kPf; ++e) {
+            const int j = j0 + 64 * e;
+            pf[e] = row[j < j1 ? j : 0];
+        }
+        pd = row[r0 + (q & 15)];
+    };
+    // row r0 + r against sx over [j0, j1) (PF: the prefetched entries)
+    auto dot = [&](int r0, int j0, int j1) {
+        double2 acc = z;
+        if constexpr (PF) {
+#pragma unroll
+            for (int e = 0; e < kPf; ++e) {
+                const int j = j0 + 64 * e;
+                const bool in = j < j1;
+                acc = zfma(acc, in ? ld2(pf[e]) : z, sx[in ? j : 0]);
+            }
+        } else {
+            acc = dot_run(A + (size_t)(r0 + r) * NP, sx, j0, j1);
+        }
+        return wave_sum(acc);
+    };
+    auto diag_entry = [&](int r0) {
+        if constexpr (PF)
+            return ld2(pd);
+        else
+            return ld2(A[(size_t)(r0 + r) * NP + r0 + (q & 15)]);
+    };
+    // forward: L y = P b, L unit lower; block r0 uses columns [0, r0)
+    if (PF) fetch(0, q, 0);
+    for (int r0 = 0; r0 < NP; r0 += 16) {
+        if (q < 16) sd[r][q] = diag_entry(r0);
+        const double2 acc = dot(r0, q, r0);
+        if (PF && r0 + 16 < NP) fetch(r0 + 16, q, r0 + 16);  // in flight across the diagonal block
         if (q == 0) st[r] = make_double2(sx[r0 + r].x - acc.x, sx[r0 + r].y - acc.y);
         __syncthreads();
         if (tid < 64) {
@@ -892,11 +938,12 @@ __device__ __forceinline__ void lu_apply_inverse(const T2 *__restrict__ A, const
         }
         __syncthreads();
     }
-    // backward: U x = y
+    // backward: U x = y; block r0 uses columns [r0 + 16, NP)
+    if (PF) fetch(NP - 16, NP + q, NP);
     for (int r0 = NP - 16; r0 >= 0; r0 -= 16) {
-        const T2 *row = A + (size_t)(r0 + r) * NP;
-        if (q < 16) sd[r][q] = ld2(row[r0 + q]);
-        const double2 acc = wave_sum(dot_run(row, sx, r0 + 16 + q, NP));
+        if (q < 16) sd[r][q] = diag_entry(r0);
+        const double2 acc = dot(r0, r0 + 16 + q, NP);
+        if (PF && r0 >= 16) fetch(r0 - 16, r0 + q, NP);
         if (q == 0) st[r] = make_double2(sx[r0 + r].x - acc.x, sx[r0 + r].y - acc.y);
         __syncthreads();
         if (tid < 64) {
@@ -973,8 +1020,12 @@ __global__ __launch_bounds__(kTS) void k_lu_solve(int NP, int S, Src src,
         sx[k] = k < r.n ? rhs_entry<RHS>(k, NP, r) : make_double2(0.0, 0.0);
     if (tid == 0) sFlag = 0;
     __syncthreads();
-    lu_apply_inverse<double2, true>(Aall + (size_t)s * NP * NP, pivall + (size_t)s * NP, NP, sx, st,
-                                    sd);
+    if (NP <= 64 * kPf)  // uniform over the launch
+        lu_apply_inverse<double2, true, true>(Aall + (size_t)s * NP * NP, pivall + (size_t)s * NP,
+                                              NP, sx, st, sd);
+    else
+        lu_apply_inverse<double2, true, false>(Aall + (size_t)s * NP * NP, pivall + (size_t)s * NP,
+                                               NP, sx, st, sd);
     write_solution<RHS>(r, sx, &sFlag);
 }
 
@@ -1050,7 +1101,7 @@ __global__ __launch_bounds__(kTS) void k_solve_refined(int NP, int S, OneInst sr
     double prev = 0.0;
     // step 0 solves for x_0 (d_0 = x_0); step i >= 1 for the correction d_i
     for (int it = 0; it <= max_iter; ++it) {
-        lu_apply_inverse<float2, false>(A, nullptr, NP, sr, st, sd);
+        lu_apply_inverse<float2, false, false>(A, nullptr, NP, sr, st, sd);
         double dm = 0.0, xm = 0.0;
         for (int k = tid; k < NP; k += kTS) {
             const double2 d = sr[k];
