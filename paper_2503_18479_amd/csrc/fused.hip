@@ -716,7 +716,9 @@ __global__ __launch_bounds__(256, 2) void k_fused_bf16x3_pipe(FusedArgs a) {
 // barrier that opens phase 4u.  Each group fetches its share of a tile into
 // registers right after storing the previous one, four phases ahead.
 // Barriers wait for LDS traffic only, so global loads stay in flight across
-// them.
+// them.  A wave raises its issue priority for its matrix-core phases, so that
+// where both waves of a SIMD have an instruction ready the products go first
+// (the other way round, the kernel runs 4% slower; with equal priorities 2%).
 template <int NP, int PT, bool GRAD>
 struct PpStage {
     static constexpr int NV = PT * NP / 8;  // 16-byte vectors per plane
@@ -935,17 +937,21 @@ __global__ __launch_bounds__(512, 1) void k_fused_bf16x3_pp(FusedArgs a) {
     };
     if (OFF && grp) lds_barrier();
     if (nsub > 0) {
+        __builtin_amdgcn_s_setprio(2);
         forward(0);
         keep_forward();
+        __builtin_amdgcn_s_setprio(0);
         lds_barrier();
         vector_phase(0);
         end_vector_phase(0);
 #pragma unroll 1
         for (int j = 1; j < nsub; ++j) {
+            __builtin_amdgcn_s_setprio(2);
             if (GRAD) adjoint(j - 1);
             forward(j);
             if (GRAD) keep_adjoint();
             keep_forward();
+            __builtin_amdgcn_s_setprio(0);
             lds_barrier();
             vector_phase(j);
             end_vector_phase(j);
