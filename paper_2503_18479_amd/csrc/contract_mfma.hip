@@ -186,8 +186,16 @@ constexpr size_t lds_bytes(int W) {
     return main > fin ? main : fin;
 }
 
-// The work of workgroup b of a launch for one set of arguments.
-template <class Pol, int MODE, int LOSS>
+// Loop steps per wave: two for up to 512 loops (more waves per workgroup, and
+// registers left to load each phase's operands one phase ahead), four above.
+__host__ __device__ constexpr int mfma_steps(int NP) { return NP <= 512 ? 2 : kMaxKs; }
+
+// The work of workgroup b of a launch for one set of arguments, with at most
+// KS loop steps per wave.  With KS = 2 (and operands of at most 32 bytes per
+// lane) the operands of G^T for the adjoint are loaded at the start of the
+// sub-tile and those of G for the next sub-tile after its forward product,
+// so that their loads are in flight across the barriers and the epilogue.
+template <class Pol, int MODE, int LOSS, int KS>
 __device__ __forceinline__ void mfma_block(const MfmaArgs &a, int b) {
     typedef typename Pol::Acc Acc;
     typedef typename Pol::V V;
@@ -221,7 +229,7 @@ __device__ __forceinline__ void mfma_block(const MfmaArgs &a, int b) {
 
     // currents of the block as forward B operands: column c of tile t is
     // system s0 + c % NS, real part for c < NS, imaginary part after
-    Op X[kMaxKs][NC];
+    Op X[KS][NC];
     if constexpr (FWD) {
 #pragma unroll
         for (int t = 0; t < NC; ++t) {
@@ -229,7 +237,7 @@ __device__ __forceinline__ void mfma_block(const MfmaArgs &a, int b) {
             const int s = s0 + col % NS;
             const bool im = col >= NS;
 #pragma unroll
-            for (int kk = 0; kk < kMaxKs; ++kk) {
+            for (int kk = 0; kk < KS; ++kk) {
                 double v[8];
 #pragma unroll
                 for (int j = 0; j < 8; ++j) {
@@ -242,17 +250,40 @@ __device__ __forceinline__ void mfma_block(const MfmaArgs &a, int b) {
             }
         }
     }
-    V racc[2 * kMaxKs][NC];
+    V racc[2 * KS][NC];
     if constexpr (ADJ) {
 #pragma unroll
-        for (int i = 0; i < 2 * kMaxKs; ++i)
+        for (int i = 0; i < 2 * KS; ++i)
 #pragma unroll
             for (int t = 0; t < NC; ++t) racc[i][t] = V{};
     }
     double lacc = 0.0;
     const int nthr = 64 * W;
 
+    constexpr bool PF = KS <= 2 && sizeof(Op) <= 32;
+    Op ga[KS][2], gt[2 * KS];  // operands loaded ahead (PF)
+    auto load_g = [&](int p, int kk, int h) {
+        return Pol::load(a.G, a.Glo, (size_t)(p + 16 * h + r16) * NP + 32 * (kb + kk) + 8 * q);
+    };
+    auto load_gt = [&](int p, int kt) {
+        return Pol::load(a.GT, a.GTlo, (size_t)(32 * kb + 16 * kt + r16) * a.P_pad + p + 8 * q);
+    };
+    auto prefetch_g = [&](int p) {
+#pragma unroll
+        for (int kk = 0; kk < KS; ++kk)
+            if (kk < ks)
+#pragma unroll
+                for (int h = 0; h < 2; ++h) ga[kk][h] = load_g(p, kk, h);
+    };
+    if constexpr (PF && FWD)
+        if (pb < pe) prefetch_g(pb);
+
     for (int p0 = pb; p0 < pe; p0 += kSub) {
+        if constexpr (PF && ADJ) {
+#pragma unroll
+            for (int kt = 0; kt < 2 * KS; ++kt)
+                if (kt < 2 * ks) gt[kt] = load_gt(p0, kt);
+        }
         // 1. partial B of this wave's loop range
         if constexpr (FWD) {
             V facc[2][NC];
@@ -261,17 +292,18 @@ __device__ __forceinline__ void mfma_block(const MfmaArgs &a, int b) {
 #pragma unroll
                 for (int t = 0; t < NC; ++t) facc[h][t] = V{};
 #pragma unroll
-            for (int kk = 0; kk < kMaxKs; ++kk) {
+            for (int kk = 0; kk < KS; ++kk) {
                 if (kk < ks) {  // uniform over the wave
 #pragma unroll
                     for (int h = 0; h < 2; ++h) {
-                        const size_t off = (size_t)(p0 + 16 * h + r16) * NP + 32 * (kb + kk) + 8 * q;
-                        const Op A = Pol::load(a.G, a.Glo, off);
+                        const Op A = PF ? ga[kk][h] : load_g(p0, kk, h);
 #pragma unroll
                         for (int t = 0; t < NC; ++t) facc[h][t] = Pol::mma(A, X[kk][t], facc[h][t]);
                     }
                 }
             }
+            if constexpr (PF)
+                if (p0 + kSub < pe) prefetch_g(p0 + kSub);
             Acc *rw = red + (size_t)wave * kSub * RS;
 #pragma unroll
             for (int h = 0; h < 2; ++h)
@@ -336,10 +368,9 @@ __device__ __forceinline__ void mfma_block(const MfmaArgs &a, int b) {
             __syncthreads();  // w visible
             // 3. r += G^T w for this wave's loops: 16 loops per tile
 #pragma unroll
-            for (int kt = 0; kt < 2 * kMaxKs; ++kt) {
+            for (int kt = 0; kt < 2 * KS; ++kt) {
                 if (kt < 2 * ks) {
-                    const size_t off = (size_t)(32 * kb + 16 * kt + r16) * a.P_pad + p0 + 8 * q;
-                    const Op A = Pol::load(a.GT, a.GTlo, off);
+                    const Op A = PF ? gt[kt] : load_gt(p0, kt);
 #pragma unroll
                     for (int t = 0; t < NC; ++t)
                         racc[kt][t] = Pol::mma(A, Pol::wload(wbuf, 16 * t + r16, q), racc[kt][t]);
@@ -366,7 +397,7 @@ __device__ __forceinline__ void mfma_block(const MfmaArgs &a, int b) {
     // r of this wave's loops: (real, imaginary) column pair of each system
     if constexpr (ADJ) {
 #pragma unroll
-        for (int kt = 0; kt < 2 * kMaxKs; ++kt) {
+        for (int kt = 0; kt < 2 * KS; ++kt) {
             if (kt < 2 * ks) {
 #pragma unroll
                 for (int mm = 0; mm < 4; ++mm) {
@@ -391,29 +422,34 @@ __device__ __forceinline__ void mfma_block(const MfmaArgs &a, int b) {
     }
 }
 
-template <class Pol, int MODE, int LOSS>
+template <class Pol, int MODE, int LOSS, int KS>
 __global__ __launch_bounds__(512) void k_mfma(MfmaArgs a) {
-    mfma_block<Pol, MODE, LOSS>(a, (int)blockIdx.x);
+    mfma_block<Pol, MODE, LOSS, KS>(a, (int)blockIdx.x);
 }
 
 // Several plans of one padded loop count in one launch: member m owns the
 // workgroups [first[m], first[m + 1]) (the last up to the launch's total);
 // first[m] is a multiple of 8, so that the member's XCD-aware order holds,
 // and the workgroups past its own count exit at once.
-template <class Pol, int MODE, int LOSS>
+template <class Pol, int MODE, int LOSS, int KS>
 __global__ __launch_bounds__(512) void k_mfma_group(MfmaGroup g) {
     const int b = (int)blockIdx.x;
     int m = 0;
     while (m + 1 < g.count && b >= g.first[m + 1]) ++m;
     const int loc = b - g.first[m];
     if (loc >= g.in[m].nchunk * g.in[m].nsb) return;
-    mfma_block<Pol, MODE, LOSS>(g.in[m], loc);
+    mfma_block<Pol, MODE, LOSS, KS>(g.in[m], loc);
 }
 
+// (the members of a group share their padded loop count)
 template <class Pol, int MODE, int LOSS>
 hipError_t go_group(const MfmaGroup &g, int blocks, int W, hipStream_t st) {
-    hipLaunchKernelGGL((k_mfma_group<Pol, MODE, LOSS>), dim3((unsigned)blocks), dim3(64 * W),
-                       lds_bytes<Pol>(W), st, g);
+    if (mfma_steps(g.in[0].NP) == 2)
+        hipLaunchKernelGGL((k_mfma_group<Pol, MODE, LOSS, 2>), dim3((unsigned)blocks),
+                           dim3(64 * W), lds_bytes<Pol>(W), st, g);
+    else
+        hipLaunchKernelGGL((k_mfma_group<Pol, MODE, LOSS, kMaxKs>), dim3((unsigned)blocks),
+                           dim3(64 * W), lds_bytes<Pol>(W), st, g);
     return hipGetLastError();
 }
 
@@ -421,7 +457,11 @@ template <class Pol, int MODE, int LOSS>
 hipError_t go(const MfmaArgs &a, int W, hipStream_t st) {
     const size_t lds = lds_bytes<Pol>(W);
     const unsigned blocks = (unsigned)a.nchunk * (unsigned)a.nsb;
-    hipLaunchKernelGGL((k_mfma<Pol, MODE, LOSS>), dim3(blocks), dim3(64 * W), lds, st, a);
+    if (mfma_steps(a.NP) == 2)
+        hipLaunchKernelGGL((k_mfma<Pol, MODE, LOSS, 2>), dim3(blocks), dim3(64 * W), lds, st, a);
+    else
+        hipLaunchKernelGGL((k_mfma<Pol, MODE, LOSS, kMaxKs>), dim3(blocks), dim3(64 * W), lds, st,
+                           a);
     return hipGetLastError();
 }
 
@@ -453,7 +493,8 @@ int mfma_systems_per_block(Prec prec) { return prec == Prec::F64 ? 8 : 16; }
 MfmaShape mfma_shape(Prec prec, int NP, int S, int P_pad, int cus) {
     MfmaShape sh;
     const int m = NP / 32;
-    sh.waves = (m + kMaxKs - 1) / kMaxKs;
+    const int ks = mfma_steps(NP);
+    sh.waves = (m + ks - 1) / ks;
     const int ns = mfma_systems_per_block(prec);
     sh.nsb = (S + ns - 1) / ns;
     // fewest chunks of points (whole sub-tiles) that give the launch at least
@@ -475,7 +516,8 @@ hipError_t launch_mfma_group(Prec prec, bool grad, int loss_mode, const MfmaGrou
     if (g.count > kGroupMax || waves < 1 || waves > 8) return hipErrorInvalidValue;
     for (int m = 0; m < g.count; ++m) {
         const MfmaArgs &a = g.in[m];
-        if (a.NP % 32 != 0 || a.NP / 32 > kMaxKs * waves || a.P_pad % kSub != 0 ||
+        if (a.NP % 32 != 0 || a.NP / 32 > mfma_steps(a.NP) * waves || a.NP != g.in[0].NP ||
+            a.P_pad % kSub != 0 ||
             a.rows_per_chunk % kSub != 0 || g.first[m] % 8 != 0 ||
             (m + 1 < g.count ? g.first[m + 1] : blocks) - g.first[m] < a.nchunk * a.nsb)
             return hipErrorInvalidValue;
@@ -504,7 +546,7 @@ hipError_t launch_mfma_group(Prec prec, bool grad, int loss_mode, const MfmaGrou
 
 hipError_t launch_mfma(Prec prec, int mode, int loss_mode, const MfmaArgs &a, int waves,
                        hipStream_t st) {
-    if (a.NP % 32 != 0 || a.NP / 32 > kMaxKs * waves || waves < 1 || waves > 8 ||
+    if (a.NP % 32 != 0 || a.NP / 32 > mfma_steps(a.NP) * waves || waves < 1 || waves > 8 ||
         a.P_pad % kSub != 0 || a.rows_per_chunk % kSub != 0)
         return hipErrorInvalidValue;
     if (a.nchunk <= 0 || a.nsb <= 0) return hipSuccess;
