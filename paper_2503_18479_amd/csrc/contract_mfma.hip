@@ -12,9 +12,10 @@
 //
 // Work split.  A workgroup owns a block of NS systems and a chunk of field
 // points, walked in sub-tiles of 32 points.  Its W waves split the loop index
-// k: wave w owns a range of at most 4 steps of 32 loops, keeps the currents of
-// that range as matrix-core B operands in registers for the whole chunk, and
-// accumulates r for that range over the chunk.  Per sub-tile:
+// k: wave w owns a range of at most 2 (up to 512 loops) or 4 steps of 32
+// loops, keeps the currents of that range as matrix-core B operands in
+// registers for the whole chunk, and accumulates r for that range over the
+// chunk.  Per sub-tile:
 //   1. each wave multiplies its loop range: a partial B (32 points x 2 NS),
 //      A operands G[p][k] read straight from memory (8 consecutive k per lane);
 //   2. the partials meet in LDS and every thread sums one or more (point,
