@@ -96,6 +96,8 @@ def _case(name):
         return Case(W.small_array(12, 12, batch=2, grid=12, n_freq=2, seed=6), dev, array_M=True)
     if name == "n256":    # NP=256, the largest size of the ragged configuration
         return Case(W.small_array(16, 16, batch=2, grid=16, n_freq=1, seed=7), dev, array_M=True)
+    if name == "n81wide":  # NP=128 with 36 systems: several system blocks of the contraction
+        return Case(W.small_array(9, 9, batch=12, grid=12, n_freq=3, seed=8), dev, array_M=True)
     raise KeyError(name)
 
 
@@ -524,6 +526,33 @@ def test_big_loss_and_grad(dev, name, prec, mode):
     eg = _nrel(grad.cpu().numpy(), gr, axis=1)
     _say(f"[big] {name} prec={prec} mode={mode}: loss {el.max():.2e} grad {eg.max():.2e}")
     assert el.max() < TOL[prec] and eg.max() < TOL[prec]
+
+
+def test_big_several_system_blocks(dev):
+    """81 loops with 36 systems, below the batch the GEMM passes take: the
+    matrix-core contraction kernel runs three blocks of 16 systems (five of 8
+    in FP64), each wave two loop steps with its operands loaded a phase ahead;
+    loss, gradient and field in every precision against the oracle."""
+    c = _case("n81wide")
+    I, st = c.plan.solve(c.C, c.om)
+    torch.cuda.synchronize()
+    assert int(st.abs().sum()) == 0
+    Ir = c.oracle_eval()[0]
+    Br = O.field(c.G, Ir)
+    ref = {mode: (c.oracle_eval(mode=mode)[2], c.oracle_grad(mode=mode))
+           for mode in (O.LOSS_MAG, O.LOSS_COMPLEX)}
+    for prec in (0, 1, 2):
+        Bz = c.plan.field(I, prec)
+        torch.cuda.synchronize()
+        assert _nrel(Bz.cpu().numpy(), Br) < TOL[prec], prec
+        for mode, (Lr, gr) in ref.items():
+            loss, grad, st = c.plan.loss_and_grad(c.C, c.om, c.T, loss_mode=mode, precision=prec)
+            torch.cuda.synchronize()
+            assert int(st.abs().sum()) == 0
+            el = np.abs(loss.cpu().numpy() - Lr) / Lr
+            eg = _nrel(grad.cpu().numpy(), gr, axis=1)
+            _say(f"[big] n81wide prec={prec} mode={mode}: loss {el.max():.2e} grad {eg.max():.2e}")
+            assert el.max() < TOL[prec] and eg.max() < TOL[prec], (prec, mode)
 
 
 def test_big_autograd_backward_matches_oracle(dev):
